@@ -1,0 +1,354 @@
+"""CPU oracle for the population-annealing hot path.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library ``paper_1711_02146_amd``; neither imports the other.
+
+The arithmetic lives in ``pa_oracle.c`` (plain C, compiled with gcc,
+``-ffp-contract=off``); this module binds it with ctypes and runs the
+annealing loop of Sec. II of Amey & Machta (arXiv:1711.02146) step by step:
+
+    resample beta_{k-1} -> beta_k   (Eqs. 1-2, nearest-integer copy counts,
+                                     copy/eliminate with family labels)
+    N_S Metropolis sweeps at beta_k (the MCMC step of Sec. II)
+    measure                          (<E>, beta F from Eq. 9, rho_t of Sec. III.A)
+
+The per-step scalars (<E>, beta F, rho_t) are formed here in Python floats,
+which are IEEE doubles, one operation at a time in the order written.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pa_oracle.c")
+_LIB = os.path.join(_HERE, "libpa_oracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off"]
+
+
+def build(force: bool = True) -> str:
+    """Compile pa_oracle.c into libpa_oracle.so with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+_i8p = np.ctypeslib.ndpointer(dtype=np.int8, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_c = ctypes
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    L = ctypes.CDLL(_LIB)
+    sig = {
+        "pao_philox": (None, [_u32p, _u32p, _u32p]),
+        "pao_colour_major": (None, [_c.c_int, _i32p]),
+        "pao_neighbours": (None, [_c.c_int, _i32p, _i32p]),
+        "pao_energy": (None, [_c.c_int, _i8p, _i8p, _c.c_int64, _i32p]),
+        "pao_init": (None, [_c.c_int, _i8p, _c.c_int64, _c.c_uint64, _i8p, _i32p, _u32p]),
+        "pao_thresholds": (None, [_c.c_double, _u64p]),
+        "pao_sweep": (None, [_c.c_int, _i8p, _i8p, _i32p, _c.c_int64, _c.c_uint64, _u64p,
+                             _c.c_uint32, _c.c_int]),
+        "pao_histogram": (None, [_i32p, _c.c_int64, _c.c_int, _u32p]),
+        "pao_table": (_c.c_int, [_u32p, _c.c_int, _c.c_int, _c.c_uint32, _c.c_uint32,
+                                 _c.c_double, _u32p, _u64p, _f64p,
+                                 _c.POINTER(_c.c_double)]),
+        "pao_copy_counts": (None, [_i32p, _c.c_int64, _u32p, _u64p, _c.c_uint64, _c.c_uint32,
+                                   _u32p]),
+        "pao_copy_eliminate": (_c.c_int64, [_c.c_int, _u32p, _c.c_int64, _c.c_int64, _i8p, _i32p,
+                                            _u32p, _i8p, _i32p, _u32p, _u64p]),
+        "pao_culling_fraction": (_c.c_double, [_u32p, _c.c_int, _c.c_uint32, _c.c_double]),
+        "pao_choose_dbeta": (_c.c_int, [_u32p, _c.c_int, _c.c_uint32, _c.c_double, _c.c_double,
+                                        _c.POINTER(_c.c_double), _c.POINTER(_c.c_int)]),
+        "pao_sum_eta2": (_c.c_uint64, [_u32p, _c.c_int64, _c.c_uint32]),
+        "pao_family_sizes": (None, [_u32p, _c.c_int64, _c.c_uint32, _c.c_int, _u64p]),
+        "pao_overlap_hist": (None, [_c.c_int, _i8p, _c.c_int64, _i8p, _c.c_int64, _u64p, _u32p]),
+        "pao_density_of_states": (_c.c_int, [_c.c_int, _i8p, _u64p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers
+# ---------------------------------------------------------------------------
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of counter (4 words) and key (2 words) -> 4 words."""
+    out = np.zeros(4, np.uint32)
+    lib().pao_philox(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def colour_major(L: int) -> np.ndarray:
+    out = np.zeros(L ** 3, np.int32)
+    lib().pao_colour_major(L, out)
+    return out
+
+
+def neighbours(L: int):
+    N = L ** 3
+    nb = np.zeros(N * 6, np.int32)
+    bd = np.zeros(N * 6, np.int32)
+    lib().pao_neighbours(L, nb, bd)
+    return nb.reshape(N, 6), bd.reshape(N, 6)
+
+
+def energy(L: int, J: np.ndarray, spins: np.ndarray) -> np.ndarray:
+    spins = np.ascontiguousarray(spins, np.int8)
+    R = spins.size // L ** 3
+    U = np.zeros(R, np.int32)
+    lib().pao_energy(L, np.ascontiguousarray(J, np.int8), spins, R, U)
+    return U
+
+
+def thresholds(beta: float) -> np.ndarray:
+    out = np.zeros(3, np.uint64)
+    lib().pao_thresholds(float(beta), out)
+    return out
+
+
+def histogram(U: np.ndarray, n_levels: int) -> np.ndarray:
+    h = np.zeros(n_levels, np.uint32)
+    lib().pao_histogram(np.ascontiguousarray(U, np.int32), U.size, n_levels, h)
+    return h
+
+
+def table(h: np.ndarray, N: int, R: int, R_tilde: int, dbeta: float):
+    """Resampling table (fl, T, tau, lnQ, jmin) for one step; see pa_oracle.c."""
+    n = h.size
+    fl = np.zeros(n, np.uint32)
+    T = np.zeros(n, np.uint64)
+    tau = np.zeros(n, np.float64)
+    lnq = ctypes.c_double(0.0)
+    jmin = lib().pao_table(np.ascontiguousarray(h, np.uint32), n, N, R, R_tilde, float(dbeta),
+                           fl, T, tau, ctypes.byref(lnq))
+    return fl, T, tau, lnq.value, jmin
+
+
+def copy_counts(U, fl, T, seed: int, step: int) -> np.ndarray:
+    n = np.zeros(U.size, np.uint32)
+    lib().pao_copy_counts(np.ascontiguousarray(U, np.int32), U.size, fl, T, seed, step, n)
+    return n
+
+
+def culling_fraction(h, R: int, dbeta: float) -> float:
+    return lib().pao_culling_fraction(np.ascontiguousarray(h, np.uint32), h.size, R, float(dbeta))
+
+
+def choose_dbeta(h, R: int, eps_target: float, rem: float):
+    """Constant-culling step: returns (dbeta, reached_end) or raises."""
+    d = ctypes.c_double(0.0)
+    e = ctypes.c_int(0)
+    rc = lib().pao_choose_dbeta(np.ascontiguousarray(h, np.uint32), h.size, R, float(eps_target),
+                                float(rem), ctypes.byref(d), ctypes.byref(e))
+    if rc != 0:
+        raise ValueError("culling fraction already exceeds the target at dbeta = 0")
+    return d.value, bool(e.value)
+
+
+def sum_eta2(fam: np.ndarray, R: int) -> int:
+    return int(lib().pao_sum_eta2(np.ascontiguousarray(fam, np.uint32), fam.size, R))
+
+
+def family_sizes(fam: np.ndarray, R: int, max_eta: int) -> np.ndarray:
+    out = np.zeros(max_eta, np.uint64)
+    lib().pao_family_sizes(np.ascontiguousarray(fam, np.uint32), fam.size, R, max_eta, out)
+    return out
+
+
+def overlap_hist(N: int, spins_a: np.ndarray, spins_b: np.ndarray):
+    Ra = spins_a.size // N
+    Rb = spins_b.size // N
+    hist = np.zeros(65, np.uint64)
+    d = np.zeros(min(Ra, Rb), np.uint32)
+    lib().pao_overlap_hist(N, np.ascontiguousarray(spins_a, np.int8), Ra,
+                           np.ascontiguousarray(spins_b, np.int8), Rb, hist, d)
+    return hist, d
+
+
+def density_of_states(L: int, J: np.ndarray) -> np.ndarray:
+    g = np.zeros(3 * L ** 3 + 1, np.uint64)
+    rc = lib().pao_density_of_states(L, np.ascontiguousarray(J, np.int8), g)
+    if rc != 0:
+        raise ValueError("lattice too large to enumerate")
+    return g
+
+
+# ---------------------------------------------------------------------------
+# the annealing loop (Sec. II)
+# ---------------------------------------------------------------------------
+@dataclass
+class StepRecord:
+    k: int
+    beta: float
+    dbeta: float
+    lnQ: float
+    beta_F: float
+    mean_E: float
+    rho_t: float
+    R_tilde: int
+    E_min: int
+    eps_expected: float
+    n_culled: int
+    sum_eta2: int
+
+
+def default_capacity(R: int) -> int:
+    return int(R + 16 * math.isqrt(R) + 256)
+
+
+class Population:
+    """One PA population: spins [slot][site] int8, U, family labels.
+
+    ``seed`` keys every draw of this population (init, sweeps, resampling).
+    ``t`` is the population's sweep counter, ``k`` its resampling-step index.
+    """
+
+    def __init__(self, L: int, J: np.ndarray, R: int, seed: int, capacity: int | None = None):
+        self.L = L
+        self.N = L ** 3
+        self.n_levels = 3 * self.N + 1
+        self.J = np.ascontiguousarray(J, np.int8)
+        assert self.J.size == 3 * self.N
+        self.R = int(R)
+        self.seed = int(seed)
+        self.capacity = int(capacity) if capacity else default_capacity(R)
+        self.spins = np.zeros(self.R * self.N, np.int8)
+        self.U = np.zeros(self.R, np.int32)
+        self.fam = np.zeros(self.R, np.uint32)
+        lib().pao_init(L, self.J, self.R, self.seed, self.spins, self.U, self.fam)
+        self.R_tilde = self.R
+        self.t = 0
+        self.k = 0
+        self.beta = 0.0
+        self.sum_lnQ = 0.0
+        self.last = None  # details of the last resampling step
+
+    # -- C-10: Metropolis sweeps ------------------------------------------
+    def sweep(self, beta: float, n_sweeps: int):
+        thr = thresholds(beta)
+        lib().pao_sweep(self.L, self.J, self.spins, self.U, self.R_tilde, self.seed, thr,
+                        self.t, int(n_sweeps))
+        self.t += int(n_sweeps)
+
+    def histogram(self) -> np.ndarray:
+        return histogram(self.U[: self.R_tilde], self.n_levels)
+
+    # -- C-7 / C-8: resampling beta -> beta_next --------------------------
+    def resample(self, beta_next: float):
+        dbeta = beta_next - self.beta
+        h = self.histogram()
+        fl, T, tau, lnQ, jmin = table(h, self.N, self.R, self.R_tilde, dbeta)
+        step = self.k + 1
+        n = copy_counts(self.U[: self.R_tilde], fl, T, self.seed, step)
+        new_spins = np.zeros(self.capacity * self.N, np.int8)
+        new_U = np.zeros(self.capacity, np.int32)
+        new_fam = np.zeros(self.capacity, np.uint32)
+        offsets = np.zeros(self.R_tilde, np.uint64)
+        Rn = lib().pao_copy_eliminate(self.L, n, self.R_tilde, self.capacity, self.spins, self.U,
+                                      self.fam, new_spins, new_U, new_fam, offsets)
+        if Rn < 0:
+            raise OverflowError("resampled population exceeds capacity")
+        eps = culling_fraction(h, self.R, dbeta)
+        self.last = dict(h=h, fl=fl, T=T, tau=tau, n=n, offsets=offsets, jmin=jmin, lnQ=lnQ,
+                         dbeta=dbeta, eps=eps, n_culled=int(np.count_nonzero(n == 0)))
+        self.spins = new_spins[: Rn * self.N].copy()
+        self.U = new_U[:Rn].copy()
+        self.fam = new_fam[:Rn].copy()
+        self.R_tilde = int(Rn)
+        self.sum_lnQ = self.sum_lnQ + lnQ
+        self.beta = beta_next
+        self.k = step
+
+    # -- C-9: constant culling fraction -----------------------------------
+    def choose_beta(self, eps_target: float, beta_max: float):
+        rem = beta_max - self.beta
+        dbeta, end = choose_dbeta(self.histogram(), self.R, eps_target, rem)
+        return beta_max if end else self.beta + dbeta
+
+    # -- C-11: observables --------------------------------------------------
+    def observables(self) -> StepRecord:
+        h = self.histogram()
+        N = self.N
+        levels = np.arange(self.n_levels, dtype=np.int64)
+        sumE = int(np.sum(h.astype(np.int64) * (2 * levels - 3 * N)))
+        mean_E = float(sumE) / float(self.R_tilde)
+        beta_F = -(float(N) * math.log(2.0) + self.sum_lnQ)
+        s2 = sum_eta2(self.fam, self.R)
+        rho_t = float(s2) / float(self.R)
+        E_min = 2 * int(np.flatnonzero(h)[0]) - 3 * N
+        last = self.last or {}
+        return StepRecord(k=self.k, beta=self.beta, dbeta=last.get("dbeta", 0.0),
+                          lnQ=last.get("lnQ", 0.0), beta_F=beta_F, mean_E=mean_E, rho_t=rho_t,
+                          R_tilde=self.R_tilde, E_min=E_min, eps_expected=last.get("eps", 0.0),
+                          n_culled=last.get("n_culled", 0), sum_eta2=s2)
+
+    def spins_2d(self) -> np.ndarray:
+        return self.spins.reshape(self.R_tilde, self.N)
+
+
+def linear_schedule(beta_max: float, n_temps: int):
+    """beta_k = (beta_max * k) / (N_T - 1), k = 0..N_T-1 (FP64, not accumulated)."""
+    return [(beta_max * k) / (n_temps - 1) for k in range(n_temps)]
+
+
+def run_linear(L, J, R, seed, beta_max, n_temps, n_sweeps, capacity=None, partner_seed=None,
+               on_step=None):
+    """Fixed linear schedule.  With ``partner_seed`` a second population with
+    the same couplings runs in lockstep and the overlap histogram is recorded."""
+    pops = [Population(L, J, R, seed, capacity)]
+    if partner_seed is not None:
+        pops.append(Population(L, J, R, partner_seed, capacity))
+    betas = linear_schedule(beta_max, n_temps)
+    records = []
+    for k in range(1, n_temps):
+        recs = []
+        for p in pops:
+            p.resample(betas[k])
+            p.sweep(betas[k], n_sweeps)
+            recs.append(p.observables())
+        q = None
+        if len(pops) == 2:
+            q, _ = overlap_hist(pops[0].N, pops[0].spins, pops[1].spins)
+        records.append((recs, q))
+        if on_step is not None:
+            on_step(k, pops)
+    return pops, records
+
+
+def run_adaptive(L, J, R, seed, eps_target, beta_max, n_sweeps, capacity=None, max_steps=100000,
+                 on_step=None):
+    """Constant-culling schedule: each step's dbeta from choose_beta."""
+    p = Population(L, J, R, seed, capacity)
+    records = []
+    while p.beta < beta_max and p.k < max_steps:
+        b = p.choose_beta(eps_target, beta_max)
+        p.resample(b)
+        p.sweep(b, n_sweeps)
+        records.append(p.observables())
+        if on_step is not None:
+            on_step(p.k, p)
+    return p, records

@@ -1,0 +1,490 @@
+/*
+ * pa_oracle.c -- plain CPU oracle for population annealing (PA) on the
+ * 3D +-J Edwards-Anderson spin glass.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  It shares no code,
+ * header, table or constant generator with the HIP path; the two meet only
+ * through the arithmetic contract written out below.
+ *
+ * Paper: C. Amey and J. Machta, "Analysis and Optimization of Population
+ * Annealing", arXiv:1711.02146 (Sec. II: the algorithm; Sec. II.A: model and
+ * observables; Sec. III: rho_t, culling fraction).
+ *
+ * Everything here is the most direct reading of the paper's steps, kept slow
+ * and obvious: spins are int8 +-1 stored [replica][site]; sites are visited
+ * in lexicographic order; every random word is drawn with its own Philox call.
+ * Built with -ffp-contract=off so every FP64 line rounds as written, left to
+ * right.  OpenMP only splits independent replicas; results do not depend on
+ * the thread count because every draw is addressed by a counter.
+ *
+ * Readings where the paper is silent (the coupling distribution, the MCMC
+ * variant and its order, the random-number contract, the reference-energy
+ * shift, the copy-count tie rule, the adaptive-step bisection) are the ones
+ * listed in the design notes; each function names the reading it takes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11).  Counter (c0,c1,c2,c3), key (k0,k1).  Each of   */
+/* ten rounds multiplies c0 and c2 by the two round multipliers, swaps the   */
+/* halves and XORs in the other counter words and the round key; the key is  */
+/* bumped by the two Weyl constants between rounds.                          */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_MUL_A 0xD2511F53u
+#define PHILOX_MUL_B 0xCD9E8D57u
+#define PHILOX_WEYL_A 0x9E3779B9u
+#define PHILOX_WEYL_B 0xBB67AE85u
+
+/* Stream tags: the fourth counter word separates the three uses of the
+ * generator so that no two uses can ever share a counter. */
+#define TAG_INIT 0x494E4954u /* initial spins */
+#define TAG_MET 0x4D455452u  /* Metropolis acceptance draws */
+#define TAG_RES 0x52455341u  /* resampling (copy-count) draws */
+
+void pao_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t pa = (uint64_t)PHILOX_MUL_A * (uint64_t)x0;
+    uint64_t pb = (uint64_t)PHILOX_MUL_B * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(pb >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)pb;
+    uint32_t y2 = (uint32_t)(pa >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)pa;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    k0 += PHILOX_WEYL_A;
+    k1 += PHILOX_WEYL_B;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* One 32-bit word of Philox(seed; c0, c1, c2, tag), word index w in 0..3.
+ * The 64-bit population seed is the key: low half first. */
+static uint32_t draw_word(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                          uint32_t tag, int w) {
+  uint32_t ctr[4] = {c0, c1, c2, tag};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  pao_philox(ctr, key, out);
+  return out[w];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice (Sec. II.A): L^3 cubic lattice, periodic boundaries, Ising spins  */
+/* s = +-1, H = -sum_<nm> J_nm s_n s_m over nearest-neighbour bonds.          */
+/*   site = x + L*(y + L*z);  bond b = d*N + site joins site and site + e_d   */
+/*   (d = 0,1,2 for x,y,z), so every bond is listed exactly once.             */
+/*   colour(site) = (x+y+z) & 1.                                              */
+/*   cm(site): list the colour-0 sites, then the colour-1 sites, each in      */
+/*   lexicographic order; cm is the position of the site in that list.  It is */
+/*   computed here by counting.                                               */
+/* ------------------------------------------------------------------------ */
+static int wrap(int a, int L) { return (a % L + L) % L; }
+
+/* Neighbour of `site` one step along direction dir: 0:+x 1:-x 2:+y 3:-y 4:+z 5:-z */
+static int neighbour(int site, int dir, int L) {
+  int x = site % L, y = (site / L) % L, z = site / (L * L);
+  switch (dir) {
+    case 0: x = wrap(x + 1, L); break;
+    case 1: x = wrap(x - 1, L); break;
+    case 2: y = wrap(y + 1, L); break;
+    case 3: y = wrap(y - 1, L); break;
+    case 4: z = wrap(z + 1, L); break;
+    default: z = wrap(z - 1, L); break;
+  }
+  return x + L * (y + L * z);
+}
+
+/* Index of the bond between `site` and its neighbour along dir. */
+static int bond_of(int site, int dir, int L) {
+  int N = L * L * L;
+  int d = dir / 2;
+  if (dir % 2 == 0) return d * N + site;          /* bond from site to site+e_d */
+  return d * N + neighbour(site, dir, L);         /* bond from site-e_d to site */
+}
+
+static int colour_of(int site, int L) {
+  int x = site % L, y = (site / L) % L, z = site / (L * L);
+  return (x + y + z) & 1;
+}
+
+/* Colour-major rank of every site, by counting (no closed form). */
+void pao_colour_major(int L, int32_t* cm_out) {
+  int N = L * L * L;
+  int n0 = 0;
+  for (int s = 0; s < N; ++s) n0 += (colour_of(s, L) == 0);
+  int next0 = 0, next1 = n0;
+  for (int s = 0; s < N; ++s) {
+    if (colour_of(s, L) == 0) cm_out[s] = next0++;
+    else cm_out[s] = next1++;
+  }
+}
+
+void pao_neighbours(int L, int32_t* nbr_out /* N*6 */, int32_t* bond_out /* N*6 */) {
+  int N = L * L * L;
+  for (int s = 0; s < N; ++s)
+    for (int dir = 0; dir < 6; ++dir) {
+      nbr_out[s * 6 + dir] = neighbour(s, dir, L);
+      bond_out[s * 6 + dir] = bond_of(s, dir, L);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Energy.  With +-1 couplings the energy of a configuration is an integer: */
+/* U = number of unsatisfied bonds (J_b s_i s_j = -1), E = 2U - 3N.           */
+/* ------------------------------------------------------------------------ */
+static int32_t unsatisfied_bonds(const int8_t* s, const int8_t* J, int L) {
+  int N = L * L * L;
+  int32_t U = 0;
+  for (int site = 0; site < N; ++site)
+    for (int d = 0; d < 3; ++d) {
+      int other = neighbour(site, 2 * d, L);
+      if ((int)J[d * N + site] * (int)s[site] * (int)s[other] < 0) ++U;
+    }
+  return U;
+}
+
+void pao_energy(int L, const int8_t* J, const int8_t* spins, int64_t R, int32_t* U_out) {
+  int N = L * L * L;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < R; ++r) U_out[r] = unsatisfied_bonds(spins + r * N, J, L);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial population (Sec. II): R independent replicas drawn uniformly at  */
+/* beta = 0, labelled 0..R-1 (each replica is its own family).               */
+/* Spin of replica r at site: bit 31 of word (site & 3) of                   */
+/* Philox(seed; r, site >> 2, 0, TAG_INIT); bit 0 -> +1, bit 1 -> -1.        */
+/* ------------------------------------------------------------------------ */
+void pao_init(int L, const int8_t* J, int64_t R, uint64_t seed, int8_t* spins_out,
+              int32_t* U_out, uint32_t* family_out) {
+  int N = L * L * L;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < R; ++r) {
+    int8_t* s = spins_out + r * N;
+    for (int site = 0; site < N; ++site) {
+      uint32_t w = draw_word(seed, (uint32_t)r, (uint32_t)(site >> 2), 0u, TAG_INIT, site & 3);
+      s[site] = (w >> 31) ? (int8_t)-1 : (int8_t)1;
+    }
+    U_out[r] = unsatisfied_bonds(s, J, L);
+    family_out[r] = (uint32_t)r;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Metropolis acceptance thresholds at inverse temperature beta: a move that */
+/* raises the energy by dE > 0 is accepted with probability exp(-beta dE),  */
+/* realised as  word < thr[dE]  with thr = floor(2^32 exp(-beta dE)).         */
+/* dE is 4, 8 or 12 for +-J couplings on the cubic lattice.                  */
+/* ------------------------------------------------------------------------ */
+void pao_thresholds(double beta, uint64_t thr_out[3]) {
+  for (int i = 0; i < 3; ++i) {
+    double dE = (double)(4 * (i + 1));
+    thr_out[i] = (uint64_t)floor(ldexp(exp(-beta * dE), 32));
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Metropolis sweeps (Sec. II: the MCMC step of PA; the variant is ours).   */
+/* A sweep visits colour 0 then colour 1; within a colour, sites in          */
+/* lexicographic order, each updated in place.  For even L same-colour sites */
+/* never touch, so this equals a simultaneous checkerboard update.           */
+/* The draw for (replica slot r, sweep t, site) is word (cm & 3) of          */
+/* Philox(seed; r, t, cm >> 2, TAG_MET); it is needed only when dE > 0.      */
+/* The population sweep counter t advances by one after every full sweep.    */
+/* U is updated incrementally: U += dE/2 on every accepted flip.             */
+/* ------------------------------------------------------------------------ */
+void pao_sweep(int L, const int8_t* J, int8_t* spins, int32_t* U, int64_t R_tilde,
+               uint64_t seed, const uint64_t thr[3], uint32_t t0, int n_sweeps) {
+  int N = L * L * L;
+  /* lattice tables, filled once: neighbour site and bond of every direction */
+  int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * N);
+  int32_t* nb = (int32_t*)malloc(sizeof(int32_t) * N * 6);
+  int32_t* bd = (int32_t*)malloc(sizeof(int32_t) * N * 6);
+  pao_colour_major(L, cm);
+  pao_neighbours(L, nb, bd);
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < R_tilde; ++r) {
+    int8_t* s = spins + r * N;
+    int32_t u = U[r];
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+      uint32_t t = t0 + (uint32_t)sw;
+      for (int colour = 0; colour < 2; ++colour) {
+        for (int site = 0; site < N; ++site) {
+          if (colour_of(site, L) != colour) continue;
+          int h = 0;
+          for (int dir = 0; dir < 6; ++dir)
+            h += (int)J[bd[site * 6 + dir]] * (int)s[nb[site * 6 + dir]];
+          int dE = 2 * (int)s[site] * h;
+          int accept;
+          if (dE <= 0) {
+            accept = 1;
+          } else {
+            uint32_t x = draw_word(seed, (uint32_t)r, t, (uint32_t)(cm[site] >> 2), TAG_MET,
+                                   cm[site] & 3);
+            accept = (uint64_t)x < thr[dE / 4 - 1];
+          }
+          if (accept) {
+            s[site] = (int8_t)(-s[site]);
+            u += dE / 2;
+          }
+        }
+      }
+    }
+    U[r] = u;
+  }
+  free(cm);
+  free(nb);
+  free(bd);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Energy histogram: h_j = number of replicas with U = j, j = 0..3N.          */
+/* With integer energies the sum in the normaliser Q (Eq. 2) regroups by    */
+/* level.                                                                    */
+/* ------------------------------------------------------------------------ */
+void pao_histogram(const int32_t* U, int64_t R_tilde, int n_levels, uint32_t* h_out) {
+  memset(h_out, 0, sizeof(uint32_t) * (size_t)n_levels);
+  for (int64_t i = 0; i < R_tilde; ++i) h_out[U[i]] += 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Resampling table for the step beta -> beta + dbeta (Sec. II, Eqs. 1-2).  */
+/*   j_min = lowest occupied level (reference energy, avoids FP overflow;   */
+/*           it cancels in tau)                                              */
+/*   w_j   = exp(-dbeta * 2 (j - j_min))          (= e^{-dbeta (E_j - E_min)})*/
+/*   S     = sum over occupied j, ascending, of h_j w_j                      */
+/*   tau_j = R w_j / S                            (Eq. 1 with Eq. 2 inserted) */
+/*   ln Q  = ln S - ln R~ - dbeta E_min           (Eq. 2, shifted back)       */
+/* Copy-count split of tau_j: floor fl_j and an integer threshold             */
+/*   T_j = ceil(frac(tau_j) 2^53), so that u53 < T_j  <=>  u < frac(tau_j).   */
+/* Levels below j_min get fl = T = 0 (no replica sits there).                */
+/* Returns j_min, or -1 for an empty histogram.                              */
+/* ------------------------------------------------------------------------ */
+int pao_table(const uint32_t* h, int n_levels, int N, uint32_t R, uint32_t R_tilde,
+              double dbeta, uint32_t* fl_out, uint64_t* T_out, double* tau_out,
+              double* lnQ_out) {
+  int jmin = -1;
+  for (int j = 0; j < n_levels; ++j)
+    if (h[j] > 0) { jmin = j; break; }
+  if (jmin < 0) return -1;
+  double S = 0.0;
+  for (int j = jmin; j < n_levels; ++j) {
+    if (h[j] == 0) continue;
+    double w = exp(-dbeta * (double)(2 * (j - jmin)));
+    S = S + (double)h[j] * w;
+  }
+  for (int j = 0; j < n_levels; ++j) {
+    if (j < jmin) {
+      fl_out[j] = 0; T_out[j] = 0;
+      if (tau_out) tau_out[j] = 0.0;
+      continue;
+    }
+    double w = exp(-dbeta * (double)(2 * (j - jmin)));
+    double tau = ((double)R * w) / S;
+    uint64_t fl = (uint64_t)floor(tau);
+    double fr = tau - (double)fl;
+    fl_out[j] = (uint32_t)fl;
+    T_out[j] = (uint64_t)ceil(ldexp(fr, 53));
+    if (tau_out) tau_out[j] = tau;
+  }
+  *lnQ_out = log(S) - log((double)R_tilde) - dbeta * (double)(2 * jmin - 3 * N);
+  return jmin;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nearest-integer copy counts (Sec. II): n_i = floor(tau_i) with           */
+/* probability ceil(tau_i) - tau_i, else ceil(tau_i).  The uniform is a     */
+/* 53-bit integer u53 from words 0 and 1 of Philox(seed; i, k, 0, TAG_RES),  */
+/* i = current slot, k = resampling step index; the extra copy is taken iff */
+/* u53 < T_j (strict, so an integer tau never gets one).                     */
+/* ------------------------------------------------------------------------ */
+void pao_copy_counts(const int32_t* U, int64_t R_tilde, const uint32_t* fl, const uint64_t* T,
+                     uint64_t seed, uint32_t step, uint32_t* n_out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < R_tilde; ++i) {
+    uint32_t ctr[4] = {(uint32_t)i, step, 0u, TAG_RES};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    pao_philox(ctr, key, out);
+    uint64_t u53 = ((uint64_t)out[0] << 21) | (uint64_t)(out[1] >> 11);
+    int j = U[i];
+    n_out[i] = fl[j] + (u53 < T[j] ? 1u : 0u);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Copy / eliminate (Sec. II): replica i is copied n_i times; its copies    */
+/* take consecutive new slots starting at offset_i = sum_{i'<i} n_i', so the */
+/* new population keeps the old order and every copy inherits the family    */
+/* label of its ancestor.  Returns the new population size, or -1 if it     */
+/* exceeds `capacity` (the old population is then left untouched).          */
+/* ------------------------------------------------------------------------ */
+int64_t pao_copy_eliminate(int L, const uint32_t* n, int64_t R_tilde, int64_t capacity,
+                           const int8_t* spins_old, const int32_t* U_old,
+                           const uint32_t* fam_old, int8_t* spins_new, int32_t* U_new,
+                           uint32_t* fam_new, uint64_t* offsets_out) {
+  int N = L * L * L;
+  uint64_t total = 0;
+  for (int64_t i = 0; i < R_tilde; ++i) {
+    if (offsets_out) offsets_out[i] = total;
+    total += n[i];
+  }
+  if ((int64_t)total > capacity) return -1;
+  uint64_t dst = 0;
+  for (int64_t i = 0; i < R_tilde; ++i) {
+    for (uint32_t c = 0; c < n[i]; ++c) {
+      memcpy(spins_new + dst * N, spins_old + i * N, (size_t)N);
+      U_new[dst] = U_old[i];
+      fam_new[dst] = fam_old[i];
+      ++dst;
+    }
+  }
+  return (int64_t)total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Culling fraction (Sec. III.C): eps R = sum over replicas with tau < 1 of */
+/* (1 - tau), evaluated from the histogram with tau_j exactly as in         */
+/* pao_table (same j_min shift, same ascending sum).                         */
+/* ------------------------------------------------------------------------ */
+double pao_culling_fraction(const uint32_t* h, int n_levels, uint32_t R, double dbeta) {
+  int jmin = -1;
+  for (int j = 0; j < n_levels; ++j)
+    if (h[j] > 0) { jmin = j; break; }
+  if (jmin < 0) return 0.0;
+  double S = 0.0;
+  for (int j = jmin; j < n_levels; ++j) {
+    if (h[j] == 0) continue;
+    double w = exp(-dbeta * (double)(2 * (j - jmin)));
+    S = S + (double)h[j] * w;
+  }
+  double acc = 0.0;
+  for (int j = jmin; j < n_levels; ++j) {
+    if (h[j] == 0) continue;
+    double w = exp(-dbeta * (double)(2 * (j - jmin)));
+    double tau = ((double)R * w) / S;
+    if (tau < 1.0) acc = acc + (double)h[j] * (1.0 - tau);
+  }
+  return acc / (double)R;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Constant-culling step (Sec. III.C and Sec. IV.B: a schedule that culls a */
+/* fixed fraction per step).  Our reading: bisect dbeta on [0, rem] so that */
+/* eps(dbeta) <= eps_target, 64 halvings, keep the lower end; if the whole  */
+/* remaining range already culls no more than eps_target, take it.          */
+/* Returns 0, or -1 when even dbeta = 0 culls more than eps_target.          */
+/* ------------------------------------------------------------------------ */
+int pao_choose_dbeta(const uint32_t* h, int n_levels, uint32_t R, double eps_target,
+                     double rem, double* dbeta_out, int* reached_end) {
+  if (pao_culling_fraction(h, n_levels, R, 0.0) > eps_target) return -1;
+  if (pao_culling_fraction(h, n_levels, R, rem) <= eps_target) {
+    *dbeta_out = rem;
+    *reached_end = 1;
+    return 0;
+  }
+  double lo = 0.0, hi = rem;
+  for (int it = 0; it < 64; ++it) {
+    double mid = lo + 0.5 * (hi - lo);
+    if (pao_culling_fraction(h, n_levels, R, mid) <= eps_target) lo = mid;
+    else hi = mid;
+  }
+  *dbeta_out = lo;
+  *reached_end = 0;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Family statistic (Sec. III.A, rho_t): sum over family labels f of eta_f^2*/
+/* where eta_f counts the replicas carrying label f.  Labels are < R.       */
+/* ------------------------------------------------------------------------ */
+uint64_t pao_sum_eta2(const uint32_t* fam, int64_t R_tilde, uint32_t R) {
+  uint64_t* eta = (uint64_t*)calloc((size_t)R, sizeof(uint64_t));
+  for (int64_t i = 0; i < R_tilde; ++i) eta[fam[i]] += 1;
+  uint64_t acc = 0;
+  for (uint32_t f = 0; f < R; ++f) acc += eta[f] * eta[f];
+  free(eta);
+  return acc;
+}
+
+/* Family-size distribution: count_out[e] = number of labels with eta = e,   */
+/* for e < max_eta; larger families are added to the last bin.              */
+void pao_family_sizes(const uint32_t* fam, int64_t R_tilde, uint32_t R, int max_eta,
+                      uint64_t* count_out) {
+  uint64_t* eta = (uint64_t*)calloc((size_t)R, sizeof(uint64_t));
+  for (int64_t i = 0; i < R_tilde; ++i) eta[fam[i]] += 1;
+  memset(count_out, 0, sizeof(uint64_t) * (size_t)max_eta);
+  for (uint32_t f = 0; f < R; ++f) {
+    uint64_t e = eta[f];
+    if (e >= (uint64_t)max_eta) e = (uint64_t)max_eta - 1;
+    count_out[e] += 1;
+  }
+  free(eta);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spin overlap (Sec. II.A): q = (1/N) sum_n s1_n s2_n between replica slot */
+/* i of population A and slot i of population B (independent populations,  */
+/* same couplings), for i < min(R~_A, R~_B).  With d = number of sites where */
+/* they differ, q = 1 - 2d/N; the bin is round-half-up of 64 (1+q)/2, i.e.  */
+/* (128 (N - d) + N) / (2N) in integer division: 65 bins over [-1, 1].       */
+/* ------------------------------------------------------------------------ */
+void pao_overlap_hist(int N, const int8_t* spins_a, int64_t Ra, const int8_t* spins_b,
+                      int64_t Rb, uint64_t* hist65_out, uint32_t* d_out) {
+  int64_t n = Ra < Rb ? Ra : Rb;
+  memset(hist65_out, 0, sizeof(uint64_t) * 65);
+  for (int64_t i = 0; i < n; ++i) {
+    int d = 0;
+    for (int site = 0; site < N; ++site) d += spins_a[i * N + site] != spins_b[i * N + site];
+    if (d_out) d_out[i] = (uint32_t)d;
+    int bin = (128 * (N - d) + N) / (2 * N);
+    hist65_out[bin] += 1;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact density of states for a small lattice (N <= 30) by enumerating all */
+/* 2^N states in Gray-code order: consecutive states differ by one spin, so */
+/* U changes by (number of that spin's bonds made unsatisfied) minus        */
+/* (number made satisfied).  g_out has 3N + 1 entries, g_out[U] = number of */
+/* states with U unsatisfied bonds.                                          */
+/* ------------------------------------------------------------------------ */
+int pao_density_of_states(int L, const int8_t* J, uint64_t* g_out) {
+  int N = L * L * L;
+  if (N > 30) return -1;
+  int nb[30][6];
+  int jb[30][6];
+  for (int s = 0; s < N; ++s)
+    for (int dir = 0; dir < 6; ++dir) {
+      nb[s][dir] = neighbour(s, dir, L);
+      jb[s][dir] = J[bond_of(s, dir, L)];
+    }
+  memset(g_out, 0, sizeof(uint64_t) * (size_t)(3 * N + 1));
+  /* state: bit s set <=> spin s is -1.  Start from all +1. */
+  uint32_t state = 0;
+  int8_t s[30];
+  for (int i = 0; i < N; ++i) s[i] = 1;
+  int U = unsatisfied_bonds(s, J, L);
+  g_out[U] += 1;
+  uint64_t total = (uint64_t)1 << N;
+  for (uint64_t g = 1; g < total; ++g) {
+    int flip = __builtin_ctzll(g);
+    /* bonds of `flip`: unsatisfied before the flip become satisfied, and the
+     * other way round */
+    int before = 0;
+    for (int dir = 0; dir < 6; ++dir)
+      before += (jb[flip][dir] * s[flip] * s[nb[flip][dir]] < 0);
+    U += 6 - 2 * before;
+    s[flip] = (int8_t)(-s[flip]);
+    state ^= 1u << flip;
+    g_out[U] += 1;
+  }
+  (void)state;
+  return 0;
+}
