@@ -1,0 +1,192 @@
+"""Benchmark: population annealing at L=10, R=5e5 on one MI355X.
+
+A step is one temperature step of the constant-culling anneal (Sec. III.C of
+Amey & Machta, arXiv:1711.02146): choose beta' (bisection to a culling
+fraction of 0.1), resample (histogram, FP64 table, copy counts, scan, copy
+with family labels), 10 checkerboard Metropolis sweeps at beta', observables
+(<E>, beta F, rho_t).  When the anneal reaches beta = 5 the population is
+started again from beta = 0, so exactly --steps steps are timed.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  value = spin-flip attempts per second of the whole
+step loop (inputs resident in HBM), roofline = the sweep kernel (the dominant
+kernel) timed with HIP events on its stream, cpu_baseline = the CPU oracle on
+one full step of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = dict(name="L10_R500k_bitpack64_adaptive_eps0.1", L=10, R=500000, eps=0.1,
+                beta_max=5.0, n_sweeps=10, layout="bitpack64")
+
+# Peak figures of one MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz
+# retire 39.3e12 full-rate 32-bit VALU lane-operations per second; HBM3E 8 TB/s.
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic work of one spin-flip attempt ("Roofline"):
+#   a quarter of one Philox4x32-10 call: 10 rounds x (2 widening multiplies,
+#   each 4 full-rate issue slots on CDNA, + 4 XOR) / 4 = 30 slots;
+#   local field: 6 (xor with coupling) + 5 (sum) + compare + flip = 13 slots.
+OPS_PER_ATTEMPT = 30 + 13
+# bit-packed HBM bytes per attempt of the fused sweep kernel: read + write
+# one bit per spin once per launch of n_sweeps sweeps, plus ~20 B per replica
+# (src index, U, family in and out).
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c3")
+    return ap.parse_args()
+
+
+def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None):
+    """n_steps temperature steps; a new population at beta = 0 whenever beta_max is hit."""
+    import torch
+
+    attempts = 0
+    pop = None
+    gen = 0
+    for _ in range(n_steps):
+        if pop is None or pop_beta >= w["beta_max"]:
+            if pop is not None:
+                pop.close()
+            pop = pam.Population(w["L"], w["R"], J, seed0 + gen, layout=w["layout"])
+            pop_beta = 0.0
+            gen += 1
+        b = pop.choose_beta(w["eps"], w["beta_max"])
+        st = pop.resample(b)
+        if sweep_events is not None:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(pop.stream)
+            pop.sweep(b, w["n_sweeps"])
+            e1.record(pop.stream)
+            sweep_events.append((e0, e1, st["R_tilde"]))
+        else:
+            pop.sweep(b, w["n_sweeps"])
+        obs = pop.observables()
+        attempts += w["n_sweeps"] * w["L"] ** 3 * st["R_tilde"]
+        pop_beta = b
+        if stats is not None:
+            stats.append((b, st["R_tilde"], obs["rho_t"], obs["beta_F"]))
+    if pop is not None:
+        pop.close()
+    return attempts
+
+
+def cpu_baseline(w):
+    """The oracle on one full temperature step of the same workload."""
+    import oracle
+    import pa_inputs
+
+    oracle.build(force=False)
+    J = pa_inputs.couplings_pm(w["L"], pa_inputs.coupling_seed(3, 0))
+    t0 = time.perf_counter()
+    p = oracle.Population(w["L"], J, w["R"], pa_inputs.population_seed(3, 0, 0))
+    b = p.choose_beta(w["eps"], w["beta_max"])
+    p.resample(b)
+    t1 = time.perf_counter()
+    p.sweep(b, w["n_sweeps"])
+    p.observables()
+    t2 = time.perf_counter()
+    att = w["n_sweeps"] * w["L"] ** 3 * p.R_tilde
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": att / (t2 - t0), "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"one temperature step (init + bisection + resample + {w['n_sweeps']} sweeps "
+                      f"over R~={p.R_tilde} replicas, {att:.3g} attempts) of the same workload; "
+                      f"sweeps alone {att / (t2 - t1):.3g} attempts/s",
+            "seconds": round(t2 - t0, 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding "
+              "is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import pa_inputs
+    import paper_1711_02146_amd as pam
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pam.lib()
+    w = WORKLOAD
+    J = pa_inputs.couplings_pm(w["L"], pa_inputs.coupling_seed(3, 0))
+    seed0 = pa_inputs.population_seed(3, 0, 0)
+    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    run_steps(pam, J, w, args.warmup, seed0 + 1000)
+    torch.cuda.synchronize()
+    print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
+    events, stats = [], []
+    t0 = time.perf_counter()
+    torch.cuda.synchronize()
+    attempts = run_steps(pam, J, w, args.steps, seed0, events, stats)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    sweep_ms = [e0.elapsed_time(e1) for e0, e1, _ in events]
+    sweep_att = sum(w["n_sweeps"] * w["L"] ** 3 * r for _, _, r in events)
+    n_launch = len(sweep_ms)
+    avg_ms = sum(sweep_ms) / n_launch
+    avg_att = sweep_att / n_launch
+    achieved_ops = OPS_PER_ATTEMPT * avg_att / (avg_ms * 1e-3)
+    avg_R = avg_att / (w["n_sweeps"] * w["L"] ** 3)
+    bytes_per_launch = 2 * avg_R * w["L"] ** 3 / 8 + 20 * avg_R
+    line = {
+        "metric": "spin-flip attempts/s",
+        "value": attempts / wall,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "L": w["L"], "R": w["R"], "eps": w["eps"],
+                   "beta_max": w["beta_max"], "n_sweeps": w["n_sweeps"], "layout": w["layout"],
+                   "couplings": "+-J p=1/2", "seed_config": 3},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_sweep<bitpack64> (gather + 10 sweeps + energy)",
+            "achieved": achieved_ops / 1e12,
+            "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "Tops/s",
+            "frac": achieved_ops / VALU_PEAK_OPS,
+            "traffic": None,
+            "avg_launch_ms": avg_ms,
+            "launches": n_launch,
+            "attempts_per_launch": avg_att,
+            "sweep_attempts_per_s": avg_att / (avg_ms * 1e-3),
+            "hbm_algorithmic_GBs": bytes_per_launch / (avg_ms * 1e-3) / 1e9,
+            "hbm_frac": bytes_per_launch / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        },
+        "sweep_fraction_of_wall": sum(sweep_ms) * 1e-3 / wall,
+        "beta_reached": stats[-1][0] if stats else None,
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle, one step)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * pa.h -- C ABI of libpa: the data-parallel hot path of population annealing
+ * (PA) for the 3D +-J Edwards-Anderson spin glass on one AMD MI355X (gfx950).
+ *
+ * Method: C. Amey and J. Machta, "Analysis and Optimization of Population
+ * Annealing", arXiv:1711.02146.
+ *   Sec. II       the annealing loop: a population of R replicas is cooled
+ *                 through a schedule of inverse temperatures; at each step the
+ *                 replicas are resampled (Eq. 1 resampling factor, Eq. 2
+ *                 normaliser Q, nearest-integer copy counts, family labels
+ *                 passed to the copies) and then decorrelated by MCMC sweeps.
+ *   Sec. II.A     the model H = -sum J_nm s_n s_m on the periodic cubic
+ *                 lattice, the population averages, the spin overlap q, and
+ *                 the free-energy estimator (Eq. 9).
+ *   Sec. III.A    the family statistic rho_t.
+ *   Sec. III.C    the culling fraction and the constant-culling step size.
+ *
+ * Conventions shared with every caller:
+ *   - N = L^3 sites, site = x + L*(y + L*z); bond b = d*N + site joins site and
+ *     site + e_d (d = 0,1,2 for x,y,z); couplings J[b] are +1 or -1.
+ *   - U = number of unsatisfied bonds (J_b s_i s_j = -1), E = 2U - 3N.
+ *   - The canonical host spin layout is int8 +-1, [replica][site].
+ *   - Every random number is a word of Philox4x32-10 (Salmon et al., SC'11)
+ *     keyed by the population seed, addressed by (slot, sweep or step, site
+ *     group, stream tag); results are therefore reproducible bit for bit and
+ *     do not depend on launch shape or on batching.
+ *
+ * Ownership: the caller owns the device workspace (one allocation per
+ * instance, size from pa_workspace_bytes; it must outlive the instance) and
+ * the HIP stream.  libpa never allocates device memory; it allocates a little
+ * pinned host memory per instance for staging, released by pa_free.
+ * Ordering: calls on one instance are stream-ordered; pa_resample,
+ * pa_choose_beta, pa_observables, pa_overlap_hist and the export/import calls
+ * synchronise the instance's stream before they return.  One host thread per
+ * instance at a time.
+ * Errors: every call returns a status; nothing aborts.  After PA_EDEVICE the
+ * instance is unusable (free it).  PA_ECAPACITY leaves the population as it
+ * was before the failing resampling step.
+ */
+#ifndef PA_H_
+#define PA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PA_OK = 0,
+  PA_EINVAL = -1,     /* bad argument (sizes, null pointers, odd L, ...) */
+  PA_ENOMEM = -2,     /* workspace smaller than pa_workspace_bytes */
+  PA_ECAPACITY = -3,  /* resampled population would exceed the capacity */
+  PA_EDEVICE = -4,    /* a HIP call failed; the instance is now unusable */
+  PA_ESTATE = -5,     /* call out of order (e.g. a failed instance) */
+  PA_ESCHEDULE = -6   /* constant-culling step impossible: eps(0) > target */
+};
+
+enum {
+  PA_LAYOUT_AUTO = 0,      /* library's choice: PA_LAYOUT_BITPACK64 */
+  PA_LAYOUT_INT8 = 1,      /* one byte per spin: tiles of 64 replicas, [tile][site][64] */
+  PA_LAYOUT_BITPACK64 = 2  /* one bit per spin: tiles of 64 replicas, [tile][site] u64,
+                              bit (r & 63) of word [r >> 6][site] is replica r, 1 <=> s = -1 */
+};
+
+typedef struct pa_instance pa_instance;
+
+typedef struct {
+  uint32_t L;        /* linear size; even, 4 <= L <= 16 (checkerboard needs even L) */
+  uint32_t R;        /* target population size (constant over the run), >= 1 */
+  uint32_t capacity; /* max population held; 0 selects R + 16*isqrt(R) + 256 */
+  uint32_t layout;   /* PA_LAYOUT_* */
+  uint64_t seed;     /* population seed: Philox key of every draw of this population */
+  uint32_t flags;    /* reserved, must be 0 */
+  uint32_t reserved; /* must be 0 */
+} pa_params;
+
+/* Scalars of one population after a step (Sec. II.A averages, Eq. 9, Sec. III.A). */
+typedef struct {
+  double beta;         /* current inverse temperature */
+  double dbeta;        /* size of the last resampling step */
+  double lnQ;          /* ln Q of the last resampling step (Eq. 2) */
+  double beta_F;       /* beta F~ = -(N ln 2 + sum of ln Q) (Eq. 9, Omega = 2^N) */
+  double mean_E;       /* population average of E */
+  double rho_t;        /* (sum over families of eta^2) / R (Sec. III.A) */
+  double eps_expected; /* culling fraction of the last step (Sec. III.C) */
+  uint32_t R_tilde;    /* current population size */
+  uint32_t n_culled;   /* replicas with zero copies in the last step */
+  int32_t E_min;       /* lowest energy in the current population */
+  uint32_t step;       /* number of resampling steps done */
+  uint64_t sum_eta2;   /* sum over families of eta^2 */
+  uint64_t sweeps_done;/* population sweep counter */
+} pa_obs;
+
+/* Bytes of device workspace an instance with these parameters needs. 0 on bad params. */
+size_t pa_workspace_bytes(const pa_params* p);
+
+/* Create a population of R replicas at beta = 0 (Sec. II): spin of replica r
+ * at site = bit 31 of word (site & 3) of Philox(seed; r, site >> 2, 0, INIT)
+ * (bit 1 <=> s = -1); family label r; U computed from the spins.
+ * J_host: 3*L^3 couplings (+1/-1), copied.  d_workspace: device memory of at
+ * least pa_workspace_bytes(p) bytes, owned by the caller.  hip_stream: the
+ * hipStream_t all work of this instance is queued on (NULL = default stream).
+ * On success *out holds the new instance. */
+int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace, size_t ws_bytes,
+                     void* hip_stream, pa_instance** out);
+
+/* n_sweeps Metropolis sweeps at beta (the MCMC step of Sec. II): colour 0
+ * then colour 1 of the checkerboard; a move raising the energy by dE > 0 is
+ * accepted iff word (cm & 3) of Philox(seed; slot, t, cm >> 2, MET) is below
+ * floor(2^32 exp(-beta dE)), cm being the site's colour-major index and t the
+ * population's sweep counter (advanced by one per sweep).  Fuses the gather
+ * of a preceding pa_resample.  Asynchronous. */
+int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps);
+
+/* Resampling step beta -> beta_next (Sec. II, Eqs. 1-2): energy histogram,
+ * FP64 normaliser and free-energy increment, nearest-integer copy counts
+ * (the extra copy iff a 53-bit Philox integer is below ceil(frac(tau) 2^53)),
+ * exclusive scan, and an order-preserving copy of the survivors with their
+ * family labels (the copy itself is done by the next pa_sweep, or on demand).
+ * Synchronises.  step_out (nullable) receives beta, dbeta, lnQ, beta_F,
+ * R_tilde (new), n_culled, eps_expected, step. */
+int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out);
+
+/* Constant-culling step (Sec. III.C): the beta_next in (beta, beta_max] whose
+ * culling fraction eps = sum_{tau<1}(1 - tau) / R is eps_target, by 64
+ * bisection halvings on [0, beta_max - beta] keeping the lower end; beta_max
+ * itself when the whole range culls no more.  PA_ESCHEDULE if eps(0) already
+ * exceeds eps_target.  Synchronises. */
+int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* beta_next);
+
+/* Current scalars (Sec. II.A averages, Eq. 9, Sec. III.A).  Synchronises. */
+int pa_observables(pa_instance* in, pa_obs* out);
+
+/* Spin-overlap histogram between slot i of population a and slot i of
+ * population b, i < min(R~_a, R~_b) (Sec. II.A spin overlap; the two
+ * populations must share L and couplings).  With d = number of differing
+ * sites, bin = (128 (N - d) + N) / (2N) (round-half-up of 64 (1+q)/2).
+ * nbins must be 65; hist_out receives 65 counts.  Synchronises. */
+int pa_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hist_out);
+
+/* Copy the current population to the host in the canonical layout.
+ * spins_host: R~ * N int8 (+1/-1), [replica][site]; U_host, family_host: R~
+ * entries each; any of the three may be NULL.  *R_tilde receives R~ (call
+ * once with all arrays NULL to size them).  Synchronises. */
+int pa_export_state(pa_instance* in, int8_t* spins_host, uint32_t* U_host, uint32_t* family_host,
+                    uint32_t* R_tilde);
+
+/* Copy counts n_i and offsets (exclusive scan) of the last resampling step,
+ * R~_old entries each (R~ before that step: *n_old receives it).  For tests
+ * and diagnostics.  Synchronises. */
+int pa_export_counts(pa_instance* in, uint32_t* counts_host, uint32_t* offsets_host,
+                     uint32_t* n_old);
+
+/* Replace the population (checkpoint restore, or tests feeding a state in):
+ * R_tilde replicas, spins [replica][site] int8 +-1, family labels (< R), the
+ * sweep counter t, the step index k, the current beta and the accumulated
+ * sum of ln Q.  U is recomputed from the spins.  Synchronises. */
+int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* family_host,
+                    uint32_t R_tilde, uint64_t sweeps_done, uint32_t step, double beta,
+                    double sum_lnQ);
+
+/* Release the host-side handle (the caller frees the workspace afterwards). */
+int pa_free(pa_instance* in);
+
+/* Static description of a status code. */
+const char* pa_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H_ */

@@ -68,6 +68,8 @@ def lib():
         "pao_thresholds": (None, [_c.c_double, _u64p]),
         "pao_sweep": (None, [_c.c_int, _i8p, _i8p, _i32p, _c.c_int64, _c.c_uint64, _u64p,
                              _c.c_uint32, _c.c_int]),
+        "pao_sweep_slots": (None, [_c.c_int, _i8p, _i8p, _i32p, _c.c_int64, _u32p, _c.c_uint64,
+                                   _u64p, _c.c_uint32, _c.c_int]),
         "pao_histogram": (None, [_i32p, _c.c_int64, _c.c_int, _u32p]),
         "pao_table": (_c.c_int, [_u32p, _c.c_int, _c.c_int, _c.c_uint32, _c.c_uint32,
                                  _c.c_double, _u32p, _u64p, _f64p,
@@ -128,6 +130,16 @@ def thresholds(beta: float) -> np.ndarray:
     out = np.zeros(3, np.uint64)
     lib().pao_thresholds(float(beta), out)
     return out
+
+
+def sweep_slots(L: int, J: np.ndarray, spins: np.ndarray, U: np.ndarray, slots: np.ndarray,
+                seed: int, beta: float, t0: int, n_sweeps: int):
+    """Sweep selected replicas in place; row i sits in population slot slots[i]."""
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous
+    assert U.dtype == np.int32 and U.flags.c_contiguous
+    slots = np.ascontiguousarray(slots, np.uint32)
+    lib().pao_sweep_slots(L, np.ascontiguousarray(J, np.int8), spins.reshape(-1), U, slots.size,
+                          slots, seed, thresholds(beta), t0, n_sweeps)
 
 
 def histogram(U: np.ndarray, n_levels: int) -> np.ndarray:

@@ -199,6 +199,39 @@ void pao_thresholds(double beta, uint64_t thr_out[3]) {
 /* The population sweep counter t advances by one after every full sweep.    */
 /* U is updated incrementally: U += dE/2 on every accepted flip.             */
 /* ------------------------------------------------------------------------ */
+/* Sweeps of one replica held in s[0..N) that sits in population slot `slot`. */
+static void sweep_one(int L, const int8_t* J, const int32_t* cm, const int32_t* nb,
+                      const int32_t* bd, int8_t* s, int32_t* U, uint32_t slot, uint64_t seed,
+                      const uint64_t thr[3], uint32_t t0, int n_sweeps) {
+  int N = L * L * L;
+  int32_t u = *U;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    uint32_t t = t0 + (uint32_t)sw;
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int site = 0; site < N; ++site) {
+        if (colour_of(site, L) != colour) continue;
+        int h = 0;
+        for (int dir = 0; dir < 6; ++dir)
+          h += (int)J[bd[site * 6 + dir]] * (int)s[nb[site * 6 + dir]];
+        int dE = 2 * (int)s[site] * h;
+        int accept;
+        if (dE <= 0) {
+          accept = 1;
+        } else {
+          uint32_t x = draw_word(seed, slot, t, (uint32_t)(cm[site] >> 2), TAG_MET, cm[site] & 3);
+          accept = (uint64_t)x < thr[dE / 4 - 1];
+        }
+        if (accept) {
+          s[site] = (int8_t)(-s[site]);
+          u += dE / 2;
+        }
+      }
+    }
+  }
+  *U = u;
+}
+
+/* All replicas of a population: replica r sits in slot r. */
 void pao_sweep(int L, const int8_t* J, int8_t* spins, int32_t* U, int64_t R_tilde,
                uint64_t seed, const uint64_t thr[3], uint32_t t0, int n_sweeps) {
   int N = L * L * L;
@@ -209,35 +242,26 @@ void pao_sweep(int L, const int8_t* J, int8_t* spins, int32_t* U, int64_t R_tild
   pao_colour_major(L, cm);
   pao_neighbours(L, nb, bd);
 #pragma omp parallel for schedule(static)
-  for (int64_t r = 0; r < R_tilde; ++r) {
-    int8_t* s = spins + r * N;
-    int32_t u = U[r];
-    for (int sw = 0; sw < n_sweeps; ++sw) {
-      uint32_t t = t0 + (uint32_t)sw;
-      for (int colour = 0; colour < 2; ++colour) {
-        for (int site = 0; site < N; ++site) {
-          if (colour_of(site, L) != colour) continue;
-          int h = 0;
-          for (int dir = 0; dir < 6; ++dir)
-            h += (int)J[bd[site * 6 + dir]] * (int)s[nb[site * 6 + dir]];
-          int dE = 2 * (int)s[site] * h;
-          int accept;
-          if (dE <= 0) {
-            accept = 1;
-          } else {
-            uint32_t x = draw_word(seed, (uint32_t)r, t, (uint32_t)(cm[site] >> 2), TAG_MET,
-                                   cm[site] & 3);
-            accept = (uint64_t)x < thr[dE / 4 - 1];
-          }
-          if (accept) {
-            s[site] = (int8_t)(-s[site]);
-            u += dE / 2;
-          }
-        }
-      }
-    }
-    U[r] = u;
-  }
+  for (int64_t r = 0; r < R_tilde; ++r)
+    sweep_one(L, J, cm, nb, bd, spins + r * N, U + r, (uint32_t)r, seed, thr, t0, n_sweeps);
+  free(cm);
+  free(nb);
+  free(bd);
+}
+
+/* Selected replicas: replica i (row i of spins) sits in slot slots[i]. */
+void pao_sweep_slots(int L, const int8_t* J, int8_t* spins, int32_t* U, int64_t n,
+                     const uint32_t* slots, uint64_t seed, const uint64_t thr[3], uint32_t t0,
+                     int n_sweeps) {
+  int N = L * L * L;
+  int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * N);
+  int32_t* nb = (int32_t*)malloc(sizeof(int32_t) * N * 6);
+  int32_t* bd = (int32_t*)malloc(sizeof(int32_t) * N * 6);
+  pao_colour_major(L, cm);
+  pao_neighbours(L, nb, bd);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    sweep_one(L, J, cm, nb, bd, spins + i * N, U + i, slots[i], seed, thr, t0, n_sweeps);
   free(cm);
   free(nb);
   free(bd);

@@ -1,0 +1,244 @@
+"""Population annealing (Amey & Machta, arXiv:1711.02146) on AMD MI355X.
+
+Thin Python binding of ``libpa.so`` (C ABI declared in ``include/pa.h``): the
+functions ``pa_*`` below carry the C names and only marshal arguments; every
+step of the annealing path runs in the library's HIP kernels and its C++ host
+code.  PyTorch supplies the device workspace and the HIP stream.
+
+There is no CPU fallback: if the library is not built, importing a function
+raises ``ImportError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpa.so")
+
+PA_OK = 0
+PA_EINVAL = -1
+PA_ENOMEM = -2
+PA_ECAPACITY = -3
+PA_EDEVICE = -4
+PA_ESTATE = -5
+PA_ESCHEDULE = -6
+
+PA_LAYOUT_AUTO = 0
+PA_LAYOUT_INT8 = 1
+PA_LAYOUT_BITPACK64 = 2
+LAYOUTS = {"auto": PA_LAYOUT_AUTO, "int8": PA_LAYOUT_INT8, "bitpack64": PA_LAYOUT_BITPACK64}
+
+
+class pa_params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("R", ctypes.c_uint32), ("capacity", ctypes.c_uint32),
+                ("layout", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class pa_obs(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("dbeta", ctypes.c_double), ("lnQ", ctypes.c_double),
+                ("beta_F", ctypes.c_double), ("mean_E", ctypes.c_double), ("rho_t", ctypes.c_double),
+                ("eps_expected", ctypes.c_double), ("R_tilde", ctypes.c_uint32),
+                ("n_culled", ctypes.c_uint32), ("E_min", ctypes.c_int32), ("step", ctypes.c_uint32),
+                ("sum_eta2", ctypes.c_uint64), ("sweeps_done", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class PAError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {pa_strerror(status)} ({status})")
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_P = ctypes.POINTER
+
+
+def lib():
+    """Load libpa.so (built in-tree by ``python -m paper_1711_02146_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1711_02146_amd.build` "
+                          "(the HIP library is the only implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "pa_workspace_bytes": (ctypes.c_size_t, [_P(pa_params)]),
+        "pa_init_instance": (ctypes.c_int, [_P(pa_params), _vp, _vp, ctypes.c_size_t, _vp,
+                                            _P(_vp)]),
+        "pa_sweep": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_uint32]),
+        "pa_resample": (ctypes.c_int, [_vp, ctypes.c_double, _P(pa_obs)]),
+        "pa_choose_beta": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double,
+                                          _P(ctypes.c_double)]),
+        "pa_observables": (ctypes.c_int, [_vp, _P(pa_obs)]),
+        "pa_overlap_hist": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp]),
+        "pa_export_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, _P(ctypes.c_uint32)]),
+        "pa_export_counts": (ctypes.c_int, [_vp, _vp, _vp, _P(ctypes.c_uint32)]),
+        "pa_import_state": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_uint32, ctypes.c_uint64,
+                                           ctypes.c_uint32, ctypes.c_double, ctypes.c_double]),
+        "pa_free": (ctypes.c_int, [_vp]),
+        "pa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample", "pa_choose_beta",
+            "pa_observables", "pa_overlap_hist", "pa_export_state", "pa_export_counts",
+            "pa_import_state", "pa_free", "pa_strerror"]
+
+
+# --- the C entry points, one Python function each ---------------------------
+def pa_workspace_bytes(params: pa_params) -> int:
+    return int(lib().pa_workspace_bytes(ctypes.byref(params)))
+
+
+def pa_strerror(status: int) -> str:
+    return lib().pa_strerror(int(status)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != PA_OK:
+        raise PAError(rc, what)
+
+
+def pa_init_instance(params: pa_params, J: np.ndarray, workspace_ptr: int, ws_bytes: int,
+                     stream_handle: int) -> int:
+    J = np.ascontiguousarray(J, np.int8)
+    out = _vp()
+    _check(lib().pa_init_instance(ctypes.byref(params), J.ctypes.data, workspace_ptr, ws_bytes,
+                                  stream_handle, ctypes.byref(out)), "pa_init_instance")
+    return out.value
+
+
+def pa_sweep(handle: int, beta: float, n_sweeps: int):
+    _check(lib().pa_sweep(handle, float(beta), int(n_sweeps)), "pa_sweep")
+
+
+def pa_resample(handle: int, beta_next: float) -> dict:
+    o = pa_obs()
+    _check(lib().pa_resample(handle, float(beta_next), ctypes.byref(o)), "pa_resample")
+    return o.as_dict()
+
+
+def pa_choose_beta(handle: int, eps_target: float, beta_max: float) -> float:
+    b = ctypes.c_double(0.0)
+    _check(lib().pa_choose_beta(handle, float(eps_target), float(beta_max), ctypes.byref(b)),
+           "pa_choose_beta")
+    return b.value
+
+
+def pa_observables(handle: int) -> dict:
+    o = pa_obs()
+    _check(lib().pa_observables(handle, ctypes.byref(o)), "pa_observables")
+    return o.as_dict()
+
+
+def pa_overlap_hist(a: int, b: int, nbins: int = 65) -> np.ndarray:
+    h = np.zeros(nbins, np.uint64)
+    _check(lib().pa_overlap_hist(a, b, nbins, h.ctypes.data), "pa_overlap_hist")
+    return h
+
+
+def pa_export_state(handle: int, N: int, spins=True, U=True, family=True):
+    n = ctypes.c_uint32(0)
+    _check(lib().pa_export_state(handle, None, None, None, ctypes.byref(n)), "pa_export_state")
+    R = n.value
+    s = np.zeros((R, N), np.int8) if spins else None
+    u = np.zeros(R, np.uint32) if U else None
+    f = np.zeros(R, np.uint32) if family else None
+    _check(lib().pa_export_state(handle, s.ctypes.data if spins else None,
+                                 u.ctypes.data if U else None, f.ctypes.data if family else None,
+                                 ctypes.byref(n)), "pa_export_state")
+    return s, u, f
+
+
+def pa_export_counts(handle: int):
+    n = ctypes.c_uint32(0)
+    _check(lib().pa_export_counts(handle, None, None, ctypes.byref(n)), "pa_export_counts")
+    c = np.zeros(n.value, np.uint32)
+    o = np.zeros(n.value, np.uint32)
+    _check(lib().pa_export_counts(handle, c.ctypes.data, o.ctypes.data, ctypes.byref(n)),
+           "pa_export_counts")
+    return c, o
+
+
+def pa_import_state(handle: int, spins: np.ndarray, family: np.ndarray, sweeps_done: int,
+                    step: int, beta: float, sum_lnQ: float):
+    spins = np.ascontiguousarray(spins, np.int8)
+    family = np.ascontiguousarray(family, np.uint32)
+    _check(lib().pa_import_state(handle, spins.ctypes.data, family.ctypes.data, family.size,
+                                 int(sweeps_done), int(step), float(beta), float(sum_lnQ)),
+           "pa_import_state")
+
+
+def pa_free(handle: int):
+    _check(lib().pa_free(handle), "pa_free")
+
+
+# --- convenience object owning the workspace ---------------------------------
+class Population:
+    """One PA population on a GPU: workspace tensor + library handle."""
+
+    def __init__(self, L: int, R: int, J: np.ndarray, seed: int, capacity: int = 0,
+                 layout: str = "bitpack64", device=None, stream=None):
+        import torch
+
+        self.L, self.N, self.R = int(L), int(L) ** 3, int(R)
+        self.params = pa_params(L=L, R=R, capacity=capacity, layout=LAYOUTS[layout], seed=seed,
+                                flags=0, reserved=0)
+        nbytes = pa_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise PAError(PA_EINVAL, "pa_workspace_bytes")
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = pa_init_instance(self.params, J, self.workspace.data_ptr(), nbytes,
+                                       self.stream.cuda_stream)
+
+    def sweep(self, beta: float, n_sweeps: int):
+        pa_sweep(self.handle, beta, n_sweeps)
+
+    def resample(self, beta_next: float) -> dict:
+        return pa_resample(self.handle, beta_next)
+
+    def choose_beta(self, eps_target: float, beta_max: float) -> float:
+        return pa_choose_beta(self.handle, eps_target, beta_max)
+
+    def observables(self) -> dict:
+        return pa_observables(self.handle)
+
+    def export_state(self, spins=True, U=True, family=True):
+        return pa_export_state(self.handle, self.N, spins, U, family)
+
+    def export_counts(self):
+        return pa_export_counts(self.handle)
+
+    def import_state(self, spins, family, sweeps_done, step, beta, sum_lnQ):
+        pa_import_state(self.handle, spins, family, sweeps_done, step, beta, sum_lnQ)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pa_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def overlap_hist(a: Population, b: Population) -> np.ndarray:
+    return pa_overlap_hist(a.handle, b.handle, 65)

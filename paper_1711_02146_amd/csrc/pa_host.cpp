@@ -1,0 +1,660 @@
+// pa_host.cpp -- the C ABI of libpa (include/pa.h): instance state, workspace
+// layout, the FP64 resampling table, the constant-culling bisection, and the
+// stream-ordered sequence of kernel launches of one annealing step.
+//
+// Method: Amey & Machta, arXiv:1711.02146.
+//   Sec. II     resampling factor tau (Eq. 1), normaliser Q (Eq. 2),
+//               nearest-integer copy counts, family labels.
+//   Sec. II.A   free-energy estimator (Eq. 9) and population averages.
+//   Sec. III.A  rho_t;  Sec. III.C  culling fraction and step size.
+//
+// The FP64 work of a step (at most 3N + 1 energy levels) runs here, on the
+// host, with the C library's exp and log and without contraction
+// (-ffp-contract=off), every line rounded left to right.  That keeps the
+// integer copy-count thresholds, which decide bits, reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pa.h"
+#include "pa_internal.hpp"
+
+using pa::DevPop;
+using pa::DevScalars;
+using pa::SiteEntry;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+uint32_t isqrt32(uint32_t v) {
+  uint32_t r = (uint32_t)std::sqrt((double)v);
+  while ((uint64_t)r * r > v) --r;
+  while ((uint64_t)(r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+struct Layout {
+  uint32_t L, N, R, cap_limit, capacity, layout, n_levels, n_blocks;
+  size_t spins_bytes;
+  size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
+      off_bcull, off_hist, off_fl, off_T, off_sites, off_cm, off_ovl, off_sc;
+  size_t total;
+};
+
+bool make_layout(const pa_params* p, Layout* out) {
+  if (!p) return false;
+  if (p->L < 4 || p->L > (uint32_t)pa::kMaxL || (p->L & 1u)) return false;
+  if (p->R < 1) return false;
+  if (p->flags != 0 || p->reserved != 0) return false;
+  uint32_t layout = p->layout == PA_LAYOUT_AUTO ? (uint32_t)PA_LAYOUT_BITPACK64 : p->layout;
+  if (layout != PA_LAYOUT_INT8 && layout != PA_LAYOUT_BITPACK64) return false;
+  uint64_t cap = p->capacity ? (uint64_t)p->capacity
+                             : (uint64_t)p->R + 16ull * isqrt32(p->R) + 256ull;
+  if (cap < p->R || cap > (1ull << 31)) return false;
+  Layout l{};
+  l.L = p->L;
+  l.N = p->L * p->L * p->L;
+  l.R = p->R;
+  l.cap_limit = (uint32_t)cap;
+  l.capacity = (uint32_t)((cap + pa::kBlockCounts - 1) / pa::kBlockCounts * pa::kBlockCounts);
+  l.layout = layout;
+  l.n_levels = 3 * l.N + 1;
+  l.n_blocks = l.capacity / pa::kBlockCounts;
+  const size_t tiles = l.capacity / 64;
+  l.spins_bytes = layout == PA_LAYOUT_BITPACK64 ? tiles * l.N * 8 : tiles * l.N * 64;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  for (int b = 0; b < 2; ++b) l.off_spins[b] = take(l.spins_bytes);
+  for (int b = 0; b < 2; ++b) l.off_U[b] = take((size_t)l.capacity * 4);
+  for (int b = 0; b < 2; ++b) l.off_fam[b] = take((size_t)l.capacity * 4);
+  l.off_counts = take((size_t)l.capacity * 4);
+  l.off_offsets = take((size_t)l.capacity * 4);
+  l.off_src = take((size_t)l.capacity * 4);
+  l.off_bsum = take((size_t)l.n_blocks * 4);
+  l.off_boff = take((size_t)l.n_blocks * 4);
+  l.off_bcull = take((size_t)l.n_blocks * 4);
+  l.off_hist = take((size_t)l.n_levels * 4);
+  l.off_fl = take((size_t)l.n_levels * 4);
+  l.off_T = take((size_t)l.n_levels * 8);
+  l.off_sites = take((size_t)l.N * sizeof(SiteEntry));
+  l.off_cm = take((size_t)l.N * 2);
+  l.off_ovl = take(65 * 8);
+  l.off_sc = take(sizeof(DevScalars));
+  l.total = o;
+  *out = l;
+  return true;
+}
+
+// Lattice tables of the colour-major order for even L.
+void build_sites(uint32_t L, const int8_t* J, std::vector<SiteEntry>* sites,
+                 std::vector<uint16_t>* cm_of_site) {
+  const uint32_t N = L * L * L, half = N / 2;
+  sites->assign(N, SiteEntry{});
+  cm_of_site->assign(N, 0);
+  auto cm_of = [&](uint32_t x, uint32_t y, uint32_t z) {
+    uint32_t s = x + L * (y + L * z);
+    return ((x + y + z) & 1u) * half + (s >> 1);
+  };
+  for (uint32_t z = 0; z < L; ++z)
+    for (uint32_t y = 0; y < L; ++y)
+      for (uint32_t x = 0; x < L; ++x) {
+        const uint32_t s = x + L * (y + L * z);
+        const uint32_t cm = cm_of(x, y, z);
+        (*cm_of_site)[s] = (uint16_t)cm;
+        SiteEntry e{};
+        const uint32_t xp = (x + 1) % L, xm = (x + L - 1) % L;
+        const uint32_t yp = (y + 1) % L, ym = (y + L - 1) % L;
+        const uint32_t zp = (z + 1) % L, zm = (z + L - 1) % L;
+        e.nb[0] = (uint16_t)cm_of(xp, y, z);
+        e.nb[1] = (uint16_t)cm_of(xm, y, z);
+        e.nb[2] = (uint16_t)cm_of(x, yp, z);
+        e.nb[3] = (uint16_t)cm_of(x, ym, z);
+        e.nb[4] = (uint16_t)cm_of(x, y, zp);
+        e.nb[5] = (uint16_t)cm_of(x, y, zm);
+        // bond d*N + site joins site and site + e_d
+        const int8_t jb[6] = {J[0 * N + s], J[0 * N + (xm + L * (y + L * z))],
+                              J[1 * N + s], J[1 * N + (x + L * (ym + L * z))],
+                              J[2 * N + s], J[2 * N + (x + L * (y + L * zm))]};
+        uint16_t neg = 0;
+        for (int k = 0; k < 6; ++k)
+          if (jb[k] < 0) neg |= (uint16_t)(1u << k);
+        e.jneg = neg;
+        e.site = (uint16_t)s;
+        (*sites)[cm] = e;
+      }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 resampling table of one step (Sec. II, Eqs. 1-2).  With the lowest
+// occupied level j_min as reference energy:
+//   w_j = exp(-dbeta * 2 (j - j_min)),  S = sum_{j ascending, h_j > 0} h_j w_j,
+//   tau_j = R w_j / S,  fl_j = floor(tau_j),  T_j = ceil(frac(tau_j) 2^53),
+//   ln Q = ln S - ln R~ - dbeta E_min,  E_min = 2 j_min - 3N.
+// ---------------------------------------------------------------------------
+struct Table {
+  int jmin = -1;
+  double S = 0.0, lnQ = 0.0;
+};
+
+Table resample_table(const uint32_t* h, uint32_t n_levels, uint32_t N, uint32_t R, uint32_t R_tilde,
+                     double dbeta, uint32_t* fl, uint64_t* T) {
+  Table t;
+  for (uint32_t j = 0; j < n_levels; ++j)
+    if (h[j] > 0) {
+      t.jmin = (int)j;
+      break;
+    }
+  if (t.jmin < 0) return t;
+  const int jmin = t.jmin;
+  double S = 0.0;
+  for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
+    if (h[j] == 0) continue;
+    const double w = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
+    S = S + (double)h[j] * w;
+  }
+  for (uint32_t j = 0; j < n_levels; ++j) {
+    if ((int)j < jmin) {
+      fl[j] = 0;
+      T[j] = 0;
+      continue;
+    }
+    const double w = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
+    const double tau = ((double)R * w) / S;
+    const uint64_t f = (uint64_t)std::floor(tau);
+    const double fr = tau - (double)f;
+    fl[j] = (uint32_t)f;
+    T[j] = (uint64_t)std::ceil(std::ldexp(fr, 53));
+  }
+  t.S = S;
+  t.lnQ = std::log(S) - std::log((double)R_tilde) - dbeta * (double)(2 * jmin - 3 * (int)N);
+  return t;
+}
+
+// Culling fraction (Sec. III.C): eps R = sum_{tau_i < 1} (1 - tau_i), tau_j
+// exactly as in resample_table.
+double culling_fraction(const uint32_t* h, uint32_t n_levels, uint32_t R, double dbeta) {
+  int jmin = -1;
+  for (uint32_t j = 0; j < n_levels; ++j)
+    if (h[j] > 0) {
+      jmin = (int)j;
+      break;
+    }
+  if (jmin < 0) return 0.0;
+  double S = 0.0;
+  for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
+    if (h[j] == 0) continue;
+    const double w = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
+    S = S + (double)h[j] * w;
+  }
+  double acc = 0.0;
+  for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
+    if (h[j] == 0) continue;
+    const double w = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
+    const double tau = ((double)R * w) / S;
+    if (tau < 1.0) acc = acc + (double)h[j] * (1.0 - tau);
+  }
+  return acc / (double)R;
+}
+
+// Metropolis thresholds: accept dE > 0 iff word < floor(2^32 exp(-beta dE)).
+void thresholds(double beta, uint64_t thr[3]) {
+  for (int i = 0; i < 3; ++i) {
+    const double dE = (double)(4 * (i + 1));
+    thr[i] = (uint64_t)std::floor(std::ldexp(std::exp(-beta * dE), 32));
+  }
+}
+
+}  // namespace
+
+struct pa_instance {
+  Layout lay;
+  DevPop dev;
+  hipStream_t stream = nullptr;
+  uint8_t* ws = nullptr;
+  std::vector<SiteEntry> sites;
+  std::vector<uint16_t> cm_of_site;
+  // host mirror of the population state
+  uint32_t cur = 0;
+  uint32_t R_tilde = 0;
+  uint64_t sweeps = 0;
+  uint32_t step = 0;
+  double beta = 0.0, sum_lnQ = 0.0;
+  double last_dbeta = 0.0, last_lnQ = 0.0, last_eps = 0.0;
+  uint32_t last_n_culled = 0, last_R_old = 0;
+  bool pending_gather = false;
+  bool hist_valid = false;
+  bool failed = false;
+  // pinned staging
+  uint32_t* h_hist = nullptr;
+  uint32_t* h_fl = nullptr;
+  uint64_t* h_T = nullptr;
+  DevScalars* h_sc = nullptr;
+  unsigned long long* h_ovl = nullptr;
+};
+
+namespace {
+
+int dev_fail(pa_instance* in) {
+  in->failed = true;
+  return PA_EDEVICE;
+}
+
+#define PA_HIP(in, call)                      \
+  do {                                        \
+    if ((call) != hipSuccess) return dev_fail(in); \
+  } while (0)
+
+// Apply a pending order-preserving copy without sweeping (buffer swap).
+int materialize(pa_instance* in) {
+  if (!in->pending_gather) return PA_OK;
+  pa::SweepParams sp{};
+  sp.thr[0] = sp.thr[1] = sp.thr[2] = 1ull << 32;
+  sp.t0 = (uint32_t)in->sweeps;
+  sp.n_sweeps = 0;
+  sp.gather = 1;
+  sp.cur = in->cur;
+  PA_HIP(in, pa::launch_sweep(in->dev, sp, in->stream));
+  in->cur ^= 1u;
+  in->pending_gather = false;
+  in->hist_valid = false;
+  return PA_OK;
+}
+
+// Histogram of the current population into in->h_hist, plus the device
+// scalars into in->h_sc.  Synchronises.
+int fetch_hist(pa_instance* in, bool with_family) {
+  int rc = materialize(in);
+  if (rc) return rc;
+  const DevPop& P = in->dev;
+  PA_HIP(in, pa::launch_fill_u32(P.hist, 0u, P.n_levels, in->stream));
+  PA_HIP(in, pa::launch_hist(P, in->cur, in->stream));
+  if (with_family) {
+    // sum_eta2 (2 words) and n_families (1 word)
+    PA_HIP(in, pa::launch_fill_u32(reinterpret_cast<uint32_t*>(&P.sc->sum_eta2), 0u, 3, in->stream));
+    PA_HIP(in, pa::launch_family(P, in->cur, in->stream));
+  }
+  PA_HIP(in, hipMemcpyAsync(in->h_hist, P.hist, (size_t)P.n_levels * 4, hipMemcpyDeviceToHost,
+                            in->stream));
+  PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
+  PA_HIP(in, hipStreamSynchronize(in->stream));
+  in->R_tilde = in->h_sc->R_tilde;
+  in->hist_valid = true;
+  return PA_OK;
+}
+
+bool usable(pa_instance* in) { return in && !in->failed; }
+
+}  // namespace
+
+extern "C" {
+
+size_t pa_workspace_bytes(const pa_params* p) {
+  Layout l;
+  if (!make_layout(p, &l)) return 0;
+  return l.total;
+}
+
+const char* pa_strerror(int status) {
+  switch (status) {
+    case PA_OK: return "ok";
+    case PA_EINVAL: return "invalid argument";
+    case PA_ENOMEM: return "workspace too small";
+    case PA_ECAPACITY: return "resampled population exceeds capacity";
+    case PA_EDEVICE: return "HIP error (instance unusable)";
+    case PA_ESTATE: return "call out of order or instance unusable";
+    case PA_ESCHEDULE: return "constant-culling step impossible (eps(0) > target)";
+    default: return "unknown status";
+  }
+}
+
+int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace, size_t ws_bytes,
+                     void* hip_stream, pa_instance** out) {
+  if (!out) return PA_EINVAL;
+  *out = nullptr;
+  Layout l;
+  if (!make_layout(p, &l) || !J_host || !d_workspace) return PA_EINVAL;
+  if (ws_bytes < l.total) return PA_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return PA_EINVAL;
+  for (uint32_t b = 0; b < 3 * l.N; ++b)
+    if (J_host[b] != 1 && J_host[b] != -1) return PA_EINVAL;
+
+  pa_instance* in = new (std::nothrow) pa_instance();
+  if (!in) return PA_EINVAL;
+  in->lay = l;
+  in->stream = static_cast<hipStream_t>(hip_stream);
+  in->ws = static_cast<uint8_t*>(d_workspace);
+  build_sites(l.L, J_host, &in->sites, &in->cm_of_site);
+
+  DevPop& P = in->dev;
+  P.L = l.L;
+  P.N = l.N;
+  P.R = l.R;
+  P.capacity = l.capacity;
+  P.layout = l.layout;
+  P.n_levels = l.n_levels;
+  P.n_blocks = l.n_blocks;
+  P.cap_limit = l.cap_limit;
+  P.seed = p->seed;
+  uint8_t* w = in->ws;
+  for (int b = 0; b < 2; ++b) {
+    P.spins[b] = w + l.off_spins[b];
+    P.U[b] = reinterpret_cast<uint32_t*>(w + l.off_U[b]);
+    P.fam[b] = reinterpret_cast<uint32_t*>(w + l.off_fam[b]);
+  }
+  P.counts = reinterpret_cast<uint32_t*>(w + l.off_counts);
+  P.offsets = reinterpret_cast<uint32_t*>(w + l.off_offsets);
+  P.src = reinterpret_cast<uint32_t*>(w + l.off_src);
+  P.block_sums = reinterpret_cast<uint32_t*>(w + l.off_bsum);
+  P.block_offsets = reinterpret_cast<uint32_t*>(w + l.off_boff);
+  P.block_culled = reinterpret_cast<uint32_t*>(w + l.off_bcull);
+  P.hist = reinterpret_cast<uint32_t*>(w + l.off_hist);
+  P.table_fl = reinterpret_cast<uint32_t*>(w + l.off_fl);
+  P.table_T = reinterpret_cast<unsigned long long*>(w + l.off_T);
+  P.sites = reinterpret_cast<const SiteEntry*>(w + l.off_sites);
+  P.cm_of_site = reinterpret_cast<const uint16_t*>(w + l.off_cm);
+  P.ovl_hist = reinterpret_cast<unsigned long long*>(w + l.off_ovl);
+  P.sc = reinterpret_cast<DevScalars*>(w + l.off_sc);
+
+  auto fail = [&](int rc) {
+    pa_free(in);
+    return rc;
+  };
+  if (hipHostMalloc(reinterpret_cast<void**>(&in->h_hist), (size_t)l.n_levels * 4) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&in->h_fl), (size_t)l.n_levels * 4) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&in->h_T), (size_t)l.n_levels * 8) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&in->h_sc), sizeof(DevScalars)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&in->h_ovl), 65 * 8) != hipSuccess)
+    return fail(PA_EDEVICE);
+
+  // tables and scalars (synchronous copies from pageable host memory)
+  DevScalars sc{};
+  sc.R_tilde = l.R;
+  if (hipMemcpyAsync(w + l.off_sites, in->sites.data(), l.N * sizeof(SiteEntry),
+                     hipMemcpyHostToDevice, in->stream) != hipSuccess ||
+      hipMemcpyAsync(w + l.off_cm, in->cm_of_site.data(), l.N * 2, hipMemcpyHostToDevice,
+                     in->stream) != hipSuccess ||
+      hipMemcpyAsync(P.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, in->stream) != hipSuccess ||
+      hipStreamSynchronize(in->stream) != hipSuccess)
+    return fail(PA_EDEVICE);
+  if (pa::launch_init(P, 0, in->stream) != hipSuccess) return fail(PA_EDEVICE);
+  in->cur = 0;
+  in->R_tilde = l.R;
+  *out = in;
+  return PA_OK;
+}
+
+int pa_free(pa_instance* in) {
+  if (!in) return PA_EINVAL;
+  (void)hipStreamSynchronize(in->stream);
+  if (in->h_hist) (void)hipHostFree(in->h_hist);
+  if (in->h_fl) (void)hipHostFree(in->h_fl);
+  if (in->h_T) (void)hipHostFree(in->h_T);
+  if (in->h_sc) (void)hipHostFree(in->h_sc);
+  if (in->h_ovl) (void)hipHostFree(in->h_ovl);
+  delete in;
+  return PA_OK;
+}
+
+int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps) {
+  if (!usable(in)) return PA_ESTATE;
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return PA_EINVAL;
+  if (n_sweeps == 0) return PA_OK;
+  if (in->sweeps + n_sweeps > 0xFFFFFFFFull) return PA_EINVAL;  // sweep counter is 32-bit
+  pa::SweepParams sp{};
+  thresholds(beta, sp.thr);
+  sp.t0 = (uint32_t)in->sweeps;
+  sp.n_sweeps = n_sweeps;
+  sp.gather = in->pending_gather ? 1u : 0u;
+  sp.cur = in->cur;
+  PA_HIP(in, pa::launch_sweep(in->dev, sp, in->stream));
+  in->cur ^= 1u;
+  in->pending_gather = false;
+  in->hist_valid = false;
+  in->sweeps += n_sweeps;
+  return PA_OK;
+}
+
+int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
+  if (!usable(in)) return PA_ESTATE;
+  if (!std::isfinite(beta_next)) return PA_EINVAL;
+  int rc;
+  if (!in->hist_valid || in->pending_gather) {
+    rc = fetch_hist(in, false);
+    if (rc) return rc;
+  }
+  const DevPop& P = in->dev;
+  const double dbeta = beta_next - in->beta;
+  const Table t = resample_table(in->h_hist, P.n_levels, P.N, P.R, in->R_tilde, dbeta, in->h_fl,
+                                 in->h_T);
+  if (t.jmin < 0) return PA_ESTATE;  // empty population
+  const double eps = culling_fraction(in->h_hist, P.n_levels, P.R, dbeta);
+  PA_HIP(in, hipMemcpyAsync(P.table_fl, in->h_fl, (size_t)P.n_levels * 4, hipMemcpyHostToDevice,
+                            in->stream));
+  PA_HIP(in, hipMemcpyAsync(P.table_T, in->h_T, (size_t)P.n_levels * 8, hipMemcpyHostToDevice,
+                            in->stream));
+  PA_HIP(in, pa::launch_counts(P, in->cur, in->step + 1, in->stream));
+  PA_HIP(in, pa::launch_scan(P, in->stream));
+  PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
+  PA_HIP(in, hipStreamSynchronize(in->stream));
+  if (in->h_sc->err) return PA_ECAPACITY;  // population untouched
+  PA_HIP(in, pa::launch_scatter(P, in->stream));
+  in->last_R_old = in->R_tilde;
+  in->R_tilde = in->h_sc->R_next;
+  in->last_n_culled = in->h_sc->n_culled;
+  in->last_dbeta = dbeta;
+  in->last_lnQ = t.lnQ;
+  in->last_eps = eps;
+  in->sum_lnQ = in->sum_lnQ + t.lnQ;
+  in->beta = beta_next;
+  in->step += 1;
+  in->pending_gather = true;
+  in->hist_valid = false;
+  if (step_out) {
+    std::memset(step_out, 0, sizeof(*step_out));
+    step_out->beta = in->beta;
+    step_out->dbeta = dbeta;
+    step_out->lnQ = t.lnQ;
+    step_out->beta_F = -((double)P.N * std::log(2.0) + in->sum_lnQ);
+    step_out->eps_expected = eps;
+    step_out->R_tilde = in->R_tilde;
+    step_out->n_culled = in->last_n_culled;
+    step_out->step = in->step;
+    step_out->sweeps_done = in->sweeps;
+  }
+  return PA_OK;
+}
+
+int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* beta_next) {
+  if (!usable(in)) return PA_ESTATE;
+  if (!beta_next || !std::isfinite(eps_target) || !std::isfinite(beta_max) || eps_target < 0.0)
+    return PA_EINVAL;
+  if (!(beta_max > in->beta)) return PA_EINVAL;
+  if (!in->hist_valid || in->pending_gather) {
+    int rc = fetch_hist(in, false);
+    if (rc) return rc;
+  }
+  const uint32_t nl = in->dev.n_levels, R = in->dev.R;
+  const uint32_t* h = in->h_hist;
+  if (culling_fraction(h, nl, R, 0.0) > eps_target) return PA_ESCHEDULE;
+  const double rem = beta_max - in->beta;
+  if (culling_fraction(h, nl, R, rem) <= eps_target) {
+    *beta_next = beta_max;
+    return PA_OK;
+  }
+  double lo = 0.0, hi = rem;
+  for (int it = 0; it < 64; ++it) {
+    const double mid = lo + 0.5 * (hi - lo);
+    if (culling_fraction(h, nl, R, mid) <= eps_target) lo = mid;
+    else hi = mid;
+  }
+  *beta_next = in->beta + lo;
+  return PA_OK;
+}
+
+int pa_observables(pa_instance* in, pa_obs* out) {
+  if (!usable(in)) return PA_ESTATE;
+  if (!out) return PA_EINVAL;
+  int rc = fetch_hist(in, true);
+  if (rc) return rc;
+  const DevPop& P = in->dev;
+  const uint32_t* h = in->h_hist;
+  int64_t sumE = 0;
+  int jmin = -1;
+  for (uint32_t j = 0; j < P.n_levels; ++j) {
+    if (h[j] && jmin < 0) jmin = (int)j;
+    sumE += (int64_t)h[j] * (2 * (int64_t)j - 3 * (int64_t)P.N);
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->beta = in->beta;
+  out->dbeta = in->last_dbeta;
+  out->lnQ = in->last_lnQ;
+  out->beta_F = -((double)P.N * std::log(2.0) + in->sum_lnQ);
+  out->mean_E = in->R_tilde ? (double)sumE / (double)in->R_tilde : 0.0;
+  out->sum_eta2 = in->h_sc->sum_eta2;
+  out->rho_t = (double)out->sum_eta2 / (double)P.R;
+  out->eps_expected = in->last_eps;
+  out->R_tilde = in->R_tilde;
+  out->n_culled = in->last_n_culled;
+  out->E_min = jmin >= 0 ? 2 * jmin - 3 * (int)P.N : 0;
+  out->step = in->step;
+  out->sweeps_done = in->sweeps;
+  return PA_OK;
+}
+
+int pa_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hist_out) {
+  if (!usable(a) || !usable(b)) return PA_ESTATE;
+  if (nbins != 65 || !hist_out || a == b) return PA_EINVAL;
+  if (a->dev.L != b->dev.L || a->dev.layout != b->dev.layout) return PA_EINVAL;
+  int rc = materialize(a);
+  if (rc) return rc;
+  rc = materialize(b);
+  if (rc) return rc;
+  PA_HIP(b, hipStreamSynchronize(b->stream));
+  PA_HIP(a, pa::launch_fill_u32(reinterpret_cast<uint32_t*>(a->dev.ovl_hist), 0u, 130, a->stream));
+  PA_HIP(a, pa::launch_overlap(a->dev, a->cur, b->dev, b->cur, a->dev.ovl_hist, a->stream));
+  PA_HIP(a, hipMemcpyAsync(a->h_ovl, a->dev.ovl_hist, 65 * 8, hipMemcpyDeviceToHost, a->stream));
+  PA_HIP(a, hipStreamSynchronize(a->stream));
+  for (int i = 0; i < 65; ++i) hist_out[i] = a->h_ovl[i];
+  return PA_OK;
+}
+
+int pa_export_state(pa_instance* in, int8_t* spins_host, uint32_t* U_host, uint32_t* family_host,
+                    uint32_t* R_tilde) {
+  if (!usable(in)) return PA_ESTATE;
+  if (!R_tilde) return PA_EINVAL;
+  int rc = materialize(in);
+  if (rc) return rc;
+  const DevPop& P = in->dev;
+  PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
+  PA_HIP(in, hipStreamSynchronize(in->stream));
+  const uint32_t R = in->h_sc->R_tilde;
+  in->R_tilde = R;
+  *R_tilde = R;
+  if (U_host && R)
+    PA_HIP(in, hipMemcpy(U_host, P.U[in->cur], (size_t)R * 4, hipMemcpyDeviceToHost));
+  if (family_host && R)
+    PA_HIP(in, hipMemcpy(family_host, P.fam[in->cur], (size_t)R * 4, hipMemcpyDeviceToHost));
+  if (spins_host && R) {
+    const uint32_t N = P.N, tiles = (R + 63) / 64;
+    const size_t tile_bytes = P.layout == PA_LAYOUT_BITPACK64 ? (size_t)N * 8 : (size_t)N * 64;
+    std::vector<uint8_t> raw((size_t)tiles * tile_bytes);
+    PA_HIP(in, hipMemcpy(raw.data(), P.spins[in->cur], raw.size(), hipMemcpyDeviceToHost));
+    for (uint32_t r = 0; r < R; ++r) {
+      const uint32_t tile = r >> 6, lane = r & 63u;
+      int8_t* dst = spins_host + (size_t)r * N;
+      for (uint32_t s = 0; s < N; ++s) {
+        const uint32_t cm = in->cm_of_site[s];
+        bool neg;
+        if (P.layout == PA_LAYOUT_BITPACK64) {
+          uint64_t wd;
+          std::memcpy(&wd, raw.data() + ((size_t)tile * N + cm) * 8, 8);
+          neg = (wd >> lane) & 1ull;
+        } else {
+          neg = (int8_t)raw[((size_t)tile * N + cm) * 64 + lane] < 0;
+        }
+        dst[s] = neg ? (int8_t)-1 : (int8_t)1;
+      }
+    }
+  }
+  return PA_OK;
+}
+
+int pa_export_counts(pa_instance* in, uint32_t* counts_host, uint32_t* offsets_host,
+                     uint32_t* n_old) {
+  if (!usable(in)) return PA_ESTATE;
+  if (!n_old) return PA_EINVAL;
+  *n_old = in->last_R_old;
+  if (in->step == 0) return PA_ESTATE;
+  PA_HIP(in, hipStreamSynchronize(in->stream));
+  const size_t n = in->last_R_old;
+  if (counts_host && n)
+    PA_HIP(in, hipMemcpy(counts_host, in->dev.counts, n * 4, hipMemcpyDeviceToHost));
+  if (offsets_host && n)
+    PA_HIP(in, hipMemcpy(offsets_host, in->dev.offsets, n * 4, hipMemcpyDeviceToHost));
+  return PA_OK;
+}
+
+int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* family_host,
+                    uint32_t R_tilde, uint64_t sweeps_done, uint32_t step, double beta,
+                    double sum_lnQ) {
+  if (!usable(in)) return PA_ESTATE;
+  const DevPop& P = in->dev;
+  if (!spins_host || !family_host || R_tilde > P.cap_limit || !std::isfinite(beta) ||
+      !std::isfinite(sum_lnQ) || sweeps_done > 0xFFFFFFFFull)
+    return PA_EINVAL;
+  for (uint32_t i = 0; i < R_tilde; ++i) {
+    if (family_host[i] >= P.R) return PA_EINVAL;
+    if (i && family_host[i] < family_host[i - 1]) return PA_EINVAL;  // labels must be sorted
+  }
+  const uint32_t N = P.N, tiles = (R_tilde + 63) / 64;
+  const size_t tile_bytes = P.layout == PA_LAYOUT_BITPACK64 ? (size_t)N * 8 : (size_t)N * 64;
+  std::vector<uint8_t> raw((size_t)tiles * tile_bytes, 0);
+  for (uint32_t r = 0; r < R_tilde; ++r) {
+    const uint32_t tile = r >> 6, lane = r & 63u;
+    const int8_t* s = spins_host + (size_t)r * N;
+    for (uint32_t site = 0; site < N; ++site) {
+      if (s[site] != 1 && s[site] != -1) return PA_EINVAL;
+      const uint32_t cm = in->cm_of_site[site];
+      if (P.layout == PA_LAYOUT_BITPACK64) {
+        if (s[site] < 0) raw[((size_t)tile * N + cm) * 8 + (lane >> 3)] |= (uint8_t)(1u << (lane & 7));
+      } else {
+        raw[((size_t)tile * N + cm) * 64 + lane] = (uint8_t)s[site];
+      }
+    }
+  }
+  int rc = materialize(in);  // drop nothing silently: finish a pending copy first
+  if (rc) return rc;
+  PA_HIP(in, hipStreamSynchronize(in->stream));
+  if (!raw.empty())
+    PA_HIP(in, hipMemcpy(P.spins[in->cur], raw.data(), raw.size(), hipMemcpyHostToDevice));
+  if (R_tilde)
+    PA_HIP(in, hipMemcpy(P.fam[in->cur], family_host, (size_t)R_tilde * 4, hipMemcpyHostToDevice));
+  DevScalars sc{};
+  sc.R_tilde = R_tilde;
+  PA_HIP(in, hipMemcpy(P.sc, &sc, sizeof(sc), hipMemcpyHostToDevice));
+  PA_HIP(in, pa::launch_energy(P, in->cur, in->stream));
+  PA_HIP(in, hipStreamSynchronize(in->stream));
+  in->R_tilde = R_tilde;
+  in->sweeps = sweeps_done;
+  in->step = step;
+  in->beta = beta;
+  in->sum_lnQ = sum_lnQ;
+  in->pending_gather = false;
+  in->hist_valid = false;
+  in->last_R_old = 0;
+  return PA_OK;
+}
+
+}  // extern "C"
