@@ -45,7 +45,7 @@ struct Layout {
   uint32_t L, N, R, cap_limit, capacity, layout, n_levels, n_blocks;
   size_t spins_bytes;
   size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
-      off_bcull, off_hist, off_fl, off_T, off_sites, off_cm, off_ovl, off_sc;
+      off_bcull, off_hist, off_fl, off_T, off_sites, off_cm, off_rowj, off_ovl, off_sc;
   size_t total;
 };
 
@@ -90,6 +90,7 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.off_T = take((size_t)l.n_levels * 8);
   l.off_sites = take((size_t)l.N * sizeof(SiteEntry));
   l.off_cm = take((size_t)l.N * 2);
+  l.off_rowj = take((size_t)2 * l.L * l.L * 8);
   l.off_ovl = take(65 * 8);
   l.off_sc = take(sizeof(DevScalars));
   l.total = o;
@@ -97,9 +98,12 @@ bool make_layout(const pa_params* p, Layout* out) {
   return true;
 }
 
-// Lattice tables of the colour-major order for even L.
+// Lattice tables of the colour-major order for even L: the per-site table,
+// lexicographic -> colour-major, and the per-row coupling words (colour c,
+// row (y, z): bit 6q + k for the bond from the row's q-th site of colour c,
+// x = 2q + ((c + y + z) & 1), to its neighbour k in the order +x,-x,+y,-y,+z,-z).
 void build_sites(uint32_t L, const int8_t* J, std::vector<SiteEntry>* sites,
-                 std::vector<uint16_t>* cm_of_site) {
+                 std::vector<uint16_t>* cm_of_site, std::vector<uint64_t>* rowj) {
   const uint32_t N = L * L * L, half = N / 2;
   sites->assign(N, SiteEntry{});
   cm_of_site->assign(N, 0);
@@ -133,6 +137,19 @@ void build_sites(uint32_t L, const int8_t* J, std::vector<SiteEntry>* sites,
         e.jneg = neg;
         e.site = (uint16_t)s;
         (*sites)[cm] = e;
+      }
+  rowj->assign((size_t)2 * L * L, 0);
+  for (uint32_t c = 0; c < 2; ++c)
+    for (uint32_t z = 0; z < L; ++z)
+      for (uint32_t y = 0; y < L; ++y) {
+        const uint32_t p = (c + y + z) & 1u;
+        uint64_t word = 0;
+        for (uint32_t q = 0; q < L / 2; ++q) {
+          const uint32_t x = 2 * q + p;
+          const uint32_t cm = c * half + ((x + L * (y + L * z)) >> 1);
+          word |= (uint64_t)(*sites)[cm].jneg << (6 * q);
+        }
+        (*rowj)[(size_t)c * L * L + y + L * z] = word;
       }
 }
 
@@ -225,6 +242,7 @@ struct pa_instance {
   uint8_t* ws = nullptr;
   std::vector<SiteEntry> sites;
   std::vector<uint16_t> cm_of_site;
+  std::vector<uint64_t> rowj;
   // host mirror of the population state
   uint32_t cur = 0;
   uint32_t R_tilde = 0;
@@ -335,7 +353,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   in->lay = l;
   in->stream = static_cast<hipStream_t>(hip_stream);
   in->ws = static_cast<uint8_t*>(d_workspace);
-  build_sites(l.L, J_host, &in->sites, &in->cm_of_site);
+  build_sites(l.L, J_host, &in->sites, &in->cm_of_site, &in->rowj);
 
   DevPop& P = in->dev;
   P.L = l.L;
@@ -364,6 +382,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   P.table_T = reinterpret_cast<unsigned long long*>(w + l.off_T);
   P.sites = reinterpret_cast<const SiteEntry*>(w + l.off_sites);
   P.cm_of_site = reinterpret_cast<const uint16_t*>(w + l.off_cm);
+  P.rowj = reinterpret_cast<const unsigned long long*>(w + l.off_rowj);
   P.ovl_hist = reinterpret_cast<unsigned long long*>(w + l.off_ovl);
   P.sc = reinterpret_cast<DevScalars*>(w + l.off_sc);
 
@@ -384,6 +403,8 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   if (hipMemcpyAsync(w + l.off_sites, in->sites.data(), l.N * sizeof(SiteEntry),
                      hipMemcpyHostToDevice, in->stream) != hipSuccess ||
       hipMemcpyAsync(w + l.off_cm, in->cm_of_site.data(), l.N * 2, hipMemcpyHostToDevice,
+                     in->stream) != hipSuccess ||
+      hipMemcpyAsync(w + l.off_rowj, in->rowj.data(), in->rowj.size() * 8, hipMemcpyHostToDevice,
                      in->stream) != hipSuccess ||
       hipMemcpyAsync(P.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, in->stream) != hipSuccess ||
       hipStreamSynchronize(in->stream) != hipSuccess)

@@ -67,6 +67,8 @@ struct DevPop {
   unsigned long long* table_T;  // n_levels: ceil(frac(tau_j) 2^53)
   const SiteEntry* sites;       // N entries, colour-major
   const uint16_t* cm_of_site;   // N entries: lexicographic site -> colour-major index
+  const unsigned long long* rowj;  // 2 L^2 row words: bit 6q + k set iff the bond from
+                                   // site q of row (colour, y, z) to neighbour k is -1
   unsigned long long* ovl_hist; // 65 bins, scratch of the overlap histogram
   DevScalars* sc;
 };

@@ -33,18 +33,26 @@ struct Words4 {
   uint32_t w[4];
 };
 
+// a ^ b ^ c in one VALU instruction (gfx950 v_bitop3_b32, truth table 0x96);
+// c must be wave-uniform (it is read from an SGPR).
+__device__ __forceinline__ uint32_t xor3_s(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
 __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                            uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo_a = 0xD2511F53u * c0;
-    const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo_b = 0xCD9E8D57u * c2;
-    const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
-    c0 = hi_b ^ c1 ^ k0;
-    c1 = lo_b;
-    c2 = hi_a ^ c3 ^ k1;
-    c3 = lo_a;
+    const uint64_t pa = (uint64_t)0xD2511F53u * c0;  // one v_mad_u64_u32
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = xor3_s((uint32_t)(pb >> 32), c1, k0);
+    const uint32_t n2 = xor3_s((uint32_t)(pa >> 32), c3, k1);
+    c0 = n0;
+    c1 = (uint32_t)pb;
+    c2 = n2;
+    c3 = (uint32_t)pa;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -147,47 +155,106 @@ __device__ uint32_t tile_energy(const uint32_t* lds, const SiteEntry* __restrict
   return U;
 }
 
-// One colour pass of the checkerboard Metropolis update on the LDS tile.
-// Sites of the colour are taken four at a time (consecutive colour-major
-// indices cm = 4g .. 4g+3 share one Philox call; word cm & 3 belongs to site
-// cm).  nu = number of unsatisfied bonds at the site; flipping changes the
-// energy by dE = 12 - 4 nu, so a move is accepted iff its draw is below
-// thr_of_nu[nu]: floor(2^32 exp(-beta dE)) for nu = 0, 1, 2 (dE = 12, 8, 4)
-// and 2^32 (always) for nu >= 3.
-__device__ void sweep_colour(uint32_t* lds, const unsigned long long* thr_of_nu,
-                             const SiteEntry* __restrict__ sites, uint32_t N, uint32_t colour,
-                             uint32_t slot, uint32_t t, bool any_draw, uint32_t k0, uint32_t k1) {
-  const uint32_t lane = lane_id();
-  const uint32_t h = lane >> 5, pos = lane & 31u;
-  const uint32_t half_n = N >> 1;
-  const uint32_t first = colour * half_n;
-  for (uint32_t g = 0; g < half_n; g += 4) {
-    // uniform by construction; readfirstlane lets the table load go scalar
-    const uint32_t cm0 = __builtin_amdgcn_readfirstlane(first + g);
-    uint32_t nu[4], own[4];
+// One colour pass of the checkerboard Metropolis update on the LDS tile,
+// walked row by row.  For even L, the sites of colour c in row (y, z) are
+// x = 2q + p, q = 0..L/2-1, p = (c + y + z) & 1, with colour-major indices
+// c*N/2 + (L/2)(y + L z) + q.  Their neighbours of the other colour are, in
+// that colour's rank order: +x at q' = (q + p) mod L/2 and -x at
+// (q + p - 1) mod L/2 of the same row, and rank q of the rows (y+-1, z) and
+// (y, z+-1).  With L a compile-time constant every neighbour is an immediate
+// offset from six per-row base addresses.
+//
+// nu = number of unsatisfied bonds at the site (bond unsatisfied iff own bit
+// ^ neighbour bit ^ [J = -1]); flipping changes the energy by dE = 12 - 4 nu,
+// so the move is accepted iff its draw is below thr_of_nu[nu]:
+// floor(2^32 exp(-beta dE)) for nu = 0, 1, 2 and 2^32 (always) for nu >= 3.
+// Consecutive colour-major indices 4g .. 4g+3 share one Philox call; word
+// cm & 3 belongs to site cm.  A group can straddle two rows, so the four words
+// are carried from row to row.
+struct RowCtx {
+  uint32_t* lds;
+  const unsigned long long* thr_of_nu;
+  uint32_t h, pos;       // this lane's half of a site word and its bit
+  uint32_t slot, t, k0, k1;
+  bool any_draw;
+  Words4 d;              // Philox words of the current site group
+};
+
+template <int L, int P, int PH>
+__device__ __forceinline__ void row_pass(RowCtx& c, uint32_t cm_row, uint32_t oth_x,
+                                         uint32_t oth_py, uint32_t oth_my, uint32_t oth_pz,
+                                         uint32_t oth_mz, unsigned long long jrow) {
+  constexpr int H = L / 2;
+  uint32_t* const a_own = c.lds + 2 * cm_row + c.h;
+  const uint32_t* const a_x = c.lds + 2 * oth_x + c.h;
+  const uint32_t* const a_py = c.lds + 2 * oth_py + c.h;
+  const uint32_t* const a_my = c.lds + 2 * oth_my + c.h;
+  const uint32_t* const a_pz = c.lds + 2 * oth_pz + c.h;
+  const uint32_t* const a_mz = c.lds + 2 * oth_mz + c.h;
+  const uint32_t jlo = (uint32_t)jrow, jhi = (uint32_t)(jrow >> 32);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const SiteWords e = load_site(sites, cm0 + q);
-      own[q] = lds[2 * (cm0 + q) + h];
-      uint32_t n = 0;
+  for (int q = 0; q < H; ++q) {
+    if (((PH + q) & 3) == 0 && c.any_draw)
+      c.d = philox10(c.slot, c.t, (cm_row + q) >> 2, kTagMet, c.k0, c.k1);
+    const uint32_t own = a_own[2 * q];
+    const uint32_t nb[6] = {a_x[2 * ((q + P) % H)], a_x[2 * ((q + P + H - 1) % H)],
+                            a_py[2 * q], a_my[2 * q], a_pz[2 * q], a_mz[2 * q]};
+    uint32_t n = 0;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        // bond to neighbour k is unsatisfied iff own bit ^ neighbour bit ^ (J = -1)
-        const uint32_t jm = ((e.jneg >> k) & 1u) ? 0xFFFFFFFFu : 0u;
-        n += bit_of(lds[2 * e.nb[k] + h] ^ own[q] ^ jm, pos);
-      }
-      nu[q] = n;
+    for (int k = 0; k < 6; ++k) {
+      const int bit = 6 * q + k;  // coupling bit of (site q, neighbour k) in the row word
+      const uint32_t jm = bit < 32 ? (uint32_t)((int32_t)(jlo << (31 - bit)) >> 31)
+                                   : (uint32_t)((int32_t)(jhi << (63 - bit)) >> 31);
+      n += __builtin_amdgcn_ubfe(xor3_s(nb[k], own, jm), c.pos, 1);
     }
-    Words4 d;
-    d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0u;
-    if (any_draw) d = philox10(slot, t, cm0 >> 2, kTagMet, k0, k1);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      // Lanes past the population (valid == false) update junk bits that are
-      // never read back as replicas; they cannot affect the valid lanes.
-      const unsigned long long f = __ballot((unsigned long long)d.w[q] < thr_of_nu[nu[q]]);
-      const uint32_t fh = h ? (uint32_t)(f >> 32) : (uint32_t)f;
-      if (pos == 0) lds[2 * (cm0 + q) + h] = own[q] ^ fh;
+    asm("" : "+v"(n));  // keep the table index a single value
+    const bool acc = (unsigned long long)c.d.w[(PH + q) & 3] < c.thr_of_nu[n];
+    const unsigned long long f = __ballot(acc);
+    const uint32_t fh = c.h ? (uint32_t)(f >> 32) : (uint32_t)f;
+    if (c.pos == 0) a_own[2 * q] = own ^ fh;
+  }
+}
+
+template <int L>
+__device__ void sweep_colour_rows(RowCtx& c, const unsigned long long* __restrict__ rowj,
+                                  uint32_t colour) {
+  constexpr uint32_t H = L / 2, N = L * L * L;
+  const uint32_t own0 = colour * (N / 2), oth0 = (colour ^ 1u) * (N / 2);
+  for (uint32_t z = 0; z < (uint32_t)L; ++z) {
+    const uint32_t zp = z + 1 == (uint32_t)L ? 0 : z + 1, zm = z == 0 ? L - 1 : z - 1;
+    for (uint32_t y = 0; y < (uint32_t)L; ++y) {
+      const uint32_t yp = y + 1 == (uint32_t)L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+      const uint32_t r0 = H * (y + L * z);
+      const uint32_t cm_row = __builtin_amdgcn_readfirstlane(own0 + r0);
+      const uint32_t ox = oth0 + r0;
+      const uint32_t opy = oth0 + H * (yp + L * z), omy = oth0 + H * (ym + L * z);
+      const uint32_t opz = oth0 + H * (y + L * zp), omz = oth0 + H * (y + L * zm);
+      const unsigned long long jrow = rowj[__builtin_amdgcn_readfirstlane(colour * L * L + y + L * z)];
+      const uint32_t p = (colour + y + z) & 1u;
+      const uint32_t ph = r0 & 3u;
+      // dispatch on the row parity and on where the row starts inside a group
+      if constexpr (H % 4 == 0) {
+        if (p) row_pass<L, 1, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow);
+        else row_pass<L, 0, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow);
+      } else if constexpr (H % 2 == 0) {
+        switch (p * 4 + ph) {
+          case 0: row_pass<L, 0, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          case 2: row_pass<L, 0, 2>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          case 4: row_pass<L, 1, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          default: row_pass<L, 1, 2>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+        }
+      } else {
+        switch (p * 4 + ph) {
+          case 0: row_pass<L, 0, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          case 1: row_pass<L, 0, 1>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          case 2: row_pass<L, 0, 2>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          case 3: row_pass<L, 0, 3>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          case 4: row_pass<L, 1, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          case 5: row_pass<L, 1, 1>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          case 6: row_pass<L, 1, 2>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+          default: row_pass<L, 1, 3>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
+        }
+      }
     }
   }
   __syncthreads();
@@ -380,9 +447,11 @@ __global__ __launch_bounds__(kBlockCounts) void k_scatter(DevPop P) {
 
 // Gather (optional) + n_sweeps checkerboard Metropolis sweeps + energy, one
 // wavefront per 64-replica tile.  Reads buffer cur, writes buffer cur ^ 1.
-template <int LAYOUT>
+template <int LAYOUT, int L>
 __global__ __launch_bounds__(64) void k_sweep(DevPop P, SweepParams sp,
-                                              const SiteEntry* __restrict__ sites) {
+                                              const SiteEntry* __restrict__ sites,
+                                              const unsigned long long* __restrict__ rowj) {
+  constexpr uint32_t N = L * L * L;
   extern __shared__ uint32_t lds[];
   __shared__ unsigned long long thr_of_nu[8];
   const uint32_t tile = blockIdx.x;
@@ -391,22 +460,31 @@ __global__ __launch_bounds__(64) void k_sweep(DevPop P, SweepParams sp,
   const uint32_t Rs = sp.gather ? P.sc->R_next : P.sc->R_tilde;
   if (tile * 64 >= Rs) return;
   if (lane < 8) thr_of_nu[lane] = lane < 3 ? sp.thr[2 - lane] : (1ull << 32);
-  const bool any_draw = (sp.thr[0] != 0 && sp.thr[0] < (1ull << 32)) ||
-                        (sp.thr[1] != 0 && sp.thr[1] < (1ull << 32)) ||
-                        (sp.thr[2] != 0 && sp.thr[2] < (1ull << 32));
   const uint32_t j = tile * 64 + lane;
   const bool valid = j < Rs;
   const uint32_t src = valid ? (sp.gather ? P.src[j] : j) : 0u;
   const uint32_t cur = sp.cur, nxt = cur ^ 1u;
-  load_tile_gather<LAYOUT>(lds, P.spins[cur], P.N, src, valid);
-  const uint32_t k0 = (uint32_t)P.seed, k1 = (uint32_t)(P.seed >> 32);
+  load_tile_gather<LAYOUT>(lds, P.spins[cur], N, src, valid);
+  RowCtx c;
+  c.lds = lds;
+  c.thr_of_nu = thr_of_nu;
+  c.h = lane >> 5;
+  c.pos = lane & 31u;
+  c.slot = j;
+  c.k0 = (uint32_t)P.seed;
+  c.k1 = (uint32_t)(P.seed >> 32);
+  // a draw matters only for a class whose threshold is neither 0 nor 2^32
+  c.any_draw = (sp.thr[0] != 0 && sp.thr[0] < (1ull << 32)) ||
+               (sp.thr[1] != 0 && sp.thr[1] < (1ull << 32)) ||
+               (sp.thr[2] != 0 && sp.thr[2] < (1ull << 32));
+  c.d.w[0] = c.d.w[1] = c.d.w[2] = c.d.w[3] = 0u;
   for (uint32_t s = 0; s < sp.n_sweeps; ++s) {
-    const uint32_t t = sp.t0 + s;
-    sweep_colour(lds, thr_of_nu, sites, P.N, 0u, j, t, any_draw, k0, k1);
-    sweep_colour(lds, thr_of_nu, sites, P.N, 1u, j, t, any_draw, k0, k1);
+    c.t = sp.t0 + s;
+    sweep_colour_rows<L>(c, rowj, 0u);
+    sweep_colour_rows<L>(c, rowj, 1u);
   }
-  const uint32_t U = tile_energy(lds, sites, P.N);
-  store_tile<LAYOUT>(lds, P.spins[nxt], P.N, tile);
+  const uint32_t U = tile_energy(lds, sites, N);
+  store_tile<LAYOUT>(lds, P.spins[nxt], N, tile);
   if (valid) {
     P.U[nxt][j] = U;
     P.fam[nxt][j] = P.fam[cur][src];
@@ -530,15 +608,33 @@ hipError_t launch_scatter(const DevPop& P, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(const DevPop& P, const SweepParams& sp, hipStream_t stream) {
+template <int LAYOUT>
+hipError_t launch_sweep_layout(const DevPop& P, const SweepParams& sp, hipStream_t stream) {
   const size_t lds = (size_t)P.N * 8;
-  if (P.layout == 2)
-    hipLaunchKernelGGL(k_sweep<2>, dim3(tiles_of(P.capacity)), dim3(64), lds, stream, P, sp,
-                       P.sites);
-  else
-    hipLaunchKernelGGL(k_sweep<1>, dim3(tiles_of(P.capacity)), dim3(64), lds, stream, P, sp,
-                       P.sites);
+  const dim3 grid(tiles_of(P.capacity)), block(64);
+  switch (P.L) {
+#define PA_SWEEP_CASE(LL)                                                                     \
+  case LL:                                                                                    \
+    hipLaunchKernelGGL((k_sweep<LAYOUT, LL>), grid, block, lds, stream, P, sp, P.sites,       \
+                       P.rowj);                                                               \
+    break;
+    PA_SWEEP_CASE(4)
+    PA_SWEEP_CASE(6)
+    PA_SWEEP_CASE(8)
+    PA_SWEEP_CASE(10)
+    PA_SWEEP_CASE(12)
+    PA_SWEEP_CASE(14)
+    PA_SWEEP_CASE(16)
+#undef PA_SWEEP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_sweep(const DevPop& P, const SweepParams& sp, hipStream_t stream) {
+  return P.layout == 2 ? launch_sweep_layout<2>(P, sp, stream)
+                       : launch_sweep_layout<1>(P, sp, stream);
 }
 
 hipError_t launch_family(const DevPop& P, uint32_t cur, hipStream_t stream) {
