@@ -51,7 +51,22 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c3")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times (used to "
+                         "scale the HBM byte counters of a profiler run)")
     return ap.parse_args()
+
+
+def copy_calibration(nbytes: int):
+    import torch
+
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
 
 
 def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None):
@@ -125,6 +140,9 @@ def main():
     import paper_1711_02146_amd as pam
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     pam.lib()
     w = WORKLOAD
     J = pa_inputs.couplings_pm(w["L"], pa_inputs.coupling_seed(3, 0))

@@ -164,6 +164,52 @@ int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* f
 /* Release the host-side handle (the caller frees the workspace afterwards). */
 int pa_free(pa_instance* in);
 
+/* ------------------------------------------------------------------------ */
+/* Batches: many populations (instances of any L, R and layout) advanced     */
+/* together through one temperature schedule (Sec. II loop), each step being */
+/* one replay of a captured HIP graph: device-side FP64 resampling tables    */
+/* (the exp weights come from the host's exp, one row per step), copy        */
+/* counts, scans, fused copy + sweeps for all populations, and the per-step  */
+/* records (sum of E, lowest E, size, sum of eta^2, ln Q inputs) and overlap */
+/* histograms of chosen population pairs.  Each population draws exactly the */
+/* numbers it would draw alone, so every result equals the result of the     */
+/* same calls made on the instance by itself (pa_resample + pa_sweep +       */
+/* pa_observables), bit for bit.                                             */
+/* ------------------------------------------------------------------------ */
+typedef struct pa_batch pa_batch;
+
+/* Device workspace for a batch of n_pops populations (largest L max_L),
+ * n_pairs overlap pairs and n_steps temperature steps.  0 on bad sizes. */
+size_t pa_batch_workspace_bytes(uint32_t n_pops, uint32_t n_pairs, uint32_t n_steps,
+                                uint32_t max_L);
+
+/* Build a batch over existing instances (all on the same HIP stream, none
+ * already in a batch, none with a pending copy step; their current beta must
+ * equal betas[0]).  betas: n_steps + 1 inverse temperatures, betas[0] the
+ * current one; each step resamples to betas[s] and runs n_sweeps sweeps there.
+ * pairs: 2 * n_pairs instance indices (same L and layout within a pair) whose
+ * overlap histogram (pa_overlap_hist's binning) is recorded after every step;
+ * may be NULL when n_pairs = 0.  The caller owns d_workspace
+ * (pa_batch_workspace_bytes bytes) until pa_batch_free.  Synchronises. */
+int pa_batch_create(pa_instance* const* pops, uint32_t n_pops, const uint32_t* pairs,
+                    uint32_t n_pairs, const double* betas, uint32_t n_steps, uint32_t n_sweeps,
+                    void* d_workspace, size_t ws_bytes, pa_batch** out);
+
+/* Run the next n_steps steps of the schedule (asynchronous: graph replays). */
+int pa_batch_run(pa_batch* b, uint32_t n_steps);
+
+/* Wait for the batch and fetch its results.  obs: [steps_done][n_pops]
+ * pa_obs records (nullable); qhist: [steps_done][n_pairs][65] counts
+ * (nullable); status: per population 0, or PA_ECAPACITY if a step would have
+ * overflowed its capacity (that population stopped before that step).
+ * *steps_done receives the number of steps run.  Afterwards each instance is
+ * at its last completed step and usable on its own again. */
+int pa_batch_results(pa_batch* b, pa_obs* obs, uint64_t* qhist, int32_t* status,
+                     uint32_t* steps_done);
+
+/* Release a batch (its instances stay valid). */
+int pa_batch_free(pa_batch* b);
+
 /* Static description of a status code. */
 const char* pa_strerror(int status);
 

@@ -85,6 +85,14 @@ def lib():
                                            ctypes.c_uint32, ctypes.c_double, ctypes.c_double]),
         "pa_free": (ctypes.c_int, [_vp]),
         "pa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "pa_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32,
+                                                       ctypes.c_uint32, ctypes.c_uint32]),
+        "pa_batch_create": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, ctypes.c_uint32, _vp,
+                                           ctypes.c_uint32, ctypes.c_uint32, _vp, ctypes.c_size_t,
+                                           _P(_vp)]),
+        "pa_batch_run": (ctypes.c_int, [_vp, ctypes.c_uint32]),
+        "pa_batch_results": (ctypes.c_int, [_vp, _vp, _vp, _vp, _P(ctypes.c_uint32)]),
+        "pa_batch_free": (ctypes.c_int, [_vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -96,7 +104,8 @@ def lib():
 
 EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample", "pa_choose_beta",
             "pa_observables", "pa_overlap_hist", "pa_export_state", "pa_export_counts",
-            "pa_import_state", "pa_free", "pa_strerror"]
+            "pa_import_state", "pa_free", "pa_strerror", "pa_batch_workspace_bytes",
+            "pa_batch_create", "pa_batch_run", "pa_batch_results", "pa_batch_free"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -187,6 +196,44 @@ def pa_free(handle: int):
     _check(lib().pa_free(handle), "pa_free")
 
 
+def pa_batch_workspace_bytes(n_pops: int, n_pairs: int, n_steps: int, max_L: int) -> int:
+    return int(lib().pa_batch_workspace_bytes(n_pops, n_pairs, n_steps, max_L))
+
+
+def pa_batch_create(handles, pairs, betas, n_sweeps: int, workspace_ptr: int,
+                    ws_bytes: int) -> int:
+    hs = (_vp * len(handles))(*handles)
+    pr = np.ascontiguousarray(np.asarray(pairs, np.uint32).reshape(-1))
+    bt = np.ascontiguousarray(betas, np.float64)
+    out = _vp()
+    _check(lib().pa_batch_create(ctypes.cast(hs, _vp), len(handles),
+                                 pr.ctypes.data if pr.size else None, pr.size // 2,
+                                 bt.ctypes.data, bt.size - 1, int(n_sweeps), workspace_ptr,
+                                 ws_bytes, ctypes.byref(out)), "pa_batch_create")
+    return out.value
+
+
+def pa_batch_run(batch: int, n_steps: int):
+    _check(lib().pa_batch_run(batch, int(n_steps)), "pa_batch_run")
+
+
+def pa_batch_results(batch: int, n_pops: int, n_pairs: int, max_steps: int):
+    """-> (records [steps][pops] of pa_obs dicts as a structured array, qhist, status)."""
+    obs = (pa_obs * (max_steps * n_pops))()
+    q = np.zeros((max_steps, max(n_pairs, 1), 65), np.uint64)
+    st = np.zeros(n_pops, np.int32)
+    done = ctypes.c_uint32(0)
+    _check(lib().pa_batch_results(batch, ctypes.cast(obs, _vp), q.ctypes.data if n_pairs else None,
+                                  st.ctypes.data, ctypes.byref(done)), "pa_batch_results")
+    n = done.value
+    recs = [[obs[s * n_pops + p].as_dict() for p in range(n_pops)] for s in range(n)]
+    return recs, q[:n, :n_pairs], st
+
+
+def pa_batch_free(batch: int):
+    _check(lib().pa_batch_free(batch), "pa_batch_free")
+
+
 # --- convenience object owning the workspace ---------------------------------
 class Population:
     """One PA population on a GPU: workspace tensor + library handle."""
@@ -242,3 +289,44 @@ class Population:
 
 def overlap_hist(a: Population, b: Population) -> np.ndarray:
     return pa_overlap_hist(a.handle, b.handle, 65)
+
+
+class Batch:
+    """Populations advanced together through one schedule (one graph replay per step).
+
+    The populations must live on a created (non-default) stream, share it, and
+    sit at betas[0].  ``pairs`` lists (a, b) index pairs whose overlap
+    histogram is recorded after every step.
+    """
+
+    def __init__(self, pops, betas, n_sweeps: int, pairs=()):
+        import torch
+
+        self.pops = list(pops)
+        self.n_pops = len(self.pops)
+        self.pairs = [tuple(p) for p in pairs]
+        self.n_steps = len(betas) - 1
+        max_L = max(p.L for p in self.pops)
+        nbytes = pa_batch_workspace_bytes(self.n_pops, len(self.pairs), self.n_steps, max_L)
+        if nbytes == 0:
+            raise PAError(PA_EINVAL, "pa_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.pops[0].device)
+        self.handle = pa_batch_create([p.handle for p in self.pops], self.pairs, betas, n_sweeps,
+                                      self.workspace.data_ptr(), nbytes)
+
+    def run(self, n_steps: int | None = None):
+        pa_batch_run(self.handle, self.n_steps if n_steps is None else n_steps)
+
+    def results(self):
+        return pa_batch_results(self.handle, self.n_pops, len(self.pairs), self.n_steps)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pa_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -22,11 +22,14 @@
 #include <vector>
 
 #include "../../include/pa.h"
+#include "pa_host_state.hpp"
 #include "pa_internal.hpp"
 
 using pa::DevPop;
 using pa::DevScalars;
 using pa::SiteEntry;
+
+using namespace pa_host;
 
 namespace {
 
@@ -40,14 +43,6 @@ uint32_t isqrt32(uint32_t v) {
   while ((uint64_t)(r + 1) * (r + 1) <= v) ++r;
   return r;
 }
-
-struct Layout {
-  uint32_t L, N, R, cap_limit, capacity, layout, n_levels, n_blocks;
-  size_t spins_bytes;
-  size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
-      off_bcull, off_hist, off_fl, off_T, off_sites, off_cm, off_rowj, off_ovl, off_sc;
-  size_t total;
-};
 
 bool make_layout(const pa_params* p, Layout* out) {
   if (!p) return false;
@@ -93,6 +88,8 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.off_rowj = take((size_t)2 * l.L * l.L * 8);
   l.off_ovl = take(65 * 8);
   l.off_sc = take(sizeof(DevScalars));
+  l.off_pops = take(2 * sizeof(DevPop));
+  l.off_meta = take(sizeof(MetaU32));
   l.total = o;
   *out = l;
   return true;
@@ -225,44 +222,33 @@ double culling_fraction(const uint32_t* h, uint32_t n_levels, uint32_t R, double
   return acc / (double)R;
 }
 
-// Metropolis thresholds: accept dE > 0 iff word < floor(2^32 exp(-beta dE)).
-void thresholds(double beta, uint64_t thr[3]) {
-  for (int i = 0; i < 3; ++i) {
-    const double dE = (double)(4 * (i + 1));
-    thr[i] = (uint64_t)std::floor(std::ldexp(std::exp(-beta * dE), 32));
-  }
-}
-
 }  // namespace
 
-struct pa_instance {
-  Layout lay;
-  DevPop dev;
-  hipStream_t stream = nullptr;
-  uint8_t* ws = nullptr;
-  std::vector<SiteEntry> sites;
-  std::vector<uint16_t> cm_of_site;
-  std::vector<uint64_t> rowj;
-  // host mirror of the population state
-  uint32_t cur = 0;
-  uint32_t R_tilde = 0;
-  uint64_t sweeps = 0;
-  uint32_t step = 0;
-  double beta = 0.0, sum_lnQ = 0.0;
-  double last_dbeta = 0.0, last_lnQ = 0.0, last_eps = 0.0;
-  uint32_t last_n_culled = 0, last_R_old = 0;
-  bool pending_gather = false;
-  bool hist_valid = false;
-  bool failed = false;
-  // pinned staging
-  uint32_t* h_hist = nullptr;
-  uint32_t* h_fl = nullptr;
-  uint64_t* h_T = nullptr;
-  DevScalars* h_sc = nullptr;
-  unsigned long long* h_ovl = nullptr;
-};
-
 namespace {
+
+pa::BatchDev one_set(const pa_instance* in, const pa::PopStep& ps) {
+  pa::BatchDev B{};
+  B.pops = in->d_pops;
+  B.n_pops = 1;
+  B.single = ps;
+  return B;
+}
+
+pa::Group group_of(const pa_instance* in, const uint32_t* d_start, uint32_t blocks) {
+  pa::Group g{};
+  g.pop = in->d_meta->pop0;
+  g.start = d_start;
+  g.n = 1;
+  g.blocks = blocks;
+  return g;
+}
+
+pa::PopStep plain_step(uint32_t cur) {
+  pa::PopStep ps{};
+  ps.thr[0] = ps.thr[1] = ps.thr[2] = 1ull << 32;
+  ps.cur = cur;
+  return ps;
+}
 
 int dev_fail(pa_instance* in) {
   in->failed = true;
@@ -277,13 +263,12 @@ int dev_fail(pa_instance* in) {
 // Apply a pending order-preserving copy without sweeping (buffer swap).
 int materialize(pa_instance* in) {
   if (!in->pending_gather) return PA_OK;
-  pa::SweepParams sp{};
-  sp.thr[0] = sp.thr[1] = sp.thr[2] = 1ull << 32;
-  sp.t0 = (uint32_t)in->sweeps;
-  sp.n_sweeps = 0;
-  sp.gather = 1;
-  sp.cur = in->cur;
-  PA_HIP(in, pa::launch_sweep(in->dev, sp, in->stream));
+  pa::PopStep ps = plain_step(in->cur);
+  ps.t0 = (uint32_t)in->sweeps;
+  ps.n_sweeps = 0;
+  ps.gather = 1;
+  PA_HIP(in, pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
+                              in->dev.layout, in->dev.L, in->stream));
   in->cur ^= 1u;
   in->pending_gather = false;
   in->hist_valid = false;
@@ -296,23 +281,24 @@ int fetch_hist(pa_instance* in, bool with_family) {
   int rc = materialize(in);
   if (rc) return rc;
   const DevPop& P = in->dev;
-  PA_HIP(in, pa::launch_fill_u32(P.hist, 0u, P.n_levels, in->stream));
-  PA_HIP(in, pa::launch_hist(P, in->cur, in->stream));
-  if (with_family) {
-    // sum_eta2 (2 words) and n_families (1 word)
-    PA_HIP(in, pa::launch_fill_u32(reinterpret_cast<uint32_t*>(&P.sc->sum_eta2), 0u, 3, in->stream));
-    PA_HIP(in, pa::launch_family(P, in->cur, in->stream));
-  }
+  const pa::BatchDev B = one_set(in, plain_step(in->cur));
+  PA_HIP(in, pa::launch_zero_acc(B, group_of(in, in->d_meta->perpop, 1), in->stream));
+  PA_HIP(in, pa::launch_hist(B, group_of(in, in->d_meta->hist, in->meta.hist[1]), P.n_levels, false,
+                             in->stream));
+  if (with_family)
+    PA_HIP(in, pa::launch_family(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), false,
+                                 in->stream));
   PA_HIP(in, hipMemcpyAsync(in->h_hist, P.hist, (size_t)P.n_levels * 4, hipMemcpyDeviceToHost,
                             in->stream));
   PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
+  if (in->h_sc->err == 2) return dev_fail(in);
   in->R_tilde = in->h_sc->R_tilde;
   in->hist_valid = true;
   return PA_OK;
 }
 
-bool usable(pa_instance* in) { return in && !in->failed; }
+bool usable(pa_instance* in) { return in && !in->failed && !in->in_batch; }
 
 }  // namespace
 
@@ -385,6 +371,17 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   P.rowj = reinterpret_cast<const unsigned long long*>(w + l.off_rowj);
   P.ovl_hist = reinterpret_cast<unsigned long long*>(w + l.off_ovl);
   P.sc = reinterpret_cast<DevScalars*>(w + l.off_sc);
+  in->d_pops = reinterpret_cast<DevPop*>(w + l.off_pops);
+  in->d_meta = reinterpret_cast<MetaU32*>(w + l.off_meta);
+  MetaU32& mt = in->meta;
+  mt.pop0[0] = 0; mt.pop0[1] = 1;
+  mt.perpop[0] = 0; mt.perpop[1] = 1;
+  mt.slots[0] = 0; mt.slots[1] = pa::blocks_slots(l.capacity);
+  mt.hist[0] = 0; mt.hist[1] = pa::blocks_hist(l.capacity);
+  mt.tiles[0] = 0; mt.tiles[1] = pa::blocks_sweep(l.capacity, l.L);
+  mt.etiles[0] = 0; mt.etiles[1] = l.capacity / 64;
+  mt.pair_pops[0] = 0; mt.pair_pops[1] = 1;
+  mt.pairs[0] = 0; mt.pairs[1] = 0;
 
   auto fail = [&](int rc) {
     pa_free(in);
@@ -394,7 +391,8 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
       hipHostMalloc(reinterpret_cast<void**>(&in->h_fl), (size_t)l.n_levels * 4) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_T), (size_t)l.n_levels * 8) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_sc), sizeof(DevScalars)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&in->h_ovl), 65 * 8) != hipSuccess)
+      hipHostMalloc(reinterpret_cast<void**>(&in->h_ovl), 65 * 8) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&in->h_meta), sizeof(MetaU32)) != hipSuccess)
     return fail(PA_EDEVICE);
 
   // tables and scalars (synchronous copies from pageable host memory)
@@ -407,6 +405,10 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
       hipMemcpyAsync(w + l.off_rowj, in->rowj.data(), in->rowj.size() * 8, hipMemcpyHostToDevice,
                      in->stream) != hipSuccess ||
       hipMemcpyAsync(P.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, in->stream) != hipSuccess ||
+      hipMemcpyAsync(in->d_pops, &in->dev, sizeof(DevPop), hipMemcpyHostToDevice, in->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(in->d_meta, &in->meta, sizeof(MetaU32), hipMemcpyHostToDevice, in->stream) !=
+          hipSuccess ||
       hipStreamSynchronize(in->stream) != hipSuccess)
     return fail(PA_EDEVICE);
   if (pa::launch_init(P, 0, in->stream) != hipSuccess) return fail(PA_EDEVICE);
@@ -424,6 +426,7 @@ int pa_free(pa_instance* in) {
   if (in->h_T) (void)hipHostFree(in->h_T);
   if (in->h_sc) (void)hipHostFree(in->h_sc);
   if (in->h_ovl) (void)hipHostFree(in->h_ovl);
+  if (in->h_meta) (void)hipHostFree(in->h_meta);
   delete in;
   return PA_OK;
 }
@@ -433,13 +436,13 @@ int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps) {
   if (!(beta >= 0.0) || !std::isfinite(beta)) return PA_EINVAL;
   if (n_sweeps == 0) return PA_OK;
   if (in->sweeps + n_sweeps > 0xFFFFFFFFull) return PA_EINVAL;  // sweep counter is 32-bit
-  pa::SweepParams sp{};
-  thresholds(beta, sp.thr);
-  sp.t0 = (uint32_t)in->sweeps;
-  sp.n_sweeps = n_sweeps;
-  sp.gather = in->pending_gather ? 1u : 0u;
-  sp.cur = in->cur;
-  PA_HIP(in, pa::launch_sweep(in->dev, sp, in->stream));
+  pa::PopStep ps = plain_step(in->cur);
+  thresholds(beta, ps.thr);
+  ps.t0 = (uint32_t)in->sweeps;
+  ps.n_sweeps = n_sweeps;
+  ps.gather = in->pending_gather ? 1u : 0u;
+  PA_HIP(in, pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
+                              in->dev.layout, in->dev.L, in->stream));
   in->cur ^= 1u;
   in->pending_gather = false;
   in->hist_valid = false;
@@ -465,12 +468,16 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
                             in->stream));
   PA_HIP(in, hipMemcpyAsync(P.table_T, in->h_T, (size_t)P.n_levels * 8, hipMemcpyHostToDevice,
                             in->stream));
-  PA_HIP(in, pa::launch_counts(P, in->cur, in->step + 1, in->stream));
-  PA_HIP(in, pa::launch_scan(P, in->stream));
+  pa::PopStep ps = plain_step(in->cur);
+  ps.step = in->step + 1;
+  const pa::BatchDev B = one_set(in, ps);
+  PA_HIP(in, pa::launch_counts(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
+  PA_HIP(in, pa::launch_scan(B, group_of(in, in->d_meta->perpop, 1), in->stream));
   PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
+  if (in->h_sc->err == 2) return dev_fail(in);
   if (in->h_sc->err) return PA_ECAPACITY;  // population untouched
-  PA_HIP(in, pa::launch_scatter(P, in->stream));
+  PA_HIP(in, pa::launch_scatter(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
   in->last_R_old = in->R_tilde;
   in->R_tilde = in->h_sc->R_next;
   in->last_n_culled = in->h_sc->n_culled;
@@ -563,8 +570,23 @@ int pa_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hi
   rc = materialize(b);
   if (rc) return rc;
   PA_HIP(b, hipStreamSynchronize(b->stream));
+  // a's set holds a in slot 0 and b in slot 1; one member pair, tiles of the smaller capacity
+  *a->h_meta = a->meta;
+  a->h_meta->pairs[1] = std::min(a->dev.capacity, b->dev.capacity) / 64;
+  PA_HIP(a, hipMemcpyAsync(a->d_pops + 1, &b->dev, sizeof(DevPop), hipMemcpyHostToDevice,
+                           a->stream));
+  PA_HIP(a, hipMemcpyAsync(a->d_meta, a->h_meta, sizeof(MetaU32), hipMemcpyHostToDevice,
+                           a->stream));
   PA_HIP(a, pa::launch_fill_u32(reinterpret_cast<uint32_t*>(a->dev.ovl_hist), 0u, 130, a->stream));
-  PA_HIP(a, pa::launch_overlap(a->dev, a->cur, b->dev, b->cur, a->dev.ovl_hist, a->stream));
+  pa::BatchDev B = one_set(a, plain_step(a->cur));
+  B.n_pops = 2;
+  pa::Group g{};
+  g.pop = a->d_meta->pop0;
+  g.start = a->d_meta->pairs;
+  g.n = 1;
+  g.blocks = a->h_meta->pairs[1];
+  PA_HIP(a, pa::launch_overlap(B, g, a->d_meta->pair_pops, a->dev.layout, false, a->cur, b->cur,
+                               a->stream));
   PA_HIP(a, hipMemcpyAsync(a->h_ovl, a->dev.ovl_hist, 65 * 8, hipMemcpyDeviceToHost, a->stream));
   PA_HIP(a, hipStreamSynchronize(a->stream));
   for (int i = 0; i < 65; ++i) hist_out[i] = a->h_ovl[i];
@@ -665,7 +687,9 @@ int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* f
   DevScalars sc{};
   sc.R_tilde = R_tilde;
   PA_HIP(in, hipMemcpy(P.sc, &sc, sizeof(sc), hipMemcpyHostToDevice));
-  PA_HIP(in, pa::launch_energy(P, in->cur, in->stream));
+  PA_HIP(in, pa::launch_energy(one_set(in, plain_step(in->cur)),
+                               group_of(in, in->d_meta->etiles, in->meta.etiles[1]), P.layout,
+                               P.L, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
   in->R_tilde = R_tilde;
   in->sweeps = sweeps_done;

@@ -1,0 +1,82 @@
+// pa_host_state.hpp -- host-side state of libpa instances, shared by the
+// single-instance C ABI (pa_host.cpp) and the batch engine (pa_batch.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/pa.h"
+#include "pa_internal.hpp"
+
+namespace pa_host {
+
+using pa::DevPop;
+using pa::DevScalars;
+using pa::SiteEntry;
+
+// Group tables of calls on one instance (two-entry start arrays {0, blocks}).
+struct MetaU32 {
+  uint32_t pop0[2];       // {0, 1}: member populations of a one-population set (+ partner)
+  uint32_t perpop[2];     // one workgroup
+  uint32_t slots[2];      // capacity / 256 workgroups
+  uint32_t hist[2];       // histogram workgroups
+  uint32_t tiles[2];      // sweep workgroups
+  uint32_t etiles[2];     // one-wave tiles (energy recompute)
+  uint32_t pair_pops[2];  // {0, 1}: the instance and its overlap partner
+  uint32_t pairs[2];      // overlap workgroups, set per call
+};
+
+struct Layout {
+  uint32_t L, N, R, cap_limit, capacity, layout, n_levels, n_blocks;
+  size_t spins_bytes;
+  size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
+      off_bcull, off_hist, off_fl, off_T, off_sites, off_cm, off_rowj, off_ovl, off_sc, off_pops,
+      off_meta;
+  size_t total;
+};
+
+// Metropolis thresholds: accept dE > 0 iff word < floor(2^32 exp(-beta dE)).
+inline void thresholds(double beta, unsigned long long thr[3]) {
+  for (int i = 0; i < 3; ++i) {
+    const double dE = (double)(4 * (i + 1));
+    thr[i] = (unsigned long long)std::floor(std::ldexp(std::exp(-beta * dE), 32));
+  }
+}
+
+}  // namespace pa_host
+
+struct pa_instance {
+  pa_host::Layout lay;
+  pa::DevPop dev;
+  pa::DevPop* d_pops = nullptr;      // device copy of dev (slot 0) and an overlap partner (slot 1)
+  pa_host::MetaU32* d_meta = nullptr;
+  pa_host::MetaU32 meta{};
+  hipStream_t stream = nullptr;
+  uint8_t* ws = nullptr;
+  std::vector<pa::SiteEntry> sites;
+  std::vector<uint16_t> cm_of_site;
+  std::vector<uint64_t> rowj;
+  // host mirror of the population state
+  uint32_t cur = 0;
+  uint32_t R_tilde = 0;
+  uint64_t sweeps = 0;
+  uint32_t step = 0;
+  double beta = 0.0, sum_lnQ = 0.0;
+  double last_dbeta = 0.0, last_lnQ = 0.0, last_eps = 0.0;
+  uint32_t last_n_culled = 0, last_R_old = 0;
+  bool pending_gather = false;
+  bool hist_valid = false;
+  bool failed = false;
+  // pinned staging
+  uint32_t* h_hist = nullptr;
+  uint32_t* h_fl = nullptr;
+  uint64_t* h_T = nullptr;
+  pa::DevScalars* h_sc = nullptr;
+  unsigned long long* h_ovl = nullptr;
+  pa_host::MetaU32* h_meta = nullptr;
+  bool in_batch = false;
+};
+

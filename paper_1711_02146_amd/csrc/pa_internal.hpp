@@ -3,6 +3,13 @@
 //
 // Method: Amey & Machta, arXiv:1711.02146 (Sec. II annealing loop, Eqs. 1-2
 // resampling, Sec. II.A model and observables, Sec. III.A rho_t).
+//
+// Every kernel works on a set of populations: a device array of DevPop plus a
+// Group that maps each workgroup to (member population, block within it).  A
+// single instance is a set of one.  Per-launch parameters come either by value
+// (calls on one instance) or from a device array indexed by a device step
+// counter, so that one captured graph can be replayed for every temperature
+// step of a batch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +26,7 @@ constexpr uint32_t kTagRes = 0x52455341u;   // copy-count draws
 
 constexpr int kWave = 64;          // wavefront width on gfx950; one spin tile = 64 replicas
 constexpr int kBlockCounts = 256;  // slots per block in the copy-count / scatter kernels
+constexpr int kHistSlots = 4096;   // slots per block of the histogram kernel
 constexpr int kMaxL = 16;
 
 // One lattice site in colour-major order (cm): colour-0 sites first, then
@@ -37,15 +45,17 @@ static_assert(sizeof(SiteEntry) == 16, "SiteEntry must be 16 bytes");
 struct DevScalars {
   uint32_t R_tilde;       // size of the current population
   uint32_t R_next;        // size after the pending copy step (written by the scan)
-  uint32_t err;           // 1: the pending copy step would exceed the capacity
+  uint32_t err;           // 1: the pending copy step would exceed the capacity;
+                          // 2: a kernel found its LDS layout unusable
   uint32_t n_culled;      // replicas with zero copies in the last resampling step
   unsigned long long sum_eta2;  // sum over families of eta^2
   uint32_t n_families;    // families with eta > 0
-  uint32_t pad[9];
+  uint32_t dead;          // batch runs: set when a step overflowed; later steps skip it
+  uint32_t pad[8];
 };
 static_assert(sizeof(DevScalars) == 64, "DevScalars is 64 bytes");
 
-// Device pointers of one population (all inside the caller's workspace).
+// Device pointers of one population (all inside its workspace).
 struct DevPop {
   uint32_t L, N, R, capacity;   // capacity: slots per buffer, a multiple of kBlockCounts
   uint32_t layout;              // PA_LAYOUT_INT8 or PA_LAYOUT_BITPACK64
@@ -73,26 +83,86 @@ struct DevPop {
   DevScalars* sc;
 };
 
-// Per-launch sweep parameters.
-struct SweepParams {
-  uint64_t thr[3];      // thresholds for dE = 4, 8, 12: accept iff word < thr
-  uint32_t t0;          // population sweep counter at the first sweep
+// Parameters of one population for one launch.
+struct PopStep {
+  unsigned long long thr[3];  // Metropolis thresholds (dE = 4, 8, 12): accept iff word < thr
+  const double* erow;         // device table path: erow[d] = exp(-dbeta * 2d), d = 0..3N
+  uint32_t t0;                // population sweep counter at the first sweep
   uint32_t n_sweeps;
-  uint32_t gather;      // 1: new slot j takes old slot src[j]; population size R_next
-  uint32_t cur;         // buffer holding the current population
+  uint32_t gather;            // 1: the sweep applies the pending copy step (size R_next)
+  uint32_t cur;               // buffer holding the population at the start of the launch
+  uint32_t step;              // resampling step index k (copy-count Philox counter)
+  uint32_t flags;             // kStepSticky: an overflow marks the population dead
+  uint32_t pad[2];
+};
+static_assert(sizeof(PopStep) == 64, "PopStep is 64 bytes");
+constexpr uint32_t kStepSticky = 1u;
+
+// What a batch records for one population at one temperature step.
+struct StepRecord {
+  double S;                // sum_j h_j w_j of the resampling table (Eq. 2, shifted)
+  double eps;              // culling fraction of the step (Sec. III.C)
+  long long sumE;          // sum over the post-sweep population of E (integer)
+  unsigned long long sum_eta2;
+  int32_t jmin;            // lowest occupied level before resampling
+  uint32_t R_old;          // population size before resampling
+  uint32_t R_new;          // population size after resampling and sweeps
+  uint32_t n_culled;
+  int32_t E_min;           // lowest energy after the sweeps
+  uint32_t status;         // 0 ok, 1 capacity overflow (population dead from here on)
+};
+static_assert(sizeof(StepRecord) == 56, "StepRecord is 56 bytes");
+
+// A set of populations as the kernels see it.
+struct BatchDev {
+  const DevPop* pops;         // n_pops descriptors
+  const PopStep* steps;       // per-step parameters [n][n_pops], or nullptr: use `single`
+  const uint32_t* step_ctr;   // index of the current step into `steps`
+  StepRecord* records;        // [n][n_pops] results of batch steps, or nullptr
+  unsigned long long* qhist;  // [n][n_pairs][65] overlap histograms, or nullptr
+  uint32_t n_pops;
+  uint32_t n_pairs;
+  PopStep single;             // parameters of a call on one population
+};
+
+// Workgroup -> population map of one launch: member m owns workgroups
+// start[m] .. start[m+1]-1 and is population pop[m] of the set.
+struct Group {
+  const uint32_t* pop;
+  const uint32_t* start;  // n + 1 entries, start[0] = 0
+  uint32_t n;
+  uint32_t blocks;        // start[n]
 };
 
 // Launchers (pa_kernels.hip).  All are asynchronous on `stream`.
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t stream);
 hipError_t launch_init(const DevPop& P, uint32_t cur, hipStream_t stream);
-hipError_t launch_hist(const DevPop& P, uint32_t cur, hipStream_t stream);
-hipError_t launch_counts(const DevPop& P, uint32_t cur, uint32_t step, hipStream_t stream);
-hipError_t launch_scan(const DevPop& P, hipStream_t stream);
-hipError_t launch_scatter(const DevPop& P, hipStream_t stream);
-hipError_t launch_sweep(const DevPop& P, const SweepParams& sp, hipStream_t stream);
-hipError_t launch_family(const DevPop& P, uint32_t cur, hipStream_t stream);
-hipError_t launch_overlap(const DevPop& A, uint32_t cur_a, const DevPop& B, uint32_t cur_b,
-                          unsigned long long* hist65, hipStream_t stream);
-hipError_t launch_energy(const DevPop& P, uint32_t cur, hipStream_t stream);
+hipError_t launch_zero_acc(const BatchDev& B, const Group& per_pop, hipStream_t stream);
+hipError_t launch_hist(const BatchDev& B, const Group& g, uint32_t max_levels, bool post,
+                       hipStream_t stream);
+hipError_t launch_table(const BatchDev& B, const Group& per_pop, hipStream_t stream);
+hipError_t launch_counts(const BatchDev& B, const Group& g, hipStream_t stream);
+hipError_t launch_scan(const BatchDev& B, const Group& per_pop, hipStream_t stream);
+hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream);
+// sweep launch over the populations of one (layout, L) group
+hipError_t launch_sweep(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
+                        hipStream_t stream);
+hipError_t launch_family(const BatchDev& B, const Group& g, bool post, hipStream_t stream);
+hipError_t launch_record(const BatchDev& B, const Group& per_pop, hipStream_t stream);
+// cur_a / cur_b: the two populations' buffers when B carries no per-step parameters
+hipError_t launch_overlap(const BatchDev& B, const Group& pairs, const uint32_t* pair_pops,
+                          uint32_t layout, bool post, uint32_t cur_a, uint32_t cur_b,
+                          hipStream_t stream);
+hipError_t launch_energy(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
+                         hipStream_t stream);
+hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream);
+
+// Blocks each population needs in each kind of launch.
+inline uint32_t blocks_hist(uint32_t capacity) { return (capacity + kHistSlots - 1) / kHistSlots; }
+inline uint32_t blocks_slots(uint32_t capacity) { return capacity / kBlockCounts; }
+uint32_t sweep_waves_for(uint32_t L);  // waves (tiles) per sweep workgroup
+inline uint32_t blocks_sweep(uint32_t capacity, uint32_t L) {
+  return capacity / 64 / sweep_waves_for(L);
+}
 
 }  // namespace pa

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "pa_internal.hpp"
 
@@ -88,30 +89,35 @@ __device__ __forceinline__ SiteWords load_site(const SiteEntry* __restrict__ sit
 // word of site cm (h = lane >> 5 holds lane's bit at position lane & 31).
 
 // New slot j (this lane) takes the spins of old slot src (a gather; src = j
-// for a plain copy).  Lanes with valid == false contribute zero bits.
-template <int LAYOUT>
-__device__ void load_tile_gather(uint32_t* lds, const void* spins_old, uint32_t N, uint32_t src,
-                                 bool valid) {
+// for a plain copy).  Lanes with valid == false contribute zero bits.  The
+// loads are issued eight sites at a time (N = L^3 is a multiple of 8 for even
+// L) so that many are in flight before their bits are balloted into LDS.
+template <int LAYOUT, uint32_t N>
+__device__ void load_tile_gather(uint32_t* lds, const void* spins_old, uint32_t src, bool valid) {
+  constexpr uint32_t B = 8;
+  static_assert(N % B == 0, "N must be a multiple of 8");
   const uint32_t lane = lane_id();
   const uint32_t stile = src >> 6;
-  if (LAYOUT == 2) {  // PA_LAYOUT_BITPACK64
-    const uint32_t* w32 = static_cast<const uint32_t*>(spins_old);
-    const size_t base = (size_t)stile * N * 2 + ((src >> 5) & 1u);
-    const uint32_t pos = src & 31u;
-    for (uint32_t cm = 0; cm < N; ++cm) {
-      const uint32_t b = valid ? bit_of(w32[base + 2 * (size_t)cm], pos) : 0u;
-      const unsigned long long m = __ballot(b);
-      if (lane == 0) {
-        lds[2 * cm] = (uint32_t)m;
-        lds[2 * cm + 1] = (uint32_t)(m >> 32);
-      }
+  const uint32_t pos = LAYOUT == 2 ? (src & 31u) : 0u;
+  const uint32_t* w32 = static_cast<const uint32_t*>(spins_old) + (size_t)stile * N * 2 +
+                        ((src >> 5) & 1u);
+  const int8_t* s8 = static_cast<const int8_t*>(spins_old) + (size_t)stile * N * 64 + (src & 63u);
+#pragma unroll 2
+  for (uint32_t cm0 = 0; cm0 < N; cm0 += B) {
+    uint32_t v[B];
+#pragma unroll
+    for (uint32_t i = 0; i < B; ++i) {
+      const uint32_t cm = cm0 + i;
+      if (LAYOUT == 2)
+        v[i] = w32[2 * (size_t)cm];
+      else
+        v[i] = (uint32_t)(uint8_t)s8[64 * (size_t)cm];
     }
-  } else {  // PA_LAYOUT_INT8
-    const int8_t* s8 = static_cast<const int8_t*>(spins_old);
-    const size_t base = (size_t)stile * N * 64 + (src & 63u);
-    for (uint32_t cm = 0; cm < N; ++cm) {
-      const uint32_t b = valid ? (s8[base + 64 * (size_t)cm] < 0 ? 1u : 0u) : 0u;
-      const unsigned long long m = __ballot(b);
+#pragma unroll
+    for (uint32_t i = 0; i < B; ++i) {
+      const uint32_t cm = cm0 + i;
+      const uint32_t b = LAYOUT == 2 ? bit_of(v[i], pos) : (v[i] >> 7);  // int8: sign bit
+      const unsigned long long m = __ballot(valid && b);
       if (lane == 0) {
         lds[2 * cm] = (uint32_t)m;
         lds[2 * cm + 1] = (uint32_t)(m >> 32);
@@ -155,114 +161,292 @@ __device__ uint32_t tile_energy(const uint32_t* lds, const SiteEntry* __restrict
   return U;
 }
 
-// One colour pass of the checkerboard Metropolis update on the LDS tile,
-// walked row by row.  For even L, the sites of colour c in row (y, z) are
-// x = 2q + p, q = 0..L/2-1, p = (c + y + z) & 1, with colour-major indices
-// c*N/2 + (L/2)(y + L z) + q.  Their neighbours of the other colour are, in
-// that colour's rank order: +x at q' = (q + p) mod L/2 and -x at
-// (q + p - 1) mod L/2 of the same row, and rank q of the rows (y+-1, z) and
-// (y, z+-1).  With L a compile-time constant every neighbour is an immediate
-// offset from six per-row base addresses.
-//
-// nu = number of unsatisfied bonds at the site (bond unsatisfied iff own bit
-// ^ neighbour bit ^ [J = -1]); flipping changes the energy by dE = 12 - 4 nu,
-// so the move is accepted iff its draw is below thr_of_nu[nu]:
-// floor(2^32 exp(-beta dE)) for nu = 0, 1, 2 and 2^32 (always) for nu >= 3.
-// Consecutive colour-major indices 4g .. 4g+3 share one Philox call; word
-// cm & 3 belongs to site cm.  A group can straddle two rows, so the four words
-// are carried from row to row.
-struct RowCtx {
-  uint32_t* lds;
-  const unsigned long long* thr_of_nu;
-  uint32_t h, pos;       // this lane's half of a site word and its bit
-  uint32_t slot, t, k0, k1;
-  bool any_draw;
-  Words4 d;              // Philox words of the current site group
+// Philox4x32-10 for the Metropolis draws of one lane.  The counter is
+// (slot, t, g, MET): slot is fixed per lane, t and g are wave-uniform.  The
+// first round multiplies only slot (a per-lane constant) and g (uniform), so
+// round 1 and the slot half of round 2 are computed once per lane; each call
+// then costs two XORs for round 2 and four instructions per round for rounds
+// 3..10 (two v_mad_u64_u32, two XORs).
+struct MetPhilox {
+  uint32_t x2, x3;    // round-1 words that depend on slot only
+  uint32_t p2hi, p2lo;  // round-2 product of the slot half
+  uint32_t k0, k1;    // key (seed)
+
+  __device__ __forceinline__ void init(uint32_t slot, uint32_t key0, uint32_t key1) {
+    k0 = key0;
+    k1 = key1;
+    const uint64_t pa = (uint64_t)0xD2511F53u * slot;
+    x2 = (uint32_t)(pa >> 32) ^ kTagMet ^ key1;
+    x3 = (uint32_t)pa;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * x2;
+    p2hi = (uint32_t)(pb >> 32);
+    p2lo = (uint32_t)pb;
+  }
+
+  __device__ __forceinline__ Words4 draw(uint32_t t, uint32_t g) const {
+    // round 1 (key k): uniform half
+    const uint64_t a = (uint64_t)0xCD9E8D57u * g;
+    const uint32_t x0 = (uint32_t)(a >> 32) ^ t ^ k0;
+    const uint32_t x1 = (uint32_t)a;
+    // round 2 (key k + W)
+    const uint32_t r2k0 = k0 + 0x9E3779B9u, r2k1 = k1 + 0xBB67AE85u;
+    const uint64_t b = (uint64_t)0xD2511F53u * x0;
+    uint32_t c0 = p2hi ^ (x1 ^ r2k0);
+    uint32_t c1 = p2lo;
+    uint32_t c2 = x3 ^ ((uint32_t)(b >> 32) ^ r2k1);
+    uint32_t c3 = (uint32_t)b;  // uniform
+    uint32_t q0 = k0 + 2u * 0x9E3779B9u, q1 = k1 + 2u * 0xBB67AE85u;
+    // round 3: c3 is uniform, fold it into the key word
+    {
+      const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+      const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+      const uint32_t n0 = xor3_s((uint32_t)(pb >> 32), c1, q0);
+      const uint32_t n2 = (uint32_t)(pa >> 32) ^ (c3 ^ q1);
+      c0 = n0; c1 = (uint32_t)pb; c2 = n2; c3 = (uint32_t)pa;
+      q0 += 0x9E3779B9u;
+      q1 += 0xBB67AE85u;
+    }
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+      const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+      const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+      const uint32_t n0 = xor3_s((uint32_t)(pb >> 32), c1, q0);
+      const uint32_t n2 = xor3_s((uint32_t)(pa >> 32), c3, q1);
+      c0 = n0; c1 = (uint32_t)pb; c2 = n2; c3 = (uint32_t)pa;
+      q0 += 0x9E3779B9u;
+      q1 += 0xBB67AE85u;
+    }
+    Words4 o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+  }
 };
 
-template <int L, int P, int PH>
-__device__ __forceinline__ void row_pass(RowCtx& c, uint32_t cm_row, uint32_t oth_x,
-                                         uint32_t oth_py, uint32_t oth_my, uint32_t oth_pz,
-                                         uint32_t oth_mz, unsigned long long jrow) {
-  constexpr int H = L / 2;
-  uint32_t* const a_own = c.lds + 2 * cm_row + c.h;
-  const uint32_t* const a_x = c.lds + 2 * oth_x + c.h;
-  const uint32_t* const a_py = c.lds + 2 * oth_py + c.h;
-  const uint32_t* const a_my = c.lds + 2 * oth_my + c.h;
-  const uint32_t* const a_pz = c.lds + 2 * oth_pz + c.h;
-  const uint32_t* const a_mz = c.lds + 2 * oth_mz + c.h;
-  const uint32_t jlo = (uint32_t)jrow, jhi = (uint32_t)(jrow >> 32);
-#pragma unroll
-  for (int q = 0; q < H; ++q) {
-    if (((PH + q) & 3) == 0 && c.any_draw)
-      c.d = philox10(c.slot, c.t, (cm_row + q) >> 2, kTagMet, c.k0, c.k1);
-    const uint32_t own = a_own[2 * q];
-    const uint32_t nb[6] = {a_x[2 * ((q + P) % H)], a_x[2 * ((q + P + H - 1) % H)],
-                            a_py[2 * q], a_my[2 * q], a_pz[2 * q], a_mz[2 * q]};
-    uint32_t n = 0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const int bit = 6 * q + k;  // coupling bit of (site q, neighbour k) in the row word
-      const uint32_t jm = bit < 32 ? (uint32_t)((int32_t)(jlo << (31 - bit)) >> 31)
-                                   : (uint32_t)((int32_t)(jhi << (63 - bit)) >> 31);
-      n += __builtin_amdgcn_ubfe(xor3_s(nb[k], own, jm), c.pos, 1);
-    }
-    asm("" : "+v"(n));  // keep the table index a single value
-    const bool acc = (unsigned long long)c.d.w[(PH + q) & 3] < c.thr_of_nu[n];
-    const unsigned long long f = __ballot(acc);
-    const uint32_t fh = c.h ? (uint32_t)(f >> 32) : (uint32_t)f;
-    if (c.pos == 0) a_own[2 * q] = own ^ fh;
-  }
-}
+// One colour pass of the checkerboard Metropolis update on the LDS tile.
+// For even L, the sites of colour c in row rho = y + L z are x = 2q + p,
+// q = 0..L/2-1, p = (c + y + z) & 1, with colour-major indices
+// c*N/2 + (L/2) rho + q.  Their neighbours of the other colour, in that
+// colour's rank order: +x at rank (q + p) mod L/2 and -x at (q + p - 1) mod L/2
+// of the same row, and rank q of the rows (y+-1, z) and (y, z+-1).  Per row
+// seven base addresses are formed (own row, x row shifted by p, the one
+// wrapped x neighbour shared by the last and first site, and the four y/z
+// rows); every site reads its words at compile-time offsets from them.
+//
+// Rows are walked four at a time: 4 (L/2) sites = L/2 whole Philox groups
+// (colour-major indices 4g .. 4g+3 share one call, word cm & 3 is site cm's),
+// so a block never shares a group with its neighbour.
+//
+// nu = number of unsatisfied bonds at the site (own bit ^ neighbour bit ^
+// [J = -1]); flipping changes the energy by dE = 12 - 4 nu, and the move is
+// accepted iff its draw is below thr_of_nu[nu] (floor(2^32 exp(-beta dE)) for
+// nu <= 2, 2^32 for nu >= 3).  With ACCUM, the pass also sums this colour's
+// post-move nu: in the colour-1 pass of the last sweep that is the energy U
+// (every bond joins one site of each colour).
+struct TileCtx {
+  uint32_t* lds;
+  const unsigned long long* thr_of_nu;
+  uint32_t hoff;   // byte offset of this lane's half word: 4 * (lane >> 5)
+  uint32_t pos;    // this lane's bit in its half word
+  MetPhilox ph;
+  uint32_t t;
+  bool any_draw;
+};
+
+struct RowAddr {
+  const uint32_t* own;
+  const uint32_t* x0;    // rank p of the other-colour x row
+  const uint32_t* wrap;  // the x neighbour that wraps around
+  const uint32_t* py;
+  const uint32_t* my;
+  const uint32_t* pz;
+  const uint32_t* mz;
+  unsigned long long j;  // coupling bits of the row
+};
 
 template <int L>
-__device__ void sweep_colour_rows(RowCtx& c, const unsigned long long* __restrict__ rowj,
-                                  uint32_t colour) {
+__device__ __forceinline__ RowAddr row_addr(const TileCtx& c, const unsigned long long* rowj,
+                                            uint32_t colour, uint32_t rho) {
   constexpr uint32_t H = L / 2, N = L * L * L;
   const uint32_t own0 = colour * (N / 2), oth0 = (colour ^ 1u) * (N / 2);
-  for (uint32_t z = 0; z < (uint32_t)L; ++z) {
-    const uint32_t zp = z + 1 == (uint32_t)L ? 0 : z + 1, zm = z == 0 ? L - 1 : z - 1;
-    for (uint32_t y = 0; y < (uint32_t)L; ++y) {
-      const uint32_t yp = y + 1 == (uint32_t)L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
-      const uint32_t r0 = H * (y + L * z);
-      const uint32_t cm_row = __builtin_amdgcn_readfirstlane(own0 + r0);
-      const uint32_t ox = oth0 + r0;
-      const uint32_t opy = oth0 + H * (yp + L * z), omy = oth0 + H * (ym + L * z);
-      const uint32_t opz = oth0 + H * (y + L * zp), omz = oth0 + H * (y + L * zm);
-      const unsigned long long jrow = rowj[__builtin_amdgcn_readfirstlane(colour * L * L + y + L * z)];
-      const uint32_t p = (colour + y + z) & 1u;
-      const uint32_t ph = r0 & 3u;
-      // dispatch on the row parity and on where the row starts inside a group
-      if constexpr (H % 4 == 0) {
-        if (p) row_pass<L, 1, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow);
-        else row_pass<L, 0, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow);
-      } else if constexpr (H % 2 == 0) {
-        switch (p * 4 + ph) {
-          case 0: row_pass<L, 0, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          case 2: row_pass<L, 0, 2>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          case 4: row_pass<L, 1, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          default: row_pass<L, 1, 2>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-        }
-      } else {
-        switch (p * 4 + ph) {
-          case 0: row_pass<L, 0, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          case 1: row_pass<L, 0, 1>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          case 2: row_pass<L, 0, 2>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          case 3: row_pass<L, 0, 3>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          case 4: row_pass<L, 1, 0>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          case 5: row_pass<L, 1, 1>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          case 6: row_pass<L, 1, 2>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-          default: row_pass<L, 1, 3>(c, cm_row, ox, opy, omy, opz, omz, jrow); break;
-        }
+  const uint32_t y = rho % L, z = rho / L;
+  const uint32_t yp = y + 1 == (uint32_t)L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+  const uint32_t zp = z + 1 == (uint32_t)L ? 0 : z + 1, zm = z == 0 ? L - 1 : z - 1;
+  const uint32_t p = (colour + y + z) & 1u;
+  const uint32_t ox = oth0 + H * rho;
+  const char* base = reinterpret_cast<const char*>(c.lds) + c.hoff;
+  RowAddr a;
+  a.own = reinterpret_cast<const uint32_t*>(base + 8 * (own0 + H * rho));
+  a.x0 = reinterpret_cast<const uint32_t*>(base + 8 * (ox + p));
+  a.wrap = reinterpret_cast<const uint32_t*>(base + 8 * (ox + (H - 1) * (1u - p)));
+  a.py = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (yp + L * z)));
+  a.my = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (ym + L * z)));
+  a.pz = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (y + L * zp)));
+  a.mz = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (y + L * zm)));
+  a.j = rowj[colour * L * L + rho];
+  return a;
+}
+
+// The seven words a site reads: its own word and its six neighbours.
+struct SiteLoad {
+  uint32_t own;
+  uint32_t nb[6];
+};
+
+template <int L, int Q>
+__device__ __forceinline__ SiteLoad load_site_words(const RowAddr& a) {
+  constexpr int H = L / 2;
+  SiteLoad w;
+  w.own = a.own[2 * Q];
+  w.nb[0] = Q < H - 1 ? a.x0[2 * Q] : a.wrap[0];
+  w.nb[1] = Q > 0 ? a.x0[2 * (Q - 1)] : a.wrap[0];
+  w.nb[2] = a.py[2 * Q];
+  w.nb[3] = a.my[2 * Q];
+  w.nb[4] = a.pz[2 * Q];
+  w.nb[5] = a.mz[2 * Q];
+  return w;
+}
+
+template <int L, int Q, bool ACCUM>
+__device__ __forceinline__ void site_update(const TileCtx& c, const RowAddr& a, const SiteLoad& w,
+                                            uint32_t draw, uint32_t& usum) {
+  uint32_t* const own_p = const_cast<uint32_t*>(a.own) + 2 * Q;
+  const uint32_t jlo = (uint32_t)a.j, jhi = (uint32_t)(a.j >> 32);
+  uint32_t b[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int bit = 6 * Q + k;  // coupling bit of (site Q, neighbour k) in the row word
+    const uint32_t jm = bit < 32 ? (uint32_t)((int32_t)(jlo << (31 - bit)) >> 31)
+                                 : (uint32_t)((int32_t)(jhi << (63 - bit)) >> 31);
+    b[k] = __builtin_amdgcn_ubfe(xor3_s(w.nb[k], w.own, jm), c.pos, 1);
+  }
+  // nu = sum of the six bits; the threshold table sits at LDS address 0, so
+  // its byte address 8 nu comes out of one v_add_lshl_u32
+  const uint32_t part = b[0] + b[1] + b[2] + b[3] + b[4];
+  uint32_t addr;
+  asm("v_add_lshl_u32 %0, %1, %2, 3" : "=v"(addr) : "v"(part), "v"(b[5]));
+  const unsigned long long thr = *reinterpret_cast<const unsigned long long*>(
+      reinterpret_cast<const char*>(c.thr_of_nu) + addr);
+  const bool acc = (unsigned long long)draw < thr;
+  if (ACCUM) {
+    const uint32_t n = addr >> 3;
+    usum += acc ? 6u - n : n;
+  }
+  const unsigned long long f = __ballot(acc);
+  const uint32_t fh = c.hoff ? (uint32_t)(f >> 32) : (uint32_t)f;
+  // one lane per half applies the flips of its 32 replicas
+  if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Sites Q.. of row I of a 4-row block.  The words of site Q + 1 are read
+// before site Q is updated: they are other-colour words (not written in this
+// pass) and a different own word, so the early read sees the same values and
+// its LDS latency overlaps the current site's work.  A new Philox group
+// starts every fourth site of the block.
+template <int L, int I, int Q, bool ACCUM>
+__device__ __forceinline__ void block_row(const TileCtx& c, const RowAddr& a, uint32_t g0,
+                                          Words4& d, uint32_t& usum, const SiteLoad& w) {
+  constexpr int H = L / 2;
+  constexpr int S = I * H + Q;  // site index within the block
+  SiteLoad wn;
+  if constexpr (Q + 1 < H) wn = load_site_words<L, Q + 1>(a);
+  if constexpr (S % 4 == 0) {
+    if (c.any_draw) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
+  }
+  site_update<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
+  if constexpr (Q + 1 < H) block_row<L, I, Q + 1, ACCUM>(c, a, g0, d, usum, wn);
+}
+
+template <int L, bool ACCUM>
+__device__ uint32_t sweep_colour_blocks(const TileCtx& c, const unsigned long long* rowj,
+                                        uint32_t colour) {
+  constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L;
+  const uint32_t own0 = colour * (N / 2);
+  uint32_t usum = 0;
+  Words4 d;
+  d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0u;
+  for (uint32_t rb = 0; rb < ROWS; rb += 4) {
+    const uint32_t rbu = __builtin_amdgcn_readfirstlane(rb);
+    const uint32_t g0 = (own0 + H * rbu) >> 2;  // first Philox group of the block
+    const RowAddr a0 = row_addr<L>(c, rowj, colour, rbu);
+    block_row<L, 0, 0, ACCUM>(c, a0, g0, d, usum, load_site_words<L, 0>(a0));
+    const RowAddr a1 = row_addr<L>(c, rowj, colour, rbu + 1);
+    block_row<L, 1, 0, ACCUM>(c, a1, g0, d, usum, load_site_words<L, 0>(a1));
+    const RowAddr a2 = row_addr<L>(c, rowj, colour, rbu + 2);
+    block_row<L, 2, 0, ACCUM>(c, a2, g0, d, usum, load_site_words<L, 0>(a2));
+    const RowAddr a3 = row_addr<L>(c, rowj, colour, rbu + 3);
+    block_row<L, 3, 0, ACCUM>(c, a3, g0, d, usum, load_site_words<L, 0>(a3));
+  }
+  __syncthreads();
+  return usum;
+}
+
+// Energy of the tile when no sweep ran: sum over colour-0 sites of nu.
+template <int L>
+__device__ uint32_t tile_energy_rows(const TileCtx& c, const unsigned long long* rowj) {
+  constexpr uint32_t H = L / 2, ROWS = L * L;
+  uint32_t U = 0;
+  for (uint32_t rho = 0; rho < ROWS; ++rho) {
+    const RowAddr a = row_addr<L>(c, rowj, 0u, __builtin_amdgcn_readfirstlane(rho));
+    const uint32_t jlo = (uint32_t)a.j, jhi = (uint32_t)(a.j >> 32);
+#pragma unroll
+    for (int q = 0; q < (int)H; ++q) {
+      const uint32_t own = a.own[2 * q];
+      const uint32_t nb[6] = {q < (int)H - 1 ? a.x0[2 * q] : a.wrap[0],
+                              q > 0 ? a.x0[2 * (q - 1)] : a.wrap[0],
+                              a.py[2 * q], a.my[2 * q], a.pz[2 * q], a.mz[2 * q]};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int bit = 6 * q + k;
+        const uint32_t jm = bit < 32 ? (uint32_t)((int32_t)(jlo << (31 - bit)) >> 31)
+                                     : (uint32_t)((int32_t)(jhi << (63 - bit)) >> 31);
+        U += __builtin_amdgcn_ubfe(xor3_s(nb[k], own, jm), c.pos, 1);
       }
     }
   }
-  __syncthreads();
+  return U;
 }
 
 // ---------------------------------------------------------------------------
-// kernels
+// kernels.  Each works on a set of populations (BatchDev) through a Group that
+// assigns workgroups to member populations.
 // ---------------------------------------------------------------------------
+struct Member {
+  uint32_t pop;  // index into B.pops
+  uint32_t lb;   // workgroup index within the member
+  uint32_t nb;   // workgroups of the member
+  uint32_t m;    // member index within the group
+};
+
+__device__ __forceinline__ Member member_of(const Group& g) {
+  const uint32_t b = blockIdx.x;
+  uint32_t lo = 0, hi = g.n;  // start[lo] <= b < start[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (g.start[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  Member r;
+  r.m = __builtin_amdgcn_readfirstlane(lo);
+  r.pop = __builtin_amdgcn_readfirstlane(g.pop[r.m]);
+  const uint32_t s0 = __builtin_amdgcn_readfirstlane(g.start[r.m]);
+  r.lb = b - s0;
+  r.nb = __builtin_amdgcn_readfirstlane(g.start[r.m + 1]) - s0;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t step_index(const BatchDev& B) {
+  return B.steps ? __builtin_amdgcn_readfirstlane(*B.step_ctr) : 0u;
+}
+
+__device__ __forceinline__ PopStep step_of(const BatchDev& B, uint32_t pop) {
+  if (!B.steps) return B.single;
+  return B.steps[(size_t)step_index(B) * B.n_pops + pop];
+}
+
+__device__ __forceinline__ StepRecord* record_of(const BatchDev& B, uint32_t pop) {
+  return B.records ? B.records + (size_t)step_index(B) * B.n_pops + pop : nullptr;
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -302,34 +486,108 @@ __global__ __launch_bounds__(64) void k_init(DevPop P, uint32_t cur,
   }
 }
 
-// U recomputed from the stored spins (after an import of a state).
-template <int LAYOUT>
-__global__ __launch_bounds__(64) void k_energy(DevPop P, uint32_t cur) {
-  extern __shared__ uint32_t lds[];
-  const uint32_t tile = blockIdx.x;
-  const uint32_t R = P.sc->R_tilde;
-  if (tile * 64 >= R) return;
-  const uint32_t j = tile * 64 + lane_id();
-  const bool valid = j < R;
-  load_tile_gather<LAYOUT>(lds, P.spins[cur], P.N, valid ? j : 0u, valid);
-  const uint32_t U = tile_energy(lds, P.sites, P.N);
-  if (valid) P.U[cur][j] = U;
+// Zero the per-step accumulators of each population (one workgroup each).
+__global__ __launch_bounds__(256) void k_zero_acc(BatchDev B, Group G) {
+  const Member m = member_of(G);
+  const DevPop& P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  for (uint32_t i = threadIdx.x; i < P.n_levels; i += blockDim.x) P.hist[i] = 0;
+  if (threadIdx.x == 0) {
+    P.sc->sum_eta2 = 0;
+    P.sc->n_families = 0;
+  }
 }
 
 // Energy histogram h_j = #{i < R~ : U_i = j} (the sum of Eq. 2 regrouped by
-// integer level), privatised in LDS.
-__global__ __launch_bounds__(256) void k_hist(DevPop P, const uint32_t* __restrict__ U) {
+// integer level), privatised in LDS; each workgroup takes kHistSlots slots.
+__global__ __launch_bounds__(256) void k_hist(BatchDev B, Group G, uint32_t post) {
   extern __shared__ uint32_t h[];
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  const PopStep sp = step_of(B, m.pop);
+  const uint32_t* U = P.U[post ? sp.cur ^ 1u : sp.cur];
   for (uint32_t i = threadIdx.x; i < P.n_levels; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const uint32_t R = P.sc->R_tilde;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < R; i += gridDim.x * blockDim.x) {
+  const uint32_t i0 = m.lb * kHistSlots, i1 = min(R, i0 + kHistSlots);
+  for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const uint32_t u = U[i];
     if (u < P.n_levels) atomicAdd(&h[u], 1u);
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < P.n_levels; i += blockDim.x)
     if (h[i]) atomicAdd(&P.hist[i], h[i]);
+}
+
+// Resampling table on the device (Sec. II, Eqs. 1-2), the same arithmetic as
+// the host builder: j_min = lowest occupied level, w_j = erow[j - j_min]
+// (erow holds exp(-dbeta * 2d) from the host's exp), S = sum over occupied
+// levels, ascending, of h_j w_j (one thread, in order), tau_j = R w_j / S,
+// fl_j = floor(tau_j), T_j = ceil(frac(tau_j) 2^53).  The culling fraction
+// (Sec. III.C) is summed the same way.  S, j_min and R~ are recorded; the
+// host finishes ln Q = ln S - ln R~ - dbeta E_min with its own log.
+__global__ __launch_bounds__(256) void k_table(BatchDev B, Group G) {
+  __shared__ double sS;
+  __shared__ int sjmin;
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  const PopStep sp = step_of(B, m.pop);
+  const uint32_t* h = P.hist;
+  const double R = (double)P.R;
+  if (threadIdx.x == 0) {
+    int jmin = -1;
+    for (uint32_t j = 0; j < P.n_levels; ++j)
+      if (h[j] > 0) {
+        jmin = (int)j;
+        break;
+      }
+    double S = 0.0;
+    double eps = 0.0;
+    if (jmin >= 0) {
+      for (uint32_t j = (uint32_t)jmin; j < P.n_levels; ++j) {
+        if (h[j] == 0) continue;
+        const double w = sp.erow[j - (uint32_t)jmin];
+        S = __dadd_rn(S, __dmul_rn((double)h[j], w));
+      }
+      double acc = 0.0;
+      for (uint32_t j = (uint32_t)jmin; j < P.n_levels; ++j) {
+        if (h[j] == 0) continue;
+        const double w = sp.erow[j - (uint32_t)jmin];
+        const double tau = __ddiv_rn(__dmul_rn(R, w), S);
+        if (tau < 1.0) acc = __dadd_rn(acc, __dmul_rn((double)h[j], __dsub_rn(1.0, tau)));
+      }
+      eps = __ddiv_rn(acc, R);
+    }
+    sS = S;
+    sjmin = jmin;
+    StepRecord* rec = record_of(B, m.pop);
+    if (rec) {
+      rec->S = S;
+      rec->eps = eps;
+      rec->jmin = jmin;
+      rec->R_old = P.sc->R_tilde;
+      rec->status = 0;
+    }
+  }
+  __syncthreads();
+  const double S = sS;
+  const int jmin = sjmin;
+  if (jmin < 0) return;
+  for (uint32_t j = threadIdx.x; j < P.n_levels; j += blockDim.x) {
+    if ((int)j < jmin) {
+      P.table_fl[j] = 0;
+      P.table_T[j] = 0;
+      continue;
+    }
+    const double w = sp.erow[j - (uint32_t)jmin];
+    const double tau = __ddiv_rn(__dmul_rn(R, w), S);
+    const double f = floor(tau);
+    const double fr = __dsub_rn(tau, f);
+    P.table_fl[j] = (uint32_t)f;
+    P.table_T[j] = (unsigned long long)ceil(ldexp(fr, 53));
+  }
 }
 
 // --- block-level scans and reductions (wave shuffles + LDS) ----------------
@@ -378,15 +636,19 @@ __device__ T block_sum(T v, T* scratch) {
 
 // Nearest-integer copy counts (Sec. II): n_i = fl[U_i] + [u53 < T[U_i]] with
 // u53 = (w0 << 21) | (w1 >> 11) from Philox(seed; i, step, 0, RES).
-__global__ __launch_bounds__(kBlockCounts) void k_counts(DevPop P, const uint32_t* __restrict__ U,
-                                                         uint32_t step) {
+__global__ __launch_bounds__(kBlockCounts) void k_counts(BatchDev B, Group G) {
   __shared__ uint32_t scratch[kBlockCounts / kWave];
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  const PopStep sp = step_of(B, m.pop);
+  const uint32_t* U = P.U[sp.cur];
   const uint32_t R = P.sc->R_tilde;
-  const uint32_t i = blockIdx.x * kBlockCounts + threadIdx.x;
+  const uint32_t i = m.lb * kBlockCounts + threadIdx.x;
   uint32_t n = 0, culled = 0;
   if (i < R) {
     const uint32_t u = min(U[i], P.n_levels - 1);
-    const Words4 w = philox10(i, step, 0u, kTagRes, (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
+    const Words4 w = philox10(i, sp.step, 0u, kTagRes, (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
     const unsigned long long u53 = ((unsigned long long)w.w[0] << 21) | (w.w[1] >> 11);
     n = P.table_fl[u] + (u53 < P.table_T[u] ? 1u : 0u);
     P.counts[i] = n;
@@ -395,16 +657,20 @@ __global__ __launch_bounds__(kBlockCounts) void k_counts(DevPop P, const uint32_
   const uint32_t s = block_sum<kBlockCounts, uint32_t>(n, scratch);
   const uint32_t c = block_sum<kBlockCounts, uint32_t>(culled, scratch);
   if (threadIdx.x == 0) {
-    P.block_sums[blockIdx.x] = s;
-    P.block_culled[blockIdx.x] = c;
+    P.block_sums[m.lb] = s;
+    P.block_culled[m.lb] = c;
   }
 }
 
-// Exclusive scan of the per-block sums (one workgroup), the new population
-// size R~' = sum n_i, and the capacity check.
-__global__ __launch_bounds__(1024) void k_scan(DevPop P, uint32_t capacity) {
+// Exclusive scan of the per-block sums (one workgroup per population), the
+// new population size R~' = sum n_i, and the capacity check.
+__global__ __launch_bounds__(1024) void k_scan(BatchDev B, Group G) {
   __shared__ uint32_t scratch[1024 / kWave];
   __shared__ unsigned long long cull_scratch[1024 / kWave];
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  const PopStep sp = step_of(B, m.pop);
   const uint32_t nb = P.n_blocks;
   const uint32_t per = (nb + 1023) / 1024;
   const uint32_t b0 = threadIdx.x * per;
@@ -422,68 +688,107 @@ __global__ __launch_bounds__(1024) void k_scan(DevPop P, uint32_t capacity) {
   const unsigned long long ctot =
       block_sum<1024, unsigned long long>((unsigned long long)cull, cull_scratch);
   if (threadIdx.x == 0) {
+    const bool over = total > P.cap_limit;
     P.sc->R_next = total;
-    P.sc->err = total > capacity ? 1u : 0u;
+    P.sc->err = over ? 1u : 0u;
     P.sc->n_culled = (uint32_t)ctot;
+    StepRecord* rec = record_of(B, m.pop);
+    if (rec) {
+      rec->n_culled = (uint32_t)ctot;
+      rec->status = over ? 1u : 0u;
+    }
+    if (over && (sp.flags & kStepSticky)) P.sc->dead = 1u;
   }
 }
 
 // Offsets and the new-slot -> old-slot map of the order-preserving copy:
 // the n_i copies of old slot i take new slots offset_i .. offset_i + n_i - 1.
-__global__ __launch_bounds__(kBlockCounts) void k_scatter(DevPop P) {
+__global__ __launch_bounds__(kBlockCounts) void k_scatter(BatchDev B, Group G) {
   __shared__ uint32_t scratch[kBlockCounts / kWave];
-  if (P.sc->err) return;
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead || P.sc->err) return;
   const uint32_t R = P.sc->R_tilde;
-  const uint32_t i = blockIdx.x * kBlockCounts + threadIdx.x;
+  const uint32_t i = m.lb * kBlockCounts + threadIdx.x;
   const uint32_t n = i < R ? P.counts[i] : 0u;
   uint32_t total;
   const uint32_t excl = block_exclusive_scan<kBlockCounts>(n, &total, scratch);
   if (i < R) {
-    const uint32_t off = P.block_offsets[blockIdx.x] + excl;
+    const uint32_t off = P.block_offsets[m.lb] + excl;
     P.offsets[i] = off;
     for (uint32_t c = 0; c < n; ++c) P.src[off + c] = i;
   }
 }
 
+// Waves per workgroup of the sweep kernel.  Every wave owns one tile and its
+// own LDS image; the workgroup only shares the threshold table and barriers.
+// One-wave workgroups run out of workgroup slots before LDS is full, so small
+// lattices pack four waves per workgroup (L <= 10: still 20 waves per CU by
+// LDS); larger ones keep one wave so that LDS is not wasted on fragments.
+template <int L>
+constexpr uint32_t sweep_waves() {
+  return L <= 10 ? 4u : 1u;
+}
+
 // Gather (optional) + n_sweeps checkerboard Metropolis sweeps + energy, one
 // wavefront per 64-replica tile.  Reads buffer cur, writes buffer cur ^ 1.
 template <int LAYOUT, int L>
-__global__ __launch_bounds__(64) void k_sweep(DevPop P, SweepParams sp,
-                                              const SiteEntry* __restrict__ sites,
-                                              const unsigned long long* __restrict__ rowj) {
+__global__ __launch_bounds__(64 * sweep_waves<L>()) void k_sweep(BatchDev B, Group G) {
   constexpr uint32_t N = L * L * L;
-  extern __shared__ uint32_t lds[];
-  __shared__ unsigned long long thr_of_nu[8];
-  const uint32_t tile = blockIdx.x;
+  constexpr uint32_t kSweepWaves = sweep_waves<L>();
+  __shared__ unsigned long long thr_of_nu[8];  // first LDS object: address 0 (see site_update)
+  extern __shared__ uint32_t lds_all[];
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  const PopStep sp = step_of(B, m.pop);
   const uint32_t lane = lane_id();
-  if (sp.gather && tile == 0 && lane == 0) P.sc->R_tilde = P.sc->R_next;
+  const uint32_t wave = threadIdx.x / 64;
+  const uint32_t tile = m.lb * kSweepWaves + wave;
+  if (sp.gather && m.lb == 0 && threadIdx.x == 0) P.sc->R_tilde = P.sc->R_next;
   const uint32_t Rs = sp.gather ? P.sc->R_next : P.sc->R_tilde;
-  if (tile * 64 >= Rs) return;
-  if (lane < 8) thr_of_nu[lane] = lane < 3 ? sp.thr[2 - lane] : (1ull << 32);
+  // whole workgroups leave together (the passes below use workgroup barriers);
+  // waves of the last workgroup that lie past the population run with no valid lane
+  if (m.lb * kSweepWaves * 64 >= Rs) return;
+  // site_update indexes the threshold table by byte address 8 nu: it must sit
+  // at LDS address 0.  If the toolchain ever places it elsewhere, report a
+  // configuration error instead of computing with a wrong table.
+  if ((uint32_t)(uintptr_t)thr_of_nu != 0u) {
+    if (threadIdx.x == 0) P.sc->err = 2u;
+    return;
+  }
+  if (threadIdx.x < 8)
+    thr_of_nu[threadIdx.x] = threadIdx.x < 3 ? sp.thr[2 - threadIdx.x] : (1ull << 32);
+  uint32_t* const lds = lds_all + wave * 2 * N;
   const uint32_t j = tile * 64 + lane;
   const bool valid = j < Rs;
   const uint32_t src = valid ? (sp.gather ? P.src[j] : j) : 0u;
   const uint32_t cur = sp.cur, nxt = cur ^ 1u;
-  load_tile_gather<LAYOUT>(lds, P.spins[cur], N, src, valid);
-  RowCtx c;
+  load_tile_gather<LAYOUT, N>(lds, P.spins[cur], src, valid);
+  TileCtx c;
   c.lds = lds;
   c.thr_of_nu = thr_of_nu;
-  c.h = lane >> 5;
+  c.hoff = 4u * (lane >> 5);
   c.pos = lane & 31u;
-  c.slot = j;
-  c.k0 = (uint32_t)P.seed;
-  c.k1 = (uint32_t)(P.seed >> 32);
+  c.ph.init(j, (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
   // a draw matters only for a class whose threshold is neither 0 nor 2^32
   c.any_draw = (sp.thr[0] != 0 && sp.thr[0] < (1ull << 32)) ||
                (sp.thr[1] != 0 && sp.thr[1] < (1ull << 32)) ||
                (sp.thr[2] != 0 && sp.thr[2] < (1ull << 32));
-  c.d.w[0] = c.d.w[1] = c.d.w[2] = c.d.w[3] = 0u;
-  for (uint32_t s = 0; s < sp.n_sweeps; ++s) {
-    c.t = sp.t0 + s;
-    sweep_colour_rows<L>(c, rowj, 0u);
-    sweep_colour_rows<L>(c, rowj, 1u);
+  const unsigned long long* rowj = P.rowj;
+  uint32_t U;
+  if (sp.n_sweeps == 0) {
+    U = tile_energy_rows<L>(c, rowj);
+  } else {
+    for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
+      c.t = sp.t0 + s;
+      sweep_colour_blocks<L, false>(c, rowj, 0u);
+      sweep_colour_blocks<L, false>(c, rowj, 1u);
+    }
+    c.t = sp.t0 + sp.n_sweeps - 1;
+    sweep_colour_blocks<L, false>(c, rowj, 0u);
+    U = sweep_colour_blocks<L, true>(c, rowj, 1u);
   }
-  const uint32_t U = tile_energy(lds, sites, N);
   store_tile<LAYOUT>(lds, P.spins[nxt], N, tile);
   if (valid) {
     P.U[nxt][j] = U;
@@ -491,13 +796,41 @@ __global__ __launch_bounds__(64) void k_sweep(DevPop P, SweepParams sp,
   }
 }
 
+// U recomputed from the stored spins of buffer cur (after an import).
+template <int LAYOUT, int L>
+__global__ __launch_bounds__(64) void k_energy(BatchDev B, Group G) {
+  constexpr uint32_t N = L * L * L;
+  extern __shared__ uint32_t lds[];
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  const PopStep sp = step_of(B, m.pop);
+  const uint32_t R = P.sc->R_tilde;
+  const uint32_t tile = m.lb;
+  if (tile * 64 >= R) return;
+  const uint32_t lane = lane_id();
+  const uint32_t j = tile * 64 + lane;
+  const bool valid = j < R;
+  load_tile_gather<LAYOUT, N>(lds, P.spins[sp.cur], valid ? j : 0u, valid);
+  TileCtx c;
+  c.lds = lds;
+  c.hoff = 4u * (lane >> 5);
+  c.pos = lane & 31u;
+  const uint32_t U = tile_energy_rows<L>(c, P.rowj);
+  if (valid) P.U[sp.cur][j] = U;
+}
+
 // Sum over families of eta^2 (Sec. III.A) from the family labels, which stay
 // sorted under the order-preserving copy: each run of equal labels is one
 // family; its first slot finds the run's end by binary search.
-__global__ __launch_bounds__(256) void k_family(DevPop P, const uint32_t* __restrict__ fam) {
+__global__ __launch_bounds__(256) void k_family(BatchDev B, Group G, uint32_t post) {
   __shared__ unsigned long long scratch[256 / kWave];
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  const PopStep sp = step_of(B, m.pop);
+  const uint32_t* fam = P.fam[post ? sp.cur ^ 1u : sp.cur];
   const uint32_t R = P.sc->R_tilde;
-  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t i = m.lb * 256 + threadIdx.x;
   unsigned long long sq = 0, nf = 0;
   if (i < R) {
     const uint32_t f = fam[i];
@@ -521,15 +854,59 @@ __global__ __launch_bounds__(256) void k_family(DevPop P, const uint32_t* __rest
   }
 }
 
-// Spin-overlap histogram (Sec. II.A): slot i of population A against slot i
-// of population B; d = differing sites, bin = (128 (N - d) + N) / (2N).
+// Post-step record of a batch step: integer sum of E over the population, the
+// lowest energy, the new size and the family sum (one workgroup each).
+__global__ __launch_bounds__(256) void k_record(BatchDev B, Group G) {
+  __shared__ long long scratch[256 / kWave];
+  __shared__ int smin;
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  StepRecord* rec = record_of(B, m.pop);
+  if (!rec || P.sc->dead) return;
+  if (threadIdx.x == 0) smin = 0x7FFFFFFF;
+  __syncthreads();
+  long long acc = 0;
+  const int N3 = 3 * (int)P.N;
+  for (uint32_t j = threadIdx.x; j < P.n_levels; j += blockDim.x) {
+    const uint32_t hj = P.hist[j];
+    if (hj) {
+      acc += (long long)hj * (2 * (long long)j - N3);
+      atomicMin(&smin, (int)j);
+    }
+  }
+  const long long s = block_sum<256, long long>(acc, scratch);
+  if (threadIdx.x == 0) {
+    rec->sumE = s;
+    rec->E_min = smin == 0x7FFFFFFF ? 0 : 2 * smin - N3;
+    rec->R_new = P.sc->R_tilde;
+    rec->sum_eta2 = P.sc->sum_eta2;
+  }
+}
+
+// Spin-overlap histogram (Sec. II.A): slot i of population a against slot i
+// of population b; d = differing sites, bin = (128 (N - d) + N) / (2N).
+// Member m of the group is pair k = G.pop[m] (populations pair_pops[2k], pair_pops[2k+1]).
 template <int LAYOUT>
-__global__ __launch_bounds__(64) void k_overlap(DevPop A, uint32_t cur_a, DevPop B,
-                                                uint32_t cur_b, unsigned long long* hist65) {
+__global__ __launch_bounds__(64) void k_overlap(BatchDev B, Group G,
+                                                const uint32_t* __restrict__ pair_pops,
+                                                uint32_t post, uint32_t cur_a1, uint32_t cur_b1) {
   __shared__ uint32_t hb[65];
-  const uint32_t tile = blockIdx.x;
+  const Member m = member_of(G);
+  const uint32_t k = m.pop;  // pair index
+  const uint32_t ia = __builtin_amdgcn_readfirstlane(pair_pops[2 * k]);
+  const uint32_t ib = __builtin_amdgcn_readfirstlane(pair_pops[2 * k + 1]);
+  const DevPop A = B.pops[ia];
+  const DevPop Bp = B.pops[ib];
+  if (A.sc->dead || Bp.sc->dead) return;
+  // batch steps carry each population's buffer; a call on two instances passes them
+  const uint32_t base_a = B.steps ? step_of(B, ia).cur : cur_a1;
+  const uint32_t base_b = B.steps ? step_of(B, ib).cur : cur_b1;
+  const uint32_t cur_a = post ? base_a ^ 1u : base_a, cur_b = post ? base_b ^ 1u : base_b;
+  unsigned long long* out =
+      B.qhist ? B.qhist + ((size_t)step_index(B) * B.n_pairs + k) * 65 : A.ovl_hist;
+  const uint32_t tile = m.lb;
   const uint32_t lane = lane_id();
-  const uint32_t n = min(A.sc->R_tilde, B.sc->R_tilde);
+  const uint32_t n = min(A.sc->R_tilde, Bp.sc->R_tilde);
   if (tile * 64 >= n) return;
   for (uint32_t b = lane; b < 65; b += 64) hb[b] = 0;
   __syncthreads();
@@ -539,23 +916,39 @@ __global__ __launch_bounds__(64) void k_overlap(DevPop A, uint32_t cur_a, DevPop
   if (LAYOUT == 2) {
     const unsigned long long* a = static_cast<const unsigned long long*>(A.spins[cur_a]) +
                                   (size_t)tile * N;
-    const unsigned long long* b = static_cast<const unsigned long long*>(B.spins[cur_b]) +
+    const unsigned long long* b = static_cast<const unsigned long long*>(Bp.spins[cur_b]) +
                                   (size_t)tile * N;
     for (uint32_t cm = 0; cm < N; ++cm) d += (uint32_t)((a[cm] ^ b[cm]) >> lane) & 1u;
   } else {
     const int8_t* a = static_cast<const int8_t*>(A.spins[cur_a]) + (size_t)tile * N * 64 + lane;
-    const int8_t* b = static_cast<const int8_t*>(B.spins[cur_b]) + (size_t)tile * N * 64 + lane;
+    const int8_t* b = static_cast<const int8_t*>(Bp.spins[cur_b]) + (size_t)tile * N * 64 + lane;
     for (uint32_t cm = 0; cm < N; ++cm) d += a[64 * (size_t)cm] != b[64 * (size_t)cm];
   }
   if (i < n) atomicAdd(&hb[(128u * (N - d) + N) / (2u * N)], 1u);
   __syncthreads();
   for (uint32_t b = lane; b < 65; b += 64)
-    if (hb[b]) atomicAdd(&hist65[b], (unsigned long long)hb[b]);
+    if (hb[b]) atomicAdd(&out[b], (unsigned long long)hb[b]);
+}
+
+__global__ void k_advance(uint32_t* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += 1u;
 }
 
 inline uint32_t tiles_of(uint32_t n) { return (n + 63) / 64; }
 
 }  // namespace
+
+uint32_t sweep_waves_for(uint32_t L) {
+  switch (L) {
+    case 4: return sweep_waves<4>();
+    case 6: return sweep_waves<6>();
+    case 8: return sweep_waves<8>();
+    case 10: return sweep_waves<10>();
+    case 12: return sweep_waves<12>();
+    case 14: return sweep_waves<14>();
+    default: return sweep_waves<16>();
+  }
+}
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -568,87 +961,130 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t st
 }
 
 hipError_t launch_init(const DevPop& P, uint32_t cur, hipStream_t stream) {
-  const uint16_t* cm_of_site = P.cm_of_site;
   const size_t lds = (size_t)P.N * 8;
   if (P.layout == 2)
-    hipLaunchKernelGGL(k_init<2>, dim3(tiles_of(P.R)), dim3(64), lds, stream, P, cur, cm_of_site);
+    hipLaunchKernelGGL(k_init<2>, dim3(tiles_of(P.R)), dim3(64), lds, stream, P, cur,
+                       P.cm_of_site);
   else
-    hipLaunchKernelGGL(k_init<1>, dim3(tiles_of(P.R)), dim3(64), lds, stream, P, cur, cm_of_site);
+    hipLaunchKernelGGL(k_init<1>, dim3(tiles_of(P.R)), dim3(64), lds, stream, P, cur,
+                       P.cm_of_site);
   return hipGetLastError();
 }
 
-hipError_t launch_energy(const DevPop& P, uint32_t cur, hipStream_t stream) {
-  const size_t lds = (size_t)P.N * 8;
-  if (P.layout == 2)
-    hipLaunchKernelGGL(k_energy<2>, dim3(tiles_of(P.capacity)), dim3(64), lds, stream, P, cur);
-  else
-    hipLaunchKernelGGL(k_energy<1>, dim3(tiles_of(P.capacity)), dim3(64), lds, stream, P, cur);
+hipError_t launch_zero_acc(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_acc, dim3(g.blocks), dim3(256), 0, stream, B, g);
   return hipGetLastError();
 }
 
-hipError_t launch_hist(const DevPop& P, uint32_t cur, hipStream_t stream) {
-  // the caller has zeroed P.hist
-  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((P.capacity + 2047) / 2048, 512));
-  hipLaunchKernelGGL(k_hist, dim3(grid), dim3(256), (size_t)P.n_levels * 4, stream, P, P.U[cur]);
+hipError_t launch_hist(const BatchDev& B, const Group& g, uint32_t max_levels, bool post,
+                       hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_hist, dim3(g.blocks), dim3(256), (size_t)max_levels * 4, stream, B, g,
+                     post ? 1u : 0u);
   return hipGetLastError();
 }
 
-hipError_t launch_counts(const DevPop& P, uint32_t cur, uint32_t step, hipStream_t stream) {
-  hipLaunchKernelGGL(k_counts, dim3(P.n_blocks), dim3(kBlockCounts), 0, stream, P, P.U[cur], step);
+hipError_t launch_table(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_table, dim3(g.blocks), dim3(256), 0, stream, B, g);
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const DevPop& P, hipStream_t stream) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, P, P.cap_limit);
+hipError_t launch_counts(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_counts, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const DevPop& P, hipStream_t stream) {
-  hipLaunchKernelGGL(k_scatter, dim3(P.n_blocks), dim3(kBlockCounts), 0, stream, P);
+hipError_t launch_scan(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_scan, dim3(g.blocks), dim3(1024), 0, stream, B, g);
   return hipGetLastError();
 }
 
-template <int LAYOUT>
-hipError_t launch_sweep_layout(const DevPop& P, const SweepParams& sp, hipStream_t stream) {
-  const size_t lds = (size_t)P.N * 8;
-  const dim3 grid(tiles_of(P.capacity)), block(64);
-  switch (P.L) {
-#define PA_SWEEP_CASE(LL)                                                                     \
-  case LL:                                                                                    \
-    hipLaunchKernelGGL((k_sweep<LAYOUT, LL>), grid, block, lds, stream, P, sp, P.sites,       \
-                       P.rowj);                                                               \
-    break;
-    PA_SWEEP_CASE(4)
-    PA_SWEEP_CASE(6)
-    PA_SWEEP_CASE(8)
-    PA_SWEEP_CASE(10)
-    PA_SWEEP_CASE(12)
-    PA_SWEEP_CASE(14)
-    PA_SWEEP_CASE(16)
-#undef PA_SWEEP_CASE
-    default:
-      return hipErrorInvalidValue;
+hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
+  return hipGetLastError();
+}
+
+template <int LAYOUT, int L>
+void launch_sweep_l(const BatchDev& B, const Group& g, hipStream_t stream) {
+  constexpr uint32_t w = sweep_waves<L>();
+  static_assert(w == 1 || w == 2 || w == 4, "1, 2 or 4 waves per block");
+  const size_t lds = (size_t)L * L * L * 8 * w;
+  hipLaunchKernelGGL((k_sweep<LAYOUT, L>), dim3(g.blocks), dim3(64 * w), lds, stream, B, g);
+}
+
+template <int LAYOUT, int L>
+void launch_energy_l(const BatchDev& B, const Group& g, hipStream_t stream) {
+  const size_t lds = (size_t)L * L * L * 8;
+  hipLaunchKernelGGL((k_energy<LAYOUT, L>), dim3(g.blocks), dim3(64), lds, stream, B, g);
+}
+
+#define PA_L_SWITCH(FN, LAYOUT)      \
+  switch (L) {                       \
+    case 4: FN<LAYOUT, 4>(B, g, stream); break;   \
+    case 6: FN<LAYOUT, 6>(B, g, stream); break;   \
+    case 8: FN<LAYOUT, 8>(B, g, stream); break;   \
+    case 10: FN<LAYOUT, 10>(B, g, stream); break; \
+    case 12: FN<LAYOUT, 12>(B, g, stream); break; \
+    case 14: FN<LAYOUT, 14>(B, g, stream); break; \
+    case 16: FN<LAYOUT, 16>(B, g, stream); break; \
+    default: return hipErrorInvalidValue;         \
+  }
+
+hipError_t launch_sweep(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
+                        hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  if (layout == 2) {
+    PA_L_SWITCH(launch_sweep_l, 2)
+  } else {
+    PA_L_SWITCH(launch_sweep_l, 1)
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(const DevPop& P, const SweepParams& sp, hipStream_t stream) {
-  return P.layout == 2 ? launch_sweep_layout<2>(P, sp, stream)
-                       : launch_sweep_layout<1>(P, sp, stream);
+hipError_t launch_energy(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
+                         hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  if (layout == 2) {
+    PA_L_SWITCH(launch_energy_l, 2)
+  } else {
+    PA_L_SWITCH(launch_energy_l, 1)
+  }
+  return hipGetLastError();
 }
+#undef PA_L_SWITCH
 
-hipError_t launch_family(const DevPop& P, uint32_t cur, hipStream_t stream) {
-  hipLaunchKernelGGL(k_family, dim3((P.capacity + 255) / 256), dim3(256), 0, stream, P, P.fam[cur]);
+hipError_t launch_family(const BatchDev& B, const Group& g, bool post, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_family, dim3(g.blocks), dim3(256), 0, stream, B, g, post ? 1u : 0u);
   return hipGetLastError();
 }
 
-hipError_t launch_overlap(const DevPop& A, uint32_t cur_a, const DevPop& B, uint32_t cur_b,
-                          unsigned long long* hist65, hipStream_t stream) {
-  const uint32_t grid = tiles_of(std::min(A.capacity, B.capacity));
-  if (A.layout == 2)
-    hipLaunchKernelGGL(k_overlap<2>, dim3(grid), dim3(64), 0, stream, A, cur_a, B, cur_b, hist65);
+hipError_t launch_record(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_record, dim3(g.blocks), dim3(256), 0, stream, B, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_overlap(const BatchDev& B, const Group& g, const uint32_t* pair_pops,
+                          uint32_t layout, bool post, uint32_t cur_a, uint32_t cur_b,
+                          hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  if (layout == 2)
+    hipLaunchKernelGGL(k_overlap<2>, dim3(g.blocks), dim3(64), 0, stream, B, g, pair_pops,
+                       post ? 1u : 0u, cur_a, cur_b);
   else
-    hipLaunchKernelGGL(k_overlap<1>, dim3(grid), dim3(64), 0, stream, A, cur_a, B, cur_b, hist65);
+    hipLaunchKernelGGL(k_overlap<1>, dim3(g.blocks), dim3(64), 0, stream, B, g, pair_pops,
+                       post ? 1u : 0u, cur_a, cur_b);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, stream, step_ctr);
   return hipGetLastError();
 }
 
