@@ -34,14 +34,28 @@ WORKLOAD = dict(name="L10_R500k_bitpack64_adaptive_eps0.1", L=10, R=500000, eps=
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic work of one spin-flip attempt ("Roofline"):
-#   a quarter of one Philox4x32-10 call: 10 rounds x (2 widening multiplies,
-#   each 4 full-rate issue slots on CDNA, + 4 XOR) / 4 = 30 slots;
-#   local field: 6 (xor with coupling) + 5 (sum) + compare + flip = 13 slots.
-OPS_PER_ATTEMPT = 30 + 13
-# bit-packed HBM bytes per attempt of the fused sweep kernel: read + write
-# one bit per spin once per launch of n_sweeps sweeps, plus ~20 B per replica
-# (src index, U, family in and out).
+# Algorithmic work of one spin-flip attempt, in 32-bit lane operations:
+#   random number: a quarter of one Philox4x32-10 call, 10 rounds x (2 widening
+#   32x32->64 multiplies + 4 XOR) / 4 = 15 (the key schedule is uniform, not
+#   per lane);
+#   Metropolis test: 6 bond products s_i J_ij s_j (XOR), 5 adds for the local
+#   field, 1 table select of the threshold, 2 for the 64-bit compare, 1 flip = 15.
+OPS_PER_ATTEMPT = 15 + 15
+# Algorithmic HBM bytes of one sweep launch: the bit-packed population read and
+# written once (N bits per replica each way) plus 20 B per replica (source index,
+# energy and family label read, energy and family label written).
+BYTES_PER_REPLICA_FIXED = 20
+
+# HBM traffic of the sweep kernel measured with rocprofv3 PMC counters on this
+# workload (FETCH_SIZE scaled by 1/2 and WRITE_SIZE by 1, the factors a plain
+# copy of known size reads), per launch, with the source it was taken on.
+# Reported only while the kernel source is unchanged.
+TRAFFIC = {
+    "kernel_src_sha256": "32c9623546d17c1a71623fe254332c968f72afd19705644c77582f45706768c9",
+    # 41384.2 KiB FETCH_SIZE x 2 + 64959.9 KiB WRITE_SIZE x 1, per k_sweep dispatch
+    "bytes_per_launch": (41384.2 * 2 + 64959.9) * 1024,
+    "profile": "profiles/k_sweep_L10_R500k_bitpack64_hbm_counters.md",
+}
 
 
 def parse():
@@ -50,6 +64,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batch run")
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (used to "
@@ -102,6 +117,111 @@ def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None):
     if pop is not None:
         pop.close()
     return attempts
+
+
+BATCH = dict(name="256_instances_L4-10_R2e4-1e5_2pops_NT101_NS10", n_instances=256, Ls=(4, 6, 8, 10),
+             R_lo=20000, R_hi=100000, n_temps=101, beta_max=5.0, n_sweeps=10, sample_every=16)
+
+
+def batch_instances(c):
+    """The 256 synthetic instances: (L, R, couplings, seed A, seed B), seeded."""
+    import numpy as np
+
+    import pa_inputs
+
+    rng = np.random.Generator(np.random.PCG64(0xBA7C4))
+    out = []
+    for i in range(c["n_instances"]):
+        L = int(rng.choice(c["Ls"]))
+        R = int(rng.integers(c["R_lo"], c["R_hi"] + 1))
+        J = pa_inputs.couplings_pm(L, pa_inputs.coupling_seed(4, i))
+        out.append((L, R, J, pa_inputs.population_seed(4, i, 0), pa_inputs.population_seed(4, i, 1)))
+    return out
+
+
+def batched_bench(pam, layout="bitpack64"):
+    """All instances in one batch (one graph replay per step) against back-to-back
+    single-instance runs of every sample_every-th instance, extrapolated."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    c = BATCH
+    insts = batch_instances(c)
+    betas = oracle.linear_schedule(c["beta_max"], c["n_temps"])
+    n_steps = len(betas) - 1
+    attempts = sum(2 * n_steps * c["n_sweeps"] * L ** 3 * R for (L, R, *_r) in insts)
+    # batched: creation (init of every population, graph capture) + all steps + results
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pops = []
+    for (L, R, J, sa, sb) in insts:
+        pops.append(pam.Population(L, R, J, sa, layout=layout, stream=stream))
+        pops.append(pam.Population(L, R, J, sb, layout=layout, stream=stream))
+    b = pam.Batch(pops, betas, c["n_sweeps"], pairs=[(2 * i, 2 * i + 1) for i in range(len(insts))])
+    t1 = time.perf_counter()
+    b.run()
+    recs, q, status = b.results()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b.close()
+    for p in pops:
+        p.close()
+    del pops
+    torch.cuda.empty_cache()
+    t_batch = t2 - t0
+    # back to back: the same calls one instance at a time, default stream
+    sample = list(range(0, len(insts), c["sample_every"]))
+    identical = True
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for i in sample:
+        L, R, J, sa, sb = insts[i]
+        pa_ = pam.Population(L, R, J, sa, layout=layout)
+        pb_ = pam.Population(L, R, J, sb, layout=layout)
+        for k in range(1, len(betas)):
+            for pidx, p in ((2 * i, pa_), (2 * i + 1, pb_)):
+                p.resample(betas[k])
+                p.sweep(betas[k], c["n_sweeps"])
+                o = p.observables()
+                r = recs[k - 1][pidx]
+                identical &= (o["beta_F"] == r["beta_F"] and o["mean_E"] == r["mean_E"]
+                              and o["rho_t"] == r["rho_t"] and o["R_tilde"] == r["R_tilde"])
+            h = pam.overlap_hist(pa_, pb_)
+            identical &= bool(np.array_equal(h, q[k - 1][i]))
+        pa_.close()
+        pb_.close()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    t_single = (t4 - t3) * len(insts) / len(sample)
+    return {
+        "workload": c["name"],
+        "instances": len(insts),
+        "populations": 2 * len(insts),
+        "steps": n_steps,
+        "attempts": attempts,
+        "batched_seconds": round(t_batch, 3),
+        "batched_setup_seconds": round(t1 - t0, 3),
+        "batched_instances_per_hour": len(insts) * 3600.0 / t_batch,
+        "batched_attempts_per_s": attempts / t_batch,
+        "back_to_back_seconds_extrapolated": round(t_single, 3),
+        "back_to_back_instances_per_hour": len(insts) * 3600.0 / t_single,
+        "back_to_back_sample": f"{len(sample)} of {len(insts)} instances (every {c['sample_every']}th)",
+        "speedup": t_single / t_batch,
+        "identical_on_sample": bool(identical),
+        "capacity_failures": int(np.count_nonzero(status)),
+        "layout": layout,
+    }
+
+
+def kernel_src_sha256():
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1711_02146_amd", "csrc", "pa_kernels.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def cpu_baseline(w):
@@ -165,7 +285,10 @@ def main():
     avg_att = sweep_att / n_launch
     achieved_ops = OPS_PER_ATTEMPT * avg_att / (avg_ms * 1e-3)
     avg_R = avg_att / (w["n_sweeps"] * w["L"] ** 3)
-    bytes_per_launch = 2 * avg_R * w["L"] ** 3 / 8 + 20 * avg_R
+    bytes_per_launch = 2 * avg_R * w["L"] ** 3 / 8 + BYTES_PER_REPLICA_FIXED * avg_R
+    traffic = None
+    if TRAFFIC is not None and TRAFFIC["kernel_src_sha256"] == kernel_src_sha256():
+        traffic = TRAFFIC["bytes_per_launch"]
     line = {
         "metric": "spin-flip attempts/s",
         "value": attempts / wall,
@@ -189,7 +312,10 @@ def main():
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s",
             "frac": achieved_ops / VALU_PEAK_OPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+            "traffic_GBs": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_ms,
             "launches": n_launch,
             "attempts_per_launch": avg_att,
@@ -200,6 +326,10 @@ def main():
         "sweep_fraction_of_wall": sum(sweep_ms) * 1e-3 / wall,
         "beta_reached": stats[-1][0] if stats else None,
     }
+    if not args.no_batched:
+        print("# batched: 256 instances, one graph per step; back-to-back sample", file=sys.stderr,
+              flush=True)
+        line["batched"] = batched_bench(pam)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, one step)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)

@@ -438,6 +438,14 @@ __device__ __forceinline__ uint32_t step_index(const BatchDev& B) {
   return B.steps ? __builtin_amdgcn_readfirstlane(*B.step_ctr) : 0u;
 }
 
+// Element b (0 or 1) of a two-entry array of a descriptor, by select: indexing
+// the array with a run-time value would make the compiler copy the whole
+// descriptor to per-lane scratch memory.
+template <typename T>
+__device__ __forceinline__ T pick(const T (&a)[2], uint32_t b) {
+  return b ? a[1] : a[0];
+}
+
 __device__ __forceinline__ PopStep step_of(const BatchDev& B, uint32_t pop) {
   if (!B.steps) return B.single;
   return B.steps[(size_t)step_index(B) * B.n_pops + pop];
@@ -479,10 +487,10 @@ __global__ __launch_bounds__(64) void k_init(DevPop P, uint32_t cur,
   }
   __syncthreads();
   const uint32_t U = tile_energy(lds, P.sites, P.N);
-  store_tile<LAYOUT>(lds, P.spins[cur], P.N, tile);
+  store_tile<LAYOUT>(lds, pick(P.spins, cur), P.N, tile);
   if (valid) {
-    P.U[cur][r] = U;
-    P.fam[cur][r] = r;
+    pick(P.U, cur)[r] = U;
+    pick(P.fam, cur)[r] = r;
   }
 }
 
@@ -506,7 +514,7 @@ __global__ __launch_bounds__(256) void k_hist(BatchDev B, Group G, uint32_t post
   const DevPop P = B.pops[m.pop];
   if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
-  const uint32_t* U = P.U[post ? sp.cur ^ 1u : sp.cur];
+  const uint32_t* U = pick(P.U, post ? sp.cur ^ 1u : sp.cur);
   for (uint32_t i = threadIdx.x; i < P.n_levels; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const uint32_t R = P.sc->R_tilde;
@@ -642,7 +650,7 @@ __global__ __launch_bounds__(kBlockCounts) void k_counts(BatchDev B, Group G) {
   const DevPop P = B.pops[m.pop];
   if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
-  const uint32_t* U = P.U[sp.cur];
+  const uint32_t* U = pick(P.U, sp.cur);
   const uint32_t R = P.sc->R_tilde;
   const uint32_t i = m.lb * kBlockCounts + threadIdx.x;
   uint32_t n = 0, culled = 0;
@@ -758,13 +766,16 @@ __global__ __launch_bounds__(64 * sweep_waves<L>()) void k_sweep(BatchDev B, Gro
     return;
   }
   if (threadIdx.x < 8)
-    thr_of_nu[threadIdx.x] = threadIdx.x < 3 ? sp.thr[2 - threadIdx.x] : (1ull << 32);
+    thr_of_nu[threadIdx.x] = threadIdx.x == 0   ? sp.thr[2]
+                             : threadIdx.x == 1 ? sp.thr[1]
+                             : threadIdx.x == 2 ? sp.thr[0]
+                                                : (1ull << 32);
   uint32_t* const lds = lds_all + wave * 2 * N;
   const uint32_t j = tile * 64 + lane;
   const bool valid = j < Rs;
   const uint32_t src = valid ? (sp.gather ? P.src[j] : j) : 0u;
   const uint32_t cur = sp.cur, nxt = cur ^ 1u;
-  load_tile_gather<LAYOUT, N>(lds, P.spins[cur], src, valid);
+  load_tile_gather<LAYOUT, N>(lds, pick(P.spins, cur), src, valid);
   TileCtx c;
   c.lds = lds;
   c.thr_of_nu = thr_of_nu;
@@ -789,10 +800,10 @@ __global__ __launch_bounds__(64 * sweep_waves<L>()) void k_sweep(BatchDev B, Gro
     sweep_colour_blocks<L, false>(c, rowj, 0u);
     U = sweep_colour_blocks<L, true>(c, rowj, 1u);
   }
-  store_tile<LAYOUT>(lds, P.spins[nxt], N, tile);
+  store_tile<LAYOUT>(lds, pick(P.spins, nxt), N, tile);
   if (valid) {
-    P.U[nxt][j] = U;
-    P.fam[nxt][j] = P.fam[cur][src];
+    pick(P.U, nxt)[j] = U;
+    pick(P.fam, nxt)[j] = pick(P.fam, cur)[src];
   }
 }
 
@@ -810,13 +821,13 @@ __global__ __launch_bounds__(64) void k_energy(BatchDev B, Group G) {
   const uint32_t lane = lane_id();
   const uint32_t j = tile * 64 + lane;
   const bool valid = j < R;
-  load_tile_gather<LAYOUT, N>(lds, P.spins[sp.cur], valid ? j : 0u, valid);
+  load_tile_gather<LAYOUT, N>(lds, pick(P.spins, sp.cur), valid ? j : 0u, valid);
   TileCtx c;
   c.lds = lds;
   c.hoff = 4u * (lane >> 5);
   c.pos = lane & 31u;
   const uint32_t U = tile_energy_rows<L>(c, P.rowj);
-  if (valid) P.U[sp.cur][j] = U;
+  if (valid) pick(P.U, sp.cur)[j] = U;
 }
 
 // Sum over families of eta^2 (Sec. III.A) from the family labels, which stay
@@ -828,7 +839,7 @@ __global__ __launch_bounds__(256) void k_family(BatchDev B, Group G, uint32_t po
   const DevPop P = B.pops[m.pop];
   if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
-  const uint32_t* fam = P.fam[post ? sp.cur ^ 1u : sp.cur];
+  const uint32_t* fam = pick(P.fam, post ? sp.cur ^ 1u : sp.cur);
   const uint32_t R = P.sc->R_tilde;
   const uint32_t i = m.lb * 256 + threadIdx.x;
   unsigned long long sq = 0, nf = 0;
@@ -914,14 +925,14 @@ __global__ __launch_bounds__(64) void k_overlap(BatchDev B, Group G,
   const uint32_t N = A.N;
   uint32_t d = 0;
   if (LAYOUT == 2) {
-    const unsigned long long* a = static_cast<const unsigned long long*>(A.spins[cur_a]) +
+    const unsigned long long* a = static_cast<const unsigned long long*>(pick(A.spins, cur_a)) +
                                   (size_t)tile * N;
-    const unsigned long long* b = static_cast<const unsigned long long*>(Bp.spins[cur_b]) +
+    const unsigned long long* b = static_cast<const unsigned long long*>(pick(Bp.spins, cur_b)) +
                                   (size_t)tile * N;
     for (uint32_t cm = 0; cm < N; ++cm) d += (uint32_t)((a[cm] ^ b[cm]) >> lane) & 1u;
   } else {
-    const int8_t* a = static_cast<const int8_t*>(A.spins[cur_a]) + (size_t)tile * N * 64 + lane;
-    const int8_t* b = static_cast<const int8_t*>(Bp.spins[cur_b]) + (size_t)tile * N * 64 + lane;
+    const int8_t* a = static_cast<const int8_t*>(pick(A.spins, cur_a)) + (size_t)tile * N * 64 + lane;
+    const int8_t* b = static_cast<const int8_t*>(pick(Bp.spins, cur_b)) + (size_t)tile * N * 64 + lane;
     for (uint32_t cm = 0; cm < N; ++cm) d += a[64 * (size_t)cm] != b[64 * (size_t)cm];
   }
   if (i < n) atomicAdd(&hb[(128u * (N - d) + N) / (2u * N)], 1u);
