@@ -65,6 +65,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batch run")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="arrival window of the serving run (0 skips it)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only run the serving workload and print its JSON object")
+    ap.add_argument("--serve-max-active", type=int, default=0,
+                    help="resident-request limit of the serving run (default 256)")
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (used to "
@@ -216,6 +222,62 @@ def batched_bench(pam, layout="bitpack64"):
     }
 
 
+SERVE = dict(name="poisson4_L4-12_R1e4-2e5_loguniform_NT51-201_NS10", rate=4.0, beta_max=5.0,
+             n_sweeps=10, hbm_budget=64 << 30, max_active=256, max_L=12)
+
+
+def serving_bench(duration_s: float, max_active: int | None = None):
+    """Poisson request stream served with continuous batching (real time)."""
+    import numpy as np
+
+    import pa_inputs
+    from paper_1711_02146_amd.serve import Request, Server
+
+    c = SERVE
+    specs = pa_inputs.serving_requests(duration_s=duration_s, rate=c["rate"])
+    reqs = [Request(rid=d["rid"], arrival=d["arrival"], L=d["L"], R=d["R"], n_temps=d["n_temps"],
+                    n_sweeps=c["n_sweeps"], beta_max=c["beta_max"],
+                    J=pa_inputs.couplings_pm(d["L"], d["coupling_seed"]), seed=d["seed"])
+            for d in specs]
+    srv = Server(hbm_budget=c["hbm_budget"], max_active=max_active or c["max_active"],
+                 max_L=c["max_L"])
+    last = [time.perf_counter()]
+
+    def progress(t, done, active, queued):
+        if time.perf_counter() - last[0] > 10.0:
+            last[0] = time.perf_counter()
+            print(f"# serve t={t:.0f}s done={done} active={active} queued={queued}",
+                  file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    res = srv.run(reqs, realtime=True, progress=progress)
+    wall = time.perf_counter() - t0
+    srv.close()
+    ok = [r for r in res if r.status == 0]
+    lat = np.array([r.latency for r in ok])
+    att = sum(r.attempts for r in ok)
+    span = max(r.finished for r in ok) - min(r.arrival for r in ok)
+    sizes = np.array(srv.tick_sizes)
+    return {
+        "workload": c["name"],
+        "arrival_seconds": duration_s,
+        "requests": len(reqs),
+        "completed": len(ok),
+        "failed": len(res) - len(ok),
+        "offered_attempts_per_s": sum(r.attempts() for r in reqs) / duration_s,
+        "attempts_per_s": att / span,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_max_s": float(lat.max()),
+        "ticks": srv.ticks,
+        "mean_resident": float(sizes.mean()) if sizes.size else 0.0,
+        "max_resident": int(sizes.max()) if sizes.size else 0,
+        "max_active": max_active or c["max_active"],
+        "hbm_budget_bytes": c["hbm_budget"],
+        "wall_seconds": wall,
+    }
+
+
 def kernel_src_sha256():
     import hashlib
 
@@ -264,6 +326,10 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     pam.lib()
+    if args.serve_only:
+        print(json.dumps({"serving": serving_bench(args.serve_seconds,
+                                                   args.serve_max_active or None)}), flush=True)
+        return
     w = WORKLOAD
     J = pa_inputs.couplings_pm(w["L"], pa_inputs.coupling_seed(3, 0))
     seed0 = pa_inputs.population_seed(3, 0, 0)
@@ -330,6 +396,10 @@ def main():
         print("# batched: 256 instances, one graph per step; back-to-back sample", file=sys.stderr,
               flush=True)
         line["batched"] = batched_bench(pam)
+    if args.serve_seconds > 0:
+        print(f"# serving: Poisson arrivals for {args.serve_seconds:.0f} s", file=sys.stderr,
+              flush=True)
+        line["serving"] = serving_bench(args.serve_seconds, args.serve_max_active or None)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, one step)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)

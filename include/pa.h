@@ -210,6 +210,41 @@ int pa_batch_results(pa_batch* b, pa_obs* obs, uint64_t* qhist, int32_t* status,
 /* Release a batch (its instances stay valid). */
 int pa_batch_free(pa_batch* b);
 
+/* ------------------------------------------------------------------------ */
+/* Stepper: continuous batching.  One call advances any set of resident      */
+/* instances by one temperature step each (Sec. II loop: resample to the     */
+/* instance's next beta with Eqs. 1-2, then its n_sweeps sweeps there), all  */
+/* in one set of launches; the set, the temperatures and the sweep counts    */
+/* may differ from call to call, so requests can join and leave between      */
+/* steps.  Each instance draws exactly the numbers it would draw alone, so    */
+/* every result equals that of pa_resample + pa_sweep + pa_observables on    */
+/* the instance by itself, bit for bit.                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct pa_stepper pa_stepper;
+
+/* Device workspace of a stepper for sets of up to max_pops instances of
+ * linear size <= max_L.  0 on bad sizes. */
+size_t pa_stepper_workspace_bytes(uint32_t max_pops, uint32_t max_L);
+
+/* Create a stepper that launches on hip_stream (every instance it steps must
+ * have been created on that stream).  The caller owns d_workspace
+ * (pa_stepper_workspace_bytes bytes, 256-byte aligned) until pa_stepper_free.
+ * libpa allocates a pinned host staging image of the same size. */
+int pa_stepper_create(uint32_t max_pops, uint32_t max_L, void* d_workspace, size_t ws_bytes,
+                      void* hip_stream, pa_stepper** out);
+
+/* One step for n instances (distinct, usable, not in a batch, no pending copy
+ * step): instance p resamples from its current beta to beta_next[p] and runs
+ * n_sweeps[p] sweeps at beta_next[p].  obs[p] (nullable array) receives its
+ * scalars after the step, as pa_observables would report them; status[p]
+ * (nullable array) PA_OK, or PA_ECAPACITY when the copy step would exceed the
+ * capacity (that instance is left as it was).  Synchronises the stream. */
+int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const double* beta_next,
+                    const uint32_t* n_sweeps, pa_obs* obs, int32_t* status);
+
+/* Release a stepper (its instances stay valid). */
+int pa_stepper_free(pa_stepper* s);
+
 /* Static description of a status code. */
 const char* pa_strerror(int status);
 

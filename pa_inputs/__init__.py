@@ -40,6 +40,28 @@ def coupling_seed(config: int, instance: int) -> int:
 WORKLOADS = {
     "c1_l4": dict(L=4, R=1000, n_temps=51, beta_max=5.0, n_sweeps=10, layout="int8", pops=1),
     "c2_l8": dict(L=8, R=100000, n_temps=201, beta_max=5.0, n_sweeps=10, layout="int8", pops=2),
-    "c3_l10": dict(L=10, R=500000, eps=0.1, beta_max=5.0, n_sweeps=10, layout="bitpack32",
+    "c3_l10": dict(L=10, R=500000, eps=0.1, beta_max=5.0, n_sweeps=10, layout="bitpack64",
                    pops=1),
 }
+
+
+def serving_requests(duration_s: float = 600.0, rate: float = 4.0, seed: int = 0x5E4E,
+                     Ls=(4, 6, 8, 10, 12), R_lo: float = 1e4, R_hi: float = 2e5,
+                     n_temps_lo: int = 51, n_temps_hi: int = 201):
+    """A Poisson stream of PA requests (numpy PCG64): exponential inter-arrival
+    times of mean 1/rate up to duration_s; L uniform over Ls; R log-uniform on
+    [R_lo, R_hi]; n_temps uniform on [n_temps_lo, n_temps_hi].  Request i uses
+    coupling_seed(5, i) and population_seed(5, i, 0)."""
+    rng = np.random.Generator(np.random.PCG64(int(seed)))
+    out = []
+    t = 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t > duration_s:
+            break
+        i = len(out)
+        out.append(dict(rid=i, arrival=t, L=int(rng.choice(Ls)),
+                        R=int(round(float(np.exp(rng.uniform(np.log(R_lo), np.log(R_hi)))))),
+                        n_temps=int(rng.integers(n_temps_lo, n_temps_hi + 1)),
+                        coupling_seed=coupling_seed(5, i), seed=population_seed(5, i, 0)))
+    return out

@@ -93,6 +93,11 @@ def lib():
         "pa_batch_run": (ctypes.c_int, [_vp, ctypes.c_uint32]),
         "pa_batch_results": (ctypes.c_int, [_vp, _vp, _vp, _vp, _P(ctypes.c_uint32)]),
         "pa_batch_free": (ctypes.c_int, [_vp]),
+        "pa_stepper_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
+        "pa_stepper_create": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _vp,
+                                             ctypes.c_size_t, _vp, _P(_vp)]),
+        "pa_stepper_step": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp]),
+        "pa_stepper_free": (ctypes.c_int, [_vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -105,7 +110,9 @@ def lib():
 EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample", "pa_choose_beta",
             "pa_observables", "pa_overlap_hist", "pa_export_state", "pa_export_counts",
             "pa_import_state", "pa_free", "pa_strerror", "pa_batch_workspace_bytes",
-            "pa_batch_create", "pa_batch_run", "pa_batch_results", "pa_batch_free"]
+            "pa_batch_create", "pa_batch_run", "pa_batch_results", "pa_batch_free",
+            "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
+            "pa_stepper_free"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -234,6 +241,37 @@ def pa_batch_free(batch: int):
     _check(lib().pa_batch_free(batch), "pa_batch_free")
 
 
+def pa_stepper_workspace_bytes(max_pops: int, max_L: int) -> int:
+    return int(lib().pa_stepper_workspace_bytes(int(max_pops), int(max_L)))
+
+
+def pa_stepper_create(max_pops: int, max_L: int, workspace_ptr: int, ws_bytes: int,
+                      stream_handle: int) -> int:
+    out = _vp()
+    _check(lib().pa_stepper_create(int(max_pops), int(max_L), workspace_ptr, ws_bytes,
+                                   stream_handle, ctypes.byref(out)), "pa_stepper_create")
+    return out.value
+
+
+def pa_stepper_step(stepper: int, handles, beta_next, n_sweeps):
+    """-> (list of pa_obs dicts, status array); one step for every handle."""
+    n = len(handles)
+    hs = (_vp * max(n, 1))(*handles)
+    bt = np.ascontiguousarray(beta_next, np.float64)
+    ns = np.ascontiguousarray(n_sweeps, np.uint32)
+    if bt.size != n or ns.size != n:
+        raise PAError(PA_EINVAL, "pa_stepper_step")
+    obs = (pa_obs * max(n, 1))()
+    st = np.zeros(max(n, 1), np.int32)
+    _check(lib().pa_stepper_step(stepper, ctypes.cast(hs, _vp), n, bt.ctypes.data, ns.ctypes.data,
+                                 ctypes.cast(obs, _vp), st.ctypes.data), "pa_stepper_step")
+    return [obs[p].as_dict() for p in range(n)], st[:n]
+
+
+def pa_stepper_free(stepper: int):
+    _check(lib().pa_stepper_free(stepper), "pa_stepper_free")
+
+
 # --- convenience object owning the workspace ---------------------------------
 class Population:
     """One PA population on a GPU: workspace tensor + library handle."""
@@ -323,6 +361,39 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             pa_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stepper:
+    """Continuous batching: one temperature step for any set of Populations
+    (all created on ``stream``) per call, in one set of launches."""
+
+    def __init__(self, max_pops: int, max_L: int, stream, device=None):
+        import torch
+
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self.stream = stream
+        self.max_pops, self.max_L = int(max_pops), int(max_L)
+        nbytes = pa_stepper_workspace_bytes(self.max_pops, self.max_L)
+        if nbytes == 0:
+            raise PAError(PA_EINVAL, "pa_stepper_workspace_bytes")
+        self.workspace_bytes = nbytes
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = pa_stepper_create(self.max_pops, self.max_L, self.workspace.data_ptr(),
+                                        nbytes, stream.cuda_stream)
+
+    def step(self, pops, beta_next, n_sweeps):
+        return pa_stepper_step(self.handle, [p.handle for p in pops], beta_next, n_sweeps)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            pa_stepper_free(self.handle)
             self.handle = None
 
     def __del__(self):

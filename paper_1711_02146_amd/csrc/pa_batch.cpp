@@ -239,25 +239,14 @@ int pa_batch_create(pa_instance* const* pops, uint32_t n_pops, const uint32_t* p
     }
   }
   // group tables
-  std::vector<uint32_t> u32;
-  u32.reserve(l.n_u32);
-  uint32_t* const d_u32 = reinterpret_cast<uint32_t*>(w + l.off_u32);
-  auto add_group = [&](const std::vector<uint32_t>& members,
-                       const std::vector<uint32_t>& blocks) {
-    pa::Group g{};
-    g.n = (uint32_t)members.size();
-    g.pop = d_u32 + u32.size();
-    for (uint32_t m : members) u32.push_back(m);
-    g.start = d_u32 + u32.size();
-    uint32_t acc = 0;
-    u32.push_back(0);
-    for (uint32_t nb : blocks) {
-      acc += nb;
-      u32.push_back(acc);
-    }
-    g.blocks = acc;
-    return g;
+  pa_host::GroupTables gt;
+  gt.d_base = reinterpret_cast<uint32_t*>(w + l.off_u32);
+  gt.u32.reserve(l.n_u32);
+  auto add_group = [&](const std::vector<uint32_t>& members, const std::vector<uint32_t>& blocks) {
+    return gt.add(members, blocks);
   };
+  std::vector<uint32_t>& u32 = gt.u32;
+  uint32_t* const d_u32 = gt.d_base;
   std::vector<uint32_t> all(n_pops), one(n_pops, 1), slots(n_pops), hist(n_pops);
   for (uint32_t p = 0; p < n_pops; ++p) {
     all[p] = p;

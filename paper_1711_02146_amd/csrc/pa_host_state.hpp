@@ -38,6 +38,30 @@ struct Layout {
   size_t total;
 };
 
+// Host image of the group tables of a multi-population launch set: each
+// group is (member population ids, n + 1 workgroup starts), laid out in one
+// u32 array that is copied to d_base.
+struct GroupTables {
+  std::vector<uint32_t> u32;
+  uint32_t* d_base = nullptr;
+
+  pa::Group add(const std::vector<uint32_t>& members, const std::vector<uint32_t>& blocks) {
+    pa::Group g{};
+    g.n = (uint32_t)members.size();
+    g.pop = d_base + u32.size();
+    for (uint32_t m : members) u32.push_back(m);
+    g.start = d_base + u32.size();
+    uint32_t acc = 0;
+    u32.push_back(0);
+    for (uint32_t nb : blocks) {
+      acc += nb;
+      u32.push_back(acc);
+    }
+    g.blocks = acc;
+    return g;
+  }
+};
+
 // Metropolis thresholds: accept dE > 0 iff word < floor(2^32 exp(-beta dE)).
 inline void thresholds(double beta, unsigned long long thr[3]) {
   for (int i = 0; i < 3; ++i) {
