@@ -83,6 +83,7 @@ struct pa_batch {
   pa::Group g_perpop{}, g_slots{}, g_hist{};
   struct SweepGroup {
     uint32_t layout, L;
+    uint32_t split;  // waves per tile
     pa::Group g;
   };
   std::vector<SweepGroup> g_sweep;
@@ -123,7 +124,7 @@ int capture_step(pa_batch* b) {
             pa::launch_scan(B, b->g_perpop, s) == hipSuccess &&
             pa::launch_scatter(B, b->g_slots, s) == hipSuccess;
   for (const auto& sg : b->g_sweep)
-    ok = ok && pa::launch_sweep(B, sg.g, sg.layout, sg.L, s) == hipSuccess;
+    ok = ok && pa::launch_sweep(B, sg.g, sg.layout, sg.L, sg.split, s) == hipSuccess;
   ok = ok && pa::launch_zero_acc(B, b->g_perpop, s) == hipSuccess &&
        pa::launch_hist(B, b->g_hist, b->max_levels, true, s) == hipSuccess &&
        pa::launch_family(B, b->g_slots, true, s) == hipSuccess &&
@@ -259,9 +260,12 @@ int pa_batch_create(pa_instance* const* pops, uint32_t n_pops, const uint32_t* p
   std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> by_kind;
   for (uint32_t p = 0; p < n_pops; ++p) by_kind[{pops[p]->dev.layout, pops[p]->dev.L}].push_back(p);
   for (const auto& kv : by_kind) {
+    uint64_t tiles = 0;
+    for (uint32_t p : kv.second) tiles += (pops[p]->dev.R + 63) / 64;
+    const uint32_t split = pa::sweep_split_for(kv.first.second, tiles);
     std::vector<uint32_t> nb;
-    for (uint32_t p : kv.second) nb.push_back(pa::blocks_sweep(pops[p]->dev.capacity, kv.first.second));
-    b->g_sweep.push_back({kv.first.first, kv.first.second, add_group(kv.second, nb)});
+    for (uint32_t p : kv.second) nb.push_back(pa::blocks_sweep(pops[p]->dev.capacity));
+    b->g_sweep.push_back({kv.first.first, kv.first.second, split, add_group(kv.second, nb)});
   }
   for (uint32_t layout : {(uint32_t)PA_LAYOUT_INT8, (uint32_t)PA_LAYOUT_BITPACK64}) {
     std::vector<uint32_t> ids, nb;

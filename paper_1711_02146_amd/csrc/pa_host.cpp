@@ -172,11 +172,15 @@ Table resample_table(const uint32_t* h, uint32_t n_levels, uint32_t N, uint32_t 
     }
   if (t.jmin < 0) return t;
   const int jmin = t.jmin;
+  // w_j once per level (both loops use the same value)
+  static thread_local std::vector<double> w;
+  w.resize(n_levels);
+  for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j)
+    w[j] = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
   double S = 0.0;
   for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
     if (h[j] == 0) continue;
-    const double w = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
-    S = S + (double)h[j] * w;
+    S = S + (double)h[j] * w[j];
   }
   for (uint32_t j = 0; j < n_levels; ++j) {
     if ((int)j < jmin) {
@@ -184,8 +188,7 @@ Table resample_table(const uint32_t* h, uint32_t n_levels, uint32_t N, uint32_t 
       T[j] = 0;
       continue;
     }
-    const double w = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
-    const double tau = ((double)R * w) / S;
+    const double tau = ((double)R * w[j]) / S;
     const uint64_t f = (uint64_t)std::floor(tau);
     const double fr = tau - (double)f;
     fl[j] = (uint32_t)f;
@@ -206,17 +209,19 @@ double culling_fraction(const uint32_t* h, uint32_t n_levels, uint32_t R, double
       break;
     }
   if (jmin < 0) return 0.0;
+  // w_j once per occupied level (both sums use the same value)
+  static thread_local std::vector<double> w;
+  w.resize(n_levels);
   double S = 0.0;
   for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
     if (h[j] == 0) continue;
-    const double w = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
-    S = S + (double)h[j] * w;
+    w[j] = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
+    S = S + (double)h[j] * w[j];
   }
   double acc = 0.0;
   for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
     if (h[j] == 0) continue;
-    const double w = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
-    const double tau = ((double)R * w) / S;
+    const double tau = ((double)R * w[j]) / S;
     if (tau < 1.0) acc = acc + (double)h[j] * (1.0 - tau);
   }
   return acc / (double)R;
@@ -250,6 +255,14 @@ pa::PopStep plain_step(uint32_t cur) {
   return ps;
 }
 
+// Sweep launch of one instance (its size after any pending copy sets the
+// waves per tile).
+hipError_t launch_sweep_of(pa_instance* in, const pa::PopStep& ps) {
+  const uint32_t split = pa::sweep_split_for(in->dev.L, ((uint64_t)in->R_tilde + 63) / 64);
+  return pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
+                          in->dev.layout, in->dev.L, split, in->stream);
+}
+
 int dev_fail(pa_instance* in) {
   in->failed = true;
   return PA_EDEVICE;
@@ -267,8 +280,7 @@ int materialize(pa_instance* in) {
   ps.t0 = (uint32_t)in->sweeps;
   ps.n_sweeps = 0;
   ps.gather = 1;
-  PA_HIP(in, pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
-                              in->dev.layout, in->dev.L, in->stream));
+  PA_HIP(in, launch_sweep_of(in, ps));
   in->cur ^= 1u;
   in->pending_gather = false;
   in->hist_valid = false;
@@ -378,7 +390,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   mt.perpop[0] = 0; mt.perpop[1] = 1;
   mt.slots[0] = 0; mt.slots[1] = pa::blocks_slots(l.capacity);
   mt.hist[0] = 0; mt.hist[1] = pa::blocks_hist(l.capacity);
-  mt.tiles[0] = 0; mt.tiles[1] = pa::blocks_sweep(l.capacity, l.L);
+  mt.tiles[0] = 0; mt.tiles[1] = pa::blocks_sweep(l.capacity);
   mt.etiles[0] = 0; mt.etiles[1] = l.capacity / 64;
   mt.pair_pops[0] = 0; mt.pair_pops[1] = 1;
   mt.pairs[0] = 0; mt.pairs[1] = 0;
@@ -441,8 +453,7 @@ int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps) {
   ps.t0 = (uint32_t)in->sweeps;
   ps.n_sweeps = n_sweeps;
   ps.gather = in->pending_gather ? 1u : 0u;
-  PA_HIP(in, pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
-                              in->dev.layout, in->dev.L, in->stream));
+  PA_HIP(in, launch_sweep_of(in, ps));
   in->cur ^= 1u;
   in->pending_gather = false;
   in->hist_valid = false;

@@ -144,9 +144,10 @@ hipError_t launch_table(const BatchDev& B, const Group& per_pop, hipStream_t str
 hipError_t launch_counts(const BatchDev& B, const Group& g, hipStream_t stream);
 hipError_t launch_scan(const BatchDev& B, const Group& per_pop, hipStream_t stream);
 hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream);
-// sweep launch over the populations of one (layout, L) group
+// sweep launch over the populations of one (layout, L) group: one tile per
+// workgroup of `split` (4 or 8) waves; g's blocks are blocks_sweep(capacity)
 hipError_t launch_sweep(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
-                        hipStream_t stream);
+                        uint32_t split, hipStream_t stream);
 hipError_t launch_family(const BatchDev& B, const Group& g, bool post, hipStream_t stream);
 hipError_t launch_record(const BatchDev& B, const Group& per_pop, hipStream_t stream);
 // cur_a / cur_b: the two populations' buffers when B carries no per-step parameters
@@ -160,9 +161,12 @@ hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream);
 // Blocks each population needs in each kind of launch.
 inline uint32_t blocks_hist(uint32_t capacity) { return (capacity + kHistSlots - 1) / kHistSlots; }
 inline uint32_t blocks_slots(uint32_t capacity) { return capacity / kBlockCounts; }
-uint32_t sweep_waves_for(uint32_t L);  // waves (tiles) per sweep workgroup
-inline uint32_t blocks_sweep(uint32_t capacity, uint32_t L) {
-  return capacity / 64 / sweep_waves_for(L);
+inline uint32_t blocks_sweep(uint32_t capacity) { return capacity / 64; }
+// Waves per tile of a sweep launch over `tiles` tiles of linear size L, from
+// timings on MI355X: eight waves pay off on large lattices and on launches too
+// small to fill the chip with four; L = 4 has only four row blocks per colour.
+inline uint32_t sweep_split_for(uint32_t L, uint64_t tiles) {
+  return (L >= 14 || (L >= 6 && tiles < 2048)) ? 8u : 4u;
 }
 
 }  // namespace pa

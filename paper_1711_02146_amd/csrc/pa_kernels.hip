@@ -92,8 +92,11 @@ __device__ __forceinline__ SiteWords load_site(const SiteEntry* __restrict__ sit
 // for a plain copy).  Lanes with valid == false contribute zero bits.  The
 // loads are issued eight sites at a time (N = L^3 is a multiple of 8 for even
 // L) so that many are in flight before their bits are balloted into LDS.
+// Waves that share a tile split its sites: wave `part` of `nparts` takes the
+// groups of eight starting at 8 part, 8 (part + nparts), ...
 template <int LAYOUT, uint32_t N>
-__device__ void load_tile_gather(uint32_t* lds, const void* spins_old, uint32_t src, bool valid) {
+__device__ void load_tile_gather(uint32_t* lds, const void* spins_old, uint32_t src, bool valid,
+                                 uint32_t part, uint32_t nparts) {
   constexpr uint32_t B = 8;
   static_assert(N % B == 0, "N must be a multiple of 8");
   const uint32_t lane = lane_id();
@@ -103,7 +106,7 @@ __device__ void load_tile_gather(uint32_t* lds, const void* spins_old, uint32_t 
                         ((src >> 5) & 1u);
   const int8_t* s8 = static_cast<const int8_t*>(spins_old) + (size_t)stile * N * 64 + (src & 63u);
 #pragma unroll 2
-  for (uint32_t cm0 = 0; cm0 < N; cm0 += B) {
+  for (uint32_t cm0 = B * part; cm0 < N; cm0 += B * nparts) {
     uint32_t v[B];
 #pragma unroll
     for (uint32_t i = 0; i < B; ++i) {
@@ -128,15 +131,17 @@ __device__ void load_tile_gather(uint32_t* lds, const void* spins_old, uint32_t 
 }
 
 template <int LAYOUT>
-__device__ void store_tile(const uint32_t* lds, void* spins_new, uint32_t N, uint32_t tile) {
+__device__ void store_tile(const uint32_t* lds, void* spins_new, uint32_t N, uint32_t tile,
+                           uint32_t part, uint32_t nparts) {
   const uint32_t lane = lane_id();
   if (LAYOUT == 2) {
     uint2* w = static_cast<uint2*>(spins_new) + (size_t)tile * N;
-    for (uint32_t cm = lane; cm < N; cm += kWave) w[cm] = make_uint2(lds[2 * cm], lds[2 * cm + 1]);
+    for (uint32_t cm = lane + kWave * part; cm < N; cm += kWave * nparts)
+      w[cm] = make_uint2(lds[2 * cm], lds[2 * cm + 1]);
   } else {
     int8_t* s8 = static_cast<int8_t*>(spins_new) + (size_t)tile * N * 64 + lane;
     const uint32_t h = lane >> 5, pos = lane & 31u;
-    for (uint32_t cm = 0; cm < N; ++cm)
+    for (uint32_t cm = part; cm < N; cm += nparts)
       s8[64 * (size_t)cm] = bit_of(lds[2 * cm + h], pos) ? (int8_t)-1 : (int8_t)1;
   }
 }
@@ -234,7 +239,9 @@ struct MetPhilox {
 //
 // Rows are walked four at a time: 4 (L/2) sites = L/2 whole Philox groups
 // (colour-major indices 4g .. 4g+3 share one call, word cm & 3 is site cm's),
-// so a block never shares a group with its neighbour.
+// so a block never shares a group with its neighbour.  Waves that share a
+// tile take every nparts-th block (same-colour sites are independent); the
+// pass ends with a workgroup barrier, so the next colour sees every flip.
 //
 // nu = number of unsatisfied bonds at the site (own bit ^ neighbour bit ^
 // [J = -1]); flipping changes the energy by dE = 12 - 4 nu, and the move is
@@ -358,13 +365,13 @@ __device__ __forceinline__ void block_row(const TileCtx& c, const RowAddr& a, ui
 
 template <int L, bool ACCUM>
 __device__ uint32_t sweep_colour_blocks(const TileCtx& c, const unsigned long long* rowj,
-                                        uint32_t colour) {
+                                        uint32_t colour, uint32_t part, uint32_t nparts) {
   constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L;
   const uint32_t own0 = colour * (N / 2);
   uint32_t usum = 0;
   Words4 d;
   d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0u;
-  for (uint32_t rb = 0; rb < ROWS; rb += 4) {
+  for (uint32_t rb = 4 * part; rb < ROWS; rb += 4 * nparts) {
     const uint32_t rbu = __builtin_amdgcn_readfirstlane(rb);
     const uint32_t g0 = (own0 + H * rbu) >> 2;  // first Philox group of the block
     const RowAddr a0 = row_addr<L>(c, rowj, colour, rbu);
@@ -382,10 +389,11 @@ __device__ uint32_t sweep_colour_blocks(const TileCtx& c, const unsigned long lo
 
 // Energy of the tile when no sweep ran: sum over colour-0 sites of nu.
 template <int L>
-__device__ uint32_t tile_energy_rows(const TileCtx& c, const unsigned long long* rowj) {
+__device__ uint32_t tile_energy_rows(const TileCtx& c, const unsigned long long* rowj,
+                                     uint32_t part, uint32_t nparts) {
   constexpr uint32_t H = L / 2, ROWS = L * L;
   uint32_t U = 0;
-  for (uint32_t rho = 0; rho < ROWS; ++rho) {
+  for (uint32_t rho = part; rho < ROWS; rho += nparts) {
     const RowAddr a = row_addr<L>(c, rowj, 0u, __builtin_amdgcn_readfirstlane(rho));
     const uint32_t jlo = (uint32_t)a.j, jhi = (uint32_t)(a.j >> 32);
 #pragma unroll
@@ -487,7 +495,7 @@ __global__ __launch_bounds__(64) void k_init(DevPop P, uint32_t cur,
   }
   __syncthreads();
   const uint32_t U = tile_energy(lds, P.sites, P.N);
-  store_tile<LAYOUT>(lds, pick(P.spins, cur), P.N, tile);
+  store_tile<LAYOUT>(lds, pick(P.spins, cur), P.N, tile, 0u, 1u);
   if (valid) {
     pick(P.U, cur)[r] = U;
     pick(P.fam, cur)[r] = r;
@@ -528,62 +536,116 @@ __global__ __launch_bounds__(256) void k_hist(BatchDev B, Group G, uint32_t post
     if (h[i]) atomicAdd(&P.hist[i], h[i]);
 }
 
+// Position of this thread's element among the flagged elements of the block,
+// in thread order (wave ballots + per-wave counts in LDS); *total receives
+// the number of flagged elements.  Every thread of the block must call it.
+template <int BLOCK>
+__device__ uint32_t block_compact_pos(bool flag, uint32_t* wcount, uint32_t* total) {
+  constexpr int NW = BLOCK / kWave;
+  const uint32_t lane = lane_id(), wid = threadIdx.x / kWave;
+  const unsigned long long b = __ballot(flag);
+  const uint32_t below = (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+  __syncthreads();  // wcount may still be read from the previous call
+  if (lane == 0) wcount[wid] = (uint32_t)__popcll(b);
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t c = wcount[w];
+    off += (uint32_t)w < wid ? c : 0u;
+    tot += c;
+  }
+  *total = tot;
+  return off + below;
+}
+
 // Resampling table on the device (Sec. II, Eqs. 1-2), the same arithmetic as
 // the host builder: j_min = lowest occupied level, w_j = erow[j - j_min]
 // (erow holds exp(-dbeta * 2d) from the host's exp), S = sum over occupied
-// levels, ascending, of h_j w_j (one thread, in order), tau_j = R w_j / S,
-// fl_j = floor(tau_j), T_j = ceil(frac(tau_j) 2^53).  The culling fraction
-// (Sec. III.C) is summed the same way.  S, j_min and R~ are recorded; the
-// host finishes ln Q = ln S - ln R~ - dbeta E_min with its own log.
-__global__ __launch_bounds__(256) void k_table(BatchDev B, Group G) {
-  __shared__ double sS;
+// levels, ascending, of h_j w_j, tau_j = R w_j / S, fl_j = floor(tau_j),
+// T_j = ceil(frac(tau_j) 2^53).  The culling fraction (Sec. III.C) is summed
+// the same way.  Each rounded product or term depends on its level only, so
+// the block forms them in parallel, 1024 levels at a time, packs the occupied
+// ones in level order into LDS, and one thread adds them in that order: the
+// sums round exactly as the host's sequential loops.  S, j_min and R~ are
+// recorded; the host finishes ln Q = ln S - ln R~ - dbeta E_min with its log.
+constexpr int kTableBlock = 1024;
+
+__global__ __launch_bounds__(kTableBlock) void k_table(BatchDev B, Group G) {
+  __shared__ double part[kTableBlock];
+  __shared__ uint32_t wcount[kTableBlock / kWave];
+  __shared__ double sS, sacc;
   __shared__ int sjmin;
   const Member m = member_of(G);
   const DevPop P = B.pops[m.pop];
   if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
   const uint32_t* h = P.hist;
+  const uint32_t nl = P.n_levels;
   const double R = (double)P.R;
   if (threadIdx.x == 0) {
-    int jmin = -1;
-    for (uint32_t j = 0; j < P.n_levels; ++j)
-      if (h[j] > 0) {
-        jmin = (int)j;
-        break;
+    sjmin = 0x7FFFFFFF;
+    sS = 0.0;
+    sacc = 0.0;
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < nl; j += kTableBlock)
+    if (h[j] > 0) atomicMin(&sjmin, (int)j);
+  __syncthreads();
+  const int jmin = sjmin == 0x7FFFFFFF ? -1 : sjmin;
+  if (jmin >= 0) {
+    // S = sum_j h_j w_j, ascending over occupied levels
+    for (uint32_t base = (uint32_t)jmin; base < nl; base += kTableBlock) {
+      const uint32_t j = base + threadIdx.x;
+      const uint32_t hj = j < nl ? h[j] : 0u;
+      uint32_t n;
+      const uint32_t pos = block_compact_pos<kTableBlock>(hj > 0, wcount, &n);
+      if (hj > 0) part[pos] = __dmul_rn((double)hj, sp.erow[j - (uint32_t)jmin]);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double S = sS;
+        for (uint32_t i = 0; i < n; ++i) S = __dadd_rn(S, part[i]);
+        sS = S;
       }
-    double S = 0.0;
-    double eps = 0.0;
-    if (jmin >= 0) {
-      for (uint32_t j = (uint32_t)jmin; j < P.n_levels; ++j) {
-        if (h[j] == 0) continue;
-        const double w = sp.erow[j - (uint32_t)jmin];
-        S = __dadd_rn(S, __dmul_rn((double)h[j], w));
-      }
-      double acc = 0.0;
-      for (uint32_t j = (uint32_t)jmin; j < P.n_levels; ++j) {
-        if (h[j] == 0) continue;
-        const double w = sp.erow[j - (uint32_t)jmin];
-        const double tau = __ddiv_rn(__dmul_rn(R, w), S);
-        if (tau < 1.0) acc = __dadd_rn(acc, __dmul_rn((double)h[j], __dsub_rn(1.0, tau)));
-      }
-      eps = __ddiv_rn(acc, R);
     }
-    sS = S;
-    sjmin = jmin;
+    __syncthreads();
+    const double S = sS;
+    // eps R = sum over occupied levels with tau_j < 1 of h_j (1 - tau_j), ascending
+    for (uint32_t base = (uint32_t)jmin; base < nl; base += kTableBlock) {
+      const uint32_t j = base + threadIdx.x;
+      const uint32_t hj = j < nl ? h[j] : 0u;
+      double term = 0.0;
+      bool take = false;
+      if (hj > 0) {
+        const double tau = __ddiv_rn(__dmul_rn(R, sp.erow[j - (uint32_t)jmin]), S);
+        take = tau < 1.0;
+        term = __dmul_rn((double)hj, __dsub_rn(1.0, tau));
+      }
+      uint32_t n;
+      const uint32_t pos = block_compact_pos<kTableBlock>(take, wcount, &n);
+      if (take) part[pos] = term;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double acc = sacc;
+        for (uint32_t i = 0; i < n; ++i) acc = __dadd_rn(acc, part[i]);
+        sacc = acc;
+      }
+    }
+  }
+  __syncthreads();
+  const double S = sS;
+  if (threadIdx.x == 0) {
     StepRecord* rec = record_of(B, m.pop);
     if (rec) {
       rec->S = S;
-      rec->eps = eps;
+      rec->eps = jmin >= 0 ? __ddiv_rn(sacc, R) : 0.0;
       rec->jmin = jmin;
       rec->R_old = P.sc->R_tilde;
       rec->status = 0;
     }
   }
-  __syncthreads();
-  const double S = sS;
-  const int jmin = sjmin;
   if (jmin < 0) return;
-  for (uint32_t j = threadIdx.x; j < P.n_levels; j += blockDim.x) {
+  for (uint32_t j = threadIdx.x; j < nl; j += kTableBlock) {
     if ((int)j < jmin) {
       P.table_fl[j] = 0;
       P.table_T[j] = 0;
@@ -728,22 +790,30 @@ __global__ __launch_bounds__(kBlockCounts) void k_scatter(BatchDev B, Group G) {
   }
 }
 
-// Waves per workgroup of the sweep kernel.  Every wave owns one tile and its
-// own LDS image; the workgroup only shares the threshold table and barriers.
-// One-wave workgroups run out of workgroup slots before LDS is full, so small
-// lattices pack four waves per workgroup (L <= 10: still 20 waves per CU by
-// LDS); larger ones keep one wave so that LDS is not wasted on fragments.
+// Gather (optional) + n_sweeps checkerboard Metropolis sweeps + energy for
+// one 64-replica tile per workgroup.  Reads buffer cur, writes buffer cur ^ 1.
+// SPLIT wavefronts share the tile's LDS image: each takes every SPLIT-th
+// group of eight sites in the gather and the store, and every SPLIT-th block
+// of four rows in each colour pass (same-colour sites are independent), with
+// a workgroup barrier between colours.  Every lane still owns one replica, and
+// every draw is addressed by (slot, sweep, site group), so the split changes
+// nothing in the results.  Sharing a tile among waves keeps SPLIT times more
+// waves in flight per tile than one wave per tile would, and shortens the walk
+// of each tile by the same factor.
+//
+// For L >= 10 the register budget is held to six waves per SIMD (measured:
+// the few values this moves to scratch cost less than the added occupancy
+// gains); smaller lattices keep the compiler's choice.
 template <int L>
-constexpr uint32_t sweep_waves() {
-  return L <= 10 ? 4u : 1u;
+constexpr int sweep_min_waves_per_eu() {
+  return L >= 10 ? 6 : 1;
 }
 
-// Gather (optional) + n_sweeps checkerboard Metropolis sweeps + energy, one
-// wavefront per 64-replica tile.  Reads buffer cur, writes buffer cur ^ 1.
-template <int LAYOUT, int L>
-__global__ __launch_bounds__(64 * sweep_waves<L>()) void k_sweep(BatchDev B, Group G) {
+template <int LAYOUT, int L, int SPLIT>
+__global__ __launch_bounds__(64 * SPLIT)
+__attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L>()))) void k_sweep(BatchDev B,
+                                                                                Group G) {
   constexpr uint32_t N = L * L * L;
-  constexpr uint32_t kSweepWaves = sweep_waves<L>();
   __shared__ unsigned long long thr_of_nu[8];  // first LDS object: address 0 (see site_update)
   extern __shared__ uint32_t lds_all[];
   const Member m = member_of(G);
@@ -751,13 +821,12 @@ __global__ __launch_bounds__(64 * sweep_waves<L>()) void k_sweep(BatchDev B, Gro
   if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
   const uint32_t lane = lane_id();
-  const uint32_t wave = threadIdx.x / 64;
-  const uint32_t tile = m.lb * kSweepWaves + wave;
+  const uint32_t part = threadIdx.x / 64;  // this wave's share of the tile
+  const uint32_t tile = m.lb;
   if (sp.gather && m.lb == 0 && threadIdx.x == 0) P.sc->R_tilde = P.sc->R_next;
   const uint32_t Rs = sp.gather ? P.sc->R_next : P.sc->R_tilde;
-  // whole workgroups leave together (the passes below use workgroup barriers);
-  // waves of the last workgroup that lie past the population run with no valid lane
-  if (m.lb * kSweepWaves * 64 >= Rs) return;
+  // whole workgroups leave together (the passes below use workgroup barriers)
+  if (tile * 64 >= Rs) return;
   // site_update indexes the threshold table by byte address 8 nu: it must sit
   // at LDS address 0.  If the toolchain ever places it elsewhere, report a
   // configuration error instead of computing with a wrong table.
@@ -770,12 +839,12 @@ __global__ __launch_bounds__(64 * sweep_waves<L>()) void k_sweep(BatchDev B, Gro
                              : threadIdx.x == 1 ? sp.thr[1]
                              : threadIdx.x == 2 ? sp.thr[0]
                                                 : (1ull << 32);
-  uint32_t* const lds = lds_all + wave * 2 * N;
+  uint32_t* const lds = lds_all;
   const uint32_t j = tile * 64 + lane;
   const bool valid = j < Rs;
   const uint32_t src = valid ? (sp.gather ? P.src[j] : j) : 0u;
   const uint32_t cur = sp.cur, nxt = cur ^ 1u;
-  load_tile_gather<LAYOUT, N>(lds, pick(P.spins, cur), src, valid);
+  load_tile_gather<LAYOUT, N>(lds, pick(P.spins, cur), src, valid, part, SPLIT);
   TileCtx c;
   c.lds = lds;
   c.thr_of_nu = thr_of_nu;
@@ -789,19 +858,27 @@ __global__ __launch_bounds__(64 * sweep_waves<L>()) void k_sweep(BatchDev B, Gro
   const unsigned long long* rowj = P.rowj;
   uint32_t U;
   if (sp.n_sweeps == 0) {
-    U = tile_energy_rows<L>(c, rowj);
+    U = tile_energy_rows<L>(c, rowj, part, SPLIT);
   } else {
     for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
       c.t = sp.t0 + s;
-      sweep_colour_blocks<L, false>(c, rowj, 0u);
-      sweep_colour_blocks<L, false>(c, rowj, 1u);
+      sweep_colour_blocks<L, false>(c, rowj, 0u, part, SPLIT);
+      sweep_colour_blocks<L, false>(c, rowj, 1u, part, SPLIT);
     }
     c.t = sp.t0 + sp.n_sweeps - 1;
-    sweep_colour_blocks<L, false>(c, rowj, 0u);
-    U = sweep_colour_blocks<L, true>(c, rowj, 1u);
+    sweep_colour_blocks<L, false>(c, rowj, 0u, part, SPLIT);
+    U = sweep_colour_blocks<L, true>(c, rowj, 1u, part, SPLIT);
   }
-  store_tile<LAYOUT>(lds, pick(P.spins, nxt), N, tile);
-  if (valid) {
+  // per-replica sum of the waves' shares (after the tile image, in LDS)
+  uint32_t* const ured = lds_all + 2 * N;
+  __syncthreads();
+  ured[part * 64 + lane] = U;
+  __syncthreads();
+  U = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < (uint32_t)SPLIT; ++w) U += ured[w * 64 + lane];
+  store_tile<LAYOUT>(lds, pick(P.spins, nxt), N, tile, part, SPLIT);
+  if (valid && part == 0) {
     pick(P.U, nxt)[j] = U;
     pick(P.fam, nxt)[j] = pick(P.fam, cur)[src];
   }
@@ -821,12 +898,12 @@ __global__ __launch_bounds__(64) void k_energy(BatchDev B, Group G) {
   const uint32_t lane = lane_id();
   const uint32_t j = tile * 64 + lane;
   const bool valid = j < R;
-  load_tile_gather<LAYOUT, N>(lds, pick(P.spins, sp.cur), valid ? j : 0u, valid);
+  load_tile_gather<LAYOUT, N>(lds, pick(P.spins, sp.cur), valid ? j : 0u, valid, 0u, 1u);
   TileCtx c;
   c.lds = lds;
   c.hoff = 4u * (lane >> 5);
   c.pos = lane & 31u;
-  const uint32_t U = tile_energy_rows<L>(c, P.rowj);
+  const uint32_t U = tile_energy_rows<L>(c, P.rowj, 0u, 1u);
   if (valid) pick(P.U, sp.cur)[j] = U;
 }
 
@@ -949,18 +1026,6 @@ inline uint32_t tiles_of(uint32_t n) { return (n + 63) / 64; }
 
 }  // namespace
 
-uint32_t sweep_waves_for(uint32_t L) {
-  switch (L) {
-    case 4: return sweep_waves<4>();
-    case 6: return sweep_waves<6>();
-    case 8: return sweep_waves<8>();
-    case 10: return sweep_waves<10>();
-    case 12: return sweep_waves<12>();
-    case 14: return sweep_waves<14>();
-    default: return sweep_waves<16>();
-  }
-}
-
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -998,7 +1063,7 @@ hipError_t launch_hist(const BatchDev& B, const Group& g, uint32_t max_levels, b
 
 hipError_t launch_table(const BatchDev& B, const Group& g, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
-  hipLaunchKernelGGL(k_table, dim3(g.blocks), dim3(256), 0, stream, B, g);
+  hipLaunchKernelGGL(k_table, dim3(g.blocks), dim3(kTableBlock), 0, stream, B, g);
   return hipGetLastError();
 }
 
@@ -1021,11 +1086,12 @@ hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream)
 }
 
 template <int LAYOUT, int L>
-void launch_sweep_l(const BatchDev& B, const Group& g, hipStream_t stream) {
-  constexpr uint32_t w = sweep_waves<L>();
-  static_assert(w == 1 || w == 2 || w == 4, "1, 2 or 4 waves per block");
-  const size_t lds = (size_t)L * L * L * 8 * w;
-  hipLaunchKernelGGL((k_sweep<LAYOUT, L>), dim3(g.blocks), dim3(64 * w), lds, stream, B, g);
+void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, hipStream_t stream) {
+  const size_t lds = (size_t)L * L * L * 8 + 4 * 64 * split;
+  if (split == 8)
+    hipLaunchKernelGGL((k_sweep<LAYOUT, L, 8>), dim3(g.blocks), dim3(64 * 8), lds, stream, B, g);
+  else
+    hipLaunchKernelGGL((k_sweep<LAYOUT, L, 4>), dim3(g.blocks), dim3(64 * 4), lds, stream, B, g);
 }
 
 template <int LAYOUT, int L>
@@ -1046,13 +1112,26 @@ void launch_energy_l(const BatchDev& B, const Group& g, hipStream_t stream) {
     default: return hipErrorInvalidValue;         \
   }
 
+#define PA_L_SWITCH_S(FN, LAYOUT)                        \
+  switch (L) {                                           \
+    case 4: FN<LAYOUT, 4>(B, g, split, stream); break;   \
+    case 6: FN<LAYOUT, 6>(B, g, split, stream); break;   \
+    case 8: FN<LAYOUT, 8>(B, g, split, stream); break;   \
+    case 10: FN<LAYOUT, 10>(B, g, split, stream); break; \
+    case 12: FN<LAYOUT, 12>(B, g, split, stream); break; \
+    case 14: FN<LAYOUT, 14>(B, g, split, stream); break; \
+    case 16: FN<LAYOUT, 16>(B, g, split, stream); break; \
+    default: return hipErrorInvalidValue;                \
+  }
+
 hipError_t launch_sweep(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
-                        hipStream_t stream) {
+                        uint32_t split, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
+  if (split != 4 && split != 8) return hipErrorInvalidValue;
   if (layout == 2) {
-    PA_L_SWITCH(launch_sweep_l, 2)
+    PA_L_SWITCH_S(launch_sweep_l, 2)
   } else {
-    PA_L_SWITCH(launch_sweep_l, 1)
+    PA_L_SWITCH_S(launch_sweep_l, 1)
   }
   return hipGetLastError();
 }
@@ -1068,6 +1147,7 @@ hipError_t launch_energy(const BatchDev& B, const Group& g, uint32_t layout, uin
   return hipGetLastError();
 }
 #undef PA_L_SWITCH
+#undef PA_L_SWITCH_S
 
 hipError_t launch_family(const BatchDev& B, const Group& g, bool post, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;

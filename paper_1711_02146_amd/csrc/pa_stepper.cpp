@@ -178,15 +178,19 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
   const pa::Group g_hist = gt.add(all, hist);
   struct SweepGroup {
     uint32_t layout, L;
+    uint32_t split;  // waves per tile
     pa::Group g;
   };
   std::vector<SweepGroup> g_sweep;
   std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> by_kind;
   for (uint32_t p = 0; p < n; ++p) by_kind[{pops[p]->dev.layout, pops[p]->dev.L}].push_back(p);
   for (const auto& kv : by_kind) {
+    uint64_t tiles = 0;
+    for (uint32_t p : kv.second) tiles += (pops[p]->dev.R + 63) / 64;
+    const uint32_t split = pa::sweep_split_for(kv.first.second, tiles);
     std::vector<uint32_t> nb;
-    for (uint32_t p : kv.second) nb.push_back(pa::blocks_sweep(pops[p]->dev.capacity, kv.first.second));
-    g_sweep.push_back({kv.first.first, kv.first.second, gt.add(kv.second, nb)});
+    for (uint32_t p : kv.second) nb.push_back(pa::blocks_sweep(pops[p]->dev.capacity));
+    g_sweep.push_back({kv.first.first, kv.first.second, split, gt.add(kv.second, nb)});
   }
   if (gt.u32.size() > l.n_u32) return PA_EINVAL;
   std::memcpy(img + l.off_u32, gt.u32.data(), gt.u32.size() * 4);
@@ -211,7 +215,7 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
             pa::launch_counts(B, g_slots, st) == hipSuccess &&
             pa::launch_scan(B, g_perpop, st) == hipSuccess &&
             pa::launch_scatter(B, g_slots, st) == hipSuccess;
-  for (const auto& sg : g_sweep) ok = ok && pa::launch_sweep(B, sg.g, sg.layout, sg.L, st) == hipSuccess;
+  for (const auto& sg : g_sweep) ok = ok && pa::launch_sweep(B, sg.g, sg.layout, sg.L, sg.split, st) == hipSuccess;
   ok = ok && pa::launch_zero_acc(B, g_perpop, st) == hipSuccess &&
        pa::launch_hist(B, g_hist, max_levels, true, st) == hipSuccess &&
        pa::launch_family(B, g_slots, true, st) == hipSuccess &&

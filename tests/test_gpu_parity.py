@@ -81,6 +81,23 @@ def test_sweep_parity(pam, layout, beta):
     g.close()
 
 
+@pytest.mark.parametrize("layout", ["int8", "bitpack64"])
+@pytest.mark.parametrize("L,R", [(4, 140000), (6, 140000), (4, 131071), (6, 5000)])
+def test_sweep_forms_parity(pam, layout, L, R):
+    """Both sweep forms: one tile per wave (populations of 2048 tiles and more)
+    and the shared-tile form (fewer tiles), each bit-exact against the oracle,
+    through two resampling steps (gather fused into the sweep) at beta 0.4, 0.8."""
+    say("sweep forms", layout, L, R)
+    J, g, o = pair(pam, L, R, 4321 + R, layout, 9 + L)
+    for b in (0.4, 0.8):
+        g.resample(b)
+        o.resample(b)
+        g.sweep(b, 2)
+        o.sweep(b, 2)
+        assert_state(g, o, f"L={L} R={R} after the step to beta={b}")
+    g.close()
+
+
 def _compare_step(g, o, k):
     c, off = g.export_counts()
     np.testing.assert_array_equal(c, o.last["n"], err_msg=f"counts step {k}")
