@@ -161,7 +161,10 @@ hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream);
 // Blocks each population needs in each kind of launch.
 inline uint32_t blocks_hist(uint32_t capacity) { return (capacity + kHistSlots - 1) / kHistSlots; }
 inline uint32_t blocks_slots(uint32_t capacity) { return capacity / kBlockCounts; }
-inline uint32_t blocks_sweep(uint32_t capacity) { return capacity / 64; }
+// One block per tile, rounded up to a multiple of 8 so that every population
+// of a launch starts at a block number divisible by the XCD count (the extra
+// blocks find no replicas and leave).
+inline uint32_t blocks_sweep(uint32_t capacity) { return (capacity / 64 + 7) / 8 * 8; }
 // Waves per tile of a sweep launch over `tiles` tiles of linear size L, from
 // timings on MI355X: eight waves pay off on large lattices and on launches too
 // small to fill the chip with four; L = 4 has only four row blocks per colour.

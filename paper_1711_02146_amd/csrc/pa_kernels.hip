@@ -425,8 +425,22 @@ struct Member {
   uint32_t m;    // member index within the group
 };
 
-__device__ __forceinline__ Member member_of(const Group& g) {
-  const uint32_t b = blockIdx.x;
+// The hardware deals the workgroups of a launch round-robin to the 8 XCDs
+// (workgroup b to XCD b mod 8), each with its own L2.  xcd_block renumbers
+// blocks 0 .. nb-1 so that each XCD takes one contiguous range: XCD x takes
+// the x-th range (ranges as equal as possible), so neighbouring tiles, which
+// read overlapping old tiles in the gather, share an L2.  A bijection on
+// [0, nb); it needs block numbers whose residue mod 8 is the XCD, which holds
+// within a population because its sweep blocks start at a multiple of 8.
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t xcd = b % kXcds, idx = b / kXcds;
+  const uint32_t base = nb / kXcds, rem = nb % kXcds;
+  return xcd < rem ? xcd * (base + 1) + idx : rem * (base + 1) + (xcd - rem) * base + idx;
+}
+
+__device__ __forceinline__ Member member_of_block(const Group& g, uint32_t b) {
   uint32_t lo = 0, hi = g.n;  // start[lo] <= b < start[hi]
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
@@ -441,6 +455,8 @@ __device__ __forceinline__ Member member_of(const Group& g) {
   r.nb = __builtin_amdgcn_readfirstlane(g.start[r.m + 1]) - s0;
   return r;
 }
+
+__device__ __forceinline__ Member member_of(const Group& g) { return member_of_block(g, blockIdx.x); }
 
 __device__ __forceinline__ uint32_t step_index(const BatchDev& B) {
   return B.steps ? __builtin_amdgcn_readfirstlane(*B.step_ctr) : 0u;
@@ -801,12 +817,11 @@ __global__ __launch_bounds__(kBlockCounts) void k_scatter(BatchDev B, Group G) {
 // waves in flight per tile than one wave per tile would, and shortens the walk
 // of each tile by the same factor.
 //
-// For L >= 10 the register budget is held to six waves per SIMD (measured:
-// the few values this moves to scratch cost less than the added occupancy
-// gains); smaller lattices keep the compiler's choice.
+// Register budget: as many waves per SIMD as fit without spilling to scratch
+// memory (eight up to L = 10, seven at L = 12, six above).
 template <int L>
 constexpr int sweep_min_waves_per_eu() {
-  return L >= 10 ? 6 : 1;
+  return L <= 10 ? 8 : L == 12 ? 7 : 6;
 }
 
 template <int LAYOUT, int L, int SPLIT>
@@ -821,10 +836,17 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L>()))) void k_sweep(B
   if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
   const uint32_t lane = lane_id();
-  const uint32_t part = threadIdx.x / 64;  // this wave's share of the tile
-  const uint32_t tile = m.lb;
+  // this wave's share of the tile (uniform: a scalar register)
+  const uint32_t part = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   if (sp.gather && m.lb == 0 && threadIdx.x == 0) P.sc->R_tilde = P.sc->R_next;
-  const uint32_t Rs = sp.gather ? P.sc->R_next : P.sc->R_tilde;
+  // uniform: held in a scalar register
+  const uint32_t Rs =
+      __builtin_amdgcn_readfirstlane(sp.gather ? P.sc->R_next : P.sc->R_tilde);
+  // the tiles that hold replicas are spread over the XCDs in contiguous
+  // ranges; blocks past them keep their number and leave
+  const uint32_t active = (Rs + 63) / 64;
+  const uint32_t tile =
+      __builtin_amdgcn_readfirstlane(m.lb < active ? xcd_block(m.lb, active) : m.lb);
   // whole workgroups leave together (the passes below use workgroup barriers)
   if (tile * 64 >= Rs) return;
   // site_update indexes the threshold table by byte address 8 nu: it must sit
@@ -843,8 +865,7 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L>()))) void k_sweep(B
   const uint32_t j = tile * 64 + lane;
   const bool valid = j < Rs;
   const uint32_t src = valid ? (sp.gather ? P.src[j] : j) : 0u;
-  const uint32_t cur = sp.cur, nxt = cur ^ 1u;
-  load_tile_gather<LAYOUT, N>(lds, pick(P.spins, cur), src, valid, part, SPLIT);
+  load_tile_gather<LAYOUT, N>(lds, pick(P.spins, sp.cur), src, valid, part, SPLIT);
   TileCtx c;
   c.lds = lds;
   c.thr_of_nu = thr_of_nu;
@@ -869,18 +890,30 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L>()))) void k_sweep(B
     sweep_colour_blocks<L, false>(c, rowj, 0u, part, SPLIT);
     U = sweep_colour_blocks<L, true>(c, rowj, 1u, part, SPLIT);
   }
+  // Epilogue.  The lane number, the slot, its source and the descriptor
+  // fields are formed or read again here rather than held in registers
+  // through the sweeps (held, some are spilled to scratch memory); the asm
+  // statements keep the compiler from reusing the first values.
+  uint32_t lane2, pop2 = m.pop;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lane2));
+  asm volatile("" : "+s"(pop2));
   // per-replica sum of the waves' shares (after the tile image, in LDS)
   uint32_t* const ured = lds_all + 2 * N;
   __syncthreads();
-  ured[part * 64 + lane] = U;
+  ured[part * 64 + lane2] = U;
   __syncthreads();
   U = 0;
 #pragma unroll
-  for (uint32_t w = 0; w < (uint32_t)SPLIT; ++w) U += ured[w * 64 + lane];
-  store_tile<LAYOUT>(lds, pick(P.spins, nxt), N, tile, part, SPLIT);
-  if (valid && part == 0) {
-    pick(P.U, nxt)[j] = U;
-    pick(P.fam, nxt)[j] = pick(P.fam, cur)[src];
+  for (uint32_t w = 0; w < (uint32_t)SPLIT; ++w) U += ured[w * 64 + lane2];
+  const DevPop P2 = B.pops[pop2];
+  const PopStep sp2 = step_of(B, pop2);
+  const uint32_t cur2 = sp2.cur, nxt2 = cur2 ^ 1u;
+  store_tile<LAYOUT>(lds, pick(P2.spins, nxt2), N, tile, part, SPLIT);
+  const uint32_t j2 = tile * 64 + lane2;
+  if (j2 < Rs && part == 0) {
+    const uint32_t src2 = sp2.gather ? P2.src[j2] : j2;
+    pick(P2.U, nxt2)[j2] = U;
+    pick(P2.fam, nxt2)[j2] = pick(P2.fam, cur2)[src2];
   }
 }
 
