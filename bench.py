@@ -71,6 +71,10 @@ def parse():
                     help="only run the serving workload and print its JSON object")
     ap.add_argument("--serve-max-active", type=int, default=0,
                     help="resident-request limit of the serving run (default 256)")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="request rate of the serving run (default 4 per second)")
+    ap.add_argument("--serve-lockstep", action="store_true",
+                    help="step every resident request on every tick (no work-fair selection)")
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (used to "
@@ -226,7 +230,8 @@ SERVE = dict(name="poisson4_L4-12_R1e4-2e5_loguniform_NT51-201_NS10", rate=4.0, 
              n_sweeps=10, hbm_budget=64 << 30, max_active=256, max_L=12)
 
 
-def serving_bench(duration_s: float, max_active: int | None = None):
+def serving_bench(duration_s: float, max_active: int | None = None, rate: float | None = None,
+                  fair: bool = True):
     """Poisson request stream served with continuous batching (real time)."""
     import numpy as np
 
@@ -234,13 +239,14 @@ def serving_bench(duration_s: float, max_active: int | None = None):
     from paper_1711_02146_amd.serve import Request, Server
 
     c = SERVE
-    specs = pa_inputs.serving_requests(duration_s=duration_s, rate=c["rate"])
+    rate = rate or c["rate"]
+    specs = pa_inputs.serving_requests(duration_s=duration_s, rate=rate)
     reqs = [Request(rid=d["rid"], arrival=d["arrival"], L=d["L"], R=d["R"], n_temps=d["n_temps"],
                     n_sweeps=c["n_sweeps"], beta_max=c["beta_max"],
                     J=pa_inputs.couplings_pm(d["L"], d["coupling_seed"]), seed=d["seed"])
             for d in specs]
     srv = Server(hbm_budget=c["hbm_budget"], max_active=max_active or c["max_active"],
-                 max_L=c["max_L"])
+                 max_L=c["max_L"], fair=fair)
     last = [time.perf_counter()]
 
     def progress(t, done, active, queued):
@@ -259,7 +265,9 @@ def serving_bench(duration_s: float, max_active: int | None = None):
     span = max(r.finished for r in ok) - min(r.arrival for r in ok)
     sizes = np.array(srv.tick_sizes)
     return {
-        "workload": c["name"],
+        "workload": c["name"] if rate == c["rate"] else c["name"].replace("poisson4", f"poisson{rate:g}"),
+        "rate_per_s": rate,
+        "tick_policy": "work-fair" if fair else "every resident each tick",
         "arrival_seconds": duration_s,
         "requests": len(reqs),
         "completed": len(ok),
@@ -328,7 +336,9 @@ def main():
     pam.lib()
     if args.serve_only:
         print(json.dumps({"serving": serving_bench(args.serve_seconds,
-                                                   args.serve_max_active or None)}), flush=True)
+                                                   args.serve_max_active or None,
+                                                   args.serve_rate or None,
+                                                   not args.serve_lockstep)}), flush=True)
         return
     w = WORKLOAD
     J = pa_inputs.couplings_pm(w["L"], pa_inputs.coupling_seed(3, 0))

@@ -91,6 +91,9 @@ typedef struct {
   uint32_t step;       /* number of resampling steps done */
   uint64_t sum_eta2;   /* sum over families of eta^2 */
   uint64_t sweeps_done;/* population sweep counter */
+  uint32_t n_at_E_min; /* replicas at E_min (ground-state estimators, Sec. II.A); 0 in the
+                          record pa_resample returns (it is taken before the sweeps) */
+  uint32_t reserved;
 } pa_obs;
 
 /* Bytes of device workspace an instance with these parameters needs. 0 on bad params. */

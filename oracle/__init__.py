@@ -226,6 +226,7 @@ class StepRecord:
     eps_expected: float
     n_culled: int
     sum_eta2: int
+    n_at_E_min: int = 0   # replicas at the lowest energy (ground-state estimators, Sec. II.A)
 
 
 def default_capacity(R: int) -> int:
@@ -311,12 +312,14 @@ class Population:
         beta_F = -(float(N) * math.log(2.0) + self.sum_lnQ)
         s2 = sum_eta2(self.fam, self.R)
         rho_t = float(s2) / float(self.R)
-        E_min = 2 * int(np.flatnonzero(h)[0]) - 3 * N
+        jmin = int(np.flatnonzero(h)[0])
+        E_min = 2 * jmin - 3 * N
         last = self.last or {}
         return StepRecord(k=self.k, beta=self.beta, dbeta=last.get("dbeta", 0.0),
                           lnQ=last.get("lnQ", 0.0), beta_F=beta_F, mean_E=mean_E, rho_t=rho_t,
                           R_tilde=self.R_tilde, E_min=E_min, eps_expected=last.get("eps", 0.0),
-                          n_culled=last.get("n_culled", 0), sum_eta2=s2)
+                          n_culled=last.get("n_culled", 0), sum_eta2=s2,
+                          n_at_E_min=int(h[jmin]))
 
     def spins_2d(self) -> np.ndarray:
         return self.spins.reshape(self.R_tilde, self.N)

@@ -43,7 +43,8 @@ class pa_obs(ctypes.Structure):
                 ("beta_F", ctypes.c_double), ("mean_E", ctypes.c_double), ("rho_t", ctypes.c_double),
                 ("eps_expected", ctypes.c_double), ("R_tilde", ctypes.c_uint32),
                 ("n_culled", ctypes.c_uint32), ("E_min", ctypes.c_int32), ("step", ctypes.c_uint32),
-                ("sum_eta2", ctypes.c_uint64), ("sweeps_done", ctypes.c_uint64)]
+                ("sum_eta2", ctypes.c_uint64), ("sweeps_done", ctypes.c_uint64),
+                ("n_at_E_min", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -68,6 +69,11 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1711_02146_amd.build` "
                           "(the HIP library is the only implementation)")
+    # torch brings its own HIP runtime; it must be loaded before libpa so that
+    # libpa binds to that runtime (the one that owns torch's device memory and
+    # streams) rather than to a second copy
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIB_PATH)
     sig = {
         "pa_workspace_bytes": (ctypes.c_size_t, [_P(pa_params)]),

@@ -567,6 +567,7 @@ int pa_observables(pa_instance* in, pa_obs* out) {
   out->R_tilde = in->R_tilde;
   out->n_culled = in->last_n_culled;
   out->E_min = jmin >= 0 ? 2 * jmin - 3 * (int)P.N : 0;
+  out->n_at_E_min = jmin >= 0 ? h[jmin] : 0u;
   out->step = in->step;
   out->sweeps_done = in->sweeps;
   return PA_OK;

@@ -110,8 +110,10 @@ struct StepRecord {
   uint32_t n_culled;
   int32_t E_min;           // lowest energy after the sweeps
   uint32_t status;         // 0 ok, 1 capacity overflow (population dead from here on)
+  uint32_t n_at_E_min;     // replicas at E_min
+  uint32_t pad;
 };
-static_assert(sizeof(StepRecord) == 56, "StepRecord is 56 bytes");
+static_assert(sizeof(StepRecord) == 64, "StepRecord is 64 bytes");
 
 // A set of populations as the kernels see it.
 struct BatchDev {

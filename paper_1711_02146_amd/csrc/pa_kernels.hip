@@ -999,6 +999,7 @@ __global__ __launch_bounds__(256) void k_record(BatchDev B, Group G) {
   if (threadIdx.x == 0) {
     rec->sumE = s;
     rec->E_min = smin == 0x7FFFFFFF ? 0 : 2 * smin - N3;
+    rec->n_at_E_min = smin == 0x7FFFFFFF ? 0u : P.hist[smin];
     rec->R_new = P.sc->R_tilde;
     rec->sum_eta2 = P.sc->sum_eta2;
   }

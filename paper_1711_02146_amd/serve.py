@@ -5,9 +5,19 @@ one +-J instance: L, R, a linear schedule of n_temps inverse temperatures on
 [0, beta_max] and n_sweeps sweeps per temperature.  Requests are admitted in
 arrival order while their device footprint (``pa_workspace_bytes``) fits the
 HBM budget; admitted populations stay resident on the GPU until their last
-temperature.  Every tick advances all resident populations by one temperature
-step in one ``pa_stepper_step`` call, so requests that arrive while others run
+temperature.  Every tick advances resident populations by one temperature step
+each in one ``pa_stepper_step`` call, so requests that arrive while others run
 join the next tick and their work shares the same launches.
+
+Which residents a tick includes is work-fair (virtual-time fair queueing with
+a batching window): every resident carries the work it has received so far
+(its step cost N_S L^3 R, plus a fixed charge for the per-step overhead, per
+step taken); a tick includes every resident within `window` attempts of the
+least-served one, and a newcomer starts level with the least-served resident.
+A cheap run therefore steps on most ticks while an expensive one waits until
+the others have received comparable work, so a small request is not held to
+the pace of the largest one in the mix and a large one is not starved by a
+stream of small ones.
 
 Each population draws only its own Philox streams, so a request's results do
 not depend on what else is resident: they equal the results of the same run
@@ -40,6 +50,10 @@ class Request:
     def attempts(self) -> int:
         """Spin-flip attempts of the whole run at the target size R."""
         return (self.n_temps - 1) * self.n_sweeps * self.L ** 3 * self.R
+
+    def step_cost(self) -> int:
+        """Spin-flip attempts of one temperature step at the target size R."""
+        return self.n_sweeps * self.L ** 3 * self.R
 
 
 @dataclass
@@ -153,8 +167,16 @@ class Server:
     """
 
     def __init__(self, hbm_budget: int = 64 << 30, max_active: int = 256, max_L: int = 16,
-                 keep_trajectory: bool = False, backend=None, device=None):
+                 keep_trajectory: bool = False, backend=None, device=None, fair: bool = True,
+                 window: float = 2e9, step_overhead: float = 1e8):
+        """fair: work-fair tick membership (else every resident steps every tick);
+        window: attempts of lead over the least-served resident that still join a
+        tick; step_overhead: attempts charged per step for the fixed per-step cost
+        (about 0.1 ms of sweeping on MI355X)."""
         self.backend = backend if backend is not None else GpuBackend(max_active, max_L, device)
+        self.fair = fair
+        self.window = float(window)
+        self.step_overhead = float(step_overhead)
         self.max_L = self.backend.max_L
         self.keep_trajectory = keep_trajectory
         self.sched = Scheduler(hbm_budget, max_active, self.backend.footprint)
@@ -170,7 +192,7 @@ class Server:
         """
         be = self.backend
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
-        active = []   # [request, population, schedule, k, result]
+        active = []   # [request, population, schedule, k, result, work received]
         results = {}
         t0 = time.perf_counter()
         vnow = 0.0
@@ -193,7 +215,8 @@ class Server:
                                               status=STATUS_INVALID)
                     continue
                 res = Result(req.rid, req.arrival, t, t, be.footprint(req))
-                active.append([req, be.create(req), req.schedule(), 0, res])
+                start = min((a[5] for a in active), default=0.0)
+                active.append([req, be.create(req), req.schedule(), 0, res, start])
             if not active:
                 if pending:
                     if realtime:
@@ -201,23 +224,31 @@ class Server:
                     else:
                         vnow = max(vnow, pending[0].arrival)
                 continue
-            pops = [a[1] for a in active]
-            beta_next = [a[2][a[3] + 1] for a in active]
-            n_sweeps = [a[0].n_sweeps for a in active]
+            if self.fair:
+                least = min(a[5] for a in active)
+                chosen = [a for a in active if a[5] <= least + self.window]
+            else:
+                chosen = active
+            for a in chosen:
+                a[5] += a[0].step_cost() + self.step_overhead
+            pops = [a[1] for a in chosen]
+            beta_next = [a[2][a[3] + 1] for a in chosen]
+            n_sweeps = [a[0].n_sweeps for a in chosen]
             obs, status = be.step(pops, beta_next, n_sweeps)
             del pops
             self.ticks += 1
-            self.tick_sizes.append(len(active))
+            self.tick_sizes.append(len(chosen))
             if not realtime:
                 vnow += tick_dt
             t = now()
-            still = []
-            for a, o, st in zip(active, obs, status):
-                req, _, sched, k, res = a
+            done = set()
+            for a, o, st in zip(chosen, obs, status):
+                req, _, sched, k, res = a[:5]
                 if st != 0:
                     res.status = int(st)
                     res.finished = t
                     self._retire(a, results)
+                    done.add(id(a))
                     continue
                 a[3] = k + 1
                 res.attempts += req.n_sweeps * req.L ** 3 * o["R_tilde"]
@@ -227,15 +258,14 @@ class Server:
                     res.final = o
                     res.finished = t
                     self._retire(a, results)
-                else:
-                    still.append(a)
-            active = still
+                    done.add(id(a))
+            active = [a for a in active if id(a) not in done]
             if progress is not None:
                 progress(t, len(results), len(active), len(self.sched.queue))
         return [results[k] for k in sorted(results)]
 
     def _retire(self, a, results):
-        req, pop, _, _, res = a
+        req, pop, _, _, res = a[:5]
         self.backend.free(pop)
         a[1] = None
         self.sched.release(req)

@@ -18,7 +18,7 @@ import pa_inputs
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("beta", "dbeta", "lnQ", "beta_F", "mean_E", "rho_t", "eps_expected", "R_tilde",
-          "n_culled", "E_min", "step", "sum_eta2", "sweeps_done")
+          "n_culled", "E_min", "step", "sum_eta2", "sweeps_done", "n_at_E_min")
 
 
 @pytest.fixture(scope="module")

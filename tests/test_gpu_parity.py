@@ -108,6 +108,7 @@ def _compare_step(g, o, k):
 def _compare_obs(go, rec, k):
     assert go["R_tilde"] == rec.R_tilde, k
     assert go["E_min"] == rec.E_min, k
+    assert go["n_at_E_min"] == rec.n_at_E_min, k
     assert go["sum_eta2"] == rec.sum_eta2, k
     assert go["step"] == rec.k
     for key in ("beta", "beta_F", "mean_E", "rho_t", "lnQ", "eps_expected", "dbeta"):

@@ -123,3 +123,35 @@ def test_serving_request_stream():
     assert nt.min() >= 51 and nt.max() <= 201
     # the same seed gives the same stream
     assert pa_inputs.serving_requests(duration_s=10.0) == pa_inputs.serving_requests(duration_s=10.0)
+
+
+def test_server_work_fair_ticks():
+    """Fair queueing by work received: a run whose steps cost 4x another's joins a
+    tick only once the cheap run has caught up; both finish all steps in order."""
+    be = FakeBackend(budget=10 ** 9)
+    srv = Server(hbm_budget=10 ** 9, max_active=8, backend=be, keep_trajectory=True,
+                 window=0.0, step_overhead=0.0)
+    cheap = req(0, 0.0, 100, n_temps=13)      # step cost 10 * 64 * 100
+    dear = req(1, 0.0, 400, n_temps=4)        # 4x that
+    res = srv.run([cheap, dear], realtime=False, tick_dt=0.01)
+    assert [r.status for r in res] == [0, 0]
+    assert len(res[0].trajectory) == 12 and len(res[1].trajectory) == 3
+    assert all(0 in c for c in be.calls[:12])
+    assert [i for i, c in enumerate(be.calls) if 1 in c] == [0, 4, 8]
+    # a window wider than the whole run lets both step on every tick
+    be1 = FakeBackend(budget=10 ** 9)
+    Server(hbm_budget=10 ** 9, max_active=8, backend=be1, window=1e12,
+           step_overhead=0.0).run([cheap, dear], realtime=False, tick_dt=0.01)
+    assert [sorted(c) for c in be1.calls[:3]] == [[0, 1]] * 3
+    # without fairness every resident steps on every tick
+    be2 = FakeBackend(budget=10 ** 9)
+    Server(hbm_budget=10 ** 9, max_active=8, backend=be2, fair=False).run(
+        [cheap, dear], realtime=False, tick_dt=0.01)
+    assert [sorted(c) for c in be2.calls[:3]] == [[0, 1]] * 3
+    # a newcomer starts level with the least-served resident
+    be3 = FakeBackend(budget=10 ** 9)
+    late = req(2, 0.05, 100, n_temps=3)
+    srv3 = Server(hbm_budget=10 ** 9, max_active=8, backend=be3, window=0.0, step_overhead=0.0)
+    srv3.run([cheap, dear, late], realtime=False, tick_dt=0.01)
+    first_late = next(i for i, c in enumerate(be3.calls) if 2 in c)
+    assert first_late == 5 and 0 in be3.calls[first_late]
