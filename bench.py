@@ -343,7 +343,12 @@ def main():
     w = WORKLOAD
     J = pa_inputs.couplings_pm(w["L"], pa_inputs.coupling_seed(3, 0))
     seed0 = pa_inputs.population_seed(3, 0, 0)
-    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    print(f"# warmup {args.warmup} steps (and the sweep autotuner on this shape)", file=sys.stderr,
+          flush=True)
+    tp = pam.Population(w["L"], w["R"], J, seed0 + 999, layout=w["layout"])
+    # tuned at beta = 0.3, the middle of the temperatures the timed steps cover
+    tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=3)
+    tp.close()
     run_steps(pam, J, w, args.warmup, seed0 + 1000)
     torch.cuda.synchronize()
     print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
@@ -400,6 +405,7 @@ def main():
             "hbm_frac": bytes_per_launch / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "sweep_fraction_of_wall": sum(sweep_ms) * 1e-3 / wall,
+        "autotune": tune,
         "beta_reached": stats[-1][0] if stats else None,
     }
     if not args.no_batched:

@@ -248,6 +248,29 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
 /* Release a stepper (its instances stay valid). */
 int pa_stepper_free(pa_stepper* s);
 
+/* ------------------------------------------------------------------------ */
+/* Autotuner.  The sweep kernel (Sec. II MCMC sweeps, Sec. II.A model) runs   */
+/* one 64-replica tile per workgroup with 4 or 8 waves sharing it; which is   */
+/* faster depends on L, the number of tiles in the launch and the device.     */
+/* Both give the same bits.  A built-in rule measured on MI355X is used until */
+/* the autotuner has timed a shape in this process.                          */
+/* ------------------------------------------------------------------------ */
+
+/* Time n_sweeps-sweep launches of both forms on the instance (repeats times
+ * each, at inverse temperature beta >= 0: the regime the caller will run in;
+ * at beta = 0 no draw is made) and remember the faster for launches of the same spin
+ * layout, L and size class (floor(log2(tiles))), in this process, for single
+ * instances, batches and steppers alike.  The population, its counters and
+ * its results are not changed (the trial sweeps write only the spare buffer).
+ * split_out (nullable): the chosen waves per tile; ms_out (nullable, 2
+ * floats): average launch time of the 4- and 8-wave forms.  Needs no pending
+ * copy step (PA_ESTATE).  Synchronises. */
+int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t repeats,
+                      uint32_t* split_out, float* ms_out);
+
+/* Forget every autotuned choice (back to the built-in rule). */
+int pa_autotune_reset(void);
+
 /* Static description of a status code. */
 const char* pa_strerror(int status);
 

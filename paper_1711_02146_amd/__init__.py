@@ -104,6 +104,9 @@ def lib():
                                              ctypes.c_size_t, _vp, _P(_vp)]),
         "pa_stepper_step": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _vp]),
         "pa_stepper_free": (ctypes.c_int, [_vp]),
+        "pa_autotune_sweep": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32,
+                                             _vp, _vp]),
+        "pa_autotune_reset": (ctypes.c_int, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -118,7 +121,7 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_import_state", "pa_free", "pa_strerror", "pa_batch_workspace_bytes",
             "pa_batch_create", "pa_batch_run", "pa_batch_results", "pa_batch_free",
             "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
-            "pa_stepper_free"]
+            "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -278,6 +281,18 @@ def pa_stepper_free(stepper: int):
     _check(lib().pa_stepper_free(stepper), "pa_stepper_free")
 
 
+def pa_autotune_sweep(handle: int, beta: float = 1.0, n_sweeps: int = 10, repeats: int = 3) -> dict:
+    split = ctypes.c_uint32(0)
+    ms = (ctypes.c_float * 2)()
+    _check(lib().pa_autotune_sweep(handle, float(beta), int(n_sweeps), int(repeats),
+                                   ctypes.byref(split), ctypes.cast(ms, _vp)), "pa_autotune_sweep")
+    return {"split": split.value, "ms_split4": ms[0], "ms_split8": ms[1]}
+
+
+def pa_autotune_reset():
+    _check(lib().pa_autotune_reset(), "pa_autotune_reset")
+
+
 # --- convenience object owning the workspace ---------------------------------
 class Population:
     """One PA population on a GPU: workspace tensor + library handle."""
@@ -318,6 +333,12 @@ class Population:
 
     def import_state(self, spins, family, sweeps_done, step, beta, sum_lnQ):
         pa_import_state(self.handle, spins, family, sweeps_done, step, beta, sum_lnQ)
+
+    def autotune(self, beta: float = 1.0, n_sweeps: int = 10, repeats: int = 3) -> dict:
+        """Time both sweep forms on this population's shape at inverse
+        temperature beta; later launches of that shape (any instance, batch or
+        stepper) use the faster."""
+        return pa_autotune_sweep(self.handle, beta, n_sweeps, repeats)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpa.so")
-SOURCES = ["pa_kernels.hip", "pa_host.cpp", "pa_batch.cpp", "pa_stepper.cpp"]
+SOURCES = ["pa_kernels.hip", "pa_host.cpp", "pa_batch.cpp", "pa_stepper.cpp", "pa_tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -258,7 +258,8 @@ pa::PopStep plain_step(uint32_t cur) {
 // Sweep launch of one instance (its size after any pending copy sets the
 // waves per tile).
 hipError_t launch_sweep_of(pa_instance* in, const pa::PopStep& ps) {
-  const uint32_t split = pa::sweep_split_for(in->dev.L, ((uint64_t)in->R_tilde + 63) / 64);
+  const uint32_t split =
+      pa::sweep_split_for(in->dev.layout, in->dev.L, ((uint64_t)in->R_tilde + 63) / 64);
   return pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
                           in->dev.layout, in->dev.L, split, in->stream);
 }
@@ -711,6 +712,54 @@ int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* f
   in->pending_gather = false;
   in->hist_valid = false;
   in->last_R_old = 0;
+  return PA_OK;
+}
+
+int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t repeats,
+                      uint32_t* split_out, float* ms_out) {
+  if (!usable(in)) return PA_ESTATE;
+  if (in->pending_gather) return PA_ESTATE;
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return PA_EINVAL;
+  if (n_sweeps == 0 || repeats == 0 || repeats > 1000) return PA_EINVAL;
+  // Trial sweeps at the caller's inverse temperature read the population's
+  // buffer and write the other one; the population, its counters and the
+  // current buffer are left as they were.
+  pa::PopStep ps = plain_step(in->cur);
+  thresholds(beta, ps.thr);
+  ps.t0 = (uint32_t)in->sweeps;
+  ps.n_sweeps = n_sweeps;
+  ps.gather = 0;
+  const uint64_t tiles = ((uint64_t)in->R_tilde + 63) / 64;
+  const uint32_t cand[2] = {4u, 8u};
+  float ms[2] = {0.0f, 0.0f};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return dev_fail(in);
+  }
+  int rc = PA_OK;
+  const pa::BatchDev B = one_set(in, ps);
+  const pa::Group g = group_of(in, in->d_meta->tiles, in->meta.tiles[1]);
+  for (int c = 0; c < 2 && rc == PA_OK; ++c) {
+    bool ok = pa::launch_sweep(B, g, in->dev.layout, in->dev.L, cand[c], in->stream) == hipSuccess &&
+              hipEventRecord(e0, in->stream) == hipSuccess;
+    for (uint32_t r = 0; ok && r < repeats; ++r)
+      ok = pa::launch_sweep(B, g, in->dev.layout, in->dev.L, cand[c], in->stream) == hipSuccess;
+    ok = ok && hipEventRecord(e1, in->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms[c], e0, e1) == hipSuccess;
+    if (!ok) rc = dev_fail(in);
+    ms[c] /= (float)repeats;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != PA_OK) return rc;
+  const uint32_t best = ms[1] < ms[0] ? cand[1] : cand[0];
+  pa::sweep_split_record(in->dev.layout, in->dev.L, tiles, best);
+  if (split_out) *split_out = best;
+  if (ms_out) {
+    ms_out[0] = ms[0];
+    ms_out[1] = ms[1];
+  }
   return PA_OK;
 }
 

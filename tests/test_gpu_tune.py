@@ -1,0 +1,69 @@
+"""GPU: the sweep autotuner times both sweep forms and remembers the faster; it
+changes neither the population nor any later result (bit-exact against the
+oracle afterwards), in the forms it picks for single instances and batches."""
+import numpy as np
+import pytest
+
+import oracle
+import pa_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pam():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_1711_02146_amd as m
+
+    m.lib()
+    yield m
+    m.pa_autotune_reset()
+
+
+@pytest.mark.parametrize("L,R,layout", [(8, 30000, "bitpack64"), (6, 5000, "int8")])
+def test_autotune_leaves_results_unchanged(pam, L, R, layout):
+    pam.pa_autotune_reset()
+    J = pa_inputs.couplings_pm(L, 808)
+    g = pam.Population(L, R, J, 4242, layout=layout)
+    o = oracle.Population(L, J, R, 4242)
+    g.resample(0.3)
+    o.resample(0.3)
+    g.sweep(0.3, 5)
+    o.sweep(0.3, 5)
+    before = g.export_state()
+    obs_before = g.observables()
+    t = g.autotune(beta=0.5, n_sweeps=10, repeats=2)
+    assert t["split"] in (4, 8)
+    assert t["ms_split4"] > 0 and t["ms_split8"] > 0
+    assert t["split"] == (8 if t["ms_split8"] < t["ms_split4"] else 4)
+    for x, y in zip(before, g.export_state()):
+        np.testing.assert_array_equal(x, y)
+    assert g.observables() == obs_before
+    # later steps (now in the tuned form) stay bit-exact
+    for b in (0.6, 0.9):
+        g.resample(b)
+        o.resample(b)
+        g.sweep(b, 10)
+        o.sweep(b, 10)
+    s, u, f = g.export_state()
+    np.testing.assert_array_equal(s.reshape(-1), o.spins)
+    np.testing.assert_array_equal(u.astype(np.int32), o.U)
+    np.testing.assert_array_equal(f, o.fam)
+    g.close()
+
+
+def test_autotune_needs_no_pending_copy(pam):
+    J = pa_inputs.couplings_pm(4, 1)
+    g = pam.Population(4, 500, J, 1)
+    g.resample(0.2)
+    with pytest.raises(pam.PAError) as e:
+        g.autotune()
+    assert e.value.status == pam.PA_ESTATE
+    g.sweep(0.2, 1)
+    for beta, n in ((0.5, 0), (-1.0, 10), (float("nan"), 10)):
+        with pytest.raises(pam.PAError) as e:
+            pam.pa_autotune_sweep(g.handle, beta, n, 1)
+        assert e.value.status == pam.PA_EINVAL
+    g.close()
