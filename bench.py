@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batch run")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the built-in sweep-form rule instead of timing both forms first")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="arrival window of the serving run (0 skips it)")
     ap.add_argument("--serve-only", action="store_true",
@@ -345,10 +347,12 @@ def main():
     seed0 = pa_inputs.population_seed(3, 0, 0)
     print(f"# warmup {args.warmup} steps (and the sweep autotuner on this shape)", file=sys.stderr,
           flush=True)
-    tp = pam.Population(w["L"], w["R"], J, seed0 + 999, layout=w["layout"])
-    # tuned at beta = 0.3, the middle of the temperatures the timed steps cover
-    tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=3)
-    tp.close()
+    tune = None
+    if not args.no_autotune:
+        tp = pam.Population(w["L"], w["R"], J, seed0 + 999, layout=w["layout"])
+        # tuned at beta = 0.3, the middle of the temperatures the timed steps cover
+        tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=5)
+        tp.close()
     run_steps(pam, J, w, args.warmup, seed0 + 1000)
     torch.cuda.synchronize()
     print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)

@@ -740,16 +740,23 @@ int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t 
   int rc = PA_OK;
   const pa::BatchDev B = one_set(in, ps);
   const pa::Group g = group_of(in, in->d_meta->tiles, in->meta.tiles[1]);
-  for (int c = 0; c < 2 && rc == PA_OK; ++c) {
-    bool ok = pa::launch_sweep(B, g, in->dev.layout, in->dev.L, cand[c], in->stream) == hipSuccess &&
-              hipEventRecord(e0, in->stream) == hipSuccess;
-    for (uint32_t r = 0; ok && r < repeats; ++r)
-      ok = pa::launch_sweep(B, g, in->dev.layout, in->dev.L, cand[c], in->stream) == hipSuccess;
-    ok = ok && hipEventRecord(e1, in->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-         hipEventElapsedTime(&ms[c], e0, e1) == hipSuccess;
-    if (!ok) rc = dev_fail(in);
-    ms[c] /= (float)repeats;
-  }
+  auto launch = [&](uint32_t split) {
+    return pa::launch_sweep(B, g, in->dev.layout, in->dev.L, split, in->stream) == hipSuccess;
+  };
+  // two untimed launches of each form (clocks and caches settle), then the
+  // timed launches alternate between the forms so that drift hits both alike
+  bool ok = launch(cand[0]) && launch(cand[1]) && launch(cand[0]) && launch(cand[1]);
+  for (uint32_t r = 0; ok && r < repeats; ++r)
+    for (int c = 0; ok && c < 2; ++c) {
+      float t = 0.0f;
+      ok = hipEventRecord(e0, in->stream) == hipSuccess && launch(cand[c]) &&
+           hipEventRecord(e1, in->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+      ms[c] += t;
+    }
+  if (!ok) rc = dev_fail(in);
+  ms[0] /= (float)repeats;
+  ms[1] /= (float)repeats;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != PA_OK) return rc;
