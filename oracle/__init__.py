@@ -85,6 +85,19 @@ def lib():
         "pao_family_sizes": (None, [_u32p, _c.c_int64, _c.c_uint32, _c.c_int, _u64p]),
         "pao_overlap_hist": (None, [_c.c_int, _i8p, _c.c_int64, _i8p, _c.c_int64, _u64p, _u32p]),
         "pao_density_of_states": (_c.c_int, [_c.c_int, _i8p, _u64p]),
+        "pao_g_energy": (None, [_c.c_int, _i8p, _i8p, _c.c_int64, _i32p]),
+        "pao_g_thresholds": (None, [_c.c_double, _c.c_int, _u64p]),
+        "pao_g_sweep_slots": (None, [_c.c_int, _i8p, _i8p, _i32p, _c.c_int64, _u32p,
+                                     _c.c_uint64, _u64p, _c.c_uint32, _c.c_int]),
+        "pao_table_unit": (_c.c_int, [_u32p, _c.c_int, _c.c_double, _c.c_int64, _c.c_uint32,
+                                      _c.c_uint32, _c.c_double, _u32p, _u64p, _f64p,
+                                      _c.POINTER(_c.c_double)]),
+        "pao_culling_fraction_unit": (_c.c_double, [_u32p, _c.c_int, _c.c_double, _c.c_uint32,
+                                                    _c.c_double]),
+        "pao_choose_dbeta_unit": (_c.c_int, [_u32p, _c.c_int, _c.c_double, _c.c_uint32,
+                                             _c.c_double, _c.c_double, _c.POINTER(_c.c_double),
+                                             _c.POINTER(_c.c_int)]),
+        "pao_g_density_of_states": (_c.c_int, [_c.c_int, _i8p, _u64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -367,3 +380,141 @@ def run_adaptive(L, J, R, seed, eps_target, beta_max, n_sweeps, capacity=None, m
         if on_step is not None:
             on_step(p.k, p)
     return p, records
+
+
+# ---------------------------------------------------------------------------
+# Gaussian couplings (Sec. II.A), quantised: J = k / 16, k in [-127, 127];
+# energies in quanta of 1/16 (E16).  Same loop, draws and copy rule as above;
+# the energy levels of the resampling table are the occupied window of E16.
+# ---------------------------------------------------------------------------
+G_UNIT = 1.0 / 16.0
+
+
+def g_energy(L: int, K: np.ndarray, spins: np.ndarray) -> np.ndarray:
+    spins = np.ascontiguousarray(spins, np.int8)
+    R = spins.size // L ** 3
+    E = np.zeros(R, np.int32)
+    lib().pao_g_energy(L, np.ascontiguousarray(K, np.int8), spins, R, E)
+    return E
+
+
+def g_dE_max(L: int, K: np.ndarray) -> int:
+    """Largest |dE16| of a single flip: 2 max over sites of sum_j |k_ij|."""
+    N = L ** 3
+    nb = np.zeros(N * 6, np.int32)
+    bd = np.zeros(N * 6, np.int32)
+    lib().pao_neighbours(L, nb, bd)
+    k = np.abs(np.asarray(K, np.int64))[bd].reshape(N, 6).sum(axis=1)
+    return int(2 * k.max())
+
+
+def g_thresholds(beta: float, dEmax: int) -> np.ndarray:
+    out = np.zeros(dEmax + 1, np.uint64)
+    lib().pao_g_thresholds(float(beta), int(dEmax), out)
+    return out
+
+
+def g_sweep_slots(L: int, K: np.ndarray, spins: np.ndarray, E16: np.ndarray, slots: np.ndarray,
+                  seed: int, beta: float, t0: int, n_sweeps: int):
+    """Sweep selected replicas in place; row i sits in population slot slots[i]."""
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous
+    assert E16.dtype == np.int32 and E16.flags.c_contiguous
+    slots = np.ascontiguousarray(slots, np.uint32)
+    lib().pao_g_sweep_slots(L, np.ascontiguousarray(K, np.int8), spins.reshape(-1), E16,
+                            slots.size, slots, seed, g_thresholds(beta, g_dE_max(L, K)), t0,
+                            n_sweeps)
+
+
+def g_density_of_states(L: int, K: np.ndarray):
+    """(g, off): g[E16 + off] = number of states with energy E16 / 16."""
+    off = 3 * 127 * L ** 3
+    g = np.zeros(2 * off + 1, np.uint64)
+    if lib().pao_g_density_of_states(L, np.ascontiguousarray(K, np.int8), g) != 0:
+        raise ValueError("lattice too large to enumerate")
+    return g, off
+
+
+class GaussPopulation(Population):
+    """A PA population with quantised Gaussian couplings K (J = K / 16).
+
+    ``U`` holds E16, the energy in quanta of 1/16; the resampling levels are
+    the occupied window [min E16, max E16]."""
+
+    def __init__(self, L: int, K: np.ndarray, R: int, seed: int, capacity: int | None = None):
+        super().__init__(L, K, R, seed, capacity)     # spins and labels as for +-J
+        self.U = g_energy(L, self.J, self.spins)
+        self.dEmax = g_dE_max(L, self.J)
+
+    def sweep(self, beta: float, n_sweeps: int):
+        slots = np.arange(self.R_tilde, dtype=np.uint32)
+        lib().pao_g_sweep_slots(self.L, self.J, self.spins, self.U, self.R_tilde, slots,
+                                self.seed, g_thresholds(beta, self.dEmax), self.t, int(n_sweeps))
+        self.t += int(n_sweeps)
+
+    def window(self):
+        E = self.U[: self.R_tilde]
+        return int(E.min()), int(E.max())
+
+    def histogram(self) -> np.ndarray:
+        lo, hi = self.window()
+        return histogram(self.U[: self.R_tilde] - lo, hi - lo + 1)
+
+    def resample(self, beta_next: float):
+        dbeta = beta_next - self.beta
+        lo, hi = self.window()
+        h = self.histogram()
+        n = h.size
+        fl = np.zeros(n, np.uint32)
+        T = np.zeros(n, np.uint64)
+        tau = np.zeros(n, np.float64)
+        lnq = ctypes.c_double(0.0)
+        jmin = lib().pao_table_unit(h, n, G_UNIT, lo, self.R, self.R_tilde, float(dbeta), fl, T,
+                                    tau, ctypes.byref(lnq))
+        step = self.k + 1
+        level = np.ascontiguousarray(self.U[: self.R_tilde] - lo, np.int32)
+        cnt = copy_counts(level, fl, T, self.seed, step)
+        new_spins = np.zeros(self.capacity * self.N, np.int8)
+        new_U = np.zeros(self.capacity, np.int32)
+        new_fam = np.zeros(self.capacity, np.uint32)
+        offsets = np.zeros(self.R_tilde, np.uint64)
+        Rn = lib().pao_copy_eliminate(self.L, cnt, self.R_tilde, self.capacity, self.spins, self.U,
+                                      self.fam, new_spins, new_U, new_fam, offsets)
+        if Rn < 0:
+            raise OverflowError("resampled population exceeds capacity")
+        eps = lib().pao_culling_fraction_unit(h, n, G_UNIT, self.R, float(dbeta))
+        self.last = dict(h=h, fl=fl, T=T, tau=tau, n=cnt, offsets=offsets, jmin=jmin,
+                         lnQ=lnq.value, dbeta=dbeta, eps=eps, E_lo=lo,
+                         n_culled=int(np.count_nonzero(cnt == 0)))
+        self.spins = new_spins[: Rn * self.N].copy()
+        self.U = new_U[:Rn].copy()
+        self.fam = new_fam[:Rn].copy()
+        self.R_tilde = int(Rn)
+        self.sum_lnQ = self.sum_lnQ + lnq.value
+        self.beta = beta_next
+        self.k = step
+
+    def choose_beta(self, eps_target: float, beta_max: float):
+        rem = beta_max - self.beta
+        h = self.histogram()
+        d = ctypes.c_double(0.0)
+        e = ctypes.c_int(0)
+        rc = lib().pao_choose_dbeta_unit(h, h.size, G_UNIT, self.R, float(eps_target), float(rem),
+                                         ctypes.byref(d), ctypes.byref(e))
+        if rc != 0:
+            raise ValueError("culling fraction already exceeds the target at dbeta = 0")
+        return beta_max if e.value else self.beta + d.value
+
+    def observables(self) -> StepRecord:
+        """As Population.observables; E_min is in quanta (E16), mean_E in units of J."""
+        E = self.U[: self.R_tilde].astype(np.int64)
+        sumE = int(E.sum())
+        mean_E = float(sumE) / float(self.R_tilde) * G_UNIT
+        beta_F = -(float(self.N) * math.log(2.0) + self.sum_lnQ)
+        s2 = sum_eta2(self.fam, self.R)
+        E_min = int(E.min())
+        last = self.last or {}
+        return StepRecord(k=self.k, beta=self.beta, dbeta=last.get("dbeta", 0.0),
+                          lnQ=last.get("lnQ", 0.0), beta_F=beta_F, mean_E=mean_E,
+                          rho_t=float(s2) / float(self.R), R_tilde=self.R_tilde, E_min=E_min,
+                          eps_expected=last.get("eps", 0.0), n_culled=last.get("n_culled", 0),
+                          sum_eta2=s2, n_at_E_min=int(np.count_nonzero(E == E_min)))

@@ -1,4 +1,4 @@
-"""Exact thermodynamics of small +-J lattices (test infrastructure).
+"""Exact thermodynamics of small lattices (test infrastructure).
 
 Two independent exact routes for checking the PA oracle:
 
@@ -42,7 +42,7 @@ class TransferMatrixL3:
     N = 27
 
     def __init__(self, J: np.ndarray):
-        J = np.asarray(J, np.int64)
+        J = np.asarray(J, np.float64)
         assert J.size == 81
         self.J = J
         L, N = 3, 27
@@ -134,4 +134,17 @@ class TransferMatrixL3:
         return float((C ** 2).sum() / 27.0 ** 2)
 
 
-__all__ = ["thermo_from_dos", "TransferMatrixL3", "density_of_states"]
+def thermo_from_levels(g: np.ndarray, E: np.ndarray, beta: float):
+    """(ln Z, <E>, var E) at beta from counts g[l] of states with energy E[l]."""
+    mask = g > 0
+    logw = np.log(g[mask].astype(np.float64)) - beta * E[mask]
+    m = logw.max()
+    w = np.exp(logw - m)
+    Zs = w.sum()
+    lnZ = m + math.log(Zs)
+    Em = float((w * E[mask]).sum() / Zs)
+    E2 = float((w * E[mask] ** 2).sum() / Zs)
+    return lnZ, Em, E2 - Em * Em
+
+
+__all__ = ["thermo_from_dos", "thermo_from_levels", "TransferMatrixL3", "density_of_states"]

@@ -512,3 +512,194 @@ int pao_density_of_states(int L, const int8_t* J, uint64_t* g_out) {
   (void)state;
   return 0;
 }
+
+/* ======================================================================== */
+/* Gaussian couplings (Sec. II.A: the paper draws J_nm from a unit normal).  */
+/* Reading: J = k / 16 with k an integer in [-127, 127] (a unit normal       */
+/* rounded to the nearest 1/16), so that every energy is an integer number  */
+/* of quanta 1/16 and the annealing loop keeps integer energy levels.       */
+/*   E16 = -sum_b k_b s_i s_j            (E = E16 / 16)                      */
+/* Flipping s_i changes E16 by dE16 = 2 s_i sum_j k_ij s_j, an even integer */
+/* with |dE16| <= 2 * 6 * 127.                                               */
+/* ======================================================================== */
+static int32_t energy16(const int8_t* s, const int8_t* K, int L) {
+  int N = L * L * L;
+  int32_t e = 0;
+  for (int d = 0; d < 3; ++d)
+    for (int site = 0; site < N; ++site) {
+      int other = neighbour(site, 2 * d, L);
+      e -= (int32_t)K[d * N + site] * (int32_t)s[site] * (int32_t)s[other];
+    }
+  return e;
+}
+
+void pao_g_energy(int L, const int8_t* K, const int8_t* spins, int64_t R, int32_t* E16_out) {
+  int N = L * L * L;
+  for (int64_t r = 0; r < R; ++r) E16_out[r] = energy16(spins + r * N, K, L);
+}
+
+/* thr[d] = floor(2^32 exp(-beta d / 16)) for d = 0..dEmax (thr[0] = 2^32): */
+/* a move raising E16 by d > 0 is taken iff its draw is below thr[d].       */
+void pao_g_thresholds(double beta, int dEmax, uint64_t* thr_out) {
+  for (int d = 0; d <= dEmax; ++d)
+    thr_out[d] = (uint64_t)floor(ldexp(exp(-beta * ((double)d / 16.0)), 32));
+}
+
+/* Sweeps of one replica (same visiting order and draws as sweep_one). */
+static void g_sweep_one(int L, const int8_t* K, const int32_t* cm, const int32_t* nb,
+                        const int32_t* bd, int8_t* s, int32_t* E16, uint32_t slot, uint64_t seed,
+                        const uint64_t* thr, uint32_t t0, int n_sweeps) {
+  int N = L * L * L;
+  int32_t e = *E16;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    uint32_t t = t0 + (uint32_t)sw;
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int site = 0; site < N; ++site) {
+        if (colour_of(site, L) != colour) continue;
+        int h = 0;
+        for (int dir = 0; dir < 6; ++dir)
+          h += (int)K[bd[site * 6 + dir]] * (int)s[nb[site * 6 + dir]];
+        int dE = 2 * (int)s[site] * h;
+        int accept;
+        if (dE <= 0) {
+          accept = 1;
+        } else {
+          uint32_t x = draw_word(seed, slot, t, (uint32_t)(cm[site] >> 2), TAG_MET, cm[site] & 3);
+          accept = (uint64_t)x < thr[dE];
+        }
+        if (accept) {
+          s[site] = (int8_t)(-s[site]);
+          e += dE;
+        }
+      }
+    }
+  }
+  *E16 = e;
+}
+
+void pao_g_sweep_slots(int L, const int8_t* K, int8_t* spins, int32_t* E16, int64_t n,
+                       const uint32_t* slots, uint64_t seed, const uint64_t* thr, uint32_t t0,
+                       int n_sweeps) {
+  int N = L * L * L;
+  int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * N);
+  int32_t* nb = (int32_t*)malloc(sizeof(int32_t) * N * 6);
+  int32_t* bd = (int32_t*)malloc(sizeof(int32_t) * N * 6);
+  pao_colour_major(L, cm);
+  pao_neighbours(L, nb, bd);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    g_sweep_one(L, K, cm, nb, bd, spins + i * N, E16 + i, slots ? slots[i] : (uint32_t)i, seed,
+                thr, t0, n_sweeps);
+  free(cm);
+  free(nb);
+  free(bd);
+}
+
+/* Resampling table with energy levels of width `unit` (Sec. II, Eqs. 1-2): */
+/* level j has energy unit * (E_lo + j); otherwise as pao_table:            */
+/*   w_j = exp(-dbeta * (unit * (j - j_min))), S = ascending sum of h_j w_j, */
+/*   tau_j = R w_j / S, fl_j, T_j as in pao_table,                           */
+/*   ln Q = ln S - ln R~ - dbeta * unit * (E_lo + j_min).                    */
+int pao_table_unit(const uint32_t* h, int n_levels, double unit, int64_t E_lo, uint32_t R,
+                   uint32_t R_tilde, double dbeta, uint32_t* fl_out, uint64_t* T_out,
+                   double* tau_out, double* lnQ_out) {
+  int jmin = -1;
+  for (int j = 0; j < n_levels; ++j)
+    if (h[j] > 0) { jmin = j; break; }
+  if (jmin < 0) return -1;
+  double S = 0.0;
+  for (int j = jmin; j < n_levels; ++j) {
+    if (h[j] == 0) continue;
+    double w = exp(-dbeta * (unit * (double)(j - jmin)));
+    S = S + (double)h[j] * w;
+  }
+  for (int j = 0; j < n_levels; ++j) {
+    if (j < jmin) {
+      fl_out[j] = 0; T_out[j] = 0;
+      if (tau_out) tau_out[j] = 0.0;
+      continue;
+    }
+    double w = exp(-dbeta * (unit * (double)(j - jmin)));
+    double tau = ((double)R * w) / S;
+    uint64_t fl = (uint64_t)floor(tau);
+    double fr = tau - (double)fl;
+    fl_out[j] = (uint32_t)fl;
+    T_out[j] = (uint64_t)ceil(ldexp(fr, 53));
+    if (tau_out) tau_out[j] = tau;
+  }
+  *lnQ_out = log(S) - log((double)R_tilde) - dbeta * (unit * (double)(E_lo + jmin));
+  return jmin;
+}
+
+/* Culling fraction with levels of width `unit` (as pao_culling_fraction). */
+double pao_culling_fraction_unit(const uint32_t* h, int n_levels, double unit, uint32_t R,
+                                 double dbeta) {
+  int jmin = -1;
+  for (int j = 0; j < n_levels; ++j)
+    if (h[j] > 0) { jmin = j; break; }
+  if (jmin < 0) return 0.0;
+  double S = 0.0;
+  for (int j = jmin; j < n_levels; ++j) {
+    if (h[j] == 0) continue;
+    double w = exp(-dbeta * (unit * (double)(j - jmin)));
+    S = S + (double)h[j] * w;
+  }
+  double acc = 0.0;
+  for (int j = jmin; j < n_levels; ++j) {
+    if (h[j] == 0) continue;
+    double w = exp(-dbeta * (unit * (double)(j - jmin)));
+    double tau = ((double)R * w) / S;
+    if (tau < 1.0) acc = acc + (double)h[j] * (1.0 - tau);
+  }
+  return acc / (double)R;
+}
+
+/* Constant-culling step with levels of width `unit` (as pao_choose_dbeta). */
+int pao_choose_dbeta_unit(const uint32_t* h, int n_levels, double unit, uint32_t R,
+                          double eps_target, double rem, double* dbeta_out, int* reached_end) {
+  if (pao_culling_fraction_unit(h, n_levels, unit, R, 0.0) > eps_target) return -1;
+  if (pao_culling_fraction_unit(h, n_levels, unit, R, rem) <= eps_target) {
+    *dbeta_out = rem;
+    *reached_end = 1;
+    return 0;
+  }
+  double lo = 0.0, hi = rem;
+  for (int it = 0; it < 64; ++it) {
+    double mid = lo + 0.5 * (hi - lo);
+    if (pao_culling_fraction_unit(h, n_levels, unit, R, mid) <= eps_target) lo = mid;
+    else hi = mid;
+  }
+  *dbeta_out = lo;
+  *reached_end = 0;
+  return 0;
+}
+
+/* Exact density of states over E16 (N <= 30), Gray-code enumeration:      */
+/* g_out[E16 + off] counts the states with energy E16, off = 3 * 127 * N.    */
+int pao_g_density_of_states(int L, const int8_t* K, uint64_t* g_out) {
+  int N = L * L * L;
+  if (N > 30) return -1;
+  int nb[30][6];
+  int kb[30][6];
+  for (int s = 0; s < N; ++s)
+    for (int dir = 0; dir < 6; ++dir) {
+      nb[s][dir] = neighbour(s, dir, L);
+      kb[s][dir] = K[bond_of(s, dir, L)];
+    }
+  const int off = 3 * 127 * N;
+  memset(g_out, 0, sizeof(uint64_t) * (size_t)(2 * off + 1));
+  int8_t s[30];
+  for (int i = 0; i < N; ++i) s[i] = 1;
+  int e = energy16(s, K, L);
+  g_out[e + off] += 1;
+  uint64_t total = (uint64_t)1 << N;
+  for (uint64_t g = 1; g < total; ++g) {
+    int f = __builtin_ctzll(g);
+    int h = 0;
+    for (int dir = 0; dir < 6; ++dir) h += kb[f][dir] * s[nb[f][dir]];
+    e += 2 * s[f] * h;
+    s[f] = (int8_t)(-s[f]);
+    g_out[e + off] += 1;
+  }
+  return 0;
+}

@@ -22,6 +22,14 @@ def couplings_pm(L: int, coupling_seed: int) -> np.ndarray:
     return (1 - 2 * bits).astype(np.int8)
 
 
+def couplings_gauss16(L: int, coupling_seed: int) -> np.ndarray:
+    """3 L^3 Gaussian couplings J ~ N(0, 1) (numpy PCG64) rounded to multiples of
+    1/16 and returned as the integers k = 16 J, clipped to [-127, 127]."""
+    rng = np.random.Generator(np.random.PCG64(int(coupling_seed)))
+    z = rng.standard_normal(3 * L ** 3)
+    return np.clip(np.rint(16.0 * z), -127, 127).astype(np.int8)
+
+
 def couplings_ferro(L: int) -> np.ndarray:
     """All couplings +1 (the ferromagnetic limit)."""
     return np.ones(3 * L ** 3, np.int8)
