@@ -64,6 +64,13 @@ enum {
                               bit (r & 63) of word [r >> 6][site] is replica r, 1 <=> s = -1 */
 };
 
+enum {
+  PA_MODEL_PM = 0,      /* J = +1 or -1 (J_host holds +-1); energy levels U = 0..3N, E = 2U - 3N */
+  PA_MODEL_GAUSS16 = 1  /* Gaussian couplings (Sec. II.A) rounded to multiples of 1/16: J_host
+                           holds k = 16 J in [-127, 127]; energies are integers E16 = 16 E.
+                           Single-instance calls only (batches and steppers take PA_MODEL_PM). */
+};
+
 typedef struct pa_instance pa_instance;
 
 typedef struct {
@@ -73,7 +80,7 @@ typedef struct {
   uint32_t layout;   /* PA_LAYOUT_* */
   uint64_t seed;     /* population seed: Philox key of every draw of this population */
   uint32_t flags;    /* reserved, must be 0 */
-  uint32_t reserved; /* must be 0 */
+  uint32_t model;    /* PA_MODEL_*: the coupling distribution J_host is drawn from */
 } pa_params;
 
 /* Scalars of one population after a step (Sec. II.A averages, Eq. 9, Sec. III.A). */
@@ -87,7 +94,8 @@ typedef struct {
   double eps_expected; /* culling fraction of the last step (Sec. III.C) */
   uint32_t R_tilde;    /* current population size */
   uint32_t n_culled;   /* replicas with zero copies in the last step */
-  int32_t E_min;       /* lowest energy in the current population */
+  int32_t E_min;       /* lowest energy in the current population (PA_MODEL_GAUSS16: in
+                          quanta 1/16, i.e. the lowest E16; mean_E is in units of J) */
   uint32_t step;       /* number of resampling steps done */
   uint64_t sum_eta2;   /* sum over families of eta^2 */
   uint64_t sweeps_done;/* population sweep counter */

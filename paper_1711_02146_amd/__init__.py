@@ -26,6 +26,10 @@ PA_EDEVICE = -4
 PA_ESTATE = -5
 PA_ESCHEDULE = -6
 
+PA_MODEL_PM = 0
+PA_MODEL_GAUSS16 = 1
+MODELS = {"pm": PA_MODEL_PM, "gauss16": PA_MODEL_GAUSS16}
+
 PA_LAYOUT_AUTO = 0
 PA_LAYOUT_INT8 = 1
 PA_LAYOUT_BITPACK64 = 2
@@ -35,7 +39,7 @@ LAYOUTS = {"auto": PA_LAYOUT_AUTO, "int8": PA_LAYOUT_INT8, "bitpack64": PA_LAYOU
 class pa_params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("R", ctypes.c_uint32), ("capacity", ctypes.c_uint32),
                 ("layout", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("model", ctypes.c_uint32)]
 
 
 class pa_obs(ctypes.Structure):
@@ -298,12 +302,14 @@ class Population:
     """One PA population on a GPU: workspace tensor + library handle."""
 
     def __init__(self, L: int, R: int, J: np.ndarray, seed: int, capacity: int = 0,
-                 layout: str = "bitpack64", device=None, stream=None):
+                 layout: str = "bitpack64", device=None, stream=None, model: str = "pm"):
+        """model "pm": J holds +-1; "gauss16": J holds k = 16 J in [-127, 127]."""
         import torch
 
         self.L, self.N, self.R = int(L), int(L) ** 3, int(R)
+        self.model = model
         self.params = pa_params(L=L, R=R, capacity=capacity, layout=LAYOUTS[layout], seed=seed,
-                                flags=0, reserved=0)
+                                flags=0, model=MODELS[model])
         nbytes = pa_workspace_bytes(self.params)
         if nbytes == 0:
             raise PAError(PA_EINVAL, "pa_workspace_bytes")

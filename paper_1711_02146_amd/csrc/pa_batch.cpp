@@ -124,7 +124,7 @@ int capture_step(pa_batch* b) {
             pa::launch_scan(B, b->g_perpop, s) == hipSuccess &&
             pa::launch_scatter(B, b->g_slots, s) == hipSuccess;
   for (const auto& sg : b->g_sweep)
-    ok = ok && pa::launch_sweep(B, sg.g, sg.layout, sg.L, sg.split, s) == hipSuccess;
+    ok = ok && pa::launch_sweep(B, sg.g, sg.layout, sg.L, sg.split, pa::kModelPm, s) == hipSuccess;
   ok = ok && pa::launch_zero_acc(B, b->g_perpop, s) == hipSuccess &&
        pa::launch_hist(B, b->g_hist, b->max_levels, true, s) == hipSuccess &&
        pa::launch_family(B, b->g_slots, true, s) == hipSuccess &&
@@ -170,6 +170,7 @@ int pa_batch_create(pa_instance* const* pops, uint32_t n_pops, const uint32_t* p
     pa_instance* in = pops[p];
     if (!in || in->failed || in->in_batch || in->pending_gather) return PA_ESTATE;
     if (in->stream != pops[0]->stream) return PA_EINVAL;
+    if (in->dev.model != pa::kModelPm) return PA_EINVAL;  // per-step exp rows cover U levels
     if (in->beta != betas[0]) return PA_EINVAL;
     for (uint32_t q = 0; q < p; ++q)
       if (pops[q] == in) return PA_EINVAL;

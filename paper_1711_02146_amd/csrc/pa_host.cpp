@@ -48,7 +48,7 @@ bool make_layout(const pa_params* p, Layout* out) {
   if (!p) return false;
   if (p->L < 4 || p->L > (uint32_t)pa::kMaxL || (p->L & 1u)) return false;
   if (p->R < 1) return false;
-  if (p->flags != 0 || p->reserved != 0) return false;
+  if (p->flags != 0 || (p->model != PA_MODEL_PM && p->model != PA_MODEL_GAUSS16)) return false;
   uint32_t layout = p->layout == PA_LAYOUT_AUTO ? (uint32_t)PA_LAYOUT_BITPACK64 : p->layout;
   if (layout != PA_LAYOUT_INT8 && layout != PA_LAYOUT_BITPACK64) return false;
   uint64_t cap = p->capacity ? (uint64_t)p->capacity
@@ -61,7 +61,10 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.cap_limit = (uint32_t)cap;
   l.capacity = (uint32_t)((cap + pa::kBlockCounts - 1) / pa::kBlockCounts * pa::kBlockCounts);
   l.layout = layout;
-  l.n_levels = 3 * l.N + 1;
+  l.model = p->model;
+  // energy levels: U = 0..3N, or every E16 window (|E16| <= 3N * 127)
+  l.n_levels = p->model == PA_MODEL_GAUSS16 ? 6 * l.N * (uint32_t)pa::kGaussKMax + 1 : 3 * l.N + 1;
+  l.rowk_stride = (6 * (l.L / 2) + 3) / 4 * 4;
   l.n_blocks = l.capacity / pa::kBlockCounts;
   const size_t tiles = l.capacity / 64;
   l.spins_bytes = layout == PA_LAYOUT_BITPACK64 ? tiles * l.N * 8 : tiles * l.N * 64;
@@ -86,6 +89,8 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.off_sites = take((size_t)l.N * sizeof(SiteEntry));
   l.off_cm = take((size_t)l.N * 2);
   l.off_rowj = take((size_t)2 * l.L * l.L * 8);
+  l.off_rowk = take((size_t)2 * l.L * l.L * l.rowk_stride);
+  l.off_gthr = take((size_t)(pa::kGaussDEMax + 1) * 8);
   l.off_ovl = take(65 * 8);
   l.off_sc = take(sizeof(DevScalars));
   l.off_pops = take(2 * sizeof(DevPop));
@@ -150,6 +155,28 @@ void build_sites(uint32_t L, const int8_t* J, std::vector<SiteEntry>* sites,
       }
 }
 
+// PA_MODEL_GAUSS16 row couplings: colour c, row (y, z), byte 6q + k of the row
+// (rows `stride` bytes apart) is the coupling of the row's q-th site of colour
+// c, x = 2q + ((c + y + z) & 1), to its neighbour k (+x,-x,+y,-y,+z,-z).
+void build_rowk(uint32_t L, const int8_t* K, uint32_t stride, std::vector<int8_t>* rowk) {
+  const uint32_t N = L * L * L;
+  rowk->assign((size_t)2 * L * L * stride, 0);
+  for (uint32_t c = 0; c < 2; ++c)
+    for (uint32_t z = 0; z < L; ++z)
+      for (uint32_t y = 0; y < L; ++y) {
+        const uint32_t p = (c + y + z) & 1u;
+        int8_t* row = rowk->data() + ((size_t)c * L * L + y + L * z) * stride;
+        for (uint32_t q = 0; q < L / 2; ++q) {
+          const uint32_t x = 2 * q + p, s = x + L * (y + L * z);
+          const uint32_t xm = (x + L - 1) % L, ym = (y + L - 1) % L, zm = (z + L - 1) % L;
+          const int8_t kb[6] = {K[0 * N + s], K[0 * N + (xm + L * (y + L * z))],
+                                K[1 * N + s], K[1 * N + (x + L * (ym + L * z))],
+                                K[2 * N + s], K[2 * N + (x + L * (y + L * zm))]};
+          for (int k = 0; k < 6; ++k) row[6 * q + k] = kb[k];
+        }
+      }
+}
+
 // ---------------------------------------------------------------------------
 // FP64 resampling table of one step (Sec. II, Eqs. 1-2).  With the lowest
 // occupied level j_min as reference energy:
@@ -162,8 +189,10 @@ struct Table {
   double S = 0.0, lnQ = 0.0;
 };
 
-Table resample_table(const uint32_t* h, uint32_t n_levels, uint32_t N, uint32_t R, uint32_t R_tilde,
-                     double dbeta, uint32_t* fl, uint64_t* T) {
+// Levels j have energy unit * (E_lo + j): unit 2, E_lo = -3N/2 for +-J (E = 2U - 3N),
+// unit 1/16, E_lo = lowest E16 of the population for quantised Gaussian couplings.
+Table resample_table(const uint32_t* h, uint32_t n_levels, double unit, int64_t E_lo, uint32_t R,
+                     uint32_t R_tilde, double dbeta, uint32_t* fl, uint64_t* T) {
   Table t;
   for (uint32_t j = 0; j < n_levels; ++j)
     if (h[j] > 0) {
@@ -176,7 +205,7 @@ Table resample_table(const uint32_t* h, uint32_t n_levels, uint32_t N, uint32_t 
   static thread_local std::vector<double> w;
   w.resize(n_levels);
   for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j)
-    w[j] = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
+    w[j] = std::exp(-dbeta * (unit * (double)((int)j - jmin)));
   double S = 0.0;
   for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
     if (h[j] == 0) continue;
@@ -195,13 +224,14 @@ Table resample_table(const uint32_t* h, uint32_t n_levels, uint32_t N, uint32_t 
     T[j] = (uint64_t)std::ceil(std::ldexp(fr, 53));
   }
   t.S = S;
-  t.lnQ = std::log(S) - std::log((double)R_tilde) - dbeta * (double)(2 * jmin - 3 * (int)N);
+  t.lnQ = std::log(S) - std::log((double)R_tilde) - dbeta * (unit * (double)(E_lo + jmin));
   return t;
 }
 
 // Culling fraction (Sec. III.C): eps R = sum_{tau_i < 1} (1 - tau_i), tau_j
 // exactly as in resample_table.
-double culling_fraction(const uint32_t* h, uint32_t n_levels, uint32_t R, double dbeta) {
+double culling_fraction(const uint32_t* h, uint32_t n_levels, double unit, uint32_t R,
+                        double dbeta) {
   int jmin = -1;
   for (uint32_t j = 0; j < n_levels; ++j)
     if (h[j] > 0) {
@@ -215,7 +245,7 @@ double culling_fraction(const uint32_t* h, uint32_t n_levels, uint32_t R, double
   double S = 0.0;
   for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
     if (h[j] == 0) continue;
-    w[j] = std::exp(-dbeta * (double)(2 * ((int)j - jmin)));
+    w[j] = std::exp(-dbeta * (unit * (double)((int)j - jmin)));
     S = S + (double)h[j] * w[j];
   }
   double acc = 0.0;
@@ -261,7 +291,20 @@ hipError_t launch_sweep_of(pa_instance* in, const pa::PopStep& ps) {
   const uint32_t split =
       pa::sweep_split_for(in->dev.layout, in->dev.L, ((uint64_t)in->R_tilde + 63) / 64);
   return pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
-                          in->dev.layout, in->dev.L, split, in->stream);
+                          in->dev.layout, in->dev.L, split, in->dev.model, in->stream);
+}
+
+// Energy levels of the histogram in in->h_hist: count, width and offset
+// (level j has energy unit * (E_lo + j)).
+struct Levels {
+  uint32_t n;
+  double unit;
+  int64_t E_lo;
+};
+
+Levels levels_of(const pa_instance* in) {
+  if (in->dev.model == pa::kModelGauss16) return {in->n_win, 1.0 / 16.0, (int64_t)in->E_lo};
+  return {in->dev.n_levels, 2.0, -(int64_t)(3 * in->dev.N / 2)};
 }
 
 int dev_fail(pa_instance* in) {
@@ -289,26 +332,63 @@ int materialize(pa_instance* in) {
 }
 
 // Histogram of the current population into in->h_hist, plus the device
-// scalars into in->h_sc.  Synchronises.
+// scalars into in->h_sc.  Synchronises.  For PA_MODEL_GAUSS16 the histogram
+// covers the occupied window [E_lo, E_hi] of E16, found on the device first.
 int fetch_hist(pa_instance* in, bool with_family) {
   int rc = materialize(in);
   if (rc) return rc;
   const DevPop& P = in->dev;
   const pa::BatchDev B = one_set(in, plain_step(in->cur));
   PA_HIP(in, pa::launch_zero_acc(B, group_of(in, in->d_meta->perpop, 1), in->stream));
-  PA_HIP(in, pa::launch_hist(B, group_of(in, in->d_meta->hist, in->meta.hist[1]), P.n_levels, false,
-                             in->stream));
+  uint32_t n = P.n_levels;
+  if (P.model == pa::kModelGauss16) {
+    PA_HIP(in, pa::launch_minmax(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
+    PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
+    PA_HIP(in, hipStreamSynchronize(in->stream));
+    const int64_t w = (int64_t)in->h_sc->E_hi - (int64_t)in->h_sc->E_lo + 1;
+    if (w < 1 || w > (int64_t)P.n_levels) return dev_fail(in);  // the population is empty or corrupt
+    n = (uint32_t)w;
+    in->E_lo = in->h_sc->E_lo;
+    in->n_win = n;
+    PA_HIP(in, pa::launch_fill_u32(P.hist, 0u, n, in->stream));
+    PA_HIP(in, pa::launch_hist_window(B, group_of(in, in->d_meta->slots, in->meta.slots[1]),
+                                      in->stream));
+  } else {
+    PA_HIP(in, pa::launch_hist(B, group_of(in, in->d_meta->hist, in->meta.hist[1]), P.n_levels,
+                               false, in->stream));
+  }
   if (with_family)
     PA_HIP(in, pa::launch_family(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), false,
                                  in->stream));
-  PA_HIP(in, hipMemcpyAsync(in->h_hist, P.hist, (size_t)P.n_levels * 4, hipMemcpyDeviceToHost,
-                            in->stream));
+  PA_HIP(in, hipMemcpyAsync(in->h_hist, P.hist, (size_t)n * 4, hipMemcpyDeviceToHost, in->stream));
   PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
   if (in->h_sc->err == 2) return dev_fail(in);
   in->R_tilde = in->h_sc->R_tilde;
   in->hist_valid = true;
   return PA_OK;
+}
+
+// Metropolis thresholds of a sweep at beta into the step parameters; for
+// PA_MODEL_GAUSS16 the dE16 table goes to the instance's device buffer,
+// stream-ordered, through a pinned buffer that is refilled only after the
+// previous copy out of it has completed.
+hipError_t set_thresholds(pa_instance* in, double beta, pa::PopStep* ps) {
+  if (in->dev.model != pa::kModelGauss16) {
+    thresholds(beta, ps->thr);
+    return hipSuccess;
+  }
+  hipError_t e = hipEventSynchronize(in->gthr_copied);
+  if (e != hipSuccess) return e;
+  unsigned long long* tab = in->h_gthr;
+  for (int d = 0; d <= pa::kGaussDEMax; ++d)
+    tab[d] = (unsigned long long)std::floor(std::ldexp(std::exp(-beta * ((double)d / 16.0)), 32));
+  ps->thr[0] = tab[2];  // the largest threshold of a positive move (dE16 is even)
+  ps->thr[1] = ps->thr[2] = 0;
+  e = hipMemcpyAsync(const_cast<unsigned long long*>(in->dev.gthr), tab,
+                     (size_t)(pa::kGaussDEMax + 1) * 8, hipMemcpyHostToDevice, in->stream);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(in->gthr_copied, in->stream);
 }
 
 bool usable(pa_instance* in) { return in && !in->failed && !in->in_batch; }
@@ -344,8 +424,11 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   if (!make_layout(p, &l) || !J_host || !d_workspace) return PA_EINVAL;
   if (ws_bytes < l.total) return PA_ENOMEM;
   if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return PA_EINVAL;
-  for (uint32_t b = 0; b < 3 * l.N; ++b)
-    if (J_host[b] != 1 && J_host[b] != -1) return PA_EINVAL;
+  for (uint32_t b = 0; b < 3 * l.N; ++b) {
+    if (l.model == PA_MODEL_PM && J_host[b] != 1 && J_host[b] != -1) return PA_EINVAL;
+    if (l.model == PA_MODEL_GAUSS16 && (J_host[b] < -pa::kGaussKMax || J_host[b] > pa::kGaussKMax))
+      return PA_EINVAL;
+  }
 
   pa_instance* in = new (std::nothrow) pa_instance();
   if (!in) return PA_EINVAL;
@@ -353,6 +436,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   in->stream = static_cast<hipStream_t>(hip_stream);
   in->ws = static_cast<uint8_t*>(d_workspace);
   build_sites(l.L, J_host, &in->sites, &in->cm_of_site, &in->rowj);
+  if (l.model == PA_MODEL_GAUSS16) build_rowk(l.L, J_host, l.rowk_stride, &in->rowk);
 
   DevPop& P = in->dev;
   P.L = l.L;
@@ -384,6 +468,10 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   P.rowj = reinterpret_cast<const unsigned long long*>(w + l.off_rowj);
   P.ovl_hist = reinterpret_cast<unsigned long long*>(w + l.off_ovl);
   P.sc = reinterpret_cast<DevScalars*>(w + l.off_sc);
+  P.model = l.model;
+  P.rowk_stride = l.rowk_stride;
+  P.rowk = reinterpret_cast<const int8_t*>(w + l.off_rowk);
+  P.gthr = reinterpret_cast<const unsigned long long*>(w + l.off_gthr);
   in->d_pops = reinterpret_cast<DevPop*>(w + l.off_pops);
   in->d_meta = reinterpret_cast<MetaU32*>(w + l.off_meta);
   MetaU32& mt = in->meta;
@@ -407,6 +495,12 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
       hipHostMalloc(reinterpret_cast<void**>(&in->h_ovl), 65 * 8) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_meta), sizeof(MetaU32)) != hipSuccess)
     return fail(PA_EDEVICE);
+  if (l.model == PA_MODEL_GAUSS16 &&
+      (hipHostMalloc(reinterpret_cast<void**>(&in->h_gthr), (size_t)(pa::kGaussDEMax + 1) * 8) !=
+           hipSuccess ||
+       hipEventCreateWithFlags(&in->gthr_copied, hipEventDisableTiming) != hipSuccess ||
+       hipEventRecord(in->gthr_copied, in->stream) != hipSuccess))
+    return fail(PA_EDEVICE);
 
   // tables and scalars (synchronous copies from pageable host memory)
   DevScalars sc{};
@@ -417,6 +511,9 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
                      in->stream) != hipSuccess ||
       hipMemcpyAsync(w + l.off_rowj, in->rowj.data(), in->rowj.size() * 8, hipMemcpyHostToDevice,
                      in->stream) != hipSuccess ||
+      (!in->rowk.empty() &&
+       hipMemcpyAsync(w + l.off_rowk, in->rowk.data(), in->rowk.size(), hipMemcpyHostToDevice,
+                      in->stream) != hipSuccess) ||
       hipMemcpyAsync(P.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, in->stream) != hipSuccess ||
       hipMemcpyAsync(in->d_pops, &in->dev, sizeof(DevPop), hipMemcpyHostToDevice, in->stream) !=
           hipSuccess ||
@@ -425,6 +522,11 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
       hipStreamSynchronize(in->stream) != hipSuccess)
     return fail(PA_EDEVICE);
   if (pa::launch_init(P, 0, in->stream) != hipSuccess) return fail(PA_EDEVICE);
+  // quantised Gaussian couplings: the energy word is E16, formed from the spins
+  if (l.model == PA_MODEL_GAUSS16 &&
+      pa::launch_energy(one_set(in, plain_step(0)), group_of(in, in->d_meta->etiles, mt.etiles[1]),
+                        l.layout, l.L, l.model, in->stream) != hipSuccess)
+    return fail(PA_EDEVICE);
   in->cur = 0;
   in->R_tilde = l.R;
   *out = in;
@@ -440,6 +542,8 @@ int pa_free(pa_instance* in) {
   if (in->h_sc) (void)hipHostFree(in->h_sc);
   if (in->h_ovl) (void)hipHostFree(in->h_ovl);
   if (in->h_meta) (void)hipHostFree(in->h_meta);
+  if (in->h_gthr) (void)hipHostFree(in->h_gthr);
+  if (in->gthr_copied) (void)hipEventDestroy(in->gthr_copied);
   delete in;
   return PA_OK;
 }
@@ -450,7 +554,7 @@ int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps) {
   if (n_sweeps == 0) return PA_OK;
   if (in->sweeps + n_sweeps > 0xFFFFFFFFull) return PA_EINVAL;  // sweep counter is 32-bit
   pa::PopStep ps = plain_step(in->cur);
-  thresholds(beta, ps.thr);
+  PA_HIP(in, set_thresholds(in, beta, &ps));
   ps.t0 = (uint32_t)in->sweeps;
   ps.n_sweeps = n_sweeps;
   ps.gather = in->pending_gather ? 1u : 0u;
@@ -472,13 +576,14 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
   }
   const DevPop& P = in->dev;
   const double dbeta = beta_next - in->beta;
-  const Table t = resample_table(in->h_hist, P.n_levels, P.N, P.R, in->R_tilde, dbeta, in->h_fl,
-                                 in->h_T);
+  const Levels lv = levels_of(in);
+  const Table t = resample_table(in->h_hist, lv.n, lv.unit, lv.E_lo, P.R, in->R_tilde, dbeta,
+                                 in->h_fl, in->h_T);
   if (t.jmin < 0) return PA_ESTATE;  // empty population
-  const double eps = culling_fraction(in->h_hist, P.n_levels, P.R, dbeta);
-  PA_HIP(in, hipMemcpyAsync(P.table_fl, in->h_fl, (size_t)P.n_levels * 4, hipMemcpyHostToDevice,
+  const double eps = culling_fraction(in->h_hist, lv.n, lv.unit, P.R, dbeta);
+  PA_HIP(in, hipMemcpyAsync(P.table_fl, in->h_fl, (size_t)lv.n * 4, hipMemcpyHostToDevice,
                             in->stream));
-  PA_HIP(in, hipMemcpyAsync(P.table_T, in->h_T, (size_t)P.n_levels * 8, hipMemcpyHostToDevice,
+  PA_HIP(in, hipMemcpyAsync(P.table_T, in->h_T, (size_t)lv.n * 8, hipMemcpyHostToDevice,
                             in->stream));
   pa::PopStep ps = plain_step(in->cur);
   ps.step = in->step + 1;
@@ -525,18 +630,19 @@ int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* 
     int rc = fetch_hist(in, false);
     if (rc) return rc;
   }
-  const uint32_t nl = in->dev.n_levels, R = in->dev.R;
+  const Levels lv = levels_of(in);
+  const uint32_t nl = lv.n, R = in->dev.R;
   const uint32_t* h = in->h_hist;
-  if (culling_fraction(h, nl, R, 0.0) > eps_target) return PA_ESCHEDULE;
+  if (culling_fraction(h, nl, lv.unit, R, 0.0) > eps_target) return PA_ESCHEDULE;
   const double rem = beta_max - in->beta;
-  if (culling_fraction(h, nl, R, rem) <= eps_target) {
+  if (culling_fraction(h, nl, lv.unit, R, rem) <= eps_target) {
     *beta_next = beta_max;
     return PA_OK;
   }
   double lo = 0.0, hi = rem;
   for (int it = 0; it < 64; ++it) {
     const double mid = lo + 0.5 * (hi - lo);
-    if (culling_fraction(h, nl, R, mid) <= eps_target) lo = mid;
+    if (culling_fraction(h, nl, lv.unit, R, mid) <= eps_target) lo = mid;
     else hi = mid;
   }
   *beta_next = in->beta + lo;
@@ -550,11 +656,15 @@ int pa_observables(pa_instance* in, pa_obs* out) {
   if (rc) return rc;
   const DevPop& P = in->dev;
   const uint32_t* h = in->h_hist;
+  const bool gauss = P.model == pa::kModelGauss16;
+  const Levels lv = levels_of(in);
+  // sum of E in integer units: 2U - 3N, or E16 = E_lo + j
   int64_t sumE = 0;
   int jmin = -1;
-  for (uint32_t j = 0; j < P.n_levels; ++j) {
+  for (uint32_t j = 0; j < lv.n; ++j) {
     if (h[j] && jmin < 0) jmin = (int)j;
-    sumE += (int64_t)h[j] * (2 * (int64_t)j - 3 * (int64_t)P.N);
+    const int64_t e = gauss ? lv.E_lo + (int64_t)j : 2 * (int64_t)j - 3 * (int64_t)P.N;
+    sumE += (int64_t)h[j] * e;
   }
   std::memset(out, 0, sizeof(*out));
   out->beta = in->beta;
@@ -562,12 +672,13 @@ int pa_observables(pa_instance* in, pa_obs* out) {
   out->lnQ = in->last_lnQ;
   out->beta_F = -((double)P.N * std::log(2.0) + in->sum_lnQ);
   out->mean_E = in->R_tilde ? (double)sumE / (double)in->R_tilde : 0.0;
+  if (gauss) out->mean_E = out->mean_E * (1.0 / 16.0);  // E16 -> E
   out->sum_eta2 = in->h_sc->sum_eta2;
   out->rho_t = (double)out->sum_eta2 / (double)P.R;
   out->eps_expected = in->last_eps;
   out->R_tilde = in->R_tilde;
   out->n_culled = in->last_n_culled;
-  out->E_min = jmin >= 0 ? 2 * jmin - 3 * (int)P.N : 0;
+  out->E_min = jmin < 0 ? 0 : gauss ? (int32_t)(lv.E_lo + jmin) : 2 * jmin - 3 * (int)P.N;
   out->n_at_E_min = jmin >= 0 ? h[jmin] : 0u;
   out->step = in->step;
   out->sweeps_done = in->sweeps;
@@ -702,7 +813,7 @@ int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* f
   PA_HIP(in, hipMemcpy(P.sc, &sc, sizeof(sc), hipMemcpyHostToDevice));
   PA_HIP(in, pa::launch_energy(one_set(in, plain_step(in->cur)),
                                group_of(in, in->d_meta->etiles, in->meta.etiles[1]), P.layout,
-                               P.L, in->stream));
+                               P.L, P.model, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
   in->R_tilde = R_tilde;
   in->sweeps = sweeps_done;
@@ -725,7 +836,7 @@ int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t 
   // buffer and write the other one; the population, its counters and the
   // current buffer are left as they were.
   pa::PopStep ps = plain_step(in->cur);
-  thresholds(beta, ps.thr);
+  if (set_thresholds(in, beta, &ps) != hipSuccess) return dev_fail(in);
   ps.t0 = (uint32_t)in->sweeps;
   ps.n_sweeps = n_sweeps;
   ps.gather = 0;
@@ -741,7 +852,8 @@ int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t 
   const pa::BatchDev B = one_set(in, ps);
   const pa::Group g = group_of(in, in->d_meta->tiles, in->meta.tiles[1]);
   auto launch = [&](uint32_t split) {
-    return pa::launch_sweep(B, g, in->dev.layout, in->dev.L, split, in->stream) == hipSuccess;
+    return pa::launch_sweep(B, g, in->dev.layout, in->dev.L, split, in->dev.model, in->stream) ==
+           hipSuccess;
   };
   // two untimed launches of each form (clocks and caches settle), then the
   // timed launches alternate between the forms so that drift hits both alike

@@ -30,11 +30,11 @@ struct MetaU32 {
 };
 
 struct Layout {
-  uint32_t L, N, R, cap_limit, capacity, layout, n_levels, n_blocks;
+  uint32_t L, N, R, cap_limit, capacity, layout, n_levels, n_blocks, model, rowk_stride;
   size_t spins_bytes;
   size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
-      off_bcull, off_hist, off_fl, off_T, off_sites, off_cm, off_rowj, off_ovl, off_sc, off_pops,
-      off_meta;
+      off_bcull, off_hist, off_fl, off_T, off_sites, off_cm, off_rowj, off_rowk, off_gthr, off_ovl,
+      off_sc, off_pops, off_meta;
   size_t total;
 };
 
@@ -83,6 +83,10 @@ struct pa_instance {
   std::vector<pa::SiteEntry> sites;
   std::vector<uint16_t> cm_of_site;
   std::vector<uint64_t> rowj;
+  std::vector<int8_t> rowk;          // PA_MODEL_GAUSS16 row couplings
+  // PA_MODEL_GAUSS16: energy window of the histogram in h_hist (valid with hist_valid)
+  int32_t E_lo = 0;
+  uint32_t n_win = 0;
   // host mirror of the population state
   uint32_t cur = 0;
   uint32_t R_tilde = 0;
@@ -101,6 +105,8 @@ struct pa_instance {
   pa::DevScalars* h_sc = nullptr;
   unsigned long long* h_ovl = nullptr;
   pa_host::MetaU32* h_meta = nullptr;
+  unsigned long long* h_gthr = nullptr;  // PA_MODEL_GAUSS16 threshold table staging
+  hipEvent_t gthr_copied = nullptr;      // recorded after each copy out of h_gthr
   bool in_batch = false;
 };
 

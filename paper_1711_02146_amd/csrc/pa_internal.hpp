@@ -28,6 +28,14 @@ constexpr int kWave = 64;          // wavefront width on gfx950; one spin tile =
 constexpr int kBlockCounts = 256;  // slots per block in the copy-count / scatter kernels
 constexpr int kHistSlots = 4096;   // slots per block of the histogram kernel
 constexpr int kMaxL = 16;
+// Energy models.  kModelPm: J = +-1, the energy word of a replica is U, the
+// number of unsatisfied bonds (E = 2U - 3N).  kModelGauss16: J = k / 16 with
+// k in [-127, 127], the energy word is E16 = -sum_b k_b s_i s_j (E = E16 / 16),
+// stored as int32.
+constexpr uint32_t kModelPm = 0;
+constexpr uint32_t kModelGauss16 = 1;
+constexpr int kGaussKMax = 127;
+constexpr int kGaussDEMax = 2 * 6 * kGaussKMax;  // largest |dE16| of one flip
 
 // One lattice site in colour-major order (cm): colour-0 sites first, then
 // colour-1 sites, each in lexicographic order; for even L, cm = c*N/2 + (site >> 1).
@@ -51,7 +59,8 @@ struct DevScalars {
   unsigned long long sum_eta2;  // sum over families of eta^2
   uint32_t n_families;    // families with eta > 0
   uint32_t dead;          // batch runs: set when a step overflowed; later steps skip it
-  uint32_t pad[8];
+  int32_t E_lo, E_hi;     // kModelGauss16: lowest / highest E16 of the population
+  uint32_t pad[6];
 };
 static_assert(sizeof(DevScalars) == 64, "DevScalars is 64 bytes");
 
@@ -81,6 +90,12 @@ struct DevPop {
                                    // site q of row (colour, y, z) to neighbour k is -1
   unsigned long long* ovl_hist; // 65 bins, scratch of the overlap histogram
   DevScalars* sc;
+  uint32_t model;               // kModelPm or kModelGauss16
+  uint32_t rowk_stride;         // kModelGauss16: bytes per row of rowk (6 L/2 rounded up to 4)
+  const int8_t* rowk;           // kModelGauss16: 2 L^2 rows; byte 6q + k of a row is the
+                                // coupling k of its site q to neighbour k (J = k / 16)
+  const unsigned long long* gthr;  // kModelGauss16: thr[d] = floor(2^32 exp(-beta d / 16)),
+                                   // d = 0..kGaussDEMax, for the coming sweep
 };
 
 // Parameters of one population for one launch.
@@ -146,10 +161,10 @@ hipError_t launch_table(const BatchDev& B, const Group& per_pop, hipStream_t str
 hipError_t launch_counts(const BatchDev& B, const Group& g, hipStream_t stream);
 hipError_t launch_scan(const BatchDev& B, const Group& per_pop, hipStream_t stream);
 hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream);
-// sweep launch over the populations of one (layout, L) group: one tile per
-// workgroup of `split` (4 or 8) waves; g's blocks are blocks_sweep(capacity)
+// sweep launch over the populations of one (layout, L, model) group: one tile
+// per workgroup of `split` (4 or 8) waves; g's blocks are blocks_sweep(capacity)
 hipError_t launch_sweep(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
-                        uint32_t split, hipStream_t stream);
+                        uint32_t split, uint32_t model, hipStream_t stream);
 hipError_t launch_family(const BatchDev& B, const Group& g, bool post, hipStream_t stream);
 hipError_t launch_record(const BatchDev& B, const Group& per_pop, hipStream_t stream);
 // cur_a / cur_b: the two populations' buffers when B carries no per-step parameters
@@ -157,7 +172,12 @@ hipError_t launch_overlap(const BatchDev& B, const Group& pairs, const uint32_t*
                           uint32_t layout, bool post, uint32_t cur_a, uint32_t cur_b,
                           hipStream_t stream);
 hipError_t launch_energy(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
-                         hipStream_t stream);
+                         uint32_t model, hipStream_t stream);
+// kModelGauss16: E_lo / E_hi of every member (zero_acc resets them first) and the
+// histogram h[E16 - E_lo] (global atomics; the host clears the window first),
+// both over the current buffer of a call on single instances
+hipError_t launch_minmax(const BatchDev& B, const Group& g, hipStream_t stream);
+hipError_t launch_hist_window(const BatchDev& B, const Group& g, hipStream_t stream);
 hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream);
 
 // Blocks each population needs in each kind of launch.

@@ -257,6 +257,10 @@ struct TileCtx {
   MetPhilox ph;
   uint32_t t;
   bool any_draw;
+  // kModelGauss16
+  const int8_t* rowk;                  // row couplings (see DevPop)
+  uint32_t rowk_stride;
+  const unsigned long long* gtab;      // LDS copy of the dE16 threshold table
 };
 
 struct RowAddr {
@@ -267,10 +271,11 @@ struct RowAddr {
   const uint32_t* my;
   const uint32_t* pz;
   const uint32_t* mz;
-  unsigned long long j;  // coupling bits of the row
+  unsigned long long j;  // coupling bits of the row (kModelPm)
+  const uint32_t* krow;  // coupling bytes of the row, 4 per word (kModelGauss16)
 };
 
-template <int L>
+template <int L, int M>
 __device__ __forceinline__ RowAddr row_addr(const TileCtx& c, const unsigned long long* rowj,
                                             uint32_t colour, uint32_t rho) {
   constexpr uint32_t H = L / 2, N = L * L * L;
@@ -289,7 +294,13 @@ __device__ __forceinline__ RowAddr row_addr(const TileCtx& c, const unsigned lon
   a.my = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (ym + L * z)));
   a.pz = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (y + L * zp)));
   a.mz = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (y + L * zm)));
-  a.j = rowj[colour * L * L + rho];
+  if constexpr (M == (int)kModelGauss16) {
+    a.j = 0;
+    a.krow = reinterpret_cast<const uint32_t*>(c.rowk + (size_t)(colour * L * L + rho) * c.rowk_stride);
+  } else {
+    a.j = rowj[colour * L * L + rho];
+    a.krow = nullptr;
+  }
   return a;
 }
 
@@ -344,12 +355,54 @@ __device__ __forceinline__ void site_update(const TileCtx& c, const RowAddr& a, 
   if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Coupling k (in quanta 1/16) of site Q of a row to its neighbour K: a
+// sign-extended byte of the row's words (uniform: scalar registers).
+template <int Q, int K>
+__device__ __forceinline__ int32_t row_k(const RowAddr& a) {
+  constexpr int b = 6 * Q + K;
+  const uint32_t w = a.krow[b / 4];
+  return (int32_t)(w << (24 - 8 * (b % 4))) >> 24;
+}
+
+// Metropolis update of one site for quantised Gaussian couplings.  With x_k =
+// [s_i != s_k] (own bit ^ neighbour bit), sum_k k_k s_i s_k = csum - 2 acc
+// where csum = sum_k k_k and acc = sum_k k_k x_k, so flipping s_i changes
+// E16 by dE = 2 csum - 4 acc.  The move is taken iff its draw is below
+// gtab[max(dE, 0)] (gtab[0] = 2^32: every move with dE <= 0 is taken).
+// With ACCUM the pass also sums the site's post-move energy
+// -sum_k k_k s_i s_k: in the colour-1 pass of the last sweep that is E16.
+template <int L, int Q, bool ACCUM>
+__device__ __forceinline__ void site_update_g(const TileCtx& c, const RowAddr& a,
+                                              const SiteLoad& w, uint32_t draw, uint32_t& usum) {
+  uint32_t* const own_p = const_cast<uint32_t*>(a.own) + 2 * Q;
+  const int32_t k0 = row_k<Q, 0>(a), k1 = row_k<Q, 1>(a), k2 = row_k<Q, 2>(a);
+  const int32_t k3 = row_k<Q, 3>(a), k4 = row_k<Q, 4>(a), k5 = row_k<Q, 5>(a);
+  const int32_t csum = k0 + k1 + k2 + k3 + k4 + k5;
+  const int32_t x0 = (int32_t)__builtin_amdgcn_ubfe(w.nb[0] ^ w.own, c.pos, 1);
+  const int32_t x1 = (int32_t)__builtin_amdgcn_ubfe(w.nb[1] ^ w.own, c.pos, 1);
+  const int32_t x2 = (int32_t)__builtin_amdgcn_ubfe(w.nb[2] ^ w.own, c.pos, 1);
+  const int32_t x3 = (int32_t)__builtin_amdgcn_ubfe(w.nb[3] ^ w.own, c.pos, 1);
+  const int32_t x4 = (int32_t)__builtin_amdgcn_ubfe(w.nb[4] ^ w.own, c.pos, 1);
+  const int32_t x5 = (int32_t)__builtin_amdgcn_ubfe(w.nb[5] ^ w.own, c.pos, 1);
+  const int32_t acc = x0 * k0 + x1 * k1 + x2 * k2 + x3 * k3 + x4 * k4 + x5 * k5;
+  const int32_t dE = 2 * csum - 4 * acc;
+  const unsigned long long thr = c.gtab[dE > 0 ? dE : 0];
+  const bool accept = (unsigned long long)draw < thr;
+  if (ACCUM) {
+    const int32_t e = 2 * acc - csum;  // the site's energy before the move
+    usum += (uint32_t)(accept ? -e : e);
+  }
+  const unsigned long long f = __ballot(accept);
+  const uint32_t fh = c.hoff ? (uint32_t)(f >> 32) : (uint32_t)f;
+  if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Sites Q.. of row I of a 4-row block.  The words of site Q + 1 are read
 // before site Q is updated: they are other-colour words (not written in this
 // pass) and a different own word, so the early read sees the same values and
 // its LDS latency overlaps the current site's work.  A new Philox group
 // starts every fourth site of the block.
-template <int L, int I, int Q, bool ACCUM>
+template <int L, int M, int I, int Q, bool ACCUM>
 __device__ __forceinline__ void block_row(const TileCtx& c, const RowAddr& a, uint32_t g0,
                                           Words4& d, uint32_t& usum, const SiteLoad& w) {
   constexpr int H = L / 2;
@@ -359,11 +412,14 @@ __device__ __forceinline__ void block_row(const TileCtx& c, const RowAddr& a, ui
   if constexpr (S % 4 == 0) {
     if (c.any_draw) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
   }
-  site_update<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
-  if constexpr (Q + 1 < H) block_row<L, I, Q + 1, ACCUM>(c, a, g0, d, usum, wn);
+  if constexpr (M == (int)kModelGauss16)
+    site_update_g<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
+  else
+    site_update<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
+  if constexpr (Q + 1 < H) block_row<L, M, I, Q + 1, ACCUM>(c, a, g0, d, usum, wn);
 }
 
-template <int L, bool ACCUM>
+template <int L, int M, bool ACCUM>
 __device__ uint32_t sweep_colour_blocks(const TileCtx& c, const unsigned long long* rowj,
                                         uint32_t colour, uint32_t part, uint32_t nparts) {
   constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L;
@@ -374,42 +430,59 @@ __device__ uint32_t sweep_colour_blocks(const TileCtx& c, const unsigned long lo
   for (uint32_t rb = 4 * part; rb < ROWS; rb += 4 * nparts) {
     const uint32_t rbu = __builtin_amdgcn_readfirstlane(rb);
     const uint32_t g0 = (own0 + H * rbu) >> 2;  // first Philox group of the block
-    const RowAddr a0 = row_addr<L>(c, rowj, colour, rbu);
-    block_row<L, 0, 0, ACCUM>(c, a0, g0, d, usum, load_site_words<L, 0>(a0));
-    const RowAddr a1 = row_addr<L>(c, rowj, colour, rbu + 1);
-    block_row<L, 1, 0, ACCUM>(c, a1, g0, d, usum, load_site_words<L, 0>(a1));
-    const RowAddr a2 = row_addr<L>(c, rowj, colour, rbu + 2);
-    block_row<L, 2, 0, ACCUM>(c, a2, g0, d, usum, load_site_words<L, 0>(a2));
-    const RowAddr a3 = row_addr<L>(c, rowj, colour, rbu + 3);
-    block_row<L, 3, 0, ACCUM>(c, a3, g0, d, usum, load_site_words<L, 0>(a3));
+    const RowAddr a0 = row_addr<L, M>(c, rowj, colour, rbu);
+    block_row<L, M, 0, 0, ACCUM>(c, a0, g0, d, usum, load_site_words<L, 0>(a0));
+    const RowAddr a1 = row_addr<L, M>(c, rowj, colour, rbu + 1);
+    block_row<L, M, 1, 0, ACCUM>(c, a1, g0, d, usum, load_site_words<L, 0>(a1));
+    const RowAddr a2 = row_addr<L, M>(c, rowj, colour, rbu + 2);
+    block_row<L, M, 2, 0, ACCUM>(c, a2, g0, d, usum, load_site_words<L, 0>(a2));
+    const RowAddr a3 = row_addr<L, M>(c, rowj, colour, rbu + 3);
+    block_row<L, M, 3, 0, ACCUM>(c, a3, g0, d, usum, load_site_words<L, 0>(a3));
   }
   __syncthreads();
   return usum;
 }
 
-// Energy of the tile when no sweep ran: sum over colour-0 sites of nu.
-template <int L>
-__device__ uint32_t tile_energy_rows(const TileCtx& c, const unsigned long long* rowj,
-                                     uint32_t part, uint32_t nparts) {
-  constexpr uint32_t H = L / 2, ROWS = L * L;
-  uint32_t U = 0;
-  for (uint32_t rho = part; rho < ROWS; rho += nparts) {
-    const RowAddr a = row_addr<L>(c, rowj, 0u, __builtin_amdgcn_readfirstlane(rho));
+// One row's share of tile_energy_rows, sites Q.. of the row.
+template <int L, int M, int Q>
+__device__ __forceinline__ void tile_energy_row(const TileCtx& c, const RowAddr& a, uint32_t& U) {
+  constexpr int H = L / 2;
+  const SiteLoad w = load_site_words<L, Q>(a);
+  if constexpr (M == (int)kModelGauss16) {
+    const int32_t k0 = row_k<Q, 0>(a), k1 = row_k<Q, 1>(a), k2 = row_k<Q, 2>(a);
+    const int32_t k3 = row_k<Q, 3>(a), k4 = row_k<Q, 4>(a), k5 = row_k<Q, 5>(a);
+    const int32_t csum = k0 + k1 + k2 + k3 + k4 + k5;
+    const int32_t acc = (int32_t)__builtin_amdgcn_ubfe(w.nb[0] ^ w.own, c.pos, 1) * k0 +
+                        (int32_t)__builtin_amdgcn_ubfe(w.nb[1] ^ w.own, c.pos, 1) * k1 +
+                        (int32_t)__builtin_amdgcn_ubfe(w.nb[2] ^ w.own, c.pos, 1) * k2 +
+                        (int32_t)__builtin_amdgcn_ubfe(w.nb[3] ^ w.own, c.pos, 1) * k3 +
+                        (int32_t)__builtin_amdgcn_ubfe(w.nb[4] ^ w.own, c.pos, 1) * k4 +
+                        (int32_t)__builtin_amdgcn_ubfe(w.nb[5] ^ w.own, c.pos, 1) * k5;
+    U += (uint32_t)(2 * acc - csum);
+  } else {
     const uint32_t jlo = (uint32_t)a.j, jhi = (uint32_t)(a.j >> 32);
 #pragma unroll
-    for (int q = 0; q < (int)H; ++q) {
-      const uint32_t own = a.own[2 * q];
-      const uint32_t nb[6] = {q < (int)H - 1 ? a.x0[2 * q] : a.wrap[0],
-                              q > 0 ? a.x0[2 * (q - 1)] : a.wrap[0],
-                              a.py[2 * q], a.my[2 * q], a.pz[2 * q], a.mz[2 * q]};
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const int bit = 6 * q + k;
-        const uint32_t jm = bit < 32 ? (uint32_t)((int32_t)(jlo << (31 - bit)) >> 31)
-                                     : (uint32_t)((int32_t)(jhi << (63 - bit)) >> 31);
-        U += __builtin_amdgcn_ubfe(xor3_s(nb[k], own, jm), c.pos, 1);
-      }
+    for (int k = 0; k < 6; ++k) {
+      const int bit = 6 * Q + k;
+      const uint32_t jm = bit < 32 ? (uint32_t)((int32_t)(jlo << (31 - bit)) >> 31)
+                                   : (uint32_t)((int32_t)(jhi << (63 - bit)) >> 31);
+      U += __builtin_amdgcn_ubfe(xor3_s(w.nb[k], w.own, jm), c.pos, 1);
     }
+  }
+  if constexpr (Q + 1 < H) tile_energy_row<L, M, Q + 1>(c, a, U);
+}
+
+// Energy of the tile when no sweep ran: sum over colour-0 sites of nu (every
+// bond joins one site of each colour); for kModelGauss16 the sum over colour-0
+// sites of -sum_k k_k s_i s_k = 2 acc - csum (see site_update_g), i.e. E16.
+template <int L, int M>
+__device__ uint32_t tile_energy_rows(const TileCtx& c, const unsigned long long* rowj,
+                                     uint32_t part, uint32_t nparts) {
+  constexpr uint32_t ROWS = L * L;
+  uint32_t U = 0;
+  for (uint32_t rho = part; rho < ROWS; rho += nparts) {
+    const RowAddr a = row_addr<L, M>(c, rowj, 0u, __builtin_amdgcn_readfirstlane(rho));
+    tile_energy_row<L, M, 0>(c, a, U);
   }
   return U;
 }
@@ -523,10 +596,14 @@ __global__ __launch_bounds__(256) void k_zero_acc(BatchDev B, Group G) {
   const Member m = member_of(G);
   const DevPop& P = B.pops[m.pop];
   if (P.sc->dead) return;
-  for (uint32_t i = threadIdx.x; i < P.n_levels; i += blockDim.x) P.hist[i] = 0;
+  // kModelGauss16: the host clears the occupied window once it is known
+  if (P.model != kModelGauss16)
+    for (uint32_t i = threadIdx.x; i < P.n_levels; i += blockDim.x) P.hist[i] = 0;
   if (threadIdx.x == 0) {
     P.sc->sum_eta2 = 0;
     P.sc->n_families = 0;
+    P.sc->E_lo = 0x7FFFFFFF;
+    P.sc->E_hi = (int32_t)0x80000000;
   }
 }
 
@@ -573,6 +650,58 @@ __device__ uint32_t block_compact_pos(bool flag, uint32_t* wcount, uint32_t* tot
   }
   *total = tot;
   return off + below;
+}
+
+// kModelGauss16: lowest and highest E16 of the population (block reduction,
+// then one atomic per workgroup).
+__global__ __launch_bounds__(256) void k_minmax(BatchDev B, Group G, uint32_t post) {
+  __shared__ int32_t smin[256 / kWave], smax[256 / kWave];
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  const PopStep sp = step_of(B, m.pop);
+  const uint32_t* U = pick(P.U, post ? sp.cur ^ 1u : sp.cur);
+  const uint32_t R = P.sc->R_tilde;
+  const uint32_t i = m.lb * 256 + threadIdx.x;
+  int32_t lo = 0x7FFFFFFF, hi = (int32_t)0x80000000;
+  if (i < R) lo = hi = (int32_t)U[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off, kWave));
+    hi = max(hi, __shfl_xor(hi, off, kWave));
+  }
+  const uint32_t wid = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    smin[wid] = lo;
+    smax[wid] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256 / kWave; ++w) {
+      lo = min(lo, smin[w]);
+      hi = max(hi, smax[w]);
+    }
+    if (m.lb * 256 < R) {
+      atomicMin(&P.sc->E_lo, lo);
+      atomicMax(&P.sc->E_hi, hi);
+    }
+  }
+}
+
+// kModelGauss16: h[E16 - E_lo] over the occupied window (cleared beforehand).
+__global__ __launch_bounds__(256) void k_hist_window(BatchDev B, Group G, uint32_t post) {
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  const PopStep sp = step_of(B, m.pop);
+  const uint32_t* U = pick(P.U, post ? sp.cur ^ 1u : sp.cur);
+  const uint32_t R = P.sc->R_tilde;
+  const int32_t lo = P.sc->E_lo;
+  const uint32_t i = m.lb * 256 + threadIdx.x;
+  if (i < R) {
+    const int32_t lev = (int32_t)U[i] - lo;
+    if (lev >= 0 && (uint32_t)lev < P.n_levels) atomicAdd(&P.hist[lev], 1u);
+  }
 }
 
 // Resampling table on the device (Sec. II, Eqs. 1-2), the same arithmetic as
@@ -733,7 +862,9 @@ __global__ __launch_bounds__(kBlockCounts) void k_counts(BatchDev B, Group G) {
   const uint32_t i = m.lb * kBlockCounts + threadIdx.x;
   uint32_t n = 0, culled = 0;
   if (i < R) {
-    const uint32_t u = min(U[i], P.n_levels - 1);
+    // energy level of the replica: U (kModelPm) or E16 - E_lo (kModelGauss16)
+    const uint32_t lev = P.model == kModelGauss16 ? U[i] - (uint32_t)P.sc->E_lo : U[i];
+    const uint32_t u = min(lev, P.n_levels - 1);
     const Words4 w = philox10(i, sp.step, 0u, kTagRes, (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
     const unsigned long long u53 = ((unsigned long long)w.w[0] << 21) | (w.w[1] >> 11);
     n = P.table_fl[u] + (u53 < P.table_T[u] ? 1u : 0u);
@@ -818,15 +949,18 @@ __global__ __launch_bounds__(kBlockCounts) void k_scatter(BatchDev B, Group G) {
 // of each tile by the same factor.
 //
 // Register budget: as many waves per SIMD as fit without spilling to scratch
-// memory (eight up to L = 10, seven at L = 12, six above).
-template <int L>
+// memory (+-J: eight up to L = 10, seven at L = 12, six above; quantised
+// Gaussian couplings, whose update holds six coupling values: seven up to
+// L = 8, six at 10, five at 12 and 14, four at 16).
+template <int L, int M>
 constexpr int sweep_min_waves_per_eu() {
+  if constexpr (M == (int)kModelGauss16) return L <= 8 ? 7 : L == 10 ? 6 : L <= 14 ? 5 : 4;
   return L <= 10 ? 8 : L == 12 ? 7 : 6;
 }
 
-template <int LAYOUT, int L, int SPLIT>
+template <int LAYOUT, int L, int SPLIT, int M>
 __global__ __launch_bounds__(64 * SPLIT)
-__attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L>()))) void k_sweep(BatchDev B,
+__attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_sweep(BatchDev B,
                                                                                 Group G) {
   constexpr uint32_t N = L * L * L;
   __shared__ unsigned long long thr_of_nu[8];  // first LDS object: address 0 (see site_update)
@@ -862,6 +996,12 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L>()))) void k_sweep(B
                              : threadIdx.x == 2 ? sp.thr[0]
                                                 : (1ull << 32);
   uint32_t* const lds = lds_all;
+  // kModelGauss16: the dE16 threshold table, after the tile image and the
+  // per-replica reduction area (visible after the gather's barrier)
+  unsigned long long* const gtab = reinterpret_cast<unsigned long long*>(lds_all + 2 * N + 64 * SPLIT);
+  if constexpr (M == (int)kModelGauss16) {
+    for (uint32_t i = threadIdx.x; i <= (uint32_t)kGaussDEMax; i += 64 * SPLIT) gtab[i] = P.gthr[i];
+  }
   const uint32_t j = tile * 64 + lane;
   const bool valid = j < Rs;
   const uint32_t src = valid ? (sp.gather ? P.src[j] : j) : 0u;
@@ -872,23 +1012,28 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L>()))) void k_sweep(B
   c.hoff = 4u * (lane >> 5);
   c.pos = lane & 31u;
   c.ph.init(j, (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
-  // a draw matters only for a class whose threshold is neither 0 nor 2^32
+  // A draw matters only for a class whose threshold is neither 0 nor 2^32.
+  // (kModelGauss16: the host passes the table's dE16 = 2 entry in thr[0], the
+  // largest threshold of a positive move, and 0 in thr[1], thr[2].)
   c.any_draw = (sp.thr[0] != 0 && sp.thr[0] < (1ull << 32)) ||
                (sp.thr[1] != 0 && sp.thr[1] < (1ull << 32)) ||
                (sp.thr[2] != 0 && sp.thr[2] < (1ull << 32));
+  c.rowk = P.rowk;
+  c.rowk_stride = P.rowk_stride;
+  c.gtab = gtab;
   const unsigned long long* rowj = P.rowj;
   uint32_t U;
   if (sp.n_sweeps == 0) {
-    U = tile_energy_rows<L>(c, rowj, part, SPLIT);
+    U = tile_energy_rows<L, M>(c, rowj, part, SPLIT);
   } else {
     for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
       c.t = sp.t0 + s;
-      sweep_colour_blocks<L, false>(c, rowj, 0u, part, SPLIT);
-      sweep_colour_blocks<L, false>(c, rowj, 1u, part, SPLIT);
+      sweep_colour_blocks<L, M, false>(c, rowj, 0u, part, SPLIT);
+      sweep_colour_blocks<L, M, false>(c, rowj, 1u, part, SPLIT);
     }
     c.t = sp.t0 + sp.n_sweeps - 1;
-    sweep_colour_blocks<L, false>(c, rowj, 0u, part, SPLIT);
-    U = sweep_colour_blocks<L, true>(c, rowj, 1u, part, SPLIT);
+    sweep_colour_blocks<L, M, false>(c, rowj, 0u, part, SPLIT);
+    U = sweep_colour_blocks<L, M, true>(c, rowj, 1u, part, SPLIT);
   }
   // Epilogue.  The lane number, the slot, its source and the descriptor
   // fields are formed or read again here rather than held in registers
@@ -917,8 +1062,9 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L>()))) void k_sweep(B
   }
 }
 
-// U recomputed from the stored spins of buffer cur (after an import).
-template <int LAYOUT, int L>
+// The energy word recomputed from the stored spins of buffer cur (after an
+// import; for kModelGauss16 also after the initial spins are drawn).
+template <int LAYOUT, int L, int M>
 __global__ __launch_bounds__(64) void k_energy(BatchDev B, Group G) {
   constexpr uint32_t N = L * L * L;
   extern __shared__ uint32_t lds[];
@@ -936,7 +1082,9 @@ __global__ __launch_bounds__(64) void k_energy(BatchDev B, Group G) {
   c.lds = lds;
   c.hoff = 4u * (lane >> 5);
   c.pos = lane & 31u;
-  const uint32_t U = tile_energy_rows<L>(c, P.rowj, 0u, 1u);
+  c.rowk = P.rowk;
+  c.rowk_stride = P.rowk_stride;
+  const uint32_t U = tile_energy_rows<L, M>(c, P.rowj, 0u, 1u);
   if (valid) pick(P.U, sp.cur)[j] = U;
 }
 
@@ -1095,6 +1243,18 @@ hipError_t launch_hist(const BatchDev& B, const Group& g, uint32_t max_levels, b
   return hipGetLastError();
 }
 
+hipError_t launch_minmax(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_minmax, dim3(g.blocks), dim3(256), 0, stream, B, g, 0u);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_window(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_hist_window, dim3(g.blocks), dim3(256), 0, stream, B, g, 0u);
+  return hipGetLastError();
+}
+
 hipError_t launch_table(const BatchDev& B, const Group& g, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
   hipLaunchKernelGGL(k_table, dim3(g.blocks), dim3(kTableBlock), 0, stream, B, g);
@@ -1120,46 +1280,64 @@ hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream)
 }
 
 template <int LAYOUT, int L>
-void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, hipStream_t stream) {
-  const size_t lds = (size_t)L * L * L * 8 + 4 * 64 * split;
-  if (split == 8)
-    hipLaunchKernelGGL((k_sweep<LAYOUT, L, 8>), dim3(g.blocks), dim3(64 * 8), lds, stream, B, g);
-  else
-    hipLaunchKernelGGL((k_sweep<LAYOUT, L, 4>), dim3(g.blocks), dim3(64 * 4), lds, stream, B, g);
+void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t model,
+                    hipStream_t stream) {
+  const size_t gbytes = model == kModelGauss16 ? (size_t)(kGaussDEMax + 1) * 8 : 0;
+  const size_t lds = (size_t)L * L * L * 8 + 4 * 64 * split + gbytes;
+  if (model == kModelGauss16) {
+    if (split == 8)
+      hipLaunchKernelGGL((k_sweep<LAYOUT, L, 8, kModelGauss16>), dim3(g.blocks), dim3(64 * 8), lds,
+                         stream, B, g);
+    else
+      hipLaunchKernelGGL((k_sweep<LAYOUT, L, 4, kModelGauss16>), dim3(g.blocks), dim3(64 * 4), lds,
+                         stream, B, g);
+  } else {
+    if (split == 8)
+      hipLaunchKernelGGL((k_sweep<LAYOUT, L, 8, kModelPm>), dim3(g.blocks), dim3(64 * 8), lds,
+                         stream, B, g);
+    else
+      hipLaunchKernelGGL((k_sweep<LAYOUT, L, 4, kModelPm>), dim3(g.blocks), dim3(64 * 4), lds,
+                         stream, B, g);
+  }
 }
 
 template <int LAYOUT, int L>
-void launch_energy_l(const BatchDev& B, const Group& g, hipStream_t stream) {
+void launch_energy_l(const BatchDev& B, const Group& g, uint32_t model, hipStream_t stream) {
   const size_t lds = (size_t)L * L * L * 8;
-  hipLaunchKernelGGL((k_energy<LAYOUT, L>), dim3(g.blocks), dim3(64), lds, stream, B, g);
+  if (model == kModelGauss16)
+    hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelGauss16>), dim3(g.blocks), dim3(64), lds, stream,
+                       B, g);
+  else
+    hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelPm>), dim3(g.blocks), dim3(64), lds, stream, B,
+                       g);
 }
 
 #define PA_L_SWITCH(FN, LAYOUT)      \
   switch (L) {                       \
-    case 4: FN<LAYOUT, 4>(B, g, stream); break;   \
-    case 6: FN<LAYOUT, 6>(B, g, stream); break;   \
-    case 8: FN<LAYOUT, 8>(B, g, stream); break;   \
-    case 10: FN<LAYOUT, 10>(B, g, stream); break; \
-    case 12: FN<LAYOUT, 12>(B, g, stream); break; \
-    case 14: FN<LAYOUT, 14>(B, g, stream); break; \
-    case 16: FN<LAYOUT, 16>(B, g, stream); break; \
+    case 4: FN<LAYOUT, 4>(B, g, model, stream); break;   \
+    case 6: FN<LAYOUT, 6>(B, g, model, stream); break;   \
+    case 8: FN<LAYOUT, 8>(B, g, model, stream); break;   \
+    case 10: FN<LAYOUT, 10>(B, g, model, stream); break; \
+    case 12: FN<LAYOUT, 12>(B, g, model, stream); break; \
+    case 14: FN<LAYOUT, 14>(B, g, model, stream); break; \
+    case 16: FN<LAYOUT, 16>(B, g, model, stream); break; \
     default: return hipErrorInvalidValue;         \
   }
 
 #define PA_L_SWITCH_S(FN, LAYOUT)                        \
   switch (L) {                                           \
-    case 4: FN<LAYOUT, 4>(B, g, split, stream); break;   \
-    case 6: FN<LAYOUT, 6>(B, g, split, stream); break;   \
-    case 8: FN<LAYOUT, 8>(B, g, split, stream); break;   \
-    case 10: FN<LAYOUT, 10>(B, g, split, stream); break; \
-    case 12: FN<LAYOUT, 12>(B, g, split, stream); break; \
-    case 14: FN<LAYOUT, 14>(B, g, split, stream); break; \
-    case 16: FN<LAYOUT, 16>(B, g, split, stream); break; \
+    case 4: FN<LAYOUT, 4>(B, g, split, model, stream); break;   \
+    case 6: FN<LAYOUT, 6>(B, g, split, model, stream); break;   \
+    case 8: FN<LAYOUT, 8>(B, g, split, model, stream); break;   \
+    case 10: FN<LAYOUT, 10>(B, g, split, model, stream); break; \
+    case 12: FN<LAYOUT, 12>(B, g, split, model, stream); break; \
+    case 14: FN<LAYOUT, 14>(B, g, split, model, stream); break; \
+    case 16: FN<LAYOUT, 16>(B, g, split, model, stream); break; \
     default: return hipErrorInvalidValue;                \
   }
 
 hipError_t launch_sweep(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
-                        uint32_t split, hipStream_t stream) {
+                        uint32_t split, uint32_t model, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
   if (split != 4 && split != 8) return hipErrorInvalidValue;
   if (layout == 2) {
@@ -1171,7 +1349,7 @@ hipError_t launch_sweep(const BatchDev& B, const Group& g, uint32_t layout, uint
 }
 
 hipError_t launch_energy(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
-                         hipStream_t stream) {
+                         uint32_t model, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
   if (layout == 2) {
     PA_L_SWITCH(launch_energy_l, 2)

@@ -129,6 +129,7 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
     if (!in) return PA_EINVAL;
     if (in->failed || in->in_batch || in->pending_gather) return PA_ESTATE;
     if (in->stream != s->stream || in->dev.L > s->max_L) return PA_EINVAL;
+    if (in->dev.model != pa::kModelPm) return PA_EINVAL;  // exp rows cover U levels only
     if (!std::isfinite(beta_next[p])) return PA_EINVAL;
     if (in->sweeps + n_sweeps[p] > 0xFFFFFFFFull) return PA_EINVAL;  // 32-bit sweep counter
     for (uint32_t q = 0; q < p; ++q)
@@ -215,7 +216,8 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
             pa::launch_counts(B, g_slots, st) == hipSuccess &&
             pa::launch_scan(B, g_perpop, st) == hipSuccess &&
             pa::launch_scatter(B, g_slots, st) == hipSuccess;
-  for (const auto& sg : g_sweep) ok = ok && pa::launch_sweep(B, sg.g, sg.layout, sg.L, sg.split, st) == hipSuccess;
+  for (const auto& sg : g_sweep) ok = ok && pa::launch_sweep(B, sg.g, sg.layout, sg.L, sg.split, pa::kModelPm, st) ==
+                                             hipSuccess;
   ok = ok && pa::launch_zero_acc(B, g_perpop, st) == hipSuccess &&
        pa::launch_hist(B, g_hist, max_levels, true, st) == hipSuccess &&
        pa::launch_family(B, g_slots, true, st) == hipSuccess &&

@@ -140,7 +140,7 @@ class GpuBackend:
         if key not in self._fp_cache:
             p = self.pam.pa_params(L=req.L, R=req.R, capacity=0,
                                    layout=self.pam.LAYOUTS[req.layout], seed=0, flags=0,
-                                   reserved=0)
+                                   model=0)
             self._fp_cache[key] = self.pam.pa_workspace_bytes(p)
         return self._fp_cache[key]
 

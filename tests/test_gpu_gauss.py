@@ -1,0 +1,218 @@
+"""GPU parity for quantised Gaussian couplings (J = k / 16, Sec. II.A draws J
+from a unit normal): the HIP library against the oracle's Gaussian path.
+
+Bit-exact on spins, E16 energies, family labels, copy counts and offsets; the
+FP64 scalars come from identical integers and operation orders, so they are
+equal.  Amey & Machta, arXiv:1711.02146: Sec. II loop, Eqs. 1-2, Eq. 9,
+Sec. III.A, Sec. III.C.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import pa_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pam():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_1711_02146_amd as m
+
+    m.lib()
+    return m
+
+
+def pair(pam, L, R, seed, layout, cseed, capacity=0):
+    K = pa_inputs.couplings_gauss16(L, cseed)
+    g = pam.Population(L, R, K, seed, capacity=capacity, layout=layout, model="gauss16")
+    o = oracle.GaussPopulation(L, K, R, seed, capacity=capacity or None)
+    return K, g, o
+
+
+def assert_state(g, o, what=""):
+    s, u, f = g.export_state()
+    assert s.shape[0] == o.R_tilde, what
+    np.testing.assert_array_equal(s.reshape(-1), o.spins, err_msg="spins " + what)
+    np.testing.assert_array_equal(u.view(np.int32), o.U, err_msg="E16 " + what)
+    np.testing.assert_array_equal(f, o.fam, err_msg="family " + what)
+
+
+def compare_obs(go, r, k):
+    for key in ("beta", "dbeta", "lnQ", "beta_F", "mean_E", "rho_t", "eps_expected"):
+        assert go[key] == getattr(r, key), (k, key, go[key], getattr(r, key))
+    for key in ("R_tilde", "E_min", "n_culled", "sum_eta2", "n_at_E_min"):
+        assert go[key] == getattr(r, key), (k, key, go[key], getattr(r, key))
+    assert go["step"] == r.k
+
+
+@pytest.mark.parametrize("layout", ["int8", "bitpack64"])
+@pytest.mark.parametrize("L,R", [(4, 1000), (6, 77), (8, 129), (10, 333), (12, 64), (16, 65)])
+def test_init_parity(pam, layout, L, R):
+    say("gauss init", layout, L, R)
+    K, g, o = pair(pam, L, R, 0x5EED0000 + L, layout, 31 + L)
+    assert_state(g, o, f"init L={L} R={R}")
+    g.close()
+
+
+@pytest.mark.parametrize("layout", ["int8", "bitpack64"])
+@pytest.mark.parametrize("beta", [0.0, 0.3, 1.0, 5.0])
+def test_sweep_parity(pam, layout, beta):
+    L, R = 8, 300
+    say("gauss sweep", layout, beta)
+    K, g, o = pair(pam, L, R, 1234, layout, 5)
+    for n in (3, 2):
+        g.sweep(beta, n)
+        o.sweep(beta, n)
+        assert_state(g, o, f"after sweeps at beta={beta}")
+    g.close()
+
+
+@pytest.mark.parametrize("layout", ["int8", "bitpack64"])
+def test_linear_run_l4_every_step(pam, layout):
+    L, R = 4, 1000
+    K, g, o = pair(pam, L, R, 77, layout, 11)
+    betas = oracle.linear_schedule(5.0, 51)
+    for k in range(1, 51):
+        g.resample(betas[k])
+        o.resample(betas[k])
+        c, off = g.export_counts()
+        np.testing.assert_array_equal(c, o.last["n"], err_msg=f"counts step {k}")
+        np.testing.assert_array_equal(off.astype(np.uint64), o.last["offsets"])
+        g.sweep(betas[k], 10)
+        o.sweep(betas[k], 10)
+        compare_obs(g.observables(), o.observables(), k)
+        if k % 10 == 0:
+            assert_state(g, o, f"step {k}")
+    g.close()
+
+
+def test_adaptive_prefix_l10_bitpack(pam):
+    L, R = 10, 2000
+    K, g, o = pair(pam, L, R, 808, "bitpack64", 12)
+    for k in range(1, 16):
+        bg = g.choose_beta(0.1, 5.0)
+        bo = o.choose_beta(0.1, 5.0)
+        assert bg == bo, (k, bg, bo)
+        g.resample(bg)
+        o.resample(bo)
+        g.sweep(bg, 10)
+        o.sweep(bo, 10)
+        compare_obs(g.observables(), o.observables(), k)
+    assert_state(g, o, "adaptive prefix")
+    g.close()
+
+
+@pytest.mark.parametrize("L,R", [(4, 140000), (6, 5000)])
+def test_sweep_forms_parity(pam, L, R):
+    K, g, o = pair(pam, L, R, 4321 + R, "bitpack64", 9 + L)
+    for b in (0.4, 0.8):
+        g.resample(b)
+        o.resample(b)
+        g.sweep(b, 2)
+        o.sweep(b, 2)
+        assert_state(g, o, f"L={L} R={R} beta={b}")
+    g.close()
+
+
+def test_two_populations_overlap(pam):
+    L, R = 8, 2000
+    K = pa_inputs.couplings_gauss16(L, 21)
+    ga = pam.Population(L, R, K, 1, model="gauss16")
+    gb = pam.Population(L, R, K, 2, model="gauss16")
+    oa = oracle.GaussPopulation(L, K, R, 1)
+    ob = oracle.GaussPopulation(L, K, R, 2)
+    betas = oracle.linear_schedule(3.0, 11)
+    for k in range(1, 11):
+        for g, o in ((ga, oa), (gb, ob)):
+            g.resample(betas[k])
+            o.resample(betas[k])
+            g.sweep(betas[k], 5)
+            o.sweep(betas[k], 5)
+        q, _ = oracle.overlap_hist(L ** 3, oa.spins, ob.spins)
+        np.testing.assert_array_equal(pam.overlap_hist(ga, gb), q)
+    ga.close()
+    gb.close()
+
+
+def test_full_size_l10_sampled_first_step(pam):
+    """L = 10, R = 2e5, bit-packed, constant culling: the first step in full
+    (table, counts, offsets, labels) and 192 sampled replicas swept by the oracle."""
+    L, R = 10, 200000
+    N = L ** 3
+    K = pa_inputs.couplings_gauss16(L, 3)
+    g = pam.Population(L, R, K, 42, layout="bitpack64", model="gauss16")
+    o = oracle.GaussPopulation(L, K, R, 42)
+    s, u, f = g.export_state()
+    np.testing.assert_array_equal(s.reshape(-1), o.spins)
+    np.testing.assert_array_equal(u.view(np.int32), o.U)
+    del s
+    bg = g.choose_beta(0.1, 5.0)
+    bo = o.choose_beta(0.1, 5.0)
+    assert bg == bo
+    g.resample(bg)
+    o.resample(bo)
+    n = o.last["n"]
+    c, off = g.export_counts()
+    np.testing.assert_array_equal(c, n)
+    np.testing.assert_array_equal(off.astype(np.uint64), o.last["offsets"])
+    Rn = int(n.sum())
+    g.sweep(bg, 10)
+    s2, u2, f2 = g.export_state()
+    assert s2.shape[0] == Rn
+    np.testing.assert_array_equal(f2, o.fam)
+    rng = np.random.default_rng(7)
+    pick = np.unique(np.concatenate([rng.integers(0, Rn, 192), [0, Rn - 1]]))
+    sp = o.spins.reshape(Rn, N)[pick].copy()
+    E = o.U[pick].copy()
+    oracle.g_sweep_slots(L, K, sp, E, pick.astype(np.uint32), o.seed, bo, 0, 10)
+    np.testing.assert_array_equal(s2[pick], sp)
+    np.testing.assert_array_equal(u2[pick].view(np.int32), E)
+    np.testing.assert_array_equal(u2.view(np.int32), oracle.g_energy(L, K, s2))
+    assert g.observables()["R_tilde"] == Rn
+    g.close()
+
+
+def test_gauss_rejected_by_batches_and_steppers(pam):
+    import torch
+
+    stream = torch.cuda.Stream()
+    K = pa_inputs.couplings_gauss16(4, 1)
+    g = pam.Population(4, 300, K, 1, model="gauss16", stream=stream)
+    st = pam.Stepper(2, 4, stream)
+    with pytest.raises(pam.PAError) as e:
+        st.step([g], [0.1], [1])
+    assert e.value.status == pam.PA_EINVAL
+    with pytest.raises(pam.PAError) as e:
+        pam.Batch([g], [0.0, 0.1], 1)
+    assert e.value.status == pam.PA_EINVAL
+    # out-of-range couplings are refused
+    with pytest.raises(pam.PAError):
+        pam.Population(4, 300, np.full(192, -128, np.int8), 1, model="gauss16")
+    st.close()
+    g.close()
+
+
+def test_import_state_roundtrip(pam):
+    """A state built by the oracle, imported (E16 recomputed on the GPU), swept on both sides."""
+    L, R = 8, 200
+    K = pa_inputs.couplings_gauss16(L, 12)
+    o = oracle.GaussPopulation(L, K, R, 4242)
+    o.sweep(0.7, 3)
+    g = pam.Population(L, R, K, 4242, layout="bitpack64", model="gauss16")
+    g.import_state(o.spins.reshape(R, -1), o.fam, o.t, o.k, o.beta, o.sum_lnQ)
+    assert_state(g, o, "imported")
+    g.sweep(0.9, 2)
+    o.sweep(0.9, 2)
+    assert_state(g, o, "imported + swept")
+    g.close()
