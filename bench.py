@@ -27,7 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = dict(name="L10_R500k_bitpack64_adaptive_eps0.1", L=10, R=500000, eps=0.1,
-                beta_max=5.0, n_sweeps=10, layout="bitpack64")
+                beta_max=5.0, n_sweeps=10, layout="bitpack64", model="pm")
+# The same anneal with Gaussian couplings quantised to 1/16 (reported beside
+# the main line, not as its value).
+GAUSS_WORKLOAD = dict(name="L10_R500k_bitpack64_gauss16_adaptive_eps0.1", L=10, R=500000,
+                      eps=0.1, beta_max=5.0, n_sweeps=10, layout="bitpack64", model="gauss16")
 
 # Peak figures of one MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz
 # retire 39.3e12 full-rate 32-bit VALU lane-operations per second; HBM3E 8 TB/s.
@@ -41,6 +45,12 @@ HBM_PEAK_GBS = 8000.0
 #   Metropolis test: 6 bond products s_i J_ij s_j (XOR), 5 adds for the local
 #   field, 1 table select of the threshold, 2 for the 64-bit compare, 1 flip = 15.
 OPS_PER_ATTEMPT = 15 + 15
+# With couplings k = 16 J (Gaussian, quantised): 6 XOR and 6 bit extracts for
+# the bonds that disagree, 6 multiply-adds for their coupling sum, 1 for
+# dE16 = 2 sum k - 4 acc, 1 clamp, 2 for the threshold-table address and LDS
+# read, 2 for the 64-bit compare, 1 flip = 25 (the row's couplings are uniform
+# over a wave's lanes, so they cost no lane operations).
+OPS_PER_ATTEMPT_GAUSS = 15 + 25
 # Algorithmic HBM bytes of one sweep launch: the bit-packed population read and
 # written once (N bits per replica each way) plus 20 B per replica (source index,
 # energy and family label read, energy and family label written).
@@ -78,6 +88,8 @@ def parse():
     ap.add_argument("--serve-lockstep", action="store_true",
                     help="step every resident request on every tick (no work-fair selection)")
     ap.add_argument("--workload", default="c3")
+    ap.add_argument("--gauss-steps", type=int, default=300,
+                    help="timed steps of the Gaussian-coupling anneal (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (used to "
                          "scale the HBM byte counters of a profiler run)")
@@ -107,7 +119,8 @@ def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None):
         if pop is None or pop_beta >= w["beta_max"]:
             if pop is not None:
                 pop.close()
-            pop = pam.Population(w["L"], w["R"], J, seed0 + gen, layout=w["layout"])
+            pop = pam.Population(w["L"], w["R"], J, seed0 + gen, layout=w["layout"],
+                                 model=w["model"])
             pop_beta = 0.0
             gen += 1
         b = pop.choose_beta(w["eps"], w["beta_max"])
@@ -288,6 +301,84 @@ def serving_bench(duration_s: float, max_active: int | None = None, rate: float 
     }
 
 
+def sweep_roofline(w, events, ops_per_attempt):
+    """Average sweep launch of a timed run against the VALU peak."""
+    sweep_ms = [e0.elapsed_time(e1) for e0, e1, _ in events]
+    sweep_att = sum(w["n_sweeps"] * w["L"] ** 3 * r for _, _, r in events)
+    n_launch = len(sweep_ms)
+    avg_ms = sum(sweep_ms) / n_launch
+    avg_att = sweep_att / n_launch
+    achieved_ops = ops_per_attempt * avg_att / (avg_ms * 1e-3)
+    avg_R = avg_att / (w["n_sweeps"] * w["L"] ** 3)
+    bytes_per_launch = 2 * avg_R * w["L"] ** 3 / 8 + BYTES_PER_REPLICA_FIXED * avg_R
+    return dict(sweep_ms=sweep_ms, avg_ms=avg_ms, avg_att=avg_att, n_launch=n_launch,
+                achieved_ops=achieved_ops, bytes_per_launch=bytes_per_launch)
+
+
+def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
+    """The benchmark anneal with quantised Gaussian couplings (k = 16 J)."""
+    import torch
+
+    import pa_inputs
+
+    w = GAUSS_WORKLOAD
+    K = pa_inputs.couplings_gauss16(w["L"], pa_inputs.coupling_seed(3, 0))
+    seed0 = pa_inputs.population_seed(3, 0, 0)
+    tune = None
+    if autotune:
+        tp = pam.Population(w["L"], w["R"], K, seed0 + 999, layout=w["layout"], model=w["model"])
+        tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=5)
+        tp.close()
+    run_steps(pam, K, w, warmup, seed0 + 1000)
+    events, stats = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    attempts = run_steps(pam, K, w, steps, seed0, events, stats)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r = sweep_roofline(w, events, OPS_PER_ATTEMPT_GAUSS)
+    return {
+        "workload": w["name"], "couplings": "Gaussian N(0,1) rounded to 1/16, |k| <= 127",
+        "value": attempts / wall, "unit": "attempts/s", "steps": steps, "warmup": warmup,
+        "ms_per_step": 1e3 * wall / steps,
+        "sweep": {"kernel": "k_sweep<bitpack64, L=10, gauss16> (gather + 10 sweeps + energy)",
+                  "avg_launch_ms": r["avg_ms"], "launches": r["n_launch"],
+                  "attempts_per_launch": r["avg_att"],
+                  "sweep_attempts_per_s": r["avg_att"] / (r["avg_ms"] * 1e-3),
+                  "achieved": r["achieved_ops"] / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                  "unit": "Tops/s", "frac": r["achieved_ops"] / VALU_PEAK_OPS,
+                  "ops_per_attempt": OPS_PER_ATTEMPT_GAUSS,
+                  "hbm_algorithmic_GBs": r["bytes_per_launch"] / (r["avg_ms"] * 1e-3) / 1e9},
+        "sweep_fraction_of_wall": sum(r["sweep_ms"]) * 1e-3 / wall,
+        "autotune": tune,
+        "beta_reached": stats[-1][0] if stats else None,
+    }
+
+
+def gauss_cpu_baseline(w, R_sample=100000):
+    """The oracle on one full temperature step of the Gaussian-coupling
+    workload at a fifth of its population (same L, couplings and culling)."""
+    import oracle
+    import pa_inputs
+
+    oracle.build(force=False)
+    K = pa_inputs.couplings_gauss16(w["L"], pa_inputs.coupling_seed(3, 0))
+    t0 = time.perf_counter()
+    p = oracle.GaussPopulation(w["L"], K, R_sample, pa_inputs.population_seed(3, 0, 0))
+    b = p.choose_beta(w["eps"], w["beta_max"])
+    p.resample(b)
+    p.sweep(b, w["n_sweeps"])
+    p.observables()
+    t1 = time.perf_counter()
+    att = w["n_sweeps"] * w["L"] ** 3 * p.R_tilde
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": att / (t1 - t0), "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"one temperature step (init + bisection + resample + {w['n_sweeps']} "
+                      f"sweeps over R~={p.R_tilde} replicas) of the Gaussian workload at "
+                      f"R={R_sample}",
+            "seconds": round(t1 - t0, 2)}
+
+
 def kernel_src_sha256():
     import hashlib
 
@@ -363,14 +454,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    sweep_ms = [e0.elapsed_time(e1) for e0, e1, _ in events]
-    sweep_att = sum(w["n_sweeps"] * w["L"] ** 3 * r for _, _, r in events)
-    n_launch = len(sweep_ms)
-    avg_ms = sum(sweep_ms) / n_launch
-    avg_att = sweep_att / n_launch
-    achieved_ops = OPS_PER_ATTEMPT * avg_att / (avg_ms * 1e-3)
-    avg_R = avg_att / (w["n_sweeps"] * w["L"] ** 3)
-    bytes_per_launch = 2 * avg_R * w["L"] ** 3 / 8 + BYTES_PER_REPLICA_FIXED * avg_R
+    r = sweep_roofline(w, events, OPS_PER_ATTEMPT)
+    sweep_ms, avg_ms, avg_att, n_launch = r["sweep_ms"], r["avg_ms"], r["avg_att"], r["n_launch"]
+    achieved_ops, bytes_per_launch = r["achieved_ops"], r["bytes_per_launch"]
     traffic = None
     if TRAFFIC is not None and TRAFFIC["kernel_src_sha256"] == kernel_src_sha256():
         traffic = TRAFFIC["bytes_per_launch"]
@@ -412,6 +498,9 @@ def main():
         "autotune": tune,
         "beta_reached": stats[-1][0] if stats else None,
     }
+    if args.gauss_steps > 0:
+        print(f"# Gaussian couplings: {args.gauss_steps} steps", file=sys.stderr, flush=True)
+        line["gauss16"] = gauss_bench(pam, args.gauss_steps, args.warmup, not args.no_autotune)
     if not args.no_batched:
         print("# batched: 256 instances, one graph per step; back-to-back sample", file=sys.stderr,
               flush=True)
@@ -423,6 +512,8 @@ def main():
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, one step)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)
+        if "gauss16" in line:
+            line["gauss16"]["cpu_baseline"] = gauss_cpu_baseline(GAUSS_WORKLOAD)
     print(json.dumps(line), flush=True)
 
 

@@ -266,9 +266,9 @@ int pa_stepper_free(pa_stepper* s);
 
 /* Time n_sweeps-sweep launches of both forms on the instance (repeats times
  * each, at inverse temperature beta >= 0: the regime the caller will run in;
- * at beta = 0 no draw is made) and remember the faster for launches of the same spin
- * layout, L and size class (floor(log2(tiles))), in this process, for single
- * instances, batches and steppers alike.  The population, its counters and
+ * at beta = 0 no draw is made) and remember the faster for launches of the same
+ * coupling model, spin layout, L and size class (floor(log2(tiles))), in this
+ * process, for single instances, batches and steppers alike.  The population, its counters and
  * its results are not changed (the trial sweeps write only the spare buffer).
  * split_out (nullable): the chosen waves per tile; ms_out (nullable, 2
  * floats): average launch time of the 4- and 8-wave forms.  Needs no pending

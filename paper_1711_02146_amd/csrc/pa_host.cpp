@@ -288,8 +288,8 @@ pa::PopStep plain_step(uint32_t cur) {
 // Sweep launch of one instance (its size after any pending copy sets the
 // waves per tile).
 hipError_t launch_sweep_of(pa_instance* in, const pa::PopStep& ps) {
-  const uint32_t split =
-      pa::sweep_split_for(in->dev.layout, in->dev.L, ((uint64_t)in->R_tilde + 63) / 64);
+  const uint32_t split = pa::sweep_split_for(in->dev.model, in->dev.layout, in->dev.L,
+                                             ((uint64_t)in->R_tilde + 63) / 64);
   return pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
                           in->dev.layout, in->dev.L, split, in->dev.model, in->stream);
 }
@@ -873,7 +873,7 @@ int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t 
   (void)hipEventDestroy(e1);
   if (rc != PA_OK) return rc;
   const uint32_t best = ms[1] < ms[0] ? cand[1] : cand[0];
-  pa::sweep_split_record(in->dev.layout, in->dev.L, tiles, best);
+  pa::sweep_split_record(in->dev.model, in->dev.layout, in->dev.L, tiles, best);
   if (split_out) *split_out = best;
   if (ms_out) {
     ms_out[0] = ms[0];

@@ -193,9 +193,10 @@ inline uint32_t blocks_sweep(uint32_t capacity) { return (capacity / 64 + 7) / 8
 inline uint32_t sweep_split_default(uint32_t L, uint64_t tiles) {
   return (L >= 14 || (L >= 6 && tiles < 2048)) ? 8u : 4u;
 }
-// The split a launch uses: the autotuner's choice for (layout, L, size class
-// of `tiles`) when one was measured in this process, else the default (pa_tune.cpp).
-uint32_t sweep_split_for(uint32_t layout, uint32_t L, uint64_t tiles);
-void sweep_split_record(uint32_t layout, uint32_t L, uint64_t tiles, uint32_t split);
+// The split a launch uses: the autotuner's choice for (model, layout, L, size
+// class of `tiles`) when one was measured in this process, else the default (pa_tune.cpp).
+uint32_t sweep_split_for(uint32_t model, uint32_t layout, uint32_t L, uint64_t tiles);
+void sweep_split_record(uint32_t model, uint32_t layout, uint32_t L, uint64_t tiles,
+                        uint32_t split);
 
 }  // namespace pa

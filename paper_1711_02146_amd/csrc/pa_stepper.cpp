@@ -188,7 +188,8 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
   for (const auto& kv : by_kind) {
     uint64_t tiles = 0;
     for (uint32_t p : kv.second) tiles += (pops[p]->dev.R + 63) / 64;
-    const uint32_t split = pa::sweep_split_for(kv.first.first, kv.first.second, tiles);
+    const uint32_t split =
+        pa::sweep_split_for(pa::kModelPm, kv.first.first, kv.first.second, tiles);
     std::vector<uint32_t> nb;
     for (uint32_t p : kv.second) nb.push_back(pa::blocks_sweep(pops[p]->dev.capacity));
     g_sweep.push_back({kv.first.first, kv.first.second, split, gt.add(kv.second, nb)});

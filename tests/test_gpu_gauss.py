@@ -216,3 +216,46 @@ def test_import_state_roundtrip(pam):
     o.sweep(0.9, 2)
     assert_state(g, o, "imported + swept")
     g.close()
+
+
+def test_full_anneal_l10_r500k(pam):
+    """The benchmark anneal with Gaussian couplings, every step (~300) checked
+    against properties that hold at any size, the final population against the
+    oracle's energies on sampled replicas and in full against its own spins."""
+    import math
+
+    L, R, eps, bmax = 10, 500000, 0.1, 5.0
+    N = L ** 3
+    K = pa_inputs.couplings_gauss16(L, pa_inputs.coupling_seed(3, 0))
+    bound = int(np.abs(K.astype(np.int64)).sum())          # |E16| <= sum |k|
+    g = pam.Population(L, R, K, pa_inputs.population_seed(3, 0, 0), layout="bitpack64",
+                       model="gauss16")
+    prev = g.observables()
+    steps = 0
+    while prev["beta"] < bmax:
+        b = g.choose_beta(eps, bmax)
+        g.resample(b)
+        g.sweep(b, 10)
+        o = g.observables()
+        assert 0 < o["R_tilde"] and abs(o["R_tilde"] - R) <= 16 * math.isqrt(R) + 256
+        assert o["rho_t"] >= 1.0 - 1e-12 and o["sum_eta2"] >= o["R_tilde"]
+        assert -bound <= o["E_min"] <= bound
+        assert o["E_min"] / 16.0 <= o["mean_E"] + 1e-9
+        assert 1 <= o["n_at_E_min"] <= o["R_tilde"]
+        assert o["step"] == prev["step"] + 1 and o["beta"] > prev["beta"]
+        if b < bmax:
+            assert o["eps_expected"] <= eps + 1e-12
+        steps += 1
+        prev = o
+    say("gauss anneal steps", steps, prev)
+    assert prev["beta"] == bmax and 50 < steps < 5000
+    s, u, f = g.export_state()
+    E = u.view(np.int32)
+    assert np.all(np.diff(f.astype(np.int64)) >= 0)
+    idx = np.sort(np.random.default_rng(5).choice(s.shape[0], 512, replace=False))
+    np.testing.assert_array_equal(E[idx], oracle.g_energy(L, K, s[idx]))
+    assert prev["mean_E"] == E.astype(np.int64).sum() / E.size / 16.0
+    assert prev["E_min"] == E.min() and prev["n_at_E_min"] == int(np.count_nonzero(E == E.min()))
+    # the annealed population sits far below the beta = 0 energy scale
+    assert prev["mean_E"] < -1.5 * N
+    g.close()
