@@ -1,7 +1,7 @@
 """Benchmark: population annealing at L=10, R=5e5 on one MI355X.
 
 A step is one temperature step of the constant-culling anneal (Sec. III.C of
-Amey & Machta, arXiv:1711.02146): choose beta' (bisection to a culling
+Amey & Machta, arXiv:1711.02146): choose beta' (the step solved for a culling
 fraction of 0.1), resample (histogram, FP64 table, copy counts, scan, copy
 with family labels), 10 checkerboard Metropolis sweeps at beta', observables
 (<E>, beta F, rho_t).  When the anneal reaches beta = 5 the population is
@@ -373,7 +373,7 @@ def gauss_cpu_baseline(w, R_sample=100000):
     att = w["n_sweeps"] * w["L"] ** 3 * p.R_tilde
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": att / (t1 - t0), "unit": "attempts/s", "cores": threads, "kind": "oracle",
-            "sample": f"one temperature step (init + bisection + resample + {w['n_sweeps']} "
+            "sample": f"one temperature step (init + step choice + resample + {w['n_sweeps']} "
                       f"sweeps over R~={p.R_tilde} replicas) of the Gaussian workload at "
                       f"R={R_sample}",
             "seconds": round(t1 - t0, 2)}
@@ -405,7 +405,7 @@ def cpu_baseline(w):
     att = w["n_sweeps"] * w["L"] ** 3 * p.R_tilde
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": att / (t2 - t0), "unit": "attempts/s", "cores": threads, "kind": "oracle",
-            "sample": f"one temperature step (init + bisection + resample + {w['n_sweeps']} sweeps "
+            "sample": f"one temperature step (init + step choice + resample + {w['n_sweeps']} sweeps "
                       f"over R~={p.R_tilde} replicas, {att:.3g} attempts) of the same workload; "
                       f"sweeps alone {att / (t2 - t1):.3g} attempts/s",
             "seconds": round(t2 - t0, 2)}

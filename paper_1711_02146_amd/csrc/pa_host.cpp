@@ -1,5 +1,5 @@
 // pa_host.cpp -- the C ABI of libpa (include/pa.h): instance state, workspace
-// layout, the FP64 resampling table, the constant-culling bisection, and the
+// layout, the FP64 resampling table, the constant-culling step solver, and the
 // stream-ordered sequence of kernel launches of one annealing step.
 //
 // Method: Amey & Machta, arXiv:1711.02146.
@@ -633,17 +633,47 @@ int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* 
   const Levels lv = levels_of(in);
   const uint32_t nl = lv.n, R = in->dev.R;
   const uint32_t* h = in->h_hist;
-  if (culling_fraction(h, nl, lv.unit, R, 0.0) > eps_target) return PA_ESCHEDULE;
+  // g(x) = eps(x) - target; its sign is that of eps(x) - target exactly
+  auto g = [&](double x) { return culling_fraction(h, nl, lv.unit, R, x) - eps_target; };
+  double g_lo = g(0.0);
+  if (g_lo > 0.0) return PA_ESCHEDULE;
   const double rem = beta_max - in->beta;
-  if (culling_fraction(h, nl, lv.unit, R, rem) <= eps_target) {
+  double g_hi = g(rem);
+  if (g_hi <= 0.0) {
     *beta_next = beta_max;
     return PA_OK;
   }
+  // Bracket [lo, hi] with g(lo) <= 0 < g(hi), narrowed by the point where the
+  // chord meets zero; an end kept twice in a row has its stored g halved
+  // (Illinois), and after a step that leaves the bracket wider than half its
+  // width two steps before, the midpoint is taken instead.  Stops at a
+  // relative width of 2^-40; the lower end is the step.
   double lo = 0.0, hi = rem;
-  for (int it = 0; it < 64; ++it) {
-    const double mid = lo + 0.5 * (hi - lo);
-    if (culling_fraction(h, nl, lv.unit, R, mid) <= eps_target) lo = mid;
-    else hi = mid;
+  double prev = hi - lo, prev2 = hi - lo;
+  int moved = 0;  // -1: the last step moved lo, +1: it moved hi
+  bool bisect = false;
+  for (int it = 0; it < 1000 && hi - lo > 0x1p-40 * hi; ++it) {
+    double x = lo + 0.5 * (hi - lo);
+    if (!bisect) {
+      const double c = lo + (hi - lo) * (g_lo / (g_lo - g_hi));
+      if (c > lo && c < hi) x = c;
+    }
+    const double gx = g(x);
+    if (gx <= 0.0) {
+      lo = x;
+      g_lo = gx;
+      if (moved == -1) g_hi = 0.5 * g_hi;
+      moved = -1;
+    } else {
+      hi = x;
+      g_hi = gx;
+      if (moved == 1) g_lo = 0.5 * g_lo;
+      moved = 1;
+    }
+    const double width = hi - lo;
+    bisect = width > 0.5 * prev2;
+    prev2 = prev;
+    prev = width;
   }
   *beta_next = in->beta + lo;
   return PA_OK;

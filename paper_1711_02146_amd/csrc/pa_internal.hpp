@@ -57,7 +57,7 @@ struct DevScalars {
                           // 2: a kernel found its LDS layout unusable
   uint32_t n_culled;      // replicas with zero copies in the last resampling step
   unsigned long long sum_eta2;  // sum over families of eta^2
-  uint32_t n_families;    // families with eta > 0
+  uint32_t reserved;
   uint32_t dead;          // batch runs: set when a step overflowed; later steps skip it
   int32_t E_lo, E_hi;     // kModelGauss16: lowest / highest E16 of the population
   uint32_t pad[6];

@@ -263,6 +263,10 @@ struct TileCtx {
   const unsigned long long* gtab;      // LDS copy of the dE16 threshold table
 };
 
+// Read-only device memory in the constant address space (scalar loads).
+typedef const __attribute__((address_space(4))) uint32_t ConstU32;
+typedef const __attribute__((address_space(4))) unsigned long long ConstU64;
+
 struct RowAddr {
   const uint32_t* own;
   const uint32_t* x0;    // rank p of the other-colour x row
@@ -272,7 +276,7 @@ struct RowAddr {
   const uint32_t* pz;
   const uint32_t* mz;
   unsigned long long j;  // coupling bits of the row (kModelPm)
-  const uint32_t* krow;  // coupling bytes of the row, 4 per word (kModelGauss16)
+  ConstU32* krow;        // coupling bytes of the row, 4 per word (kModelGauss16)
 };
 
 template <int L, int M>
@@ -294,11 +298,14 @@ __device__ __forceinline__ RowAddr row_addr(const TileCtx& c, const unsigned lon
   a.my = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (ym + L * z)));
   a.pz = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (y + L * zp)));
   a.mz = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (y + L * zm)));
+  // The coupling words are read through the constant address space: the
+  // index is uniform and nothing in the kernel writes them, so they arrive in
+  // scalar registers and the per-bond masks and bytes are scalar work.
   if constexpr (M == (int)kModelGauss16) {
     a.j = 0;
-    a.krow = reinterpret_cast<const uint32_t*>(c.rowk + (size_t)(colour * L * L + rho) * c.rowk_stride);
+    a.krow = (const ConstU32*)(c.rowk + (size_t)(colour * L * L + rho) * c.rowk_stride);
   } else {
-    a.j = rowj[colour * L * L + rho];
+    a.j = ((const ConstU64*)rowj)[colour * L * L + rho];
     a.krow = nullptr;
   }
   return a;
@@ -364,13 +371,24 @@ __device__ __forceinline__ int32_t row_k(const RowAddr& a) {
   return (int32_t)(w << (24 - 8 * (b % 4))) >> 24;
 }
 
+// b * k + c for a 0/1 lane value b and a uniform coupling k (|k| < 2^23):
+// one v_mad_i32_i24 with k in a scalar register.
+__device__ __forceinline__ int32_t mad_i24(uint32_t b, int32_t k, int32_t c) {
+  int32_t r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(b), "s"(k), "v"(c));
+  return r;
+}
+
 // Metropolis update of one site for quantised Gaussian couplings.  With x_k =
 // [s_i != s_k] (own bit ^ neighbour bit), sum_k k_k s_i s_k = csum - 2 acc
 // where csum = sum_k k_k and acc = sum_k k_k x_k, so flipping s_i changes
-// E16 by dE = 2 csum - 4 acc.  The move is taken iff its draw is below
-// gtab[max(dE, 0)] (gtab[0] = 2^32: every move with dE <= 0 is taken).
-// With ACCUM the pass also sums the site's post-move energy
-// -sum_k k_k s_i s_k: in the colour-1 pass of the last sweep that is E16.
+// E16 by dE = 2 csum - 4 acc.  acc is formed from the neighbour bits b_k
+// alone: with m = sum_k k_k b_k, acc = m if the own bit is 0 and csum - m if
+// it is 1 (x_k = b_k or 1 - b_k), which saves the six XORs with the own word.
+// The move is taken iff its draw is below gtab[max(dE, 0)] (gtab[0] = 2^32:
+// every move with dE <= 0 is taken).  With ACCUM the pass also sums the
+// site's post-move energy -sum_k k_k s_i s_k: in the colour-1 pass of the
+// last sweep that is E16.
 template <int L, int Q, bool ACCUM>
 __device__ __forceinline__ void site_update_g(const TileCtx& c, const RowAddr& a,
                                               const SiteLoad& w, uint32_t draw, uint32_t& usum) {
@@ -378,13 +396,14 @@ __device__ __forceinline__ void site_update_g(const TileCtx& c, const RowAddr& a
   const int32_t k0 = row_k<Q, 0>(a), k1 = row_k<Q, 1>(a), k2 = row_k<Q, 2>(a);
   const int32_t k3 = row_k<Q, 3>(a), k4 = row_k<Q, 4>(a), k5 = row_k<Q, 5>(a);
   const int32_t csum = k0 + k1 + k2 + k3 + k4 + k5;
-  const int32_t x0 = (int32_t)__builtin_amdgcn_ubfe(w.nb[0] ^ w.own, c.pos, 1);
-  const int32_t x1 = (int32_t)__builtin_amdgcn_ubfe(w.nb[1] ^ w.own, c.pos, 1);
-  const int32_t x2 = (int32_t)__builtin_amdgcn_ubfe(w.nb[2] ^ w.own, c.pos, 1);
-  const int32_t x3 = (int32_t)__builtin_amdgcn_ubfe(w.nb[3] ^ w.own, c.pos, 1);
-  const int32_t x4 = (int32_t)__builtin_amdgcn_ubfe(w.nb[4] ^ w.own, c.pos, 1);
-  const int32_t x5 = (int32_t)__builtin_amdgcn_ubfe(w.nb[5] ^ w.own, c.pos, 1);
-  const int32_t acc = x0 * k0 + x1 * k1 + x2 * k2 + x3 * k3 + x4 * k4 + x5 * k5;
+  int32_t m = (int32_t)__builtin_amdgcn_ubfe(w.nb[0], c.pos, 1) * k0;
+  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[1], c.pos, 1), k1, m);
+  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[2], c.pos, 1), k2, m);
+  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[3], c.pos, 1), k3, m);
+  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[4], c.pos, 1), k4, m);
+  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[5], c.pos, 1), k5, m);
+  const bool own1 = __builtin_amdgcn_ubfe(w.own, c.pos, 1) != 0u;
+  const int32_t acc = own1 ? csum - m : m;
   const int32_t dE = 2 * csum - 4 * acc;
   const unsigned long long thr = c.gtab[dE > 0 ? dE : 0];
   const bool accept = (unsigned long long)draw < thr;
@@ -601,7 +620,6 @@ __global__ __launch_bounds__(256) void k_zero_acc(BatchDev B, Group G) {
     for (uint32_t i = threadIdx.x; i < P.n_levels; i += blockDim.x) P.hist[i] = 0;
   if (threadIdx.x == 0) {
     P.sc->sum_eta2 = 0;
-    P.sc->n_families = 0;
     P.sc->E_lo = 0x7FFFFFFF;
     P.sc->E_hi = (int32_t)0x80000000;
   }
@@ -1090,37 +1108,45 @@ __global__ __launch_bounds__(64) void k_energy(BatchDev B, Group G) {
 
 // Sum over families of eta^2 (Sec. III.A) from the family labels, which stay
 // sorted under the order-preserving copy: each run of equal labels is one
-// family; its first slot finds the run's end by binary search.
+// family.  Its first slot i finds the run's end by galloping (probes at i + 1,
+// i + 2, i + 4, ... until one leaves the run) and then bisecting the last gap,
+// so a family of eta replicas costs about 2 log2(eta) dependent loads.  Only
+// the first kFamilyBlocks workgroups of a population work (the rest leave at
+// once), each over a stride of the slots, so that few atomic adds reach the
+// population's counter.
+constexpr uint32_t kFamilyBlocks = 512;
+
 __global__ __launch_bounds__(256) void k_family(BatchDev B, Group G, uint32_t post) {
   __shared__ unsigned long long scratch[256 / kWave];
   const Member m = member_of(G);
+  if (m.lb >= kFamilyBlocks) return;
   const DevPop P = B.pops[m.pop];
   if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
   const uint32_t* fam = pick(P.fam, post ? sp.cur ^ 1u : sp.cur);
-  const uint32_t R = P.sc->R_tilde;
-  const uint32_t i = m.lb * 256 + threadIdx.x;
-  unsigned long long sq = 0, nf = 0;
-  if (i < R) {
+  const uint64_t R = P.sc->R_tilde;
+  unsigned long long sq = 0;
+  for (uint64_t i = (uint64_t)m.lb * 256 + threadIdx.x; i < R; i += (uint64_t)kFamilyBlocks * 256) {
     const uint32_t f = fam[i];
-    if (i == 0 || fam[i - 1] != f) {
-      uint32_t lo = i + 1, hi = R;  // first index in [i+1, R) with fam != f
-      while (lo < hi) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        if (fam[mid] == f) lo = mid + 1;
-        else hi = mid;
-      }
-      const unsigned long long eta = lo - i;
-      sq = eta * eta;
-      nf = 1;
+    if (i > 0 && fam[i - 1] == f) continue;
+    // [i, in) lies in the run; the run ends at or before `out`
+    uint64_t in = i + 1, out = in, step = 1;
+    while (out < R && fam[out] == f) {
+      in = out + 1;
+      step <<= 1;
+      out = i + step;
     }
+    uint64_t lo = in, hi = out < R ? out : R;
+    while (lo < hi) {  // first index in [lo, hi) with fam != f, else hi
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if (fam[mid] == f) lo = mid + 1;
+      else hi = mid;
+    }
+    const unsigned long long eta = lo - i;
+    sq += eta * eta;
   }
   const unsigned long long s = block_sum<256, unsigned long long>(sq, scratch);
-  const unsigned long long c = block_sum<256, unsigned long long>(nf, scratch);
-  if (threadIdx.x == 0) {
-    if (s) atomicAdd(&P.sc->sum_eta2, s);
-    if (c) atomicAdd(&P.sc->n_families, (uint32_t)c);
-  }
+  if (threadIdx.x == 0 && s) atomicAdd(&P.sc->sum_eta2, s);
 }
 
 // Post-step record of a batch step: integer sum of E over the population, the

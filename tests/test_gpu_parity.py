@@ -168,7 +168,7 @@ def test_two_population_overlap_l8(pam, layout):
 
 
 def test_adaptive_prefix_l10_bitpack(pam):
-    """Constant culling eps = 0.1 (bisection on dbeta), bit-packed L=10."""
+    """Constant culling eps = 0.1 (dbeta solved on a bracket), bit-packed L=10."""
     L, R = 10, 2000
     J, g, o = pair(pam, L, R, pa_inputs.population_seed(3, 0, 0), "bitpack64",
                    pa_inputs.coupling_seed(3, 0))

@@ -342,7 +342,20 @@ def test_ferromagnet_anneals_to_ground_state(oracle_lib):
 # ---------------------------------------------------------------------------
 # Families and the constant-culling schedule (Sec. III.A, III.C-III.E)
 # ---------------------------------------------------------------------------
-def test_adaptive_step_bisection_and_gaussian_estimate(oracle_lib):
+def _bisect_crossing(h, R, eps, rem):
+    """The crossing by plain bisection (64 halvings, lower end kept): an
+    independent check of the oracle's bracketed solver."""
+    lo, hi = 0.0, rem
+    for _ in range(64):
+        mid = lo + 0.5 * (hi - lo)
+        if oracle.culling_fraction(h, R, mid) <= eps:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+def test_adaptive_step_solver_and_gaussian_estimate(oracle_lib):
     p = _random_hist(6, 20000, 0.0, 4)
     h = p.histogram()
     for eps in (0.02, 0.05, 0.1):
@@ -350,6 +363,8 @@ def test_adaptive_step_bisection_and_gaussian_estimate(oracle_lib):
         assert not end
         assert oracle.culling_fraction(h, p.R, dbeta) <= eps
         assert oracle.culling_fraction(h, p.R, dbeta * (1 + 1e-9) + 1e-15) > eps
+        # the solver stops at a relative bracket width of 2^-40
+        assert dbeta == pytest.approx(_bisect_crossing(h, p.R, eps, 5.0), rel=2.0 ** -39)
         # Sec. III.C: dbeta ~ eps sqrt(2 pi) / sigma_E for small dbeta sigma_E
         E = 2.0 * np.arange(h.size) - 3 * p.N
         w = h.astype(np.float64)
@@ -360,6 +375,18 @@ def test_adaptive_step_bisection_and_gaussian_estimate(oracle_lib):
     # a range that culls less than the target is taken whole
     dbeta, end = oracle.choose_dbeta(h, p.R, 0.1, 1e-6)
     assert end and dbeta == 1e-6
+    # a late-anneal histogram with three occupied levels: eps(dbeta) flattens
+    # out and the crossing lies far from the small-step estimate
+    h3 = np.zeros(h.size, np.uint32)
+    h3[[10, 11, 13]] = [15000, 4000, 1000]
+    for eps in (0.05, 0.1, 0.2):
+        dbeta, end = oracle.choose_dbeta(h3, 20000, eps, 5.0)
+        if end:
+            assert oracle.culling_fraction(h3, 20000, 5.0) <= eps
+            continue
+        assert oracle.culling_fraction(h3, 20000, dbeta) <= eps
+        assert oracle.culling_fraction(h3, 20000, dbeta * (1 + 2.0 ** -38)) > eps
+        assert dbeta == pytest.approx(_bisect_crossing(h3, 20000, eps, 5.0), rel=2.0 ** -39)
 
 
 def test_high_temperature_family_growth(oracle_lib):
