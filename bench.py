@@ -45,12 +45,13 @@ HBM_PEAK_GBS = 8000.0
 #   Metropolis test: 6 bond products s_i J_ij s_j (XOR), 5 adds for the local
 #   field, 1 table select of the threshold, 2 for the 64-bit compare, 1 flip = 15.
 OPS_PER_ATTEMPT = 15 + 15
-# With couplings k = 16 J (Gaussian, quantised): 6 XOR and 6 bit extracts for
-# the bonds that disagree, 6 multiply-adds for their coupling sum, 1 for
-# dE16 = 2 sum k - 4 acc, 1 clamp, 2 for the threshold-table address and LDS
-# read, 2 for the 64-bit compare, 1 flip = 25 (the row's couplings are uniform
-# over a wave's lanes, so they cost no lane operations).
-OPS_PER_ATTEMPT_GAUSS = 15 + 25
+# With couplings k = 16 J (Gaussian, quantised): 6 bit extracts of the
+# neighbour spins and 6 multiply-adds for m = sum k b, 1 extract of the own
+# spin and 1 select for acc = m or sum k - m, 1 for dE16 = 2 sum k - 4 acc,
+# 1 clamp, 2 for the threshold-table address and LDS read, 2 for the 64-bit
+# compare, 1 flip = 21 (the row's couplings are uniform over a wave's lanes,
+# so sum k and the coupling bytes cost no lane operations).
+OPS_PER_ATTEMPT_GAUSS = 15 + 21
 # Algorithmic HBM bytes of one sweep launch: the bit-packed population read and
 # written once (N bits per replica each way) plus 20 B per replica (source index,
 # energy and family label read, energy and family label written).

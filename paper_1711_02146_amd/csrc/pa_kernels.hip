@@ -263,6 +263,16 @@ struct TileCtx {
   const unsigned long long* gtab;      // LDS copy of the dE16 threshold table
 };
 
+// A uniform byte offset kept whole in a scalar register.  Added to the lane's
+// LDS base it costs one vector add per row pointer; left to the compiler, a
+// constant part (the other colour's base) is split off into the access's
+// immediate offset, which does not fit the 8-bit fields of ds_read2 and costs
+// a second add per pointer.
+__device__ __forceinline__ uint32_t whole_s(uint32_t x) {
+  asm("" : "+s"(x));
+  return x;
+}
+
 // Read-only device memory in the constant address space (scalar loads).
 typedef const __attribute__((address_space(4))) uint32_t ConstU32;
 typedef const __attribute__((address_space(4))) unsigned long long ConstU64;
@@ -291,13 +301,13 @@ __device__ __forceinline__ RowAddr row_addr(const TileCtx& c, const unsigned lon
   const uint32_t ox = oth0 + H * rho;
   const char* base = reinterpret_cast<const char*>(c.lds) + c.hoff;
   RowAddr a;
-  a.own = reinterpret_cast<const uint32_t*>(base + 8 * (own0 + H * rho));
-  a.x0 = reinterpret_cast<const uint32_t*>(base + 8 * (ox + p));
-  a.wrap = reinterpret_cast<const uint32_t*>(base + 8 * (ox + (H - 1) * (1u - p)));
-  a.py = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (yp + L * z)));
-  a.my = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (ym + L * z)));
-  a.pz = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (y + L * zp)));
-  a.mz = reinterpret_cast<const uint32_t*>(base + 8 * (oth0 + H * (y + L * zm)));
+  a.own = reinterpret_cast<const uint32_t*>(base + whole_s(8 * (own0 + H * rho)));
+  a.x0 = reinterpret_cast<const uint32_t*>(base + whole_s(8 * (ox + p)));
+  a.wrap = reinterpret_cast<const uint32_t*>(base + whole_s(8 * (ox + (H - 1) * (1u - p))));
+  a.py = reinterpret_cast<const uint32_t*>(base + whole_s(8 * (oth0 + H * (yp + L * z))));
+  a.my = reinterpret_cast<const uint32_t*>(base + whole_s(8 * (oth0 + H * (ym + L * z))));
+  a.pz = reinterpret_cast<const uint32_t*>(base + whole_s(8 * (oth0 + H * (y + L * zp))));
+  a.mz = reinterpret_cast<const uint32_t*>(base + whole_s(8 * (oth0 + H * (y + L * zm))));
   // The coupling words are read through the constant address space: the
   // index is uniform and nothing in the kernel writes them, so they arrive in
   // scalar registers and the per-bond masks and bytes are scalar work.
