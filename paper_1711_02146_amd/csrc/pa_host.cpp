@@ -342,7 +342,7 @@ int fetch_hist(pa_instance* in, bool with_family) {
   PA_HIP(in, pa::launch_zero_acc(B, group_of(in, in->d_meta->perpop, 1), in->stream));
   uint32_t n = P.n_levels;
   if (P.model == pa::kModelGauss16) {
-    PA_HIP(in, pa::launch_minmax(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
+    PA_HIP(in, pa::launch_minmax(B, group_of(in, in->d_meta->hist, in->meta.hist[1]), in->stream));
     PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
     PA_HIP(in, hipStreamSynchronize(in->stream));
     const int64_t w = (int64_t)in->h_sc->E_hi - (int64_t)in->h_sc->E_lo + 1;
@@ -351,7 +351,7 @@ int fetch_hist(pa_instance* in, bool with_family) {
     in->E_lo = in->h_sc->E_lo;
     in->n_win = n;
     PA_HIP(in, pa::launch_fill_u32(P.hist, 0u, n, in->stream));
-    PA_HIP(in, pa::launch_hist_window(B, group_of(in, in->d_meta->slots, in->meta.slots[1]),
+    PA_HIP(in, pa::launch_hist_window(B, group_of(in, in->d_meta->hist, in->meta.hist[1]), n,
                                       in->stream));
   } else {
     PA_HIP(in, pa::launch_hist(B, group_of(in, in->d_meta->hist, in->meta.hist[1]), P.n_levels,

@@ -27,6 +27,7 @@ constexpr uint32_t kTagRes = 0x52455341u;   // copy-count draws
 constexpr int kWave = 64;          // wavefront width on gfx950; one spin tile = 64 replicas
 constexpr int kBlockCounts = 256;  // slots per block in the copy-count / scatter kernels
 constexpr int kHistSlots = 4096;   // slots per block of the histogram kernel
+constexpr int kWindowLdsLevels = 16384;  // largest E16 window counted in LDS (64 KiB)
 constexpr int kMaxL = 16;
 // Energy models.  kModelPm: J = +-1, the energy word of a replica is U, the
 // number of unsatisfied bonds (E = 2U - 3N).  kModelGauss16: J = k / 16 with
@@ -176,8 +177,11 @@ hipError_t launch_energy(const BatchDev& B, const Group& g, uint32_t layout, uin
 // kModelGauss16: E_lo / E_hi of every member (zero_acc resets them first) and the
 // histogram h[E16 - E_lo] (global atomics; the host clears the window first),
 // both over the current buffer of a call on single instances
+// kModelGauss16 (groups of kHistSlots slots per workgroup): the population's
+// E16 range into E_lo / E_hi, then the histogram over the n_win-level window.
 hipError_t launch_minmax(const BatchDev& B, const Group& g, hipStream_t stream);
-hipError_t launch_hist_window(const BatchDev& B, const Group& g, hipStream_t stream);
+hipError_t launch_hist_window(const BatchDev& B, const Group& g, uint32_t n_win,
+                              hipStream_t stream);
 hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream);
 
 // Blocks each population needs in each kind of launch.

@@ -680,8 +680,8 @@ __device__ uint32_t block_compact_pos(bool flag, uint32_t* wcount, uint32_t* tot
   return off + below;
 }
 
-// kModelGauss16: lowest and highest E16 of the population (block reduction,
-// then one atomic per workgroup).
+// kModelGauss16: lowest and highest E16 of the population.  Each workgroup
+// takes kHistSlots slots, reduces them, and adds one atomic min and max.
 __global__ __launch_bounds__(256) void k_minmax(BatchDev B, Group G, uint32_t post) {
   __shared__ int32_t smin[256 / kWave], smax[256 / kWave];
   const Member m = member_of(G);
@@ -690,9 +690,14 @@ __global__ __launch_bounds__(256) void k_minmax(BatchDev B, Group G, uint32_t po
   const PopStep sp = step_of(B, m.pop);
   const uint32_t* U = pick(P.U, post ? sp.cur ^ 1u : sp.cur);
   const uint32_t R = P.sc->R_tilde;
-  const uint32_t i = m.lb * 256 + threadIdx.x;
+  const uint32_t i0 = m.lb * kHistSlots, i1 = min(R, i0 + kHistSlots);
+  if (i0 >= R) return;
   int32_t lo = 0x7FFFFFFF, hi = (int32_t)0x80000000;
-  if (i < R) lo = hi = (int32_t)U[i];
+  for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const int32_t e = (int32_t)U[i];
+    lo = min(lo, e);
+    hi = max(hi, e);
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     lo = min(lo, __shfl_xor(lo, off, kWave));
@@ -709,26 +714,44 @@ __global__ __launch_bounds__(256) void k_minmax(BatchDev B, Group G, uint32_t po
       lo = min(lo, smin[w]);
       hi = max(hi, smax[w]);
     }
-    if (m.lb * 256 < R) {
-      atomicMin(&P.sc->E_lo, lo);
-      atomicMax(&P.sc->E_hi, hi);
-    }
+    atomicMin(&P.sc->E_lo, lo);
+    atomicMax(&P.sc->E_hi, hi);
   }
 }
 
-// kModelGauss16: h[E16 - E_lo] over the occupied window (cleared beforehand).
-__global__ __launch_bounds__(256) void k_hist_window(BatchDev B, Group G, uint32_t post) {
+// kModelGauss16: h[E16 - E_lo] over the occupied window of n_win levels
+// (global histogram cleared beforehand).  Each workgroup takes kHistSlots
+// slots; with LDS (n_win <= kWindowLdsLevels, n_win * 4 bytes of dynamic LDS)
+// it counts them in LDS and adds its nonzero bins, else it adds to the global
+// bins directly.
+__global__ __launch_bounds__(256) void k_hist_window(BatchDev B, Group G, uint32_t n_win,
+                                                     uint32_t use_lds) {
+  extern __shared__ uint32_t hl[];
   const Member m = member_of(G);
   const DevPop P = B.pops[m.pop];
   if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
-  const uint32_t* U = pick(P.U, post ? sp.cur ^ 1u : sp.cur);
+  const uint32_t* U = pick(P.U, sp.cur);
   const uint32_t R = P.sc->R_tilde;
   const int32_t lo = P.sc->E_lo;
-  const uint32_t i = m.lb * 256 + threadIdx.x;
-  if (i < R) {
-    const int32_t lev = (int32_t)U[i] - lo;
-    if (lev >= 0 && (uint32_t)lev < P.n_levels) atomicAdd(&P.hist[lev], 1u);
+  const uint32_t i0 = m.lb * kHistSlots, i1 = min(R, i0 + kHistSlots);
+  if (i0 >= R) return;
+  if (use_lds) {
+    for (uint32_t b = threadIdx.x; b < n_win; b += blockDim.x) hl[b] = 0;
+    __syncthreads();
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      const int32_t lev = (int32_t)U[i] - lo;
+      if (lev >= 0 && (uint32_t)lev < n_win) atomicAdd(&hl[lev], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < n_win; b += blockDim.x)
+      if (hl[b]) atomicAdd(&P.hist[b], hl[b]);
+  } else {
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      const int32_t lev = (int32_t)U[i] - lo;
+      if (lev >= 0 && (uint32_t)lev < n_win && (uint32_t)lev < P.n_levels)
+        atomicAdd(&P.hist[lev], 1u);
+    }
   }
 }
 
@@ -1285,9 +1308,12 @@ hipError_t launch_minmax(const BatchDev& B, const Group& g, hipStream_t stream) 
   return hipGetLastError();
 }
 
-hipError_t launch_hist_window(const BatchDev& B, const Group& g, hipStream_t stream) {
+hipError_t launch_hist_window(const BatchDev& B, const Group& g, uint32_t n_win,
+                              hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
-  hipLaunchKernelGGL(k_hist_window, dim3(g.blocks), dim3(256), 0, stream, B, g, 0u);
+  const bool lds = n_win <= (uint32_t)kWindowLdsLevels;
+  hipLaunchKernelGGL(k_hist_window, dim3(g.blocks), dim3(256), lds ? (size_t)n_win * 4 : 0, stream,
+                     B, g, n_win, lds ? 1u : 0u);
   return hipGetLastError();
 }
 
