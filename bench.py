@@ -62,9 +62,11 @@ BYTES_PER_REPLICA_FIXED = 20
 # copy of known size reads), per launch, with the source it was taken on.
 # Reported only while the kernel source is unchanged.
 TRAFFIC = {
-    "kernel_src_sha256": "24f9d8f41757ed03d6a95cb1e7c0d66fb7f1841821e23dd3252dcc42cc26f6c2",
-    # 33226.2 KiB FETCH_SIZE x 2 + 64945.4 KiB WRITE_SIZE x 1, per k_sweep dispatch
-    "bytes_per_launch": (33226.2 * 2 + 64945.4) * 1024,
+    "kernel_src_sha256": "21d52dd0b13f87311b67090bcdc9c3bcb590fa3b0c09bb274ef4089a1a23fedf",
+    # 33228.8 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
+    "bytes_per_launch": (33228.8 * 2 + 64942.3) * 1024,
+    # the same for the Gaussian-coupling sweep: 32986.0 x 2 + 64952.2 KiB
+    "gauss16_bytes_per_launch": (32986.0 * 2 + 64952.2) * 1024,
     "profile": "profiles/k_sweep_L10_R500k_bitpack64_hbm_counters.md",
 }
 
@@ -338,8 +340,11 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     r = sweep_roofline(w, events, OPS_PER_ATTEMPT_GAUSS)
+    traffic = None
+    if TRAFFIC is not None and TRAFFIC["kernel_src_sha256"] == kernel_src_sha256():
+        traffic = TRAFFIC["gauss16_bytes_per_launch"]
     return {
-        "workload": w["name"], "couplings": "Gaussian N(0,1) rounded to 1/16, |k| <= 127",
+        "workload": w["name"], "couplings": "Gaussian N(0,1) rounded to 1/16, k in [-127, 127]",
         "value": attempts / wall, "unit": "attempts/s", "steps": steps, "warmup": warmup,
         "ms_per_step": 1e3 * wall / steps,
         "sweep": {"kernel": "k_sweep<bitpack64, L=10, gauss16> (gather + 10 sweeps + energy)",
@@ -349,6 +354,7 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
                   "achieved": r["achieved_ops"] / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                   "unit": "Tops/s", "frac": r["achieved_ops"] / VALU_PEAK_OPS,
                   "ops_per_attempt": OPS_PER_ATTEMPT_GAUSS,
+                  "traffic": traffic, "algorithmic_bytes_per_launch": r["bytes_per_launch"],
                   "hbm_algorithmic_GBs": r["bytes_per_launch"] / (r["avg_ms"] * 1e-3) / 1e9},
         "sweep_fraction_of_wall": sum(r["sweep_ms"]) * 1e-3 / wall,
         "autotune": tune,
