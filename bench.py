@@ -4,8 +4,10 @@ A step is one temperature step of the constant-culling anneal (Sec. III.C of
 Amey & Machta, arXiv:1711.02146): choose beta' (the step solved for a culling
 fraction of 0.1), resample (histogram, FP64 table, copy counts, scan, copy
 with family labels), 10 checkerboard Metropolis sweeps at beta', observables
-(<E>, beta F, rho_t).  When the anneal reaches beta = 5 the population is
-started again from beta = 0, so exactly --steps steps are timed.
+(<E>, beta F, rho_t).  When the anneal reaches beta = 5 (about 190 steps
+with +-J couplings, 210 with Gaussian ones) a new population starts again from
+beta = 0 (its initialisation is timed too), so exactly --steps steps are timed;
+the default 300 cover one whole anneal and the start of the next.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -111,20 +113,25 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
 
 
-def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None):
-    """n_steps temperature steps; a new population at beta = 0 whenever beta_max is hit."""
+def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None, anneals=None):
+    """n_steps temperature steps; a new population at beta = 0 whenever beta_max is hit.
+    anneals (list, optional) receives the step count of every anneal completed."""
     import torch
 
     attempts = 0
     pop = None
     gen = 0
+    in_anneal = 0
     for _ in range(n_steps):
         if pop is None or pop_beta >= w["beta_max"]:
             if pop is not None:
                 pop.close()
+                if anneals is not None:
+                    anneals.append(in_anneal)
             pop = pam.Population(w["L"], w["R"], J, seed0 + gen, layout=w["layout"],
                                  model=w["model"])
             pop_beta = 0.0
+            in_anneal = 0
             gen += 1
         b = pop.choose_beta(w["eps"], w["beta_max"])
         st = pop.resample(b)
@@ -140,10 +147,13 @@ def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None):
         obs = pop.observables()
         attempts += w["n_sweeps"] * w["L"] ** 3 * st["R_tilde"]
         pop_beta = b
+        in_anneal += 1
         if stats is not None:
             stats.append((b, st["R_tilde"], obs["rho_t"], obs["beta_F"]))
     if pop is not None:
         pop.close()
+        if anneals is not None and pop_beta >= w["beta_max"]:
+            anneals.append(in_anneal)
     return attempts
 
 
@@ -333,10 +343,10 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
         tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=5)
         tp.close()
     run_steps(pam, K, w, warmup, seed0 + 1000)
-    events, stats = [], []
+    events, stats, anneals = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    attempts = run_steps(pam, K, w, steps, seed0, events, stats)
+    attempts = run_steps(pam, K, w, steps, seed0, events, stats, anneals)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     r = sweep_roofline(w, events, OPS_PER_ATTEMPT_GAUSS)
@@ -358,7 +368,9 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
                   "hbm_algorithmic_GBs": r["bytes_per_launch"] / (r["avg_ms"] * 1e-3) / 1e9},
         "sweep_fraction_of_wall": sum(r["sweep_ms"]) * 1e-3 / wall,
         "autotune": tune,
-        "beta_reached": stats[-1][0] if stats else None,
+        "anneals_completed": len(anneals),
+        "steps_per_anneal": anneals,
+        "beta_at_end": stats[-1][0] if stats else None,
     }
 
 
@@ -454,10 +466,10 @@ def main():
     run_steps(pam, J, w, args.warmup, seed0 + 1000)
     torch.cuda.synchronize()
     print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
-    events, stats = [], []
+    events, stats, anneals = [], [], []
     t0 = time.perf_counter()
     torch.cuda.synchronize()
-    attempts = run_steps(pam, J, w, args.steps, seed0, events, stats)
+    attempts = run_steps(pam, J, w, args.steps, seed0, events, stats, anneals)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
@@ -503,7 +515,9 @@ def main():
         },
         "sweep_fraction_of_wall": sum(sweep_ms) * 1e-3 / wall,
         "autotune": tune,
-        "beta_reached": stats[-1][0] if stats else None,
+        "anneals_completed": len(anneals),
+        "steps_per_anneal": anneals,
+        "beta_at_end": stats[-1][0] if stats else None,
     }
     if args.gauss_steps > 0:
         print(f"# Gaussian couplings: {args.gauss_steps} steps", file=sys.stderr, flush=True)

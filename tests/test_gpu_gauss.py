@@ -259,3 +259,47 @@ def test_full_anneal_l10_r500k(pam):
     # the annealed population sits far below the beta = 0 energy scale
     assert prev["mean_E"] < -1.5 * N
     g.close()
+
+
+@pytest.mark.parametrize("layout", ["int8", "bitpack64"])
+@pytest.mark.parametrize("L,R", [(4, 500), (12, 130), (16, 70)])
+def test_sweep_parity_other_sizes(pam, layout, L, R):
+    """Sweeps and a resampling step at the smallest and the two largest lattices
+    (a ragged last tile in each)."""
+    say("gauss sweep sizes", layout, L, R)
+    K, g, o = pair(pam, L, R, 900 + L, layout, 40 + L)
+    g.sweep(0.6, 2)
+    o.sweep(0.6, 2)
+    assert_state(g, o, f"L={L} swept")
+    g.resample(0.7)
+    o.resample(0.7)
+    g.sweep(0.7, 3)
+    o.sweep(0.7, 3)
+    compare_obs(g.observables(), o.observables(), 1)
+    assert_state(g, o, f"L={L} resampled and swept")
+    g.close()
+
+
+def test_capacity_overflow_keeps_population(pam):
+    """With capacity R, a resampling step soon needs more slots: the call fails
+    with PA_ECAPACITY and leaves the population as it was."""
+    L, R = 4, 256
+    K = pa_inputs.couplings_gauss16(L, 8)
+    g = pam.Population(L, R, K, 5, capacity=R, layout="int8", model="gauss16")
+    g.sweep(0.5, 2)
+    before = g.export_state()
+    failed = False
+    for beta in np.linspace(0.5, 5.0, 40)[1:]:
+        try:
+            g.resample(float(beta))
+        except pam.PAError as e:
+            assert e.status == pam.PA_ECAPACITY
+            failed = True
+            break
+        g.sweep(float(beta), 1)
+        before = g.export_state()
+    assert failed
+    after = g.export_state()
+    for x, y in zip(before, after):
+        np.testing.assert_array_equal(x, y)
+    g.close()
