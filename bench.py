@@ -433,8 +433,8 @@ def cpu_baseline(w):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding "
-              "is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
+              "multi-GPU path; value is one GPU's throughput.", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -464,6 +464,8 @@ def main():
         tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=5)
         tp.close()
     run_steps(pam, J, w, args.warmup, seed0 + 1000)
+    # this device's measured ceilings: sustained VALU issue and Philox draws alone
+    ceil = pam.pa_probe_ceilings()
     torch.cuda.synchronize()
     print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
     events, stats, anneals = [], [], []
@@ -512,6 +514,15 @@ def main():
             "sweep_attempts_per_s": avg_att / (avg_ms * 1e-3),
             "hbm_algorithmic_GBs": bytes_per_launch / (avg_ms * 1e-3) / 1e9,
             "hbm_frac": bytes_per_launch / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            # measured on this device just before the timed steps: the issue rate
+            # of two-source operations (v_add_u32; XOR and v_bitop3 run as fast)
+            # and of three-source ones (v_bfe_u32; extracts, v_add3, 24-bit mads)
+            "measured_valu_peak": ceil["valu_lane_ops_per_s"] / 1e12,
+            "measured_valu3_peak": ceil["valu3_lane_ops_per_s"] / 1e12,
+            "frac_of_measured_valu_peak": achieved_ops / ceil["valu_lane_ops_per_s"],
+            "frac_of_measured_valu3_peak": achieved_ops / ceil["valu3_lane_ops_per_s"],
+            "philox_only_attempts_per_s": ceil["philox_draws_per_s"],
+            "sweep_vs_philox_only": (avg_att / (avg_ms * 1e-3)) / ceil["philox_draws_per_s"],
         },
         "sweep_fraction_of_wall": sum(sweep_ms) * 1e-3 / wall,
         "autotune": tune,

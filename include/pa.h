@@ -281,6 +281,30 @@ int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t 
 /* Forget every autotuned choice (back to the built-in rule). */
 int pa_autotune_reset(void);
 
+/* ------------------------------------------------------------------------ */
+/* Diagnostics: this device's ceilings for the sweep's roofline.             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double valu_lane_ops_per_s;  /* sustained issue rate of v_add_u32 (two register
+                                  sources), lane-operations per second */
+  double valu3_lane_ops_per_s; /* the same for v_bfe_u32 (three sources), the rate
+                                  of bit-field extracts and three-input adds */
+  double philox_draws_per_s;   /* Metropolis Philox4x32-10 draws per second with
+                                  nothing else computed (the sweep's counter layout) */
+} pa_ceilings;
+
+/* Device bytes pa_probe_ceilings needs as scratch (one word per probe lane). */
+size_t pa_probe_scratch_bytes(void);
+
+/* Time three probe kernels on hip_stream (null: the default stream) with HIP
+ * events, two untimed launches then five timed ones each, and report their
+ * average rates: independent v_add_u32 chains and v_bfe_u32 chains over a grid
+ * that fills every SIMD, and the sweep's Philox calls alone.  d_scratch: caller-owned device
+ * memory of at least pa_probe_scratch_bytes() bytes, 4-byte aligned; its
+ * contents are overwritten.  PA_EINVAL on a null or short buffer or a null
+ * out; PA_EDEVICE on a HIP error.  Synchronises. */
+int pa_probe_ceilings(void* d_scratch, size_t bytes, void* hip_stream, pa_ceilings* out);
+
 /* Static description of a status code. */
 const char* pa_strerror(int status);
 

@@ -54,6 +54,11 @@ class pa_obs(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class pa_ceilings(ctypes.Structure):
+    _fields_ = [("valu_lane_ops_per_s", ctypes.c_double), ("valu3_lane_ops_per_s", ctypes.c_double),
+                ("philox_draws_per_s", ctypes.c_double)]
+
+
 class PAError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -111,6 +116,8 @@ def lib():
         "pa_autotune_sweep": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32,
                                              _vp, _vp]),
         "pa_autotune_reset": (ctypes.c_int, []),
+        "pa_probe_scratch_bytes": (ctypes.c_size_t, []),
+        "pa_probe_ceilings": (ctypes.c_int, [_vp, ctypes.c_size_t, _vp, _P(pa_ceilings)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -125,7 +132,8 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_import_state", "pa_free", "pa_strerror", "pa_batch_workspace_bytes",
             "pa_batch_create", "pa_batch_run", "pa_batch_results", "pa_batch_free",
             "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
-            "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset"]
+            "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset", "pa_probe_scratch_bytes",
+            "pa_probe_ceilings"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -295,6 +303,23 @@ def pa_autotune_sweep(handle: int, beta: float = 1.0, n_sweeps: int = 10, repeat
 
 def pa_autotune_reset():
     _check(lib().pa_autotune_reset(), "pa_autotune_reset")
+
+
+def pa_probe_ceilings(stream=None, device=None) -> dict:
+    """This device's sustained VALU lane-op rate and Philox draw rate (scratch
+    from torch on the device; stream defaults to the current one)."""
+    import torch
+
+    dev = torch.device(device) if device is not None else torch.device("cuda")
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    nbytes = lib().pa_probe_scratch_bytes()
+    scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = pa_ceilings()
+    _check(lib().pa_probe_ceilings(scratch.data_ptr(), nbytes, stream.cuda_stream,
+                                   ctypes.byref(out)), "pa_probe_ceilings")
+    return {"valu_lane_ops_per_s": out.valu_lane_ops_per_s,
+            "valu3_lane_ops_per_s": out.valu3_lane_ops_per_s,
+            "philox_draws_per_s": out.philox_draws_per_s}
 
 
 # --- convenience object owning the workspace ---------------------------------

@@ -154,6 +154,15 @@ struct Group {
 
 // Launchers (pa_kernels.hip).  All are asynchronous on `stream`.
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t stream);
+
+// Diagnostics (pa_probe_ceilings): kProbeThreads lanes, each writing one word
+// of `out`; the VALU probe issues kProbeValuOpsPerIter instructions per
+// iteration (form 0: v_add_u32, form 1: v_bfe_u32), the Philox probe makes
+// `calls` Metropolis Philox calls (4 draws each).
+constexpr uint32_t kProbeThreads = 2048 * 256;
+constexpr int kProbeValuOpsPerIter = 32;
+hipError_t launch_probe_valu(uint32_t* out, uint32_t iters, uint32_t form, hipStream_t stream);
+hipError_t launch_probe_philox(uint32_t* out, uint32_t calls, hipStream_t stream);
 hipError_t launch_init(const DevPop& P, uint32_t cur, hipStream_t stream);
 hipError_t launch_zero_acc(const BatchDev& B, const Group& per_pop, hipStream_t stream);
 hipError_t launch_hist(const BatchDev& B, const Group& g, uint32_t max_levels, bool post,

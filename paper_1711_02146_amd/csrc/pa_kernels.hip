@@ -1265,6 +1265,60 @@ __global__ void k_advance(uint32_t* ctr) {
 
 inline uint32_t tiles_of(uint32_t n) { return (n + 63) / 64; }
 
+// ---------------------------------------------------------------------------
+// Diagnostics: the device's ceilings for the sweep's roofline.
+// ---------------------------------------------------------------------------
+// Sustained issue rate of a 32-bit VALU instruction: eight independent chains
+// per lane (no chain waits on its own latency), kProbeValuOpsPerIter
+// instructions per iteration, a grid of kProbeThreads lanes that fills every
+// SIMD.  FORM 0: v_add_u32 (two register sources; on gfx950 such simple
+// operations, XOR and v_bitop3_b32 among them, issue faster than one wave per
+// four cycles); FORM 1: v_bfe_u32 (three sources, the rate of the sweep's
+// bit-field extracts, three-input adds and 24-bit multiply-adds).
+template <int FORM>
+__global__ __launch_bounds__(256) void k_probe_valu(uint32_t* out, uint32_t iters) {
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t v0 = gid, v1 = gid + 1, v2 = gid + 2, v3 = gid + 3;
+  uint32_t v4 = gid + 4, v5 = gid + 5, v6 = gid + 6, v7 = gid + 7;
+  const uint32_t d = gid | 1u;
+  for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int r = 0; r < kProbeValuOpsPerIter / 8; ++r) {
+      if constexpr (FORM == 0)
+        asm volatile(
+            "v_add_u32 %0, %0, %8\n\tv_add_u32 %1, %1, %8\n\tv_add_u32 %2, %2, %8\n\t"
+            "v_add_u32 %3, %3, %8\n\tv_add_u32 %4, %4, %8\n\tv_add_u32 %5, %5, %8\n\t"
+            "v_add_u32 %6, %6, %8\n\tv_add_u32 %7, %7, %8"
+            : "+v"(v0), "+v"(v1), "+v"(v2), "+v"(v3), "+v"(v4), "+v"(v5), "+v"(v6), "+v"(v7)
+            : "v"(d));
+      else
+        asm volatile(
+            "v_bfe_u32 %0, %0, %8, 9\n\tv_bfe_u32 %1, %1, %8, 9\n\tv_bfe_u32 %2, %2, %8, 9\n\t"
+            "v_bfe_u32 %3, %3, %8, 9\n\tv_bfe_u32 %4, %4, %8, 9\n\tv_bfe_u32 %5, %5, %8, 9\n\t"
+            "v_bfe_u32 %6, %6, %8, 9\n\tv_bfe_u32 %7, %7, %8, 9"
+            : "+v"(v0), "+v"(v1), "+v"(v2), "+v"(v3), "+v"(v4), "+v"(v5), "+v"(v6), "+v"(v7)
+            : "v"(d));
+    }
+  }
+  out[gid] = v0 ^ v1 ^ v2 ^ v3 ^ v4 ^ v5 ^ v6 ^ v7;
+}
+
+// Metropolis draws alone: the sweep's Philox calls (same counter layout and
+// hoisting), one call per group g, four draws each, folded into one word so
+// that no call is dead.
+__global__ __launch_bounds__(256) void k_probe_philox(uint32_t* out, uint32_t calls) {
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  MetPhilox ph;
+  ph.init(gid, 0x5EED1234u, 0xC0DE5678u);
+  const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x);
+  uint32_t acc = 0;
+  for (uint32_t g = 0; g < calls; ++g) {
+    const Words4 w = ph.draw(t, g);
+    acc ^= w.w[0] ^ w.w[1] ^ w.w[2] ^ w.w[3];
+  }
+  out[gid] = acc;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1450,6 +1504,19 @@ hipError_t launch_overlap(const BatchDev& B, const Group& g, const uint32_t* pai
 
 hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, stream, step_ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_valu(uint32_t* out, uint32_t iters, uint32_t form, hipStream_t stream) {
+  if (form == 0)
+    hipLaunchKernelGGL(k_probe_valu<0>, dim3(kProbeThreads / 256), dim3(256), 0, stream, out, iters);
+  else
+    hipLaunchKernelGGL(k_probe_valu<1>, dim3(kProbeThreads / 256), dim3(256), 0, stream, out, iters);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_philox(uint32_t* out, uint32_t calls, hipStream_t stream) {
+  hipLaunchKernelGGL(k_probe_philox, dim3(kProbeThreads / 256), dim3(256), 0, stream, out, calls);
   return hipGetLastError();
 }
 

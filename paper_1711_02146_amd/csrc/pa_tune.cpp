@@ -1,6 +1,7 @@
-// pa_tune.cpp -- the sweep autotuner's table: for (coupling model, spin
-// layout, L, size class of the launch) the number of waves per tile that
-// measured fastest on this device.  Size class = floor(log2(tiles)).  The form of a sweep changes no
+// pa_tune.cpp -- device measurement: the sweep autotuner's table (for
+// coupling model, spin layout, L and size class of the launch, the number of
+// waves per tile that measured fastest on this device) and the probes of the
+// device's VALU and Philox ceilings.  Size class = floor(log2(tiles)).  The form of a sweep changes no
 // result (every draw is addressed by slot, sweep and site group), only its time.
 #include <cstdint>
 #include <map>
@@ -48,5 +49,50 @@ void sweep_split_record(uint32_t model, uint32_t layout, uint32_t L, uint64_t ti
 extern "C" int pa_autotune_reset(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_table.clear();
+  return PA_OK;
+}
+
+extern "C" size_t pa_probe_scratch_bytes(void) { return (size_t)pa::kProbeThreads * 4; }
+
+extern "C" int pa_probe_ceilings(void* d_scratch, size_t bytes, void* hip_stream,
+                                 pa_ceilings* out) {
+  if (!d_scratch || !out || bytes < pa_probe_scratch_bytes()) return PA_EINVAL;
+  if (reinterpret_cast<uintptr_t>(d_scratch) % 4) return PA_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  uint32_t* o = static_cast<uint32_t*>(d_scratch);
+  constexpr uint32_t kIters = 4096, kCalls = 2048, kWarm = 2, kTimed = 5;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return PA_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return PA_EDEVICE;
+  }
+  // average launch time of `launch` in ms, or a negative value on a HIP error
+  auto time_of = [&](auto launch) -> float {
+    for (uint32_t w = 0; w < kWarm; ++w)
+      if (launch() != hipSuccess) return -1.0f;
+    float sum = 0.0f;
+    for (uint32_t r = 0; r < kTimed; ++r) {
+      float ms = 0.0f;
+      if (hipEventRecord(e0, s) != hipSuccess || launch() != hipSuccess ||
+          hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return -1.0f;
+      sum += ms;
+    }
+    return sum / (float)kTimed;
+  };
+  const float ms_valu = time_of([&] { return pa::launch_probe_valu(o, kIters, 0u, s); });
+  const float ms_valu3 =
+      ms_valu > 0.0f ? time_of([&] { return pa::launch_probe_valu(o, kIters, 1u, s); }) : -1.0f;
+  const float ms_philox =
+      ms_valu3 > 0.0f ? time_of([&] { return pa::launch_probe_philox(o, kCalls, s); }) : -1.0f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!(ms_valu > 0.0f) || !(ms_valu3 > 0.0f) || !(ms_philox > 0.0f)) return PA_EDEVICE;
+  const double lane_instr = (double)pa::kProbeThreads * kIters * pa::kProbeValuOpsPerIter;
+  out->valu_lane_ops_per_s = lane_instr / (ms_valu * 1e-3);
+  out->valu3_lane_ops_per_s = lane_instr / (ms_valu3 * 1e-3);
+  out->philox_draws_per_s = (double)pa::kProbeThreads * kCalls * 4.0 / (ms_philox * 1e-3);
   return PA_OK;
 }

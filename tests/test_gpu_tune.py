@@ -1,6 +1,7 @@
 """GPU: the sweep autotuner times both sweep forms and remembers the faster; it
 changes neither the population nor any later result (bit-exact against the
-oracle afterwards), in the forms it picks for single instances and batches."""
+oracle afterwards), in the forms it picks for single instances and batches.
+The ceiling probes report rates within the chip's limits."""
 import numpy as np
 import pytest
 
@@ -67,3 +68,19 @@ def test_autotune_needs_no_pending_copy(pam):
             pam.pa_autotune_sweep(g.handle, beta, n, 1)
         assert e.value.status == pam.PA_EINVAL
     g.close()
+
+
+def test_probe_ceilings(pam):
+    """The device ceilings the sweep is measured against.  With one wave
+    instruction per SIMD every four cycles, the chip issues 256 CUs x 64 lanes
+    x 2.4 GHz = 39.3e12 lane-operations per second; three-source operations
+    (v_bfe_u32) stay within that, two-source ones (v_add_u32) may exceed it but
+    not the 32 lanes per SIMD per cycle of the packed FP32 peak.  Philox draws
+    alone take about ten lane-operations each."""
+    c = pam.pa_probe_ceilings()
+    peak = 256 * 64 * 2.4e9
+    assert 0.5 * peak < c["valu3_lane_ops_per_s"] <= 1.02 * peak
+    assert c["valu3_lane_ops_per_s"] <= c["valu_lane_ops_per_s"] <= 2.02 * peak
+    assert 1e11 < c["philox_draws_per_s"] < c["valu_lane_ops_per_s"] / 6
+    # a missing scratch buffer is refused before any launch
+    assert pam.lib().pa_probe_ceilings(None, 0, None, None) == pam.PA_EINVAL
