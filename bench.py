@@ -64,11 +64,11 @@ BYTES_PER_REPLICA_FIXED = 20
 # copy of known size reads), per launch, with the source it was taken on.
 # Reported only while the kernel source is unchanged.
 TRAFFIC = {
-    "kernel_src_sha256": "21d52dd0b13f87311b67090bcdc9c3bcb590fa3b0c09bb274ef4089a1a23fedf",
-    # 33228.8 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
-    "bytes_per_launch": (33228.8 * 2 + 64942.3) * 1024,
-    # the same for the Gaussian-coupling sweep: 32986.0 x 2 + 64952.2 KiB
-    "gauss16_bytes_per_launch": (32986.0 * 2 + 64952.2) * 1024,
+    "kernel_src_sha256": "d473ffdba9f7ef7c7ed5e10709a5d71ec70fff1b89c42e41424f67c67f3a730b",
+    # 33229.6 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
+    "bytes_per_launch": (33229.6 * 2 + 64942.3) * 1024,
+    # the same for the Gaussian-coupling sweep: 32976.4 x 2 + 64952.2 KiB
+    "gauss16_bytes_per_launch": (32976.4 * 2 + 64952.2) * 1024,
     "profile": "profiles/k_sweep_L10_R500k_bitpack64_hbm_counters.md",
 }
 
