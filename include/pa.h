@@ -1,6 +1,7 @@
 /*
  * pa.h -- C ABI of libpa: the data-parallel hot path of population annealing
- * (PA) for the 3D +-J Edwards-Anderson spin glass on one AMD MI355X (gfx950).
+ * (PA) for the 3D Edwards-Anderson spin glass, with +-J couplings or Gaussian
+ * couplings rounded to multiples of 1/16, on one AMD MI355X (gfx950).
  *
  * Method: C. Amey and J. Machta, "Analysis and Optimization of Population
  * Annealing", arXiv:1711.02146.
@@ -17,8 +18,11 @@
  *
  * Conventions shared with every caller:
  *   - N = L^3 sites, site = x + L*(y + L*z); bond b = d*N + site joins site and
- *     site + e_d (d = 0,1,2 for x,y,z); couplings J[b] are +1 or -1.
- *   - U = number of unsatisfied bonds (J_b s_i s_j = -1), E = 2U - 3N.
+ *     site + e_d (d = 0,1,2 for x,y,z); couplings J[b] are +1 or -1
+ *     (PA_MODEL_PM) or the integers k = 16 J in [-127, 127] (PA_MODEL_GAUSS16).
+ *   - The energy word U of a replica: PA_MODEL_PM, the number of unsatisfied
+ *     bonds (J_b s_i s_j = -1), E = 2U - 3N; PA_MODEL_GAUSS16, E16 = 16 E =
+ *     -sum_b k_b s_i s_j as a two's-complement int32.
  *   - The canonical host spin layout is int8 +-1, [replica][site].
  *   - Every random number is a word of Philox4x32-10 (Salmon et al., SC'11)
  *     keyed by the population seed, addressed by (slot, sweep or step, site
@@ -110,7 +114,8 @@ size_t pa_workspace_bytes(const pa_params* p);
 /* Create a population of R replicas at beta = 0 (Sec. II): spin of replica r
  * at site = bit 31 of word (site & 3) of Philox(seed; r, site >> 2, 0, INIT)
  * (bit 1 <=> s = -1); family label r; U computed from the spins.
- * J_host: 3*L^3 couplings (+1/-1), copied.  d_workspace: device memory of at
+ * J_host: 3*L^3 couplings, +1/-1 (PA_MODEL_PM) or k in [-127, 127]
+ * (PA_MODEL_GAUSS16), copied; any other value is PA_EINVAL.  d_workspace: device memory of at
  * least pa_workspace_bytes(p) bytes, owned by the caller.  hip_stream: the
  * hipStream_t all work of this instance is queued on (NULL = default stream).
  * On success *out holds the new instance. */
@@ -139,8 +144,8 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out);
  * bracket of the step [0, beta_max - beta] by regula falsi with the Illinois
  * rule (a midpoint step whenever the bracket fails to halve over two steps)
  * to a relative width of 2^-40, keeping the lower end, so eps <= eps_target;
- * beta_max itself when the whole range culls no more.  PA_ESCHEDULE if eps(0) already
- * exceeds eps_target.  Synchronises. */
+ * beta_max itself when the whole range culls no more.  PA_ESCHEDULE if eps(0)
+ * already exceeds eps_target.  Synchronises. */
 int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* beta_next);
 
 /* Current scalars (Sec. II.A averages, Eq. 9, Sec. III.A).  Synchronises. */
@@ -155,7 +160,8 @@ int pa_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hi
 
 /* Copy the current population to the host in the canonical layout.
  * spins_host: R~ * N int8 (+1/-1), [replica][site]; U_host, family_host: R~
- * entries each; any of the three may be NULL.  *R_tilde receives R~ (call
+ * entries each (U_host: the energy word, for PA_MODEL_GAUSS16 the bits of the
+ * int32 E16); any of the three may be NULL.  *R_tilde receives R~ (call
  * once with all arrays NULL to size them).  Synchronises. */
 int pa_export_state(pa_instance* in, int8_t* spins_host, uint32_t* U_host, uint32_t* family_host,
                     uint32_t* R_tilde);
@@ -178,7 +184,7 @@ int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* f
 int pa_free(pa_instance* in);
 
 /* ------------------------------------------------------------------------ */
-/* Batches: many populations (instances of any L, R and layout) advanced     */
+/* Batches: many populations (PA_MODEL_PM instances of any L, R and layout)  */
 /* together through one temperature schedule (Sec. II loop), each step being */
 /* one replay of a captured HIP graph: device-side FP64 resampling tables    */
 /* (the exp weights come from the host's exp, one row per step), copy        */
@@ -200,6 +206,7 @@ size_t pa_batch_workspace_bytes(uint32_t n_pops, uint32_t n_pairs, uint32_t n_st
  * already in a batch, none with a pending copy step; their current beta must
  * equal betas[0]).  betas: n_steps + 1 inverse temperatures, betas[0] the
  * current one; each step resamples to betas[s] and runs n_sweeps sweeps there.
+ * A PA_MODEL_GAUSS16 instance is PA_EINVAL.
  * pairs: 2 * n_pairs instance indices (same L and layout within a pair) whose
  * overlap histogram (pa_overlap_hist's binning) is recorded after every step;
  * may be NULL when n_pairs = 0.  The caller owns d_workspace
@@ -251,7 +258,8 @@ int pa_stepper_create(uint32_t max_pops, uint32_t max_L, void* d_workspace, size
  * n_sweeps[p] sweeps at beta_next[p].  obs[p] (nullable array) receives its
  * scalars after the step, as pa_observables would report them; status[p]
  * (nullable array) PA_OK, or PA_ECAPACITY when the copy step would exceed the
- * capacity (that instance is left as it was).  Synchronises the stream. */
+ * capacity (that instance is left as it was).  PA_MODEL_GAUSS16 instances are
+ * PA_EINVAL.  Synchronises the stream. */
 int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const double* beta_next,
                     const uint32_t* n_sweeps, pa_obs* obs, int32_t* status);
 
