@@ -15,6 +15,9 @@ annealing loop of Sec. II of Amey & Machta (arXiv:1711.02146) step by step:
 
 The per-step scalars (<E>, beta F, rho_t) are formed here in Python floats,
 which are IEEE doubles, one operation at a time in the order written.
+
+Parity unpinned: the overlap bin convention and the denominator R of rho_t
+(see pa_oracle.c) are checked between the oracle and the GPU only.
 """
 from __future__ import annotations
 

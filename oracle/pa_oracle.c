@@ -1,6 +1,7 @@
 /*
  * pa_oracle.c -- plain CPU oracle for population annealing (PA) on the
- * 3D +-J Edwards-Anderson spin glass.
+ * 3D Edwards-Anderson spin glass, with +-J couplings and with Gaussian
+ * couplings rounded to multiples of 1/16.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
  * CPU-baseline leg of the benchmark load this library.  It shares no code,
@@ -20,8 +21,14 @@
  *
  * Readings where the paper is silent (the coupling distribution, the MCMC
  * variant and its order, the random-number contract, the reference-energy
- * shift, the copy-count tie rule, the adaptive-step bisection) are the ones
- * listed in the design notes; each function names the reading it takes.
+ * shift, the copy-count tie rule, the constant-culling step solver) are
+ * stated at the function that takes them.
+ *
+ * Parity unpinned: the overlap histogram's bin convention (pao_overlap_hist)
+ * and the denominator R of rho_t (pao_sum_eta2's use) are conventions the
+ * paper does not fix; no independent value checks them, so they are compared
+ * between this oracle and the GPU only.  Everything else is pinned by the CPU
+ * tests against closed forms, exact enumeration and the paper's relations.
  */
 #include <math.h>
 #include <stdint.h>
