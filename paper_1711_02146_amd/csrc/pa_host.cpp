@@ -590,11 +590,14 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
   const pa::BatchDev B = one_set(in, ps);
   PA_HIP(in, pa::launch_counts(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
   PA_HIP(in, pa::launch_scan(B, group_of(in, in->d_meta->perpop, 1), in->stream));
+  // the copy map is built before the host sees the capacity check: k_scatter
+  // does nothing when the scan flagged an overflow, and on success the host
+  // does not wait for a launch after its synchronisation
+  PA_HIP(in, pa::launch_scatter(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
   PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
   if (in->h_sc->err == 2) return dev_fail(in);
   if (in->h_sc->err) return PA_ECAPACITY;  // population untouched
-  PA_HIP(in, pa::launch_scatter(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
   in->last_R_old = in->R_tilde;
   in->R_tilde = in->h_sc->R_next;
   in->last_n_culled = in->h_sc->n_culled;
