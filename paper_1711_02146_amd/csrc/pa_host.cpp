@@ -185,46 +185,49 @@ void build_rowk(uint32_t L, const int8_t* K, uint32_t stride, std::vector<int8_t
 //   ln Q = ln S - ln R~ - dbeta E_min,  E_min = 2 j_min - 3N.
 // ---------------------------------------------------------------------------
 struct Table {
-  int jmin = -1;
+  int jmin = -1, jmax = -1;  // lowest and highest occupied level
   double S = 0.0, lnQ = 0.0;
+  double eps = 0.0;          // culling fraction (Sec. III.C) of this step
 };
 
 // Levels j have energy unit * (E_lo + j): unit 2, E_lo = -3N/2 for +-J (E = 2U - 3N),
 // unit 1/16, E_lo = lowest E16 of the population for quantised Gaussian couplings.
+// Entries are written for the occupied levels only: the copy counts read the
+// table at each replica's own level, which is occupied.  The culling fraction
+// of the step is summed in the same pass, with the same tau_j as
+// culling_fraction() forms.
 Table resample_table(const uint32_t* h, uint32_t n_levels, double unit, int64_t E_lo, uint32_t R,
                      uint32_t R_tilde, double dbeta, uint32_t* fl, uint64_t* T) {
   Table t;
   for (uint32_t j = 0; j < n_levels; ++j)
     if (h[j] > 0) {
-      t.jmin = (int)j;
-      break;
+      if (t.jmin < 0) t.jmin = (int)j;
+      t.jmax = (int)j;
     }
   if (t.jmin < 0) return t;
   const int jmin = t.jmin;
-  // w_j once per level (both loops use the same value)
+  // w_j once per occupied level (both loops use the same value)
   static thread_local std::vector<double> w;
   w.resize(n_levels);
-  for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j)
-    w[j] = std::exp(-dbeta * (unit * (double)((int)j - jmin)));
   double S = 0.0;
-  for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
+  for (uint32_t j = (uint32_t)jmin; j <= (uint32_t)t.jmax; ++j) {
     if (h[j] == 0) continue;
+    w[j] = std::exp(-dbeta * (unit * (double)((int)j - jmin)));
     S = S + (double)h[j] * w[j];
   }
-  for (uint32_t j = 0; j < n_levels; ++j) {
-    if ((int)j < jmin) {
-      fl[j] = 0;
-      T[j] = 0;
-      continue;
-    }
+  double acc = 0.0;
+  for (uint32_t j = (uint32_t)jmin; j <= (uint32_t)t.jmax; ++j) {
+    if (h[j] == 0) continue;
     const double tau = ((double)R * w[j]) / S;
     const uint64_t f = (uint64_t)std::floor(tau);
     const double fr = tau - (double)f;
     fl[j] = (uint32_t)f;
     T[j] = (uint64_t)std::ceil(std::ldexp(fr, 53));
+    if (tau < 1.0) acc = acc + (double)h[j] * (1.0 - tau);
   }
   t.S = S;
   t.lnQ = std::log(S) - std::log((double)R_tilde) - dbeta * (unit * (double)(E_lo + jmin));
+  t.eps = acc / (double)R;
   return t;
 }
 
@@ -580,10 +583,12 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
   const Table t = resample_table(in->h_hist, lv.n, lv.unit, lv.E_lo, P.R, in->R_tilde, dbeta,
                                  in->h_fl, in->h_T);
   if (t.jmin < 0) return PA_ESTATE;  // empty population
-  const double eps = culling_fraction(in->h_hist, lv.n, lv.unit, P.R, dbeta);
-  PA_HIP(in, hipMemcpyAsync(P.table_fl, in->h_fl, (size_t)lv.n * 4, hipMemcpyHostToDevice,
+  const double eps = t.eps;
+  // only the occupied range is read by the copy counts
+  const size_t j0 = (size_t)t.jmin, nj = (size_t)(t.jmax - t.jmin + 1);
+  PA_HIP(in, hipMemcpyAsync(P.table_fl + j0, in->h_fl + j0, nj * 4, hipMemcpyHostToDevice,
                             in->stream));
-  PA_HIP(in, hipMemcpyAsync(P.table_T, in->h_T, (size_t)lv.n * 8, hipMemcpyHostToDevice,
+  PA_HIP(in, hipMemcpyAsync(P.table_T + j0, in->h_T + j0, nj * 8, hipMemcpyHostToDevice,
                             in->stream));
   pa::PopStep ps = plain_step(in->cur);
   ps.step = in->step + 1;
