@@ -303,3 +303,37 @@ def test_capacity_overflow_keeps_population(pam):
     for x, y in zip(before, after):
         np.testing.assert_array_equal(x, y)
     g.close()
+
+
+def test_wide_energy_window_global_histogram(pam):
+    """A window wider than the LDS histogram (16384 levels): couplings all
+    k = +127 and a population of 64 aligned replicas (E16 = -3 N 127) among
+    random ones (E16 near 0) span about 2e5 levels, so the window histogram
+    takes its global-atomic path.  Imported into both sides; one resampling
+    step and sweeps bit-exact."""
+    L, R = 8, 256
+    N = L ** 3
+    K = np.full(3 * N, 127, np.int8)
+    rng = np.random.default_rng(11)
+    spins = np.where(rng.random((R, N)) < 0.5, 1, -1).astype(np.int8)
+    spins[:64] = 1
+    fam = np.arange(R, dtype=np.uint32)
+    o = oracle.GaussPopulation(L, K, R, 321)
+    o.spins = spins.reshape(-1).copy()
+    o.U = oracle.g_energy(L, K, o.spins)
+    o.fam = fam.copy()
+    lo, hi = o.window()
+    assert hi - lo + 1 > 16384 and lo == -3 * N * 127
+    g = pam.Population(L, R, K, 321, layout="bitpack64", model="gauss16")
+    g.import_state(spins, fam, 0, 0, 0.0, 0.0)
+    assert_state(g, o, "imported wide window")
+    g.resample(2e-4)
+    o.resample(2e-4)
+    c, off = g.export_counts()
+    np.testing.assert_array_equal(c, o.last["n"])
+    np.testing.assert_array_equal(off.astype(np.uint64), o.last["offsets"])
+    g.sweep(2e-4, 2)
+    o.sweep(2e-4, 2)
+    compare_obs(g.observables(), o.observables(), 1)
+    assert_state(g, o, "wide window after a step")
+    g.close()
