@@ -262,7 +262,7 @@ def test_full_anneal_l10_r500k(pam):
 
 
 @pytest.mark.parametrize("layout", ["int8", "bitpack64"])
-@pytest.mark.parametrize("L,R", [(4, 500), (12, 130), (16, 70)])
+@pytest.mark.parametrize("L,R", [(4, 500), (12, 130), (14, 100), (16, 70)])
 def test_sweep_parity_other_sizes(pam, layout, L, R):
     """Sweeps and a resampling step at the smallest and the two largest lattices
     (a ragged last tile in each)."""

@@ -316,3 +316,23 @@ def test_full_size_l10_r500k_bitpack_adaptive(pam):
 def test_full_size_l8_r100k_int8_linear(pam):
     _first_step_sampled(pam, 8, 100000, "int8", pa_inputs.population_seed(2, 0, 0),
                         pa_inputs.coupling_seed(2, 0), adaptive=False)
+
+
+@pytest.mark.parametrize("layout", ["int8", "bitpack64"])
+@pytest.mark.parametrize("L,R", [(12, 130), (14, 100), (16, 70)])
+def test_sweep_parity_large_lattices(pam, layout, L, R):
+    """The largest lattices (8 waves per tile, lower occupancy): sweeps, a
+    resampling step and more sweeps, each with a ragged last tile."""
+    say("large lattice", layout, L, R)
+    J, g, o = pair(pam, L, R, 700 + L, layout, 60 + L)
+    g.sweep(0.5, 2)
+    o.sweep(0.5, 2)
+    assert_state(g, o, f"L={L} swept")
+    g.resample(0.6)
+    o.resample(0.6)
+    _compare_step(g, o, 1)
+    g.sweep(0.6, 3)
+    o.sweep(0.6, 3)
+    _compare_obs(g.observables(), o.observables(), 1)
+    assert_state(g, o, f"L={L} resampled and swept")
+    g.close()
