@@ -183,6 +183,14 @@ int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* f
 /* Release the host-side handle (the caller frees the workspace afterwards). */
 int pa_free(pa_instance* in);
 
+/* +-J couplings of one disorder sample (Sec. II.A model with couplings +-1 of
+ * probability 1/2), on the host: J_out[b] = +1 if bit 31 of word (b & 3) of
+ * Philox4x32-10(key = coupling_seed; counter = (b >> 2, 0, 0, TAG_J)) is 0,
+ * else -1, for the 3 L^3 bonds b (TAG_J = 0x434F5550).  J_out: 3 L^3 int8,
+ * caller-owned.  PA_EINVAL for a null J_out or L outside [2, 64].  Callers
+ * may pass any other couplings to pa_init_instance instead. */
+int pa_make_couplings_pm(uint64_t coupling_seed, uint32_t L, int8_t* J_out);
+
 /* ------------------------------------------------------------------------ */
 /* Batches: many populations (PA_MODEL_PM instances of any L, R and layout)  */
 /* together through one temperature schedule (Sec. II loop), each step being */

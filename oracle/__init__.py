@@ -64,6 +64,7 @@ def lib():
     L = ctypes.CDLL(_LIB)
     sig = {
         "pao_philox": (None, [_u32p, _u32p, _u32p]),
+        "pao_make_couplings_pm": (None, [_c.c_uint64, _c.c_int, _i8p]),
         "pao_colour_major": (None, [_c.c_int, _i32p]),
         "pao_neighbours": (None, [_c.c_int, _i32p, _i32p]),
         "pao_energy": (None, [_c.c_int, _i8p, _i8p, _c.c_int64, _i32p]),
@@ -117,6 +118,13 @@ def philox(ctr, key) -> np.ndarray:
     """Philox4x32-10 of counter (4 words) and key (2 words) -> 4 words."""
     out = np.zeros(4, np.uint32)
     lib().pao_philox(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def make_couplings_pm(L: int, coupling_seed: int) -> np.ndarray:
+    """3 L^3 couplings +-1 drawn from Philox under the coupling seed (tag J)."""
+    out = np.zeros(3 * L ** 3, np.int8)
+    lib().pao_make_couplings_pm(int(coupling_seed), int(L), out)
     return out
 
 

@@ -52,6 +52,7 @@
 #define TAG_INIT 0x494E4954u /* initial spins */
 #define TAG_MET 0x4D455452u  /* Metropolis acceptance draws */
 #define TAG_RES 0x52455341u  /* resampling (copy-count) draws */
+#define TAG_J 0x434F5550u    /* +-J couplings of a disorder sample */
 
 void pao_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
@@ -68,6 +69,21 @@ void pao_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
     k1 += PHILOX_WEYL_B;
   }
   out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* +-J couplings of one disorder sample (Sec. II.A, couplings +-1 with
+ * probability 1/2): bond b takes +1 when the top bit of word b & 3 of the
+ * Philox call with counter (b >> 2, 0, 0, TAG_J) under the coupling seed is
+ * clear, -1 when it is set. */
+void pao_make_couplings_pm(uint64_t coupling_seed, int L, int8_t* J_out) {
+  int64_t nb = 3 * (int64_t)L * L * L;
+  uint32_t key[2] = {(uint32_t)coupling_seed, (uint32_t)(coupling_seed >> 32)};
+  for (int64_t b = 0; b < nb; ++b) {
+    uint32_t ctr[4] = {(uint32_t)(b >> 2), 0u, 0u, TAG_J};
+    uint32_t w[4];
+    pao_philox(ctr, key, w);
+    J_out[b] = (w[b & 3] >> 31) ? -1 : 1;
+  }
 }
 
 /* One 32-bit word of Philox(seed; c0, c1, c2, tag), word index w in 0..3.

@@ -117,6 +117,7 @@ def lib():
                                              _vp, _vp]),
         "pa_autotune_reset": (ctypes.c_int, []),
         "pa_probe_scratch_bytes": (ctypes.c_size_t, []),
+        "pa_make_couplings_pm": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, _vp]),
         "pa_probe_ceilings": (ctypes.c_int, [_vp, ctypes.c_size_t, _vp, _P(pa_ceilings)]),
     }
     for name, (res, args) in sig.items():
@@ -133,7 +134,7 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_batch_create", "pa_batch_run", "pa_batch_results", "pa_batch_free",
             "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
             "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset", "pa_probe_scratch_bytes",
-            "pa_probe_ceilings"]
+            "pa_probe_ceilings", "pa_make_couplings_pm"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -218,6 +219,14 @@ def pa_import_state(handle: int, spins: np.ndarray, family: np.ndarray, sweeps_d
     _check(lib().pa_import_state(handle, spins.ctypes.data, family.ctypes.data, family.size,
                                  int(sweeps_done), int(step), float(beta), float(sum_lnQ)),
            "pa_import_state")
+
+
+def pa_make_couplings_pm(L: int, coupling_seed: int) -> np.ndarray:
+    """+-J couplings of one disorder sample from the library's Philox stream."""
+    out = np.zeros(3 * int(L) ** 3, np.int8)
+    _check(lib().pa_make_couplings_pm(int(coupling_seed), int(L), out.ctypes.data),
+           "pa_make_couplings_pm")
+    return out
 
 
 def pa_free(handle: int):

@@ -396,6 +396,30 @@ hipError_t set_thresholds(pa_instance* in, double beta, pa::PopStep* ps) {
 
 bool usable(pa_instance* in) { return in && !in->failed && !in->in_batch; }
 
+// Philox4x32-10 on the host (Salmon et al., SC'11): counter (c0, c1, c2, c3),
+// key (k0, k1); each round multiplies c0 and c2 by the round constants,
+// swaps in the high halves XORed with the other counter words and the key,
+// and bumps the key by the Weyl constants.
+void philox_host(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                 uint32_t out[4]) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)pb;
+    c3 = (uint32_t)pa;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
 }  // namespace
 
 extern "C" {
@@ -404,6 +428,19 @@ size_t pa_workspace_bytes(const pa_params* p) {
   Layout l;
   if (!make_layout(p, &l)) return 0;
   return l.total;
+}
+
+int pa_make_couplings_pm(uint64_t coupling_seed, uint32_t L, int8_t* J_out) {
+  if (!J_out || L < 2 || L > 64) return PA_EINVAL;
+  const uint64_t nb = 3ull * L * L * L;
+  const uint32_t k0 = (uint32_t)coupling_seed, k1 = (uint32_t)(coupling_seed >> 32);
+  for (uint64_t g = 0; 4 * g < nb; ++g) {
+    uint32_t w[4];
+    philox_host((uint32_t)g, 0u, 0u, pa::kTagJ, k0, k1, w);
+    for (uint32_t i = 0; i < 4 && 4 * g + i < nb; ++i)
+      J_out[4 * g + i] = (w[i] >> 31) ? (int8_t)-1 : (int8_t)1;
+  }
+  return PA_OK;
 }
 
 const char* pa_strerror(int status) {

@@ -23,6 +23,7 @@ namespace pa {
 constexpr uint32_t kTagInit = 0x494E4954u;  // initial spins
 constexpr uint32_t kTagMet = 0x4D455452u;   // Metropolis acceptance draws
 constexpr uint32_t kTagRes = 0x52455341u;   // copy-count draws
+constexpr uint32_t kTagJ = 0x434F5550u;     // +-J couplings (pa_make_couplings_pm)
 
 constexpr int kWave = 64;          // wavefront width on gfx950; one spin tile = 64 replicas
 constexpr int kBlockCounts = 256;  // slots per block in the copy-count / scatter kernels

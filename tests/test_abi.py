@@ -55,3 +55,22 @@ def test_workspace_sizing_and_argument_checks():
     assert pam.pa_strerror(pam.PA_ECAPACITY) == "resampled population exceeds capacity"
     with pytest.raises(pam.PAError):
         pam.pa_init_instance(p, np.ones(3000, np.int8), 0, 0, 0)  # null workspace: PA_EINVAL
+
+
+def test_make_couplings_pm_host_call():
+    """The library's host coupling generator (no GPU work) against the
+    oracle's, written separately from the same rule; the couplings are +-1
+    with probability 1/2 (Sec. II.A)."""
+    import oracle
+    import paper_1711_02146_amd as pam
+
+    for L, seed in ((2, 0), (3, 1), (4, 0xC0DE0000), (10, 2 ** 63 + 5), (16, 77)):
+        J = pam.pa_make_couplings_pm(L, seed)
+        np.testing.assert_array_equal(J, oracle.make_couplings_pm(L, seed))
+        assert set(np.unique(J)) <= {-1, 1}
+    J = pam.pa_make_couplings_pm(16, 12345).astype(np.float64)
+    assert abs(J.mean()) < 4.0 / np.sqrt(J.size)
+    assert not np.array_equal(pam.pa_make_couplings_pm(8, 1), pam.pa_make_couplings_pm(8, 2))
+    assert pam.lib().pa_make_couplings_pm(1, 1, None) == pam.PA_EINVAL
+    with pytest.raises(pam.PAError):
+        pam.pa_make_couplings_pm(1, 3)
