@@ -1,7 +1,7 @@
 """Benchmark: population annealing at L=10, R=5e5 on one MI355X.
 
 A step is one temperature step of the constant-culling anneal (Sec. III.C of
-Amey & Machta, arXiv:1711.02146): choose beta' (the step solved for a culling
+Amey & Machta, arXiv:1711.02146): choose beta' (bisection to a culling
 fraction of 0.1), resample (histogram, FP64 table, copy counts, scan, copy
 with family labels), 10 checkerboard Metropolis sweeps at beta', observables
 (<E>, beta F, rho_t).  When the anneal reaches beta = 5 (about 190 steps

@@ -140,12 +140,11 @@ int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps);
 int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out);
 
 /* Constant-culling step (Sec. III.C): the beta_next in (beta, beta_max] whose
- * culling fraction eps = sum_{tau<1}(1 - tau) / R is eps_target, solved on a
- * bracket of the step [0, beta_max - beta] by regula falsi with the Illinois
- * rule (a midpoint step whenever the bracket fails to halve over two steps)
- * to a relative width of 2^-40, keeping the lower end, so eps <= eps_target;
- * beta_max itself when the whole range culls no more.  PA_ESCHEDULE if eps(0)
- * already exceeds eps_target.  Synchronises. */
+ * culling fraction eps = sum_{tau<1}(1 - tau) / R is eps_target, by 64
+ * bisection halvings on [0, beta_max - beta] (mid = lo + (hi - lo)/2) keeping
+ * the lower end, so eps <= eps_target; beta_max itself when the whole range
+ * culls no more.  PA_ESCHEDULE if eps(0) already exceeds eps_target.
+ * Synchronises. */
 int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* beta_next);
 
 /* Current scalars (Sec. II.A averages, Eq. 9, Sec. III.A).  Synchronises. */

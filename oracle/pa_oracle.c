@@ -21,7 +21,7 @@
  *
  * Readings where the paper is silent (the coupling distribution, the MCMC
  * variant and its order, the random-number contract, the reference-energy
- * shift, the copy-count tie rule, the constant-culling step solver) are
+ * shift, the copy-count tie rule, the constant-culling bisection) are
  * stated at the function that takes them.
  *
  * Parity unpinned: the overlap histogram's bin convention (pao_overlap_hist)
@@ -423,12 +423,8 @@ double pao_culling_fraction(const uint32_t* h, int n_levels, uint32_t R, double 
 
 /* ------------------------------------------------------------------------ */
 /* Constant-culling step (Sec. III.C and Sec. IV.B: a schedule that culls a */
-/* fixed fraction per step).  Our reading: the step dbeta in [0, rem] where */
-/* the culling fraction crosses eps_target, found on a bracket [lo, hi]     */
-/* with eps(lo) <= eps_target < eps(hi) (see pao_choose_dbeta_unit); the    */
-/* lower end is kept.  If the whole remaining range culls no more than      */
-/* eps_target, it is taken.  Returns 0, or -1 when even dbeta = 0 culls     */
-/* more than eps_target.  Levels of +-J are 2 apart in energy.              */
+/* fixed fraction per step), by the bisection of pao_choose_dbeta_unit with */
+/* the +-J level width 2.                                                   */
 /* ------------------------------------------------------------------------ */
 int pao_choose_dbeta_unit(const uint32_t* h, int n_levels, double unit, uint32_t R,
                           double eps_target, double rem, double* dbeta_out, int* reached_end);
@@ -668,51 +664,25 @@ double pao_culling_fraction_unit(const uint32_t* h, int n_levels, double unit, u
   return acc / (double)R;
 }
 
-/* Constant-culling step with levels of width `unit`.  The crossing of     */
-/* f(x) = eps(x) - eps_target is found by regula falsi with the Illinois    */
-/* rule: the next point is where the chord through (lo, f(lo)) and          */
-/* (hi, f(hi)) meets zero, and when the same end of the bracket is kept     */
-/* twice in a row, the f value stored for it is halved.  When a step leaves */
-/* the bracket wider than half of what it was two steps earlier, the next   */
-/* point is the midpoint, so the width at least halves every three steps.   */
-/* Stop when hi - lo <= 2^-40 hi and return lo (eps(lo) <= eps_target).     */
+/* Constant-culling step with levels of width `unit` (Sec. III.C).  Our     */
+/* reading: bisect dbeta on [0, rem] so that eps(dbeta) <= eps_target, 64   */
+/* halvings with mid = lo + (hi - lo)/2, keeping the lower end; if the whole */
+/* remaining range already culls no more than eps_target, take it.  Returns */
+/* 0, or -1 when even dbeta = 0 culls more than eps_target.                 */
 /* ------------------------------------------------------------------------ */
 int pao_choose_dbeta_unit(const uint32_t* h, int n_levels, double unit, uint32_t R,
                           double eps_target, double rem, double* dbeta_out, int* reached_end) {
-  double f_lo = pao_culling_fraction_unit(h, n_levels, unit, R, 0.0) - eps_target;
-  if (f_lo > 0.0) return -1;
-  double f_hi = pao_culling_fraction_unit(h, n_levels, unit, R, rem) - eps_target;
-  if (f_hi <= 0.0) {
+  if (pao_culling_fraction_unit(h, n_levels, unit, R, 0.0) > eps_target) return -1;
+  if (pao_culling_fraction_unit(h, n_levels, unit, R, rem) <= eps_target) {
     *dbeta_out = rem;
     *reached_end = 1;
     return 0;
   }
   double lo = 0.0, hi = rem;
-  double width1 = hi - lo, width2 = hi - lo; /* bracket width one and two steps back */
-  int kept = 0;                              /* -1: the last step moved lo, +1: hi */
-  int midpoint = 0;
-  for (int it = 0; it < 1000 && hi - lo > 0x1p-40 * hi; ++it) {
-    double x = lo + 0.5 * (hi - lo);
-    if (!midpoint) {
-      double chord = lo + (hi - lo) * (f_lo / (f_lo - f_hi));
-      if (chord > lo && chord < hi) x = chord;
-    }
-    double fx = pao_culling_fraction_unit(h, n_levels, unit, R, x) - eps_target;
-    if (fx <= 0.0) {
-      lo = x;
-      f_lo = fx;
-      if (kept == -1) f_hi = 0.5 * f_hi;
-      kept = -1;
-    } else {
-      hi = x;
-      f_hi = fx;
-      if (kept == 1) f_lo = 0.5 * f_lo;
-      kept = 1;
-    }
-    double width = hi - lo;
-    midpoint = width > 0.5 * width2;
-    width2 = width1;
-    width1 = width;
+  for (int it = 0; it < 64; ++it) {
+    double mid = lo + 0.5 * (hi - lo);
+    if (pao_culling_fraction_unit(h, n_levels, unit, R, mid) <= eps_target) lo = mid;
+    else hi = mid;
   }
   *dbeta_out = lo;
   *reached_end = 0;

@@ -74,7 +74,7 @@ def paper_sweep_schedule(beta: float) -> int:
 # --- drivers (GPU) ------------------------------------------------------------
 def constant_eps_schedule(L: int, R: int, J, seed: int, eps: float, beta_max: float,
                           n_sweeps=10, layout: str = "bitpack64", max_steps: int = 100000):
-    """betas of one constant-culling run (the step solved for culling fraction eps,
+    """betas of one constant-culling run (bisection to culling fraction eps,
     Sec. III.C), from beta = 0 to beta_max.  n_sweeps: int or callable(beta)."""
     import paper_1711_02146_amd as pam
 

@@ -1,5 +1,5 @@
 // pa_host.cpp -- the C ABI of libpa (include/pa.h): instance state, workspace
-// layout, the FP64 resampling table, the constant-culling step solver, and the
+// layout, the FP64 resampling table, the constant-culling bisection, and the
 // stream-ordered sequence of kernel launches of one annealing step.
 //
 // Method: Amey & Machta, arXiv:1711.02146.
@@ -194,8 +194,8 @@ struct Table {
 // unit 1/16, E_lo = lowest E16 of the population for quantised Gaussian couplings.
 // Entries are written for the occupied levels only: the copy counts read the
 // table at each replica's own level, which is occupied.  The culling fraction
-// of the step is summed in the same pass, with the same tau_j as
-// culling_fraction() forms.
+// eps R = sum over occupied levels with tau_j < 1 of h_j (1 - tau_j) (Sec.
+// III.C) is summed in the same pass, as pa_choose_beta evaluates it.
 Table resample_table(const uint32_t* h, uint32_t n_levels, double unit, int64_t E_lo, uint32_t R,
                      uint32_t R_tilde, double dbeta, uint32_t* fl, uint64_t* T) {
   Table t;
@@ -229,35 +229,6 @@ Table resample_table(const uint32_t* h, uint32_t n_levels, double unit, int64_t 
   t.lnQ = std::log(S) - std::log((double)R_tilde) - dbeta * (unit * (double)(E_lo + jmin));
   t.eps = acc / (double)R;
   return t;
-}
-
-// Culling fraction (Sec. III.C): eps R = sum_{tau_i < 1} (1 - tau_i), tau_j
-// exactly as in resample_table.
-double culling_fraction(const uint32_t* h, uint32_t n_levels, double unit, uint32_t R,
-                        double dbeta) {
-  int jmin = -1;
-  for (uint32_t j = 0; j < n_levels; ++j)
-    if (h[j] > 0) {
-      jmin = (int)j;
-      break;
-    }
-  if (jmin < 0) return 0.0;
-  // w_j once per occupied level (both sums use the same value)
-  static thread_local std::vector<double> w;
-  w.resize(n_levels);
-  double S = 0.0;
-  for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
-    if (h[j] == 0) continue;
-    w[j] = std::exp(-dbeta * (unit * (double)((int)j - jmin)));
-    S = S + (double)h[j] * w[j];
-  }
-  double acc = 0.0;
-  for (uint32_t j = (uint32_t)jmin; j < n_levels; ++j) {
-    if (h[j] == 0) continue;
-    const double tau = ((double)R * w[j]) / S;
-    if (tau < 1.0) acc = acc + (double)h[j] * (1.0 - tau);
-  }
-  return acc / (double)R;
 }
 
 }  // namespace
@@ -678,47 +649,49 @@ int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* 
   const Levels lv = levels_of(in);
   const uint32_t nl = lv.n, R = in->dev.R;
   const uint32_t* h = in->h_hist;
-  // g(x) = eps(x) - target; its sign is that of eps(x) - target exactly
-  auto g = [&](double x) { return culling_fraction(h, nl, lv.unit, R, x) - eps_target; };
-  double g_lo = g(0.0);
-  if (g_lo > 0.0) return PA_ESCHEDULE;
+  // The occupied levels once, as (exp argument, count) pairs in level order;
+  // each evaluation of the culling fraction below, eps R = sum over them
+  // with tau_j < 1 of h_j (1 - tau_j) (Sec. III.C), forms w_j, S and tau_j
+  // exactly as resample_table() does, without scanning empty levels.
+  static thread_local std::vector<double> arg, cnt;
+  arg.clear();
+  cnt.clear();
+  int jmin = -1;
+  for (uint32_t j = 0; j < nl; ++j) {
+    if (h[j] == 0) continue;
+    if (jmin < 0) jmin = (int)j;
+    arg.push_back(lv.unit * (double)((int)j - jmin));
+    cnt.push_back((double)h[j]);
+  }
+  const size_t n_occ = arg.size();
+  auto eps_of = [&](double dbeta) {
+    if (n_occ == 0) return 0.0;
+    static thread_local std::vector<double> w;
+    w.resize(n_occ);
+    double S = 0.0;
+    for (size_t i = 0; i < n_occ; ++i) {
+      w[i] = std::exp(-dbeta * arg[i]);
+      S = S + cnt[i] * w[i];
+    }
+    double acc = 0.0;
+    for (size_t i = 0; i < n_occ; ++i) {
+      const double tau = ((double)R * w[i]) / S;
+      if (tau < 1.0) acc = acc + cnt[i] * (1.0 - tau);
+    }
+    return acc / (double)R;
+  };
+  if (eps_of(0.0) > eps_target) return PA_ESCHEDULE;
   const double rem = beta_max - in->beta;
-  double g_hi = g(rem);
-  if (g_hi <= 0.0) {
+  if (eps_of(rem) <= eps_target) {
     *beta_next = beta_max;
     return PA_OK;
   }
-  // Bracket [lo, hi] with g(lo) <= 0 < g(hi), narrowed by the point where the
-  // chord meets zero; an end kept twice in a row has its stored g halved
-  // (Illinois), and after a step that leaves the bracket wider than half its
-  // width two steps before, the midpoint is taken instead.  Stops at a
-  // relative width of 2^-40; the lower end is the step.
+  // 64 halvings of [0, rem], keeping the lower end (eps(lo) <= target)
   double lo = 0.0, hi = rem;
-  double prev = hi - lo, prev2 = hi - lo;
-  int moved = 0;  // -1: the last step moved lo, +1: it moved hi
-  bool bisect = false;
-  for (int it = 0; it < 1000 && hi - lo > 0x1p-40 * hi; ++it) {
-    double x = lo + 0.5 * (hi - lo);
-    if (!bisect) {
-      const double c = lo + (hi - lo) * (g_lo / (g_lo - g_hi));
-      if (c > lo && c < hi) x = c;
-    }
-    const double gx = g(x);
-    if (gx <= 0.0) {
-      lo = x;
-      g_lo = gx;
-      if (moved == -1) g_hi = 0.5 * g_hi;
-      moved = -1;
-    } else {
-      hi = x;
-      g_hi = gx;
-      if (moved == 1) g_lo = 0.5 * g_lo;
-      moved = 1;
-    }
-    const double width = hi - lo;
-    bisect = width > 0.5 * prev2;
-    prev2 = prev;
-    prev = width;
+  for (int it = 0; it < 64; ++it) {
+    const double mid = lo + 0.5 * (hi - lo);
+    if (eps_of(mid) <= eps_target) lo = mid;
+    else hi = mid;
   }
   *beta_next = in->beta + lo;
   return PA_OK;

@@ -68,7 +68,7 @@ def test_c3_full_anneal(pam):
         o = g.observables()
         check_step(o, prev, L, R, cap)
         if b < bmax:
-            # the step solver keeps eps(lo) <= target; the step taken is
+            # the bisection keeps eps(lo) <= target; the step taken is
             # (beta + lo) - beta, which differs from lo by rounding
             assert o["eps_expected"] <= eps + 1e-12
         steps += 1
