@@ -389,6 +389,61 @@ def test_adaptive_step_bisection_and_gaussian_estimate(oracle_lib):
         assert dbeta == _bisect_crossing(h3, 20000, eps, 5.0)
 
 
+def _plaquette_sum(L, J):
+    """Sum over the 3N elementary plaquettes of the product of their four
+    couplings, from the bond convention b = d N + site (site to site + e_d)."""
+    N = L ** 3
+
+    def site(x, y, z):
+        return (x % L) + L * ((y % L) + L * (z % L))
+
+    e = ((1, 0, 0), (0, 1, 0), (0, 0, 1))
+    tot = 0
+    for z in range(L):
+        for y in range(L):
+            for x in range(L):
+                s = site(x, y, z)
+                for d1 in range(3):
+                    for d2 in range(d1 + 1, 3):
+                        a, b = e[d1], e[d2]
+                        s1 = site(x + a[0], y + a[1], z + a[2])
+                        s2 = site(x + b[0], y + b[1], z + b[2])
+                        tot += (int(J[d1 * N + s]) * int(J[d2 * N + s1]) * int(J[d1 * N + s2])
+                                * int(J[d2 * N + s]))
+    return tot
+
+
+def test_high_temperature_series_and_culled_count(oracle_lib):
+    """A lattice too large to enumerate, L = 6, at high temperature.  With
+    t = tanh(beta), Z = 2^N cosh(beta)^3N (1 + t^4 sum_p prod_p J + O(t^6)):
+    closed loops of the expansion are plaquettes first (the shortest winding
+    loops have length L = 6).  PA on a linear schedule to beta = 0.2 must give
+    beta F~ = -ln Z and <E> = -d ln Z / d beta within its statistical error
+    (Sec. II.A, Eq. 9), and at every step the realised number of culled
+    replicas must match eps R, the expected count of Sec. III.C (a sum of
+    independent Bernoulli(1 - tau) trials, so within 5 sqrt(eps R))."""
+    L, R, bmax, n_t = 6, 30000, 0.2, 21
+    N = L ** 3
+    J = pa_inputs.couplings_pm(L, 5)
+    P = _plaquette_sum(L, J)
+    t = math.tanh(bmax)
+    lnZ = N * math.log(2.0) + 3 * N * math.log(math.cosh(bmax)) + t ** 4 * P
+    E_ht = -3 * N * t - 4 * t ** 3 * (1 - t * t) * P
+    p = oracle.Population(L, J, R, seed=105)
+    for k in range(1, n_t):
+        b = bmax * k / (n_t - 1)
+        p.resample(b)
+        eps, culled = p.last["eps"], p.last["n_culled"]
+        assert abs(culled - eps * R) <= 5 * math.sqrt(eps * R) + 1, (k, culled, eps * R)
+        p.sweep(b, 10)
+    r = p.observables()
+    # statistics (rho_f <= rho_t - 1, Sec. III.B) plus the neglected t^6 loops
+    tol_F = 4 * math.sqrt(max(r.rho_t - 1.0, 1.0) / R) + r.rho_t / (2 * R) + 0.02
+    assert abs(r.beta_F + lnZ) <= tol_F, (r.beta_F, -lnZ)
+    tol_E = 5 * math.sqrt(3 * N * r.rho_t / R) + 0.05
+    assert abs(r.mean_E - E_ht) <= tol_E, (r.mean_E, E_ht)
+
+
 def test_high_temperature_family_growth(oracle_lib):
     """MCMC-equilibrated regime, constant eps: rho_t - 1 = 2 eps k (Sec. III.E)
     and a geometric family-size law P_eta(k) (same section)."""
