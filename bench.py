@@ -113,8 +113,25 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
 
 
-def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None, anneals=None):
+def event_pairs(n):
+    """n pairs of timing events, each recorded once so that its HIP event
+    exists before a timed region (torch creates it at the first record)."""
+    import torch
+
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(n)]
+    for e0, e1 in pairs:
+        e0.record()
+        e1.record()
+    torch.cuda.synchronize()
+    return pairs
+
+
+def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None, anneals=None,
+              event_pool=None):
     """n_steps temperature steps; a new population at beta = 0 whenever beta_max is hit.
+    sweep_events (list, optional) receives (start, end, R~) per sweep launch, the
+    events taken in order from event_pool (made by event_pairs) when given;
     anneals (list, optional) receives the step count of every anneal completed."""
     import torch
 
@@ -136,8 +153,11 @@ def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None, anneals=
         b = pop.choose_beta(w["eps"], w["beta_max"])
         st = pop.resample(b)
         if sweep_events is not None:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
+            if event_pool is not None:
+                e0, e1 = event_pool[len(sweep_events)]
+            else:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
             e0.record(pop.stream)
             pop.sweep(b, w["n_sweeps"])
             e1.record(pop.stream)
@@ -344,9 +364,10 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
         tp.close()
     run_steps(pam, K, w, warmup, seed0 + 1000)
     events, stats, anneals = [], [], []
+    pool = event_pairs(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    attempts = run_steps(pam, K, w, steps, seed0, events, stats, anneals)
+    attempts = run_steps(pam, K, w, steps, seed0, events, stats, anneals, pool)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     r = sweep_roofline(w, events, OPS_PER_ATTEMPT_GAUSS)
@@ -474,9 +495,10 @@ def main():
     torch.cuda.synchronize()
     print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
     events, stats, anneals = [], [], []
-    t0 = time.perf_counter()
+    pool = event_pairs(args.steps)
     torch.cuda.synchronize()
-    attempts = run_steps(pam, J, w, args.steps, seed0, events, stats, anneals)
+    t0 = time.perf_counter()
+    attempts = run_steps(pam, J, w, args.steps, seed0, events, stats, anneals, pool)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
