@@ -296,6 +296,15 @@ int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t 
 /* Forget every autotuned choice (back to the built-in rule). */
 int pa_autotune_reset(void);
 
+/* Pin the sweep form for a shape instead of timing it: launches of the
+ * coupling model (PA_MODEL_*), spin layout (PA_LAYOUT_INT8 or
+ * PA_LAYOUT_BITPACK64), L and size class of `tiles` (floor(log2(tiles)),
+ * tiles = ceil(R~ / 64)) use `split` waves per tile (4 or 8) in this process,
+ * until pa_autotune_reset or another choice for the same shape.  The results
+ * do not depend on it.  PA_EINVAL on an unknown model or layout, L outside
+ * [4, 16] or odd, tiles = 0, or another split. */
+int pa_autotune_set(uint32_t model, uint32_t layout, uint32_t L, uint64_t tiles, uint32_t split);
+
 /* ------------------------------------------------------------------------ */
 /* Diagnostics: this device's ceilings for the sweep's roofline.             */
 /* ------------------------------------------------------------------------ */

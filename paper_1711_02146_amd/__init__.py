@@ -116,6 +116,8 @@ def lib():
         "pa_autotune_sweep": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32,
                                              _vp, _vp]),
         "pa_autotune_reset": (ctypes.c_int, []),
+        "pa_autotune_set": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.c_uint64, ctypes.c_uint32]),
         "pa_probe_scratch_bytes": (ctypes.c_size_t, []),
         "pa_make_couplings_pm": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, _vp]),
         "pa_probe_ceilings": (ctypes.c_int, [_vp, ctypes.c_size_t, _vp, _P(pa_ceilings)]),
@@ -134,7 +136,7 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_batch_create", "pa_batch_run", "pa_batch_results", "pa_batch_free",
             "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
             "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset", "pa_probe_scratch_bytes",
-            "pa_probe_ceilings", "pa_make_couplings_pm"]
+            "pa_probe_ceilings", "pa_make_couplings_pm", "pa_autotune_set"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -312,6 +314,14 @@ def pa_autotune_sweep(handle: int, beta: float = 1.0, n_sweeps: int = 10, repeat
 
 def pa_autotune_reset():
     _check(lib().pa_autotune_reset(), "pa_autotune_reset")
+
+
+def pa_autotune_set(L: int, R_tilde: int, split: int, layout: str = "bitpack64",
+                    model: str = "pm"):
+    """Pin the sweep form (4 or 8 waves per tile) for populations of this shape."""
+    tiles = (int(R_tilde) + 63) // 64
+    _check(lib().pa_autotune_set(MODELS[model], LAYOUTS[layout], int(L), tiles, int(split)),
+           "pa_autotune_set")
 
 
 def pa_probe_ceilings(stream=None, device=None) -> dict:

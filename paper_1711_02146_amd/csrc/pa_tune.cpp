@@ -46,6 +46,16 @@ void sweep_split_record(uint32_t model, uint32_t layout, uint32_t L, uint64_t ti
 
 }  // namespace pa
 
+extern "C" int pa_autotune_set(uint32_t model, uint32_t layout, uint32_t L, uint64_t tiles,
+                               uint32_t split) {
+  if (model != PA_MODEL_PM && model != PA_MODEL_GAUSS16) return PA_EINVAL;
+  if (layout != PA_LAYOUT_INT8 && layout != PA_LAYOUT_BITPACK64) return PA_EINVAL;
+  if (L < 4 || L > (uint32_t)pa::kMaxL || (L & 1u) || tiles == 0) return PA_EINVAL;
+  if (split != 4 && split != 8) return PA_EINVAL;
+  pa::sweep_split_record(model, layout, L, tiles, split);
+  return PA_OK;
+}
+
 extern "C" int pa_autotune_reset(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_table.clear();

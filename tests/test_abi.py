@@ -74,3 +74,15 @@ def test_make_couplings_pm_host_call():
     assert pam.lib().pa_make_couplings_pm(1, 1, None) == pam.PA_EINVAL
     with pytest.raises(pam.PAError):
         pam.pa_make_couplings_pm(1, 3)
+
+
+def test_autotune_set_checks_its_arguments():
+    """Pinning a sweep form is host bookkeeping (no GPU work)."""
+    import paper_1711_02146_amd as pam
+
+    lib = pam.lib()
+    assert lib.pa_autotune_set(0, 2, 10, 7813, 8) == pam.PA_OK
+    for bad in ((2, 2, 10, 7813, 8), (0, 0, 10, 7813, 8), (0, 2, 5, 7813, 8), (0, 2, 18, 7813, 8),
+                (0, 2, 10, 0, 8), (0, 2, 10, 7813, 6)):
+        assert lib.pa_autotune_set(*bad) == pam.PA_EINVAL, bad
+    assert lib.pa_autotune_reset() == pam.PA_OK

@@ -336,3 +336,18 @@ def test_sweep_parity_large_lattices(pam, layout, L, R):
     _compare_obs(g.observables(), o.observables(), 1)
     assert_state(g, o, f"L={L} resampled and swept")
     g.close()
+
+
+@pytest.mark.parametrize("split", [4, 8])
+def test_full_size_l10_r500k_bitpack_both_forms(pam, split):
+    """The full-size first step in both launch configurations the benchmark
+    may time: its autotuner picks 4 or 8 waves per tile for this shape, by
+    device and run, so each form is pinned here in turn."""
+    L, R = 10, 500000
+    pam.pa_autotune_reset()
+    try:
+        pam.pa_autotune_set(L, R, split, layout="bitpack64")
+        _first_step_sampled(pam, L, R, "bitpack64", pa_inputs.population_seed(3, 0, 0),
+                            pa_inputs.coupling_seed(3, 0), adaptive=True)
+    finally:
+        pam.pa_autotune_reset()
