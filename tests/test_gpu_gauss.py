@@ -145,12 +145,16 @@ def test_two_populations_overlap(pam):
     gb.close()
 
 
-def test_full_size_l10_sampled_first_step(pam):
-    """L = 10, R = 2e5, bit-packed, constant culling: the first step in full
-    (table, counts, offsets, labels) and 192 sampled replicas swept by the oracle."""
-    L, R = 10, 200000
+@pytest.mark.parametrize("split", [4, 8])
+def test_full_size_l10_sampled_first_step(pam, split):
+    """The benchmark's Gaussian workload, L = 10, R = 5e5, bit-packed, constant
+    culling, in each sweep form its autotuner may pick: the first step in full
+    (counts, offsets, labels) and 192 sampled replicas swept by the oracle."""
+    L, R = 10, 500000
     N = L ** 3
     K = pa_inputs.couplings_gauss16(L, 3)
+    pam.pa_autotune_reset()
+    pam.pa_autotune_set(L, R, split, layout="bitpack64", model="gauss16")
     g = pam.Population(L, R, K, 42, layout="bitpack64", model="gauss16")
     o = oracle.GaussPopulation(L, K, R, 42)
     s, u, f = g.export_state()
@@ -181,6 +185,7 @@ def test_full_size_l10_sampled_first_step(pam):
     np.testing.assert_array_equal(u2.view(np.int32), oracle.g_energy(L, K, s2))
     assert g.observables()["R_tilde"] == Rn
     g.close()
+    pam.pa_autotune_reset()
 
 
 def test_gauss_rejected_by_batches_and_steppers(pam):
