@@ -88,6 +88,7 @@ def lib():
         "pao_sum_eta2": (_c.c_uint64, [_u32p, _c.c_int64, _c.c_uint32]),
         "pao_family_sizes": (None, [_u32p, _c.c_int64, _c.c_uint32, _c.c_int, _u64p]),
         "pao_overlap_hist": (None, [_c.c_int, _i8p, _c.c_int64, _i8p, _c.c_int64, _u64p, _u32p]),
+        "pao_link_overlap": (None, [_c.c_int, _i8p, _c.c_int64, _i8p, _c.c_int64, _u32p]),
         "pao_density_of_states": (_c.c_int, [_c.c_int, _i8p, _u64p]),
         "pao_g_energy": (None, [_c.c_int, _i8p, _i8p, _c.c_int64, _i32p]),
         "pao_g_thresholds": (None, [_c.c_double, _c.c_int, _u64p]),
@@ -223,6 +224,19 @@ def overlap_hist(N: int, spins_a: np.ndarray, spins_b: np.ndarray):
     lib().pao_overlap_hist(N, np.ascontiguousarray(spins_a, np.int8), Ra,
                            np.ascontiguousarray(spins_b, np.int8), Rb, hist, d)
     return hist, d
+
+
+def link_overlap(L: int, spins_a: np.ndarray, spins_b: np.ndarray):
+    """Link overlap of replica i of a with replica i of b (Sec. II.A): D[i]
+    bonds with s^a_n s^a_m s^b_n s^b_m = -1, q_l = 1 - 2 D / (3N), and the
+    counts of D = 0..3N."""
+    N = L ** 3
+    n = min(spins_a.size // N, spins_b.size // N)
+    D = np.zeros(n, np.uint32)
+    lib().pao_link_overlap(L, np.ascontiguousarray(spins_a, np.int8), spins_a.size // N,
+                           np.ascontiguousarray(spins_b, np.int8), spins_b.size // N, D)
+    hist = np.bincount(D, minlength=3 * N + 1).astype(np.uint64)
+    return hist, D
 
 
 def density_of_states(L: int, J: np.ndarray) -> np.ndarray:

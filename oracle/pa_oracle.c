@@ -483,6 +483,38 @@ void pao_overlap_hist(int N, const int8_t* spins_a, int64_t Ra, const int8_t* sp
 }
 
 /* ------------------------------------------------------------------------ */
+/* Link overlap (Sec. II.A): for replica i of population a and replica i of  */
+/* population b, q_l = (1/N_b) sum over the N_b = 3N bonds <n,m> of          */
+/* s^a_n s^a_m s^b_n s^b_m.  Each term is +1 or -1, so the sum is N_b - 2 D  */
+/* with D the number of bonds whose term is -1; D_out[i] receives D.  The    */
+/* bonds are those of the periodic cubic lattice: every site with its +x, +y */
+/* and +z neighbour (site = x + L (y + L z)).                                 */
+/* ------------------------------------------------------------------------ */
+void pao_link_overlap(int L, const int8_t* spins_a, int64_t Ra, const int8_t* spins_b, int64_t Rb,
+                      uint32_t* D_out) {
+  int64_t n = Ra < Rb ? Ra : Rb;
+  int N = L * L * L;
+  for (int64_t i = 0; i < n; ++i) {
+    const int8_t* sa = spins_a + i * N;
+    const int8_t* sb = spins_b + i * N;
+    uint32_t D = 0;
+    for (int z = 0; z < L; ++z)
+      for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+          int site = x + L * (y + L * z);
+          int nb[3] = {(x + 1) % L + L * (y + L * z), x + L * ((y + 1) % L + L * z),
+                       x + L * (y + L * ((z + 1) % L))};
+          for (int d = 0; d < 3; ++d) {
+            int m = nb[d];
+            int term = sa[site] * sa[m] * sb[site] * sb[m];
+            if (term < 0) D += 1;
+          }
+        }
+    D_out[i] = D;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exact density of states for a small lattice (N <= 30) by enumerating all */
 /* 2^N states in Gray-code order: consecutive states differ by one spin, so */
 /* U changes by (number of that spin's bonds made unsatisfied) minus        */

@@ -474,3 +474,71 @@ def test_high_temperature_family_growth(oracle_lib):
         expect = ek ** (eta - 1) / (1 + ek) ** (eta + 1)
         assert sizes[eta] == pytest.approx(expect, rel=0.1, abs=0.004)
     assert sizes[0] == pytest.approx(ek / (1 + ek), rel=0.1)
+
+
+# ---------------------------------------------------------------------------
+# Link overlap q_l (Sec. II.A): configurations whose bond count D is known by
+# construction, and the identity D(a, b) = unsatisfied bonds of a*b in the
+# ferromagnet, which goes through the oracle's separately written energy
+# (itself pinned by exact enumeration above)
+# ---------------------------------------------------------------------------
+def _flip(s, L, *sites):
+    t = s.copy()
+    for (x, y, z) in sites:
+        t[x + L * (y + L * z)] *= -1
+    return t
+
+
+@pytest.mark.parametrize("L", [3, 4, 6])
+def test_link_overlap_known_configurations(oracle_lib, L):
+    N = L ** 3
+    rng = np.random.default_rng(L)
+    a = rng.choice(np.array([-1, 1], np.int8), N)
+    x, y, z = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    stagger = np.where((x + y + z) % 2 == 0, 1, -1).astype(np.int8)
+    stagger = stagger.transpose(2, 1, 0).reshape(-1)  # index x + L (y + L z)
+    cases = [
+        (a, 0),                                              # the same configuration: q_l = 1
+        (-a, 0),                                             # global flip: q_l = 1
+        (_flip(a, L, (1, 1, 1)), 6),                         # one spin: its six bonds
+        (_flip(a, L, (1, 1, 1), (2, 1, 1)), 10),             # x neighbours share one bond
+        (_flip(a, L, (1, 1, 1), (1, 2, 1)), 10),             # y neighbours
+        (_flip(a, L, (1, 1, 1), (1, 1, 2)), 10),             # z neighbours
+        (_flip(a, L, (0, 1, 1), (L - 1, 1, 1)), 10),         # x neighbours across the boundary
+        (_flip(a, L, (1, 0, 1), (1, L - 1, 1)), 10),         # y across the boundary
+        (_flip(a, L, (1, 1, 0), (1, 1, L - 1)), 10),         # z across the boundary
+    ]
+    if L >= 4:
+        cases.append((_flip(a, L, (0, 0, 0), (2, 2, 2)), 12))  # two far apart: 6 + 6
+    if L % 2 == 0:
+        cases.append((a * stagger, 3 * N))                   # staggered: every bond, q_l = -1
+    A = np.stack([a] * len(cases))
+    B = np.stack([c for c, _ in cases])
+    hist, D = oracle.link_overlap(L, A.reshape(-1), B.reshape(-1))
+    assert D.tolist() == [d for _, d in cases]
+    assert int(hist.sum()) == len(cases) and hist.size == 3 * N + 1
+    q_l = 1.0 - 2.0 * D / (3 * N)
+    assert q_l[0] == 1.0 and q_l[1] == 1.0
+    if L % 2 == 0:
+        assert q_l[-1] == -1.0
+
+
+@pytest.mark.parametrize("L", [4, 5, 8])
+def test_link_overlap_is_ferro_energy_of_product(oracle_lib, L):
+    N = L ** 3
+    rng = np.random.default_rng(100 + L)
+    R = 64
+    a = rng.choice(np.array([-1, 1], np.int8), (R, N))
+    b = rng.choice(np.array([-1, 1], np.int8), (R, N))
+    _, D = oracle.link_overlap(L, a.reshape(-1), b.reshape(-1))
+    ferro = np.ones(3 * N, np.int8)
+    U = oracle.energy(L, ferro, (a * b).reshape(-1))
+    np.testing.assert_array_equal(D, U)
+    # a gauge transformation of both replicas leaves every bond term unchanged
+    tau = rng.choice(np.array([-1, 1], np.int8), N)
+    _, Dg = oracle.link_overlap(L, (a * tau).reshape(-1), (b * tau).reshape(-1))
+    np.testing.assert_array_equal(Dg, D)
+    # unequal population sizes: the first min(Ra, Rb) pairs
+    hist, Dm = oracle.link_overlap(L, a[:40].reshape(-1), b.reshape(-1))
+    np.testing.assert_array_equal(Dm, D[:40])
+    assert int(hist.sum()) == 40
