@@ -38,6 +38,9 @@ GAUSS_WORKLOAD = dict(name="L10_R500k_bitpack64_gauss16_adaptive_eps0.1", L=10, 
 # Peak figures of one MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz
 # retire 39.3e12 full-rate 32-bit VALU lane-operations per second; HBM3E 8 TB/s.
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# link overlap: per bond and pair, the XOR of the two ends' x words, the
+# extraction of the pair's bit and its addition to the count
+LINK_OPS_PER_BOND = 3
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic work of one spin-flip attempt, in 32-bit lane operations:
@@ -64,11 +67,13 @@ BYTES_PER_REPLICA_FIXED = 20
 # copy of known size reads), per launch, with the source it was taken on.
 # Reported only while the kernel source is unchanged.
 TRAFFIC = {
-    "kernel_src_sha256": "d473ffdba9f7ef7c7ed5e10709a5d71ec70fff1b89c42e41424f67c67f3a730b",
-    # 33229.6 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
-    "bytes_per_launch": (33229.6 * 2 + 64942.3) * 1024,
-    # the same for the Gaussian-coupling sweep: 32976.4 x 2 + 64952.2 KiB
-    "gauss16_bytes_per_launch": (32976.4 * 2 + 64952.2) * 1024,
+    "kernel_src_sha256": "6725499b96bae221c02b60ce0d1890457dd2533dcd86160f8f76cba76187f855",
+    # 33241.8 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
+    "bytes_per_launch": (33241.8 * 2 + 64942.3) * 1024,
+    # the same for the Gaussian-coupling sweep: 32884.1 x 2 + 64951.6 KiB
+    "gauss16_bytes_per_launch": (32884.1 * 2 + 64951.6) * 1024,
+    # k_link_overlap at L=10, 5e5 pairs: 61562.6 x 2 + 10484.4 KiB
+    "link_overlap_bytes_per_launch": (61562.6 * 2 + 10484.4) * 1024,
     "profile": "profiles/k_sweep_L10_R500k_bitpack64_hbm_counters.md",
 }
 
@@ -371,9 +376,11 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     r = sweep_roofline(w, events, OPS_PER_ATTEMPT_GAUSS)
+    link = link_overlap_bench(pam, K, w)
     traffic = None
     if TRAFFIC is not None and TRAFFIC["kernel_src_sha256"] == kernel_src_sha256():
         traffic = TRAFFIC["gauss16_bytes_per_launch"]
+        link["traffic"] = TRAFFIC["link_overlap_bytes_per_launch"]
     return {
         "workload": w["name"], "couplings": "Gaussian N(0,1) rounded to 1/16, k in [-127, 127]",
         "value": attempts / wall, "unit": "attempts/s", "steps": steps, "warmup": warmup,
@@ -392,7 +399,47 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
         "anneals_completed": len(anneals),
         "steps_per_anneal": anneals,
         "beta_at_end": stats[-1][0] if stats else None,
+        "link_overlap": link,
     }
+
+
+def link_overlap_bench(pam, K, w, repeats: int = 5):
+    """The link-overlap histogram (Sec. II.A q_l) between two independent
+    populations of the Gaussian workload's size after N_S sweeps at beta = 0.3:
+    HIP events on the populations' stream around each call (the call clears
+    the partial counts, runs k_link_overlap and k_link_reduce, and copies the
+    3N + 1 counts back)."""
+    import numpy as np
+
+    import pa_inputs
+
+    seed = pa_inputs.population_seed(3, 0, 1)
+    a = pam.Population(w["L"], w["R"], K, seed, layout=w["layout"], model=w["model"])
+    b = pam.Population(w["L"], w["R"], K, seed + 1, layout=w["layout"], model=w["model"])
+    for p in (a, b):
+        p.sweep(0.3, w["n_sweeps"])
+    pam.link_overlap_hist(a, b)
+    ms = []
+    for e0, e1 in event_pairs(repeats):
+        e0.record(a.stream)
+        h = pam.link_overlap_hist(a, b)
+        e1.record(a.stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    pairs = int(h.sum())
+    N = w["L"] ** 3
+    q_l = float(1.0 - 2.0 * (h * np.arange(h.size)).sum() / (pairs * 3 * N))
+    a.close()
+    b.close()
+    avg = sum(ms) / len(ms)
+    ops = LINK_OPS_PER_BOND * 3 * N * pairs
+    return {"kernel": "k_link_overlap<bitpack64> (one 64-pair tile per wave)", "pairs": pairs,
+            "avg_call_ms": avg, "pairs_per_s": pairs / (avg * 1e-3),
+            "ops_per_bond": LINK_OPS_PER_BOND, "achieved": ops / (avg * 1e-3) / 1e12,
+            "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+            "frac": ops / (avg * 1e-3) / VALU_PEAK_OPS,
+            "algorithmic_bytes": 2 * pairs * N // 8, "traffic": None, "q_l_mean": q_l,
+            "beta": 0.3}
 
 
 def gauss_cpu_baseline(w, R_sample=100000, n_steps=3):

@@ -11,8 +11,8 @@
  *                 normaliser Q, nearest-integer copy counts, family labels
  *                 passed to the copies) and then decorrelated by MCMC sweeps.
  *   Sec. II.A     the model H = -sum J_nm s_n s_m on the periodic cubic
- *                 lattice, the population averages, the spin overlap q, and
- *                 the free-energy estimator (Eq. 9).
+ *                 lattice, the population averages, the spin overlap q, the
+ *                 link overlap q_l, and the free-energy estimator (Eq. 9).
  *   Sec. III.A    the family statistic rho_t.
  *   Sec. III.C    the culling fraction and the constant-culling step size.
  *
@@ -34,7 +34,7 @@
  * the HIP stream.  libpa never allocates device memory; it allocates a little
  * pinned host memory per instance for staging, released by pa_free.
  * Ordering: calls on one instance are stream-ordered; pa_resample,
- * pa_choose_beta, pa_observables, pa_overlap_hist and the export/import calls
+ * pa_choose_beta, pa_observables, the two overlap calls and the export/import calls
  * synchronise the instance's stream before they return.  One host thread per
  * instance at a time.
  * Errors: every call returns a status; nothing aborts.  After PA_EDEVICE the
@@ -156,6 +156,17 @@ int pa_observables(pa_instance* in, pa_obs* out);
  * sites, bin = (128 (N - d) + N) / (2N) (round-half-up of 64 (1+q)/2).
  * nbins must be 65; hist_out receives 65 counts.  Synchronises. */
 int pa_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hist_out);
+
+/* Link-overlap histogram between slot i of population a and slot i of
+ * population b, i < min(R~_a, R~_b) (Sec. II.A link overlap q_l over the
+ * N_b = 3N bonds; the two populations must share L, layout and couplings;
+ * either model).  With x_n = s^a_n s^b_n, a bond <n,m> contributes
+ * x_n x_m, so q_l = 1 - 2 D / N_b where D counts the bonds whose two ends
+ * have different x.  nbins must be 3N + 1; hist_out (caller-owned, nbins
+ * entries) receives hist_out[D] = the number of pairs with that D.
+ * PA_EINVAL for a == b, different L or layout, a wrong nbins or a null
+ * hist_out; PA_ESTATE for an unusable instance.  Synchronises. */
+int pa_link_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hist_out);
 
 /* Copy the current population to the host in the canonical layout.
  * spins_host: R~ * N int8 (+1/-1), [replica][site]; U_host, family_host: R~

@@ -94,6 +94,7 @@ def lib():
                                           _P(ctypes.c_double)]),
         "pa_observables": (ctypes.c_int, [_vp, _P(pa_obs)]),
         "pa_overlap_hist": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp]),
+        "pa_link_overlap_hist": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp]),
         "pa_export_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, _P(ctypes.c_uint32)]),
         "pa_export_counts": (ctypes.c_int, [_vp, _vp, _vp, _P(ctypes.c_uint32)]),
         "pa_import_state": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_uint32, ctypes.c_uint64,
@@ -136,7 +137,8 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_batch_create", "pa_batch_run", "pa_batch_results", "pa_batch_free",
             "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
             "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset", "pa_probe_scratch_bytes",
-            "pa_probe_ceilings", "pa_make_couplings_pm", "pa_autotune_set"]
+            "pa_probe_ceilings", "pa_make_couplings_pm", "pa_autotune_set",
+            "pa_link_overlap_hist"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -188,6 +190,12 @@ def pa_observables(handle: int) -> dict:
 def pa_overlap_hist(a: int, b: int, nbins: int = 65) -> np.ndarray:
     h = np.zeros(nbins, np.uint64)
     _check(lib().pa_overlap_hist(a, b, nbins, h.ctypes.data), "pa_overlap_hist")
+    return h
+
+
+def pa_link_overlap_hist(a: int, b: int, nbins: int) -> np.ndarray:
+    h = np.zeros(nbins, np.uint64)
+    _check(lib().pa_link_overlap_hist(a, b, nbins, h.ctypes.data), "pa_link_overlap_hist")
     return h
 
 
@@ -404,6 +412,12 @@ class Population:
 
 def overlap_hist(a: Population, b: Population) -> np.ndarray:
     return pa_overlap_hist(a.handle, b.handle, 65)
+
+
+def link_overlap_hist(a: Population, b: Population) -> np.ndarray:
+    """Counts of D = 0..3N over the slot pairs (i, i) of a and b: D bonds whose
+    two ends differ in s^a s^b, i.e. link overlap q_l = 1 - 2 D / (3N)."""
+    return pa_link_overlap_hist(a.handle, b.handle, 3 * a.N + 1)
 
 
 class Batch:

@@ -14,6 +14,10 @@
     run; g0~(beta), the fraction of the population at E0~; and the Boltzmann
     estimate g0_bar = d exp(-beta E0~ + beta F~) with d the ground-state
     degeneracy (2 for continuous couplings).
+  * The link overlap q_l and the Katzgraber-Young equilibration measure
+    (Sec. II.A): <q_l> over the pairs of two independent populations,
+    e_l = -beta (N_b / N) (1 - <q_l>), and e_l - e, whose average over Gaussian
+    disorder samples, Delta_KY, vanishes in equilibrium.
 
 Every step runs in the library's kernels; this module only schedules calls and
 reduces the per-step scalars they return.
@@ -60,6 +64,39 @@ def ground_state_estimates(E_min_steps, n_at_E_min_steps, R_tilde_steps, betas, 
     g_tilde = np.where(E == E0, n / Rt, 0.0)
     g_bar = degeneracy * np.exp(-b * E0 + bF)
     return E0, g_tilde, g_bar
+
+
+def link_overlap_mean(hist, N: int) -> float:
+    """<q_l> over the pairs of a link-overlap histogram: hist[D] pairs with D
+    of the N_b = 3N bonds differing, q_l = 1 - 2 D / N_b."""
+    h = np.asarray(hist, dtype=np.float64)
+    if h.size != 3 * N + 1 or h.sum() == 0:
+        raise ValueError("need a non-empty histogram of 3N + 1 bins")
+    D = np.arange(h.size, dtype=np.float64)
+    return float(1.0 - 2.0 * (h * D).sum() / (h.sum() * 3 * N))
+
+
+def katzgraber_young(beta: float, e: float, q_l: float, coupling_variance: float = 1.0):
+    """e_l = -beta sigma^2 (N_b / N) (1 - <q_l>) with N_b / N = 3 on the cubic
+    lattice, and e_l - e for one disorder sample (e: energy per spin).  The
+    paper's form has sigma^2 = 1 (unit-variance Gaussian couplings); the
+    relation comes from Gaussian integration by parts, so couplings of
+    variance sigma^2 scale it by sigma^2.  Averaged over samples, e_l - e is
+    Delta_KY."""
+    e_l = -beta * coupling_variance * 3.0 * (1.0 - q_l)
+    return e_l, e_l - e
+
+
+def quantised_gauss_variance(quantum: float = 1.0 / 16.0, kmax: int = 127) -> float:
+    """Variance of a unit normal rounded to multiples of `quantum` and clipped
+    to +-kmax quanta (the PA_MODEL_GAUSS16 couplings): sum over k of
+    (k quantum)^2 times the normal mass of the k-th rounding interval."""
+    k = np.arange(-kmax, kmax + 1, dtype=np.float64)
+    lo = np.where(k == -kmax, -np.inf, (k - 0.5) * quantum)
+    hi = np.where(k == kmax, np.inf, (k + 0.5) * quantum)
+    cdf = np.vectorize(lambda x: 0.5 * math.erfc(-x / math.sqrt(2.0)))
+    mass = cdf(hi) - cdf(lo)
+    return float(((k * quantum) ** 2 * mass).sum())
 
 
 def paper_sweep_schedule(beta: float) -> int:
@@ -158,6 +195,38 @@ def rho_f_study(runs: dict, R: int):
     eps = runs["eps_expected"][ok].mean(axis=0)
     return {"rho_f": rf, "rho_f_err": drf, "rho_t": rt, "eps": eps,
             "rho_f_predicted": rho_f_predicted(rt, eps), "runs": int(ok.sum())}
+
+
+def link_overlap_run(L: int, J, seeds, betas, n_sweeps=10, model: str = "gauss16",
+                     layout: str = "bitpack64", R: int = 2000):
+    """Two independent populations of one disorder sample (seeds[0], seeds[1])
+    through one schedule; after every step <q_l> between them, e (the two
+    populations' mean energy per spin), e_l and e_l - e (Sec. II.A).  J: the
+    couplings in the model's form (k = 16 J for "gauss16").  Returns a dict of
+    per-step arrays."""
+    import paper_1711_02146_amd as pam
+
+    N = L ** 3
+    var = quantised_gauss_variance() if model == "gauss16" else 1.0
+    pops = [pam.Population(L, R, J, s, layout=layout, model=model) for s in seeds[:2]]
+    out = {k: [] for k in ("beta", "q_l", "e", "e_l", "delta")}
+    try:
+        for k in range(1, len(betas)):
+            b = float(betas[k])
+            es = []
+            for p in pops:
+                p.resample(b)
+                p.sweep(b, n_sweeps(b) if callable(n_sweeps) else n_sweeps)
+                es.append(p.observables()["mean_E"] / N)
+            q = link_overlap_mean(pam.link_overlap_hist(pops[0], pops[1]), N)
+            e = 0.5 * (es[0] + es[1])
+            e_l, d = katzgraber_young(b, e, q, var)
+            for key, v in zip(("beta", "q_l", "e", "e_l", "delta"), (b, q, e, e_l, d)):
+                out[key].append(v)
+    finally:
+        for p in pops:
+            p.close()
+    return {k: np.asarray(v) for k, v in out.items()}
 
 
 def equilibrate(L: int, J, seed: int, R0: int, betas, n_sweeps=10, layout: str = "bitpack64",

@@ -92,6 +92,8 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.off_rowk = take((size_t)2 * l.L * l.L * l.rowk_stride);
   l.off_gthr = take((size_t)(pa::kGaussDEMax + 1) * 8);
   l.off_ovl = take(65 * 8);
+  l.off_lovl = take((size_t)(3 * l.N + 1) * 8);
+  l.off_lpart = take((size_t)pa::kLinkCopies * (3 * l.N + 1) * 4);
   l.off_sc = take(sizeof(DevScalars));
   l.off_pops = take(2 * sizeof(DevPop));
   l.off_meta = take(sizeof(MetaU32));
@@ -478,6 +480,8 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   P.cm_of_site = reinterpret_cast<const uint16_t*>(w + l.off_cm);
   P.rowj = reinterpret_cast<const unsigned long long*>(w + l.off_rowj);
   P.ovl_hist = reinterpret_cast<unsigned long long*>(w + l.off_ovl);
+  P.lovl_hist = reinterpret_cast<unsigned long long*>(w + l.off_lovl);
+  P.lovl_part = reinterpret_cast<uint32_t*>(w + l.off_lpart);
   P.sc = reinterpret_cast<DevScalars*>(w + l.off_sc);
   P.model = l.model;
   P.rowk_stride = l.rowk_stride;
@@ -504,6 +508,8 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
       hipHostMalloc(reinterpret_cast<void**>(&in->h_T), (size_t)l.n_levels * 8) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_sc), sizeof(DevScalars)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_ovl), 65 * 8) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&in->h_lovl), (size_t)(3 * l.N + 1) * 8) !=
+          hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_meta), sizeof(MetaU32)) != hipSuccess)
     return fail(PA_EDEVICE);
   if (l.model == PA_MODEL_GAUSS16 &&
@@ -552,6 +558,7 @@ int pa_free(pa_instance* in) {
   if (in->h_T) (void)hipHostFree(in->h_T);
   if (in->h_sc) (void)hipHostFree(in->h_sc);
   if (in->h_ovl) (void)hipHostFree(in->h_ovl);
+  if (in->h_lovl) (void)hipHostFree(in->h_lovl);
   if (in->h_meta) (void)hipHostFree(in->h_meta);
   if (in->h_gthr) (void)hipHostFree(in->h_gthr);
   if (in->gthr_copied) (void)hipEventDestroy(in->gthr_copied);
@@ -762,6 +769,27 @@ int pa_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hi
   PA_HIP(a, hipMemcpyAsync(a->h_ovl, a->dev.ovl_hist, 65 * 8, hipMemcpyDeviceToHost, a->stream));
   PA_HIP(a, hipStreamSynchronize(a->stream));
   for (int i = 0; i < 65; ++i) hist_out[i] = a->h_ovl[i];
+  return PA_OK;
+}
+
+int pa_link_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hist_out) {
+  if (!usable(a) || !usable(b)) return PA_ESTATE;
+  if (!hist_out || a == b) return PA_EINVAL;
+  if (a->dev.L != b->dev.L || a->dev.layout != b->dev.layout) return PA_EINVAL;
+  if (nbins != 3 * a->dev.N + 1) return PA_EINVAL;
+  int rc = materialize(a);
+  if (rc) return rc;
+  rc = materialize(b);
+  if (rc) return rc;
+  PA_HIP(b, hipStreamSynchronize(b->stream));
+  PA_HIP(a, pa::launch_fill_u32(a->dev.lovl_part, 0u, (size_t)pa::kLinkCopies * nbins,
+                                a->stream));
+  PA_HIP(a, pa::launch_link_overlap(a->dev, b->dev, a->cur, b->cur, a->dev.lovl_part,
+                                    a->dev.lovl_hist, a->stream));
+  PA_HIP(a, hipMemcpyAsync(a->h_lovl, a->dev.lovl_hist, (size_t)nbins * 8, hipMemcpyDeviceToHost,
+                           a->stream));
+  PA_HIP(a, hipStreamSynchronize(a->stream));
+  for (uint32_t i = 0; i < nbins; ++i) hist_out[i] = a->h_lovl[i];
   return PA_OK;
 }
 

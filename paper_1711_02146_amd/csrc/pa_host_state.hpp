@@ -34,7 +34,7 @@ struct Layout {
   size_t spins_bytes;
   size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
       off_bcull, off_hist, off_fl, off_T, off_sites, off_cm, off_rowj, off_rowk, off_gthr, off_ovl,
-      off_sc, off_pops, off_meta;
+      off_lovl, off_lpart, off_sc, off_pops, off_meta;
   size_t total;
 };
 
@@ -104,6 +104,7 @@ struct pa_instance {
   uint64_t* h_T = nullptr;
   pa::DevScalars* h_sc = nullptr;
   unsigned long long* h_ovl = nullptr;
+  unsigned long long* h_lovl = nullptr;  // 3N + 1 link-overlap counts
   pa_host::MetaU32* h_meta = nullptr;
   unsigned long long* h_gthr = nullptr;  // PA_MODEL_GAUSS16 threshold table staging
   hipEvent_t gthr_copied = nullptr;      // recorded after each copy out of h_gthr

@@ -30,6 +30,7 @@ constexpr int kBlockCounts = 256;  // slots per block in the copy-count / scatte
 constexpr int kHistSlots = 4096;   // slots per block of the histogram kernel
 constexpr int kWindowLdsLevels = 16384;  // largest E16 window counted in LDS (64 KiB)
 constexpr int kMaxL = 16;
+constexpr uint32_t kLinkCopies = 32;  // partial link-overlap histograms (see launch_link_overlap)
 // Energy models.  kModelPm: J = +-1, the energy word of a replica is U, the
 // number of unsatisfied bonds (E = 2U - 3N).  kModelGauss16: J = k / 16 with
 // k in [-127, 127], the energy word is E16 = -sum_b k_b s_i s_j (E = E16 / 16),
@@ -91,6 +92,8 @@ struct DevPop {
   const unsigned long long* rowj;  // 2 L^2 row words: bit 6q + k set iff the bond from
                                    // site q of row (colour, y, z) to neighbour k is -1
   unsigned long long* ovl_hist; // 65 bins, scratch of the overlap histogram
+  unsigned long long* lovl_hist;  // 3N + 1 bins, scratch of the link-overlap histogram
+  uint32_t* lovl_part;            // kLinkCopies x (3N + 1) partial link-overlap counts
   DevScalars* sc;
   uint32_t model;               // kModelPm or kModelGauss16
   uint32_t rowk_stride;         // kModelGauss16: bytes per row of rowk (6 L/2 rounded up to 4)
@@ -184,6 +187,12 @@ hipError_t launch_overlap(const BatchDev& B, const Group& pairs, const uint32_t*
                           hipStream_t stream);
 hipError_t launch_energy(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
                          uint32_t model, hipStream_t stream);
+// link-overlap histogram of slot i of a against slot i of b, i < min of their
+// R~ (read on the device): the pairs count into kLinkCopies partial histograms
+// part[kLinkCopies][3N + 1] (u32, cleared by the host first), which are then
+// summed into hist[D], D = 0..3N
+hipError_t launch_link_overlap(const DevPop& a, const DevPop& b, uint32_t cur_a, uint32_t cur_b,
+                               uint32_t* part, unsigned long long* hist, hipStream_t stream);
 // kModelGauss16: E_lo / E_hi of every member (zero_acc resets them first) and the
 // histogram h[E16 - E_lo] (global atomics; the host clears the window first),
 // both over the current buffer of a call on single instances

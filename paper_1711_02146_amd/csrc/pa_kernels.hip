@@ -971,8 +971,14 @@ __global__ __launch_bounds__(1024) void k_scan(BatchDev B, Group G) {
 
 // Offsets and the new-slot -> old-slot map of the order-preserving copy:
 // the n_i copies of old slot i take new slots offset_i .. offset_i + n_i - 1.
+// The block's new slots are written by all its threads together, slot j of
+// the block's range by thread j mod kBlockCounts: its source is the last old
+// slot t of the block whose exclusive offset is <= j (that slot has n_t > 0),
+// found by bisection over the offsets in LDS.  A step that gives one replica
+// many copies therefore costs no more than one that spreads them.
 __global__ __launch_bounds__(kBlockCounts) void k_scatter(BatchDev B, Group G) {
   __shared__ uint32_t scratch[kBlockCounts / kWave];
+  __shared__ uint32_t excl_s[kBlockCounts];
   const Member m = member_of(G);
   const DevPop P = B.pops[m.pop];
   if (P.sc->dead || P.sc->err) return;
@@ -981,10 +987,20 @@ __global__ __launch_bounds__(kBlockCounts) void k_scatter(BatchDev B, Group G) {
   const uint32_t n = i < R ? P.counts[i] : 0u;
   uint32_t total;
   const uint32_t excl = block_exclusive_scan<kBlockCounts>(n, &total, scratch);
-  if (i < R) {
-    const uint32_t off = P.block_offsets[m.lb] + excl;
-    P.offsets[i] = off;
-    for (uint32_t c = 0; c < n; ++c) P.src[off + c] = i;
+  const uint32_t base = P.block_offsets[m.lb];
+  if (i < R) P.offsets[i] = base + excl;
+  excl_s[threadIdx.x] = excl;
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < total; j += kBlockCounts) {
+    uint32_t lo = 0, hi = kBlockCounts;  // excl_s[lo] <= j < excl_s[hi] (excl_s[kBlockCounts] = total)
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (excl_s[mid] <= j)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    P.src[base + j] = m.lb * kBlockCounts + lo;
   }
 }
 
@@ -1259,6 +1275,108 @@ __global__ __launch_bounds__(64) void k_overlap(BatchDev B, Group G,
     if (hb[b]) atomicAdd(&out[b], (unsigned long long)hb[b]);
 }
 
+// Link-overlap histogram (Sec. II.A): slot i of population a against slot i
+// of population b, one 64-pair tile per wave.  With x_n = s^a_n s^b_n a bond
+// <n,m> contributes x_n x_m, so only the bonds whose ends differ in x count:
+// D = their number, q_l = 1 - 2 D / (3N), hist[D] += 1 per pair.  The tile's x
+// words go to LDS (colour-major, 64 pairs per site, 8N bytes); each lane then
+// reads the half word holding its pair.  For even L every bond joins a
+// colour-0 site to a colour-1 site, so the walk over the six bonds of every
+// colour-0 site counts each bond once.
+//
+// The colour-0 sites of row (y, z) sit at x = 2q + P, P = (y + z) & 1; their
+// +x and -x neighbours are ranks (q + P) and (q + P - 1) mod L/2 of the
+// colour-1 row (y, z), their y and z neighbours rank q of the colour-1 rows
+// (y +- 1, z) and (y, z +- 1).  Each bond costs one masked XOR (the lane's
+// bit of own ^ neighbour) and one popcount-accumulate.
+template <int L, int P>
+__device__ __forceinline__ uint32_t link_row(const uint32_t* own, const uint32_t* xr,
+                                             const uint32_t* py, const uint32_t* my,
+                                             const uint32_t* pz, const uint32_t* mz, uint32_t m,
+                                             uint32_t d) {
+  constexpr int H = L / 2;
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    const uint32_t o = own[2 * q];
+    const int qp = (q + P) % H, qm = (q + P + H - 1) % H;
+    d += __builtin_popcount((o ^ xr[2 * qp]) & m);
+    d += __builtin_popcount((o ^ xr[2 * qm]) & m);
+    d += __builtin_popcount((o ^ py[2 * q]) & m);
+    d += __builtin_popcount((o ^ my[2 * q]) & m);
+    d += __builtin_popcount((o ^ pz[2 * q]) & m);
+    d += __builtin_popcount((o ^ mz[2 * q]) & m);
+  }
+  return d;
+}
+
+template <int LAYOUT, int L>
+__global__ __launch_bounds__(64) void k_link_overlap(DevPop A, DevPop Bp, uint32_t cur_a,
+                                                     uint32_t cur_b,
+                                                     uint32_t* __restrict__ part) {
+  constexpr uint32_t H = L / 2, N = L * L * L;
+  __shared__ uint32_t xs[2 * N];  // site cm: words 2 cm (pairs 0..31), 2 cm + 1 (32..63)
+  const uint32_t tile = blockIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t n = min(A.sc->R_tilde, Bp.sc->R_tilde);
+  if (tile * 64 >= n) return;
+  if (LAYOUT == 2) {
+    const unsigned long long* a = static_cast<const unsigned long long*>(pick(A.spins, cur_a)) +
+                                  (size_t)tile * N;
+    const unsigned long long* b = static_cast<const unsigned long long*>(pick(Bp.spins, cur_b)) +
+                                  (size_t)tile * N;
+    for (uint32_t cm = lane; cm < N; cm += 64) {
+      const unsigned long long x = a[cm] ^ b[cm];
+      xs[2 * cm] = (uint32_t)x;
+      xs[2 * cm + 1] = (uint32_t)(x >> 32);
+    }
+  } else {
+    const int8_t* a = static_cast<const int8_t*>(pick(A.spins, cur_a)) + (size_t)tile * N * 64 + lane;
+    const int8_t* b = static_cast<const int8_t*>(pick(Bp.spins, cur_b)) + (size_t)tile * N * 64 + lane;
+#pragma unroll 8
+    for (uint32_t cm = 0; cm < N; ++cm) {
+      const unsigned long long x = __ballot(a[64 * (size_t)cm] != b[64 * (size_t)cm]);
+      if (lane == 0) {
+        xs[2 * cm] = (uint32_t)x;
+        xs[2 * cm + 1] = (uint32_t)(x >> 32);
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t* xh = xs + (lane >> 5);
+  const uint32_t m = 1u << (lane & 31u);
+  uint32_t d = 0;
+  for (uint32_t z = 0; z < (uint32_t)L; ++z) {
+    const uint32_t zp = z + 1 == (uint32_t)L ? 0 : z + 1, zm = z == 0 ? L - 1 : z - 1;
+    for (uint32_t y = 0; y < (uint32_t)L; ++y) {
+      const uint32_t yp = y + 1 == (uint32_t)L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+      const uint32_t* own = xh + whole_s(2 * H * (y + L * z));
+      const uint32_t* xr = xh + whole_s(2 * (N / 2 + H * (y + L * z)));
+      const uint32_t* py = xh + whole_s(2 * (N / 2 + H * (yp + L * z)));
+      const uint32_t* my = xh + whole_s(2 * (N / 2 + H * (ym + L * z)));
+      const uint32_t* pz = xh + whole_s(2 * (N / 2 + H * (y + L * zp)));
+      const uint32_t* mz = xh + whole_s(2 * (N / 2 + H * (y + L * zm)));
+      if ((y + z) & 1u)
+        d = link_row<L, 1>(own, xr, py, my, pz, mz, m, d);
+      else
+        d = link_row<L, 0>(own, xr, py, my, pz, mz, m, d);
+    }
+  }
+  // each tile counts into copy tile mod kLinkCopies of the histogram, so that
+  // concurrent waves rarely update the same word; k_link_reduce sums the copies
+  if (tile * 64 + lane < n) atomicAdd(&part[(tile % kLinkCopies) * (3 * N + 1) + d], 1u);
+}
+
+// hist[D] = sum over the kLinkCopies partial histograms (nbins = 3N + 1).
+__global__ __launch_bounds__(256) void k_link_reduce(const uint32_t* __restrict__ part,
+                                                     uint32_t nbins,
+                                                     unsigned long long* __restrict__ hist) {
+  const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= nbins) return;
+  unsigned long long acc = 0;
+  for (uint32_t k = 0; k < kLinkCopies; ++k) acc += part[(size_t)k * nbins + b];
+  hist[b] = acc;
+}
+
 __global__ void k_advance(uint32_t* ctr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += 1u;
 }
@@ -1499,6 +1617,41 @@ hipError_t launch_overlap(const BatchDev& B, const Group& g, const uint32_t* pai
   else
     hipLaunchKernelGGL(k_overlap<1>, dim3(g.blocks), dim3(64), 0, stream, B, g, pair_pops,
                        post ? 1u : 0u, cur_a, cur_b);
+  return hipGetLastError();
+}
+
+template <int LAYOUT>
+static hipError_t launch_link_overlap_l(const DevPop& a, const DevPop& b, uint32_t cur_a,
+                                        uint32_t cur_b, uint32_t* part, uint32_t tiles,
+                                        hipStream_t stream) {
+  switch (a.L) {
+#define PA_LINK_CASE(LL)                                                                       \
+  case LL:                                                                                     \
+    hipLaunchKernelGGL((k_link_overlap<LAYOUT, LL>), dim3(tiles), dim3(64), 0, stream, a, b,   \
+                       cur_a, cur_b, part);                                                    \
+    break;
+    PA_LINK_CASE(4) PA_LINK_CASE(6) PA_LINK_CASE(8) PA_LINK_CASE(10) PA_LINK_CASE(12)
+    PA_LINK_CASE(14) PA_LINK_CASE(16)
+#undef PA_LINK_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_link_overlap(const DevPop& a, const DevPop& b, uint32_t cur_a, uint32_t cur_b,
+                               uint32_t* part, unsigned long long* hist, hipStream_t stream) {
+  if (a.L != b.L || a.layout != b.layout) return hipErrorInvalidValue;
+  const uint32_t tiles = min(a.capacity, b.capacity) / 64;
+  const uint32_t nbins = 3 * a.N + 1;
+  hipError_t e = hipSuccess;
+  if (tiles) {
+    e = a.layout == 2 ? launch_link_overlap_l<2>(a, b, cur_a, cur_b, part, tiles, stream)
+                      : launch_link_overlap_l<1>(a, b, cur_a, cur_b, part, tiles, stream);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_link_reduce, dim3((nbins + 255) / 256), dim3(256), 0, stream, part, nbins,
+                     hist);
   return hipGetLastError();
 }
 

@@ -109,3 +109,29 @@ def test_ground_state_estimators_l3_exact():
         err = math.sqrt(g0 * (1 - g0) * max(rho_t, 1.0) / R) + 1e-3
         assert abs(g_tilde[k] - g0) < 5 * err, (b, g_tilde[k], g0)
         assert abs(g_bar[k] - g0) < 5 * err + 0.02 * g0, (b, g_bar[k], g0)
+
+
+def test_link_overlap_mean_and_katzgraber_young_arithmetic():
+    """<q_l> from a D histogram (q_l = 1 - 2 D / 3N) and e_l = -beta sigma^2 3 (1 - <q_l>)
+    (Sec. II.A), on histograms whose answer is known."""
+    N = 4 ** 3
+    h = np.zeros(3 * N + 1, np.uint64)
+    h[0] = 5
+    assert analysis.link_overlap_mean(h, N) == 1.0
+    h[:] = 0
+    h[3 * N] = 2
+    assert analysis.link_overlap_mean(h, N) == -1.0
+    h[:] = 0
+    h[3 * N // 2] = 7  # half the bonds differ: q_l = 0
+    assert analysis.link_overlap_mean(h, N) == 0.0
+    e_l, d = analysis.katzgraber_young(0.5, -1.25, 0.0)
+    assert e_l == -1.5 and d == -0.25
+    e_l, _ = analysis.katzgraber_young(2.0, 0.0, 1.0, coupling_variance=1.3)
+    assert e_l == 0.0
+
+
+def test_quantised_gauss_variance_is_sheppard():
+    """Rounding a unit normal to multiples of h adds h^2 / 12 to its variance
+    (Sheppard's correction; the remainder is of order exp(-2 pi^2 / h^2))."""
+    assert abs(analysis.quantised_gauss_variance() - (1.0 + 1.0 / (12 * 256))) < 1e-12
+    assert abs(analysis.quantised_gauss_variance(1.0, 40) - (1.0 + 1.0 / 12)) < 1e-6

@@ -97,3 +97,26 @@ def test_ground_state_ferromagnet(an):
     assert E0 == -3 * L ** 3
     assert g_tilde[-1] > 0.99
     assert abs(g_bar[-1] - g_tilde[-1]) < 0.05
+
+
+def test_katzgraber_young_vanishes_over_gaussian_disorder(an):
+    """Delta_KY = [e_l - e] over Gaussian disorder samples is zero in
+    equilibrium (Sec. II.A; Gaussian integration by parts, exact at any L).
+    16 samples at L = 6, two populations each, annealed to beta = 1 (above
+    the glass transition, where PA equilibrates easily): the sample mean of
+    e_l - e must be within four standard errors of zero, while e and e_l
+    themselves are far from zero."""
+    L, M = 6, 16
+    betas = np.linspace(0.0, 1.0, 16)
+    deltas, es = [], []
+    for m in range(M):
+        K = pa_inputs.couplings_gauss16(L, 700 + m)
+        r = an.link_overlap_run(L, K, [2 * m + 1, 2 * m + 2], betas, n_sweeps=5, R=1000)
+        assert r["q_l"][0] < r["q_l"][-1]
+        deltas.append(r["delta"][-1])
+        es.append(r["e"][-1])
+    d = np.asarray(deltas)
+    se = d.std(ddof=1) / math.sqrt(M)
+    print("Delta_KY", d.mean(), "+-", se, "e", np.mean(es), flush=True)
+    assert abs(d.mean()) < 4 * se + 1e-3
+    assert np.mean(es) < -0.8

@@ -117,6 +117,25 @@ def _compare_obs(go, rec, k):
 
 
 @pytest.mark.parametrize("layout", ["int8", "bitpack64"])
+@pytest.mark.parametrize("L,R,beta", [(4, 20000, 5.0), (6, 5000, 1.5), (10, 70000, 0.3)])
+def test_one_large_step_concentrates_copies(pam, layout, L, R, beta):
+    """One resampling step from beta = 0 straight to beta: a few low-energy
+    replicas take most of the new population (thousands of copies each, more
+    than one block of old slots holds), and the copy map must still be exact."""
+    say("large step", layout, L, R, beta)
+    J, g, o = pair(pam, L, R, 0x5EED0700 + L, layout, 70 + L)
+    g.resample(beta)
+    o.resample(beta)
+    _compare_step(g, o, 1)
+    assert int(o.last["n"].max()) > 1024
+    g.sweep(beta, 2)
+    o.sweep(beta, 2)
+    assert_state(g, o, f"after the step to beta={beta}")
+    _compare_obs(g.observables(), o.observables(), 1)
+    g.close()
+
+
+@pytest.mark.parametrize("layout", ["int8", "bitpack64"])
 def test_linear_run_l4_every_step(pam, layout):
     """Plain PA at L=4, R=1000, N_T=51 to beta=5, N_S=10: every step bit-exact."""
     L, R = 4, 1000
