@@ -36,27 +36,32 @@ GAUSS_WORKLOAD = dict(name="L10_R500k_bitpack64_gauss16_adaptive_eps0.1", L=10, 
                       eps=0.1, beta_max=5.0, n_sweeps=10, layout="bitpack64", model="gauss16")
 
 # Peak figures of one MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz
-# retire 39.3e12 full-rate 32-bit VALU lane-operations per second; HBM3E 8 TB/s.
+# retire 39.3e12 full-rate 32-bit VALU lane-instructions per second; HBM3E 8 TB/s.
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # link overlap: per bond and pair, the XOR of the two ends' x words, the
 # extraction of the pair's bit and its addition to the count
 LINK_OPS_PER_BOND = 3
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic work of one spin-flip attempt, in 32-bit lane operations:
-#   random number: a quarter of one Philox4x32-10 call, 10 rounds x (2 widening
-#   32x32->64 multiplies + 4 XOR) / 4 = 15 (the key schedule is uniform, not
-#   per lane);
-#   Metropolis test: 6 bond products s_i J_ij s_j (XOR), 5 adds for the local
-#   field, 1 table select of the threshold, 2 for the 64-bit compare, 1 flip = 15.
-OPS_PER_ATTEMPT = 15 + 15
-# With couplings k = 16 J (Gaussian, quantised): 6 bit extracts of the
-# neighbour spins and 6 multiply-adds for m = sum k b, 1 extract of the own
-# spin and 1 select for acc = m or sum k - m, 1 for dE16 = 2 sum k - 4 acc,
-# 1 clamp, 2 for the threshold-table address and LDS read, 2 for the 64-bit
-# compare, 1 flip = 21 (the row's couplings are uniform over a wave's lanes,
-# so sum k and the coupling bytes cost no lane operations).
-OPS_PER_ATTEMPT_GAUSS = 15 + 21
+# Algorithmic work of one spin-flip attempt, in gfx950 VALU lane-instructions
+# (the unit of the peak above: one instruction per lane, whatever its number
+# of inputs):
+#   random number: a quarter of one Philox4x32-10 call, 10 rounds x (2
+#   widening multiply-adds v_mad_u64_u32 + 2 three-input XORs v_bitop3) / 4 = 10;
+#   +-J Metropolis test, bit-sliced: per site and 64 replicas, 6 J masks, 12
+#   XORs (neighbour ^ own ^ J, two 32-replica halves) and 16 adder instructions
+#   (two full adders, a half adder and the carries, per half) form the bit
+#   planes of nu, 34/64 per attempt; per replica, 3 bit extracts and 3 for the
+#   threshold address, 1 compare (64-bit) and 1 select of the flip mask's half
+#   = 8.
+OPS_PER_ATTEMPT = 10 + 8 + 34 / 64
+# With couplings k = 16 J (Gaussian, quantised), per replica: 6 bit extracts
+# of the neighbour spins and 6 multiply-adds for m = sum k b, 1 extract of the
+# own spin and 1 select for acc = m or sum k - m, 1 for dE16 = 2 sum k - 4 acc,
+# 1 clamp, 1 for the threshold-table address, 1 compare (64-bit), 1 select of
+# the flip mask's half = 19 (the row's couplings are uniform over a wave's
+# lanes, so sum k and the coupling bytes cost no lane instructions).
+OPS_PER_ATTEMPT_GAUSS = 10 + 19
 # Algorithmic HBM bytes of one sweep launch: the bit-packed population read and
 # written once (N bits per replica each way) plus 20 B per replica (source index,
 # energy and family label read, energy and family label written).
@@ -573,11 +578,12 @@ def main():
                    "couplings": "+-J p=1/2", "seed_config": 3},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_sweep<bitpack64, L=10> (gather + 10 sweeps + energy)",
+            "kernel": "k_sweep<bitpack64, L=10, +-J> (gather + 10 bit-sliced sweeps + energy)",
             "achieved": achieved_ops / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s",
             "frac": achieved_ops / VALU_PEAK_OPS,
+            "ops_per_attempt": OPS_PER_ATTEMPT,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
             "traffic_GBs": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9,

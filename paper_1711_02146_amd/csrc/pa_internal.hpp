@@ -30,6 +30,7 @@ constexpr int kBlockCounts = 256;  // slots per block in the copy-count / scatte
 constexpr int kHistSlots = 4096;   // slots per block of the histogram kernel
 constexpr int kWindowLdsLevels = 16384;  // largest E16 window counted in LDS (64 KiB)
 constexpr int kMaxL = 16;
+constexpr uint32_t kPlaneWords = 64 * 6;  // +-J sweep: nu bit planes of 64 sites per wave
 constexpr uint32_t kLinkCopies = 32;  // partial link-overlap histograms (see launch_link_overlap)
 // Energy models.  kModelPm: J = +-1, the energy word of a replica is U, the
 // number of unsatisfied bonds (E = 2U - 3N).  kModelGauss16: J = k / 16 with

@@ -472,6 +472,170 @@ __device__ uint32_t sweep_colour_blocks(const TileCtx& c, const unsigned long lo
   return usum;
 }
 
+// ---------------------------------------------------------------------------
+// +-J colour pass in two phases.  The bond arithmetic of a site is the same
+// for its 64 replicas up to their bits, so it is done once per site on whole
+// 32-bit words: phase 1 gives each lane one site (lane = site), forms the six
+// words x_k = neighbour ^ own ^ J mask (bit r set iff bond k of replica r is
+// unsatisfied), and adds them bitwise with two full adders and a half adder
+// into three bit planes, nu = p0 + 2 p1 + 4 p2 per replica.  Phase 2 returns
+// to lane = replica: each lane takes its three bits of the planes, looks up the
+// threshold of its nu and applies the Metropolis test with the same draw as
+// before.  nu, the draws and the test are unchanged, so every result is too.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3_v(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// bitwise majority of three words (v_bitop3_b32 truth table 0xe8)
+__device__ __forceinline__ uint32_t maj3_v(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xe8" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+struct NuPlanes {
+  uint32_t p0, p1, p2;
+};
+
+// nu of 32 replicas as bit planes: x0 + .. + x5 = (s1 + 2 c1) + (s2 + 2 c2)
+// = p0 + 2 (c1 + c2 + c3) with p0 = s1 ^ s2, c3 = s1 & s2, and c1 + c2 + c3 =
+// p1 + 2 p2 (their XOR and majority).
+__device__ __forceinline__ NuPlanes nu_planes(uint32_t own, const uint32_t (&nb)[6],
+                                              const uint32_t (&jm)[6]) {
+  uint32_t x[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) x[k] = xor3_v(nb[k], own, jm[k]);
+  const uint32_t s1 = xor3_v(x[0], x[1], x[2]), c1 = maj3_v(x[0], x[1], x[2]);
+  const uint32_t s2 = xor3_v(x[3], x[4], x[5]), c2 = maj3_v(x[3], x[4], x[5]);
+  const uint32_t c3 = s1 & s2;
+  NuPlanes r;
+  r.p0 = s1 ^ s2;
+  r.p1 = xor3_v(c1, c2, c3);
+  r.p2 = maj3_v(c1, c2, c3);
+  return r;
+}
+
+// Phase 1 for one group of a wave's blocks: lane l takes site sb = l mod BS
+// of block bi = l / BS (BS = 4 L/2 sites per block of four rows; GB = 64 / BS
+// blocks per group, rows rb0 + step bi .. + 3) and writes its planes to entry
+// l of the wave's plane area: words (p0, p1, p2) x (replicas 0..31, 32..63)
+// in the order p0 lo, p0 hi, p1 lo, p1 hi, p2 lo, p2 hi.
+template <int L>
+__device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* __restrict__ sites,
+                                            uint32_t own0, uint32_t rb0, uint32_t step,
+                                            uint32_t lane, uint32_t* planes) {
+  constexpr uint32_t H = L / 2, BS = 4 * H, GB = 64 / BS, ROWS = L * L;
+  const uint32_t bi = lane / BS, sb = lane - bi * BS;
+  const uint32_t rb = rb0 + step * bi;
+  if (bi < GB && rb < ROWS) {
+    const uint32_t cm = own0 + H * rb + sb;
+    const SiteEntry e = sites[cm];
+    const uint2* w = reinterpret_cast<const uint2*>(c.lds);
+    const uint2 o = w[cm];
+    uint32_t lo[6], hi[6], jm[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const uint2 v = w[e.nb[k]];
+      lo[k] = v.x;
+      hi[k] = v.y;
+      jm[k] = (uint32_t)((int32_t)((uint32_t)e.jneg << (31 - k)) >> 31);
+    }
+    const NuPlanes a = nu_planes(o.x, lo, jm), b = nu_planes(o.y, hi, jm);
+    uint32_t* dst = planes + 6 * lane;
+    dst[0] = a.p0;
+    dst[1] = b.p0;
+    dst[2] = a.p1;
+    dst[3] = b.p1;
+    dst[4] = a.p2;
+    dst[5] = b.p2;
+  }
+}
+
+struct PlaneBits {
+  uint32_t p0, p1, p2;
+};
+
+// this lane's half of the planes of site S of a block (plb: the block's first
+// entry, offset by the lane's half)
+template <int S>
+__device__ __forceinline__ PlaneBits load_planes(const char* plb) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(plb + 24 * S);
+  PlaneBits r;
+  r.p0 = p[0];
+  r.p1 = p[2];
+  r.p2 = p[4];
+  return r;
+}
+
+// Phase 2 for site S.. of a block: nu from the lane's plane bits, then the
+// Metropolis test and the flip as in site_update.  The planes of site S + 1
+// are read before site S is updated (the plane area is not written in this
+// phase), so their LDS latency overlaps the update.
+template <int L, int S, bool ACCUM>
+__device__ __forceinline__ void block_planes(const TileCtx& c, const char* ownb, const char* plb,
+                                             uint32_t g0, Words4& d, uint32_t& usum,
+                                             const PlaneBits& pb) {
+  constexpr int BS = 2 * L;
+  PlaneBits nx;
+  if constexpr (S + 1 < BS) nx = load_planes<S + 1>(plb);
+  if constexpr (S % 4 == 0) {
+    if (c.any_draw) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
+  }
+  // byte address 8 nu of the threshold table (at LDS address 0): two
+  // v_lshl_or_b32 after the shift of the lowest bit (the compiler's own form
+  // takes three shifts and an OR)
+  const uint32_t t0 = __builtin_amdgcn_ubfe(pb.p0, c.pos, 1) << 3;
+  uint32_t t1, a8;
+  asm("v_lshl_or_b32 %0, %1, 4, %2" : "=v"(t1) : "v"(__builtin_amdgcn_ubfe(pb.p1, c.pos, 1)), "v"(t0));
+  asm("v_lshl_or_b32 %0, %1, 5, %2" : "=v"(a8) : "v"(__builtin_amdgcn_ubfe(pb.p2, c.pos, 1)), "v"(t1));
+  const uint32_t n = a8 >> 3;
+  const unsigned long long thr = *reinterpret_cast<const unsigned long long*>(
+      reinterpret_cast<const char*>(c.thr_of_nu) + a8);
+  const bool acc = (unsigned long long)d.w[S % 4] < thr;
+  if (ACCUM) usum += acc ? 6u - n : n;
+  const unsigned long long f = __ballot(acc);
+  const uint32_t fh = c.hoff ? (uint32_t)(f >> 32) : (uint32_t)f;
+  uint32_t* const own_p = reinterpret_cast<uint32_t*>(const_cast<char*>(ownb) + 8 * S);
+  if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if constexpr (S + 1 < BS) block_planes<L, S + 1, ACCUM>(c, ownb, plb, g0, d, usum, nx);
+}
+
+// One +-J colour pass of this wave (blocks rb = 4 part + 4 nparts i, as in
+// sweep_colour_blocks), GB blocks at a time: phase 1 for the group, then
+// phase 2 block by block.  The wave's plane area holds one group.
+template <int L, bool ACCUM>
+__device__ uint32_t sweep_colour_planes(const TileCtx& c, const SiteEntry* __restrict__ sites,
+                                        uint32_t colour, uint32_t part, uint32_t nparts,
+                                        uint32_t* planes, uint32_t lane) {
+  constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L, BS = 4 * H, GB = 64 / BS;
+  const uint32_t own0 = colour * (N / 2);
+  const uint32_t step = 4 * nparts;
+  uint32_t usum = 0;
+  Words4 d;
+  d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0u;
+  const char* const plane_h = reinterpret_cast<const char*>(planes) + c.hoff;
+  const char* const own_h = reinterpret_cast<const char*>(c.lds) + c.hoff;
+  for (uint32_t rb0 = 4 * part; rb0 < ROWS; rb0 += step * GB) {
+    plane_group<L>(c, sites, own0, rb0, step, lane, planes);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+    for (uint32_t bi = 0; bi < GB; ++bi) {
+      const uint32_t rb = __builtin_amdgcn_readfirstlane(rb0 + step * bi);
+      if (rb >= ROWS) break;
+      const uint32_t g0 = (own0 + H * rb) >> 2;  // first Philox group of the block
+      const char* ownb = own_h + whole_s(8 * (own0 + H * rb));
+      const char* plb = plane_h + 24 * BS * bi;
+      block_planes<L, 0, ACCUM>(c, ownb, plb, g0, d, usum, load_planes<0>(plb));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  return usum;
+}
+
 // One row's share of tile_energy_rows, sites Q.. of the row.
 template <int L, int M, int Q>
 __device__ __forceinline__ void tile_energy_row(const TileCtx& c, const RowAddr& a, uint32_t& U) {
@@ -1093,14 +1257,28 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   if (sp.n_sweeps == 0) {
     U = tile_energy_rows<L, M>(c, rowj, part, SPLIT);
   } else {
-    for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
-      c.t = sp.t0 + s;
+    if constexpr (M == (int)kModelGauss16) {
+      for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
+        c.t = sp.t0 + s;
+        sweep_colour_blocks<L, M, false>(c, rowj, 0u, part, SPLIT);
+        sweep_colour_blocks<L, M, false>(c, rowj, 1u, part, SPLIT);
+      }
+      c.t = sp.t0 + sp.n_sweeps - 1;
       sweep_colour_blocks<L, M, false>(c, rowj, 0u, part, SPLIT);
-      sweep_colour_blocks<L, M, false>(c, rowj, 1u, part, SPLIT);
+      U = sweep_colour_blocks<L, M, true>(c, rowj, 1u, part, SPLIT);
+    } else {
+      // this wave's plane area (phase 1 of the +-J colour passes), after the
+      // tile image and the per-replica reduction area
+      uint32_t* const planes = lds_all + 2 * N + 64 * SPLIT + kPlaneWords * part;
+      for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
+        c.t = sp.t0 + s;
+        sweep_colour_planes<L, false>(c, P.sites, 0u, part, SPLIT, planes, lane);
+        sweep_colour_planes<L, false>(c, P.sites, 1u, part, SPLIT, planes, lane);
+      }
+      c.t = sp.t0 + sp.n_sweeps - 1;
+      sweep_colour_planes<L, false>(c, P.sites, 0u, part, SPLIT, planes, lane);
+      U = sweep_colour_planes<L, true>(c, P.sites, 1u, part, SPLIT, planes, lane);
     }
-    c.t = sp.t0 + sp.n_sweeps - 1;
-    sweep_colour_blocks<L, M, false>(c, rowj, 0u, part, SPLIT);
-    U = sweep_colour_blocks<L, M, true>(c, rowj, 1u, part, SPLIT);
   }
   // Epilogue.  The lane number, the slot, its source and the descriptor
   // fields are formed or read again here rather than held in registers
@@ -1516,7 +1694,10 @@ hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream)
 template <int LAYOUT, int L>
 void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t model,
                     hipStream_t stream) {
-  const size_t gbytes = model == kModelGauss16 ? (size_t)(kGaussDEMax + 1) * 8 : 0;
+  // after the tile image and the reduction area: the Gaussian threshold table,
+  // or the +-J plane areas (one per wave)
+  const size_t gbytes = model == kModelGauss16 ? (size_t)(kGaussDEMax + 1) * 8
+                                               : (size_t)kPlaneWords * 4 * split;
   const size_t lds = (size_t)L * L * L * 8 + 4 * 64 * split + gbytes;
   if (model == kModelGauss16) {
     if (split == 8)
