@@ -359,8 +359,11 @@ hipError_t set_thresholds(pa_instance* in, double beta, pa::PopStep* ps) {
   unsigned long long* tab = in->h_gthr;
   for (int d = 0; d <= pa::kGaussDEMax; ++d)
     tab[d] = (unsigned long long)std::floor(std::ldexp(std::exp(-beta * ((double)d / 16.0)), 32));
-  ps->thr[0] = tab[2];  // the largest threshold of a positive move (dE16 is even)
-  ps->thr[1] = ps->thr[2] = 0;
+  // the largest and the smallest threshold of a positive move (dE16 is even):
+  // a draw is needed unless every entry is 0 or every entry is 2^32
+  ps->thr[0] = tab[2];
+  ps->thr[1] = tab[pa::kGaussDEMax];
+  ps->thr[2] = 0;
   e = hipMemcpyAsync(const_cast<unsigned long long*>(in->dev.gthr), tab,
                      (size_t)(pa::kGaussDEMax + 1) * 8, hipMemcpyHostToDevice, in->stream);
   if (e != hipSuccess) return e;

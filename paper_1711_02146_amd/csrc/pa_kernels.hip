@@ -1244,8 +1244,10 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   c.pos = lane & 31u;
   c.ph.init(j, (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
   // A draw matters only for a class whose threshold is neither 0 nor 2^32.
-  // (kModelGauss16: the host passes the table's dE16 = 2 entry in thr[0], the
-  // largest threshold of a positive move, and 0 in thr[1], thr[2].)
+  // (kModelGauss16: the host passes the largest and the smallest threshold of
+  // a positive move, the table's dE16 = 2 and last entries, in thr[0] and
+  // thr[1], and 0 in thr[2]; the table is non-increasing, so a draw matters
+  // unless both are 0 or both are 2^32.)
   c.any_draw = (sp.thr[0] != 0 && sp.thr[0] < (1ull << 32)) ||
                (sp.thr[1] != 0 && sp.thr[1] < (1ull << 32)) ||
                (sp.thr[2] != 0 && sp.thr[2] < (1ull << 32));
