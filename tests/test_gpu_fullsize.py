@@ -1,8 +1,11 @@
 """GPU: whole runs at full size (Amey & Machta, arXiv:1711.02146, Sec. II loop).
 
 The oracle cannot follow these runs step by step in seconds, so every step is
-checked against properties that hold at any size, and the final populations
-against the oracle on sampled replicas:
+checked against properties that hold at any size, and so are the final
+populations: sorted family labels, the energy word of sampled replicas
+against the energy of their exported spins, and the overlap histogram against
+the exported spins of both populations (tests/props.py; no GPU output is fed
+to the oracle):
   * L = 10, R = 5e5, bit-packed, constant culling eps = 0.1 to beta = 5 (the
     benchmark workload, all ~300 steps);
   * L = 8, R = 1e5, int8, two populations, 201 linear temperatures to beta = 5,
@@ -14,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+import props
 import pa_inputs
 
 pytestmark = pytest.mark.gpu
@@ -49,8 +53,7 @@ def check_final(pam, g, L, J, n_sample, rng):
     R_t = s.shape[0]
     assert np.all(np.diff(f.astype(np.int64)) >= 0)          # family labels stay sorted
     idx = np.sort(rng.choice(R_t, size=min(n_sample, R_t), replace=False))
-    U_oracle = oracle.energy(L, J, s[idx].reshape(-1))
-    np.testing.assert_array_equal(u[idx].astype(np.int32), U_oracle)
+    np.testing.assert_array_equal(u[idx].astype(np.int32), props.unsatisfied_bonds(L, J, s[idx]))
     return s, u, f
 
 
@@ -111,9 +114,8 @@ def test_c2_two_populations_linear(pam):
     rng = np.random.default_rng(2)
     sa, _, _ = check_final(pam, a, L, J, 512, rng)
     sb, _, _ = check_final(pam, b, L, J, 512, rng)
-    # the last histogram, recomputed by the oracle from the exported spins
+    # the last histogram, recomputed from the exported spins
     n = min(sa.shape[0], sb.shape[0])
-    ho, _ = oracle.overlap_hist(N, sa[:n].reshape(-1), sb[:n].reshape(-1))
-    np.testing.assert_array_equal(pam.overlap_hist(a, b), ho)
+    np.testing.assert_array_equal(pam.overlap_hist(a, b), props.overlap_hist65(N, sa, sb))
     a.close()
     b.close()

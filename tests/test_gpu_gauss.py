@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import props
 import pa_inputs
 
 pytestmark = pytest.mark.gpu
@@ -182,7 +183,7 @@ def test_full_size_l10_sampled_first_step(pam, split):
     oracle.g_sweep_slots(L, K, sp, E, pick.astype(np.uint32), o.seed, bo, 0, 10)
     np.testing.assert_array_equal(s2[pick], sp)
     np.testing.assert_array_equal(u2[pick].view(np.int32), E)
-    np.testing.assert_array_equal(u2.view(np.int32), oracle.g_energy(L, K, s2))
+    np.testing.assert_array_equal(u2.view(np.int32), props.energy16(L, K, s2))
     assert g.observables()["R_tilde"] == Rn
     g.close()
     pam.pa_autotune_reset()
@@ -225,8 +226,9 @@ def test_import_state_roundtrip(pam):
 
 def test_full_anneal_l10_r500k(pam):
     """The benchmark anneal with Gaussian couplings, every step (~300) checked
-    against properties that hold at any size, the final population against the
-    oracle's energies on sampled replicas and in full against its own spins."""
+    against properties that hold at any size, and the final population too:
+    the E16 of sampled replicas against the energy of their exported spins
+    (tests/props.py), the step record against the exported population."""
     import math
 
     L, R, eps, bmax = 10, 500000, 0.1, 5.0
@@ -258,7 +260,7 @@ def test_full_anneal_l10_r500k(pam):
     E = u.view(np.int32)
     assert np.all(np.diff(f.astype(np.int64)) >= 0)
     idx = np.sort(np.random.default_rng(5).choice(s.shape[0], 512, replace=False))
-    np.testing.assert_array_equal(E[idx], oracle.g_energy(L, K, s[idx]))
+    np.testing.assert_array_equal(E[idx], props.energy16(L, K, s[idx]))
     assert prev["mean_E"] == E.astype(np.int64).sum() / E.size / 16.0
     assert prev["E_min"] == E.min() and prev["n_at_E_min"] == int(np.count_nonzero(E == E.min()))
     # the annealed population sits far below the beta = 0 energy scale
