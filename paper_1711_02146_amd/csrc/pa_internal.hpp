@@ -30,7 +30,17 @@ constexpr int kBlockCounts = 256;  // slots per block in the copy-count / scatte
 constexpr int kHistSlots = 4096;   // slots per block of the histogram kernel
 constexpr int kWindowLdsLevels = 16384;  // largest E16 window counted in LDS (64 KiB)
 constexpr int kMaxL = 16;
-constexpr uint32_t kPlaneWords = 64 * 6;  // +-J sweep: nu bit planes of 64 sites per wave
+// +-J sweep: per wave, the threshold byte addresses 8 nu of one group of
+// plane_blocks(L) blocks of four rows (2L sites each) x 64 replicas, one byte
+// each.  A larger group fills more of a wave's 64 lanes in phase 1; a smaller
+// one leaves LDS for more waves per SIMD.  The sizes were chosen by timing
+// both sweep forms on MI355X (at L = 10, two blocks and 8 waves per SIMD beat
+// three blocks and 6 by 4%; at L = 8 four blocks beat three by 6%).
+constexpr uint32_t plane_blocks(uint32_t L) {
+  return L <= 4 ? 8u : L == 6 ? 5u : L == 8 ? 4u : L <= 12 ? 2u : 1u;
+}
+constexpr uint32_t plane_sites(uint32_t L) { return plane_blocks(L) * 2u * L; }
+constexpr uint32_t plane_words(uint32_t L) { return plane_sites(L) * 16u; }
 constexpr uint32_t kLinkCopies = 32;  // partial link-overlap histograms (see launch_link_overlap)
 // Energy models.  kModelPm: J = +-1, the energy word of a replica is U, the
 // number of unsatisfied bonds (E = 2U - 3N).  kModelGauss16: J = k / 16 with
@@ -214,8 +224,11 @@ inline uint32_t blocks_sweep(uint32_t capacity) { return (capacity / 64 + 7) / 8
 // Waves per tile of a sweep launch over `tiles` tiles of linear size L, from
 // timings on MI355X: eight waves pay off on large lattices and on launches too
 // small to fill the chip with four; L = 4 has only four row blocks per colour.
-inline uint32_t sweep_split_default(uint32_t L, uint64_t tiles) {
-  return (L >= 14 || (L >= 6 && tiles < 2048)) ? 8u : 4u;
+inline uint32_t sweep_split_default(uint32_t model, uint32_t L, uint64_t tiles) {
+  // +-J (bit-sliced colour pass): eight waves from L = 12 up, where a wave's
+  // plane group is one or two blocks and the longer rows hide less latency
+  const uint32_t big = model == kModelPm ? 12u : 14u;
+  return (L >= big || (L >= 6 && tiles < 2048)) ? 8u : 4u;
 }
 // The split a launch uses: the autotuner's choice for (model, layout, L, size
 // class of `tiles`) when one was measured in this process, else the default (pa_tune.cpp).

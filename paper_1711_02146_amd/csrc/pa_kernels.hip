@@ -477,11 +477,12 @@ __device__ uint32_t sweep_colour_blocks(const TileCtx& c, const unsigned long lo
 // for its 64 replicas up to their bits, so it is done once per site on whole
 // 32-bit words: phase 1 gives each lane one site (lane = site), forms the six
 // words x_k = neighbour ^ own ^ J mask (bit r set iff bond k of replica r is
-// unsatisfied), and adds them bitwise with two full adders and a half adder
-// into three bit planes, nu = p0 + 2 p1 + 4 p2 per replica.  Phase 2 returns
-// to lane = replica: each lane takes its three bits of the planes, looks up the
-// threshold of its nu and applies the Metropolis test with the same draw as
-// before.  nu, the draws and the test are unchanged, so every result is too.
+// unsatisfied), adds them bitwise with two full adders and a half adder into
+// three bit planes, nu = p0 + 2 p1 + 4 p2 per replica, and spreads the planes
+// into one byte per replica holding 8 nu, the byte address of the replica's
+// threshold.  Phase 2 returns to lane = replica: each lane reads its byte and
+// applies the Metropolis test with the same draw as before.  nu, the draws and
+// the test are unchanged, so every result is too.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t xor3_v(uint32_t a, uint32_t b, uint32_t c) {
   uint32_t r;
@@ -518,16 +519,35 @@ __device__ __forceinline__ NuPlanes nu_planes(uint32_t own, const uint32_t (&nb)
   return r;
 }
 
+// Word j (j = 0..7) of a half's 32 bytes: byte m holds 8 nu of the replica at
+// bit j + 8m of the planes.  Rotating plane k right by j - 3 - k brings bit
+// j + 8m to bit 8m + 3 + k, so three rotations and three masks fill the word.
+// The replica at bit b of a half therefore finds its byte at 4 (b & 7) +
+// (b >> 3) (plane_byte below).
+__device__ __forceinline__ uint32_t rotr32(uint32_t x, uint32_t s) {
+  return __builtin_amdgcn_alignbit(x, x, s);
+}
+
+template <int J>
+__device__ __forceinline__ uint32_t nu8_word(const NuPlanes& p) {
+  return (rotr32(p.p0, (J - 3) & 31) & 0x08080808u) | (rotr32(p.p1, (J - 4) & 31) & 0x10101010u) |
+         (rotr32(p.p2, (J - 5) & 31) & 0x20202020u);
+}
+
+// byte of replica r (lane r) within a site's 64-byte entry
+__device__ __forceinline__ uint32_t plane_byte(uint32_t r) {
+  return (r & 32u) + 4u * (r & 7u) + ((r >> 3) & 3u);
+}
+
 // Phase 1 for one group of a wave's blocks: lane l takes site sb = l mod BS
-// of block bi = l / BS (BS = 4 L/2 sites per block of four rows; GB = 64 / BS
-// blocks per group, rows rb0 + step bi .. + 3) and writes its planes to entry
-// l of the wave's plane area: words (p0, p1, p2) x (replicas 0..31, 32..63)
-// in the order p0 lo, p0 hi, p1 lo, p1 hi, p2 lo, p2 hi.
+// of block bi = l / BS (BS = 4 L/2 sites per block of four rows; GB blocks
+// per group, rows rb0 + step bi .. + 3) and writes entry l of the wave's
+// plane area: 64 bytes, byte plane_byte(r) = 8 nu of replica r at that site.
 template <int L>
 __device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* __restrict__ sites,
                                             uint32_t own0, uint32_t rb0, uint32_t step,
                                             uint32_t lane, uint32_t* planes) {
-  constexpr uint32_t H = L / 2, BS = 4 * H, GB = 64 / BS, ROWS = L * L;
+  constexpr uint32_t H = L / 2, BS = 4 * H, GB = plane_blocks(L), ROWS = L * L;
   const uint32_t bi = lane / BS, sb = lane - bi * BS;
   const uint32_t rb = rb0 + step * bi;
   if (bi < GB && rb < ROWS) {
@@ -544,58 +564,37 @@ __device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* _
       jm[k] = (uint32_t)((int32_t)((uint32_t)e.jneg << (31 - k)) >> 31);
     }
     const NuPlanes a = nu_planes(o.x, lo, jm), b = nu_planes(o.y, hi, jm);
-    uint32_t* dst = planes + 6 * lane;
-    dst[0] = a.p0;
-    dst[1] = b.p0;
-    dst[2] = a.p1;
-    dst[3] = b.p1;
-    dst[4] = a.p2;
-    dst[5] = b.p2;
+    uint4* dst = reinterpret_cast<uint4*>(planes + 16 * lane);
+    dst[0] = make_uint4(nu8_word<0>(a), nu8_word<1>(a), nu8_word<2>(a), nu8_word<3>(a));
+    dst[1] = make_uint4(nu8_word<4>(a), nu8_word<5>(a), nu8_word<6>(a), nu8_word<7>(a));
+    dst[2] = make_uint4(nu8_word<0>(b), nu8_word<1>(b), nu8_word<2>(b), nu8_word<3>(b));
+    dst[3] = make_uint4(nu8_word<4>(b), nu8_word<5>(b), nu8_word<6>(b), nu8_word<7>(b));
   }
 }
 
-struct PlaneBits {
-  uint32_t p0, p1, p2;
-};
-
-// this lane's half of the planes of site S of a block (plb: the block's first
-// entry, offset by the lane's half)
-template <int S>
-__device__ __forceinline__ PlaneBits load_planes(const char* plb) {
-  const uint32_t* p = reinterpret_cast<const uint32_t*>(plb + 24 * S);
-  PlaneBits r;
-  r.p0 = p[0];
-  r.p1 = p[2];
-  r.p2 = p[4];
-  return r;
-}
-
-// Phase 2 for site S.. of a block: nu from the lane's plane bits, then the
-// Metropolis test and the flip as in site_update.  The planes of site S + 1
-// are read before site S is updated (the plane area is not written in this
-// phase), so their LDS latency overlaps the update.
+// Phase 2 for site S.. of a block: the lane's threshold address from its byte
+// (plb: the block's first entry plus the lane's byte offset), then the Metropolis test
+// and the flip as in site_update.  The byte of site S + 1 is read before site
+// S is updated (the plane area is not written in this phase), so its LDS
+// latency overlaps the update.
 template <int L, int S, bool ACCUM>
-__device__ __forceinline__ void block_planes(const TileCtx& c, const char* ownb, const char* plb,
-                                             uint32_t g0, Words4& d, uint32_t& usum,
-                                             const PlaneBits& pb) {
+__device__ __forceinline__ void block_planes(const TileCtx& c, const char* ownb,
+                                             const uint8_t* plb, uint32_t g0, Words4& d,
+                                             uint32_t& usum, uint32_t a8) {
   constexpr int BS = 2 * L;
-  PlaneBits nx;
-  if constexpr (S + 1 < BS) nx = load_planes<S + 1>(plb);
+  uint32_t nx = 0;
+  if constexpr (S + 1 < BS) nx = (uint32_t)plb[64 * (S + 1)];
   if constexpr (S % 4 == 0) {
     if (c.any_draw) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
   }
-  // byte address 8 nu of the threshold table (at LDS address 0): two
-  // v_lshl_or_b32 after the shift of the lowest bit (the compiler's own form
-  // takes three shifts and an OR)
-  const uint32_t t0 = __builtin_amdgcn_ubfe(pb.p0, c.pos, 1) << 3;
-  uint32_t t1, a8;
-  asm("v_lshl_or_b32 %0, %1, 4, %2" : "=v"(t1) : "v"(__builtin_amdgcn_ubfe(pb.p1, c.pos, 1)), "v"(t0));
-  asm("v_lshl_or_b32 %0, %1, 5, %2" : "=v"(a8) : "v"(__builtin_amdgcn_ubfe(pb.p2, c.pos, 1)), "v"(t1));
-  const uint32_t n = a8 >> 3;
+  __builtin_assume(a8 < 256u);  // a byte: no mask before the address
   const unsigned long long thr = *reinterpret_cast<const unsigned long long*>(
       reinterpret_cast<const char*>(c.thr_of_nu) + a8);
   const bool acc = (unsigned long long)d.w[S % 4] < thr;
-  if (ACCUM) usum += acc ? 6u - n : n;
+  if (ACCUM) {
+    const uint32_t n = a8 >> 3;
+    usum += acc ? 6u - n : n;
+  }
   const unsigned long long f = __ballot(acc);
   const uint32_t fh = c.hoff ? (uint32_t)(f >> 32) : (uint32_t)f;
   uint32_t* const own_p = reinterpret_cast<uint32_t*>(const_cast<char*>(ownb) + 8 * S);
@@ -610,13 +609,14 @@ template <int L, bool ACCUM>
 __device__ uint32_t sweep_colour_planes(const TileCtx& c, const SiteEntry* __restrict__ sites,
                                         uint32_t colour, uint32_t part, uint32_t nparts,
                                         uint32_t* planes, uint32_t lane) {
-  constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L, BS = 4 * H, GB = 64 / BS;
+  constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L, BS = 4 * H;
+  constexpr uint32_t GB = plane_blocks(L);
   const uint32_t own0 = colour * (N / 2);
   const uint32_t step = 4 * nparts;
   uint32_t usum = 0;
   Words4 d;
   d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0u;
-  const char* const plane_h = reinterpret_cast<const char*>(planes) + c.hoff;
+  const uint8_t* const plane_l = reinterpret_cast<const uint8_t*>(planes) + plane_byte(lane);
   const char* const own_h = reinterpret_cast<const char*>(c.lds) + c.hoff;
   for (uint32_t rb0 = 4 * part; rb0 < ROWS; rb0 += step * GB) {
     plane_group<L>(c, sites, own0, rb0, step, lane, planes);
@@ -627,8 +627,8 @@ __device__ uint32_t sweep_colour_planes(const TileCtx& c, const SiteEntry* __res
       if (rb >= ROWS) break;
       const uint32_t g0 = (own0 + H * rb) >> 2;  // first Philox group of the block
       const char* ownb = own_h + whole_s(8 * (own0 + H * rb));
-      const char* plb = plane_h + 24 * BS * bi;
-      block_planes<L, 0, ACCUM>(c, ownb, plb, g0, d, usum, load_planes<0>(plb));
+      const uint8_t* plb = plane_l + 64 * BS * bi;
+      block_planes<L, 0, ACCUM>(c, ownb, plb, g0, d, usum, plb[0]);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -1271,7 +1271,7 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
     } else {
       // this wave's plane area (phase 1 of the +-J colour passes), after the
       // tile image and the per-replica reduction area
-      uint32_t* const planes = lds_all + 2 * N + 64 * SPLIT + kPlaneWords * part;
+      uint32_t* const planes = lds_all + 2 * N + 64 * SPLIT + plane_words(L) * part;
       for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
         c.t = sp.t0 + s;
         sweep_colour_planes<L, false>(c, P.sites, 0u, part, SPLIT, planes, lane);
@@ -1699,7 +1699,7 @@ void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t 
   // after the tile image and the reduction area: the Gaussian threshold table,
   // or the +-J plane areas (one per wave)
   const size_t gbytes = model == kModelGauss16 ? (size_t)(kGaussDEMax + 1) * 8
-                                               : (size_t)kPlaneWords * 4 * split;
+                                               : (size_t)plane_words(L) * 4 * split;
   const size_t lds = (size_t)L * L * L * 8 + 4 * 64 * split + gbytes;
   if (model == kModelGauss16) {
     if (split == 8)

@@ -35,7 +35,7 @@ uint32_t sweep_split_for(uint32_t model, uint32_t layout, uint32_t L, uint64_t t
     const auto it = g_table.find({model, layout, L, size_class(tiles)});
     if (it != g_table.end()) return it->second;
   }
-  return sweep_split_default(L, tiles);
+  return sweep_split_default(model, L, tiles);
 }
 
 void sweep_split_record(uint32_t model, uint32_t layout, uint32_t L, uint64_t tiles,
