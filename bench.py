@@ -50,11 +50,12 @@ HBM_PEAK_GBS = 8000.0
 #   widening multiply-adds v_mad_u64_u32 + 2 three-input XORs v_bitop3) / 4 = 10;
 #   +-J Metropolis test, bit-sliced: per site and 64 replicas, 6 J masks, 12
 #   XORs (neighbour ^ own ^ J, two 32-replica halves), 16 adder instructions
-#   (the bit planes of nu) and 96 to spread the planes into one byte per
-#   replica (16 words x 3 rotations and 3 masked merges) = 130, i.e. 130/64
-#   per attempt; per replica, the byte is the threshold's address, then 1
-#   compare (64-bit) and 1 select of the flip mask's half = 2.
-OPS_PER_ATTEMPT = 10 + 2 + 130 / 64
+#   (the bit planes of nu) and 68 to spread the planes into one byte per
+#   replica (per half, 2 plane rotations, then 8 words x 3 masked merges and
+#   1 rotation) = 102, i.e. 102/64 per attempt; per replica, the byte is the
+#   threshold's address, then 1 compare (64-bit) and 1 select of the flip
+#   mask's half = 2.
+OPS_PER_ATTEMPT = 10 + 2 + 102 / 64
 # With couplings k = 16 J (Gaussian, quantised), per replica: 6 bit extracts
 # of the neighbour spins and 6 multiply-adds for m = sum k b, 1 extract of the
 # own spin and 1 select for acc = m or sum k - m, 1 for dE16 = 2 sum k - 4 acc,

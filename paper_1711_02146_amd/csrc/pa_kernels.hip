@@ -520,18 +520,34 @@ __device__ __forceinline__ NuPlanes nu_planes(uint32_t own, const uint32_t (&nb)
 }
 
 // Word j (j = 0..7) of a half's 32 bytes: byte m holds 8 nu of the replica at
-// bit j + 8m of the planes.  Rotating plane k right by j - 3 - k brings bit
-// j + 8m to bit 8m + 3 + k, so three rotations and three masks fill the word.
-// The replica at bit b of a half therefore finds its byte at 4 (b & 7) +
-// (b >> 3) (plane_byte below).
+// bit j + 8m of the planes.  With p1 rotated left by 1 and p2 by 2 (once per
+// half), the bits that word j needs sit at positions j, j + 1, j + 2 (mod 8)
+// of p0, p1', p2' and never overlap: three masked merges collect them and one
+// rotation right by j - 3 moves bit j + 8m of p0 to 8m + 3, of p1 to 8m + 4
+// and of p2 to 8m + 5.  The replica at bit b of a half therefore finds its
+// byte at 4 (b & 7) + (b >> 3) (plane_byte below).
 __device__ __forceinline__ uint32_t rotr32(uint32_t x, uint32_t s) {
   return __builtin_amdgcn_alignbit(x, x, s);
 }
 
+struct NuPlanesRot {
+  uint32_t p0, p1r, p2r;  // p0, p1 rotated left by 1, p2 rotated left by 2
+};
+
+__device__ __forceinline__ NuPlanesRot rot_planes(const NuPlanes& p) {
+  NuPlanesRot r;
+  r.p0 = p.p0;
+  r.p1r = rotr32(p.p1, 31);
+  r.p2r = rotr32(p.p2, 30);
+  return r;
+}
+
 template <int J>
-__device__ __forceinline__ uint32_t nu8_word(const NuPlanes& p) {
-  return (rotr32(p.p0, (J - 3) & 31) & 0x08080808u) | (rotr32(p.p1, (J - 4) & 31) & 0x10101010u) |
-         (rotr32(p.p2, (J - 5) & 31) & 0x20202020u);
+__device__ __forceinline__ uint32_t nu8_word(const NuPlanesRot& p) {
+  constexpr uint32_t m = 0x01010101u << J;
+  constexpr uint32_t m1 = (m << 1) | (m >> 31), m2 = (m << 2) | (m >> 30);
+  const uint32_t t = (p.p0 & m) | (p.p1r & m1) | (p.p2r & m2);
+  return rotr32(t, (J - 3) & 31);
 }
 
 // byte of replica r (lane r) within a site's 64-byte entry
@@ -563,7 +579,8 @@ __device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* _
       hi[k] = v.y;
       jm[k] = (uint32_t)((int32_t)((uint32_t)e.jneg << (31 - k)) >> 31);
     }
-    const NuPlanes a = nu_planes(o.x, lo, jm), b = nu_planes(o.y, hi, jm);
+    const NuPlanesRot a = rot_planes(nu_planes(o.x, lo, jm));
+    const NuPlanesRot b = rot_planes(nu_planes(o.y, hi, jm));
     uint4* dst = reinterpret_cast<uint4*>(planes + 16 * lane);
     dst[0] = make_uint4(nu8_word<0>(a), nu8_word<1>(a), nu8_word<2>(a), nu8_word<3>(a));
     dst[1] = make_uint4(nu8_word<4>(a), nu8_word<5>(a), nu8_word<6>(a), nu8_word<7>(a));
