@@ -36,11 +36,14 @@ constexpr int kMaxL = 16;
 // one leaves LDS for more waves per SIMD.  The sizes were chosen by timing
 // both sweep forms on MI355X (at L = 10, two blocks and 8 waves per SIMD beat
 // three blocks and 6 by 4%; at L = 8 four blocks beat three by 6%).
-constexpr uint32_t plane_blocks(uint32_t L) {
-  return L <= 4 ? 8u : L == 6 ? 5u : L == 8 ? 4u : L <= 12 ? 2u : 1u;
+// With eight waves per tile the tile image and the reduction area are shared
+// by twice the waves, so at L = 10 three blocks per group still leave four
+// workgroups (eight waves per SIMD) in a CU's 160 KB.
+constexpr uint32_t plane_blocks(uint32_t L, uint32_t split) {
+  return L <= 4 ? 8u : L == 6 ? 5u : L == 8 ? 4u : L == 10 ? (split == 8 ? 3u : 2u) : L == 12 ? 2u : 1u;
 }
-constexpr uint32_t plane_sites(uint32_t L) { return plane_blocks(L) * 2u * L; }
-constexpr uint32_t plane_words(uint32_t L) { return plane_sites(L) * 16u; }
+constexpr uint32_t plane_sites(uint32_t L, uint32_t split) { return plane_blocks(L, split) * 2u * L; }
+constexpr uint32_t plane_words(uint32_t L, uint32_t split) { return plane_sites(L, split) * 16u; }
 constexpr uint32_t kLinkCopies = 32;  // partial link-overlap histograms (see launch_link_overlap)
 // Energy models.  kModelPm: J = +-1, the energy word of a replica is U, the
 // number of unsatisfied bonds (E = 2U - 3N).  kModelGauss16: J = k / 16 with
@@ -225,9 +228,9 @@ inline uint32_t blocks_sweep(uint32_t capacity) { return (capacity / 64 + 7) / 8
 // timings on MI355X: eight waves pay off on large lattices and on launches too
 // small to fill the chip with four; L = 4 has only four row blocks per colour.
 inline uint32_t sweep_split_default(uint32_t model, uint32_t L, uint64_t tiles) {
-  // +-J (bit-sliced colour pass): eight waves from L = 12 up, where a wave's
-  // plane group is one or two blocks and the longer rows hide less latency
-  const uint32_t big = model == kModelPm ? 12u : 14u;
+  // +-J (bit-sliced colour pass): eight waves from L = 10 up (at L = 10 they
+  // take three blocks per plane group against two with four waves)
+  const uint32_t big = model == kModelPm ? 10u : 14u;
   return (L >= big || (L >= 6 && tiles < 2048)) ? 8u : 4u;
 }
 // The split a launch uses: the autotuner's choice for (model, layout, L, size

@@ -559,11 +559,11 @@ __device__ __forceinline__ uint32_t plane_byte(uint32_t r) {
 // of block bi = l / BS (BS = 4 L/2 sites per block of four rows; GB blocks
 // per group, rows rb0 + step bi .. + 3) and writes entry l of the wave's
 // plane area: 64 bytes, byte plane_byte(r) = 8 nu of replica r at that site.
-template <int L>
+template <int L, int SPLIT>
 __device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* __restrict__ sites,
                                             uint32_t own0, uint32_t rb0, uint32_t step,
                                             uint32_t lane, uint32_t* planes) {
-  constexpr uint32_t H = L / 2, BS = 4 * H, GB = plane_blocks(L), ROWS = L * L;
+  constexpr uint32_t H = L / 2, BS = 4 * H, GB = plane_blocks(L, SPLIT), ROWS = L * L;
   const uint32_t bi = lane / BS, sb = lane - bi * BS;
   const uint32_t rb = rb0 + step * bi;
   if (bi < GB && rb < ROWS) {
@@ -622,12 +622,12 @@ __device__ __forceinline__ void block_planes(const TileCtx& c, const char* ownb,
 // One +-J colour pass of this wave (blocks rb = 4 part + 4 nparts i, as in
 // sweep_colour_blocks), GB blocks at a time: phase 1 for the group, then
 // phase 2 block by block.  The wave's plane area holds one group.
-template <int L, bool ACCUM>
+template <int L, int SPLIT, bool ACCUM>
 __device__ uint32_t sweep_colour_planes(const TileCtx& c, const SiteEntry* __restrict__ sites,
                                         uint32_t colour, uint32_t part, uint32_t nparts,
                                         uint32_t* planes, uint32_t lane) {
   constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L, BS = 4 * H;
-  constexpr uint32_t GB = plane_blocks(L);
+  constexpr uint32_t GB = plane_blocks(L, SPLIT);
   const uint32_t own0 = colour * (N / 2);
   const uint32_t step = 4 * nparts;
   uint32_t usum = 0;
@@ -636,7 +636,7 @@ __device__ uint32_t sweep_colour_planes(const TileCtx& c, const SiteEntry* __res
   const uint8_t* const plane_l = reinterpret_cast<const uint8_t*>(planes) + plane_byte(lane);
   const char* const own_h = reinterpret_cast<const char*>(c.lds) + c.hoff;
   for (uint32_t rb0 = 4 * part; rb0 < ROWS; rb0 += step * GB) {
-    plane_group<L>(c, sites, own0, rb0, step, lane, planes);
+    plane_group<L, SPLIT>(c, sites, own0, rb0, step, lane, planes);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
     for (uint32_t bi = 0; bi < GB; ++bi) {
@@ -1288,15 +1288,15 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
     } else {
       // this wave's plane area (phase 1 of the +-J colour passes), after the
       // tile image and the per-replica reduction area
-      uint32_t* const planes = lds_all + 2 * N + 64 * SPLIT + plane_words(L) * part;
+      uint32_t* const planes = lds_all + 2 * N + 64 * SPLIT + plane_words(L, SPLIT) * part;
       for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
         c.t = sp.t0 + s;
-        sweep_colour_planes<L, false>(c, P.sites, 0u, part, SPLIT, planes, lane);
-        sweep_colour_planes<L, false>(c, P.sites, 1u, part, SPLIT, planes, lane);
+        sweep_colour_planes<L, SPLIT, false>(c, P.sites, 0u, part, SPLIT, planes, lane);
+        sweep_colour_planes<L, SPLIT, false>(c, P.sites, 1u, part, SPLIT, planes, lane);
       }
       c.t = sp.t0 + sp.n_sweeps - 1;
-      sweep_colour_planes<L, false>(c, P.sites, 0u, part, SPLIT, planes, lane);
-      U = sweep_colour_planes<L, true>(c, P.sites, 1u, part, SPLIT, planes, lane);
+      sweep_colour_planes<L, SPLIT, false>(c, P.sites, 0u, part, SPLIT, planes, lane);
+      U = sweep_colour_planes<L, SPLIT, true>(c, P.sites, 1u, part, SPLIT, planes, lane);
     }
   }
   // Epilogue.  The lane number, the slot, its source and the descriptor
@@ -1716,7 +1716,7 @@ void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t 
   // after the tile image and the reduction area: the Gaussian threshold table,
   // or the +-J plane areas (one per wave)
   const size_t gbytes = model == kModelGauss16 ? (size_t)(kGaussDEMax + 1) * 8
-                                               : (size_t)plane_words(L) * 4 * split;
+                                               : (size_t)plane_words(L, split) * 4 * split;
   const size_t lds = (size_t)L * L * L * 8 + 4 * 64 * split + gbytes;
   if (model == kModelGauss16) {
     if (split == 8)
