@@ -73,13 +73,14 @@ BYTES_PER_REPLICA_FIXED = 20
 # copy of known size reads), per launch, with the source it was taken on.
 # Reported only while the kernel source is unchanged.
 TRAFFIC = {
-    "kernel_src_sha256": "0b51d0bffdf6b93d2b320fa3697d8e10bee8dd770fc5fac695fc72fc765b7f36",
-    # 33168.8 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
-    "bytes_per_launch": (33168.8 * 2 + 64942.3) * 1024,
-    # the same for the Gaussian-coupling sweep: 32881.6 x 2 + 64951.6 KiB
-    "gauss16_bytes_per_launch": (32881.6 * 2 + 64951.6) * 1024,
-    # k_link_overlap at L=10, 5e5 pairs: 61562.5 x 2 + 10484.4 KiB
-    "link_overlap_bytes_per_launch": (61562.5 * 2 + 10484.4) * 1024,
+    "kernel_src_sha256": "a18bfdc9ceeb9ac11a644cdaae1a64e1f81d8624ca281166ad32178bee66b7a6",
+    # 32767.2 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
+    # (eight waves per tile, the built-in form at this size)
+    "bytes_per_launch": (32767.2 * 2 + 64942.3) * 1024,
+    # the same for the Gaussian-coupling sweep: 32888.9 x 2 + 64951.6 KiB
+    "gauss16_bytes_per_launch": (32888.9 * 2 + 64951.6) * 1024,
+    # k_link_overlap at L=10, 5e5 pairs: 61562.6 x 2 + 10484.4 KiB
+    "link_overlap_bytes_per_launch": (61562.6 * 2 + 10484.4) * 1024,
     "profile": "profiles/k_sweep_L10_R500k_bitpack64_hbm_counters.md",
 }
 
