@@ -73,12 +73,12 @@ BYTES_PER_REPLICA_FIXED = 20
 # copy of known size reads), per launch, with the source it was taken on.
 # Reported only while the kernel source is unchanged.
 TRAFFIC = {
-    "kernel_src_sha256": "a18bfdc9ceeb9ac11a644cdaae1a64e1f81d8624ca281166ad32178bee66b7a6",
-    # 32767.2 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
+    "kernel_src_sha256": "6602fe1829a2f7fa7e80f1ef85134f03aeec7154ddf76abc5d1fa7c9b622cce7",
+    # 32767.4 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
     # (eight waves per tile, the built-in form at this size)
-    "bytes_per_launch": (32767.2 * 2 + 64942.3) * 1024,
-    # the same for the Gaussian-coupling sweep: 32888.9 x 2 + 64951.6 KiB
-    "gauss16_bytes_per_launch": (32888.9 * 2 + 64951.6) * 1024,
+    "bytes_per_launch": (32767.4 * 2 + 64942.3) * 1024,
+    # the same for the Gaussian-coupling sweep: 32885.8 x 2 + 64951.6 KiB
+    "gauss16_bytes_per_launch": (32885.8 * 2 + 64951.6) * 1024,
     # k_link_overlap at L=10, 5e5 pairs: 61562.6 x 2 + 10484.4 KiB
     "link_overlap_bytes_per_launch": (61562.6 * 2 + 10484.4) * 1024,
     "profile": "profiles/k_sweep_L10_R500k_bitpack64_hbm_counters.md",

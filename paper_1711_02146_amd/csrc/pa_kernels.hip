@@ -604,7 +604,6 @@ __device__ __forceinline__ void block_planes(const TileCtx& c, const char* ownb,
   if constexpr (S % 4 == 0) {
     if (c.any_draw) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
   }
-  __builtin_assume(a8 < 256u);  // a byte: no mask before the address
   const unsigned long long thr = *reinterpret_cast<const unsigned long long*>(
       reinterpret_cast<const char*>(c.thr_of_nu) + a8);
   const bool acc = (unsigned long long)d.w[S % 4] < thr;
