@@ -215,11 +215,9 @@ def batched_bench(pam, layout="bitpack64"):
     import numpy as np
     import torch
 
-    import oracle
-
     c = BATCH
     insts = batch_instances(c)
-    betas = oracle.linear_schedule(c["beta_max"], c["n_temps"])
+    betas = pam.linear_schedule(c["beta_max"], c["n_temps"])
     n_steps = len(betas) - 1
     attempts = sum(2 * n_steps * c["n_sweeps"] * L ** 3 * R for (L, R, *_r) in insts)
     # batched: creation (init of every population, graph capture) + all steps + results

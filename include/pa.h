@@ -58,7 +58,20 @@ enum {
   PA_ECAPACITY = -3,  /* resampled population would exceed the capacity */
   PA_EDEVICE = -4,    /* a HIP call failed; the instance is now unusable */
   PA_ESTATE = -5,     /* call out of order (e.g. a failed instance) */
-  PA_ESCHEDULE = -6   /* constant-culling step impossible: eps(0) > target */
+  PA_ESCHEDULE = -6,  /* constant-culling step impossible: eps(0) > target */
+  PA_ECHECK = -7      /* PA_FLAG_CHECK_ENERGY: a stored energy word differs from the energy
+                         recomputed from the spins; the instance is now unusable */
+};
+
+/* pa_params.flags bits (debugging aids; 0 for production runs). */
+enum {
+  PA_FLAG_CHECK_ENERGY = 1u, /* after every sweep launch, and before every call that reads the
+                                energy histogram (pa_resample, pa_choose_beta, pa_observables),
+                                recompute each replica's energy word from its spins and the
+                                couplings (the Sec. II.A Hamiltonian) and compare it with the
+                                stored word; any difference is PA_ECHECK.  Costs one extra
+                                kernel and one synchronisation per checked call. */
+  PA_FLAG_FAULT_HOOK = 2u    /* allow pa_debug_inject on this instance */
 };
 
 enum {
@@ -83,7 +96,7 @@ typedef struct {
   uint32_t capacity; /* max population held; 0 selects R + 16*isqrt(R) + 256 */
   uint32_t layout;   /* PA_LAYOUT_* */
   uint64_t seed;     /* population seed: Philox key of every draw of this population */
-  uint32_t flags;    /* reserved, must be 0 */
+  uint32_t flags;    /* PA_FLAG_* bits; any other bit is PA_EINVAL */
   uint32_t model;    /* PA_MODEL_*: the coupling distribution J_host is drawn from */
 } pa_params;
 
@@ -106,6 +119,10 @@ typedef struct {
   uint32_t n_at_E_min; /* replicas at E_min (ground-state estimators, Sec. II.A); 0 in the
                           record pa_resample returns (it is taken before the sweeps) */
   uint32_t reserved;
+  double sum_lnQ;      /* sum of ln Q over the steps so far (Eq. 9: beta F = -(N ln 2 +
+                          sum_lnQ)); with the exported spins, family labels, R_tilde,
+                          sweeps_done, step and beta it is the whole state a checkpoint
+                          needs (pa_import_state) */
 } pa_obs;
 
 /* Bytes of device workspace an instance with these parameters needs. 0 on bad params. */
@@ -192,6 +209,21 @@ int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* f
 
 /* Release the host-side handle (the caller frees the workspace afterwards). */
 int pa_free(pa_instance* in);
+
+/* Fault injection for tests of callers' error handling (instances created
+ * with PA_FLAG_FAULT_HOOK only; PA_EINVAL otherwise or for an unknown `what`).
+ * Everything is done on the host: no kernel is made to fail.
+ *   PA_INJECT_FAIL_AFTER: after `arg` more calls on this instance return
+ *     normally, the next one returns PA_EDEVICE without queuing any work and
+ *     the instance becomes unusable, as after a real HIP error.  Calls that
+ *     count: pa_sweep, pa_resample, pa_choose_beta, pa_observables, the two
+ *     overlap calls (for either instance), the export/import calls,
+ *     pa_autotune_sweep and pa_stepper_step (per instance in its set).
+ *   PA_INJECT_ENERGY: add 1 to the stored energy word of replica `arg`
+ *     (< R~) with a host-to-device copy, so that a PA_FLAG_CHECK_ENERGY
+ *     check finds it.  Synchronises. */
+enum { PA_INJECT_FAIL_AFTER = 1, PA_INJECT_ENERGY = 2 };
+int pa_debug_inject(pa_instance* in, uint32_t what, uint32_t arg);
 
 /* +-J couplings of one disorder sample (Sec. II.A model with couplings +-1 of
  * probability 1/2), on the host: J_out[b] = +1 if bit 31 of word (b & 3) of
@@ -280,6 +312,12 @@ int pa_stepper_create(uint32_t max_pops, uint32_t max_L, void* d_workspace, size
  * PA_EINVAL.  Synchronises the stream. */
 int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const double* beta_next,
                     const uint32_t* n_sweeps, pa_obs* obs, int32_t* status);
+
+/* pa_stepper_step is also the batch step to caller-given temperatures (the
+ * "batch step with beta_next per instance" of a batch interface): a stepper
+ * over the batch's instances, called with one beta_next per instance, advances
+ * them all by one step in one set of launches.  pa_batch_run replays steps whose
+ * temperatures were fixed at creation, as captured graphs. */
 
 /* Release a stepper (its instances stay valid). */
 int pa_stepper_free(pa_stepper* s);

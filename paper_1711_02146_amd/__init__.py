@@ -25,6 +25,12 @@ PA_ECAPACITY = -3
 PA_EDEVICE = -4
 PA_ESTATE = -5
 PA_ESCHEDULE = -6
+PA_ECHECK = -7
+
+PA_FLAG_CHECK_ENERGY = 1
+PA_FLAG_FAULT_HOOK = 2
+PA_INJECT_FAIL_AFTER = 1
+PA_INJECT_ENERGY = 2
 
 PA_MODEL_PM = 0
 PA_MODEL_GAUSS16 = 1
@@ -48,7 +54,8 @@ class pa_obs(ctypes.Structure):
                 ("eps_expected", ctypes.c_double), ("R_tilde", ctypes.c_uint32),
                 ("n_culled", ctypes.c_uint32), ("E_min", ctypes.c_int32), ("step", ctypes.c_uint32),
                 ("sum_eta2", ctypes.c_uint64), ("sweeps_done", ctypes.c_uint64),
-                ("n_at_E_min", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("n_at_E_min", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("sum_lnQ", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -122,6 +129,7 @@ def lib():
         "pa_probe_scratch_bytes": (ctypes.c_size_t, []),
         "pa_make_couplings_pm": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, _vp]),
         "pa_probe_ceilings": (ctypes.c_int, [_vp, ctypes.c_size_t, _vp, _P(pa_ceilings)]),
+        "pa_debug_inject": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -138,7 +146,7 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
             "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset", "pa_probe_scratch_bytes",
             "pa_probe_ceilings", "pa_make_couplings_pm", "pa_autotune_set",
-            "pa_link_overlap_hist"]
+            "pa_link_overlap_hist", "pa_debug_inject"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -241,6 +249,17 @@ def pa_make_couplings_pm(L: int, coupling_seed: int) -> np.ndarray:
 
 def pa_free(handle: int):
     _check(lib().pa_free(handle), "pa_free")
+
+
+def pa_debug_inject(handle: int, what: int, arg: int):
+    _check(lib().pa_debug_inject(handle, int(what), int(arg)), "pa_debug_inject")
+
+
+def linear_schedule(beta_max: float, n_temps: int):
+    """beta_k = (beta_max k) / (N_T - 1), k = 0 .. N_T - 1, each formed that way
+    in FP64 (not accumulated): the ascending linear schedule of N_T temperatures
+    from 0 to beta_max (Sec. II loop)."""
+    return [(beta_max * k) / (n_temps - 1) for k in range(n_temps)]
 
 
 def pa_batch_workspace_bytes(n_pops: int, n_pairs: int, n_steps: int, max_L: int) -> int:
@@ -354,14 +373,16 @@ class Population:
     """One PA population on a GPU: workspace tensor + library handle."""
 
     def __init__(self, L: int, R: int, J: np.ndarray, seed: int, capacity: int = 0,
-                 layout: str = "bitpack64", device=None, stream=None, model: str = "pm"):
-        """model "pm": J holds +-1; "gauss16": J holds k = 16 J in [-127, 127]."""
+                 layout: str = "bitpack64", device=None, stream=None, model: str = "pm",
+                 flags: int = 0):
+        """model "pm": J holds +-1; "gauss16": J holds k = 16 J in [-127, 127].
+        flags: PA_FLAG_* bits (debugging aids)."""
         import torch
 
         self.L, self.N, self.R = int(L), int(L) ** 3, int(R)
         self.model = model
         self.params = pa_params(L=L, R=R, capacity=capacity, layout=LAYOUTS[layout], seed=seed,
-                                flags=0, model=MODELS[model])
+                                flags=int(flags), model=MODELS[model])
         nbytes = pa_workspace_bytes(self.params)
         if nbytes == 0:
             raise PAError(PA_EINVAL, "pa_workspace_bytes")

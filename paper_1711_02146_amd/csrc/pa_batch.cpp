@@ -364,7 +364,7 @@ int pa_batch_results(pa_batch* b, pa_obs* obs, uint64_t* qhist, int32_t* status,
       const pa::StepRecord& r = rec[(size_t)s * np + p];
       pa_obs* o = obs ? obs + (size_t)s * np + p : nullptr;
       if (r.status != 0) {
-        st = PA_ECAPACITY;
+        st = r.status == 2 ? PA_EDEVICE : PA_ECAPACITY;
         if (o) std::memset(o, 0, sizeof(*o));
         for (uint32_t t = s + 1; t < n; ++t)
           if (obs) std::memset(obs + (size_t)t * np + p, 0, sizeof(pa_obs));
@@ -390,6 +390,7 @@ int pa_batch_results(pa_batch* b, pa_obs* obs, uint64_t* qhist, int32_t* status,
       o->n_at_E_min = r.n_at_E_min;
         o->step = b->step0[p] + s + 1;
         o->sweeps_done = b->sweeps0[p] + (uint64_t)(s + 1) * b->n_sweeps;
+        o->sum_lnQ = sum_lnQ;
       }
       completed = s + 1;
       in->last_dbeta = dbeta;
@@ -408,7 +409,9 @@ int pa_batch_results(pa_batch* b, pa_obs* obs, uint64_t* qhist, int32_t* status,
     in->sum_lnQ = sum_lnQ;
     in->pending_gather = false;
     in->hist_valid = false;
-    if (st != PA_OK) {
+    if (st == PA_EDEVICE) {
+      in->failed = true;  // the sweep kernel found its LDS layout unusable
+    } else if (st != PA_OK) {
       // the failed step left the population as it was; clear its flags
       pa::DevScalars sc{};
       PB_HIP(hipMemcpy(&sc, P.sc, sizeof(sc), hipMemcpyDeviceToHost));

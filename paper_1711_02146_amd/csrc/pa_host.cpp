@@ -48,7 +48,9 @@ bool make_layout(const pa_params* p, Layout* out) {
   if (!p) return false;
   if (p->L < 4 || p->L > (uint32_t)pa::kMaxL || (p->L & 1u)) return false;
   if (p->R < 1) return false;
-  if (p->flags != 0 || (p->model != PA_MODEL_PM && p->model != PA_MODEL_GAUSS16)) return false;
+  if ((p->flags & ~(uint32_t)(PA_FLAG_CHECK_ENERGY | PA_FLAG_FAULT_HOOK)) != 0 ||
+      (p->model != PA_MODEL_PM && p->model != PA_MODEL_GAUSS16))
+    return false;
   uint32_t layout = p->layout == PA_LAYOUT_AUTO ? (uint32_t)PA_LAYOUT_BITPACK64 : p->layout;
   if (layout != PA_LAYOUT_INT8 && layout != PA_LAYOUT_BITPACK64) return false;
   uint64_t cap = p->capacity ? (uint64_t)p->capacity
@@ -372,6 +374,31 @@ hipError_t set_thresholds(pa_instance* in, double beta, pa::PopStep* ps) {
 
 bool usable(pa_instance* in) { return in && !in->failed && !in->in_batch; }
 
+// Entry of every call on an instance: PA_ESTATE for an unusable one, then one
+// call counted for fault injection.
+int enter(pa_instance* in) {
+  if (!usable(in)) return PA_ESTATE;
+  return pa_host::count_call(in);
+}
+
+// PA_FLAG_CHECK_ENERGY: every replica's stored energy word of the current
+// buffer against the energy recomputed from its spins.  Synchronises.
+int check_energy(pa_instance* in) {
+  if (!(in->flags & PA_FLAG_CHECK_ENERGY)) return PA_OK;
+  const DevPop& P = in->dev;
+  PA_HIP(in, pa::launch_fill_u32(&P.sc->check_bad, 0u, 1, in->stream));
+  PA_HIP(in, pa::launch_energy(one_set(in, plain_step(in->cur)),
+                               group_of(in, in->d_meta->etiles, in->meta.etiles[1]), P.layout, P.L,
+                               P.model, true, in->stream));
+  PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
+  PA_HIP(in, hipStreamSynchronize(in->stream));
+  if (in->h_sc->check_bad != 0) {
+    in->failed = true;
+    return PA_ECHECK;
+  }
+  return PA_OK;
+}
+
 // Philox4x32-10 on the host (Salmon et al., SC'11): counter (c0, c1, c2, c3),
 // key (k0, k1); each round multiplies c0 and c2 by the round constants,
 // swaps in the high halves XORed with the other counter words and the key,
@@ -428,6 +455,7 @@ const char* pa_strerror(int status) {
     case PA_EDEVICE: return "HIP error (instance unusable)";
     case PA_ESTATE: return "call out of order or instance unusable";
     case PA_ESCHEDULE: return "constant-culling step impossible (eps(0) > target)";
+    case PA_ECHECK: return "energy check failed (instance unusable)";
     default: return "unknown status";
   }
 }
@@ -449,6 +477,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   pa_instance* in = new (std::nothrow) pa_instance();
   if (!in) return PA_EINVAL;
   in->lay = l;
+  in->flags = p->flags;
   in->stream = static_cast<hipStream_t>(hip_stream);
   in->ws = static_cast<uint8_t*>(d_workspace);
   build_sites(l.L, J_host, &in->sites, &in->cm_of_site, &in->rowj);
@@ -545,7 +574,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   // quantised Gaussian couplings: the energy word is E16, formed from the spins
   if (l.model == PA_MODEL_GAUSS16 &&
       pa::launch_energy(one_set(in, plain_step(0)), group_of(in, in->d_meta->etiles, mt.etiles[1]),
-                        l.layout, l.L, l.model, in->stream) != hipSuccess)
+                        l.layout, l.L, l.model, false, in->stream) != hipSuccess)
     return fail(PA_EDEVICE);
   in->cur = 0;
   in->R_tilde = l.R;
@@ -569,8 +598,31 @@ int pa_free(pa_instance* in) {
   return PA_OK;
 }
 
-int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps) {
+int pa_debug_inject(pa_instance* in, uint32_t what, uint32_t arg) {
+  if (!in || !(in->flags & PA_FLAG_FAULT_HOOK)) return PA_EINVAL;
   if (!usable(in)) return PA_ESTATE;
+  if (what == PA_INJECT_FAIL_AFTER) {
+    in->fail_countdown = (int64_t)arg;
+    return PA_OK;
+  }
+  if (what != PA_INJECT_ENERGY) return PA_EINVAL;
+  int rc = materialize(in);
+  if (rc) return rc;
+  PA_HIP(in, hipMemcpyAsync(in->h_sc, in->dev.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
+                            in->stream));
+  PA_HIP(in, hipStreamSynchronize(in->stream));
+  if (arg >= in->h_sc->R_tilde) return PA_EINVAL;
+  uint32_t* word = in->dev.U[in->cur] + arg;
+  uint32_t v = 0;
+  PA_HIP(in, hipMemcpy(&v, word, 4, hipMemcpyDeviceToHost));
+  v += 1u;
+  PA_HIP(in, hipMemcpy(word, &v, 4, hipMemcpyHostToDevice));
+  in->hist_valid = false;
+  return PA_OK;
+}
+
+int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps) {
+  if (int rc0 = enter(in)) return rc0;
   if (!(beta >= 0.0) || !std::isfinite(beta)) return PA_EINVAL;
   if (n_sweeps == 0) return PA_OK;
   if (in->sweeps + n_sweeps > 0xFFFFFFFFull) return PA_EINVAL;  // sweep counter is 32-bit
@@ -584,13 +636,14 @@ int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps) {
   in->pending_gather = false;
   in->hist_valid = false;
   in->sweeps += n_sweeps;
-  return PA_OK;
+  return check_energy(in);
 }
 
 int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
-  if (!usable(in)) return PA_ESTATE;
+  if (int rc0 = enter(in)) return rc0;
   if (!std::isfinite(beta_next)) return PA_EINVAL;
-  int rc;
+  int rc = check_energy(in);
+  if (rc) return rc;
   if (!in->hist_valid || in->pending_gather) {
     rc = fetch_hist(in, false);
     if (rc) return rc;
@@ -643,15 +696,17 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
     step_out->n_culled = in->last_n_culled;
     step_out->step = in->step;
     step_out->sweeps_done = in->sweeps;
+    step_out->sum_lnQ = in->sum_lnQ;
   }
   return PA_OK;
 }
 
 int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* beta_next) {
-  if (!usable(in)) return PA_ESTATE;
+  if (int rc0 = enter(in)) return rc0;
   if (!beta_next || !std::isfinite(eps_target) || !std::isfinite(beta_max) || eps_target < 0.0)
     return PA_EINVAL;
   if (!(beta_max > in->beta)) return PA_EINVAL;
+  if (int rc = check_energy(in)) return rc;
   if (!in->hist_valid || in->pending_gather) {
     int rc = fetch_hist(in, false);
     if (rc) return rc;
@@ -708,9 +763,11 @@ int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* 
 }
 
 int pa_observables(pa_instance* in, pa_obs* out) {
-  if (!usable(in)) return PA_ESTATE;
+  if (int rc0 = enter(in)) return rc0;
   if (!out) return PA_EINVAL;
-  int rc = fetch_hist(in, true);
+  int rc = check_energy(in);
+  if (rc) return rc;
+  rc = fetch_hist(in, true);
   if (rc) return rc;
   const DevPop& P = in->dev;
   const uint32_t* h = in->h_hist;
@@ -740,11 +797,14 @@ int pa_observables(pa_instance* in, pa_obs* out) {
   out->n_at_E_min = jmin >= 0 ? h[jmin] : 0u;
   out->step = in->step;
   out->sweeps_done = in->sweeps;
+  out->sum_lnQ = in->sum_lnQ;
   return PA_OK;
 }
 
 int pa_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hist_out) {
   if (!usable(a) || !usable(b)) return PA_ESTATE;
+  if (int rc0 = enter(a)) return rc0;
+  if (int rc0 = enter(b)) return rc0;
   if (nbins != 65 || !hist_out || a == b) return PA_EINVAL;
   if (a->dev.L != b->dev.L || a->dev.layout != b->dev.layout) return PA_EINVAL;
   int rc = materialize(a);
@@ -777,6 +837,8 @@ int pa_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hi
 
 int pa_link_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hist_out) {
   if (!usable(a) || !usable(b)) return PA_ESTATE;
+  if (int rc0 = enter(a)) return rc0;
+  if (int rc0 = enter(b)) return rc0;
   if (!hist_out || a == b) return PA_EINVAL;
   if (a->dev.L != b->dev.L || a->dev.layout != b->dev.layout) return PA_EINVAL;
   if (nbins != 3 * a->dev.N + 1) return PA_EINVAL;
@@ -798,7 +860,7 @@ int pa_link_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_
 
 int pa_export_state(pa_instance* in, int8_t* spins_host, uint32_t* U_host, uint32_t* family_host,
                     uint32_t* R_tilde) {
-  if (!usable(in)) return PA_ESTATE;
+  if (int rc0 = enter(in)) return rc0;
   if (!R_tilde) return PA_EINVAL;
   int rc = materialize(in);
   if (rc) return rc;
@@ -839,7 +901,7 @@ int pa_export_state(pa_instance* in, int8_t* spins_host, uint32_t* U_host, uint3
 
 int pa_export_counts(pa_instance* in, uint32_t* counts_host, uint32_t* offsets_host,
                      uint32_t* n_old) {
-  if (!usable(in)) return PA_ESTATE;
+  if (int rc0 = enter(in)) return rc0;
   if (!n_old) return PA_EINVAL;
   *n_old = in->last_R_old;
   if (in->step == 0) return PA_ESTATE;
@@ -855,7 +917,7 @@ int pa_export_counts(pa_instance* in, uint32_t* counts_host, uint32_t* offsets_h
 int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* family_host,
                     uint32_t R_tilde, uint64_t sweeps_done, uint32_t step, double beta,
                     double sum_lnQ) {
-  if (!usable(in)) return PA_ESTATE;
+  if (int rc0 = enter(in)) return rc0;
   const DevPop& P = in->dev;
   if (!spins_host || !family_host || R_tilde > P.cap_limit || !std::isfinite(beta) ||
       !std::isfinite(sum_lnQ) || sweeps_done > 0xFFFFFFFFull)
@@ -892,7 +954,7 @@ int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* f
   PA_HIP(in, hipMemcpy(P.sc, &sc, sizeof(sc), hipMemcpyHostToDevice));
   PA_HIP(in, pa::launch_energy(one_set(in, plain_step(in->cur)),
                                group_of(in, in->d_meta->etiles, in->meta.etiles[1]), P.layout,
-                               P.L, P.model, in->stream));
+                               P.L, P.model, false, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
   in->R_tilde = R_tilde;
   in->sweeps = sweeps_done;
@@ -907,7 +969,7 @@ int pa_import_state(pa_instance* in, const int8_t* spins_host, const uint32_t* f
 
 int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t repeats,
                       uint32_t* split_out, float* ms_out) {
-  if (!usable(in)) return PA_ESTATE;
+  if (int rc0 = enter(in)) return rc0;
   if (in->pending_gather) return PA_ESTATE;
   if (!(beta >= 0.0) || !std::isfinite(beta)) return PA_EINVAL;
   if (n_sweeps == 0 || repeats == 0 || repeats > 1000) return PA_EINVAL;

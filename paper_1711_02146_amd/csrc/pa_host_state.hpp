@@ -109,5 +109,25 @@ struct pa_instance {
   unsigned long long* h_gthr = nullptr;  // PA_MODEL_GAUSS16 threshold table staging
   hipEvent_t gthr_copied = nullptr;      // recorded after each copy out of h_gthr
   bool in_batch = false;
+  uint32_t flags = 0;                 // PA_FLAG_* of the instance's parameters
+  int64_t fail_countdown = -1;        // PA_INJECT_FAIL_AFTER: calls left before the failure
 };
 
+namespace pa_host {
+
+// Counts one call on a usable instance: with an armed PA_INJECT_FAIL_AFTER
+// countdown, the call at which it runs out fails as a HIP error would, before
+// anything is queued, and the instance becomes unusable.
+inline int count_call(pa_instance* in) {
+  if (in->fail_countdown >= 0) {
+    if (in->fail_countdown == 0) {
+      in->fail_countdown = -1;
+      in->failed = true;
+      return PA_EDEVICE;
+    }
+    --in->fail_countdown;
+  }
+  return PA_OK;
+}
+
+}  // namespace pa_host

@@ -76,7 +76,7 @@ struct DevScalars {
                           // 2: a kernel found its LDS layout unusable
   uint32_t n_culled;      // replicas with zero copies in the last resampling step
   unsigned long long sum_eta2;  // sum over families of eta^2
-  uint32_t reserved;
+  uint32_t check_bad;     // energy check: replicas whose stored word differs from the spins'
   uint32_t dead;          // batch runs: set when a step overflowed; later steps skip it
   int32_t E_lo, E_hi;     // kModelGauss16: lowest / highest E16 of the population
   uint32_t pad[6];
@@ -145,7 +145,8 @@ struct StepRecord {
   uint32_t R_new;          // population size after resampling and sweeps
   uint32_t n_culled;
   int32_t E_min;           // lowest energy after the sweeps
-  uint32_t status;         // 0 ok, 1 capacity overflow (population dead from here on)
+  uint32_t status;         // 0 ok, 1 capacity overflow (population dead from here on),
+                           // 2 the sweep kernel found its LDS layout unusable (dead)
   uint32_t n_at_E_min;     // replicas at E_min
   uint32_t pad;
 };
@@ -201,8 +202,11 @@ hipError_t launch_record(const BatchDev& B, const Group& per_pop, hipStream_t st
 hipError_t launch_overlap(const BatchDev& B, const Group& pairs, const uint32_t* pair_pops,
                           uint32_t layout, bool post, uint32_t cur_a, uint32_t cur_b,
                           hipStream_t stream);
+// energy word of every replica of buffer cur recomputed from its spins: stored
+// (check == false), or compared with the stored word, the number of replicas
+// that differ added to sc->check_bad (check == true)
 hipError_t launch_energy(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
-                         uint32_t model, hipStream_t stream);
+                         uint32_t model, bool check, hipStream_t stream);
 // link-overlap histogram of slot i of a against slot i of b, i < min of their
 // R~ (read on the device): the pairs count into kLinkCopies partial histograms
 // part[kLinkCopies][3N + 1] (u32, cleared by the host first), which are then

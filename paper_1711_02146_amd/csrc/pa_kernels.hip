@@ -1234,7 +1234,10 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   // at LDS address 0.  If the toolchain ever places it elsewhere, report a
   // configuration error instead of computing with a wrong table.
   if ((uint32_t)(uintptr_t)thr_of_nu != 0u) {
-    if (threadIdx.x == 0) P.sc->err = 2u;
+    if (threadIdx.x == 0) {
+      P.sc->err = 2u;
+      P.sc->dead = 1u;
+    }
     return;
   }
   if (threadIdx.x < 8)
@@ -1326,8 +1329,9 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
 }
 
 // The energy word recomputed from the stored spins of buffer cur (after an
-// import; for kModelGauss16 also after the initial spins are drawn).
-template <int LAYOUT, int L, int M>
+// import; for kModelGauss16 also after the initial spins are drawn), or, with
+// CHECK, compared with the stored word (the debug energy check).
+template <int LAYOUT, int L, int M, bool CHECK>
 __global__ __launch_bounds__(64) void k_energy(BatchDev B, Group G) {
   constexpr uint32_t N = L * L * L;
   extern __shared__ uint32_t lds[];
@@ -1348,7 +1352,13 @@ __global__ __launch_bounds__(64) void k_energy(BatchDev B, Group G) {
   c.rowk = P.rowk;
   c.rowk_stride = P.rowk_stride;
   const uint32_t U = tile_energy_rows<L, M>(c, P.rowj, 0u, 1u);
-  if (valid) pick(P.U, sp.cur)[j] = U;
+  if (CHECK) {
+    const bool bad = valid && pick(P.U, sp.cur)[j] != U;
+    const unsigned long long m = __ballot(bad);
+    if (lane == 0 && m) atomicAdd(&P.sc->check_bad, (uint32_t)__popcll(m));
+  } else if (valid) {
+    pick(P.U, sp.cur)[j] = U;
+  }
 }
 
 // Sum over families of eta^2 (Sec. III.A) from the family labels, which stay
@@ -1402,7 +1412,12 @@ __global__ __launch_bounds__(256) void k_record(BatchDev B, Group G) {
   const Member m = member_of(G);
   const DevPop P = B.pops[m.pop];
   StepRecord* rec = record_of(B, m.pop);
-  if (!rec || P.sc->dead) return;
+  if (!rec) return;
+  if (P.sc->err == 2u) {  // the sweep did not run: report it, and nothing else
+    if (threadIdx.x == 0) rec->status = 2u;
+    return;
+  }
+  if (P.sc->dead) return;
   if (threadIdx.x == 0) smin = 0x7FFFFFFF;
   __syncthreads();
   long long acc = 0;
@@ -1735,25 +1750,35 @@ void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t 
 }
 
 template <int LAYOUT, int L>
-void launch_energy_l(const BatchDev& B, const Group& g, uint32_t model, hipStream_t stream) {
+void launch_energy_l(const BatchDev& B, const Group& g, uint32_t model, bool check,
+                     hipStream_t stream) {
   const size_t lds = (size_t)L * L * L * 8;
-  if (model == kModelGauss16)
-    hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelGauss16>), dim3(g.blocks), dim3(64), lds, stream,
-                       B, g);
-  else
-    hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelPm>), dim3(g.blocks), dim3(64), lds, stream, B,
-                       g);
+  if (model == kModelGauss16) {
+    if (check)
+      hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelGauss16, true>), dim3(g.blocks), dim3(64), lds,
+                         stream, B, g);
+    else
+      hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelGauss16, false>), dim3(g.blocks), dim3(64),
+                         lds, stream, B, g);
+  } else {
+    if (check)
+      hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelPm, true>), dim3(g.blocks), dim3(64), lds,
+                         stream, B, g);
+    else
+      hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelPm, false>), dim3(g.blocks), dim3(64), lds,
+                         stream, B, g);
+  }
 }
 
 #define PA_L_SWITCH(FN, LAYOUT)      \
   switch (L) {                       \
-    case 4: FN<LAYOUT, 4>(B, g, model, stream); break;   \
-    case 6: FN<LAYOUT, 6>(B, g, model, stream); break;   \
-    case 8: FN<LAYOUT, 8>(B, g, model, stream); break;   \
-    case 10: FN<LAYOUT, 10>(B, g, model, stream); break; \
-    case 12: FN<LAYOUT, 12>(B, g, model, stream); break; \
-    case 14: FN<LAYOUT, 14>(B, g, model, stream); break; \
-    case 16: FN<LAYOUT, 16>(B, g, model, stream); break; \
+    case 4: FN<LAYOUT, 4>(B, g, model, check, stream); break;   \
+    case 6: FN<LAYOUT, 6>(B, g, model, check, stream); break;   \
+    case 8: FN<LAYOUT, 8>(B, g, model, check, stream); break;   \
+    case 10: FN<LAYOUT, 10>(B, g, model, check, stream); break; \
+    case 12: FN<LAYOUT, 12>(B, g, model, check, stream); break; \
+    case 14: FN<LAYOUT, 14>(B, g, model, check, stream); break; \
+    case 16: FN<LAYOUT, 16>(B, g, model, check, stream); break; \
     default: return hipErrorInvalidValue;         \
   }
 
@@ -1782,7 +1807,7 @@ hipError_t launch_sweep(const BatchDev& B, const Group& g, uint32_t layout, uint
 }
 
 hipError_t launch_energy(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,
-                         uint32_t model, hipStream_t stream) {
+                         uint32_t model, bool check, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
   if (layout == 2) {
     PA_L_SWITCH(launch_energy_l, 2)

@@ -135,6 +135,15 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
     for (uint32_t q = 0; q < p; ++q)
       if (pops[q] == in) return PA_EINVAL;
   }
+  // every instance of the set counts one call (fault injection); one that
+  // fails fails the whole call before anything is queued
+  for (uint32_t p = 0; p < n; ++p) {
+    const int rc = pa_host::count_call(pops[p]);
+    if (rc != PA_OK) {
+      if (status) status[p] = rc;
+      return rc;
+    }
+  }
   const StepperLayout& l = s->lay;
   uint8_t* const img = s->h_img;
   uint8_t* const w = s->ws;
@@ -235,6 +244,13 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
     const pa::StepRecord& r = s->h_rec[p];
     pa_obs* o = obs ? obs + p : nullptr;
     if (o) std::memset(o, 0, sizeof(*o));
+    if (r.status == 2) {
+      // the sweep kernel found its LDS layout unusable and wrote nothing
+      if (status) status[p] = PA_EDEVICE;
+      in->failed = true;
+      s->failed = true;
+      continue;
+    }
     if (r.status != 0) {
       // the copy step would overflow the capacity: nothing after the scan ran
       // for this instance, so its population is as it was; clear its flags
@@ -277,9 +293,10 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
       o->n_at_E_min = r.n_at_E_min;
       o->step = in->step;
       o->sweeps_done = in->sweeps;
+      o->sum_lnQ = in->sum_lnQ;
     }
   }
-  return PA_OK;
+  return s->failed ? PA_EDEVICE : PA_OK;
 }
 
 }  // extern "C"

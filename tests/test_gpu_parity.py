@@ -337,12 +337,25 @@ def test_full_size_l8_r100k_int8_linear(pam):
                         pa_inputs.coupling_seed(2, 0), adaptive=False)
 
 
+@pytest.mark.parametrize("split", [4, 8])
 @pytest.mark.parametrize("layout", ["int8", "bitpack64"])
 @pytest.mark.parametrize("L,R", [(12, 130), (14, 100), (16, 70)])
-def test_sweep_parity_large_lattices(pam, layout, L, R):
-    """The largest lattices (8 waves per tile, lower occupancy): sweeps, a
-    resampling step and more sweeps, each with a ragged last tile."""
-    say("large lattice", layout, L, R)
+def test_sweep_parity_large_lattices(pam, layout, L, R, split):
+    """The largest lattices (lower occupancy): sweeps, a resampling step and
+    more sweeps, each with a ragged last tile, in both sweep forms (4 and 8
+    waves per tile, pinned for every size class these populations pass through;
+    each form has its own plane-group size at L = 14)."""
+    say("large lattice", layout, L, R, split)
+    pam.pa_autotune_reset()
+    try:
+        for tiles in (1, 2, 4, 8):
+            pam.pa_autotune_set(L, 64 * tiles, split, layout=layout)
+        _large_lattice_steps(pam, layout, L, R)
+    finally:
+        pam.pa_autotune_reset()
+
+
+def _large_lattice_steps(pam, layout, L, R):
     J, g, o = pair(pam, L, R, 700 + L, layout, 60 + L)
     g.sweep(0.5, 2)
     o.sweep(0.5, 2)
