@@ -45,14 +45,16 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic work of one spin-flip attempt, in gfx950 VALU lane-instructions
 # (the unit of the peak above: one instruction per lane, whatever its number
-# of inputs):
+# of inputs).  This count is fixed: it is the work of the bit-sliced algorithm
+# below, and kernel changes that execute fewer instructions per attempt show as
+# a higher fraction, never as a smaller count.
 #   random number: a quarter of one Philox4x32-10 call, 10 rounds x (2
 #   widening multiply-adds v_mad_u64_u32 + 2 three-input XORs v_bitop3) / 4 = 10;
 #   +-J Metropolis test, bit-sliced: per site and 64 replicas, 6 J masks, 12
 #   XORs (neighbour ^ own ^ J, two 32-replica halves), 16 adder instructions
-#   (the bit planes of nu) and 68 to spread the planes into one byte per
-#   replica (per half, 2 plane rotations, then 8 words x 3 masked merges and
-#   1 rotation) = 102, i.e. 102/64 per attempt; per replica, the byte is the
+#   (the bit planes of nu) and 68 to spread them into one byte per replica
+#   (per half, 2 plane rotations, then 8 words x 3 masked merges and 1
+#   rotation) = 102, i.e. 102/64 per attempt; per replica, the byte is the
 #   threshold's address, then 1 compare (64-bit) and 1 select of the flip
 #   mask's half = 2.
 OPS_PER_ATTEMPT = 10 + 2 + 102 / 64
@@ -68,21 +70,13 @@ OPS_PER_ATTEMPT_GAUSS = 10 + 19
 # energy and family label read, energy and family label written).
 BYTES_PER_REPLICA_FIXED = 20
 
-# HBM traffic of the sweep kernel measured with rocprofv3 PMC counters on this
-# workload (FETCH_SIZE scaled by 1/2 and WRITE_SIZE by 1, the factors a plain
-# copy of known size reads), per launch, with the source it was taken on.
-# Reported only while the kernel source is unchanged.
-TRAFFIC = {
-    "kernel_src_sha256": "6602fe1829a2f7fa7e80f1ef85134f03aeec7154ddf76abc5d1fa7c9b622cce7",
-    # 32767.4 KiB FETCH_SIZE x 2 + 64942.3 KiB WRITE_SIZE x 1, per k_sweep dispatch
-    # (eight waves per tile, the built-in form at this size)
-    "bytes_per_launch": (32767.4 * 2 + 64942.3) * 1024,
-    # the same for the Gaussian-coupling sweep: 32885.8 x 2 + 64951.6 KiB
-    "gauss16_bytes_per_launch": (32885.8 * 2 + 64951.6) * 1024,
-    # k_link_overlap at L=10, 5e5 pairs: 61562.6 x 2 + 10484.4 KiB
-    "link_overlap_bytes_per_launch": (61562.6 * 2 + 10484.4) * 1024,
-    "profile": "profiles/k_sweep_L10_R500k_bitpack64_hbm_counters.md",
-}
+# Counters of the sweep kernel from rocprofv3 on this workload, per launch,
+# with the kernel source they were taken on (reported only while that source
+# is unchanged): HBM bytes = FETCH_SIZE x 2 + WRITE_SIZE x 1 (the factors a
+# plain copy of known size reads, --copy-calibration), and the executed VALU
+# lane-instructions per attempt = SQ_INSTS_VALU x 64 / attempts per launch.
+# None: no counters for the current source yet.
+PROFILE = None
 
 
 def parse():
@@ -107,6 +101,8 @@ def parse():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--gauss-steps", type=int, default=300,
                     help="timed steps of the Gaussian-coupling anneal (0 skips it)")
+    ap.add_argument("--no-int8", action="store_true", help="skip the int8-layout C1/C2 runs")
+    ap.add_argument("--oracle-one-thread", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (used to "
                          "scale the HBM byte counters of a profiler run)")
@@ -139,18 +135,19 @@ def event_pairs(n):
     return pairs
 
 
-def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None, anneals=None,
-              event_pool=None):
-    """n_steps temperature steps; a new population at beta = 0 whenever beta_max is hit.
-    sweep_events (list, optional) receives (start, end, R~) per sweep launch, the
-    events taken in order from event_pool (made by event_pairs) when given;
-    anneals (list, optional) receives the step count of every anneal completed."""
-    import torch
-
+def run_steps(pam, J, w, n_steps, seed0, sweeps=None, stats=None, anneals=None):
+    """n_steps temperature steps, each one pa_anneal_step call (step choice,
+    resample, sweeps, observables, one synchronisation); a new population at
+    beta = 0 whenever beta_max is hit.  sweeps (list, optional) receives
+    (sweep launch ms, R~) per step: the library brackets each sweep launch with
+    HIP events on the population's stream (PA_FLAG_TIME_SWEEPS); anneals (list,
+    optional) receives the step count of every anneal completed."""
     attempts = 0
     pop = None
     gen = 0
     in_anneal = 0
+    flags = pam.PA_FLAG_TIME_SWEEPS if sweeps is not None else 0
+    N = w["L"] ** 3
     for _ in range(n_steps):
         if pop is None or pop_beta >= w["beta_max"]:
             if pop is not None:
@@ -158,35 +155,65 @@ def run_steps(pam, J, w, n_steps, seed0, sweep_events=None, stats=None, anneals=
                 if anneals is not None:
                     anneals.append(in_anneal)
             pop = pam.Population(w["L"], w["R"], J, seed0 + gen, layout=w["layout"],
-                                 model=w["model"])
+                                 model=w["model"], flags=flags)
             pop_beta = 0.0
             in_anneal = 0
             gen += 1
-        b = pop.choose_beta(w["eps"], w["beta_max"])
-        st = pop.resample(b)
-        if sweep_events is not None:
-            if event_pool is not None:
-                e0, e1 = event_pool[len(sweep_events)]
-            else:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(pop.stream)
-            pop.sweep(b, w["n_sweeps"])
-            e1.record(pop.stream)
-            sweep_events.append((e0, e1, st["R_tilde"]))
-        else:
-            pop.sweep(b, w["n_sweeps"])
-        obs = pop.observables()
-        attempts += w["n_sweeps"] * w["L"] ** 3 * st["R_tilde"]
+        b, obs = pop.anneal_step(w["eps"], w["beta_max"], w["n_sweeps"])
+        attempts += w["n_sweeps"] * N * obs["R_tilde"]
+        if sweeps is not None:
+            sweeps.append((obs["sweep_ms"], obs["R_tilde"]))
         pop_beta = b
         in_anneal += 1
         if stats is not None:
-            stats.append((b, st["R_tilde"], obs["rho_t"], obs["beta_F"]))
+            stats.append((b, obs["R_tilde"], obs["rho_t"], obs["beta_F"]))
     if pop is not None:
         pop.close()
         if anneals is not None and pop_beta >= w["beta_max"]:
             anneals.append(in_anneal)
     return attempts
+
+
+def whole_anneal(pam, J, w, seed):
+    """One complete anneal from a new population at beta = 0 to beta_max, timed
+    from creation (initialisation included) to the last step's observables."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pop = pam.Population(w["L"], w["R"], J, seed, layout=w["layout"], model=w["model"])
+    b, steps, attempts = 0.0, 0, 0
+    while b < w["beta_max"]:
+        b, obs = pop.anneal_step(w["eps"], w["beta_max"], w["n_sweeps"])
+        attempts += w["n_sweeps"] * w["L"] ** 3 * obs["R_tilde"]
+        steps += 1
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out = {"steps": steps, "seconds": round(t, 4), "attempts": attempts,
+           "attempts_per_s": attempts / t, "beta_F": obs["beta_F"], "rho_t": obs["rho_t"],
+           "E_min": obs["E_min"]}
+    pop.close()
+    return out
+
+
+def copy_rate_GBs(nbytes: int = 1 << 30, repeats: int = 5) -> float:
+    """Sustained device-to-device copy rate (read + write bytes per second) of a
+    plain torch copy of nbytes, timed with HIP events: the measured HBM ceiling."""
+    import torch
+
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = []
+    for e0, e1 in event_pairs(repeats):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (min(ms) * 1e-3) / 1e9
 
 
 BATCH = dict(name="256_instances_L4-10_R2e4-1e5_2pops_NT101_NS10", n_instances=256, Ls=(4, 6, 8, 10),
@@ -344,18 +371,115 @@ def serving_bench(duration_s: float, max_active: int | None = None, rate: float 
     }
 
 
-def sweep_roofline(w, events, ops_per_attempt):
-    """Average sweep launch of a timed run against the VALU peak."""
-    sweep_ms = [e0.elapsed_time(e1) for e0, e1, _ in events]
-    sweep_att = sum(w["n_sweeps"] * w["L"] ** 3 * r for _, _, r in events)
+def sweep_roofline(w, sweeps, ops_per_attempt, layout_bytes_per_site):
+    """Average sweep launch of a timed run against the VALU peak.
+    sweeps: (ms, R~) per launch; layout_bytes_per_site: spin bytes per site and
+    replica in HBM (1/8 bit-packed, 1 int8)."""
+    sweep_ms = [ms for ms, _ in sweeps]
+    sweep_att = sum(w["n_sweeps"] * w["L"] ** 3 * r for _, r in sweeps)
     n_launch = len(sweep_ms)
     avg_ms = sum(sweep_ms) / n_launch
     avg_att = sweep_att / n_launch
     achieved_ops = ops_per_attempt * avg_att / (avg_ms * 1e-3)
     avg_R = avg_att / (w["n_sweeps"] * w["L"] ** 3)
-    bytes_per_launch = 2 * avg_R * w["L"] ** 3 / 8 + BYTES_PER_REPLICA_FIXED * avg_R
+    bytes_per_launch = (2 * avg_R * w["L"] ** 3 * layout_bytes_per_site
+                        + BYTES_PER_REPLICA_FIXED * avg_R)
     return dict(sweep_ms=sweep_ms, avg_ms=avg_ms, avg_att=avg_att, n_launch=n_launch,
                 achieved_ops=achieved_ops, bytes_per_launch=bytes_per_launch)
+
+
+C1 = dict(name="C1_L4_R1000_int8_linear_NT51_NS10", L=4, R=1000, n_temps=51, beta_max=5.0,
+          n_sweeps=10, layout="int8", config=1)
+C2 = dict(name="C2_L8_R1e5_int8_2pops_linear_NT201_NS10_q65", L=8, R=100000, n_temps=201,
+          beta_max=5.0, n_sweeps=10, layout="int8", config=2)
+
+
+def linear_run(pam, c, pops_n, with_q):
+    """A whole linear-schedule run of the config: pops_n populations of one
+    sample stepped in lockstep (one pa_anneal_step each per temperature), the
+    overlap histogram of the first two after every step when with_q.  Timed
+    from the creation of the populations to the last result."""
+    import numpy as np
+    import torch
+
+    import pa_inputs
+
+    J = pa_inputs.couplings_pm(c["L"], pa_inputs.coupling_seed(c["config"], 0))
+    seeds = [pa_inputs.population_seed(c["config"], 0, p) for p in range(pops_n)]
+    betas = pam.linear_schedule(c["beta_max"], c["n_temps"])
+    N = c["L"] ** 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pops = [pam.Population(c["L"], c["R"], J, s, layout=c["layout"],
+                           flags=pam.PA_FLAG_TIME_SWEEPS) for s in seeds]
+    attempts, sweep_ms, sweep_att, q_ms, last = 0, [], 0, [], None
+    for k in range(1, len(betas)):
+        for p in pops:
+            o = p.step_to(betas[k], c["n_sweeps"])
+            attempts += c["n_sweeps"] * N * o["R_tilde"]
+            sweep_ms.append(o["sweep_ms"])
+            sweep_att += c["n_sweeps"] * N * o["R_tilde"]
+            last = o
+        if with_q:
+            t1 = time.perf_counter()
+            q = pam.overlap_hist(pops[0], pops[1])
+            q_ms.append(1e3 * (time.perf_counter() - t1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avg_ms = sum(sweep_ms) / len(sweep_ms)
+    avg_att = sweep_att / len(sweep_ms)
+    avg_R = avg_att / (c["n_sweeps"] * N)
+    ops = OPS_PER_ATTEMPT * avg_att / (avg_ms * 1e-3)
+    bytes_launch = 2 * avg_R * N + BYTES_PER_REPLICA_FIXED * avg_R
+    out = {"workload": c["name"], "populations": pops_n, "steps": len(betas) - 1,
+           "attempts": attempts, "seconds": round(wall, 4), "value": attempts / wall,
+           "unit": "attempts/s",
+           "sweep": {"kernel": f"k_sweep<int8, L={c['L']}, +-J>", "avg_launch_ms": avg_ms,
+                     "launches": len(sweep_ms), "attempts_per_launch": avg_att,
+                     "sweep_attempts_per_s": avg_att / (avg_ms * 1e-3),
+                     "bound": "alu", "achieved": ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": ops / VALU_PEAK_OPS,
+                     "ops_per_attempt": OPS_PER_ATTEMPT,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "hbm_algorithmic_GBs": bytes_launch / (avg_ms * 1e-3) / 1e9,
+                     "bytes_per_attempt": bytes_launch / avg_att},
+           "beta_F": [p.observables()["beta_F"] for p in pops], "rho_t": last["rho_t"]}
+    if with_q:
+        pairs = min(p.observables()["R_tilde"] for p in pops[:2])
+        out["overlap"] = {"kernel": "k_overlap<int8> (+ clear, copy of 65 counts, sync)",
+                          "avg_call_ms": sum(q_ms) / len(q_ms), "calls": len(q_ms),
+                          "pairs": pairs, "algorithmic_bytes": 2 * pairs * N,
+                          "hbm_GBs": 2 * pairs * N / (sum(q_ms) / len(q_ms) * 1e-3) / 1e9,
+                          "q_bins_nonzero": int(np.count_nonzero(q))}
+    for p in pops:
+        p.close()
+    return out
+
+
+def int8_cpu_baseline(c, pops_n, with_q, n_steps):
+    """The oracle on the first n_steps of the int8 config (all of C1)."""
+    import oracle
+    import pa_inputs
+
+    oracle.build(force=False)
+    J = pa_inputs.couplings_pm(c["L"], pa_inputs.coupling_seed(c["config"], 0))
+    betas = oracle.linear_schedule(c["beta_max"], c["n_temps"])
+    t0 = time.perf_counter()
+    pops = [oracle.Population(c["L"], J, c["R"], pa_inputs.population_seed(c["config"], 0, p))
+            for p in range(pops_n)]
+    att = 0
+    for k in range(1, n_steps + 1):
+        for p in pops:
+            p.resample(betas[k])
+            p.sweep(betas[k], c["n_sweeps"])
+            p.observables()
+            att += c["n_sweeps"] * c["L"] ** 3 * p.R_tilde
+        if with_q:
+            oracle.overlap_hist(pops[0].N, pops[0].spins, pops[1].spins)
+    t = time.perf_counter() - t0
+    return {"value": att / t, "unit": "attempts/s", "cores": omp_threads(), "kind": "oracle",
+            "sample": f"the first {n_steps} of {len(betas) - 1} steps" if n_steps < len(betas) - 1
+                      else "the whole run", "seconds": round(t, 2)}
 
 
 def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
@@ -373,19 +497,18 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
         tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=5)
         tp.close()
     run_steps(pam, K, w, warmup, seed0 + 1000)
-    events, stats, anneals = [], [], []
-    pool = event_pairs(steps)
+    sweeps, stats, anneals = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    attempts = run_steps(pam, K, w, steps, seed0, events, stats, anneals, pool)
+    attempts = run_steps(pam, K, w, steps, seed0, sweeps, stats, anneals)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    r = sweep_roofline(w, events, OPS_PER_ATTEMPT_GAUSS)
+    r = sweep_roofline(w, sweeps, OPS_PER_ATTEMPT_GAUSS, 1 / 8)
     link = link_overlap_bench(pam, K, w)
     traffic = None
-    if TRAFFIC is not None and TRAFFIC["kernel_src_sha256"] == kernel_src_sha256():
-        traffic = TRAFFIC["gauss16_bytes_per_launch"]
-        link["traffic"] = TRAFFIC["link_overlap_bytes_per_launch"]
+    if PROFILE is not None and PROFILE["kernel_src_sha256"] == kernel_src_sha256():
+        traffic = PROFILE["gauss16_bytes_per_launch"]
+        link["traffic"] = PROFILE["link_overlap_bytes_per_launch"]
     return {
         "workload": w["name"], "couplings": "Gaussian N(0,1) rounded to 1/16, k in [-127, 127]",
         "value": attempts / wall, "unit": "attempts/s", "steps": steps, "warmup": warmup,
@@ -465,8 +588,7 @@ def gauss_cpu_baseline(w, R_sample=100000, n_steps=3):
         p.observables()
         att += w["n_sweeps"] * w["L"] ** 3 * p.R_tilde
     t1 = time.perf_counter()
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": att / (t1 - t0), "unit": "attempts/s", "cores": threads, "kind": "oracle",
+    return {"value": att / (t1 - t0), "unit": "attempts/s", "cores": omp_threads(), "kind": "oracle",
             "sample": f"the first {n_steps} temperature steps (init, then step choice + resample + "
                       f"{w['n_sweeps']} sweeps each) of the Gaussian workload at R={R_sample}",
             "seconds": round(t1 - t0, 2)}
@@ -480,9 +602,27 @@ def kernel_src_sha256():
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def omp_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, n_steps=3):
     """The oracle on the first n_steps temperature steps of the same workload
-    (initialisation included)."""
+    (initialisation included), on all host threads; and on one thread (a child
+    process with OMP_NUM_THREADS=1) over the first step at a fifth of R."""
+    import subprocess
+
     import oracle
     import pa_inputs
 
@@ -500,16 +640,45 @@ def cpu_baseline(w, n_steps=3):
         p.observables()
         att += w["n_sweeps"] * w["L"] ** 3 * p.R_tilde
     t2 = time.perf_counter()
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": att / (t2 - t0), "unit": "attempts/s", "cores": threads, "kind": "oracle",
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-one-thread"],
+                         env=env, capture_output=True, text=True, check=True)
+    return {"value": att / (t2 - t0), "unit": "attempts/s", "cores": omp_threads(),
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"the first {n_steps} temperature steps (init, then step choice + resample + "
                       f"{w['n_sweeps']} sweeps each, {att:.3g} attempts) of the same workload; "
                       f"sweeps alone {att / t_sweep:.3g} attempts/s",
-            "seconds": round(t2 - t0, 2)}
+            "seconds": round(t2 - t0, 2),
+            "one_thread": json.loads(one.stdout.strip().splitlines()[-1])}
+
+
+def oracle_one_thread(w=None, R_sample=100000):
+    """Run in a child with OMP_NUM_THREADS=1: the oracle on the first step of
+    the workload at R_sample replicas (same L, couplings and culling)."""
+    import oracle
+    import pa_inputs
+
+    w = w or WORKLOAD
+    oracle.build(force=False)
+    J = pa_inputs.couplings_pm(w["L"], pa_inputs.coupling_seed(3, 0))
+    t0 = time.perf_counter()
+    p = oracle.Population(w["L"], J, R_sample, pa_inputs.population_seed(3, 0, 0))
+    b = p.choose_beta(w["eps"], w["beta_max"])
+    p.resample(b)
+    p.sweep(b, w["n_sweeps"])
+    p.observables()
+    t = time.perf_counter() - t0
+    att = w["n_sweeps"] * w["L"] ** 3 * p.R_tilde
+    print(json.dumps({"value": att / t, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+                      "sample": f"the first temperature step at R={R_sample} ({att:.3g} attempts)",
+                      "seconds": round(t, 2)}), flush=True)
 
 
 def main():
     args = parse()
+    if args.oracle_one_thread:
+        oracle_one_thread()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
               "multi-GPU path; value is one GPU's throughput.", file=sys.stderr)
@@ -542,24 +711,26 @@ def main():
         tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=5)
         tp.close()
     run_steps(pam, J, w, args.warmup, seed0 + 1000)
-    # this device's measured ceilings: sustained VALU issue and Philox draws alone
+    # this device's measured ceilings: sustained VALU issue, Philox draws alone,
+    # and the plain copy rate of HBM
     ceil = pam.pa_probe_ceilings()
+    copy_GBs = copy_rate_GBs()
     torch.cuda.synchronize()
     print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
-    events, stats, anneals = [], [], []
-    pool = event_pairs(args.steps)
+    sweeps, stats, anneals = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    attempts = run_steps(pam, J, w, args.steps, seed0, events, stats, anneals, pool)
+    attempts = run_steps(pam, J, w, args.steps, seed0, sweeps, stats, anneals)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    r = sweep_roofline(w, events, OPS_PER_ATTEMPT)
+    r = sweep_roofline(w, sweeps, OPS_PER_ATTEMPT, 1 / 8)
     sweep_ms, avg_ms, avg_att, n_launch = r["sweep_ms"], r["avg_ms"], r["avg_att"], r["n_launch"]
     achieved_ops, bytes_per_launch = r["achieved_ops"], r["bytes_per_launch"]
-    traffic = None
-    if TRAFFIC is not None and TRAFFIC["kernel_src_sha256"] == kernel_src_sha256():
-        traffic = TRAFFIC["bytes_per_launch"]
+    profiled = PROFILE is not None and PROFILE["kernel_src_sha256"] == kernel_src_sha256()
+    traffic = PROFILE["bytes_per_launch"] if profiled else None
+    sweep_rate = avg_att / (avg_ms * 1e-3)
+    hbm_GBs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     line = {
         "metric": "spin-flip attempts/s",
         "value": attempts / wall,
@@ -591,9 +762,18 @@ def main():
             "avg_launch_ms": avg_ms,
             "launches": n_launch,
             "attempts_per_launch": avg_att,
-            "sweep_attempts_per_s": avg_att / (avg_ms * 1e-3),
-            "hbm_algorithmic_GBs": bytes_per_launch / (avg_ms * 1e-3) / 1e9,
-            "hbm_frac": bytes_per_launch / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "sweep_attempts_per_s": sweep_rate,
+            # the kernel against the rate of its random numbers alone: Philox
+            # draws with nothing else computed, measured on this device
+            "philox_only_attempts_per_s": ceil["philox_draws_per_s"],
+            "frac_of_philox_only": sweep_rate / ceil["philox_draws_per_s"],
+            # executed VALU lane-instructions per attempt (rocprofv3 SQ_INSTS_VALU
+            # per launch x 64 / attempts), for the source the counters were taken on
+            "executed_valu_per_attempt": PROFILE["valu_per_attempt"] if profiled else None,
+            "hbm_algorithmic_GBs": hbm_GBs,
+            "hbm_frac": hbm_GBs / HBM_PEAK_GBS,
+            "copy_GBs_measured": copy_GBs,
+            "hbm_frac_of_copy": hbm_GBs / copy_GBs,
             # measured on this device just before the timed steps: the issue rate
             # of two-source operations (v_add_u32; XOR and v_bitop3 run as fast)
             # and of three-source ones (v_bfe_u32; extracts, v_add3, 24-bit mads)
@@ -601,18 +781,22 @@ def main():
             "measured_valu3_peak": ceil["valu3_lane_ops_per_s"] / 1e12,
             "frac_of_measured_valu_peak": achieved_ops / ceil["valu_lane_ops_per_s"],
             "frac_of_measured_valu3_peak": achieved_ops / ceil["valu3_lane_ops_per_s"],
-            "philox_only_attempts_per_s": ceil["philox_draws_per_s"],
-            "sweep_vs_philox_only": (avg_att / (avg_ms * 1e-3)) / ceil["philox_draws_per_s"],
         },
         "sweep_fraction_of_wall": sum(sweep_ms) * 1e-3 / wall,
+        "outside_sweep_us_per_step": 1e6 * (wall - sum(sweep_ms) * 1e-3) / args.steps,
         "autotune": tune,
         "anneals_completed": len(anneals),
         "steps_per_anneal": anneals,
         "beta_at_end": stats[-1][0] if stats else None,
     }
+    print("# one whole anneal", file=sys.stderr, flush=True)
+    line["whole_anneal"] = whole_anneal(pam, J, w, seed0 + 2000)
     if args.gauss_steps > 0:
         print(f"# Gaussian couplings: {args.gauss_steps} steps", file=sys.stderr, flush=True)
         line["gauss16"] = gauss_bench(pam, args.gauss_steps, args.warmup, not args.no_autotune)
+    if not args.no_int8:
+        print("# int8 layout: C1 and C2 whole runs", file=sys.stderr, flush=True)
+        line["int8"] = {"C1": linear_run(pam, C1, 1, False), "C2": linear_run(pam, C2, 2, True)}
     if not args.no_batched:
         print("# batched: 256 instances, one graph per step; back-to-back sample", file=sys.stderr,
               flush=True)
@@ -622,10 +806,13 @@ def main():
               flush=True)
         line["serving"] = serving_bench(args.serve_seconds, args.serve_max_active or None)
     if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle, one step)", file=sys.stderr, flush=True)
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)
         if "gauss16" in line:
             line["gauss16"]["cpu_baseline"] = gauss_cpu_baseline(GAUSS_WORKLOAD)
+        if "int8" in line:
+            line["int8"]["C1"]["cpu_baseline"] = int8_cpu_baseline(C1, 1, False, C1["n_temps"] - 1)
+            line["int8"]["C2"]["cpu_baseline"] = int8_cpu_baseline(C2, 2, True, 2)
     print(json.dumps(line), flush=True)
 
 

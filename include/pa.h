@@ -71,7 +71,9 @@ enum {
                                 couplings (the Sec. II.A Hamiltonian) and compare it with the
                                 stored word; any difference is PA_ECHECK.  Costs one extra
                                 kernel and one synchronisation per checked call. */
-  PA_FLAG_FAULT_HOOK = 2u    /* allow pa_debug_inject on this instance */
+  PA_FLAG_FAULT_HOOK = 2u,   /* allow pa_debug_inject on this instance */
+  PA_FLAG_TIME_SWEEPS = 4u   /* bracket every sweep launch with HIP events on the instance's
+                                stream; pa_obs.sweep_ms reports the last one's duration */
 };
 
 enum {
@@ -123,6 +125,8 @@ typedef struct {
                           sum_lnQ)); with the exported spins, family labels, R_tilde,
                           sweeps_done, step and beta it is the whole state a checkpoint
                           needs (pa_import_state) */
+  double sweep_ms;     /* PA_FLAG_TIME_SWEEPS: duration of the last sweep launch on the
+                          device (HIP events around it), ms; 0 otherwise */
 } pa_obs;
 
 /* Bytes of device workspace an instance with these parameters needs. 0 on bad params. */
@@ -155,6 +159,18 @@ int pa_sweep(pa_instance* in, double beta, uint32_t n_sweeps);
  * Synchronises.  step_out (nullable) receives beta, dbeta, lnQ, beta_F,
  * R_tilde (new), n_culled, eps_expected, step. */
 int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out);
+
+/* One whole temperature step of the anneal (Sec. II loop) with a single
+ * host synchronisation: with eps_target >= 0, the constant-culling step of
+ * pa_choose_beta (target eps_target, at most beta_max); with eps_target < 0,
+ * the caller's *beta_next (finite, >= 0; beta_max is ignored).  Then the
+ * resampling step to it (pa_resample), n_sweeps (>= 1) sweeps there (pa_sweep)
+ * and the observables (pa_observables) into out (nullable).  *beta_next
+ * receives the new inverse temperature.  Every bit equals that sequence of
+ * calls.  PA_ECAPACITY leaves the population as it was (nothing after the
+ * capacity check runs); PA_ESCHEDULE as pa_choose_beta. */
+int pa_anneal_step(pa_instance* in, double eps_target, double beta_max, uint32_t n_sweeps,
+                   double* beta_next, pa_obs* out);
 
 /* Constant-culling step (Sec. III.C): the beta_next in (beta, beta_max] whose
  * culling fraction eps = sum_{tau<1}(1 - tau) / R is eps_target, by 64

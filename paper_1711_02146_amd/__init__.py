@@ -29,6 +29,7 @@ PA_ECHECK = -7
 
 PA_FLAG_CHECK_ENERGY = 1
 PA_FLAG_FAULT_HOOK = 2
+PA_FLAG_TIME_SWEEPS = 4
 PA_INJECT_FAIL_AFTER = 1
 PA_INJECT_ENERGY = 2
 
@@ -55,7 +56,7 @@ class pa_obs(ctypes.Structure):
                 ("n_culled", ctypes.c_uint32), ("E_min", ctypes.c_int32), ("step", ctypes.c_uint32),
                 ("sum_eta2", ctypes.c_uint64), ("sweeps_done", ctypes.c_uint64),
                 ("n_at_E_min", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("sum_lnQ", ctypes.c_double)]
+                ("sum_lnQ", ctypes.c_double), ("sweep_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -130,6 +131,8 @@ def lib():
         "pa_make_couplings_pm": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, _vp]),
         "pa_probe_ceilings": (ctypes.c_int, [_vp, ctypes.c_size_t, _vp, _P(pa_ceilings)]),
         "pa_debug_inject": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32]),
+        "pa_anneal_step": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+                                          _P(ctypes.c_double), _P(pa_obs)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -146,7 +149,7 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
             "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset", "pa_probe_scratch_bytes",
             "pa_probe_ceilings", "pa_make_couplings_pm", "pa_autotune_set",
-            "pa_link_overlap_hist", "pa_debug_inject"]
+            "pa_link_overlap_hist", "pa_debug_inject", "pa_anneal_step"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -187,6 +190,16 @@ def pa_choose_beta(handle: int, eps_target: float, beta_max: float) -> float:
     _check(lib().pa_choose_beta(handle, float(eps_target), float(beta_max), ctypes.byref(b)),
            "pa_choose_beta")
     return b.value
+
+
+def pa_anneal_step(handle: int, eps_target: float, beta_max: float, n_sweeps: int,
+                   beta_next: float = 0.0):
+    """-> (beta reached, observables dict).  eps_target < 0: step to beta_next."""
+    b = ctypes.c_double(float(beta_next))
+    o = pa_obs()
+    _check(lib().pa_anneal_step(handle, float(eps_target), float(beta_max), int(n_sweeps),
+                                ctypes.byref(b), ctypes.byref(o)), "pa_anneal_step")
+    return b.value, o.as_dict()
 
 
 def pa_observables(handle: int) -> dict:
@@ -403,6 +416,15 @@ class Population:
 
     def observables(self) -> dict:
         return pa_observables(self.handle)
+
+    def anneal_step(self, eps_target: float, beta_max: float, n_sweeps: int):
+        """One constant-culling step (choose beta, resample, sweep, measure) with
+        one synchronisation -> (beta, observables)."""
+        return pa_anneal_step(self.handle, eps_target, beta_max, n_sweeps)
+
+    def step_to(self, beta_next: float, n_sweeps: int) -> dict:
+        """One step to the given beta (resample, sweep, measure) -> observables."""
+        return pa_anneal_step(self.handle, -1.0, 0.0, n_sweeps, beta_next)[1]
 
     def export_state(self, spins=True, U=True, family=True):
         return pa_export_state(self.handle, self.N, spins, U, family)

@@ -48,7 +48,8 @@ bool make_layout(const pa_params* p, Layout* out) {
   if (!p) return false;
   if (p->L < 4 || p->L > (uint32_t)pa::kMaxL || (p->L & 1u)) return false;
   if (p->R < 1) return false;
-  if ((p->flags & ~(uint32_t)(PA_FLAG_CHECK_ENERGY | PA_FLAG_FAULT_HOOK)) != 0 ||
+  if ((p->flags & ~(uint32_t)(PA_FLAG_CHECK_ENERGY | PA_FLAG_FAULT_HOOK | PA_FLAG_TIME_SWEEPS)) !=
+          0 ||
       (p->model != PA_MODEL_PM && p->model != PA_MODEL_GAUSS16))
     return false;
   uint32_t layout = p->layout == PA_LAYOUT_AUTO ? (uint32_t)PA_LAYOUT_BITPACK64 : p->layout;
@@ -268,8 +269,26 @@ pa::PopStep plain_step(uint32_t cur) {
 hipError_t launch_sweep_of(pa_instance* in, const pa::PopStep& ps) {
   const uint32_t split = pa::sweep_split_for(in->dev.model, in->dev.layout, in->dev.L,
                                              ((uint64_t)in->R_tilde + 63) / 64);
-  return pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
-                          in->dev.layout, in->dev.L, split, in->dev.model, in->stream);
+  const bool timed = in->sweep_ev[0] != nullptr;
+  hipError_t e = timed ? hipEventRecord(in->sweep_ev[0], in->stream) : hipSuccess;
+  if (e != hipSuccess) return e;
+  e = pa::launch_sweep(one_set(in, ps), group_of(in, in->d_meta->tiles, in->meta.tiles[1]),
+                       in->dev.layout, in->dev.L, split, in->dev.model, in->stream);
+  if (e != hipSuccess || !timed) return e;
+  in->sweep_timed = true;
+  return hipEventRecord(in->sweep_ev[1], in->stream);
+}
+
+// PA_FLAG_TIME_SWEEPS: the duration of the last timed sweep launch, once the
+// stream has passed it (call after a synchronisation).
+hipError_t read_sweep_time(pa_instance* in) {
+  if (!in->sweep_timed) return hipSuccess;
+  float ms = 0.0f;
+  const hipError_t e = hipEventElapsedTime(&ms, in->sweep_ev[0], in->sweep_ev[1]);
+  if (e != hipSuccess) return e;
+  in->last_sweep_ms = ms;
+  in->sweep_timed = false;
+  return hipSuccess;
 }
 
 // Energy levels of the histogram in in->h_hist: count, width and offset
@@ -341,6 +360,7 @@ int fetch_hist(pa_instance* in, bool with_family) {
   PA_HIP(in, hipMemcpyAsync(in->h_hist, P.hist, (size_t)n * 4, hipMemcpyDeviceToHost, in->stream));
   PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
+  PA_HIP(in, read_sweep_time(in));
   if (in->h_sc->err == 2) return dev_fail(in);
   in->R_tilde = in->h_sc->R_tilde;
   in->hist_valid = true;
@@ -421,6 +441,139 @@ void philox_host(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0
   out[1] = c1;
   out[2] = c2;
   out[3] = c3;
+}
+
+// The constant-culling step of Sec. III.C on the histogram in in->h_hist:
+// the beta_next in (beta, beta_max] whose culling fraction is eps_target, by
+// 64 bisection halvings keeping the lower end (pa_choose_beta).
+int choose_from_hist(pa_instance* in, double eps_target, double beta_max, double* beta_next) {
+  const Levels lv = levels_of(in);
+  const uint32_t nl = lv.n, R = in->dev.R;
+  const uint32_t* h = in->h_hist;
+  // The occupied levels once, as (exp argument, count) pairs in level order;
+  // each evaluation of the culling fraction below, eps R = sum over them
+  // with tau_j < 1 of h_j (1 - tau_j) (Sec. III.C), forms w_j, S and tau_j
+  // exactly as resample_table() does, without scanning empty levels.
+  static thread_local std::vector<double> arg, cnt;
+  arg.clear();
+  cnt.clear();
+  int jmin = -1;
+  for (uint32_t j = 0; j < nl; ++j) {
+    if (h[j] == 0) continue;
+    if (jmin < 0) jmin = (int)j;
+    arg.push_back(lv.unit * (double)((int)j - jmin));
+    cnt.push_back((double)h[j]);
+  }
+  const size_t n_occ = arg.size();
+  auto eps_of = [&](double dbeta) {
+    if (n_occ == 0) return 0.0;
+    static thread_local std::vector<double> w;
+    w.resize(n_occ);
+    double S = 0.0;
+    for (size_t i = 0; i < n_occ; ++i) {
+      w[i] = std::exp(-dbeta * arg[i]);
+      S = S + cnt[i] * w[i];
+    }
+    double acc = 0.0;
+    for (size_t i = 0; i < n_occ; ++i) {
+      const double tau = ((double)R * w[i]) / S;
+      if (tau < 1.0) acc = acc + cnt[i] * (1.0 - tau);
+    }
+    return acc / (double)R;
+  };
+  if (eps_of(0.0) > eps_target) return PA_ESCHEDULE;
+  const double rem = beta_max - in->beta;
+  if (eps_of(rem) <= eps_target) {
+    *beta_next = beta_max;
+    return PA_OK;
+  }
+  // 64 halvings of [0, rem], keeping the lower end (eps(lo) <= target)
+  double lo = 0.0, hi = rem;
+  for (int it = 0; it < 64; ++it) {
+    const double mid = lo + 0.5 * (hi - lo);
+    if (eps_of(mid) <= eps_target) lo = mid;
+    else hi = mid;
+  }
+  *beta_next = in->beta + lo;
+  return PA_OK;
+}
+
+// The resampling step beta -> beta_next from the histogram in in->h_hist
+// (Sec. II, Eqs. 1-2): the FP64 table on the host, its occupied range
+// uploaded, then copy counts, scan (with the capacity check) and the copy map
+// queued.  Nothing is synchronised.
+int queue_resample(pa_instance* in, double beta_next, Table* t) {
+  const DevPop& P = in->dev;
+  const double dbeta = beta_next - in->beta;
+  const Levels lv = levels_of(in);
+  *t = resample_table(in->h_hist, lv.n, lv.unit, lv.E_lo, P.R, in->R_tilde, dbeta, in->h_fl,
+                      in->h_T);
+  if (t->jmin < 0) return PA_ESTATE;  // empty population
+  // only the occupied range is read by the copy counts
+  const size_t j0 = (size_t)t->jmin, nj = (size_t)(t->jmax - t->jmin + 1);
+  PA_HIP(in, hipMemcpyAsync(P.table_fl + j0, in->h_fl + j0, nj * 4, hipMemcpyHostToDevice,
+                            in->stream));
+  PA_HIP(in, hipMemcpyAsync(P.table_T + j0, in->h_T + j0, nj * 8, hipMemcpyHostToDevice,
+                            in->stream));
+  pa::PopStep ps = plain_step(in->cur);
+  ps.step = in->step + 1;
+  const pa::BatchDev B = one_set(in, ps);
+  PA_HIP(in, pa::launch_counts(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
+  PA_HIP(in, pa::launch_scan(B, group_of(in, in->d_meta->perpop, 1), in->stream));
+  // k_scatter does nothing when the scan flagged an overflow
+  PA_HIP(in, pa::launch_scatter(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
+  return PA_OK;
+}
+
+// The host mirror after a resampling step that fitted (in->h_sc holds the
+// scan's results; R_old: the population size before the step).
+void commit_resample(pa_instance* in, const Table& t, double beta_next, uint32_t R_old) {
+  in->last_R_old = R_old;
+  in->R_tilde = in->h_sc->R_next;
+  in->last_n_culled = in->h_sc->n_culled;
+  in->last_dbeta = beta_next - in->beta;
+  in->last_lnQ = t.lnQ;
+  in->last_eps = t.eps;
+  in->sum_lnQ = in->sum_lnQ + t.lnQ;
+  in->beta = beta_next;
+  in->step += 1;
+  in->pending_gather = true;
+  in->hist_valid = false;
+}
+
+// Scalars of the current population from in->h_hist and in->h_sc (filled by
+// fetch_hist with the family sums).
+void fill_observables(pa_instance* in, pa_obs* out) {
+  const DevPop& P = in->dev;
+  const uint32_t* h = in->h_hist;
+  const bool gauss = P.model == pa::kModelGauss16;
+  const Levels lv = levels_of(in);
+  // sum of E in integer units: 2U - 3N, or E16 = E_lo + j
+  int64_t sumE = 0;
+  int jmin = -1;
+  for (uint32_t j = 0; j < lv.n; ++j) {
+    if (h[j] && jmin < 0) jmin = (int)j;
+    const int64_t e = gauss ? lv.E_lo + (int64_t)j : 2 * (int64_t)j - 3 * (int64_t)P.N;
+    sumE += (int64_t)h[j] * e;
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->beta = in->beta;
+  out->dbeta = in->last_dbeta;
+  out->lnQ = in->last_lnQ;
+  out->beta_F = -((double)P.N * std::log(2.0) + in->sum_lnQ);
+  out->mean_E = in->R_tilde ? (double)sumE / (double)in->R_tilde : 0.0;
+  if (gauss) out->mean_E = out->mean_E * (1.0 / 16.0);  // E16 -> E
+  out->sum_eta2 = in->h_sc->sum_eta2;
+  out->rho_t = (double)out->sum_eta2 / (double)P.R;
+  out->eps_expected = in->last_eps;
+  out->R_tilde = in->R_tilde;
+  out->n_culled = in->last_n_culled;
+  out->E_min = jmin < 0 ? 0 : gauss ? (int32_t)(lv.E_lo + jmin) : 2 * jmin - 3 * (int)P.N;
+  out->n_at_E_min = jmin >= 0 ? h[jmin] : 0u;
+  out->step = in->step;
+  out->sweeps_done = in->sweeps;
+  out->sum_lnQ = in->sum_lnQ;
+  out->sweep_ms = in->last_sweep_ms;
 }
 
 }  // namespace
@@ -576,6 +729,10 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
       pa::launch_energy(one_set(in, plain_step(0)), group_of(in, in->d_meta->etiles, mt.etiles[1]),
                         l.layout, l.L, l.model, false, in->stream) != hipSuccess)
     return fail(PA_EDEVICE);
+  if ((p->flags & PA_FLAG_TIME_SWEEPS) &&
+      (hipEventCreate(&in->sweep_ev[0]) != hipSuccess ||
+       hipEventCreate(&in->sweep_ev[1]) != hipSuccess))
+    return fail(PA_EDEVICE);
   in->cur = 0;
   in->R_tilde = l.R;
   *out = in;
@@ -594,6 +751,8 @@ int pa_free(pa_instance* in) {
   if (in->h_meta) (void)hipHostFree(in->h_meta);
   if (in->h_gthr) (void)hipHostFree(in->h_gthr);
   if (in->gthr_copied) (void)hipEventDestroy(in->gthr_copied);
+  for (hipEvent_t e : in->sweep_ev)
+    if (e) (void)hipEventDestroy(e);
   delete in;
   return PA_OK;
 }
@@ -648,56 +807,94 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
     rc = fetch_hist(in, false);
     if (rc) return rc;
   }
-  const DevPop& P = in->dev;
-  const double dbeta = beta_next - in->beta;
-  const Levels lv = levels_of(in);
-  const Table t = resample_table(in->h_hist, lv.n, lv.unit, lv.E_lo, P.R, in->R_tilde, dbeta,
-                                 in->h_fl, in->h_T);
-  if (t.jmin < 0) return PA_ESTATE;  // empty population
-  const double eps = t.eps;
-  // only the occupied range is read by the copy counts
-  const size_t j0 = (size_t)t.jmin, nj = (size_t)(t.jmax - t.jmin + 1);
-  PA_HIP(in, hipMemcpyAsync(P.table_fl + j0, in->h_fl + j0, nj * 4, hipMemcpyHostToDevice,
+  Table t;
+  rc = queue_resample(in, beta_next, &t);
+  if (rc) return rc;
+  PA_HIP(in, hipMemcpyAsync(in->h_sc, in->dev.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
                             in->stream));
-  PA_HIP(in, hipMemcpyAsync(P.table_T + j0, in->h_T + j0, nj * 8, hipMemcpyHostToDevice,
-                            in->stream));
-  pa::PopStep ps = plain_step(in->cur);
-  ps.step = in->step + 1;
-  const pa::BatchDev B = one_set(in, ps);
-  PA_HIP(in, pa::launch_counts(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
-  PA_HIP(in, pa::launch_scan(B, group_of(in, in->d_meta->perpop, 1), in->stream));
-  // the copy map is built before the host sees the capacity check: k_scatter
-  // does nothing when the scan flagged an overflow, and on success the host
-  // does not wait for a launch after its synchronisation
-  PA_HIP(in, pa::launch_scatter(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
-  PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
   if (in->h_sc->err == 2) return dev_fail(in);
   if (in->h_sc->err) return PA_ECAPACITY;  // population untouched
-  in->last_R_old = in->R_tilde;
-  in->R_tilde = in->h_sc->R_next;
-  in->last_n_culled = in->h_sc->n_culled;
-  in->last_dbeta = dbeta;
-  in->last_lnQ = t.lnQ;
-  in->last_eps = eps;
-  in->sum_lnQ = in->sum_lnQ + t.lnQ;
-  in->beta = beta_next;
-  in->step += 1;
-  in->pending_gather = true;
-  in->hist_valid = false;
+  commit_resample(in, t, beta_next, in->R_tilde);
   if (step_out) {
     std::memset(step_out, 0, sizeof(*step_out));
     step_out->beta = in->beta;
-    step_out->dbeta = dbeta;
+    step_out->dbeta = in->last_dbeta;
     step_out->lnQ = t.lnQ;
-    step_out->beta_F = -((double)P.N * std::log(2.0) + in->sum_lnQ);
-    step_out->eps_expected = eps;
+    step_out->beta_F = -((double)in->dev.N * std::log(2.0) + in->sum_lnQ);
+    step_out->eps_expected = in->last_eps;
     step_out->R_tilde = in->R_tilde;
     step_out->n_culled = in->last_n_culled;
     step_out->step = in->step;
     step_out->sweeps_done = in->sweeps;
     step_out->sum_lnQ = in->sum_lnQ;
   }
+  return PA_OK;
+}
+
+int pa_anneal_step(pa_instance* in, double eps_target, double beta_max, uint32_t n_sweeps,
+                   double* beta_next, pa_obs* out) {
+  if (int rc0 = enter(in)) return rc0;
+  if (!beta_next || n_sweeps == 0 || in->sweeps + n_sweeps > 0xFFFFFFFFull) return PA_EINVAL;
+  const bool adaptive = eps_target >= 0.0;
+  if (adaptive && (!std::isfinite(eps_target) || !std::isfinite(beta_max) ||
+                   !(beta_max > in->beta)))
+    return PA_EINVAL;
+  if (!adaptive && (!std::isfinite(*beta_next) || !(*beta_next >= 0.0))) return PA_EINVAL;
+  int rc = check_energy(in);
+  if (rc) return rc;
+  if (!in->hist_valid || in->pending_gather) {
+    rc = fetch_hist(in, false);
+    if (rc) return rc;
+  }
+  double b = *beta_next;
+  if (adaptive) {
+    rc = choose_from_hist(in, eps_target, beta_max, &b);
+    if (rc) return rc;
+  }
+  Table t;
+  rc = queue_resample(in, b, &t);
+  if (rc) return rc;
+  // the copy and the sweeps, queued behind the capacity check: on an
+  // overflow the scan has flagged it and the sweep kernel leaves at once
+  pa::PopStep ps = plain_step(in->cur);
+  PA_HIP(in, set_thresholds(in, b, &ps));
+  ps.t0 = (uint32_t)in->sweeps;
+  ps.n_sweeps = n_sweeps;
+  ps.gather = 1;
+  PA_HIP(in, launch_sweep_of(in, ps));
+  const uint32_t old_cur = in->cur, R_old = in->R_tilde;
+  if (in->dev.model == pa::kModelGauss16) {
+    // the energy window of the new population is found on the device and
+    // read first; an unwritten buffer has none, so the overflow check comes first
+    PA_HIP(in, hipMemcpyAsync(in->h_sc, in->dev.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
+                              in->stream));
+    PA_HIP(in, hipStreamSynchronize(in->stream));
+    if (in->h_sc->err == 2) return dev_fail(in);
+    if (in->h_sc->err) {
+      in->sweep_timed = false;
+      return PA_ECAPACITY;  // nothing after the scan ran: the population is as it was
+    }
+  }
+  in->cur ^= 1u;
+  // histogram and family sums of the new population: the one synchronisation
+  rc = fetch_hist(in, true);
+  if (rc) return rc;
+  if (in->h_sc->err) {  // nothing after the scan ran: the population is as it was
+    in->cur = old_cur;
+    in->R_tilde = R_old;
+    in->hist_valid = false;
+    return PA_ECAPACITY;
+  }
+  commit_resample(in, t, b, R_old);
+  in->R_tilde = in->h_sc->R_tilde;
+  in->pending_gather = false;
+  in->hist_valid = true;
+  in->sweeps += n_sweeps;
+  rc = check_energy(in);
+  if (rc) return rc;
+  *beta_next = b;
+  if (out) fill_observables(in, out);
   return PA_OK;
 }
 
@@ -711,55 +908,7 @@ int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* 
     int rc = fetch_hist(in, false);
     if (rc) return rc;
   }
-  const Levels lv = levels_of(in);
-  const uint32_t nl = lv.n, R = in->dev.R;
-  const uint32_t* h = in->h_hist;
-  // The occupied levels once, as (exp argument, count) pairs in level order;
-  // each evaluation of the culling fraction below, eps R = sum over them
-  // with tau_j < 1 of h_j (1 - tau_j) (Sec. III.C), forms w_j, S and tau_j
-  // exactly as resample_table() does, without scanning empty levels.
-  static thread_local std::vector<double> arg, cnt;
-  arg.clear();
-  cnt.clear();
-  int jmin = -1;
-  for (uint32_t j = 0; j < nl; ++j) {
-    if (h[j] == 0) continue;
-    if (jmin < 0) jmin = (int)j;
-    arg.push_back(lv.unit * (double)((int)j - jmin));
-    cnt.push_back((double)h[j]);
-  }
-  const size_t n_occ = arg.size();
-  auto eps_of = [&](double dbeta) {
-    if (n_occ == 0) return 0.0;
-    static thread_local std::vector<double> w;
-    w.resize(n_occ);
-    double S = 0.0;
-    for (size_t i = 0; i < n_occ; ++i) {
-      w[i] = std::exp(-dbeta * arg[i]);
-      S = S + cnt[i] * w[i];
-    }
-    double acc = 0.0;
-    for (size_t i = 0; i < n_occ; ++i) {
-      const double tau = ((double)R * w[i]) / S;
-      if (tau < 1.0) acc = acc + cnt[i] * (1.0 - tau);
-    }
-    return acc / (double)R;
-  };
-  if (eps_of(0.0) > eps_target) return PA_ESCHEDULE;
-  const double rem = beta_max - in->beta;
-  if (eps_of(rem) <= eps_target) {
-    *beta_next = beta_max;
-    return PA_OK;
-  }
-  // 64 halvings of [0, rem], keeping the lower end (eps(lo) <= target)
-  double lo = 0.0, hi = rem;
-  for (int it = 0; it < 64; ++it) {
-    const double mid = lo + 0.5 * (hi - lo);
-    if (eps_of(mid) <= eps_target) lo = mid;
-    else hi = mid;
-  }
-  *beta_next = in->beta + lo;
-  return PA_OK;
+  return choose_from_hist(in, eps_target, beta_max, beta_next);
 }
 
 int pa_observables(pa_instance* in, pa_obs* out) {
@@ -769,35 +918,7 @@ int pa_observables(pa_instance* in, pa_obs* out) {
   if (rc) return rc;
   rc = fetch_hist(in, true);
   if (rc) return rc;
-  const DevPop& P = in->dev;
-  const uint32_t* h = in->h_hist;
-  const bool gauss = P.model == pa::kModelGauss16;
-  const Levels lv = levels_of(in);
-  // sum of E in integer units: 2U - 3N, or E16 = E_lo + j
-  int64_t sumE = 0;
-  int jmin = -1;
-  for (uint32_t j = 0; j < lv.n; ++j) {
-    if (h[j] && jmin < 0) jmin = (int)j;
-    const int64_t e = gauss ? lv.E_lo + (int64_t)j : 2 * (int64_t)j - 3 * (int64_t)P.N;
-    sumE += (int64_t)h[j] * e;
-  }
-  std::memset(out, 0, sizeof(*out));
-  out->beta = in->beta;
-  out->dbeta = in->last_dbeta;
-  out->lnQ = in->last_lnQ;
-  out->beta_F = -((double)P.N * std::log(2.0) + in->sum_lnQ);
-  out->mean_E = in->R_tilde ? (double)sumE / (double)in->R_tilde : 0.0;
-  if (gauss) out->mean_E = out->mean_E * (1.0 / 16.0);  // E16 -> E
-  out->sum_eta2 = in->h_sc->sum_eta2;
-  out->rho_t = (double)out->sum_eta2 / (double)P.R;
-  out->eps_expected = in->last_eps;
-  out->R_tilde = in->R_tilde;
-  out->n_culled = in->last_n_culled;
-  out->E_min = jmin < 0 ? 0 : gauss ? (int32_t)(lv.E_lo + jmin) : 2 * jmin - 3 * (int)P.N;
-  out->n_at_E_min = jmin >= 0 ? h[jmin] : 0u;
-  out->step = in->step;
-  out->sweeps_done = in->sweeps;
-  out->sum_lnQ = in->sum_lnQ;
+  fill_observables(in, out);
   return PA_OK;
 }
 

@@ -257,6 +257,8 @@ struct TileCtx {
   MetPhilox ph;
   uint32_t t;
   bool any_draw;
+  unsigned long long writers;  // lanes 0 and 32: the lanes that apply a site's flips
+  uint32_t hshift;             // 8 hoff: shift of a ballot that brings this lane's half down
   // kModelGauss16
   const int8_t* rowk;                  // row couplings (see DevPop)
   uint32_t rowk_stride;
@@ -438,9 +440,9 @@ __device__ __forceinline__ void block_row(const TileCtx& c, const RowAddr& a, ui
   constexpr int S = I * H + Q;  // site index within the block
   SiteLoad wn;
   if constexpr (Q + 1 < H) wn = load_site_words<L, Q + 1>(a);
-  if constexpr (S % 4 == 0) {
-    if (c.any_draw) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
-  }
+  // a Philox call per group of four sites whether or not a draw can matter (a
+  // threshold of 0 or 2^32 decides without it): no branch in the unrolled rows
+  if constexpr (S % 4 == 0) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
   if constexpr (M == (int)kModelGauss16)
     site_update_g<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
   else
@@ -550,6 +552,16 @@ __device__ __forceinline__ uint32_t nu8_word(const NuPlanesRot& p) {
   return rotr32(t, (J - 3) & 31);
 }
 
+// The two-plane form of the same spread for the class c = min(nu, 3) of a
+// replica (c0 = p0 | p2, c1 = p1 | p2, c1 rotated left by 1 once per half):
+// word J, byte m holds 8 c of the replica at bit J + 8m, at bits 3 and 4.
+template <int J>
+__device__ __forceinline__ uint32_t cls8_word(uint32_t c0, uint32_t c1r) {
+  constexpr uint32_t m = 0x01010101u << J;
+  constexpr uint32_t m1 = (m << 1) | (m >> 31);
+  return rotr32((c0 & m) | (c1r & m1), (J - 3) & 31);
+}
+
 // byte of replica r (lane r) within a site's 64-byte entry
 __device__ __forceinline__ uint32_t plane_byte(uint32_t r) {
   return (r & 32u) + 4u * (r & 7u) + ((r >> 3) & 3u);
@@ -559,7 +571,15 @@ __device__ __forceinline__ uint32_t plane_byte(uint32_t r) {
 // of block bi = l / BS (BS = 4 L/2 sites per block of four rows; GB blocks
 // per group, rows rb0 + step bi .. + 3) and writes entry l of the wave's
 // plane area: 64 bytes, byte plane_byte(r) = 8 nu of replica r at that site.
-template <int L, int SPLIT>
+//
+// FAST (every move that raises the energy has a threshold below 2^32): the
+// replicas with nu >= 3, whose move does not raise the energy and is always
+// taken, are flipped here, in the site's word, and the byte holds 8 min(nu, 3).
+// Phase 2 then reads the low 32-bit word of the threshold table at that byte:
+// thr(nu) for nu <= 2, and 0 (never, the move is done) for nu >= 3.  Only this
+// wave writes the words of its own sites during the pass, and phase 2 does not
+// read them, so the early flip changes nothing but the order of the XORs.
+template <int L, int SPLIT, bool FAST>
 __device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* __restrict__ sites,
                                             uint32_t own0, uint32_t rb0, uint32_t step,
                                             uint32_t lane, uint32_t* planes) {
@@ -569,7 +589,7 @@ __device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* _
   if (bi < GB && rb < ROWS) {
     const uint32_t cm = own0 + H * rb + sb;
     const SiteEntry e = sites[cm];
-    const uint2* w = reinterpret_cast<const uint2*>(c.lds);
+    uint2* w = reinterpret_cast<uint2*>(c.lds);
     const uint2 o = w[cm];
     uint32_t lo[6], hi[6], jm[6];
 #pragma unroll
@@ -579,52 +599,108 @@ __device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* _
       hi[k] = v.y;
       jm[k] = (uint32_t)((int32_t)((uint32_t)e.jneg << (31 - k)) >> 31);
     }
-    const NuPlanesRot a = rot_planes(nu_planes(o.x, lo, jm));
-    const NuPlanesRot b = rot_planes(nu_planes(o.y, hi, jm));
+    const NuPlanes pa = nu_planes(o.x, lo, jm);
+    const NuPlanes pb = nu_planes(o.y, hi, jm);
     uint4* dst = reinterpret_cast<uint4*>(planes + 16 * lane);
-    dst[0] = make_uint4(nu8_word<0>(a), nu8_word<1>(a), nu8_word<2>(a), nu8_word<3>(a));
-    dst[1] = make_uint4(nu8_word<4>(a), nu8_word<5>(a), nu8_word<6>(a), nu8_word<7>(a));
-    dst[2] = make_uint4(nu8_word<0>(b), nu8_word<1>(b), nu8_word<2>(b), nu8_word<3>(b));
-    dst[3] = make_uint4(nu8_word<4>(b), nu8_word<5>(b), nu8_word<6>(b), nu8_word<7>(b));
+    if constexpr (FAST) {
+      // nu >= 3: p2 | (p1 & p0); flipped now
+      w[cm] = make_uint2(o.x ^ (pa.p2 | (pa.p1 & pa.p0)), o.y ^ (pb.p2 | (pb.p1 & pb.p0)));
+      const uint32_t a0 = pa.p0 | pa.p2, a1 = rotr32(pa.p1 | pa.p2, 31);
+      const uint32_t b0 = pb.p0 | pb.p2, b1 = rotr32(pb.p1 | pb.p2, 31);
+      dst[0] = make_uint4(cls8_word<0>(a0, a1), cls8_word<1>(a0, a1), cls8_word<2>(a0, a1),
+                          cls8_word<3>(a0, a1));
+      dst[1] = make_uint4(cls8_word<4>(a0, a1), cls8_word<5>(a0, a1), cls8_word<6>(a0, a1),
+                          cls8_word<7>(a0, a1));
+      dst[2] = make_uint4(cls8_word<0>(b0, b1), cls8_word<1>(b0, b1), cls8_word<2>(b0, b1),
+                          cls8_word<3>(b0, b1));
+      dst[3] = make_uint4(cls8_word<4>(b0, b1), cls8_word<5>(b0, b1), cls8_word<6>(b0, b1),
+                          cls8_word<7>(b0, b1));
+    } else {
+      const NuPlanesRot a = rot_planes(pa);
+      const NuPlanesRot b = rot_planes(pb);
+      dst[0] = make_uint4(nu8_word<0>(a), nu8_word<1>(a), nu8_word<2>(a), nu8_word<3>(a));
+      dst[1] = make_uint4(nu8_word<4>(a), nu8_word<5>(a), nu8_word<6>(a), nu8_word<7>(a));
+      dst[2] = make_uint4(nu8_word<0>(b), nu8_word<1>(b), nu8_word<2>(b), nu8_word<3>(b));
+      dst[3] = make_uint4(nu8_word<4>(b), nu8_word<5>(b), nu8_word<6>(b), nu8_word<7>(b));
+    }
   }
+}
+
+// XOR of data into the LDS word at addr + OFF by the two lanes in `writers`
+// (lanes 0 and 32: one per 32-replica half of a site word), under an exec
+// mask set and restored in the same statement.  Written as a branch around an
+// atomic, the flip would split the unrolled block into basic blocks, and the
+// compiler would then mask every prefetched threshold byte again.  All 64
+// lanes are active wherever this is called, so exec is set to `writers`
+// outright: only s_mov_b64 touches it, which leaves SCC alone (the compiler
+// may hold a branch condition in SCC across this statement; s_and_saveexec
+// would overwrite it).
+template <int OFF>
+__device__ __forceinline__ void lds_xor_two_lanes(const char* addr, uint32_t data,
+                                                  unsigned long long writers) {
+  unsigned long long saved;
+  const uint32_t a = (uint32_t)(uintptr_t)addr;
+  asm volatile(
+      "s_mov_b64 %0, exec\n\t"
+      "s_mov_b64 exec, %3\n\t"
+      "ds_xor_b32 %1, %2 offset:%4\n\t"
+      "s_mov_b64 exec, %0"
+      : "=&s"(saved)
+      : "v"(a), "v"(data), "s"(writers), "i"(OFF)
+      : "memory");
 }
 
 // Phase 2 for site S.. of a block: the lane's threshold address from its byte
 // (plb: the block's first entry plus the lane's byte offset), then the Metropolis test
 // and the flip as in site_update.  The byte of site S + 1 is read before site
 // S is updated (the plane area is not written in this phase), so its LDS
-// latency overlaps the update.
-template <int L, int S, bool ACCUM>
+// latency overlaps the update.  Every group of four sites makes its Philox
+// call whether or not a draw can matter (a threshold of 0 or 2^32 decides
+// without it), so that the unrolled block has no branch and the byte and the
+// threshold are read in one basic block.
+//
+// FAST: the byte is 8 min(nu, 3) and the threshold the table's low 32-bit
+// word (see plane_group): one 32-bit compare.  Otherwise the byte is 8 nu and
+// the threshold the whole 64-bit entry (2^32: always taken); with ACCUM the
+// lane also sums its replica's post-move nu.
+template <int L, int S, bool FAST, bool ACCUM>
 __device__ __forceinline__ void block_planes(const TileCtx& c, const char* ownb,
                                              const uint8_t* plb, uint32_t g0, Words4& d,
                                              uint32_t& usum, uint32_t a8) {
   constexpr int BS = 2 * L;
   uint32_t nx = 0;
   if constexpr (S + 1 < BS) nx = (uint32_t)plb[64 * (S + 1)];
-  if constexpr (S % 4 == 0) {
-    if (c.any_draw) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
+  if constexpr (S % 4 == 0) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
+  bool acc;
+  if constexpr (FAST) {
+    const uint32_t thr =
+        *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(c.thr_of_nu) + a8);
+    acc = d.w[S % 4] < thr;
+  } else {
+    const unsigned long long thr = *reinterpret_cast<const unsigned long long*>(
+        reinterpret_cast<const char*>(c.thr_of_nu) + a8);
+    acc = (unsigned long long)d.w[S % 4] < thr;
+    if (ACCUM) {
+      const uint32_t n = a8 >> 3;
+      usum += acc ? 6u - n : n;
+    }
   }
-  const unsigned long long thr = *reinterpret_cast<const unsigned long long*>(
-      reinterpret_cast<const char*>(c.thr_of_nu) + a8);
-  const bool acc = (unsigned long long)d.w[S % 4] < thr;
-  if (ACCUM) {
-    const uint32_t n = a8 >> 3;
-    usum += acc ? 6u - n : n;
-  }
-  const unsigned long long f = __ballot(acc);
-  const uint32_t fh = c.hoff ? (uint32_t)(f >> 32) : (uint32_t)f;
-  uint32_t* const own_p = reinterpret_cast<uint32_t*>(const_cast<char*>(ownb) + 8 * S);
-  if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  if constexpr (S + 1 < BS) block_planes<L, S + 1, ACCUM>(c, ownb, plb, g0, d, usum, nx);
+  // this lane's half of the ballot: one 64-bit shift of the scalar mask
+  const uint32_t fh = (uint32_t)(__ballot(acc) >> c.hshift);
+  lds_xor_two_lanes<8 * S>(ownb, fh, c.writers);
+  if constexpr (S + 1 < BS) block_planes<L, S + 1, FAST, ACCUM>(c, ownb, plb, g0, d, usum, nx);
 }
 
 // One +-J colour pass of this wave (blocks rb = 4 part + 4 nparts i, as in
 // sweep_colour_blocks), GB blocks at a time: phase 1 for the group, then
-// phase 2 block by block.  The wave's plane area holds one group.
-template <int L, int SPLIT, bool ACCUM>
+// phase 2 block by block.  The wave's plane area holds one group.  FAST
+// passes skip phase 2 when no move that raises the energy can be taken
+// (every such threshold 0): phase 1 has done all the flips.
+template <int L, int SPLIT, bool FAST, bool ACCUM>
 __device__ uint32_t sweep_colour_planes(const TileCtx& c, const SiteEntry* __restrict__ sites,
                                         uint32_t colour, uint32_t part, uint32_t nparts,
                                         uint32_t* planes, uint32_t lane) {
+  static_assert(!(FAST && ACCUM), "the energy is summed by the 64-bit form of the pass");
   constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L, BS = 4 * H;
   constexpr uint32_t GB = plane_blocks(L, SPLIT);
   const uint32_t own0 = colour * (N / 2);
@@ -634,17 +710,20 @@ __device__ uint32_t sweep_colour_planes(const TileCtx& c, const SiteEntry* __res
   d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0u;
   const uint8_t* const plane_l = reinterpret_cast<const uint8_t*>(planes) + plane_byte(lane);
   const char* const own_h = reinterpret_cast<const char*>(c.lds) + c.hoff;
+  const bool phase2 = !FAST || c.any_draw;
   for (uint32_t rb0 = 4 * part; rb0 < ROWS; rb0 += step * GB) {
-    plane_group<L, SPLIT>(c, sites, own0, rb0, step, lane, planes);
+    plane_group<L, SPLIT, FAST>(c, sites, own0, rb0, step, lane, planes);
     __builtin_amdgcn_wave_barrier();
+    if (phase2) {
 #pragma unroll 1
-    for (uint32_t bi = 0; bi < GB; ++bi) {
-      const uint32_t rb = __builtin_amdgcn_readfirstlane(rb0 + step * bi);
-      if (rb >= ROWS) break;
-      const uint32_t g0 = (own0 + H * rb) >> 2;  // first Philox group of the block
-      const char* ownb = own_h + whole_s(8 * (own0 + H * rb));
-      const uint8_t* plb = plane_l + 64 * BS * bi;
-      block_planes<L, 0, ACCUM>(c, ownb, plb, g0, d, usum, plb[0]);
+      for (uint32_t bi = 0; bi < GB; ++bi) {
+        const uint32_t rb = __builtin_amdgcn_readfirstlane(rb0 + step * bi);
+        if (rb >= ROWS) break;
+        const uint32_t g0 = (own0 + H * rb) >> 2;  // first Philox group of the block
+        const char* ownb = own_h + whole_s(8 * (own0 + H * rb));
+        const uint8_t* plb = plane_l + 64 * BS * bi;
+        block_planes<L, 0, FAST, ACCUM>(c, ownb, plb, g0, d, usum, plb[0]);
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -1219,6 +1298,8 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   const uint32_t lane = lane_id();
   // this wave's share of the tile (uniform: a scalar register)
   const uint32_t part = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  // a copy step the scan found over capacity is not applied: nothing runs
+  if (sp.gather && P.sc->err != 0u) return;
   if (sp.gather && m.lb == 0 && threadIdx.x == 0) P.sc->R_tilde = P.sc->R_next;
   // uniform: held in a scalar register
   const uint32_t Rs =
@@ -1267,6 +1348,8 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   // a positive move, the table's dE16 = 2 and last entries, in thr[0] and
   // thr[1], and 0 in thr[2]; the table is non-increasing, so a draw matters
   // unless both are 0 or both are 2^32.)
+  c.writers = 0x0000000100000001ull;
+  c.hshift = 8u * c.hoff;
   c.any_draw = (sp.thr[0] != 0 && sp.thr[0] < (1ull << 32)) ||
                (sp.thr[1] != 0 && sp.thr[1] < (1ull << 32)) ||
                (sp.thr[2] != 0 && sp.thr[2] < (1ull << 32));
@@ -1291,14 +1374,24 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
       // this wave's plane area (phase 1 of the +-J colour passes), after the
       // tile image and the per-replica reduction area
       uint32_t* const planes = lds_all + 2 * N + 64 * SPLIT + plane_words(L, SPLIT) * part;
-      for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
+      // every move that raises the energy has a threshold below 2^32 (beta
+      // not 0 in double precision): the passes take the 32-bit form, but for
+      // the last colour-1 pass, which also sums the energy
+      const bool fast = sp.thr[0] < (1ull << 32);
+      for (uint32_t s = 0; s < sp.n_sweeps; ++s) {
         c.t = sp.t0 + s;
-        sweep_colour_planes<L, SPLIT, false>(c, P.sites, 0u, part, SPLIT, planes, lane);
-        sweep_colour_planes<L, SPLIT, false>(c, P.sites, 1u, part, SPLIT, planes, lane);
+        for (uint32_t colour = 0; colour < 2; ++colour) {
+          if (s + 1 == sp.n_sweeps && colour == 1)
+            U = sweep_colour_planes<L, SPLIT, false, true>(c, P.sites, 1u, part, SPLIT, planes,
+                                                           lane);
+          else if (fast)
+            sweep_colour_planes<L, SPLIT, true, false>(c, P.sites, colour, part, SPLIT, planes,
+                                                       lane);
+          else
+            sweep_colour_planes<L, SPLIT, false, false>(c, P.sites, colour, part, SPLIT, planes,
+                                                        lane);
+        }
       }
-      c.t = sp.t0 + sp.n_sweeps - 1;
-      sweep_colour_planes<L, SPLIT, false>(c, P.sites, 0u, part, SPLIT, planes, lane);
-      U = sweep_colour_planes<L, SPLIT, true>(c, P.sites, 1u, part, SPLIT, planes, lane);
     }
   }
   // Epilogue.  The lane number, the slot, its source and the descriptor

@@ -42,7 +42,7 @@ def test_workspace_sizing_and_argument_checks():
     cap = 500000 + 16 * 707 + 256
     assert nb >= 2 * (cap // 64) * 1000 * 8
     assert nb < 200 * 2 ** 20
-    for bad in (dict(L=5), dict(L=2), dict(L=18), dict(R=0), dict(layout=7), dict(flags=4),
+    for bad in (dict(L=5), dict(L=2), dict(L=18), dict(R=0), dict(layout=7), dict(flags=8),
                 dict(flags=0x80000000), dict(capacity=10), dict(model=2)):
         q = pam.pa_params(L=10, R=1000, capacity=0, layout=1, seed=1, flags=0, model=0)
         for k, v in bad.items():
@@ -53,7 +53,7 @@ def test_workspace_sizing_and_argument_checks():
     q = pam.pa_params(L=10, R=1000, capacity=0, layout=2, seed=1, flags=0, model=0)
     assert pam.pa_workspace_bytes(g) >= pam.pa_workspace_bytes(q) + 16 * (6 * 1000 * 127 - 3 * 1000)
     # the debugging flags change nothing in the workspace
-    for flags in (pam.PA_FLAG_CHECK_ENERGY, pam.PA_FLAG_FAULT_HOOK,
+    for flags in (pam.PA_FLAG_CHECK_ENERGY, pam.PA_FLAG_FAULT_HOOK, pam.PA_FLAG_TIME_SWEEPS,
                   pam.PA_FLAG_CHECK_ENERGY | pam.PA_FLAG_FAULT_HOOK):
         f = pam.pa_params(L=10, R=500000, capacity=0, layout=pam.PA_LAYOUT_BITPACK64, seed=1,
                           flags=flags, model=0)

@@ -172,3 +172,88 @@ def test_checkpoint_resume_is_bit_identical(pam, layout, model):
     np.testing.assert_array_equal(f1, f2)
     full.close()
     resumed.close()
+
+
+# ---------------------------------------------------------------------------
+# pa_anneal_step: one whole step with a single synchronisation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("layout", ["int8", "bitpack64"])
+@pytest.mark.parametrize("model", ["pm", "gauss16"])
+def test_anneal_step_equals_separate_calls(pam, layout, model):
+    say("anneal step", layout, model)
+    L, R, seed = 8, 9000, 0x5EED1401
+    J = (pa_inputs.couplings_pm(L, 4) if model == "pm" else pa_inputs.couplings_gauss16(L, 4))
+    a = pam.Population(L, R, J, seed, layout=layout, model=model)
+    b = pam.Population(L, R, J, seed, layout=layout, model=model,
+                       flags=pam.PA_FLAG_TIME_SWEEPS)
+    ref = _anneal(a, 8)
+    for k in range(8):
+        beta, obs = b.anneal_step(0.1, 5.0, 4)
+        assert beta == ref[k]["beta"], k
+        assert obs["sweep_ms"] > 0.0
+        obs["sweep_ms"] = 0.0
+        assert obs == ref[k], k
+    # fixed temperatures (eps_target < 0): the step to the given beta
+    for beta in (0.9, 1.3):
+        a.resample(beta)
+        a.sweep(beta, 3)
+        want = a.observables()
+        got = b.step_to(beta, 3)
+        got["sweep_ms"] = 0.0
+        assert got == want
+    s1, u1, f1 = a.export_state()
+    s2, u2, f2 = b.export_state()
+    np.testing.assert_array_equal(s1, s2)
+    np.testing.assert_array_equal(u1, u2)
+    np.testing.assert_array_equal(f1, f2)
+    a.close()
+    b.close()
+
+
+def test_anneal_step_against_oracle(pam):
+    import oracle
+
+    say("anneal step vs oracle")
+    L, R, seed = 6, 4000, 0x5EED1501
+    J = pa_inputs.couplings_pm(L, 21)
+    g = pam.Population(L, R, J, seed, layout="bitpack64")
+    o = oracle.Population(L, J, R, seed)
+    for k in range(12):
+        beta, obs = g.anneal_step(0.1, 5.0, 5)
+        bo = o.choose_beta(0.1, 5.0)
+        assert beta == bo, k
+        o.resample(bo)
+        o.sweep(bo, 5)
+        rec = o.observables()
+        for key in ("beta_F", "mean_E", "rho_t", "lnQ", "eps_expected"):
+            assert obs[key] == getattr(rec, key), (k, key)
+        assert obs["R_tilde"] == rec.R_tilde and obs["sum_eta2"] == rec.sum_eta2
+    s, u, f = g.export_state()
+    np.testing.assert_array_equal(s.reshape(-1), o.spins)
+    np.testing.assert_array_equal(u.astype(np.int32), o.U)
+    np.testing.assert_array_equal(f, o.fam)
+    g.close()
+
+
+@pytest.mark.parametrize("model", ["pm", "gauss16"])
+def test_anneal_step_overflow_keeps_population(pam, model):
+    """With capacity R, a large step overflows: PA_ECAPACITY, and the
+    population, its counters and its next steps are as if it had not been tried."""
+    say("anneal step overflow", model)
+    L, R = 4, 256
+    J = (pa_inputs.couplings_pm(L, 8) if model == "pm" else pa_inputs.couplings_gauss16(L, 8))
+    g = pam.Population(L, R, J, 5, capacity=R, layout="int8", model=model)
+    failed = False
+    for beta in np.linspace(0.5, 5.0, 40):
+        before, obs_before = g.export_state(), g.observables()
+        try:
+            g.step_to(float(beta), 1)
+        except pam.PAError as e:
+            assert e.status == pam.PA_ECAPACITY
+            failed = True
+            break
+    assert failed
+    for x, y in zip(before, g.export_state()):
+        np.testing.assert_array_equal(x, y)
+    assert g.observables() == obs_before
+    g.close()
