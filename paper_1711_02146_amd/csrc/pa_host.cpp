@@ -90,6 +90,7 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.off_fl = take((size_t)l.n_levels * 4);
   l.off_T = take((size_t)l.n_levels * 8);
   l.off_sites = take((size_t)l.N * sizeof(SiteEntry));
+  l.off_psites = take((size_t)l.N * sizeof(pa::PlaneSite));
   l.off_cm = take((size_t)l.N * 2);
   l.off_rowj = take((size_t)2 * l.L * l.L * 8);
   l.off_rowk = take((size_t)2 * l.L * l.L * l.rowk_stride);
@@ -662,6 +663,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   P.table_fl = reinterpret_cast<uint32_t*>(w + l.off_fl);
   P.table_T = reinterpret_cast<unsigned long long*>(w + l.off_T);
   P.sites = reinterpret_cast<const SiteEntry*>(w + l.off_sites);
+  P.psites = reinterpret_cast<const pa::PlaneSite*>(w + l.off_psites);
   P.cm_of_site = reinterpret_cast<const uint16_t*>(w + l.off_cm);
   P.rowj = reinterpret_cast<const unsigned long long*>(w + l.off_rowj);
   P.ovl_hist = reinterpret_cast<unsigned long long*>(w + l.off_ovl);
@@ -704,6 +706,15 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
        hipEventRecord(in->gthr_copied, in->stream) != hipSuccess))
     return fail(PA_EDEVICE);
 
+  // phase 1 of the +-J colour pass reads each site's neighbours at the LDS
+  // addresses of their words in the tile image
+  std::vector<pa::PlaneSite> psites(l.N);
+  for (uint32_t cm = 0; cm < l.N; ++cm) {
+    pa::PlaneSite& q = psites[cm];
+    for (int k = 0; k < 6; ++k) q.nb8[k] = pa::kTileLdsBase + 8u * in->sites[cm].nb[k];
+    q.jneg = in->sites[cm].jneg;
+    q.pad = 0;
+  }
   // tables and scalars (synchronous copies from pageable host memory)
   DevScalars sc{};
   sc.R_tilde = l.R;
@@ -711,6 +722,8 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
                      hipMemcpyHostToDevice, in->stream) != hipSuccess ||
       hipMemcpyAsync(w + l.off_cm, in->cm_of_site.data(), l.N * 2, hipMemcpyHostToDevice,
                      in->stream) != hipSuccess ||
+      hipMemcpyAsync(w + l.off_psites, psites.data(), l.N * sizeof(pa::PlaneSite),
+                     hipMemcpyHostToDevice, in->stream) != hipSuccess ||
       hipMemcpyAsync(w + l.off_rowj, in->rowj.data(), in->rowj.size() * 8, hipMemcpyHostToDevice,
                      in->stream) != hipSuccess ||
       (!in->rowk.empty() &&

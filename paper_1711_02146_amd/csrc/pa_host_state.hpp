@@ -33,7 +33,7 @@ struct Layout {
   uint32_t L, N, R, cap_limit, capacity, layout, n_levels, n_blocks, model, rowk_stride;
   size_t spins_bytes;
   size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
-      off_bcull, off_hist, off_fl, off_T, off_sites, off_cm, off_rowj, off_rowk, off_gthr, off_ovl,
+      off_bcull, off_hist, off_fl, off_T, off_sites, off_psites, off_cm, off_rowj, off_rowk, off_gthr, off_ovl,
       off_lovl, off_lpart, off_sc, off_pops, off_meta;
   size_t total;
 };

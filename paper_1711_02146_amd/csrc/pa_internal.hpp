@@ -45,7 +45,14 @@ constexpr uint32_t plane_blocks(uint32_t L, uint32_t split) {
          : L == 14 ? (split == 8 ? 2u : 1u) : 1u;
 }
 constexpr uint32_t plane_sites(uint32_t L, uint32_t split) { return plane_blocks(L, split) * 2u * L; }
-constexpr uint32_t plane_words(uint32_t L, uint32_t split) { return plane_sites(L, split) * 16u; }
+// A site's entry in the plane area is 64 bytes (one per replica), stored 68
+// bytes apart: phase 1 writes the entries of 64 sites at once, lane l to words
+// 17 l + k, and 17 is odd, so the 64 lanes of each write fall in different LDS
+// banks (at a 64-byte stride lanes l, l + 4, ... would share one).
+constexpr uint32_t kPlaneEntryWords = 17;
+constexpr uint32_t plane_words(uint32_t L, uint32_t split) {
+  return plane_sites(L, split) * kPlaneEntryWords;
+}
 constexpr uint32_t kLinkCopies = 32;  // partial link-overlap histograms (see launch_link_overlap)
 // Energy models.  kModelPm: J = +-1, the energy word of a replica is U, the
 // number of unsatisfied bonds (E = 2U - 3N).  kModelGauss16: J = k / 16 with
@@ -67,6 +74,21 @@ struct SiteEntry {
   uint16_t site;
 };
 static_assert(sizeof(SiteEntry) == 16, "SiteEntry must be 16 bytes");
+
+// LDS address of the tile image in the sweep kernel: right after its 8-entry
+// threshold table, which sits at address 0 (the kernel checks both).
+constexpr uint32_t kTileLdsBase = 64;
+
+// The same site for phase 1 of the +-J colour pass (lane = site), laid out so
+// that nothing needs unpacking: the LDS addresses kTileLdsBase + 8 nb[k] of
+// the six neighbours' words, and the coupling bits.  32 bytes: two 16-byte
+// loads per lane.
+struct PlaneSite {
+  uint32_t nb8[6];
+  uint32_t jneg;
+  uint32_t pad;
+};
+static_assert(sizeof(PlaneSite) == 32, "PlaneSite must be 32 bytes");
 
 // Device-resident scalars of one population.
 struct DevScalars {
@@ -104,6 +126,7 @@ struct DevPop {
   uint32_t* table_fl;           // n_levels: floor(tau_j)
   unsigned long long* table_T;  // n_levels: ceil(frac(tau_j) 2^53)
   const SiteEntry* sites;       // N entries, colour-major
+  const PlaneSite* psites;      // N entries, colour-major (phase 1 of the +-J pass)
   const uint16_t* cm_of_site;   // N entries: lexicographic site -> colour-major index
   const unsigned long long* rowj;  // 2 L^2 row words: bit 6q + k set iff the bond from
                                    // site q of row (colour, y, z) to neighbour k is -1

@@ -570,7 +570,8 @@ __device__ __forceinline__ uint32_t plane_byte(uint32_t r) {
 // Phase 1 for one group of a wave's blocks: lane l takes site sb = l mod BS
 // of block bi = l / BS (BS = 4 L/2 sites per block of four rows; GB blocks
 // per group, rows rb0 + step bi .. + 3) and writes entry l of the wave's
-// plane area: 64 bytes, byte plane_byte(r) = 8 nu of replica r at that site.
+// plane area: 64 bytes at words 17 l .. 17 l + 15 (kPlaneEntryWords), byte
+// plane_byte(r) = 8 nu of replica r at that site.
 //
 // FAST (every move that raises the energy has a threshold below 2^32): the
 // replicas with nu >= 3, whose move does not raise the energy and is always
@@ -580,7 +581,7 @@ __device__ __forceinline__ uint32_t plane_byte(uint32_t r) {
 // wave writes the words of its own sites during the pass, and phase 2 does not
 // read them, so the early flip changes nothing but the order of the XORs.
 template <int L, int SPLIT, bool FAST>
-__device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* __restrict__ sites,
+__device__ __forceinline__ void plane_group(const TileCtx& c, const PlaneSite* __restrict__ sites,
                                             uint32_t own0, uint32_t rb0, uint32_t step,
                                             uint32_t lane, uint32_t* planes) {
   constexpr uint32_t H = L / 2, BS = 4 * H, GB = plane_blocks(L, SPLIT), ROWS = L * L;
@@ -588,40 +589,48 @@ __device__ __forceinline__ void plane_group(const TileCtx& c, const SiteEntry* _
   const uint32_t rb = rb0 + step * bi;
   if (bi < GB && rb < ROWS) {
     const uint32_t cm = own0 + H * rb + sb;
-    const SiteEntry e = sites[cm];
+    const uint4 e0 = reinterpret_cast<const uint4*>(sites)[2 * cm];
+    const uint4 e1 = reinterpret_cast<const uint4*>(sites)[2 * cm + 1];
+    const uint32_t nb8[6] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y};
+    const uint32_t jneg = e1.z;
     uint2* w = reinterpret_cast<uint2*>(c.lds);
+    // LDS address 0: the table's addresses are absolute (the kernel has
+    // checked that the tile image starts at kTileLdsBase)
+    const char* lds0 = reinterpret_cast<const char*>(c.thr_of_nu);
     const uint2 o = w[cm];
     uint32_t lo[6], hi[6], jm[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const uint2 v = w[e.nb[k]];
+      const uint2 v = *reinterpret_cast<const uint2*>(lds0 + nb8[k]);
       lo[k] = v.x;
       hi[k] = v.y;
-      jm[k] = (uint32_t)((int32_t)((uint32_t)e.jneg << (31 - k)) >> 31);
+      jm[k] = (uint32_t)((int32_t)(jneg << (31 - k)) >> 31);
     }
     const NuPlanes pa = nu_planes(o.x, lo, jm);
     const NuPlanes pb = nu_planes(o.y, hi, jm);
-    uint4* dst = reinterpret_cast<uint4*>(planes + 16 * lane);
+    uint32_t* dst = planes + kPlaneEntryWords * lane;
     if constexpr (FAST) {
       // nu >= 3: p2 | (p1 & p0); flipped now
       w[cm] = make_uint2(o.x ^ (pa.p2 | (pa.p1 & pa.p0)), o.y ^ (pb.p2 | (pb.p1 & pb.p0)));
       const uint32_t a0 = pa.p0 | pa.p2, a1 = rotr32(pa.p1 | pa.p2, 31);
       const uint32_t b0 = pb.p0 | pb.p2, b1 = rotr32(pb.p1 | pb.p2, 31);
-      dst[0] = make_uint4(cls8_word<0>(a0, a1), cls8_word<1>(a0, a1), cls8_word<2>(a0, a1),
-                          cls8_word<3>(a0, a1));
-      dst[1] = make_uint4(cls8_word<4>(a0, a1), cls8_word<5>(a0, a1), cls8_word<6>(a0, a1),
-                          cls8_word<7>(a0, a1));
-      dst[2] = make_uint4(cls8_word<0>(b0, b1), cls8_word<1>(b0, b1), cls8_word<2>(b0, b1),
-                          cls8_word<3>(b0, b1));
-      dst[3] = make_uint4(cls8_word<4>(b0, b1), cls8_word<5>(b0, b1), cls8_word<6>(b0, b1),
-                          cls8_word<7>(b0, b1));
+      dst[0] = cls8_word<0>(a0, a1); dst[1] = cls8_word<1>(a0, a1);
+      dst[2] = cls8_word<2>(a0, a1); dst[3] = cls8_word<3>(a0, a1);
+      dst[4] = cls8_word<4>(a0, a1); dst[5] = cls8_word<5>(a0, a1);
+      dst[6] = cls8_word<6>(a0, a1); dst[7] = cls8_word<7>(a0, a1);
+      dst[8] = cls8_word<0>(b0, b1); dst[9] = cls8_word<1>(b0, b1);
+      dst[10] = cls8_word<2>(b0, b1); dst[11] = cls8_word<3>(b0, b1);
+      dst[12] = cls8_word<4>(b0, b1); dst[13] = cls8_word<5>(b0, b1);
+      dst[14] = cls8_word<6>(b0, b1); dst[15] = cls8_word<7>(b0, b1);
     } else {
       const NuPlanesRot a = rot_planes(pa);
       const NuPlanesRot b = rot_planes(pb);
-      dst[0] = make_uint4(nu8_word<0>(a), nu8_word<1>(a), nu8_word<2>(a), nu8_word<3>(a));
-      dst[1] = make_uint4(nu8_word<4>(a), nu8_word<5>(a), nu8_word<6>(a), nu8_word<7>(a));
-      dst[2] = make_uint4(nu8_word<0>(b), nu8_word<1>(b), nu8_word<2>(b), nu8_word<3>(b));
-      dst[3] = make_uint4(nu8_word<4>(b), nu8_word<5>(b), nu8_word<6>(b), nu8_word<7>(b));
+      dst[0] = nu8_word<0>(a); dst[1] = nu8_word<1>(a); dst[2] = nu8_word<2>(a);
+      dst[3] = nu8_word<3>(a); dst[4] = nu8_word<4>(a); dst[5] = nu8_word<5>(a);
+      dst[6] = nu8_word<6>(a); dst[7] = nu8_word<7>(a);
+      dst[8] = nu8_word<0>(b); dst[9] = nu8_word<1>(b); dst[10] = nu8_word<2>(b);
+      dst[11] = nu8_word<3>(b); dst[12] = nu8_word<4>(b); dst[13] = nu8_word<5>(b);
+      dst[14] = nu8_word<6>(b); dst[15] = nu8_word<7>(b);
     }
   }
 }
@@ -668,8 +677,9 @@ __device__ __forceinline__ void block_planes(const TileCtx& c, const char* ownb,
                                              const uint8_t* plb, uint32_t g0, Words4& d,
                                              uint32_t& usum, uint32_t a8) {
   constexpr int BS = 2 * L;
+  constexpr int E = 4 * kPlaneEntryWords;  // bytes from one site's entry to the next
   uint32_t nx = 0;
-  if constexpr (S + 1 < BS) nx = (uint32_t)plb[64 * (S + 1)];
+  if constexpr (S + 1 < BS) nx = (uint32_t)plb[E * (S + 1)];
   if constexpr (S % 4 == 0) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
   bool acc;
   if constexpr (FAST) {
@@ -697,7 +707,7 @@ __device__ __forceinline__ void block_planes(const TileCtx& c, const char* ownb,
 // passes skip phase 2 when no move that raises the energy can be taken
 // (every such threshold 0): phase 1 has done all the flips.
 template <int L, int SPLIT, bool FAST, bool ACCUM>
-__device__ uint32_t sweep_colour_planes(const TileCtx& c, const SiteEntry* __restrict__ sites,
+__device__ uint32_t sweep_colour_planes(const TileCtx& c, const PlaneSite* __restrict__ sites,
                                         uint32_t colour, uint32_t part, uint32_t nparts,
                                         uint32_t* planes, uint32_t lane) {
   static_assert(!(FAST && ACCUM), "the energy is summed by the 64-bit form of the pass");
@@ -721,7 +731,7 @@ __device__ uint32_t sweep_colour_planes(const TileCtx& c, const SiteEntry* __res
         if (rb >= ROWS) break;
         const uint32_t g0 = (own0 + H * rb) >> 2;  // first Philox group of the block
         const char* ownb = own_h + whole_s(8 * (own0 + H * rb));
-        const uint8_t* plb = plane_l + 64 * BS * bi;
+        const uint8_t* plb = plane_l + 4 * kPlaneEntryWords * BS * bi;
         block_planes<L, 0, FAST, ACCUM>(c, ownb, plb, g0, d, usum, plb[0]);
       }
     }
@@ -1312,9 +1322,11 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   // whole workgroups leave together (the passes below use workgroup barriers)
   if (tile * 64 >= Rs) return;
   // site_update indexes the threshold table by byte address 8 nu: it must sit
-  // at LDS address 0.  If the toolchain ever places it elsewhere, report a
-  // configuration error instead of computing with a wrong table.
-  if ((uint32_t)(uintptr_t)thr_of_nu != 0u) {
+  // at LDS address 0, and phase 1 of the +-J pass reads the tile image at the
+  // absolute addresses of its site table, so the image must start at
+  // kTileLdsBase.  If the toolchain ever places them elsewhere, report a
+  // configuration error instead of computing with wrong addresses.
+  if ((uint32_t)(uintptr_t)thr_of_nu != 0u || (uint32_t)(uintptr_t)lds_all != kTileLdsBase) {
     if (threadIdx.x == 0) {
       P.sc->err = 2u;
       P.sc->dead = 1u;
@@ -1373,7 +1385,7 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
     } else {
       // this wave's plane area (phase 1 of the +-J colour passes), after the
       // tile image and the per-replica reduction area
-      uint32_t* const planes = lds_all + 2 * N + 64 * SPLIT + plane_words(L, SPLIT) * part;
+      uint32_t* const planes = lds_all + 2 * N + plane_words(L, SPLIT) * part;
       // every move that raises the energy has a threshold below 2^32 (beta
       // not 0 in double precision): the passes take the 32-bit form, but for
       // the last colour-1 pass, which also sums the energy
@@ -1382,13 +1394,13 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
         c.t = sp.t0 + s;
         for (uint32_t colour = 0; colour < 2; ++colour) {
           if (s + 1 == sp.n_sweeps && colour == 1)
-            U = sweep_colour_planes<L, SPLIT, false, true>(c, P.sites, 1u, part, SPLIT, planes,
+            U = sweep_colour_planes<L, SPLIT, false, true>(c, P.psites, 1u, part, SPLIT, planes,
                                                            lane);
           else if (fast)
-            sweep_colour_planes<L, SPLIT, true, false>(c, P.sites, colour, part, SPLIT, planes,
+            sweep_colour_planes<L, SPLIT, true, false>(c, P.psites, colour, part, SPLIT, planes,
                                                        lane);
           else
-            sweep_colour_planes<L, SPLIT, false, false>(c, P.sites, colour, part, SPLIT, planes,
+            sweep_colour_planes<L, SPLIT, false, false>(c, P.psites, colour, part, SPLIT, planes,
                                                         lane);
         }
       }
@@ -1401,7 +1413,8 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   uint32_t lane2, pop2 = m.pop;
   asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lane2));
   asm volatile("" : "+s"(pop2));
-  // per-replica sum of the waves' shares (after the tile image, in LDS)
+  // per-replica sum of the waves' shares (after the tile image, in LDS: the
+  // +-J plane areas, free once every wave has passed the barrier below)
   uint32_t* const ured = lds_all + 2 * N;
   __syncthreads();
   ured[part * 64 + lane2] = U;
@@ -1822,9 +1835,12 @@ void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t 
                     hipStream_t stream) {
   // after the tile image and the reduction area: the Gaussian threshold table,
   // or the +-J plane areas (one per wave)
-  const size_t gbytes = model == kModelGauss16 ? (size_t)(kGaussDEMax + 1) * 8
-                                               : (size_t)plane_words(L, split) * 4 * split;
-  const size_t lds = (size_t)L * L * L * 8 + 4 * 64 * split + gbytes;
+  // after the tile image: the reduction area and the Gaussian threshold table,
+  // or the +-J plane areas (one per wave; the reduction area lies over them)
+  const size_t after = model == kModelGauss16
+                           ? 4 * 64 * split + (size_t)(kGaussDEMax + 1) * 8
+                           : std::max((size_t)plane_words(L, split) * 4 * split, (size_t)4 * 64 * split);
+  const size_t lds = (size_t)L * L * L * 8 + after;
   if (model == kModelGauss16) {
     if (split == 8)
       hipLaunchKernelGGL((k_sweep<LAYOUT, L, 8, kModelGauss16>), dim3(g.blocks), dim3(64 * 8), lds,
