@@ -30,29 +30,11 @@ constexpr int kBlockCounts = 256;  // slots per block in the copy-count / scatte
 constexpr int kHistSlots = 4096;   // slots per block of the histogram kernel
 constexpr int kWindowLdsLevels = 16384;  // largest E16 window counted in LDS (64 KiB)
 constexpr int kMaxL = 16;
-// +-J sweep: per wave, the threshold byte addresses 8 nu of one group of
-// plane_blocks(L) blocks of four rows (2L sites each) x 64 replicas, one byte
-// each.  A larger group fills more of a wave's 64 lanes in phase 1; a smaller
-// one leaves LDS for more waves per SIMD.  The sizes were chosen by timing
-// both sweep forms on MI355X (at L = 10, two blocks and 8 waves per SIMD beat
-// three blocks and 6 by 4%; at L = 8 four blocks beat three by 6%).
-// With eight waves per tile the tile image and the reduction area are shared
-// by twice the waves, so at L = 10 three blocks per group still leave four
-// workgroups (eight waves per SIMD) in a CU's 160 KB, and at L = 14 two
-// blocks fit the six waves per SIMD its registers allow (9% faster than one).
-constexpr uint32_t plane_blocks(uint32_t L, uint32_t split) {
-  return L <= 4 ? 8u : L == 6 ? 5u : L == 8 ? 4u : L == 10 ? (split == 8 ? 3u : 2u) : L == 12 ? 2u
-         : L == 14 ? (split == 8 ? 2u : 1u) : 1u;
-}
-constexpr uint32_t plane_sites(uint32_t L, uint32_t split) { return plane_blocks(L, split) * 2u * L; }
-// A site's entry in the plane area is 64 bytes (one per replica), stored 68
-// bytes apart: phase 1 writes the entries of 64 sites at once, lane l to words
-// 17 l + k, and 17 is odd, so the 64 lanes of each write fall in different LDS
-// banks (at a 64-byte stride lanes l, l + 4, ... would share one).
-constexpr uint32_t kPlaneEntryWords = 17;
-constexpr uint32_t plane_words(uint32_t L, uint32_t split) {
-  return plane_sites(L, split) * kPlaneEntryWords;
-}
+// +-J sweep: per wave, the threshold byte addresses of one chunk of 64 sites
+// x 64 replicas, one byte each (phase 1 of the colour pass: one site per
+// lane).  With the 8 KB tile image at L = 10, eight such areas leave four
+// workgroups of eight waves (eight waves per SIMD) in a CU's 160 KB.
+constexpr uint32_t kPlaneAreaBytes = 64 * 64;
 constexpr uint32_t kLinkCopies = 32;  // partial link-overlap histograms (see launch_link_overlap)
 // Energy models.  kModelPm: J = +-1, the energy word of a replica is U, the
 // number of unsatisfied bonds (E = 2U - 3N).  kModelGauss16: J = k / 16 with

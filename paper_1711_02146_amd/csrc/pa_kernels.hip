@@ -562,33 +562,48 @@ __device__ __forceinline__ uint32_t cls8_word(uint32_t c0, uint32_t c1r) {
   return rotr32((c0 & m) | (c1r & m1), (J - 3) & 31);
 }
 
-// byte of replica r (lane r) within a site's 64-byte entry
+// byte of replica r (lane r) within a site's 64 bytes, before the rotation below
 __device__ __forceinline__ uint32_t plane_byte(uint32_t r) {
   return (r & 32u) + 4u * (r & 7u) + ((r >> 3) & 3u);
 }
 
-// Phase 1 for one group of a wave's blocks: lane l takes site sb = l mod BS
-// of block bi = l / BS (BS = 4 L/2 sites per block of four rows; GB blocks
-// per group, rows rb0 + step bi .. + 3) and writes entry l of the wave's
-// plane area: 64 bytes at words 17 l .. 17 l + 15 (kPlaneEntryWords), byte
-// plane_byte(r) = 8 nu of replica r at that site.
+// The +-J colour pass gives each wave one contiguous range of the colour's
+// sites (same-colour sites are independent, and a range that starts on a
+// multiple of 4 holds whole Philox groups), taken 64 sites (one per lane in
+// phase 1) at a time.  W sites per wave: an even share rounded up to whole
+// groups; the last wave's range is shorter.
+template <int L, int SPLIT>
+constexpr uint32_t wave_sites() {
+  return ((uint32_t)(L * L * L / 2 + SPLIT - 1) / SPLIT + 3u) / 4u * 4u;
+}
+
+// Plane area of a wave: entry e (the e-th site of a 64-site chunk) is 64
+// bytes at 64 e, the replicas' bytes in four 16-byte slots: the 16 bytes a
+// phase-1 lane forms as words 4j .. 4j + 3 go to slot (j + rot(e)) & 3.  With
+// rot(e) = ((e >> 1) + (e >> 3)) & 3, each 16-byte store of phase 1 puts the
+// 16 (or 8) lanes the LDS serves together in different banks, for 64 banks
+// of 4 bytes and for 32; unrotated, lanes 64 bytes apart share banks.
+__host__ __device__ constexpr uint32_t plane_rot(uint32_t e) { return ((e >> 1) + (e >> 3)) & 3u; }
+
+// Phase 1 for a chunk of n <= 64 sites from colour-major index cm0: lane e < n
+// takes site cm0 + e, reads its six neighbours' words (absolute LDS addresses
+// from the site table) and its own, forms the bit planes of nu for both
+// 32-replica halves and writes its plane entry.
 //
 // FAST (every move that raises the energy has a threshold below 2^32): the
 // replicas with nu >= 3, whose move does not raise the energy and is always
-// taken, are flipped here, in the site's word, and the byte holds 8 min(nu, 3).
+// taken, are flipped here, in the site's word, and the bytes hold 8 min(nu, 3).
 // Phase 2 then reads the low 32-bit word of the threshold table at that byte:
 // thr(nu) for nu <= 2, and 0 (never, the move is done) for nu >= 3.  Only this
 // wave writes the words of its own sites during the pass, and phase 2 does not
 // read them, so the early flip changes nothing but the order of the XORs.
-template <int L, int SPLIT, bool FAST>
-__device__ __forceinline__ void plane_group(const TileCtx& c, const PlaneSite* __restrict__ sites,
-                                            uint32_t own0, uint32_t rb0, uint32_t step,
-                                            uint32_t lane, uint32_t* planes) {
-  constexpr uint32_t H = L / 2, BS = 4 * H, GB = plane_blocks(L, SPLIT), ROWS = L * L;
-  const uint32_t bi = lane / BS, sb = lane - bi * BS;
-  const uint32_t rb = rb0 + step * bi;
-  if (bi < GB && rb < ROWS) {
-    const uint32_t cm = own0 + H * rb + sb;
+// Otherwise the bytes hold 8 nu (the 64-bit table's byte address).
+template <bool FAST>
+__device__ __forceinline__ void plane_chunk(const TileCtx& c, const PlaneSite* __restrict__ sites,
+                                            uint32_t cm0, uint32_t n, uint32_t lane,
+                                            char* planes) {
+  if (lane < n) {
+    const uint32_t cm = cm0 + lane;
     const uint4 e0 = reinterpret_cast<const uint4*>(sites)[2 * cm];
     const uint4 e1 = reinterpret_cast<const uint4*>(sites)[2 * cm + 1];
     const uint32_t nb8[6] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y};
@@ -608,37 +623,40 @@ __device__ __forceinline__ void plane_group(const TileCtx& c, const PlaneSite* _
     }
     const NuPlanes pa = nu_planes(o.x, lo, jm);
     const NuPlanes pb = nu_planes(o.y, hi, jm);
-    uint32_t* dst = planes + kPlaneEntryWords * lane;
+    uint4 q[4];
     if constexpr (FAST) {
       // nu >= 3: p2 | (p1 & p0); flipped now
       w[cm] = make_uint2(o.x ^ (pa.p2 | (pa.p1 & pa.p0)), o.y ^ (pb.p2 | (pb.p1 & pb.p0)));
       const uint32_t a0 = pa.p0 | pa.p2, a1 = rotr32(pa.p1 | pa.p2, 31);
       const uint32_t b0 = pb.p0 | pb.p2, b1 = rotr32(pb.p1 | pb.p2, 31);
-      dst[0] = cls8_word<0>(a0, a1); dst[1] = cls8_word<1>(a0, a1);
-      dst[2] = cls8_word<2>(a0, a1); dst[3] = cls8_word<3>(a0, a1);
-      dst[4] = cls8_word<4>(a0, a1); dst[5] = cls8_word<5>(a0, a1);
-      dst[6] = cls8_word<6>(a0, a1); dst[7] = cls8_word<7>(a0, a1);
-      dst[8] = cls8_word<0>(b0, b1); dst[9] = cls8_word<1>(b0, b1);
-      dst[10] = cls8_word<2>(b0, b1); dst[11] = cls8_word<3>(b0, b1);
-      dst[12] = cls8_word<4>(b0, b1); dst[13] = cls8_word<5>(b0, b1);
-      dst[14] = cls8_word<6>(b0, b1); dst[15] = cls8_word<7>(b0, b1);
+      q[0] = make_uint4(cls8_word<0>(a0, a1), cls8_word<1>(a0, a1), cls8_word<2>(a0, a1),
+                        cls8_word<3>(a0, a1));
+      q[1] = make_uint4(cls8_word<4>(a0, a1), cls8_word<5>(a0, a1), cls8_word<6>(a0, a1),
+                        cls8_word<7>(a0, a1));
+      q[2] = make_uint4(cls8_word<0>(b0, b1), cls8_word<1>(b0, b1), cls8_word<2>(b0, b1),
+                        cls8_word<3>(b0, b1));
+      q[3] = make_uint4(cls8_word<4>(b0, b1), cls8_word<5>(b0, b1), cls8_word<6>(b0, b1),
+                        cls8_word<7>(b0, b1));
     } else {
       const NuPlanesRot a = rot_planes(pa);
       const NuPlanesRot b = rot_planes(pb);
-      dst[0] = nu8_word<0>(a); dst[1] = nu8_word<1>(a); dst[2] = nu8_word<2>(a);
-      dst[3] = nu8_word<3>(a); dst[4] = nu8_word<4>(a); dst[5] = nu8_word<5>(a);
-      dst[6] = nu8_word<6>(a); dst[7] = nu8_word<7>(a);
-      dst[8] = nu8_word<0>(b); dst[9] = nu8_word<1>(b); dst[10] = nu8_word<2>(b);
-      dst[11] = nu8_word<3>(b); dst[12] = nu8_word<4>(b); dst[13] = nu8_word<5>(b);
-      dst[14] = nu8_word<6>(b); dst[15] = nu8_word<7>(b);
+      q[0] = make_uint4(nu8_word<0>(a), nu8_word<1>(a), nu8_word<2>(a), nu8_word<3>(a));
+      q[1] = make_uint4(nu8_word<4>(a), nu8_word<5>(a), nu8_word<6>(a), nu8_word<7>(a));
+      q[2] = make_uint4(nu8_word<0>(b), nu8_word<1>(b), nu8_word<2>(b), nu8_word<3>(b));
+      q[3] = make_uint4(nu8_word<4>(b), nu8_word<5>(b), nu8_word<6>(b), nu8_word<7>(b));
     }
+    char* const entry = planes + 64 * lane;
+    const uint32_t rot = plane_rot(lane);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      *reinterpret_cast<uint4*>(entry + 16 * ((j + rot) & 3u)) = q[j];
   }
 }
 
 // XOR of data into the LDS word at addr + OFF by the two lanes in `writers`
 // (lanes 0 and 32: one per 32-replica half of a site word), under an exec
 // mask set and restored in the same statement.  Written as a branch around an
-// atomic, the flip would split the unrolled block into basic blocks, and the
+// atomic, the flip would split the unrolled sites into basic blocks, and the
 // compiler would then mask every prefetched threshold byte again.  All 64
 // lanes are active wherever this is called, so exec is set to `writers`
 // outright: only s_mov_b64 touches it, which leaves SCC alone (the compiler
@@ -659,81 +677,88 @@ __device__ __forceinline__ void lds_xor_two_lanes(const char* addr, uint32_t dat
       : "memory");
 }
 
-// Phase 2 for site S.. of a block: the lane's threshold address from its byte
-// (plb: the block's first entry plus the lane's byte offset), then the Metropolis test
-// and the flip as in site_update.  The byte of site S + 1 is read before site
-// S is updated (the plane area is not written in this phase), so its LDS
-// latency overlaps the update.  Every group of four sites makes its Philox
-// call whether or not a draw can matter (a threshold of 0 or 2^32 decides
-// without it), so that the unrolled block has no branch and the byte and the
-// threshold are read in one basic block.
+// The lane's byte of entry E of a chunk: one of four per-lane addresses (by
+// the entry's rotation) plus 64 E, a constant offset of the instruction.
+struct PlaneReads {
+  const uint8_t* at[4];  // the lane's byte for entries of rotation 0..3, entry 0
+};
+
+template <int E>
+__device__ __forceinline__ uint32_t plane_read(const PlaneReads& pr) {
+  return (uint32_t)pr.at[plane_rot(E)][64 * E];
+}
+
+// Phase 2 for sites E.. of a chunk of n sites (n uniform): the Metropolis
+// test of this lane's replica at each site, and the flip.  A new Philox call
+// starts every fourth site, whether or not a draw can matter (a threshold of
+// 0 or 2^32 decides without it), so that each group of four sites is one
+// basic block; the chunk ends at the first group at or past n.  The byte of
+// site E + 1 of the same group is read before site E is updated (the plane
+// area is not written in this phase), so its LDS latency overlaps the update.
 //
 // FAST: the byte is 8 min(nu, 3) and the threshold the table's low 32-bit
-// word (see plane_group): one 32-bit compare.  Otherwise the byte is 8 nu and
+// word (see plane_chunk): one 32-bit compare.  Otherwise the byte is 8 nu and
 // the threshold the whole 64-bit entry (2^32: always taken); with ACCUM the
 // lane also sums its replica's post-move nu.
-template <int L, int S, bool FAST, bool ACCUM>
-__device__ __forceinline__ void block_planes(const TileCtx& c, const char* ownb,
-                                             const uint8_t* plb, uint32_t g0, Words4& d,
-                                             uint32_t& usum, uint32_t a8) {
-  constexpr int BS = 2 * L;
-  constexpr int E = 4 * kPlaneEntryWords;  // bytes from one site's entry to the next
+template <int E, bool FAST, bool ACCUM>
+__device__ __forceinline__ void chunk_sites(const TileCtx& c, const char* ownb,
+                                            const PlaneReads& pr, uint32_t g0, uint32_t n,
+                                            Words4& d, uint32_t& usum, uint32_t a8) {
+  if constexpr (E % 4 == 0) {
+    if ((uint32_t)E >= n) return;
+    a8 = plane_read<E>(pr);
+    d = c.ph.draw(c.t, g0 + (uint32_t)(E / 4));
+  }
   uint32_t nx = 0;
-  if constexpr (S + 1 < BS) nx = (uint32_t)plb[E * (S + 1)];
-  if constexpr (S % 4 == 0) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
+  if constexpr (E % 4 != 3) nx = plane_read<E + 1>(pr);
   bool acc;
   if constexpr (FAST) {
     const uint32_t thr =
         *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(c.thr_of_nu) + a8);
-    acc = d.w[S % 4] < thr;
+    acc = d.w[E % 4] < thr;
   } else {
     const unsigned long long thr = *reinterpret_cast<const unsigned long long*>(
         reinterpret_cast<const char*>(c.thr_of_nu) + a8);
-    acc = (unsigned long long)d.w[S % 4] < thr;
+    acc = (unsigned long long)d.w[E % 4] < thr;
     if (ACCUM) {
-      const uint32_t n = a8 >> 3;
-      usum += acc ? 6u - n : n;
+      const uint32_t nu = a8 >> 3;
+      usum += acc ? 6u - nu : nu;
     }
   }
   // this lane's half of the ballot: one 64-bit shift of the scalar mask
   const uint32_t fh = (uint32_t)(__ballot(acc) >> c.hshift);
-  lds_xor_two_lanes<8 * S>(ownb, fh, c.writers);
-  if constexpr (S + 1 < BS) block_planes<L, S + 1, FAST, ACCUM>(c, ownb, plb, g0, d, usum, nx);
+  lds_xor_two_lanes<8 * E>(ownb, fh, c.writers);
+  if constexpr (E + 1 < 64) chunk_sites<E + 1, FAST, ACCUM>(c, ownb, pr, g0, n, d, usum, nx);
 }
 
-// One +-J colour pass of this wave (blocks rb = 4 part + 4 nparts i, as in
-// sweep_colour_blocks), GB blocks at a time: phase 1 for the group, then
-// phase 2 block by block.  The wave's plane area holds one group.  FAST
-// passes skip phase 2 when no move that raises the energy can be taken
-// (every such threshold 0): phase 1 has done all the flips.
+// One +-J colour pass of this wave over its range of wave_sites() sites, a
+// 64-site chunk at a time: phase 1 for the chunk, then phase 2.  The wave's
+// plane area holds one chunk.  FAST passes skip phase 2 when no move that
+// raises the energy can be taken (every such threshold 0): phase 1 has done
+// all the flips.  The pass ends with a workgroup barrier, so the next colour
+// sees every flip.
 template <int L, int SPLIT, bool FAST, bool ACCUM>
 __device__ uint32_t sweep_colour_planes(const TileCtx& c, const PlaneSite* __restrict__ sites,
-                                        uint32_t colour, uint32_t part, uint32_t nparts,
-                                        uint32_t* planes, uint32_t lane) {
+                                        uint32_t colour, uint32_t part, char* planes,
+                                        const PlaneReads& pr, uint32_t lane) {
   static_assert(!(FAST && ACCUM), "the energy is summed by the 64-bit form of the pass");
-  constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L, BS = 4 * H;
-  constexpr uint32_t GB = plane_blocks(L, SPLIT);
-  const uint32_t own0 = colour * (N / 2);
-  const uint32_t step = 4 * nparts;
+  constexpr uint32_t N = L * L * L, HALF = N / 2, W = wave_sites<L, SPLIT>();
+  const uint32_t own0 = colour * HALF;
+  const uint32_t first = part * W;
+  const uint32_t last = min(first + W, HALF);
   uint32_t usum = 0;
   Words4 d;
   d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0u;
-  const uint8_t* const plane_l = reinterpret_cast<const uint8_t*>(planes) + plane_byte(lane);
   const char* const own_h = reinterpret_cast<const char*>(c.lds) + c.hoff;
   const bool phase2 = !FAST || c.any_draw;
-  for (uint32_t rb0 = 4 * part; rb0 < ROWS; rb0 += step * GB) {
-    plane_group<L, SPLIT, FAST>(c, sites, own0, rb0, step, lane, planes);
+  for (uint32_t s0 = first; s0 < last; s0 += 64) {
+    const uint32_t n = __builtin_amdgcn_readfirstlane(min(64u, last - s0));
+    const uint32_t cm0 = own0 + s0;
+    plane_chunk<FAST>(c, sites, cm0, n, lane, planes);
     __builtin_amdgcn_wave_barrier();
     if (phase2) {
-#pragma unroll 1
-      for (uint32_t bi = 0; bi < GB; ++bi) {
-        const uint32_t rb = __builtin_amdgcn_readfirstlane(rb0 + step * bi);
-        if (rb >= ROWS) break;
-        const uint32_t g0 = (own0 + H * rb) >> 2;  // first Philox group of the block
-        const char* ownb = own_h + whole_s(8 * (own0 + H * rb));
-        const uint8_t* plb = plane_l + 4 * kPlaneEntryWords * BS * bi;
-        block_planes<L, 0, FAST, ACCUM>(c, ownb, plb, g0, d, usum, plb[0]);
-      }
+      const char* ownb = own_h + whole_s(8 * cm0);
+      chunk_sites<0, FAST, ACCUM>(c, ownb, pr, cm0 >> 2, n, d, usum, 0u);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -1384,8 +1409,16 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
       U = sweep_colour_blocks<L, M, true>(c, rowj, 1u, part, SPLIT);
     } else {
       // this wave's plane area (phase 1 of the +-J colour passes), after the
-      // tile image and the per-replica reduction area
-      uint32_t* const planes = lds_all + 2 * N + plane_words(L, SPLIT) * part;
+      // tile image, and the lane's byte address in it for each rotation
+      char* const planes = reinterpret_cast<char*>(lds_all + 2 * N) + kPlaneAreaBytes * part;
+      PlaneReads pr;
+      {
+        const uint32_t pb = plane_byte(lane);
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k)
+          pr.at[k] = reinterpret_cast<const uint8_t*>(planes) + 16u * (((pb >> 4) + k) & 3u) +
+                     (pb & 15u);
+      }
       // every move that raises the energy has a threshold below 2^32 (beta
       // not 0 in double precision): the passes take the 32-bit form, but for
       // the last colour-1 pass, which also sums the energy
@@ -1394,13 +1427,13 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
         c.t = sp.t0 + s;
         for (uint32_t colour = 0; colour < 2; ++colour) {
           if (s + 1 == sp.n_sweeps && colour == 1)
-            U = sweep_colour_planes<L, SPLIT, false, true>(c, P.psites, 1u, part, SPLIT, planes,
+            U = sweep_colour_planes<L, SPLIT, false, true>(c, P.psites, 1u, part, planes, pr,
                                                            lane);
           else if (fast)
-            sweep_colour_planes<L, SPLIT, true, false>(c, P.psites, colour, part, SPLIT, planes,
+            sweep_colour_planes<L, SPLIT, true, false>(c, P.psites, colour, part, planes, pr,
                                                        lane);
           else
-            sweep_colour_planes<L, SPLIT, false, false>(c, P.psites, colour, part, SPLIT, planes,
+            sweep_colour_planes<L, SPLIT, false, false>(c, P.psites, colour, part, planes, pr,
                                                         lane);
         }
       }
@@ -1839,7 +1872,7 @@ void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t 
   // or the +-J plane areas (one per wave; the reduction area lies over them)
   const size_t after = model == kModelGauss16
                            ? 4 * 64 * split + (size_t)(kGaussDEMax + 1) * 8
-                           : std::max((size_t)plane_words(L, split) * 4 * split, (size_t)4 * 64 * split);
+                           : std::max((size_t)kPlaneAreaBytes * split, (size_t)4 * 64 * split);
   const size_t lds = (size_t)L * L * L * 8 + after;
   if (model == kModelGauss16) {
     if (split == 8)
