@@ -136,19 +136,22 @@ def event_pairs(n):
 
 
 def run_steps(pam, J, w, n_steps, seed0, sweeps=None, stats=None, anneals=None):
-    """n_steps temperature steps, each one pa_anneal_step call (step choice,
-    resample, sweeps, observables, one synchronisation); a new population at
-    beta = 0 whenever beta_max is hit.  sweeps (list, optional) receives
-    (sweep launch ms, R~) per step: the library brackets each sweep launch with
-    HIP events on the population's stream (PA_FLAG_TIME_SWEEPS); anneals (list,
-    optional) receives the step count of every anneal completed."""
+    """n_steps temperature steps of the constant-culling anneal (step choice,
+    resample, sweeps, observables), taken with pa_anneal_run: many steps per
+    call, one synchronisation per step, the family sums of one step computed
+    on the device while the host chooses the next; a new population at beta = 0
+    whenever beta_max is hit.  sweeps (list, optional) receives (sweep launch
+    ms, R~) per step: the library brackets each sweep launch with HIP events on
+    the population's stream (PA_FLAG_TIME_SWEEPS); anneals (list, optional)
+    receives the step count of every anneal completed."""
     attempts = 0
     pop = None
     gen = 0
     in_anneal = 0
     flags = pam.PA_FLAG_TIME_SWEEPS if sweeps is not None else 0
     N = w["L"] ** 3
-    for _ in range(n_steps):
+    left = n_steps
+    while left > 0:
         if pop is None or pop_beta >= w["beta_max"]:
             if pop is not None:
                 pop.close()
@@ -159,14 +162,16 @@ def run_steps(pam, J, w, n_steps, seed0, sweeps=None, stats=None, anneals=None):
             pop_beta = 0.0
             in_anneal = 0
             gen += 1
-        b, obs = pop.anneal_step(w["eps"], w["beta_max"], w["n_sweeps"])
-        attempts += w["n_sweeps"] * N * obs["R_tilde"]
-        if sweeps is not None:
-            sweeps.append((obs["sweep_ms"], obs["R_tilde"]))
-        pop_beta = b
-        in_anneal += 1
-        if stats is not None:
-            stats.append((b, obs["R_tilde"], obs["rho_t"], obs["beta_F"]))
+        chunk = pop.anneal_run(w["eps"], w["beta_max"], w["n_sweeps"], left)
+        for obs in chunk:
+            attempts += w["n_sweeps"] * N * obs["R_tilde"]
+            if sweeps is not None:
+                sweeps.append((obs["sweep_ms"], obs["R_tilde"]))
+            if stats is not None:
+                stats.append((obs["beta"], obs["R_tilde"], obs["rho_t"], obs["beta_F"]))
+        pop_beta = chunk[-1]["beta"]
+        in_anneal += len(chunk)
+        left -= len(chunk)
     if pop is not None:
         pop.close()
         if anneals is not None and pop_beta >= w["beta_max"]:
@@ -182,11 +187,10 @@ def whole_anneal(pam, J, w, seed):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pop = pam.Population(w["L"], w["R"], J, seed, layout=w["layout"], model=w["model"])
-    b, steps, attempts = 0.0, 0, 0
-    while b < w["beta_max"]:
-        b, obs = pop.anneal_step(w["eps"], w["beta_max"], w["n_sweeps"])
-        attempts += w["n_sweeps"] * w["L"] ** 3 * obs["R_tilde"]
-        steps += 1
+    chunk = pop.anneal_run(w["eps"], w["beta_max"], w["n_sweeps"], 100000)
+    steps = len(chunk)
+    attempts = sum(w["n_sweeps"] * w["L"] ** 3 * o["R_tilde"] for o in chunk)
+    obs = chunk[-1]
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     out = {"steps": steps, "seconds": round(t, 4), "attempts": attempts,

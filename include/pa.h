@@ -172,6 +172,19 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out);
 int pa_anneal_step(pa_instance* in, double eps_target, double beta_max, uint32_t n_sweeps,
                    double* beta_next, pa_obs* out);
 
+/* Up to max_steps steps of the constant-culling anneal (Sec. II loop with the
+ * Sec. III.C step choice, target eps_target >= 0), stopping when beta_max is
+ * reached: each step is exactly pa_anneal_step(in, eps_target, beta_max,
+ * n_sweeps, ...), bit for bit.  For +-J populations the steps are queued so
+ * that the device computes one step's family sums while the host chooses the
+ * next step, with one synchronisation per step.  obs (nullable, max_steps
+ * entries) receives each step's scalars; *steps_done the number of steps
+ * taken.  On an error (PA_ECAPACITY, PA_ESCHEDULE, ...) the steps before it
+ * stand and *steps_done counts them; PA_ECAPACITY leaves the population as it
+ * was after the last of them. */
+int pa_anneal_run(pa_instance* in, double eps_target, double beta_max, uint32_t n_sweeps,
+                  uint32_t max_steps, pa_obs* obs, uint32_t* steps_done);
+
 /* Constant-culling step (Sec. III.C): the beta_next in (beta, beta_max] whose
  * culling fraction eps = sum_{tau<1}(1 - tau) / R is eps_target, by 64
  * bisection halvings on [0, beta_max - beta] (mid = lo + (hi - lo)/2) keeping

@@ -133,6 +133,8 @@ def lib():
         "pa_debug_inject": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32]),
         "pa_anneal_step": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
                                           _P(ctypes.c_double), _P(pa_obs)]),
+        "pa_anneal_run": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+                                         ctypes.c_uint32, _vp, _P(ctypes.c_uint32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -149,7 +151,7 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
             "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset", "pa_probe_scratch_bytes",
             "pa_probe_ceilings", "pa_make_couplings_pm", "pa_autotune_set",
-            "pa_link_overlap_hist", "pa_debug_inject", "pa_anneal_step"]
+            "pa_link_overlap_hist", "pa_debug_inject", "pa_anneal_step", "pa_anneal_run"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -200,6 +202,23 @@ def pa_anneal_step(handle: int, eps_target: float, beta_max: float, n_sweeps: in
     _check(lib().pa_anneal_step(handle, float(eps_target), float(beta_max), int(n_sweeps),
                                 ctypes.byref(b), ctypes.byref(o)), "pa_anneal_step")
     return b.value, o.as_dict()
+
+
+def pa_anneal_run(handle: int, eps_target: float, beta_max: float, n_sweeps: int,
+                  max_steps: int):
+    """-> list of observables dicts, one per step taken (at most max_steps;
+    fewer when beta_max is reached).  A failing step raises PAError after the
+    steps before it have been taken."""
+    obs = (pa_obs * max(int(max_steps), 1))()
+    done = ctypes.c_uint32(0)
+    rc = lib().pa_anneal_run(handle, float(eps_target), float(beta_max), int(n_sweeps),
+                             int(max_steps), ctypes.cast(obs, _vp), ctypes.byref(done))
+    out = [obs[k].as_dict() for k in range(done.value)]
+    if rc != PA_OK:
+        err = PAError(rc, "pa_anneal_run")
+        err.steps = out
+        raise err
+    return out
 
 
 def pa_observables(handle: int) -> dict:
@@ -421,6 +440,11 @@ class Population:
         """One constant-culling step (choose beta, resample, sweep, measure) with
         one synchronisation -> (beta, observables)."""
         return pa_anneal_step(self.handle, eps_target, beta_max, n_sweeps)
+
+    def anneal_run(self, eps_target: float, beta_max: float, n_sweeps: int, max_steps: int):
+        """Up to max_steps constant-culling steps (stops at beta_max) in one call
+        -> list of observables dicts."""
+        return pa_anneal_run(self.handle, eps_target, beta_max, n_sweeps, max_steps)
 
     def step_to(self, beta_next: float, n_sweeps: int) -> dict:
         """One step to the given beta (resample, sweep, measure) -> observables."""

@@ -86,9 +86,12 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.off_bsum = take((size_t)l.n_blocks * 4);
   l.off_boff = take((size_t)l.n_blocks * 4);
   l.off_bcull = take((size_t)l.n_blocks * 4);
-  l.off_hist = take((size_t)l.n_levels * 4);
-  l.off_fl = take((size_t)l.n_levels * 4);
-  l.off_T = take((size_t)l.n_levels * 8);
+  // the histogram and the device scalars side by side: one copy brings both
+  // to the host after a step (PA_MODEL_PM, whose histogram covers every level)
+  l.hist_bytes = ((size_t)l.n_levels * 4 + 63) / 64 * 64;
+  l.off_hist = take(l.hist_bytes + sizeof(DevScalars));
+  l.off_sc = l.off_hist + l.hist_bytes;
+  l.off_table = take((size_t)l.n_levels * sizeof(pa::TableEntry));
   l.off_sites = take((size_t)l.N * sizeof(SiteEntry));
   l.off_psites = take((size_t)l.N * sizeof(pa::PlaneSite));
   l.off_cm = take((size_t)l.N * 2);
@@ -98,7 +101,6 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.off_ovl = take(65 * 8);
   l.off_lovl = take((size_t)(3 * l.N + 1) * 8);
   l.off_lpart = take((size_t)pa::kLinkCopies * (3 * l.N + 1) * 4);
-  l.off_sc = take(sizeof(DevScalars));
   l.off_pops = take(2 * sizeof(DevPop));
   l.off_meta = take(sizeof(MetaU32));
   l.total = o;
@@ -203,7 +205,7 @@ struct Table {
 // eps R = sum over occupied levels with tau_j < 1 of h_j (1 - tau_j) (Sec.
 // III.C) is summed in the same pass, as pa_choose_beta evaluates it.
 Table resample_table(const uint32_t* h, uint32_t n_levels, double unit, int64_t E_lo, uint32_t R,
-                     uint32_t R_tilde, double dbeta, uint32_t* fl, uint64_t* T) {
+                     uint32_t R_tilde, double dbeta, pa::TableEntry* tab) {
   Table t;
   for (uint32_t j = 0; j < n_levels; ++j)
     if (h[j] > 0) {
@@ -227,8 +229,8 @@ Table resample_table(const uint32_t* h, uint32_t n_levels, double unit, int64_t 
     const double tau = ((double)R * w[j]) / S;
     const uint64_t f = (uint64_t)std::floor(tau);
     const double fr = tau - (double)f;
-    fl[j] = (uint32_t)f;
-    T[j] = (uint64_t)std::ceil(std::ldexp(fr, 53));
+    tab[j].fl = (uint32_t)f;
+    tab[j].T = (uint64_t)std::ceil(std::ldexp(fr, 53));
     if (tau < 1.0) acc = acc + (double)h[j] * (1.0 - tau);
   }
   t.S = S;
@@ -358,8 +360,15 @@ int fetch_hist(pa_instance* in, bool with_family) {
   if (with_family)
     PA_HIP(in, pa::launch_family(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), false,
                                  in->stream));
-  PA_HIP(in, hipMemcpyAsync(in->h_hist, P.hist, (size_t)n * 4, hipMemcpyDeviceToHost, in->stream));
-  PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
+  if (P.model == pa::kModelGauss16) {
+    PA_HIP(in, hipMemcpyAsync(in->h_hist, P.hist, (size_t)n * 4, hipMemcpyDeviceToHost,
+                              in->stream));
+    PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
+                              in->stream));
+  } else {  // the scalars follow the histogram in the workspace and in the staging
+    PA_HIP(in, hipMemcpyAsync(in->h_hist, P.hist, in->lay.hist_bytes + sizeof(DevScalars),
+                              hipMemcpyDeviceToHost, in->stream));
+  }
   PA_HIP(in, hipStreamSynchronize(in->stream));
   PA_HIP(in, read_sweep_time(in));
   if (in->h_sc->err == 2) return dev_fail(in);
@@ -503,21 +512,19 @@ int choose_from_hist(pa_instance* in, double eps_target, double beta_max, double
 // (Sec. II, Eqs. 1-2): the FP64 table on the host, its occupied range
 // uploaded, then copy counts, scan (with the capacity check) and the copy map
 // queued.  Nothing is synchronised.
-int queue_resample(pa_instance* in, double beta_next, Table* t) {
+int queue_resample(pa_instance* in, double beta_next, Table* t, uint32_t step_flags = 0) {
   const DevPop& P = in->dev;
   const double dbeta = beta_next - in->beta;
   const Levels lv = levels_of(in);
-  *t = resample_table(in->h_hist, lv.n, lv.unit, lv.E_lo, P.R, in->R_tilde, dbeta, in->h_fl,
-                      in->h_T);
+  *t = resample_table(in->h_hist, lv.n, lv.unit, lv.E_lo, P.R, in->R_tilde, dbeta, in->h_table);
   if (t->jmin < 0) return PA_ESTATE;  // empty population
   // only the occupied range is read by the copy counts
   const size_t j0 = (size_t)t->jmin, nj = (size_t)(t->jmax - t->jmin + 1);
-  PA_HIP(in, hipMemcpyAsync(P.table_fl + j0, in->h_fl + j0, nj * 4, hipMemcpyHostToDevice,
-                            in->stream));
-  PA_HIP(in, hipMemcpyAsync(P.table_T + j0, in->h_T + j0, nj * 8, hipMemcpyHostToDevice,
-                            in->stream));
+  PA_HIP(in, hipMemcpyAsync(P.table + j0, in->h_table + j0, nj * sizeof(pa::TableEntry),
+                            hipMemcpyHostToDevice, in->stream));
   pa::PopStep ps = plain_step(in->cur);
   ps.step = in->step + 1;
+  ps.flags = step_flags;
   const pa::BatchDev B = one_set(in, ps);
   PA_HIP(in, pa::launch_counts(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
   PA_HIP(in, pa::launch_scan(B, group_of(in, in->d_meta->perpop, 1), in->stream));
@@ -575,6 +582,186 @@ void fill_observables(pa_instance* in, pa_obs* out) {
   out->sweeps_done = in->sweeps;
   out->sum_lnQ = in->sum_lnQ;
   out->sweep_ms = in->last_sweep_ms;
+}
+
+// One step of the anneal queued for a +-J population: the resampling step to
+// `beta` (the scan clears the histogram and the family sum), the sweeps, the
+// new population's histogram, one copy of the histogram and the scalars
+// (event ev_step), the family sums and a copy of their total into staging slot
+// `slot` (event ev_fam[slot]).
+struct QueuedStep {
+  double beta;
+  Table t;
+  uint32_t R_old, n_sweeps, slot;
+};
+
+int queue_step_pm(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t slot, QueuedStep* q) {
+  const DevPop& P = in->dev;
+  q->beta = beta;
+  q->R_old = in->R_tilde;
+  q->n_sweeps = n_sweeps;
+  q->slot = slot;
+  int rc = queue_resample(in, beta, &q->t, pa::kStepHist);
+  if (rc) return rc;
+  pa::PopStep ps = plain_step(in->cur);
+  PA_HIP(in, set_thresholds(in, beta, &ps));
+  ps.t0 = (uint32_t)in->sweeps;
+  ps.n_sweeps = n_sweeps;
+  ps.gather = 1;
+  // leaves at once when the scan flagged an overflow
+  PA_HIP(in, launch_sweep_of(in, ps));
+  const pa::BatchDev B = one_set(in, plain_step(in->cur ^ 1u));
+  PA_HIP(in, pa::launch_hist(B, group_of(in, in->d_meta->hist, in->meta.hist[1]), P.n_levels,
+                             false, in->stream));
+  PA_HIP(in, hipMemcpyAsync(in->h_hist, P.hist, in->lay.hist_bytes + sizeof(DevScalars),
+                            hipMemcpyDeviceToHost, in->stream));
+  PA_HIP(in, hipEventRecord(in->ev_step, in->stream));
+  PA_HIP(in, pa::launch_family(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), false,
+                               in->stream));
+  PA_HIP(in, hipMemcpyAsync(in->h_eta2 + slot, &P.sc->sum_eta2, 8, hipMemcpyDeviceToHost,
+                            in->stream));
+  PA_HIP(in, hipEventRecord(in->ev_fam[slot], in->stream));
+  return PA_OK;
+}
+
+// Wait for the histogram and scalars of a queued step and take it over into
+// the host mirror (obs without the family sum, which finish_family adds).
+// PA_ECAPACITY: nothing after the scan ran; the population is as it was.
+int finish_step_pm(pa_instance* in, const QueuedStep& q, pa_obs* out) {
+  PA_HIP(in, hipEventSynchronize(in->ev_step));
+  PA_HIP(in, read_sweep_time(in));
+  if (in->h_sc->err == 2) return dev_fail(in);
+  if (in->h_sc->err) {
+    in->hist_valid = false;  // the scan cleared it for a sweep that did not run
+    return PA_ECAPACITY;
+  }
+  commit_resample(in, q.t, q.beta, q.R_old);
+  in->cur ^= 1u;
+  in->R_tilde = in->h_sc->R_tilde;
+  in->pending_gather = false;
+  in->hist_valid = true;
+  in->sweeps += q.n_sweeps;
+  if (out) fill_observables(in, out);
+  return PA_OK;
+}
+
+int finish_family(pa_instance* in, const QueuedStep& q, pa_obs* out) {
+  PA_HIP(in, hipEventSynchronize(in->ev_fam[q.slot]));
+  if (out) {
+    out->sum_eta2 = in->h_eta2[q.slot];
+    out->rho_t = (double)out->sum_eta2 / (double)in->dev.R;
+  }
+  return PA_OK;
+}
+
+// Up to max_steps steps of the anneal (Sec. II loop): with eps_target >= 0
+// the constant-culling step (Sec. III.C) to at most beta_max, stopping there;
+// otherwise one step to beta_fixed.  obs (nullable) receives each step's
+// scalars.  Every bit equals pa_choose_beta + pa_resample + pa_sweep +
+// pa_observables per step.  For +-J populations the work is queued so that
+// one synchronisation per step brings back the histogram, and the family sums
+// of a step run on the device while the host chooses the next step.
+int anneal_steps(pa_instance* in, double eps_target, double beta_max, double beta_fixed,
+                 uint32_t n_sweeps, uint32_t max_steps, pa_obs* obs, uint32_t* done) {
+  const bool adaptive = eps_target >= 0.0;
+  if (n_sweeps == 0 || in->sweeps + (uint64_t)n_sweeps * max_steps > 0xFFFFFFFFull)
+    return PA_EINVAL;
+  if (adaptive && (!std::isfinite(eps_target) || !std::isfinite(beta_max) ||
+                   !(beta_max > in->beta)))
+    return PA_EINVAL;
+  if (!adaptive && (!std::isfinite(beta_fixed) || !(beta_fixed >= 0.0))) return PA_EINVAL;
+  const bool fused = in->dev.model == pa::kModelPm && !(in->flags & PA_FLAG_CHECK_ENERGY);
+  if (!fused) {
+    // the separate calls, step by step
+    for (uint32_t k = 0; k < max_steps; ++k) {
+      if (adaptive && !(in->beta < beta_max)) break;
+      double b = beta_fixed;
+      int rc = check_energy(in);
+      if (rc) return rc;
+      if (!in->hist_valid || in->pending_gather) {
+        rc = fetch_hist(in, false);
+        if (rc) return rc;
+      }
+      if (adaptive) {
+        rc = choose_from_hist(in, eps_target, beta_max, &b);
+        if (rc) return rc;
+      }
+      Table t;
+      rc = queue_resample(in, b, &t);
+      if (rc) return rc;
+      pa::PopStep ps = plain_step(in->cur);
+      PA_HIP(in, set_thresholds(in, b, &ps));
+      ps.t0 = (uint32_t)in->sweeps;
+      ps.n_sweeps = n_sweeps;
+      ps.gather = 1;
+      PA_HIP(in, launch_sweep_of(in, ps));
+      const uint32_t old_cur = in->cur, R_old = in->R_tilde;
+      if (in->dev.model == pa::kModelGauss16) {
+        // the energy window of the new population is found on the device
+        // and read first; an unwritten buffer has none, so the overflow
+        // check comes first
+        PA_HIP(in, hipMemcpyAsync(in->h_sc, in->dev.sc, sizeof(DevScalars),
+                                  hipMemcpyDeviceToHost, in->stream));
+        PA_HIP(in, hipStreamSynchronize(in->stream));
+        if (in->h_sc->err == 2) return dev_fail(in);
+        if (in->h_sc->err) {
+          in->sweep_timed = false;
+          return PA_ECAPACITY;  // nothing after the scan ran: the population is as it was
+        }
+      }
+      in->cur ^= 1u;
+      rc = fetch_hist(in, true);  // histogram and family sums: the synchronisation
+      if (rc) return rc;
+      if (in->h_sc->err) {
+        in->cur = old_cur;
+        in->R_tilde = R_old;
+        in->hist_valid = false;
+        return PA_ECAPACITY;
+      }
+      commit_resample(in, t, b, R_old);
+      in->R_tilde = in->h_sc->R_tilde;
+      in->pending_gather = false;
+      in->hist_valid = true;
+      in->sweeps += n_sweeps;
+      rc = check_energy(in);
+      if (rc) return rc;
+      if (obs) fill_observables(in, obs + k);
+      *done = k + 1;
+    }
+    return PA_OK;
+  }
+  if (!in->hist_valid || in->pending_gather) {
+    const int rc = fetch_hist(in, false);
+    if (rc) return rc;
+  }
+  double b = beta_fixed;
+  if (adaptive) {
+    const int rc = choose_from_hist(in, eps_target, beta_max, &b);
+    if (rc) return rc;
+  }
+  QueuedStep q[2];
+  int rc = queue_step_pm(in, b, n_sweeps, 0, &q[0]);
+  if (rc) return rc;
+  for (uint32_t k = 0;; ++k) {
+    const QueuedStep& cur = q[k & 1];
+    pa_obs* o = obs ? obs + k : nullptr;
+    rc = finish_step_pm(in, cur, o);
+    if (rc) {
+      (void)hipStreamSynchronize(in->stream);  // let the queued family sums finish
+      return rc;
+    }
+    *done = k + 1;
+    // the next step is chosen and queued while this one's family sums run
+    const bool more = k + 1 < max_steps && adaptive && in->beta < beta_max;
+    if (more) {
+      rc = choose_from_hist(in, eps_target, beta_max, &b);
+      if (rc == PA_OK) rc = queue_step_pm(in, b, n_sweeps, (k + 1) & 1, &q[(k + 1) & 1]);
+    }
+    const int rc_fam = finish_family(in, cur, o);
+    if (rc) return rc;
+    if (rc_fam) return rc_fam;
+    if (!more) return PA_OK;
+  }
 }
 
 }  // namespace
@@ -660,8 +847,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   P.block_offsets = reinterpret_cast<uint32_t*>(w + l.off_boff);
   P.block_culled = reinterpret_cast<uint32_t*>(w + l.off_bcull);
   P.hist = reinterpret_cast<uint32_t*>(w + l.off_hist);
-  P.table_fl = reinterpret_cast<uint32_t*>(w + l.off_fl);
-  P.table_T = reinterpret_cast<unsigned long long*>(w + l.off_T);
+  P.table = reinterpret_cast<pa::TableEntry*>(w + l.off_table);
   P.sites = reinterpret_cast<const SiteEntry*>(w + l.off_sites);
   P.psites = reinterpret_cast<const pa::PlaneSite*>(w + l.off_psites);
   P.cm_of_site = reinterpret_cast<const uint16_t*>(w + l.off_cm);
@@ -690,14 +876,22 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
     pa_free(in);
     return rc;
   };
-  if (hipHostMalloc(reinterpret_cast<void**>(&in->h_hist), (size_t)l.n_levels * 4) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&in->h_fl), (size_t)l.n_levels * 4) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&in->h_T), (size_t)l.n_levels * 8) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&in->h_sc), sizeof(DevScalars)) != hipSuccess ||
+  // histogram and scalars in one pinned block, laid out as in the workspace
+  if (hipHostMalloc(reinterpret_cast<void**>(&in->h_hist), l.hist_bytes + sizeof(DevScalars)) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&in->h_table),
+                    (size_t)l.n_levels * sizeof(pa::TableEntry)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_ovl), 65 * 8) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_lovl), (size_t)(3 * l.N + 1) * 8) !=
           hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_meta), sizeof(MetaU32)) != hipSuccess)
+    return fail(PA_EDEVICE);
+  in->h_sc = reinterpret_cast<DevScalars*>(reinterpret_cast<uint8_t*>(in->h_hist) + l.hist_bytes);
+  if (hipHostMalloc(reinterpret_cast<void**>(&in->h_eta2), 2 * sizeof(unsigned long long)) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&in->ev_step, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&in->ev_fam[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&in->ev_fam[1], hipEventDisableTiming) != hipSuccess)
     return fail(PA_EDEVICE);
   if (l.model == PA_MODEL_GAUSS16 &&
       (hipHostMalloc(reinterpret_cast<void**>(&in->h_gthr), (size_t)(pa::kGaussDEMax + 1) * 8) !=
@@ -756,9 +950,7 @@ int pa_free(pa_instance* in) {
   if (!in) return PA_EINVAL;
   (void)hipStreamSynchronize(in->stream);
   if (in->h_hist) (void)hipHostFree(in->h_hist);
-  if (in->h_fl) (void)hipHostFree(in->h_fl);
-  if (in->h_T) (void)hipHostFree(in->h_T);
-  if (in->h_sc) (void)hipHostFree(in->h_sc);
+  if (in->h_table) (void)hipHostFree(in->h_table);
   if (in->h_ovl) (void)hipHostFree(in->h_ovl);
   if (in->h_lovl) (void)hipHostFree(in->h_lovl);
   if (in->h_meta) (void)hipHostFree(in->h_meta);
@@ -766,6 +958,9 @@ int pa_free(pa_instance* in) {
   if (in->gthr_copied) (void)hipEventDestroy(in->gthr_copied);
   for (hipEvent_t e : in->sweep_ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {in->ev_step, in->ev_fam[0], in->ev_fam[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (in->h_eta2) (void)hipHostFree(in->h_eta2);
   delete in;
   return PA_OK;
 }
@@ -848,67 +1043,20 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
 int pa_anneal_step(pa_instance* in, double eps_target, double beta_max, uint32_t n_sweeps,
                    double* beta_next, pa_obs* out) {
   if (int rc0 = enter(in)) return rc0;
-  if (!beta_next || n_sweeps == 0 || in->sweeps + n_sweeps > 0xFFFFFFFFull) return PA_EINVAL;
-  const bool adaptive = eps_target >= 0.0;
-  if (adaptive && (!std::isfinite(eps_target) || !std::isfinite(beta_max) ||
-                   !(beta_max > in->beta)))
-    return PA_EINVAL;
-  if (!adaptive && (!std::isfinite(*beta_next) || !(*beta_next >= 0.0))) return PA_EINVAL;
-  int rc = check_energy(in);
-  if (rc) return rc;
-  if (!in->hist_valid || in->pending_gather) {
-    rc = fetch_hist(in, false);
-    if (rc) return rc;
-  }
-  double b = *beta_next;
-  if (adaptive) {
-    rc = choose_from_hist(in, eps_target, beta_max, &b);
-    if (rc) return rc;
-  }
-  Table t;
-  rc = queue_resample(in, b, &t);
-  if (rc) return rc;
-  // the copy and the sweeps, queued behind the capacity check: on an
-  // overflow the scan has flagged it and the sweep kernel leaves at once
-  pa::PopStep ps = plain_step(in->cur);
-  PA_HIP(in, set_thresholds(in, b, &ps));
-  ps.t0 = (uint32_t)in->sweeps;
-  ps.n_sweeps = n_sweeps;
-  ps.gather = 1;
-  PA_HIP(in, launch_sweep_of(in, ps));
-  const uint32_t old_cur = in->cur, R_old = in->R_tilde;
-  if (in->dev.model == pa::kModelGauss16) {
-    // the energy window of the new population is found on the device and
-    // read first; an unwritten buffer has none, so the overflow check comes first
-    PA_HIP(in, hipMemcpyAsync(in->h_sc, in->dev.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
-                              in->stream));
-    PA_HIP(in, hipStreamSynchronize(in->stream));
-    if (in->h_sc->err == 2) return dev_fail(in);
-    if (in->h_sc->err) {
-      in->sweep_timed = false;
-      return PA_ECAPACITY;  // nothing after the scan ran: the population is as it was
-    }
-  }
-  in->cur ^= 1u;
-  // histogram and family sums of the new population: the one synchronisation
-  rc = fetch_hist(in, true);
-  if (rc) return rc;
-  if (in->h_sc->err) {  // nothing after the scan ran: the population is as it was
-    in->cur = old_cur;
-    in->R_tilde = R_old;
-    in->hist_valid = false;
-    return PA_ECAPACITY;
-  }
-  commit_resample(in, t, b, R_old);
-  in->R_tilde = in->h_sc->R_tilde;
-  in->pending_gather = false;
-  in->hist_valid = true;
-  in->sweeps += n_sweeps;
-  rc = check_energy(in);
-  if (rc) return rc;
-  *beta_next = b;
-  if (out) fill_observables(in, out);
-  return PA_OK;
+  if (!beta_next) return PA_EINVAL;
+  uint32_t done = 0;
+  const int rc = anneal_steps(in, eps_target, beta_max, *beta_next, n_sweeps, 1, out, &done);
+  if (rc == PA_OK) *beta_next = in->beta;
+  return rc;
+}
+
+int pa_anneal_run(pa_instance* in, double eps_target, double beta_max, uint32_t n_sweeps,
+                  uint32_t max_steps, pa_obs* obs, uint32_t* steps_done) {
+  if (int rc0 = enter(in)) return rc0;
+  if (!steps_done || !(eps_target >= 0.0)) return PA_EINVAL;
+  *steps_done = 0;
+  if (max_steps == 0) return PA_OK;
+  return anneal_steps(in, eps_target, beta_max, 0.0, n_sweeps, max_steps, obs, steps_done);
 }
 
 int pa_choose_beta(pa_instance* in, double eps_target, double beta_max, double* beta_next) {

@@ -32,8 +32,9 @@ struct MetaU32 {
 struct Layout {
   uint32_t L, N, R, cap_limit, capacity, layout, n_levels, n_blocks, model, rowk_stride;
   size_t spins_bytes;
+  size_t hist_bytes;  // the histogram's share of its block (n_levels words, 64-byte multiple)
   size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
-      off_bcull, off_hist, off_fl, off_T, off_sites, off_psites, off_cm, off_rowj, off_rowk, off_gthr, off_ovl,
+      off_bcull, off_hist, off_table, off_sites, off_psites, off_cm, off_rowj, off_rowk, off_gthr, off_ovl,
       off_lovl, off_lpart, off_sc, off_pops, off_meta;
   size_t total;
 };
@@ -100,8 +101,7 @@ struct pa_instance {
   bool failed = false;
   // pinned staging
   uint32_t* h_hist = nullptr;
-  uint32_t* h_fl = nullptr;
-  uint64_t* h_T = nullptr;
+  pa::TableEntry* h_table = nullptr;  // staging of the resampling table
   pa::DevScalars* h_sc = nullptr;
   unsigned long long* h_ovl = nullptr;
   unsigned long long* h_lovl = nullptr;  // 3N + 1 link-overlap counts
@@ -113,6 +113,11 @@ struct pa_instance {
   hipEvent_t sweep_ev[2] = {nullptr, nullptr};  // PA_FLAG_TIME_SWEEPS: around the last sweep
   bool sweep_timed = false;           // the events bracket a launch not yet read
   double last_sweep_ms = 0.0;
+  // pipelined steps (pa_anneal_run): the histogram copy of a queued step, and
+  // the family sums of two steps in flight
+  hipEvent_t ev_step = nullptr;
+  hipEvent_t ev_fam[2] = {nullptr, nullptr};
+  unsigned long long* h_eta2 = nullptr;  // pinned, two slots
   int64_t fail_countdown = -1;        // PA_INJECT_FAIL_AFTER: calls left before the failure
 };
 

@@ -87,6 +87,16 @@ struct DevScalars {
 };
 static_assert(sizeof(DevScalars) == 64, "DevScalars is 64 bytes");
 
+// One energy level of the resampling table (Sec. II copy rule): a replica
+// at that level gets fl copies, and one more iff a 53-bit draw is below T.
+// The two live together so that the table goes to the device in one copy.
+struct TableEntry {
+  unsigned long long T;  // ceil(frac(tau_j) 2^53)
+  uint32_t fl;           // floor(tau_j)
+  uint32_t pad;
+};
+static_assert(sizeof(TableEntry) == 16, "TableEntry is 16 bytes");
+
 // Device pointers of one population (all inside its workspace).
 struct DevPop {
   uint32_t L, N, R, capacity;   // capacity: slots per buffer, a multiple of kBlockCounts
@@ -105,8 +115,7 @@ struct DevPop {
   uint32_t* block_offsets;
   uint32_t* block_culled;
   uint32_t* hist;               // n_levels
-  uint32_t* table_fl;           // n_levels: floor(tau_j)
-  unsigned long long* table_T;  // n_levels: ceil(frac(tau_j) 2^53)
+  struct TableEntry* table;     // n_levels: the resampling table by energy level
   const SiteEntry* sites;       // N entries, colour-major
   const PlaneSite* psites;      // N entries, colour-major (phase 1 of the +-J pass)
   const uint16_t* cm_of_site;   // N entries: lexicographic site -> colour-major index
@@ -133,11 +142,15 @@ struct PopStep {
   uint32_t gather;            // 1: the sweep applies the pending copy step (size R_next)
   uint32_t cur;               // buffer holding the population at the start of the launch
   uint32_t step;              // resampling step index k (copy-count Philox counter)
-  uint32_t flags;             // kStepSticky: an overflow marks the population dead
+  uint32_t flags;             // kStepSticky: an overflow marks the population dead; kStepHist
   uint32_t pad[2];
 };
 static_assert(sizeof(PopStep) == 64, "PopStep is 64 bytes");
 constexpr uint32_t kStepSticky = 1u;
+// kStepHist (+-J): the scan also clears the energy histogram and the family
+// sum, for the histogram and family kernels that follow the sweep (no
+// separate clearing launch).
+constexpr uint32_t kStepHist = 2u;
 
 // What a batch records for one population at one temperature step.
 struct StepRecord {

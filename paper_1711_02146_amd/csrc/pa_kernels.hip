@@ -1137,16 +1137,16 @@ __global__ __launch_bounds__(kTableBlock) void k_table(BatchDev B, Group G) {
   if (jmin < 0) return;
   for (uint32_t j = threadIdx.x; j < nl; j += kTableBlock) {
     if ((int)j < jmin) {
-      P.table_fl[j] = 0;
-      P.table_T[j] = 0;
+      P.table[j].fl = 0;
+      P.table[j].T = 0;
       continue;
     }
     const double w = sp.erow[j - (uint32_t)jmin];
     const double tau = __ddiv_rn(__dmul_rn(R, w), S);
     const double f = floor(tau);
     const double fr = __dsub_rn(tau, f);
-    P.table_fl[j] = (uint32_t)f;
-    P.table_T[j] = (unsigned long long)ceil(ldexp(fr, 53));
+    P.table[j].fl = (uint32_t)f;
+    P.table[j].T = (unsigned long long)ceil(ldexp(fr, 53));
   }
 }
 
@@ -1212,7 +1212,8 @@ __global__ __launch_bounds__(kBlockCounts) void k_counts(BatchDev B, Group G) {
     const uint32_t u = min(lev, P.n_levels - 1);
     const Words4 w = philox10(i, sp.step, 0u, kTagRes, (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
     const unsigned long long u53 = ((unsigned long long)w.w[0] << 21) | (w.w[1] >> 11);
-    n = P.table_fl[u] + (u53 < P.table_T[u] ? 1u : 0u);
+    const TableEntry te = P.table[u];
+    n = te.fl + (u53 < te.T ? 1u : 0u);
     P.counts[i] = n;
     culled = n == 0;
   }
@@ -1249,6 +1250,10 @@ __global__ __launch_bounds__(1024) void k_scan(BatchDev B, Group G) {
   }
   const unsigned long long ctot =
       block_sum<1024, unsigned long long>((unsigned long long)cull, cull_scratch);
+  if (sp.flags & kStepHist) {  // for the histogram and family sums after the sweep
+    for (uint32_t j = threadIdx.x; j < P.n_levels; j += 1024) P.hist[j] = 0;
+    if (threadIdx.x == 0) P.sc->sum_eta2 = 0;
+  }
   if (threadIdx.x == 0) {
     const bool over = total > P.cap_limit;
     P.sc->R_next = total;

@@ -257,3 +257,63 @@ def test_anneal_step_overflow_keeps_population(pam, model):
         np.testing.assert_array_equal(x, y)
     assert g.observables() == obs_before
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# pa_anneal_run: many steps per call, pipelined
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("layout", ["int8", "bitpack64"])
+@pytest.mark.parametrize("model", ["pm", "gauss16"])
+def test_anneal_run_equals_separate_calls_to_the_end(pam, layout, model):
+    """A whole anneal to beta = 5 in chunks of steps: every step's scalars,
+    and the final population, equal the separate calls'."""
+    say("anneal run", layout, model)
+    L, R, seed = 6, 3000, 0x5EED1601
+    J = (pa_inputs.couplings_pm(L, 14) if model == "pm" else pa_inputs.couplings_gauss16(L, 14))
+    a = pam.Population(L, R, J, seed, layout=layout, model=model)
+    b = pam.Population(L, R, J, seed, layout=layout, model=model, flags=pam.PA_FLAG_TIME_SWEEPS)
+    ref = []
+    while not ref or ref[-1]["beta"] < 5.0:
+        ref += _anneal(a, 1, n_sweeps=3)
+    got = []
+    while not got or got[-1]["beta"] < 5.0:
+        chunk = b.anneal_run(0.1, 5.0, 3, 17)
+        assert 1 <= len(chunk) <= 17
+        got += chunk
+    assert len(got) == len(ref)
+    for k, (x, y) in enumerate(zip(got, ref)):
+        assert x["sweep_ms"] > 0.0
+        x["sweep_ms"] = 0.0
+        assert x == y, k
+    with pytest.raises(pam.PAError) as e:
+        b.anneal_run(0.1, 5.0, 3, 4)  # beta_max reached: no step left
+    assert e.value.status == pam.PA_EINVAL
+    for x, y in zip(a.export_state(), b.export_state()):
+        np.testing.assert_array_equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_anneal_run_stops_at_an_overflow(pam):
+    """With capacity R some step overflows: the steps before it stand (equal
+    to the separate calls), the call reports PA_ECAPACITY, and the population
+    is as after the last step taken."""
+    say("anneal run overflow")
+    L, R = 4, 256
+    J = pa_inputs.couplings_pm(L, 18)
+    a = pam.Population(L, R, J, 9, capacity=R, layout="int8")
+    b = pam.Population(L, R, J, 9, capacity=R, layout="int8")
+    with pytest.raises(pam.PAError) as e:
+        b.anneal_run(0.3, 5.0, 2, 400)
+    assert e.value.status == pam.PA_ECAPACITY
+    taken = e.value.steps
+    ref = _anneal(a, len(taken), eps=0.3, n_sweeps=2)
+    assert taken == ref
+    with pytest.raises(pam.PAError) as e2:
+        _anneal(a, 1, eps=0.3, n_sweeps=2)
+    assert e2.value.status == pam.PA_ECAPACITY
+    for x, y in zip(a.export_state(), b.export_state()):
+        np.testing.assert_array_equal(x, y)
+    assert a.observables() == b.observables()
+    a.close()
+    b.close()
