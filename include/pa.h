@@ -214,6 +214,24 @@ int pa_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hi
  * hist_out; PA_ESTATE for an unusable instance.  Synchronises. */
 int pa_link_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_t* hist_out);
 
+/* pa_link_overlap_hist for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the partial and the final counts live in a fixed scratch array
+ * of the library in each GPU's memory (PA_NOALLOC_SCRATCH_BYTES, held from the
+ * first instance created on that GPU until the process ends), not in the
+ * workspace of instance a.  Same arguments, result and errors as
+ * pa_link_overlap_hist, and in addition: PA_ENOMEM when nbins exceeds
+ * PA_NOALLOC_MAX_BINS (the array holds the counts of lattices up to L = 12);
+ * PA_EINVAL unless both instances were created on the current device;
+ * PA_EDEVICE if the array's address could not be obtained.  Allocates
+ * nothing.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap in time on one GPU (from other host threads, on other streams) race
+ * and must not be made.  Synchronises. */
+#define PA_NOALLOC_MAX_BINS 5185u
+#define PA_NOALLOC_SCRATCH_BYTES (32u * PA_NOALLOC_MAX_BINS * 4u + PA_NOALLOC_MAX_BINS * 8u)
+int pa_link_overlap_hist_noalloc(pa_instance* a, pa_instance* b, uint32_t nbins,
+                                 uint64_t* hist_out);
+
 /* Copy the current population to the host in the canonical layout.
  * spins_host: R~ * N int8 (+1/-1), [replica][site]; U_host, family_host: R~
  * entries each (U_host: the energy word, for PA_MODEL_GAUSS16 the bits of the

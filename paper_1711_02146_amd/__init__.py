@@ -135,6 +135,7 @@ def lib():
                                           _P(ctypes.c_double), _P(pa_obs)]),
         "pa_anneal_run": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
                                          ctypes.c_uint32, _vp, _P(ctypes.c_uint32)]),
+        "pa_link_overlap_hist_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -151,7 +152,8 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_stepper_workspace_bytes", "pa_stepper_create", "pa_stepper_step",
             "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset", "pa_probe_scratch_bytes",
             "pa_probe_ceilings", "pa_make_couplings_pm", "pa_autotune_set",
-            "pa_link_overlap_hist", "pa_debug_inject", "pa_anneal_step", "pa_anneal_run"]
+            "pa_link_overlap_hist", "pa_debug_inject", "pa_anneal_step", "pa_anneal_run",
+            "pa_link_overlap_hist_noalloc"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -230,6 +232,16 @@ def pa_observables(handle: int) -> dict:
 def pa_overlap_hist(a: int, b: int, nbins: int = 65) -> np.ndarray:
     h = np.zeros(nbins, np.uint64)
     _check(lib().pa_overlap_hist(a, b, nbins, h.ctypes.data), "pa_overlap_hist")
+    return h
+
+
+PA_NOALLOC_MAX_BINS = 5185
+
+
+def pa_link_overlap_hist_noalloc(a: int, b: int, nbins: int) -> np.ndarray:
+    h = np.zeros(nbins, np.uint64)
+    _check(lib().pa_link_overlap_hist_noalloc(a, b, nbins, h.ctypes.data),
+           "pa_link_overlap_hist_noalloc")
     return h
 
 

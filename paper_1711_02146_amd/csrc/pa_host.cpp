@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -30,6 +31,14 @@ using pa::DevScalars;
 using pa::SiteEntry;
 
 using namespace pa_host;
+
+// Scratch of pa_link_overlap_hist_noalloc, one copy in each GPU's memory:
+// the kLinkCopies partial link-overlap histograms (u32, nbins apart), then the
+// final counts (u64).  In host code `scratch` is only a stand-in for the
+// symbol; its device address comes from hipGetSymbolAddress, once per device.
+static_assert(pa::kLinkCopies == 32, "PA_NOALLOC_SCRATCH_BYTES counts 32 partial histograms");
+constexpr size_t kScratchPartWords = (size_t)pa::kLinkCopies * PA_NOALLOC_MAX_BINS;
+static __device__ __align__(256) uint32_t scratch[PA_NOALLOC_SCRATCH_BYTES / 4];
 
 namespace {
 
@@ -305,6 +314,27 @@ struct Levels {
 Levels levels_of(const pa_instance* in) {
   if (in->dev.model == pa::kModelGauss16) return {in->n_win, 1.0 / 16.0, (int64_t)in->E_lo};
   return {in->dev.n_levels, 2.0, -(int64_t)(3 * in->dev.N / 2)};
+}
+
+// Device address of `scratch` per device, resolved at the first instance
+// created on that device (with the device current), kept for the process.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+
+void resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+    g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+}
+
+uint32_t* scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
 }
 
 int dev_fail(pa_instance* in) {
@@ -819,6 +849,11 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   if (!in) return PA_EINVAL;
   in->lay = l;
   in->flags = p->flags;
+  if (hipGetDevice(&in->device) != hipSuccess) {
+    delete in;
+    return PA_EDEVICE;
+  }
+  resolve_scratch(in->device);
   in->stream = static_cast<hipStream_t>(hip_stream);
   in->ws = static_cast<uint8_t*>(d_workspace);
   build_sites(l.L, J_host, &in->sites, &in->cm_of_site, &in->rowj);
@@ -1135,6 +1170,35 @@ int pa_link_overlap_hist(pa_instance* a, pa_instance* b, uint32_t nbins, uint64_
                                     a->dev.lovl_hist, a->stream));
   PA_HIP(a, hipMemcpyAsync(a->h_lovl, a->dev.lovl_hist, (size_t)nbins * 8, hipMemcpyDeviceToHost,
                            a->stream));
+  PA_HIP(a, hipStreamSynchronize(a->stream));
+  for (uint32_t i = 0; i < nbins; ++i) hist_out[i] = a->h_lovl[i];
+  return PA_OK;
+}
+
+int pa_link_overlap_hist_noalloc(pa_instance* a, pa_instance* b, uint32_t nbins,
+                                 uint64_t* hist_out) {
+  if (!usable(a) || !usable(b)) return PA_ESTATE;
+  if (int rc0 = enter(a)) return rc0;
+  if (int rc0 = enter(b)) return rc0;
+  if (!hist_out || a == b) return PA_EINVAL;
+  if (a->dev.L != b->dev.L || a->dev.layout != b->dev.layout) return PA_EINVAL;
+  if (nbins != 3 * a->dev.N + 1) return PA_EINVAL;
+  if (nbins > PA_NOALLOC_MAX_BINS) return PA_ENOMEM;  // beyond the fixed array
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return PA_EDEVICE;
+  if (dev != a->device || dev != b->device) return PA_EINVAL;
+  uint32_t* const part = scratch_of(dev);
+  if (!part) return PA_EDEVICE;
+  unsigned long long* const hist = reinterpret_cast<unsigned long long*>(part + kScratchPartWords);
+  int rc = materialize(a);
+  if (rc) return rc;
+  rc = materialize(b);
+  if (rc) return rc;
+  PA_HIP(b, hipStreamSynchronize(b->stream));
+  // the partial counts start at zero (the array keeps the last call's)
+  PA_HIP(a, pa::launch_fill_u32(part, 0u, (size_t)pa::kLinkCopies * nbins, a->stream));
+  PA_HIP(a, pa::launch_link_overlap(a->dev, b->dev, a->cur, b->cur, part, hist, a->stream));
+  PA_HIP(a, hipMemcpyAsync(a->h_lovl, hist, (size_t)nbins * 8, hipMemcpyDeviceToHost, a->stream));
   PA_HIP(a, hipStreamSynchronize(a->stream));
   for (uint32_t i = 0; i < nbins; ++i) hist_out[i] = a->h_lovl[i];
   return PA_OK;

@@ -110,6 +110,7 @@ struct pa_instance {
   hipEvent_t gthr_copied = nullptr;      // recorded after each copy out of h_gthr
   bool in_batch = false;
   uint32_t flags = 0;                 // PA_FLAG_* of the instance's parameters
+  int device = -1;                    // the device current at creation
   hipEvent_t sweep_ev[2] = {nullptr, nullptr};  // PA_FLAG_TIME_SWEEPS: around the last sweep
   bool sweep_timed = false;           // the events bracket a launch not yet read
   double last_sweep_ms = 0.0;
