@@ -240,14 +240,41 @@ def batch_instances(c):
     return out
 
 
-def batched_bench(pam, layout="bitpack64"):
+def size_class(R: int) -> int:
+    """floor(log2(ceil(R / 64))): the autotuner's size class of a population."""
+    return ((R + 63) // 64).bit_length() - 1
+
+
+def layout_tune(pam, L, R, J, seed, beta=0.3, n_sweeps=10, repeats=3):
+    """Time both spin layouts on (L, R) and record the faster for "auto"."""
+    t = pam.pa_autotune_layout(L, R, J, seed=seed, beta=beta, n_sweeps=n_sweeps, repeats=repeats)
+    return {"L": L, "R": R, "size_class": size_class(R), "layout": t["layout"],
+            "ms_int8": t["ms_int8"], "ms_bitpack64": t["ms_bitpack64"]}
+
+
+def batched_bench(pam, layout="auto"):
     """All instances in one batch (one graph replay per step) against back-to-back
-    single-instance runs of every sample_every-th instance, extrapolated."""
+    single-instance runs of every sample_every-th instance, extrapolated.  With
+    layout "auto" the layout autotuner first times both layouts on each
+    (L, size class) the instances fall into; every population then takes the
+    faster (batch and back-to-back runs alike)."""
     import numpy as np
     import torch
 
     c = BATCH
     insts = batch_instances(c)
+    tuned = []
+    if layout == "auto":
+        seen = set()
+        for (L, R, J, sa, _sb) in insts:
+            if (L, size_class(R)) not in seen:
+                seen.add((L, size_class(R)))
+                tuned.append(layout_tune(pam, L, R, J, sa, beta=1.0, n_sweeps=c["n_sweeps"]))
+    layouts_used = {}
+    for (L, R, *_r) in insts:
+        lay = pam.pa_layout_choice(L, R) if layout == "auto" else layout
+        layouts_used.setdefault(str(L), {}).setdefault(lay, 0)
+        layouts_used[str(L)][lay] += 1
     betas = pam.linear_schedule(c["beta_max"], c["n_temps"])
     n_steps = len(betas) - 1
     attempts = sum(2 * n_steps * c["n_sweeps"] * L ** 3 * R for (L, R, *_r) in insts)
@@ -312,6 +339,10 @@ def batched_bench(pam, layout="bitpack64"):
         "identical_on_sample": bool(identical),
         "capacity_failures": int(np.count_nonzero(status)),
         "layout": layout,
+        # instances per L in each layout, and the autotuner's timings per
+        # (L, size class): best sweep launch of n_sweeps sweeps at beta = 1
+        "layouts_per_L": layouts_used,
+        "layout_autotune": tuned,
     }
 
 
@@ -528,6 +559,7 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
                   "hbm_algorithmic_GBs": r["bytes_per_launch"] / (r["avg_ms"] * 1e-3) / 1e9},
         "sweep_fraction_of_wall": sum(r["sweep_ms"]) * 1e-3 / wall,
         "autotune": tune,
+        "layout_autotune": ltune,
         "anneals_completed": len(anneals),
         "steps_per_anneal": anneals,
         "beta_at_end": stats[-1][0] if stats else None,
@@ -708,8 +740,13 @@ def main():
     seed0 = pa_inputs.population_seed(3, 0, 0)
     print(f"# warmup {args.warmup} steps (and the sweep autotuner on this shape)", file=sys.stderr,
           flush=True)
-    tune = None
+    tune, ltune = None, None
     if not args.no_autotune:
+        # spin layout first (each timed in its faster sweep form), then the
+        # sweep form of the chosen layout on its own population
+        ltune = layout_tune(pam, w["L"], w["R"], J, seed0 + 998, n_sweeps=w["n_sweeps"],
+                            repeats=5)
+        w = dict(w, layout=ltune["layout"], name=w["name"].replace("bitpack64", ltune["layout"]))
         tp = pam.Population(w["L"], w["R"], J, seed0 + 999, layout=w["layout"])
         # tuned at beta = 0.3, the middle of the temperatures the timed steps cover
         tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=5)
@@ -728,10 +765,11 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    r = sweep_roofline(w, sweeps, OPS_PER_ATTEMPT, 1 / 8)
+    r = sweep_roofline(w, sweeps, OPS_PER_ATTEMPT, 1 / 8 if w["layout"] == "bitpack64" else 1.0)
     sweep_ms, avg_ms, avg_att, n_launch = r["sweep_ms"], r["avg_ms"], r["avg_att"], r["n_launch"]
     achieved_ops, bytes_per_launch = r["achieved_ops"], r["bytes_per_launch"]
-    profiled = PROFILE is not None and PROFILE["kernel_src_sha256"] == kernel_src_sha256()
+    profiled = (PROFILE is not None and PROFILE["kernel_src_sha256"] == kernel_src_sha256()
+                and w["layout"] == "bitpack64")
     traffic = PROFILE["bytes_per_launch"] if profiled else None
     sweep_rate = avg_att / (avg_ms * 1e-3)
     hbm_GBs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
@@ -753,7 +791,7 @@ def main():
                    "couplings": "+-J p=1/2", "seed_config": 3},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_sweep<bitpack64, L=10, +-J> (gather + 10 bit-sliced sweeps + energy)",
+            "kernel": f"k_sweep<{w['layout']}, L=10, +-J> (gather + 10 bit-sliced sweeps + energy)",
             "achieved": achieved_ops / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s",
@@ -789,6 +827,7 @@ def main():
         "sweep_fraction_of_wall": sum(sweep_ms) * 1e-3 / wall,
         "outside_sweep_us_per_step": 1e6 * (wall - sum(sweep_ms) * 1e-3) / args.steps,
         "autotune": tune,
+        "layout_autotune": ltune,
         "anneals_completed": len(anneals),
         "steps_per_anneal": anneals,
         "beta_at_end": stats[-1][0] if stats else None,

@@ -77,7 +77,11 @@ enum {
 };
 
 enum {
-  PA_LAYOUT_AUTO = 0,      /* library's choice: PA_LAYOUT_BITPACK64 */
+  PA_LAYOUT_AUTO = 0,      /* library's choice, resolved when the instance is created (and by
+                              pa_workspace_bytes): the layout the autotuner measured or was
+                              given for (model, L, size class of R) in this process
+                              (pa_autotune_layout, pa_autotune_set_layout), else
+                              PA_LAYOUT_BITPACK64.  pa_layout_choice tells which. */
   PA_LAYOUT_INT8 = 1,      /* one byte per spin: tiles of 64 replicas, [tile][site][64] */
   PA_LAYOUT_BITPACK64 = 2  /* one bit per spin: tiles of 64 replicas, [tile][site] u64,
                               bit (r & 63) of word [r >> 6][site] is replica r, 1 <=> s = -1 */
@@ -389,8 +393,54 @@ int pa_stepper_free(pa_stepper* s);
 int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t repeats,
                       uint32_t* split_out, float* ms_out);
 
-/* Forget every autotuned choice (back to the built-in rule). */
+/* Forget every autotuned choice, sweep forms and layouts (back to the built-in
+ * rules). */
 int pa_autotune_reset(void);
+
+/* Spin layout (Sec. II state of a replica; both layouts hold the same spins and
+ * every result is the same in either).  Which one sweeps faster depends on L,
+ * the population size and the device: the autotuner times both on a shape and
+ * PA_LAYOUT_AUTO then resolves to the faster for every population of that
+ * coupling model, L and size class (floor(log2(ceil(R / 64)))) created later
+ * in this process, single instances and the members of batches and steppers
+ * alike.  Because the choice is process-wide, a caller that sizes a workspace
+ * with PA_LAYOUT_AUTO and creates the instance later should resolve the layout
+ * once (pa_layout_choice) and pass it explicitly, or a choice recorded in
+ * between may make the workspace too small (PA_ENOMEM). */
+
+/* Device workspace pa_autotune_layout needs for params p (the larger of the
+ * two layouts' pa_workspace_bytes; p->layout and p->flags are ignored); 0 on bad
+ * params. */
+size_t pa_autotune_layout_workspace_bytes(const pa_params* p);
+
+/* Time both layouts on the shape of p: for each, create a population (p with
+ * that layout and flags 0; J_host as for pa_init_instance) in d_workspace (at
+ * least pa_autotune_layout_workspace_bytes(p) bytes, caller-owned, 256-byte
+ * aligned) on hip_stream, time its sweep forms as pa_autotune_sweep does at
+ * (beta, n_sweeps, repeats) and record the faster form for that layout, then
+ * free it.  The layout whose faster form is faster is recorded for
+ * (p->model, p->L, size class of p->R).  layout_out (nullable): the chosen
+ * PA_LAYOUT_*; ms_out (nullable, 2 floats): the best launch time of the int8
+ * and the bit-packed layout.  PA_EINVAL on bad params or arguments, PA_ENOMEM
+ * on a small workspace, PA_EDEVICE on a HIP error.  Synchronises; the workspace
+ * holds nothing of value afterwards. */
+int pa_autotune_layout(const pa_params* p, const int8_t* J_host, void* d_workspace,
+                       size_t ws_bytes, void* hip_stream, double beta, uint32_t n_sweeps,
+                       uint32_t repeats, uint32_t* layout_out, float* ms_out);
+
+/* The layout PA_LAYOUT_AUTO resolves to now for (model, L, size class of R):
+ * *layout_out = PA_LAYOUT_INT8 or PA_LAYOUT_BITPACK64.  Host only (no device
+ * call).  PA_EINVAL on an unknown model, L outside [4, 16] or odd, R = 0 or a
+ * null layout_out. */
+int pa_layout_choice(uint32_t model, uint32_t L, uint32_t R, uint32_t* layout_out);
+
+/* Pin the layout for a shape instead of timing it: populations of the coupling
+ * model, L and size class of `tiles` (floor(log2(tiles)), tiles = ceil(R / 64))
+ * created with PA_LAYOUT_AUTO get `layout` (PA_LAYOUT_INT8 or
+ * PA_LAYOUT_BITPACK64), until pa_autotune_reset or another choice for the shape.
+ * PA_EINVAL on an unknown model or layout, L outside [4, 16] or odd, or
+ * tiles = 0. */
+int pa_autotune_set_layout(uint32_t model, uint32_t L, uint64_t tiles, uint32_t layout);
 
 /* Pin the sweep form for a shape instead of timing it: launches of the
  * coupling model (PA_MODEL_*), spin layout (PA_LAYOUT_INT8 or

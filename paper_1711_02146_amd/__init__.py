@@ -136,6 +136,14 @@ def lib():
         "pa_anneal_run": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
                                          ctypes.c_uint32, _vp, _P(ctypes.c_uint32)]),
         "pa_link_overlap_hist_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp]),
+        "pa_autotune_layout_workspace_bytes": (ctypes.c_size_t, [_P(pa_params)]),
+        "pa_autotune_layout": (ctypes.c_int, [_P(pa_params), _vp, _vp, ctypes.c_size_t, _vp,
+                                              ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32,
+                                              _P(ctypes.c_uint32), _vp]),
+        "pa_layout_choice": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                            _P(ctypes.c_uint32)]),
+        "pa_autotune_set_layout": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32,
+                                                  ctypes.c_uint64, ctypes.c_uint32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -153,7 +161,8 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_stepper_free", "pa_autotune_sweep", "pa_autotune_reset", "pa_probe_scratch_bytes",
             "pa_probe_ceilings", "pa_make_couplings_pm", "pa_autotune_set",
             "pa_link_overlap_hist", "pa_debug_inject", "pa_anneal_step", "pa_anneal_run",
-            "pa_link_overlap_hist_noalloc"]
+            "pa_link_overlap_hist_noalloc", "pa_autotune_layout_workspace_bytes",
+            "pa_autotune_layout", "pa_layout_choice", "pa_autotune_set_layout"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -395,6 +404,50 @@ def pa_autotune_set(L: int, R_tilde: int, split: int, layout: str = "bitpack64",
            "pa_autotune_set")
 
 
+LAYOUT_NAMES = {PA_LAYOUT_INT8: "int8", PA_LAYOUT_BITPACK64: "bitpack64"}
+
+
+def pa_layout_choice(L: int, R: int, model: str = "pm") -> str:
+    """The concrete layout "auto" resolves to now for populations of this shape."""
+    out = ctypes.c_uint32(0)
+    _check(lib().pa_layout_choice(MODELS[model], int(L), int(R), ctypes.byref(out)),
+           "pa_layout_choice")
+    return LAYOUT_NAMES[out.value]
+
+
+def pa_autotune_set_layout(L: int, R: int, layout: str, model: str = "pm"):
+    """Pin the layout "auto" resolves to for populations of this shape."""
+    tiles = (int(R) + 63) // 64
+    _check(lib().pa_autotune_set_layout(MODELS[model], int(L), tiles, LAYOUTS[layout]),
+           "pa_autotune_set_layout")
+
+
+def pa_autotune_layout(L: int, R: int, J: np.ndarray, seed: int = 0, beta: float = 1.0,
+                       n_sweeps: int = 10, repeats: int = 3, model: str = "pm", capacity: int = 0,
+                       device=None, stream=None) -> dict:
+    """Time both spin layouts (each with its faster sweep form) on this shape
+    and record the faster for "auto" -> {"layout", "ms_int8", "ms_bitpack64"}.
+    The workspace is a temporary torch allocation on the device."""
+    import torch
+
+    params = pa_params(L=L, R=R, capacity=capacity, layout=PA_LAYOUT_AUTO, seed=seed, flags=0,
+                       model=MODELS[model])
+    nbytes = lib().pa_autotune_layout_workspace_bytes(ctypes.byref(params))
+    if nbytes == 0:
+        raise PAError(PA_EINVAL, "pa_autotune_layout_workspace_bytes")
+    dev = torch.device(device) if device is not None else torch.device("cuda")
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    Jc = np.ascontiguousarray(J, dtype=np.int8)
+    out = ctypes.c_uint32(0)
+    ms = (ctypes.c_float * 2)()
+    _check(lib().pa_autotune_layout(ctypes.byref(params), Jc.ctypes.data, ws.data_ptr(), nbytes,
+                                    stream.cuda_stream, float(beta), int(n_sweeps), int(repeats),
+                                    ctypes.byref(out), ctypes.cast(ms, _vp)), "pa_autotune_layout")
+    del ws
+    return {"layout": LAYOUT_NAMES[out.value], "ms_int8": ms[0], "ms_bitpack64": ms[1]}
+
+
 def pa_probe_ceilings(stream=None, device=None) -> dict:
     """This device's sustained VALU lane-op rate and Philox draw rate (scratch
     from torch on the device; stream defaults to the current one)."""
@@ -417,14 +470,18 @@ class Population:
     """One PA population on a GPU: workspace tensor + library handle."""
 
     def __init__(self, L: int, R: int, J: np.ndarray, seed: int, capacity: int = 0,
-                 layout: str = "bitpack64", device=None, stream=None, model: str = "pm",
+                 layout: str = "auto", device=None, stream=None, model: str = "pm",
                  flags: int = 0):
         """model "pm": J holds +-1; "gauss16": J holds k = 16 J in [-127, 127].
-        flags: PA_FLAG_* bits (debugging aids)."""
+        layout: "int8", "bitpack64" or "auto" (the autotuner's choice for this
+        shape, resolved once here).  flags: PA_FLAG_* bits (debugging aids)."""
         import torch
 
         self.L, self.N, self.R = int(L), int(L) ** 3, int(R)
         self.model = model
+        if layout == "auto":
+            layout = pa_layout_choice(L, R, model)
+        self.layout = layout
         self.params = pa_params(L=L, R=R, capacity=capacity, layout=LAYOUTS[layout], seed=seed,
                                 flags=int(flags), model=MODELS[model])
         nbytes = pa_workspace_bytes(self.params)

@@ -61,7 +61,11 @@ bool make_layout(const pa_params* p, Layout* out) {
           0 ||
       (p->model != PA_MODEL_PM && p->model != PA_MODEL_GAUSS16))
     return false;
-  uint32_t layout = p->layout == PA_LAYOUT_AUTO ? (uint32_t)PA_LAYOUT_BITPACK64 : p->layout;
+  // PA_LAYOUT_AUTO: the autotuner's layout for this shape (size class of the
+  // target population), else the built-in one
+  uint32_t layout = p->layout == PA_LAYOUT_AUTO
+                        ? pa::layout_for(p->model, p->L, ((uint64_t)p->R + 63) / 64)
+                        : p->layout;
   if (layout != PA_LAYOUT_INT8 && layout != PA_LAYOUT_BITPACK64) return false;
   uint64_t cap = p->capacity ? (uint64_t)p->capacity
                              : (uint64_t)p->R + 16ull * isqrt32(p->R) + 256ull;
@@ -1365,6 +1369,56 @@ int pa_autotune_sweep(pa_instance* in, double beta, uint32_t n_sweeps, uint32_t 
   if (ms_out) {
     ms_out[0] = ms[0];
     ms_out[1] = ms[1];
+  }
+  return PA_OK;
+}
+
+size_t pa_autotune_layout_workspace_bytes(const pa_params* p) {
+  if (!p) return 0;
+  size_t most = 0;
+  for (uint32_t lay : {(uint32_t)PA_LAYOUT_INT8, (uint32_t)PA_LAYOUT_BITPACK64}) {
+    pa_params q = *p;
+    q.layout = lay;
+    q.flags = 0;
+    Layout l;
+    if (!make_layout(&q, &l)) return 0;
+    most = std::max(most, l.total);
+  }
+  return most;
+}
+
+int pa_autotune_layout(const pa_params* p, const int8_t* J_host, void* d_workspace,
+                       size_t ws_bytes, void* hip_stream, double beta, uint32_t n_sweeps,
+                       uint32_t repeats, uint32_t* layout_out, float* ms_out) {
+  if (!p || !J_host || !d_workspace) return PA_EINVAL;
+  const size_t need = pa_autotune_layout_workspace_bytes(p);
+  if (need == 0) return PA_EINVAL;
+  if (ws_bytes < need) return PA_ENOMEM;
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return PA_EINVAL;
+  if (n_sweeps == 0 || repeats == 0 || repeats > 1000) return PA_EINVAL;
+  const uint32_t lays[2] = {(uint32_t)PA_LAYOUT_INT8, (uint32_t)PA_LAYOUT_BITPACK64};
+  float best_ms[2] = {0.0f, 0.0f};
+  for (int i = 0; i < 2; ++i) {
+    // a throwaway population of each layout in the caller's workspace; the
+    // split autotuner times both sweep forms on it and records the faster
+    pa_params q = *p;
+    q.layout = lays[i];
+    q.flags = 0;
+    pa_instance* in = nullptr;
+    if (int rc = pa_init_instance(&q, J_host, d_workspace, ws_bytes, hip_stream, &in)) return rc;
+    float ms[2] = {0.0f, 0.0f};
+    const int rc = pa_autotune_sweep(in, beta, n_sweeps, repeats, nullptr, ms);
+    const int rc_free = pa_free(in);
+    if (rc != PA_OK) return rc;
+    if (rc_free != PA_OK) return rc_free;
+    best_ms[i] = std::min(ms[0], ms[1]);
+  }
+  const uint32_t best = best_ms[1] <= best_ms[0] ? lays[1] : lays[0];
+  pa::layout_record(p->model, p->L, ((uint64_t)p->R + 63) / 64, best);
+  if (layout_out) *layout_out = best;
+  if (ms_out) {
+    ms_out[0] = best_ms[0];
+    ms_out[1] = best_ms[1];
   }
   return PA_OK;
 }

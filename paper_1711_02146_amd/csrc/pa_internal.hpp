@@ -263,4 +263,14 @@ uint32_t sweep_split_for(uint32_t model, uint32_t layout, uint32_t L, uint64_t t
 void sweep_split_record(uint32_t model, uint32_t layout, uint32_t L, uint64_t tiles,
                         uint32_t split);
 
+// Spin layout of a population created with the library's choice, when the
+// autotuner has not timed its shape: bit-packed (one bit per spin, 64
+// replicas per word) for every shape; values are PA_LAYOUT_INT8 = 1 and
+// PA_LAYOUT_BITPACK64 = 2.
+inline uint32_t layout_default(uint32_t, uint32_t, uint64_t) { return 2u; }
+// The autotuner's layout for (model, L, size class of `tiles`) when one was
+// measured or pinned in this process, else layout_default (pa_tune.cpp).
+uint32_t layout_for(uint32_t model, uint32_t L, uint64_t tiles);
+void layout_record(uint32_t model, uint32_t L, uint64_t tiles, uint32_t layout);
+
 }  // namespace pa

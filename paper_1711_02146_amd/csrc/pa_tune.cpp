@@ -1,8 +1,12 @@
-// pa_tune.cpp -- device measurement: the sweep autotuner's table (for
-// coupling model, spin layout, L and size class of the launch, the number of
-// waves per tile that measured fastest on this device) and the probes of the
-// device's VALU and Philox ceilings.  Size class = floor(log2(tiles)).  The form of a sweep changes no
-// result (every draw is addressed by slot, sweep and site group), only its time.
+// pa_tune.cpp -- device measurement: the autotuner's two tables and the probes
+// of the device's VALU and Philox ceilings.  The split table holds, per
+// coupling model, spin layout, L and size class of a sweep launch, the number
+// of waves per tile that measured fastest on this device; the layout table
+// holds, per coupling model, L and size class, the spin layout whose sweep
+// measured fastest (the layout PA_LAYOUT_AUTO resolves to at creation).  Size
+// class = floor(log2(tiles)).  Neither choice changes a result (every draw is
+// addressed by slot, sweep and site group, and both layouts hold the same
+// spins), only the time.
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -15,6 +19,7 @@ namespace {
 
 std::mutex g_mu;
 std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, uint32_t> g_table;
+std::map<std::tuple<uint32_t, uint32_t, uint32_t>, uint32_t> g_layouts;
 
 uint32_t size_class(uint64_t tiles) {
   uint32_t c = 0;
@@ -44,7 +49,37 @@ void sweep_split_record(uint32_t model, uint32_t layout, uint32_t L, uint64_t ti
   g_table[{model, layout, L, size_class(tiles)}] = split;
 }
 
+uint32_t layout_for(uint32_t model, uint32_t L, uint64_t tiles) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const auto it = g_layouts.find({model, L, size_class(tiles)});
+    if (it != g_layouts.end()) return it->second;
+  }
+  return layout_default(model, L, tiles);
+}
+
+void layout_record(uint32_t model, uint32_t L, uint64_t tiles, uint32_t layout) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_layouts[{model, L, size_class(tiles)}] = layout;
+}
+
 }  // namespace pa
+
+extern "C" int pa_layout_choice(uint32_t model, uint32_t L, uint32_t R, uint32_t* layout_out) {
+  if (!layout_out) return PA_EINVAL;
+  if (model != PA_MODEL_PM && model != PA_MODEL_GAUSS16) return PA_EINVAL;
+  if (L < 4 || L > (uint32_t)pa::kMaxL || (L & 1u) || R == 0) return PA_EINVAL;
+  *layout_out = pa::layout_for(model, L, ((uint64_t)R + 63) / 64);
+  return PA_OK;
+}
+
+extern "C" int pa_autotune_set_layout(uint32_t model, uint32_t L, uint64_t tiles, uint32_t layout) {
+  if (model != PA_MODEL_PM && model != PA_MODEL_GAUSS16) return PA_EINVAL;
+  if (layout != PA_LAYOUT_INT8 && layout != PA_LAYOUT_BITPACK64) return PA_EINVAL;
+  if (L < 4 || L > (uint32_t)pa::kMaxL || (L & 1u) || tiles == 0) return PA_EINVAL;
+  pa::layout_record(model, L, tiles, layout);
+  return PA_OK;
+}
 
 extern "C" int pa_autotune_set(uint32_t model, uint32_t layout, uint32_t L, uint64_t tiles,
                                uint32_t split) {
@@ -59,6 +94,7 @@ extern "C" int pa_autotune_set(uint32_t model, uint32_t layout, uint32_t L, uint
 extern "C" int pa_autotune_reset(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_table.clear();
+  g_layouts.clear();
   return PA_OK;
 }
 

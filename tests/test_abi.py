@@ -94,3 +94,50 @@ def test_autotune_set_checks_its_arguments():
                 (0, 2, 10, 0, 8), (0, 2, 10, 7813, 6)):
         assert lib.pa_autotune_set(*bad) == pam.PA_EINVAL, bad
     assert lib.pa_autotune_reset() == pam.PA_OK
+
+
+def test_layout_choice_follows_the_layout_table():
+    """PA_LAYOUT_AUTO resolves through the autotuner's layout table, keyed by
+    (model, L, floor(log2(ceil(R / 64)))), with bit-packing as the built-in
+    choice; pinning, lookup and workspace sizing are host bookkeeping."""
+    import paper_1711_02146_amd as pam
+
+    lib = pam.lib()
+    assert lib.pa_autotune_reset() == pam.PA_OK
+    try:
+        for L in (4, 6, 8, 10, 12, 16):
+            assert pam.pa_layout_choice(L, 100000) == "bitpack64"
+            assert pam.pa_layout_choice(L, 100000, "gauss16") == "bitpack64"
+        pam.pa_autotune_set_layout(8, 100000, "int8")  # 1563 tiles: size class 10
+        assert pam.pa_layout_choice(8, 100000) == "int8"
+        assert pam.pa_layout_choice(8, 65537) == "int8"    # 1025 tiles: class 10
+        assert pam.pa_layout_choice(8, 65536) == "int8"  # 1024 tiles: class 10
+        assert pam.pa_layout_choice(8, 65472) == "bitpack64"  # 1023 tiles: class 9
+        assert pam.pa_layout_choice(8, 131073) == "bitpack64"  # 2049 tiles: class 11
+        assert pam.pa_layout_choice(8, 50000) == "bitpack64"  # 782 tiles: class 9
+        assert pam.pa_layout_choice(10, 100000) == "bitpack64"
+        assert pam.pa_layout_choice(8, 100000, "gauss16") == "bitpack64"
+
+        def ws(layout, R=100000, L=8):
+            return pam.pa_workspace_bytes(pam.pa_params(L=L, R=R, capacity=0, layout=layout,
+                                                        seed=1, flags=0, model=0))
+
+        assert ws(pam.PA_LAYOUT_AUTO) == ws(pam.PA_LAYOUT_INT8) > ws(pam.PA_LAYOUT_BITPACK64)
+        assert ws(pam.PA_LAYOUT_AUTO, R=50000) == ws(pam.PA_LAYOUT_BITPACK64, R=50000)
+        p = pam.pa_params(L=8, R=100000, capacity=0, layout=pam.PA_LAYOUT_BITPACK64, seed=1,
+                          flags=pam.PA_FLAG_FAULT_HOOK, model=0)
+        assert lib.pa_autotune_layout_workspace_bytes(ctypes.byref(p)) == ws(pam.PA_LAYOUT_INT8)
+        p.L = 7
+        assert lib.pa_autotune_layout_workspace_bytes(ctypes.byref(p)) == 0
+        assert lib.pa_autotune_reset() == pam.PA_OK
+        assert pam.pa_layout_choice(8, 100000) == "bitpack64"
+        out = ctypes.c_uint32(0)
+        for bad in ((2, 8, 1000), (0, 7, 1000), (0, 2, 1000), (0, 18, 1000), (0, 8, 0)):
+            assert lib.pa_layout_choice(*bad, ctypes.byref(out)) == pam.PA_EINVAL, bad
+        assert lib.pa_layout_choice(0, 8, 1000, None) == pam.PA_EINVAL
+        for bad in ((2, 8, 16, 1), (0, 8, 16, 0), (0, 8, 16, 3), (0, 9, 16, 1), (0, 8, 0, 1)):
+            assert lib.pa_autotune_set_layout(*bad) == pam.PA_EINVAL, bad
+        assert lib.pa_autotune_layout(None, None, None, 0, None, 1.0, 10, 3, None,
+                                      None) == pam.PA_EINVAL
+    finally:
+        lib.pa_autotune_reset()

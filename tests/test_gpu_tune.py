@@ -1,7 +1,10 @@
 """GPU: the sweep autotuner times both sweep forms and remembers the faster; it
 changes neither the population nor any later result (bit-exact against the
 oracle afterwards), in the forms it picks for single instances and batches.
-The ceiling probes report rates within the chip's limits."""
+The layout autotuner times both spin layouts on a shape; populations created
+with layout "auto" then take the faster, and every result is the same under
+either choice (against the oracle, bit for bit).  The ceiling probes report
+rates within the chip's limits."""
 import numpy as np
 import pytest
 
@@ -68,6 +71,86 @@ def test_autotune_needs_no_pending_copy(pam):
             pam.pa_autotune_sweep(g.handle, beta, n, 1)
         assert e.value.status == pam.PA_EINVAL
     g.close()
+
+
+def _run_steps(pam, g, o, betas):
+    for b in betas:
+        g.resample(b)
+        g.sweep(b, 10)
+        if o is not None:
+            o.resample(b)
+            o.sweep(b, 10)
+
+
+def test_autotune_layout_records_a_choice_auto_uses(pam):
+    L, R = 6, 6000
+    J = pa_inputs.couplings_pm(L, 909)
+    pam.pa_autotune_reset()
+    try:
+        t = pam.pa_autotune_layout(L, R, J, seed=5, beta=0.5, n_sweeps=10, repeats=2)
+        assert t["ms_int8"] > 0 and t["ms_bitpack64"] > 0
+        assert t["layout"] == ("bitpack64" if t["ms_bitpack64"] <= t["ms_int8"] else "int8")
+        assert pam.pa_layout_choice(L, R) == t["layout"]
+        g = pam.Population(L, R, J, 77)
+        assert g.layout == t["layout"]
+        o = oracle.Population(L, J, R, 77)
+        _run_steps(pam, g, o, (0.3, 0.7))
+        s, u, f = g.export_state()
+        np.testing.assert_array_equal(s.reshape(-1), o.spins)
+        np.testing.assert_array_equal(u.astype(np.int32), o.U)
+        np.testing.assert_array_equal(f, o.fam)
+        g.close()
+    finally:
+        pam.pa_autotune_reset()
+
+
+@pytest.mark.parametrize("pinned", ["int8", "bitpack64"])
+def test_auto_layout_results_identical_under_either_choice(pam, pinned):
+    """Pin each layout for one shape: a population created with "auto" takes it,
+    and its observables, spins, energies and families after a few steps equal
+    those of populations created with either explicit layout."""
+    L, R = 8, 9000
+    J = pa_inputs.couplings_pm(L, 910)
+    pam.pa_autotune_reset()
+    try:
+        pam.pa_autotune_set_layout(L, R, pinned)
+        pops = {"auto": pam.Population(L, R, J, 31)}
+        assert pops["auto"].layout == pinned
+        for lay in ("int8", "bitpack64"):
+            pops[lay] = pam.Population(L, R, J, 31, layout=lay)
+        for g in pops.values():
+            _run_steps(pam, g, None, (0.4, 0.8, 1.2))
+        ref = pops["int8"]
+        ref_state = ref.export_state()
+        for name, g in pops.items():
+            assert g.observables() == ref.observables(), name
+            for x, y in zip(ref_state, g.export_state()):
+                np.testing.assert_array_equal(x, y, err_msg=name)
+        for g in pops.values():
+            g.close()
+    finally:
+        pam.pa_autotune_reset()
+
+
+def test_autotune_layout_checks_its_workspace(pam):
+    import ctypes
+
+    import torch
+
+    L, R = 6, 1000
+    J = np.ascontiguousarray(pa_inputs.couplings_pm(L, 1), np.int8)
+    p = pam.pa_params(L=L, R=R, capacity=0, layout=0, seed=1, flags=0, model=0)
+    need = pam.lib().pa_autotune_layout_workspace_bytes(ctypes.byref(p))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    lib = pam.lib()
+    assert lib.pa_autotune_layout(ctypes.byref(p), J.ctypes.data, ws.data_ptr(), need - 256, s,
+                                  1.0, 10, 1, None, None) == pam.PA_ENOMEM
+    assert lib.pa_autotune_layout(ctypes.byref(p), J.ctypes.data, ws.data_ptr(), need, s,
+                                  -1.0, 10, 1, None, None) == pam.PA_EINVAL
+    assert lib.pa_autotune_layout(ctypes.byref(p), J.ctypes.data, ws.data_ptr(), need, s,
+                                  1.0, 0, 1, None, None) == pam.PA_EINVAL
+    pam.pa_autotune_reset()
 
 
 def test_probe_ceilings(pam):
