@@ -16,6 +16,11 @@ annealing loop of Sec. II of Amey & Machta (arXiv:1711.02146) step by step:
 The per-step scalars (<E>, beta F, rho_t) are formed here in Python floats,
 which are IEEE doubles, one operation at a time in the order written.
 
+Three coupling models: +-J (Population), Gaussian rounded to multiples of
+1/16 (GaussPopulation, integer energy levels) and real Gaussian couplings on
+the grid 2^-32 (GaussRealPopulation: exact FP64 energies, per-replica
+weights, the normaliser and culled mass summed in fixed point).
+
 Parity unpinned: the overlap bin convention and the denominator R of rho_t
 (see pa_oracle.c) are checked between the oracle and the GPU only.
 """
@@ -103,6 +108,19 @@ def lib():
                                              _c.c_double, _c.c_double, _c.POINTER(_c.c_double),
                                              _c.POINTER(_c.c_int)]),
         "pao_g_density_of_states": (_c.c_int, [_c.c_int, _i8p, _u64p]),
+        "pao_r_exp": (_c.c_double, [_c.c_double]),
+        "pao_r_exp_many": (None, [_f64p, _c.c_int64, _f64p]),
+        "pao_r_energy": (None, [_c.c_int, _f64p, _i8p, _c.c_int64, _f64p]),
+        "pao_r_threshold": (_c.c_uint64, [_c.c_double, _c.c_double]),
+        "pao_r_sweep_slots": (None, [_c.c_int, _f64p, _i8p, _f64p, _c.c_int64, _u32p,
+                                     _c.c_uint64, _c.c_double, _c.c_uint32, _c.c_int]),
+        "pao_r_weights": (None, [_f64p, _c.c_int64, _c.c_double, _c.c_double, _f64p]),
+        "pao_r_fixsum96": (None, [_f64p, _c.c_int64, _u64p]),
+        "pao_r_copy_counts": (None, [_f64p, _c.c_int64, _c.c_uint32, _c.c_double, _c.c_uint64,
+                                     _c.c_uint32, _u32p, _f64p]),
+        "pao_r_cull_terms": (None, [_f64p, _c.c_int64, _c.c_uint32, _c.c_double, _f64p]),
+        "pao_r_exact_thermo": (_c.c_int, [_c.c_int, _f64p, _c.c_int, _f64p, _f64p, _f64p, _f64p,
+                                          _c.POINTER(_c.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -537,6 +555,174 @@ class GaussPopulation(Population):
         beta_F = -(float(self.N) * math.log(2.0) + self.sum_lnQ)
         s2 = sum_eta2(self.fam, self.R)
         E_min = int(E.min())
+        last = self.last or {}
+        return StepRecord(k=self.k, beta=self.beta, dbeta=last.get("dbeta", 0.0),
+                          lnQ=last.get("lnQ", 0.0), beta_F=beta_F, mean_E=mean_E,
+                          rho_t=float(s2) / float(self.R), R_tilde=self.R_tilde, E_min=E_min,
+                          eps_expected=last.get("eps", 0.0), n_culled=last.get("n_culled", 0),
+                          sum_eta2=s2, n_at_E_min=int(np.count_nonzero(E == E_min)))
+
+
+# ---------------------------------------------------------------------------
+# Gaussian couplings, continuous (Sec. II.A): J on the grid 2^-32, |J| < 8, so
+# every energy is exact in FP64.  Same loop, draws and copy rule as above; the
+# resampling works on per-replica weights instead of energy levels (there are
+# no levels to group by), with the normaliser S of Eq. 2 and the culled mass
+# of Sec. III.C summed in fixed point (pa_oracle.c, pao_r_fixsum96).
+# ---------------------------------------------------------------------------
+R_GRID = 2.0 ** -32
+
+
+def r_exp(x) -> np.ndarray:
+    """pao_r_exp elementwise (exp for x <= 0 by a fixed IEEE sequence)."""
+    x = np.ascontiguousarray(np.atleast_1d(x), np.float64)
+    out = np.zeros_like(x)
+    lib().pao_r_exp_many(x, x.size, out)
+    return out
+
+
+def r_energy(L: int, J: np.ndarray, spins: np.ndarray) -> np.ndarray:
+    spins = np.ascontiguousarray(spins, np.int8)
+    R = spins.size // L ** 3
+    E = np.zeros(R, np.float64)
+    lib().pao_r_energy(L, np.ascontiguousarray(J, np.float64), spins, R, E)
+    return E
+
+
+def r_fixsum96(v: np.ndarray) -> int:
+    """sum_i floor(v_i 2^96) for v_i in [0, 1], as an exact Python int."""
+    v = np.ascontiguousarray(v, np.float64)
+    out = np.zeros(2, np.uint64)
+    lib().pao_r_fixsum96(v, v.size, out)
+    return (int(out[1]) << 64) | int(out[0])
+
+
+def r_round96(total: int) -> float:
+    """A fixed-point sum rounded once to FP64 (nearest, ties to even) and
+    scaled by 2^-96 (exact)."""
+    return math.ldexp(float(total), -96)
+
+
+def r_weights(E: np.ndarray, dbeta: float, E_min: float) -> np.ndarray:
+    E = np.ascontiguousarray(E, np.float64)
+    w = np.zeros_like(E)
+    lib().pao_r_weights(E, E.size, float(dbeta), float(E_min), w)
+    return w
+
+
+def r_normaliser(w: np.ndarray) -> float:
+    """S = sum of the weights (Eq. 2 up to the factor 1/R~), fixed point."""
+    return r_round96(r_fixsum96(w))
+
+
+def r_culling_fraction(E: np.ndarray, R: int, dbeta: float) -> float:
+    """eps(dbeta) = (sum over replicas with tau < 1 of (1 - tau)) / R."""
+    E = np.ascontiguousarray(E, np.float64)
+    w = r_weights(E, dbeta, float(E.min()))
+    S = r_normaliser(w)
+    c = np.zeros_like(w)
+    lib().pao_r_cull_terms(w, w.size, int(R), S, c)
+    return r_round96(r_fixsum96(c)) / float(R)
+
+
+def r_choose_dbeta(E: np.ndarray, R: int, eps_target: float, rem: float):
+    """The constant-culling bisection of pao_choose_dbeta_unit (Sec. III.C),
+    with r_culling_fraction: (dbeta, reached_end) or ValueError."""
+    if r_culling_fraction(E, R, 0.0) > eps_target:
+        raise ValueError("culling fraction already exceeds the target at dbeta = 0")
+    if r_culling_fraction(E, R, rem) <= eps_target:
+        return rem, True
+    lo, hi = 0.0, rem
+    for _ in range(64):
+        mid = lo + 0.5 * (hi - lo)
+        if r_culling_fraction(E, R, mid) <= eps_target:
+            lo = mid
+        else:
+            hi = mid
+    return lo, False
+
+
+def r_exact_thermo(L: int, J: np.ndarray, betas):
+    """(lnZ, <E>, var E, E0) per beta by enumerating all 2^N states (N <= 30)."""
+    betas = np.ascontiguousarray(betas, np.float64)
+    n = betas.size
+    lnZ, Em, vE = np.zeros(n), np.zeros(n), np.zeros(n)
+    E0 = ctypes.c_double(0.0)
+    if lib().pao_r_exact_thermo(L, np.ascontiguousarray(J, np.float64), n, betas, lnZ, Em, vE,
+                                ctypes.byref(E0)) != 0:
+        raise ValueError("lattice too large to enumerate")
+    return lnZ, Em, vE, E0.value
+
+
+class GaussRealPopulation(Population):
+    """A PA population with real Gaussian couplings J (FP64 on the 2^-32 grid).
+
+    ``U`` holds the energies (FP64, exact).  Initial spins and family labels
+    are those of every model (Philox INIT draws)."""
+
+    def __init__(self, L: int, J: np.ndarray, R: int, seed: int, capacity: int | None = None):
+        super().__init__(L, np.ones(3 * L ** 3, np.int8), R, seed, capacity)
+        J = np.ascontiguousarray(J, np.float64)
+        assert J.size == 3 * self.N
+        assert np.all(np.abs(J) < 8.0) and np.all(np.ldexp(J, 32) == np.rint(np.ldexp(J, 32)))
+        self.J = J
+        self.U = r_energy(L, J, self.spins)
+
+    def sweep(self, beta: float, n_sweeps: int):
+        slots = np.arange(self.R_tilde, dtype=np.uint32)
+        lib().pao_r_sweep_slots(self.L, self.J, self.spins, self.U, self.R_tilde, slots,
+                                self.seed, float(beta), self.t, int(n_sweeps))
+        self.t += int(n_sweeps)
+
+    def histogram(self):
+        raise TypeError("continuous energies have no level histogram")
+
+    def resample(self, beta_next: float):
+        dbeta = beta_next - self.beta
+        E = self.U[: self.R_tilde]
+        E_min = float(E.min())
+        w = r_weights(E, dbeta, E_min)
+        S = r_normaliser(w)
+        step = self.k + 1
+        cnt = np.zeros(self.R_tilde, np.uint32)
+        tau = np.zeros(self.R_tilde, np.float64)
+        lib().pao_r_copy_counts(w, self.R_tilde, self.R, S, self.seed, step, cnt, tau)
+        total = int(cnt.astype(np.uint64).sum())
+        offsets = np.zeros(self.R_tilde, np.uint64)
+        offsets[1:] = np.cumsum(cnt[:-1].astype(np.uint64))
+        if total > self.capacity:
+            raise OverflowError("resampled population exceeds capacity")
+        # copy / eliminate (Sec. II): copies of replica i fill consecutive new
+        # slots from offset_i on, in the old order, with i's family label
+        src = np.repeat(np.arange(self.R_tilde), cnt.astype(np.int64))
+        lnQ = math.log(S) - math.log(float(self.R_tilde)) - dbeta * E_min
+        eps = r_culling_fraction(E, self.R, dbeta)
+        self.last = dict(w=w, S=S, tau=tau, n=cnt, offsets=offsets, lnQ=lnQ, dbeta=dbeta,
+                         eps=eps, E_ref=E_min, n_culled=int(np.count_nonzero(cnt == 0)))
+        self.spins = self.spins.reshape(self.R_tilde, self.N)[src].reshape(-1).copy()
+        self.U = E[src].copy()
+        self.fam = self.fam[: self.R_tilde][src].copy()
+        self.R_tilde = total
+        self.sum_lnQ = self.sum_lnQ + lnQ
+        self.beta = beta_next
+        self.k = step
+
+    def choose_beta(self, eps_target: float, beta_max: float):
+        rem = beta_max - self.beta
+        dbeta, end = r_choose_dbeta(self.U[: self.R_tilde], self.R, eps_target, rem)
+        return beta_max if end else self.beta + dbeta
+
+    def observables(self) -> StepRecord:
+        """As Population.observables, with E_min an FP64 energy and <E> the
+        exact sum of the energies (integers in units 2^-32) rounded once to
+        FP64, divided by R~ and scaled by 2^-32."""
+        E = self.U[: self.R_tilde]
+        q = np.ldexp(E, 32).astype(np.int64)        # exact: |E 2^32| < 2^49
+        sumE = (int((q >> 24).sum()) << 24) + int((q & ((1 << 24) - 1)).sum())
+        mean_E = float(sumE) / float(self.R_tilde) * R_GRID
+        beta_F = -(float(self.N) * math.log(2.0) + self.sum_lnQ)
+        s2 = sum_eta2(self.fam, self.R)
+        E_min = float(E.min())
         last = self.last or {}
         return StepRecord(k=self.k, beta=self.beta, dbeta=last.get("dbeta", 0.0),
                           lnQ=last.get("lnQ", 0.0), beta_F=beta_F, mean_E=mean_E,

@@ -1,7 +1,8 @@
 /*
  * pa_oracle.c -- plain CPU oracle for population annealing (PA) on the
- * 3D Edwards-Anderson spin glass, with +-J couplings and with Gaussian
- * couplings rounded to multiples of 1/16.
+ * 3D Edwards-Anderson spin glass, with +-J couplings, with Gaussian
+ * couplings rounded to multiples of 1/16, and with real Gaussian couplings
+ * (FP64 on the grid 2^-32, per-replica weights and fixed-point sums).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
  * CPU-baseline leg of the benchmark load this library.  It shares no code,
@@ -747,6 +748,278 @@ int pao_g_density_of_states(int L, const int8_t* K, uint64_t* g_out) {
     e += 2 * s[f] * h;
     s[f] = (int8_t)(-s[f]);
     g_out[e + off] += 1;
+  }
+  return 0;
+}
+
+/* ======================================================================== */
+/* Gaussian couplings, continuous (Sec. II.A: J_nm drawn from a unit        */
+/* normal).                                                                  */
+/*                                                                           */
+/* Reading: every coupling is an FP64 number on the grid 2^-32 with          */
+/* |J| < 8 (the caller rounds a unit normal to the nearest grid point; a     */
+/* draw beyond 8 sd has probability 1e-15 per bond).  Every energy is then a */
+/* sum of at most 3N <= 12288 grid numbers below 8 in size: |E| < 2^17, a    */
+/* multiple of 2^-32, so every partial sum fits in 49 bits and FP64 adds it  */
+/* exactly, in any order.  Energies and energy changes are therefore exact.  */
+/*                                                                           */
+/* Floating point enters in three places, each written out below so that a   */
+/* second implementation of the same steps gets the same bits:               */
+/*   pao_r_exp     exp(x), x <= 0, by a fixed sequence of IEEE operations     */
+/*   fixed-point sums of weights (S of Eq. 2, the culled mass of Sec. III.C)  */
+/*   the copy-count split (as for the other models)                           */
+/* ======================================================================== */
+
+/* exp(x) for x <= 0.  Cody and Waite's argument reduction (Software Manual   */
+/* for the Elementary Functions, 1980) with a Taylor polynomial:              */
+/*   x < -708          -> 0 (below 2^-1021; no weight or threshold uses it)   */
+/*   k  = x * log2(e), rounded to the nearest integer (ties to even)         */
+/*   r  = fma(-k, ln2_hi, x);  r = fma(-k, ln2_lo, r)    (|r| <= 0.3466)      */
+/*   p  = sum_{n=0..13} r^n / n!   by Horner's rule, one fma per degree      */
+/*   exp(x) = p 2^k                                                           */
+/* ln2_hi is ln 2 rounded to FP64, ln2_lo the rounded remainder, log2(e) and  */
+/* 1/n! rounded to FP64.  The truncated series errs by r^14/14! < 5e-18,     */
+/* below half an ulp of p; the result is within about one ulp of exp(x).     */
+/* ------------------------------------------------------------------------ */
+double pao_r_exp(double x) {
+  if (x < -708.0) return 0.0;
+  double k = nearbyint(x * 0x1.71547652b82fep+0);
+  double r = fma(-k, 0x1.62e42fefa39efp-1, x);
+  r = fma(-k, 0x1.abc9e3b39803fp-56, r);
+  double p = 1.0 / 6227020800.0;               /* 1/13! */
+  p = fma(p, r, 1.0 / 479001600.0);            /* 1/12! */
+  p = fma(p, r, 1.0 / 39916800.0);             /* 1/11! */
+  p = fma(p, r, 1.0 / 3628800.0);              /* 1/10! */
+  p = fma(p, r, 1.0 / 362880.0);               /* 1/9!  */
+  p = fma(p, r, 1.0 / 40320.0);                /* 1/8!  */
+  p = fma(p, r, 1.0 / 5040.0);                 /* 1/7!  */
+  p = fma(p, r, 1.0 / 720.0);                  /* 1/6!  */
+  p = fma(p, r, 1.0 / 120.0);                  /* 1/5!  */
+  p = fma(p, r, 1.0 / 24.0);                   /* 1/4!  */
+  p = fma(p, r, 1.0 / 6.0);                    /* 1/3!  */
+  p = fma(p, r, 0.5);                          /* 1/2!  */
+  p = fma(p, r, 1.0);                          /* 1/1!  */
+  p = fma(p, r, 1.0);                          /* 1/0!  */
+  return ldexp(p, (int)k);
+}
+
+void pao_r_exp_many(const double* x, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = pao_r_exp(x[i]);
+}
+
+/* E = -sum_b J_b s_i s_j over the 3N bonds (exact, see above). */
+static double energy_r(const int8_t* s, const double* J, int L) {
+  int N = L * L * L;
+  double e = 0.0;
+  for (int d = 0; d < 3; ++d)
+    for (int site = 0; site < N; ++site) {
+      int other = neighbour(site, 2 * d, L);
+      e -= J[d * N + site] * (double)(s[site] * s[other]);
+    }
+  return e;
+}
+
+void pao_r_energy(int L, const double* J, const int8_t* spins, int64_t R, double* E_out) {
+  int N = L * L * L;
+  for (int64_t r = 0; r < R; ++r) E_out[r] = energy_r(spins + r * N, J, L);
+}
+
+/* Metropolis threshold of a move raising the energy by dE at inverse       */
+/* temperature beta: 2^32 (always taken) for dE <= 0, else                  */
+/* floor(2^32 pao_r_exp(-beta dE)); the move is taken iff its draw is below. */
+uint64_t pao_r_threshold(double beta, double dE) {
+  if (dE <= 0.0) return (uint64_t)1 << 32;
+  return (uint64_t)floor(ldexp(pao_r_exp(-beta * dE), 32));
+}
+
+/* Sweeps of one replica: the visiting order and draws of sweep_one, with    */
+/* dE = 2 s_i sum_j J_ij s_j in FP64 (exact) and the threshold above.       */
+static void r_sweep_one(int L, const double* J, const int32_t* cm, const int32_t* nb,
+                        const int32_t* bd, int8_t* s, double* E, uint32_t slot, uint64_t seed,
+                        double beta, uint32_t t0, int n_sweeps) {
+  int N = L * L * L;
+  double e = *E;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    uint32_t t = t0 + (uint32_t)sw;
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int site = 0; site < N; ++site) {
+        if (colour_of(site, L) != colour) continue;
+        double h = 0.0;
+        for (int dir = 0; dir < 6; ++dir)
+          h += J[bd[site * 6 + dir]] * (double)s[nb[site * 6 + dir]];
+        double dE = 2.0 * (double)s[site] * h;
+        int accept;
+        if (dE <= 0.0) {
+          accept = 1;
+        } else {
+          uint32_t x = draw_word(seed, slot, t, (uint32_t)(cm[site] >> 2), TAG_MET, cm[site] & 3);
+          accept = (uint64_t)x < pao_r_threshold(beta, dE);
+        }
+        if (accept) {
+          s[site] = (int8_t)(-s[site]);
+          e += dE;
+        }
+      }
+    }
+  }
+  *E = e;
+}
+
+void pao_r_sweep_slots(int L, const double* J, int8_t* spins, double* E, int64_t n,
+                       const uint32_t* slots, uint64_t seed, double beta, uint32_t t0,
+                       int n_sweeps) {
+  int N = L * L * L;
+  int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * N);
+  int32_t* nb = (int32_t*)malloc(sizeof(int32_t) * N * 6);
+  int32_t* bd = (int32_t*)malloc(sizeof(int32_t) * N * 6);
+  pao_colour_major(L, cm);
+  pao_neighbours(L, nb, bd);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    r_sweep_one(L, J, cm, nb, bd, spins + i * N, E + i, slots ? slots[i] : (uint32_t)i, seed,
+                beta, t0, n_sweeps);
+  free(cm);
+  free(nb);
+  free(bd);
+}
+
+/* Resampling weights (Eq. 1): w_i = pao_r_exp(-(dbeta (E_i - E_min))),     */
+/* E_min the population's lowest energy (reference shift; it cancels in     */
+/* tau), so 0 <= w_i <= 1 and the lowest replica has weight 1.              */
+void pao_r_weights(const double* E, int64_t n, double dbeta, double E_min, double* w_out) {
+  for (int64_t i = 0; i < n; ++i) w_out[i] = pao_r_exp(-(dbeta * (E[i] - E_min)));
+}
+
+/* Fixed-point sum of values in [0, 1]: sum_i floor(v_i 2^96), exactly, as a */
+/* 128-bit integer (out[0] low word, out[1] high word; R <= 2^31 terms keep */
+/* it below 2^127).  The caller rounds it once to FP64 (nearest, ties to    */
+/* even) and scales by 2^-96.  Reading: the normaliser S of Eq. 2 and the    */
+/* culled mass of Sec. III.C are such sums; truncating each term moves the   */
+/* total by less than R 2^-96, and the integer sum has no order.             */
+void pao_r_fixsum96(const double* v, int64_t n, uint64_t out[2]) {
+  unsigned __int128 acc = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double x = v[i];
+    if (x == 0.0) continue;
+    int e;
+    double m = frexp(x, &e);                       /* x = m 2^e, 1/2 <= m < 1 */
+    uint64_t M = (uint64_t)ldexp(m, 53);           /* x = M 2^(e - 53), exact */
+    int sh = e - 53 + 96;
+    if (sh >= 0) acc += (unsigned __int128)M << sh;
+    else if (sh > -64) acc += (unsigned __int128)(M >> -sh);
+  }
+  out[0] = (uint64_t)acc;
+  out[1] = (uint64_t)(acc >> 64);
+}
+
+/* Copy counts from per-replica weights (Sec. II, Eqs. 1-2):                */
+/*   tau_i = (R w_i) / S,  fl_i = floor(tau_i),                              */
+/*   T_i = ceil(frac(tau_i) 2^53),  n_i = fl_i + [u53 < T_i]                 */
+/* with u53 drawn as in pao_copy_counts (slot i, step k).                    */
+void pao_r_copy_counts(const double* w, int64_t R_tilde, uint32_t R, double S, uint64_t seed,
+                       uint32_t step, uint32_t* n_out, double* tau_out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < R_tilde; ++i) {
+    double tau = ((double)R * w[i]) / S;
+    uint64_t fl = (uint64_t)floor(tau);
+    double fr = tau - (double)fl;
+    uint64_t T = (uint64_t)ceil(ldexp(fr, 53));
+    uint32_t ctr[4] = {(uint32_t)i, step, 0u, TAG_RES};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    pao_philox(ctr, key, out);
+    uint64_t u53 = ((uint64_t)out[0] << 21) | (uint64_t)(out[1] >> 11);
+    n_out[i] = (uint32_t)fl + (u53 < T ? 1u : 0u);
+    if (tau_out) tau_out[i] = tau;
+  }
+}
+
+/* Culled mass terms (Sec. III.C): c_i = 1 - tau_i if tau_i < 1, else 0;    */
+/* eps = (fixed-point sum of c_i) / R.                                       */
+void pao_r_cull_terms(const double* w, int64_t R_tilde, uint32_t R, double S, double* c_out) {
+  for (int64_t i = 0; i < R_tilde; ++i) {
+    double tau = ((double)R * w[i]) / S;
+    c_out[i] = tau < 1.0 ? 1.0 - tau : 0.0;
+  }
+}
+
+/* Exact thermodynamics of a small lattice with real couplings (N <= 30):   */
+/* Gray-code enumeration of all 2^N states, in 2^6 independent slices.      */
+/* Pass 1 finds the ground-state energy E0 (exact); pass 2 sums, for every  */
+/* beta, Z0 = sum exp(-beta (E - E0)), Z1 = sum (E - E0) exp(.), Z2 = sum   */
+/* (E - E0)^2 exp(.) with the C library's exp.  Out (per beta):             */
+/* lnZ = ln Z0 - beta E0, <E> = E0 + Z1/Z0, var E = Z2/Z0 - (Z1/Z0)^2.       */
+int pao_r_exact_thermo(int L, const double* J, int n_beta, const double* betas,
+                       double* lnZ_out, double* E_out, double* varE_out, double* E0_out) {
+  int N = L * L * L;
+  if (N > 30 || N < 7 || n_beta > 64) return -1;
+  int nb[30][6];
+  double jb[30][6];
+  for (int s = 0; s < N; ++s)
+    for (int dir = 0; dir < 6; ++dir) {
+      nb[s][dir] = neighbour(s, dir, L);
+      jb[s][dir] = J[bond_of(s, dir, L)];
+    }
+  const int SLICE_BITS = 6;
+  const int low = N - SLICE_BITS;
+  const uint64_t per = (uint64_t)1 << low;
+  double e0_slice[64];
+  double z[64][64][3];
+  for (int pass = 0; pass < 2; ++pass) {
+    double E0 = 0.0;
+    if (pass == 1) {
+      E0 = e0_slice[0];
+      for (int sl = 1; sl < 64; ++sl)
+        if (e0_slice[sl] < E0) E0 = e0_slice[sl];
+      *E0_out = E0;
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int sl = 0; sl < 64; ++sl) {
+      int8_t s[30];
+      for (int i = 0; i < N; ++i) s[i] = 1;
+      for (int b = 0; b < SLICE_BITS; ++b)
+        if ((sl >> b) & 1) s[low + b] = -1;
+      double e = energy_r(s, J, L);
+      double emin = e;
+      double acc[64][3];
+      memset(acc, 0, sizeof(acc));
+      for (uint64_t g = 0; g < per; ++g) {
+        if (g > 0) {
+          int f = __builtin_ctzll(g);
+          double h = 0.0;
+          for (int dir = 0; dir < 6; ++dir) h += jb[f][dir] * (double)s[nb[f][dir]];
+          e += 2.0 * (double)s[f] * h;
+          s[f] = (int8_t)(-s[f]);
+        }
+        if (pass == 0) {
+          if (e < emin) emin = e;
+        } else {
+          double d = e - E0;
+          for (int k = 0; k < n_beta; ++k) {
+            double x = exp(-betas[k] * d);
+            acc[k][0] += x;
+            acc[k][1] += d * x;
+            acc[k][2] += d * d * x;
+          }
+        }
+      }
+      if (pass == 0) e0_slice[sl] = emin;
+      else memcpy(z[sl], acc, sizeof(acc));
+    }
+    if (pass == 1) {
+      for (int k = 0; k < n_beta; ++k) {
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+        for (int sl = 0; sl < 64; ++sl) {
+          z0 += z[sl][k][0];
+          z1 += z[sl][k][1];
+          z2 += z[sl][k][2];
+        }
+        double m1 = z1 / z0;
+        lnZ_out[k] = log(z0) - betas[k] * E0;
+        E_out[k] = E0 + m1;
+        varE_out[k] = z2 / z0 - m1 * m1;
+      }
+    }
   }
   return 0;
 }

@@ -30,6 +30,15 @@ def couplings_gauss16(L: int, coupling_seed: int) -> np.ndarray:
     return np.clip(np.rint(16.0 * z), -127, 127).astype(np.int8)
 
 
+def couplings_gauss(L: int, coupling_seed: int) -> np.ndarray:
+    """3 L^3 Gaussian couplings J ~ N(0, 1) (numpy PCG64) as FP64 numbers rounded
+    to the nearest multiple of 2^-32 (ties to even) and kept inside (-8, 8)."""
+    rng = np.random.Generator(np.random.PCG64(int(coupling_seed)))
+    z = rng.standard_normal(3 * L ** 3)
+    k = np.clip(np.rint(np.ldexp(z, 32)), -(2.0 ** 35) + 1, 2.0 ** 35 - 1)
+    return np.ldexp(k, -32)
+
+
 def couplings_ferro(L: int) -> np.ndarray:
     """All couplings +1 (the ferromagnetic limit)."""
     return np.ones(3 * L ** 3, np.int8)
