@@ -89,9 +89,15 @@ enum {
 
 enum {
   PA_MODEL_PM = 0,      /* J = +1 or -1 (J_host holds +-1); energy levels U = 0..3N, E = 2U - 3N */
-  PA_MODEL_GAUSS16 = 1  /* Gaussian couplings (Sec. II.A) rounded to multiples of 1/16: J_host
+  PA_MODEL_GAUSS16 = 1, /* Gaussian couplings (Sec. II.A) rounded to multiples of 1/16: J_host
                            holds k = 16 J in [-127, 127]; energies are integers E16 = 16 E.
                            Single-instance calls only (batches and steppers take PA_MODEL_PM). */
+  PA_MODEL_GAUSS = 2    /* Gaussian couplings (Sec. II.A) as real numbers: created by
+                           pa_init_instance_real from FP64 couplings, each rounded to the
+                           nearest multiple of 2^-32 (ties to even), |J| < 8; every energy is
+                           then exact (a multiple of 2^-32 below 2^17 in size).  Resampling
+                           works on per-replica weights (no energy levels); see
+                           pa_init_instance_real.  Single-instance calls only. */
 };
 
 typedef struct pa_instance pa_instance;
@@ -131,6 +137,9 @@ typedef struct {
                           needs (pa_import_state) */
   double sweep_ms;     /* PA_FLAG_TIME_SWEEPS: duration of the last sweep launch on the
                           device (HIP events around it), ms; 0 otherwise */
+  double E_lowest;     /* lowest energy in the current population in units of J, every model
+                          (PA_MODEL_GAUSS: E_min above is 0; this is the exact value); 0 in
+                          the record pa_resample returns */
 } pa_obs;
 
 /* Bytes of device workspace an instance with these parameters needs. 0 on bad params. */
@@ -146,6 +155,33 @@ size_t pa_workspace_bytes(const pa_params* p);
  * On success *out holds the new instance. */
 int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace, size_t ws_bytes,
                      void* hip_stream, pa_instance** out);
+
+/* The same for Gaussian couplings as real numbers (Sec. II.A), p->model =
+ * PA_MODEL_GAUSS: J_host holds 3*L^3 FP64 couplings in bond order (bond
+ * d*N + site joins site and its +d neighbour), each finite with |J| < 8
+ * (PA_EINVAL otherwise), rounded to the nearest multiple of 2^-32.  The
+ * model's readings (the paper fixes no arithmetic):
+ *   - energies are exact: the int64 word E 2^32 per replica;
+ *   - a move raising E by dE > 0 is taken iff its draw is below
+ *     floor(2^32 e(-beta dE)), where e(x) is exp evaluated by Cody and Waite's
+ *     reduction (x = k ln 2 + r, k the nearest integer to x log2(e), r by two
+ *     fused multiply-adds with ln 2 split into its FP64 rounding and the
+ *     rounded remainder) and the Taylor polynomial of degree 13 in r by
+ *     Horner's rule, one fused multiply-add per degree, times 2^k; e(x) = 0
+ *     below x = -708;
+ *   - a resampling step weighs replica i by w_i = e(-(dbeta (E_i - E_min)));
+ *     the normaliser S = sum w_i (Eq. 2 times R~) and the culled mass
+ *     sum_{tau_i < 1} (1 - tau_i) (Sec. III.C) are sums of terms truncated to
+ *     multiples of 2^-96, added exactly and rounded once to FP64 (nearest,
+ *     ties to even), so they do not depend on the order of addition;
+ *     tau_i = (R w_i) / S and the copy counts follow the rule of every model;
+ *     ln Q = ln S - ln R~ - dbeta E_min;
+ *   - <E> = (the exact sum of the energy words rounded once to FP64) / R~ 2^-32.
+ * pa_choose_beta runs the constant-culling bisection on the device.  U_host
+ * of pa_export_state must be NULL (pa_export_energies gives the energies).
+ * Other errors as pa_init_instance. */
+int pa_init_instance_real(const pa_params* p, const double* J_host, void* d_workspace,
+                          size_t ws_bytes, void* hip_stream, pa_instance** out);
 
 /* n_sweeps Metropolis sweeps at beta (the MCMC step of Sec. II): colour 0
  * then colour 1 of the checkerboard; a move raising the energy by dE > 0 is
@@ -249,6 +285,12 @@ int pa_export_state(pa_instance* in, int8_t* spins_host, uint32_t* U_host, uint3
  * and diagnostics.  Synchronises. */
 int pa_export_counts(pa_instance* in, uint32_t* counts_host, uint32_t* offsets_host,
                      uint32_t* n_old);
+
+/* Energies of the current population in units of J, one FP64 per replica
+ * (exact for every model: E = 2U - 3N for PA_MODEL_PM, E16 / 16 for
+ * PA_MODEL_GAUSS16, E32 2^-32 for PA_MODEL_GAUSS).  E_host: R~ doubles
+ * (pa_observables tells R~).  Synchronises. */
+int pa_export_energies(pa_instance* in, double* E_host);
 
 /* Replace the population (checkpoint restore, or tests feeding a state in):
  * R_tilde replicas, spins [replica][site] int8 +-1, family labels (< R), the

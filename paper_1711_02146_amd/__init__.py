@@ -35,7 +35,8 @@ PA_INJECT_ENERGY = 2
 
 PA_MODEL_PM = 0
 PA_MODEL_GAUSS16 = 1
-MODELS = {"pm": PA_MODEL_PM, "gauss16": PA_MODEL_GAUSS16}
+PA_MODEL_GAUSS = 2
+MODELS = {"pm": PA_MODEL_PM, "gauss16": PA_MODEL_GAUSS16, "gauss": PA_MODEL_GAUSS}
 
 PA_LAYOUT_AUTO = 0
 PA_LAYOUT_INT8 = 1
@@ -56,7 +57,8 @@ class pa_obs(ctypes.Structure):
                 ("n_culled", ctypes.c_uint32), ("E_min", ctypes.c_int32), ("step", ctypes.c_uint32),
                 ("sum_eta2", ctypes.c_uint64), ("sweeps_done", ctypes.c_uint64),
                 ("n_at_E_min", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("sum_lnQ", ctypes.c_double), ("sweep_ms", ctypes.c_double)]
+                ("sum_lnQ", ctypes.c_double), ("sweep_ms", ctypes.c_double),
+                ("E_lowest", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -137,6 +139,9 @@ def lib():
                                          ctypes.c_uint32, _vp, _P(ctypes.c_uint32)]),
         "pa_link_overlap_hist_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp]),
         "pa_autotune_layout_workspace_bytes": (ctypes.c_size_t, [_P(pa_params)]),
+        "pa_init_instance_real": (ctypes.c_int, [_P(pa_params), _vp, _vp, ctypes.c_size_t, _vp,
+                                                 _P(_vp)]),
+        "pa_export_energies": (ctypes.c_int, [_vp, _vp]),
         "pa_autotune_layout": (ctypes.c_int, [_P(pa_params), _vp, _vp, ctypes.c_size_t, _vp,
                                               ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32,
                                               _P(ctypes.c_uint32), _vp]),
@@ -162,7 +167,8 @@ EXPORTED = ["pa_workspace_bytes", "pa_init_instance", "pa_sweep", "pa_resample",
             "pa_probe_ceilings", "pa_make_couplings_pm", "pa_autotune_set",
             "pa_link_overlap_hist", "pa_debug_inject", "pa_anneal_step", "pa_anneal_run",
             "pa_link_overlap_hist_noalloc", "pa_autotune_layout_workspace_bytes",
-            "pa_autotune_layout", "pa_layout_choice", "pa_autotune_set_layout"]
+            "pa_autotune_layout", "pa_layout_choice", "pa_autotune_set_layout",
+            "pa_init_instance_real", "pa_export_energies"]
 
 
 # --- the C entry points, one Python function each ---------------------------
@@ -271,6 +277,25 @@ def pa_export_state(handle: int, N: int, spins=True, U=True, family=True):
                                  u.ctypes.data if U else None, f.ctypes.data if family else None,
                                  ctypes.byref(n)), "pa_export_state")
     return s, u, f
+
+
+def pa_init_instance_real(params: pa_params, J: np.ndarray, workspace_ptr: int, ws_bytes: int,
+                          stream_handle: int) -> int:
+    J = np.ascontiguousarray(J, np.float64)
+    out = _vp()
+    _check(lib().pa_init_instance_real(ctypes.byref(params), J.ctypes.data, workspace_ptr,
+                                       ws_bytes, stream_handle, ctypes.byref(out)),
+           "pa_init_instance_real")
+    return out.value
+
+
+def pa_export_energies(handle: int) -> np.ndarray:
+    """Energies of the current population in units of J (FP64, exact)."""
+    n = ctypes.c_uint32(0)
+    _check(lib().pa_export_state(handle, None, None, None, ctypes.byref(n)), "pa_export_state")
+    E = np.zeros(n.value, np.float64)
+    _check(lib().pa_export_energies(handle, E.ctypes.data), "pa_export_energies")
+    return E
 
 
 def pa_export_counts(handle: int):
@@ -472,7 +497,8 @@ class Population:
     def __init__(self, L: int, R: int, J: np.ndarray, seed: int, capacity: int = 0,
                  layout: str = "auto", device=None, stream=None, model: str = "pm",
                  flags: int = 0):
-        """model "pm": J holds +-1; "gauss16": J holds k = 16 J in [-127, 127].
+        """model "pm": J holds +-1; "gauss16": J holds k = 16 J in [-127, 127];
+        "gauss": J holds real couplings (FP64, |J| < 8, rounded to the grid 2^-32).
         layout: "int8", "bitpack64" or "auto" (the autotuner's choice for this
         shape, resolved once here).  flags: PA_FLAG_* bits (debugging aids)."""
         import torch
@@ -490,8 +516,9 @@ class Population:
         self.device = torch.device(device) if device is not None else torch.device("cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.handle = pa_init_instance(self.params, J, self.workspace.data_ptr(), nbytes,
-                                       self.stream.cuda_stream)
+        init = pa_init_instance_real if model == "gauss" else pa_init_instance
+        self.handle = init(self.params, J, self.workspace.data_ptr(), nbytes,
+                           self.stream.cuda_stream)
 
     def sweep(self, beta: float, n_sweeps: int):
         pa_sweep(self.handle, beta, n_sweeps)
@@ -520,7 +547,15 @@ class Population:
         return pa_anneal_step(self.handle, -1.0, 0.0, n_sweeps, beta_next)[1]
 
     def export_state(self, spins=True, U=True, family=True):
+        """(spins, energy words, family labels); for model "gauss" the energies
+        in units of J (FP64) stand in for the energy words."""
+        if self.model == "gauss":
+            s, _, f = pa_export_state(self.handle, self.N, spins, False, family)
+            return s, (pa_export_energies(self.handle) if U else None), f
         return pa_export_state(self.handle, self.N, spins, U, family)
+
+    def export_energies(self) -> np.ndarray:
+        return pa_export_energies(self.handle)
 
     def export_counts(self):
         return pa_export_counts(self.handle)

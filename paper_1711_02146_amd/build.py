@@ -13,6 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpa.so")
 SOURCES = ["pa_kernels.hip", "pa_host.cpp", "pa_batch.cpp", "pa_stepper.cpp", "pa_tune.cpp"]
+# pa_kernels.hip includes pa_real_kernels.inc (the real-coupling kernels)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -387,6 +387,7 @@ int pa_batch_results(pa_batch* b, pa_obs* obs, uint64_t* qhist, int32_t* status,
         o->R_tilde = r.R_new;
         o->n_culled = r.n_culled;
         o->E_min = r.E_min;
+        o->E_lowest = (double)r.E_min;
       o->n_at_E_min = r.n_at_E_min;
         o->step = b->step0[p] + s + 1;
         o->sweeps_done = b->sweeps0[p] + (uint64_t)(s + 1) * b->n_sweeps;

@@ -59,7 +59,7 @@ bool make_layout(const pa_params* p, Layout* out) {
   if (p->R < 1) return false;
   if ((p->flags & ~(uint32_t)(PA_FLAG_CHECK_ENERGY | PA_FLAG_FAULT_HOOK | PA_FLAG_TIME_SWEEPS)) !=
           0 ||
-      (p->model != PA_MODEL_PM && p->model != PA_MODEL_GAUSS16))
+      (p->model != PA_MODEL_PM && p->model != PA_MODEL_GAUSS16 && p->model != PA_MODEL_GAUSS))
     return false;
   // PA_LAYOUT_AUTO: the autotuner's layout for this shape (size class of the
   // target population), else the built-in one
@@ -78,8 +78,12 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.capacity = (uint32_t)((cap + pa::kBlockCounts - 1) / pa::kBlockCounts * pa::kBlockCounts);
   l.layout = layout;
   l.model = p->model;
-  // energy levels: U = 0..3N, or every E16 window (|E16| <= 3N * 127)
-  l.n_levels = p->model == PA_MODEL_GAUSS16 ? 6 * l.N * (uint32_t)pa::kGaussKMax + 1 : 3 * l.N + 1;
+  // energy levels: U = 0..3N, or every E16 window (|E16| <= 3N * 127); real
+  // couplings have none (one placeholder level)
+  const bool real = p->model == PA_MODEL_GAUSS;
+  l.n_levels = p->model == PA_MODEL_GAUSS16 ? 6 * l.N * (uint32_t)pa::kGaussKMax + 1
+               : real                       ? 1
+                                            : 3 * l.N + 1;
   l.rowk_stride = (6 * (l.L / 2) + 3) / 4 * 4;
   l.n_blocks = l.capacity / pa::kBlockCounts;
   const size_t tiles = l.capacity / 64;
@@ -91,7 +95,8 @@ bool make_layout(const pa_params* p, Layout* out) {
     return at;
   };
   for (int b = 0; b < 2; ++b) l.off_spins[b] = take(l.spins_bytes);
-  for (int b = 0; b < 2; ++b) l.off_U[b] = take((size_t)l.capacity * 4);
+  // energy words: u32 (PA_MODEL_PM, PA_MODEL_GAUSS16) or int64 (PA_MODEL_GAUSS)
+  for (int b = 0; b < 2; ++b) l.off_U[b] = take((size_t)l.capacity * (real ? 8 : 4));
   for (int b = 0; b < 2; ++b) l.off_fam[b] = take((size_t)l.capacity * 4);
   l.off_counts = take((size_t)l.capacity * 4);
   l.off_offsets = take((size_t)l.capacity * 4);
@@ -102,8 +107,9 @@ bool make_layout(const pa_params* p, Layout* out) {
   // the histogram and the device scalars side by side: one copy brings both
   // to the host after a step (PA_MODEL_PM, whose histogram covers every level)
   l.hist_bytes = ((size_t)l.n_levels * 4 + 63) / 64 * 64;
-  l.off_hist = take(l.hist_bytes + sizeof(DevScalars));
+  l.off_hist = take(l.hist_bytes + sizeof(DevScalars) + sizeof(pa::RealScalars));
   l.off_sc = l.off_hist + l.hist_bytes;
+  l.off_rs = l.off_sc + sizeof(DevScalars);
   l.off_table = take((size_t)l.n_levels * sizeof(pa::TableEntry));
   l.off_sites = take((size_t)l.N * sizeof(SiteEntry));
   l.off_psites = take((size_t)l.N * sizeof(pa::PlaneSite));
@@ -116,6 +122,12 @@ bool make_layout(const pa_params* p, Layout* out) {
   l.off_lpart = take((size_t)pa::kLinkCopies * (3 * l.N + 1) * 4);
   l.off_pops = take(2 * sizeof(DevPop));
   l.off_meta = take(sizeof(MetaU32));
+  // PA_MODEL_GAUSS: the he and threshold tables of every (site, pattern), and
+  // one reduction partial per workgroup of the slot kernels
+  const size_t per_site = real ? (size_t)l.N * pa::kRealPatterns * 8 : 0;
+  l.off_rhe = take(per_site);
+  l.off_rthr = take(per_site);
+  l.off_rpart = take(real ? (size_t)l.n_blocks * sizeof(pa::RealPartial) : 0);
   l.total = o;
   *out = l;
   return true;
@@ -374,6 +386,22 @@ int fetch_hist(pa_instance* in, bool with_family) {
   const DevPop& P = in->dev;
   const pa::BatchDev B = one_set(in, plain_step(in->cur));
   PA_HIP(in, pa::launch_zero_acc(B, group_of(in, in->d_meta->perpop, 1), in->stream));
+  if (P.model == pa::kModelReal) {
+    // no levels: the lowest energy, the replicas at it and the energy sum
+    PA_HIP(in, pa::launch_real_stats(B, group_of(in, in->d_meta->slots, in->meta.slots[1]),
+                                     in->stream));
+    if (with_family)
+      PA_HIP(in, pa::launch_family(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), false,
+                                   in->stream));
+    PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars) + sizeof(pa::RealScalars),
+                              hipMemcpyDeviceToHost, in->stream));
+    PA_HIP(in, hipStreamSynchronize(in->stream));
+    PA_HIP(in, read_sweep_time(in));
+    if (in->h_sc->err == 2) return dev_fail(in);
+    in->R_tilde = in->h_sc->R_tilde;
+    in->hist_valid = true;
+    return PA_OK;
+  }
   uint32_t n = P.n_levels;
   if (P.model == pa::kModelGauss16) {
     PA_HIP(in, pa::launch_minmax(B, group_of(in, in->d_meta->hist, in->meta.hist[1]), in->stream));
@@ -416,6 +444,8 @@ int fetch_hist(pa_instance* in, bool with_family) {
 // stream-ordered, through a pinned buffer that is refilled only after the
 // previous copy out of it has completed.
 hipError_t set_thresholds(pa_instance* in, double beta, pa::PopStep* ps) {
+  if (in->dev.model == pa::kModelReal)  // the (site, pattern) table, on the device
+    return pa::launch_real_thresholds(in->dev, beta, in->stream);
   if (in->dev.model != pa::kModelGauss16) {
     thresholds(beta, ps->thr);
     return hipSuccess;
@@ -491,6 +521,28 @@ void philox_host(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0
 // the beta_next in (beta, beta_max] whose culling fraction is eps_target, by
 // 64 bisection halvings keeping the lower end (pa_choose_beta).
 int choose_from_hist(pa_instance* in, double eps_target, double beta_max, double* beta_next) {
+  if (in->dev.model == pa::kModelReal) {
+    // the same bisection on the device (weights of every replica): 66
+    // evaluations of the culling fraction, each a weight sum and a culled
+    // mass, decided and advanced by the last workgroup of each
+    const double rem = beta_max - in->beta;
+    const pa::BatchDev B = one_set(in, plain_step(in->cur));
+    const pa::Group g = group_of(in, in->d_meta->slots, in->meta.slots[1]);
+    PA_HIP(in, pa::launch_real_bisect_init(in->dev, rem, eps_target, in->stream));
+    for (int e = 0; e < 66; ++e) PA_HIP(in, pa::launch_real_bisect_eval(B, g, in->stream));
+    PA_HIP(in, hipMemcpyAsync(in->h_rs, in->dev.rs, sizeof(pa::RealScalars),
+                              hipMemcpyDeviceToHost, in->stream));
+    PA_HIP(in, hipStreamSynchronize(in->stream));
+    const int32_t res = in->h_rs->result;
+    if (res == -1) return PA_ESCHEDULE;
+    if (res == 1) {
+      *beta_next = beta_max;
+      return PA_OK;
+    }
+    if (res != 2) return dev_fail(in);
+    *beta_next = in->beta + in->h_rs->lo;
+    return PA_OK;
+  }
   const Levels lv = levels_of(in);
   const uint32_t nl = lv.n, R = in->dev.R;
   const uint32_t* h = in->h_hist;
@@ -549,6 +601,25 @@ int choose_from_hist(pa_instance* in, double eps_target, double beta_max, double
 int queue_resample(pa_instance* in, double beta_next, Table* t, uint32_t step_flags = 0) {
   const DevPop& P = in->dev;
   const double dbeta = beta_next - in->beta;
+  if (P.model == pa::kModelReal) {
+    // weights on the device: S at dbeta, then the counts (and the culled
+    // fraction) from it; ln Q and eps are taken when the scalars come back
+    if (in->R_tilde == 0) return PA_ESTATE;
+    *t = Table{};
+    t->jmin = 0;
+    in->r_Emin_pre = in->h_rs->E_min;
+    pa::PopStep ps = plain_step(in->cur);
+    ps.step = in->step + 1;
+    ps.flags = step_flags;
+    ps.dbeta = dbeta;
+    const pa::BatchDev B = one_set(in, ps);
+    const pa::Group g = group_of(in, in->d_meta->slots, in->meta.slots[1]);
+    PA_HIP(in, pa::launch_real_sum(B, g, false, in->stream));
+    PA_HIP(in, pa::launch_real_counts(B, g, in->stream));
+    PA_HIP(in, pa::launch_scan(B, group_of(in, in->d_meta->perpop, 1), in->stream));
+    PA_HIP(in, pa::launch_scatter(B, g, in->stream));
+    return PA_OK;
+  }
   const Levels lv = levels_of(in);
   *t = resample_table(in->h_hist, lv.n, lv.unit, lv.E_lo, P.R, in->R_tilde, dbeta, in->h_table);
   if (t->jmin < 0) return PA_ESTATE;  // empty population
@@ -565,6 +636,17 @@ int queue_resample(pa_instance* in, double beta_next, Table* t, uint32_t step_fl
   // k_scatter does nothing when the scan flagged an overflow
   PA_HIP(in, pa::launch_scatter(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
   return PA_OK;
+}
+
+// PA_MODEL_GAUSS: ln Q (Eq. 2) and eps of a queued step from the scalars the
+// device computed (in->h_rs after a synchronisation): ln Q = ln S - ln R~ -
+// dbeta E_min with E_min the lowest energy of the population it weighed.
+void finish_real_table(pa_instance* in, Table* t, double dbeta, uint32_t R_old) {
+  if (in->dev.model != pa::kModelReal) return;
+  t->S = in->h_rs->S;
+  t->lnQ = std::log(t->S) - std::log((double)R_old) -
+           dbeta * std::ldexp((double)in->r_Emin_pre, -32);
+  t->eps = in->h_rs->eps;
 }
 
 // The host mirror after a resampling step that fitted (in->h_sc holds the
@@ -585,8 +667,60 @@ void commit_resample(pa_instance* in, const Table& t, double beta_next, uint32_t
 
 // Scalars of the current population from in->h_hist and in->h_sc (filled by
 // fetch_hist with the family sums).
+// A 128-bit two's-complement integer rounded to FP64 (nearest, ties to even).
+double i128_to_double(unsigned long long lo, long long hi) {
+  const bool neg = hi < 0;
+  unsigned __int128 x = ((unsigned __int128)(unsigned long long)hi << 64) | lo;
+  if (neg) x = ~x + 1;
+  if (x == 0) return 0.0;
+  int p = 127;
+  while (!((x >> p) & 1)) --p;
+  double v;
+  if (p <= 52) {
+    v = (double)(unsigned long long)x;
+  } else {
+    const int sh = p - 52;
+    unsigned __int128 mant = x >> sh;
+    const unsigned __int128 rem = x - (mant << sh), half = (unsigned __int128)1 << (sh - 1);
+    int e = sh;
+    if (rem > half || (rem == half && (mant & 1))) {
+      mant += 1;
+      if (mant >> 53) {
+        mant >>= 1;
+        e += 1;
+      }
+    }
+    v = std::ldexp((double)(unsigned long long)mant, e);
+  }
+  return neg ? -v : v;
+}
+
 void fill_observables(pa_instance* in, pa_obs* out) {
   const DevPop& P = in->dev;
+  if (P.model == pa::kModelReal) {
+    const pa::RealScalars& rs = *in->h_rs;
+    std::memset(out, 0, sizeof(*out));
+    out->beta = in->beta;
+    out->dbeta = in->last_dbeta;
+    out->lnQ = in->last_lnQ;
+    out->beta_F = -((double)P.N * std::log(2.0) + in->sum_lnQ);
+    out->mean_E = in->R_tilde ? i128_to_double(rs.sumE_lo, rs.sumE_hi) / (double)in->R_tilde *
+                                    std::ldexp(1.0, -32)
+                              : 0.0;
+    out->sum_eta2 = in->h_sc->sum_eta2;
+    out->rho_t = (double)out->sum_eta2 / (double)P.R;
+    out->eps_expected = in->last_eps;
+    out->R_tilde = in->R_tilde;
+    out->n_culled = in->last_n_culled;
+    out->E_min = 0;
+    out->E_lowest = std::ldexp((double)rs.E_min, -32);
+    out->n_at_E_min = rs.n_at_min;
+    out->step = in->step;
+    out->sweeps_done = in->sweeps;
+    out->sum_lnQ = in->sum_lnQ;
+    out->sweep_ms = in->last_sweep_ms;
+    return;
+  }
   const uint32_t* h = in->h_hist;
   const bool gauss = P.model == pa::kModelGauss16;
   const Levels lv = levels_of(in);
@@ -612,6 +746,7 @@ void fill_observables(pa_instance* in, pa_obs* out) {
   out->n_culled = in->last_n_culled;
   out->E_min = jmin < 0 ? 0 : gauss ? (int32_t)(lv.E_lo + jmin) : 2 * jmin - 3 * (int)P.N;
   out->n_at_E_min = jmin >= 0 ? h[jmin] : 0u;
+  out->E_lowest = gauss ? (double)out->E_min / 16.0 : (double)out->E_min;
   out->step = in->step;
   out->sweeps_done = in->sweeps;
   out->sum_lnQ = in->sum_lnQ;
@@ -752,6 +887,7 @@ int anneal_steps(pa_instance* in, double eps_target, double beta_max, double bet
         in->hist_valid = false;
         return PA_ECAPACITY;
       }
+      finish_real_table(in, &t, b - in->beta, R_old);
       commit_resample(in, t, b, R_old);
       in->R_tilde = in->h_sc->R_tilde;
       in->pending_gather = false;
@@ -835,19 +971,22 @@ const char* pa_strerror(int status) {
   }
 }
 
-int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace, size_t ws_bytes,
-                     void* hip_stream, pa_instance** out) {
+}  // extern "C"
+
+namespace {
+
+// The body of pa_init_instance and pa_init_instance_real.  rhe: the he table
+// of PA_MODEL_GAUSS (N x 64, colour-major), else null; J_host then only
+// shapes the lattice tables.
+int init_instance(const pa_params* p, const int8_t* J_host, const std::vector<long long>* rhe,
+                  void* d_workspace, size_t ws_bytes, void* hip_stream, pa_instance** out) {
   if (!out) return PA_EINVAL;
   *out = nullptr;
   Layout l;
   if (!make_layout(p, &l) || !J_host || !d_workspace) return PA_EINVAL;
+  if ((l.model == PA_MODEL_GAUSS) != (rhe != nullptr)) return PA_EINVAL;
   if (ws_bytes < l.total) return PA_ENOMEM;
   if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) return PA_EINVAL;
-  for (uint32_t b = 0; b < 3 * l.N; ++b) {
-    if (l.model == PA_MODEL_PM && J_host[b] != 1 && J_host[b] != -1) return PA_EINVAL;
-    if (l.model == PA_MODEL_GAUSS16 && (J_host[b] < -pa::kGaussKMax || J_host[b] > pa::kGaussKMax))
-      return PA_EINVAL;
-  }
 
   pa_instance* in = new (std::nothrow) pa_instance();
   if (!in) return PA_EINVAL;
@@ -899,6 +1038,11 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   P.rowk_stride = l.rowk_stride;
   P.rowk = reinterpret_cast<const int8_t*>(w + l.off_rowk);
   P.gthr = reinterpret_cast<const unsigned long long*>(w + l.off_gthr);
+  const bool real = l.model == PA_MODEL_GAUSS;
+  P.rhe = real ? reinterpret_cast<const long long*>(w + l.off_rhe) : nullptr;
+  P.rthr = real ? reinterpret_cast<unsigned long long*>(w + l.off_rthr) : nullptr;
+  P.rs = reinterpret_cast<pa::RealScalars*>(w + l.off_rs);
+  P.rpart = real ? reinterpret_cast<pa::RealPartial*>(w + l.off_rpart) : nullptr;
   in->d_pops = reinterpret_cast<DevPop*>(w + l.off_pops);
   in->d_meta = reinterpret_cast<MetaU32*>(w + l.off_meta);
   MetaU32& mt = in->meta;
@@ -916,8 +1060,8 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
     return rc;
   };
   // histogram and scalars in one pinned block, laid out as in the workspace
-  if (hipHostMalloc(reinterpret_cast<void**>(&in->h_hist), l.hist_bytes + sizeof(DevScalars)) !=
-          hipSuccess ||
+  if (hipHostMalloc(reinterpret_cast<void**>(&in->h_hist),
+                    l.hist_bytes + sizeof(DevScalars) + sizeof(pa::RealScalars)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_table),
                     (size_t)l.n_levels * sizeof(pa::TableEntry)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&in->h_ovl), 65 * 8) != hipSuccess ||
@@ -926,6 +1070,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
       hipHostMalloc(reinterpret_cast<void**>(&in->h_meta), sizeof(MetaU32)) != hipSuccess)
     return fail(PA_EDEVICE);
   in->h_sc = reinterpret_cast<DevScalars*>(reinterpret_cast<uint8_t*>(in->h_hist) + l.hist_bytes);
+  in->h_rs = reinterpret_cast<pa::RealScalars*>(in->h_sc + 1);
   if (hipHostMalloc(reinterpret_cast<void**>(&in->h_eta2), 2 * sizeof(unsigned long long)) !=
           hipSuccess ||
       hipEventCreateWithFlags(&in->ev_step, hipEventDisableTiming) != hipSuccess ||
@@ -951,6 +1096,7 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   // tables and scalars (synchronous copies from pageable host memory)
   DevScalars sc{};
   sc.R_tilde = l.R;
+  const pa::RealScalars rs0{};
   if (hipMemcpyAsync(w + l.off_sites, in->sites.data(), l.N * sizeof(SiteEntry),
                      hipMemcpyHostToDevice, in->stream) != hipSuccess ||
       hipMemcpyAsync(w + l.off_cm, in->cm_of_site.data(), l.N * 2, hipMemcpyHostToDevice,
@@ -963,6 +1109,9 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
        hipMemcpyAsync(w + l.off_rowk, in->rowk.data(), in->rowk.size(), hipMemcpyHostToDevice,
                       in->stream) != hipSuccess) ||
       hipMemcpyAsync(P.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, in->stream) != hipSuccess ||
+      hipMemcpyAsync(P.rs, &rs0, sizeof(rs0), hipMemcpyHostToDevice, in->stream) != hipSuccess ||
+      (real && hipMemcpyAsync(w + l.off_rhe, rhe->data(), rhe->size() * 8, hipMemcpyHostToDevice,
+                              in->stream) != hipSuccess) ||
       hipMemcpyAsync(in->d_pops, &in->dev, sizeof(DevPop), hipMemcpyHostToDevice, in->stream) !=
           hipSuccess ||
       hipMemcpyAsync(in->d_meta, &in->meta, sizeof(MetaU32), hipMemcpyHostToDevice, in->stream) !=
@@ -970,8 +1119,8 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
       hipStreamSynchronize(in->stream) != hipSuccess)
     return fail(PA_EDEVICE);
   if (pa::launch_init(P, 0, in->stream) != hipSuccess) return fail(PA_EDEVICE);
-  // quantised Gaussian couplings: the energy word is E16, formed from the spins
-  if (l.model == PA_MODEL_GAUSS16 &&
+  // Gaussian couplings: the energy word (E16 or E32) is formed from the spins
+  if ((l.model == PA_MODEL_GAUSS16 || real) &&
       pa::launch_energy(one_set(in, plain_step(0)), group_of(in, in->d_meta->etiles, mt.etiles[1]),
                         l.layout, l.L, l.model, false, in->stream) != hipSuccess)
     return fail(PA_EDEVICE);
@@ -982,6 +1131,95 @@ int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace
   in->cur = 0;
   in->R_tilde = l.R;
   *out = in;
+  return PA_OK;
+}
+
+// he[cm][y] of PA_MODEL_GAUSS from couplings k (units 2^-32): for the site at
+// colour-major index cm and its couplings k_0..k_5 to the neighbours
+// +x,-x,+y,-y,+z,-z, he = sum_k k_k (1 - 2 y_k) over the bits y_k of y.
+std::vector<long long> real_he_table(uint32_t L, const std::vector<long long>& k) {
+  const uint32_t N = L * L * L, half = N / 2;
+  std::vector<long long> he((size_t)N * pa::kRealPatterns);
+  for (uint32_t z = 0; z < L; ++z)
+    for (uint32_t y = 0; y < L; ++y)
+      for (uint32_t x = 0; x < L; ++x) {
+        const uint32_t s = x + L * (y + L * z);
+        const uint32_t cm = ((x + y + z) & 1u) * half + (s >> 1);
+        const uint32_t xm = (x + L - 1) % L, ym = (y + L - 1) % L, zm = (z + L - 1) % L;
+        const long long kb[6] = {k[0 * N + s], k[0 * N + (xm + L * (y + L * z))],
+                                 k[1 * N + s], k[1 * N + (x + L * (ym + L * z))],
+                                 k[2 * N + s], k[2 * N + (x + L * (y + L * zm))]};
+        for (uint32_t pat = 0; pat < pa::kRealPatterns; ++pat) {
+          long long v = 0;
+          for (int b = 0; b < 6; ++b) v += ((pat >> b) & 1u) ? -kb[b] : kb[b];
+          he[(size_t)cm * pa::kRealPatterns + pat] = v;
+        }
+      }
+  return he;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pa_init_instance(const pa_params* p, const int8_t* J_host, void* d_workspace, size_t ws_bytes,
+                     void* hip_stream, pa_instance** out) {
+  if (p && p->model == PA_MODEL_GAUSS) return PA_EINVAL;  // real couplings: pa_init_instance_real
+  if (p && J_host && p->L >= 4 && p->L <= (uint32_t)pa::kMaxL) {
+    const uint32_t N = p->L * p->L * p->L;
+    for (uint32_t b = 0; b < 3 * N; ++b) {
+      if (p->model == PA_MODEL_PM && J_host[b] != 1 && J_host[b] != -1) return PA_EINVAL;
+      if (p->model == PA_MODEL_GAUSS16 &&
+          (J_host[b] < -pa::kGaussKMax || J_host[b] > pa::kGaussKMax))
+        return PA_EINVAL;
+    }
+  }
+  return init_instance(p, J_host, nullptr, d_workspace, ws_bytes, hip_stream, out);
+}
+
+int pa_init_instance_real(const pa_params* p, const double* J_host, void* d_workspace,
+                          size_t ws_bytes, void* hip_stream, pa_instance** out) {
+  if (!out) return PA_EINVAL;
+  *out = nullptr;
+  if (!p || !J_host || p->model != PA_MODEL_GAUSS) return PA_EINVAL;
+  if (p->L < 4 || p->L > (uint32_t)pa::kMaxL || (p->L & 1u)) return PA_EINVAL;
+  const uint32_t N = p->L * p->L * p->L;
+  // each coupling to the nearest multiple of 2^-32 (ties to even: the
+  // default rounding of nearbyint), as the integer k = J 2^32
+  std::vector<long long> k(3 * (size_t)N);
+  for (uint32_t b = 0; b < 3 * N; ++b) {
+    const double J = J_host[b];
+    if (!std::isfinite(J) || !(std::fabs(J) < 8.0)) return PA_EINVAL;
+    k[b] = (long long)std::nearbyint(std::ldexp(J, 32));
+  }
+  const std::vector<long long> he = real_he_table(p->L, k);
+  // the lattice tables need couplings only for the +-J bit words, unused here
+  const std::vector<int8_t> ones(3 * (size_t)N, (int8_t)1);
+  return init_instance(p, ones.data(), &he, d_workspace, ws_bytes, hip_stream, out);
+}
+
+int pa_export_energies(pa_instance* in, double* E_host) {
+  if (int rc0 = enter(in)) return rc0;
+  if (!E_host) return PA_EINVAL;
+  int rc = materialize(in);
+  if (rc) return rc;
+  const DevPop& P = in->dev;
+  PA_HIP(in, hipMemcpyAsync(in->h_sc, P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, in->stream));
+  PA_HIP(in, hipStreamSynchronize(in->stream));
+  const uint32_t R = in->h_sc->R_tilde;
+  in->R_tilde = R;
+  if (R == 0) return PA_OK;
+  if (P.model == pa::kModelReal) {
+    std::vector<long long> e(R);
+    PA_HIP(in, hipMemcpy(e.data(), P.U[in->cur], (size_t)R * 8, hipMemcpyDeviceToHost));
+    for (uint32_t r = 0; r < R; ++r) E_host[r] = std::ldexp((double)e[r], -32);
+  } else {
+    std::vector<uint32_t> u(R);
+    PA_HIP(in, hipMemcpy(u.data(), P.U[in->cur], (size_t)R * 4, hipMemcpyDeviceToHost));
+    for (uint32_t r = 0; r < R; ++r)
+      E_host[r] = P.model == pa::kModelGauss16 ? (double)(int32_t)u[r] / 16.0
+                                               : 2.0 * (double)u[r] - 3.0 * (double)P.N;
+  }
   return PA_OK;
 }
 
@@ -1057,11 +1295,12 @@ int pa_resample(pa_instance* in, double beta_next, pa_obs* step_out) {
   Table t;
   rc = queue_resample(in, beta_next, &t);
   if (rc) return rc;
-  PA_HIP(in, hipMemcpyAsync(in->h_sc, in->dev.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
-                            in->stream));
+  PA_HIP(in, hipMemcpyAsync(in->h_sc, in->dev.sc, sizeof(DevScalars) + sizeof(pa::RealScalars),
+                            hipMemcpyDeviceToHost, in->stream));
   PA_HIP(in, hipStreamSynchronize(in->stream));
   if (in->h_sc->err == 2) return dev_fail(in);
   if (in->h_sc->err) return PA_ECAPACITY;  // population untouched
+  finish_real_table(in, &t, beta_next - in->beta, in->R_tilde);
   commit_resample(in, t, beta_next, in->R_tilde);
   if (step_out) {
     std::memset(step_out, 0, sizeof(*step_out));
@@ -1212,6 +1451,7 @@ int pa_export_state(pa_instance* in, int8_t* spins_host, uint32_t* U_host, uint3
                     uint32_t* R_tilde) {
   if (int rc0 = enter(in)) return rc0;
   if (!R_tilde) return PA_EINVAL;
+  if (U_host && in->dev.model == pa::kModelReal) return PA_EINVAL;  // pa_export_energies
   int rc = materialize(in);
   if (rc) return rc;
   const DevPop& P = in->dev;

@@ -35,7 +35,7 @@ struct Layout {
   size_t hist_bytes;  // the histogram's share of its block (n_levels words, 64-byte multiple)
   size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
       off_bcull, off_hist, off_table, off_sites, off_psites, off_cm, off_rowj, off_rowk, off_gthr, off_ovl,
-      off_lovl, off_lpart, off_sc, off_pops, off_meta;
+      off_lovl, off_lpart, off_sc, off_rs, off_pops, off_meta, off_rhe, off_rthr, off_rpart;
   size_t total;
 };
 
@@ -103,6 +103,9 @@ struct pa_instance {
   uint32_t* h_hist = nullptr;
   pa::TableEntry* h_table = nullptr;  // staging of the resampling table
   pa::DevScalars* h_sc = nullptr;
+  pa::RealScalars* h_rs = nullptr;    // PA_MODEL_GAUSS: after h_sc in the same block
+  long long r_Emin_pre = 0;           // PA_MODEL_GAUSS: E_min of the population a queued
+                                      // resampling step weighs (its ln Q needs it)
   unsigned long long* h_ovl = nullptr;
   unsigned long long* h_lovl = nullptr;  // 3N + 1 link-overlap counts
   pa_host::MetaU32* h_meta = nullptr;

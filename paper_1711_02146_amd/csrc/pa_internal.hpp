@@ -42,6 +42,15 @@ constexpr uint32_t kLinkCopies = 32;  // partial link-overlap histograms (see la
 // stored as int32.
 constexpr uint32_t kModelPm = 0;
 constexpr uint32_t kModelGauss16 = 1;
+// kModelReal: real Gaussian couplings (Sec. II.A) carried on the grid 2^-32
+// with |J| < 8.  The energy word is the int64 E32 = E 2^32, exact: every sum
+// of at most 3N such couplings fits in 49 bits.  Per site (colour-major cm)
+// and per pattern y of its six "neighbour differs" bits (bit k: s_i != s_k,
+// k in the order +x,-x,+y,-y,+z,-z), he[cm][y] = sum_k k_k (1 - 2 y_k) with
+// k_k = J_k 2^32: flipping s_i changes E32 by 2 he, and the site's bond
+// energy is -he before and +he after the flip.
+constexpr uint32_t kModelReal = 2;
+constexpr uint32_t kRealPatterns = 64;  // patterns y per site
 constexpr int kGaussKMax = 127;
 constexpr int kGaussDEMax = 2 * 6 * kGaussKMax;  // largest |dE16| of one flip
 
@@ -87,6 +96,36 @@ struct DevScalars {
 };
 static_assert(sizeof(DevScalars) == 64, "DevScalars is 64 bytes");
 
+// Device scalars of a kModelReal population (after DevScalars in the same
+// block, so one copy brings both to the host).  The reductions over replicas
+// finish in the last workgroup to arrive (counter `done`, reset by it).
+struct RealScalars {
+  long long E_min;             // lowest energy word (k_rstats)
+  unsigned long long sumE_lo;  // sum of the energy words, a 128-bit two's-complement
+  long long sumE_hi;           //   integer (low and high word)
+  uint32_t n_at_min;           // replicas at E_min
+  uint32_t done;               // workgroups arrived at the current reduction
+  double S;                    // sum of the weights of dbeta (Eq. 2, fixed point, rounded)
+  double eps;                  // culled fraction (Sec. III.C) of the last copy-count pass
+  double dbeta;                // the step the bisection evaluates next
+  double lo, hi;               // bisection interval
+  double rem, target;          // remaining range and culling target of the bisection
+  uint32_t phase;              // evaluations the bisection has finished
+  int32_t result;              // 0 running, 1 whole range, 2 bisected (lo), -1 impossible
+  uint32_t pad[4];
+};
+static_assert(sizeof(RealScalars) == 112, "RealScalars is 112 bytes");
+
+// One workgroup's share of a kModelReal reduction.
+struct RealPartial {
+  unsigned long long lo;  // fixed-point sum (unsigned) or energy sum (signed), low word
+  unsigned long long hi;  //   high word
+  long long m;            // lowest energy word
+  uint32_t c;             // replicas at m
+  uint32_t pad;
+};
+static_assert(sizeof(RealPartial) == 32, "RealPartial is 32 bytes");
+
 // One energy level of the resampling table (Sec. II copy rule): a replica
 // at that level gets fl copies, and one more iff a 53-bit draw is below T.
 // The two live together so that the table goes to the device in one copy.
@@ -131,6 +170,11 @@ struct DevPop {
                                 // coupling k of its site q to neighbour k (J = k / 16)
   const unsigned long long* gthr;  // kModelGauss16: thr[d] = floor(2^32 exp(-beta d / 16)),
                                    // d = 0..kGaussDEMax, for the coming sweep
+  const long long* rhe;            // kModelReal: he[cm][y], N x 64 (see kModelReal)
+  unsigned long long* rthr;        // kModelReal: Metropolis threshold of (cm, y) for the
+                                   // coming sweep, N x 64
+  RealScalars* rs;                 // kModelReal: scalars of the weight reductions
+  RealPartial* rpart;              // kModelReal: one per workgroup of kBlockCounts slots
 };
 
 // Parameters of one population for one launch.
@@ -143,7 +187,7 @@ struct PopStep {
   uint32_t cur;               // buffer holding the population at the start of the launch
   uint32_t step;              // resampling step index k (copy-count Philox counter)
   uint32_t flags;             // kStepSticky: an overflow marks the population dead; kStepHist
-  uint32_t pad[2];
+  double dbeta;               // kModelReal: the resampling step of the copy-count pass
 };
 static_assert(sizeof(PopStep) == 64, "PopStep is 64 bytes");
 constexpr uint32_t kStepSticky = 1u;
@@ -240,6 +284,24 @@ hipError_t launch_minmax(const BatchDev& B, const Group& g, hipStream_t stream);
 hipError_t launch_hist_window(const BatchDev& B, const Group& g, uint32_t n_win,
                               hipStream_t stream);
 hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream);
+
+// kModelReal (pa_real.hip), single populations, on the current buffer:
+// thresholds of every (site, pattern) at beta for the coming sweep
+hipError_t launch_real_thresholds(const DevPop& P, double beta, hipStream_t stream);
+// E_min, replicas at E_min and the sum of the energy words into P.rs
+hipError_t launch_real_stats(const BatchDev& B, const Group& slots, hipStream_t stream);
+// the sum S of the weights exp(-dbeta (E - E_min)) into P.rs->S: dbeta of the
+// step parameters (bisect = false) or the bisection's next candidate
+hipError_t launch_real_sum(const BatchDev& B, const Group& slots, bool bisect, hipStream_t stream);
+// the constant-culling bisection (Sec. III.C): set up for the remaining range
+// and target, then one evaluation (weight sum + culled mass + decision) per
+// launch_real_bisect_eval; 66 of them finish it (P.rs->result)
+hipError_t launch_real_bisect_init(const DevPop& P, double rem, double target,
+                                   hipStream_t stream);
+hipError_t launch_real_bisect_eval(const BatchDev& B, const Group& slots, hipStream_t stream);
+// copy counts of the step (after launch_real_sum at its dbeta): counts, block
+// sums and culled counts as k_counts, and the culled fraction into P.rs->eps
+hipError_t launch_real_counts(const BatchDev& B, const Group& slots, hipStream_t stream);
 
 // Blocks each population needs in each kind of launch.
 inline uint32_t blocks_hist(uint32_t capacity) { return (capacity + kHistSlots - 1) / kHistSlots; }

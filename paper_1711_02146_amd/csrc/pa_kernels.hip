@@ -263,6 +263,20 @@ struct TileCtx {
   const int8_t* rowk;                  // row couplings (see DevPop)
   uint32_t rowk_stride;
   const unsigned long long* gtab;      // LDS copy of the dE16 threshold table
+  // kModelReal
+  const unsigned long long* rthr;      // thresholds of (site, pattern) for this sweep
+  const long long* rhe;                // half energy changes he of (site, pattern)
+};
+
+// Energy accumulator of a pass: 32-bit words for the integer models (the
+// sums wrap like the stored words), 64-bit for kModelReal.
+template <int M>
+struct AccOf {
+  using type = uint32_t;
+};
+template <>
+struct AccOf<(int)kModelReal> {
+  using type = long long;
 };
 
 // A uniform byte offset kept whole in a scalar register.  Added to the lane's
@@ -289,6 +303,7 @@ struct RowAddr {
   const uint32_t* mz;
   unsigned long long j;  // coupling bits of the row (kModelPm)
   ConstU32* krow;        // coupling bytes of the row, 4 per word (kModelGauss16)
+  uint32_t cm0;          // colour-major index of the row's first site (kModelReal)
 };
 
 template <int L, int M>
@@ -313,9 +328,13 @@ __device__ __forceinline__ RowAddr row_addr(const TileCtx& c, const unsigned lon
   // The coupling words are read through the constant address space: the
   // index is uniform and nothing in the kernel writes them, so they arrive in
   // scalar registers and the per-bond masks and bytes are scalar work.
+  a.cm0 = own0 + H * rho;
   if constexpr (M == (int)kModelGauss16) {
     a.j = 0;
     a.krow = (const ConstU32*)(c.rowk + (size_t)(colour * L * L + rho) * c.rowk_stride);
+  } else if constexpr (M == (int)kModelReal) {
+    a.j = 0;
+    a.krow = nullptr;
   } else {
     a.j = ((const ConstU64*)rowj)[colour * L * L + rho];
     a.krow = nullptr;
@@ -428,6 +447,36 @@ __device__ __forceinline__ void site_update_g(const TileCtx& c, const RowAddr& a
   if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Pattern y of a site for this lane: bit k set iff neighbour k's spin differs
+// from the site's own (k in the order +x,-x,+y,-y,+z,-z).
+__device__ __forceinline__ uint32_t real_pattern(const TileCtx& c, const SiteLoad& w) {
+  uint32_t y = __builtin_amdgcn_ubfe(w.nb[0] ^ w.own, c.pos, 1);
+#pragma unroll
+  for (int k = 1; k < 6; ++k) y |= __builtin_amdgcn_ubfe(w.nb[k] ^ w.own, c.pos, 1) << k;
+  return y;
+}
+
+// Metropolis update of one site for real couplings: the move is taken iff
+// the draw is below thr[cm][y] (the table of the sweep's beta, 2^32 for
+// dE <= 0); with ACCUM the pass also sums the site's post-move bond energy,
+// +he[cm][y] if the spin flipped and -he[cm][y] if not (in the colour-1 pass
+// of the last sweep that is the energy word E32).
+template <int L, int Q, bool ACCUM>
+__device__ __forceinline__ void site_update_r(const TileCtx& c, const RowAddr& a,
+                                              const SiteLoad& w, uint32_t draw, long long& esum) {
+  uint32_t* const own_p = const_cast<uint32_t*>(a.own) + 2 * Q;
+  const uint32_t idx = (a.cm0 + Q) * kRealPatterns + real_pattern(c, w);
+  const unsigned long long thr = c.rthr[idx];
+  const bool accept = (unsigned long long)draw < thr;
+  if (ACCUM) {
+    const long long he = c.rhe[idx];
+    esum += accept ? he : -he;
+  }
+  const unsigned long long f = __ballot(accept);
+  const uint32_t fh = c.hoff ? (uint32_t)(f >> 32) : (uint32_t)f;
+  if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Sites Q.. of row I of a 4-row block.  The words of site Q + 1 are read
 // before site Q is updated: they are other-colour words (not written in this
 // pass) and a different own word, so the early read sees the same values and
@@ -435,7 +484,8 @@ __device__ __forceinline__ void site_update_g(const TileCtx& c, const RowAddr& a
 // starts every fourth site of the block.
 template <int L, int M, int I, int Q, bool ACCUM>
 __device__ __forceinline__ void block_row(const TileCtx& c, const RowAddr& a, uint32_t g0,
-                                          Words4& d, uint32_t& usum, const SiteLoad& w) {
+                                          Words4& d, typename AccOf<M>::type& usum,
+                                          const SiteLoad& w) {
   constexpr int H = L / 2;
   constexpr int S = I * H + Q;  // site index within the block
   SiteLoad wn;
@@ -445,17 +495,21 @@ __device__ __forceinline__ void block_row(const TileCtx& c, const RowAddr& a, ui
   if constexpr (S % 4 == 0) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
   if constexpr (M == (int)kModelGauss16)
     site_update_g<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
+  else if constexpr (M == (int)kModelReal)
+    site_update_r<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
   else
     site_update<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
   if constexpr (Q + 1 < H) block_row<L, M, I, Q + 1, ACCUM>(c, a, g0, d, usum, wn);
 }
 
 template <int L, int M, bool ACCUM>
-__device__ uint32_t sweep_colour_blocks(const TileCtx& c, const unsigned long long* rowj,
-                                        uint32_t colour, uint32_t part, uint32_t nparts) {
+__device__ typename AccOf<M>::type sweep_colour_blocks(const TileCtx& c,
+                                                       const unsigned long long* rowj,
+                                                       uint32_t colour, uint32_t part,
+                                                       uint32_t nparts) {
   constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L;
   const uint32_t own0 = colour * (N / 2);
-  uint32_t usum = 0;
+  typename AccOf<M>::type usum = 0;
   Words4 d;
   d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0u;
   for (uint32_t rb = 4 * part; rb < ROWS; rb += 4 * nparts) {
@@ -768,10 +822,13 @@ __device__ uint32_t sweep_colour_planes(const TileCtx& c, const PlaneSite* __res
 
 // One row's share of tile_energy_rows, sites Q.. of the row.
 template <int L, int M, int Q>
-__device__ __forceinline__ void tile_energy_row(const TileCtx& c, const RowAddr& a, uint32_t& U) {
+__device__ __forceinline__ void tile_energy_row(const TileCtx& c, const RowAddr& a,
+                                                typename AccOf<M>::type& U) {
   constexpr int H = L / 2;
   const SiteLoad w = load_site_words<L, Q>(a);
-  if constexpr (M == (int)kModelGauss16) {
+  if constexpr (M == (int)kModelReal) {
+    U -= c.rhe[(a.cm0 + Q) * kRealPatterns + real_pattern(c, w)];
+  } else if constexpr (M == (int)kModelGauss16) {
     const int32_t k0 = row_k<Q, 0>(a), k1 = row_k<Q, 1>(a), k2 = row_k<Q, 2>(a);
     const int32_t k3 = row_k<Q, 3>(a), k4 = row_k<Q, 4>(a), k5 = row_k<Q, 5>(a);
     const int32_t csum = k0 + k1 + k2 + k3 + k4 + k5;
@@ -799,10 +856,11 @@ __device__ __forceinline__ void tile_energy_row(const TileCtx& c, const RowAddr&
 // bond joins one site of each colour); for kModelGauss16 the sum over colour-0
 // sites of -sum_k k_k s_i s_k = 2 acc - csum (see site_update_g), i.e. E16.
 template <int L, int M>
-__device__ uint32_t tile_energy_rows(const TileCtx& c, const unsigned long long* rowj,
-                                     uint32_t part, uint32_t nparts) {
+__device__ typename AccOf<M>::type tile_energy_rows(const TileCtx& c,
+                                                    const unsigned long long* rowj, uint32_t part,
+                                                    uint32_t nparts) {
   constexpr uint32_t ROWS = L * L;
-  uint32_t U = 0;
+  typename AccOf<M>::type U = 0;
   for (uint32_t rho = part; rho < ROWS; rho += nparts) {
     const RowAddr a = row_addr<L, M>(c, rowj, 0u, __builtin_amdgcn_readfirstlane(rho));
     tile_energy_row<L, M, 0>(c, a, U);
@@ -1321,6 +1379,7 @@ __global__ __launch_bounds__(kBlockCounts) void k_scatter(BatchDev B, Group G) {
 template <int L, int M>
 constexpr int sweep_min_waves_per_eu() {
   if constexpr (M == (int)kModelGauss16) return L <= 8 ? 7 : L == 10 ? 6 : L <= 14 ? 5 : 4;
+  if constexpr (M == (int)kModelReal) return L <= 8 ? 7 : L == 10 ? 6 : L <= 14 ? 5 : 4;
   return L <= 10 ? 8 : L == 12 ? 7 : 6;
 }
 
@@ -1398,12 +1457,14 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   c.rowk = P.rowk;
   c.rowk_stride = P.rowk_stride;
   c.gtab = gtab;
+  c.rthr = P.rthr;
+  c.rhe = P.rhe;
   const unsigned long long* rowj = P.rowj;
-  uint32_t U;
+  typename AccOf<M>::type U;
   if (sp.n_sweeps == 0) {
     U = tile_energy_rows<L, M>(c, rowj, part, SPLIT);
   } else {
-    if constexpr (M == (int)kModelGauss16) {
+    if constexpr (M != (int)kModelPm) {
       for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
         c.t = sp.t0 + s;
         sweep_colour_blocks<L, M, false>(c, rowj, 0u, part, SPLIT);
@@ -1453,7 +1514,8 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   asm volatile("" : "+s"(pop2));
   // per-replica sum of the waves' shares (after the tile image, in LDS: the
   // +-J plane areas, free once every wave has passed the barrier below)
-  uint32_t* const ured = lds_all + 2 * N;
+  using Acc = typename AccOf<M>::type;
+  Acc* const ured = reinterpret_cast<Acc*>(lds_all + 2 * N);
   __syncthreads();
   ured[part * 64 + lane2] = U;
   __syncthreads();
@@ -1467,7 +1529,10 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   const uint32_t j2 = tile * 64 + lane2;
   if (j2 < Rs && part == 0) {
     const uint32_t src2 = sp2.gather ? P2.src[j2] : j2;
-    pick(P2.U, nxt2)[j2] = U;
+    if constexpr (M == (int)kModelReal)
+      reinterpret_cast<long long*>(pick(P2.U, nxt2))[j2] = U;
+    else
+      pick(P2.U, nxt2)[j2] = U;
     pick(P2.fam, nxt2)[j2] = pick(P2.fam, cur2)[src2];
   }
 }
@@ -1495,13 +1560,16 @@ __global__ __launch_bounds__(64) void k_energy(BatchDev B, Group G) {
   c.pos = lane & 31u;
   c.rowk = P.rowk;
   c.rowk_stride = P.rowk_stride;
-  const uint32_t U = tile_energy_rows<L, M>(c, P.rowj, 0u, 1u);
+  c.rhe = P.rhe;
+  const typename AccOf<M>::type U = tile_energy_rows<L, M>(c, P.rowj, 0u, 1u);
+  using Word = typename AccOf<M>::type;
+  Word* const words = reinterpret_cast<Word*>(pick(P.U, sp.cur));
   if (CHECK) {
-    const bool bad = valid && pick(P.U, sp.cur)[j] != U;
+    const bool bad = valid && words[j] != U;
     const unsigned long long m = __ballot(bad);
     if (lane == 0 && m) atomicAdd(&P.sc->check_bad, (uint32_t)__popcll(m));
   } else if (valid) {
-    pick(P.U, sp.cur)[j] = U;
+    words[j] = U;
   }
 }
 
@@ -1792,6 +1860,9 @@ __global__ __launch_bounds__(256) void k_probe_philox(uint32_t* out, uint32_t ca
   out[gid] = acc;
 }
 
+// the kernels of the real-coupling model (kModelReal)
+#include "pa_real_kernels.inc"
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1877,9 +1948,18 @@ void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t 
   // or the +-J plane areas (one per wave; the reduction area lies over them)
   const size_t after = model == kModelGauss16
                            ? 4 * 64 * split + (size_t)(kGaussDEMax + 1) * 8
+                       : model == kModelReal
+                           ? (size_t)8 * 64 * split
                            : std::max((size_t)kPlaneAreaBytes * split, (size_t)4 * 64 * split);
   const size_t lds = (size_t)L * L * L * 8 + after;
-  if (model == kModelGauss16) {
+  if (model == kModelReal) {
+    if (split == 8)
+      hipLaunchKernelGGL((k_sweep<LAYOUT, L, 8, kModelReal>), dim3(g.blocks), dim3(64 * 8), lds,
+                         stream, B, g);
+    else
+      hipLaunchKernelGGL((k_sweep<LAYOUT, L, 4, kModelReal>), dim3(g.blocks), dim3(64 * 4), lds,
+                         stream, B, g);
+  } else if (model == kModelGauss16) {
     if (split == 8)
       hipLaunchKernelGGL((k_sweep<LAYOUT, L, 8, kModelGauss16>), dim3(g.blocks), dim3(64 * 8), lds,
                          stream, B, g);
@@ -1900,7 +1980,14 @@ template <int LAYOUT, int L>
 void launch_energy_l(const BatchDev& B, const Group& g, uint32_t model, bool check,
                      hipStream_t stream) {
   const size_t lds = (size_t)L * L * L * 8;
-  if (model == kModelGauss16) {
+  if (model == kModelReal) {
+    if (check)
+      hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelReal, true>), dim3(g.blocks), dim3(64), lds,
+                         stream, B, g);
+    else
+      hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelReal, false>), dim3(g.blocks), dim3(64), lds,
+                         stream, B, g);
+  } else if (model == kModelGauss16) {
     if (check)
       hipLaunchKernelGGL((k_energy<LAYOUT, L, kModelGauss16, true>), dim3(g.blocks), dim3(64), lds,
                          stream, B, g);
@@ -2028,6 +2115,44 @@ hipError_t launch_link_overlap(const DevPop& a, const DevPop& b, uint32_t cur_a,
 
 hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, stream, step_ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_thresholds(const DevPop& P, double beta, hipStream_t stream) {
+  const uint32_t n = P.N * kRealPatterns;
+  hipLaunchKernelGGL(k_rthr, dim3((n + 255) / 256), dim3(256), 0, stream, P, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_stats(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_rstats, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_sum(const BatchDev& B, const Group& g, bool bisect, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_rsum, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g,
+                     bisect ? 1u : 0u);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_bisect_init(const DevPop& P, double rem, double target,
+                                   hipStream_t stream) {
+  hipLaunchKernelGGL(k_rbisect_init, dim3(1), dim3(64), 0, stream, P, rem, target);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_bisect_eval(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_rsum, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g, 1u);
+  hipLaunchKernelGGL(k_rcull, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_counts(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_rcounts, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
   return hipGetLastError();
 }
 

@@ -290,6 +290,7 @@ int pa_stepper_step(pa_stepper* s, pa_instance* const* pops, uint32_t n, const d
       o->R_tilde = r.R_new;
       o->n_culled = r.n_culled;
       o->E_min = r.E_min;
+      o->E_lowest = (double)r.E_min;
       o->n_at_E_min = r.n_at_E_min;
       o->step = in->step;
       o->sweeps_done = in->sweeps;

@@ -67,14 +67,14 @@ void layout_record(uint32_t model, uint32_t L, uint64_t tiles, uint32_t layout) 
 
 extern "C" int pa_layout_choice(uint32_t model, uint32_t L, uint32_t R, uint32_t* layout_out) {
   if (!layout_out) return PA_EINVAL;
-  if (model != PA_MODEL_PM && model != PA_MODEL_GAUSS16) return PA_EINVAL;
+  if (model != PA_MODEL_PM && model != PA_MODEL_GAUSS16 && model != PA_MODEL_GAUSS) return PA_EINVAL;
   if (L < 4 || L > (uint32_t)pa::kMaxL || (L & 1u) || R == 0) return PA_EINVAL;
   *layout_out = pa::layout_for(model, L, ((uint64_t)R + 63) / 64);
   return PA_OK;
 }
 
 extern "C" int pa_autotune_set_layout(uint32_t model, uint32_t L, uint64_t tiles, uint32_t layout) {
-  if (model != PA_MODEL_PM && model != PA_MODEL_GAUSS16) return PA_EINVAL;
+  if (model != PA_MODEL_PM && model != PA_MODEL_GAUSS16 && model != PA_MODEL_GAUSS) return PA_EINVAL;
   if (layout != PA_LAYOUT_INT8 && layout != PA_LAYOUT_BITPACK64) return PA_EINVAL;
   if (L < 4 || L > (uint32_t)pa::kMaxL || (L & 1u) || tiles == 0) return PA_EINVAL;
   pa::layout_record(model, L, tiles, layout);
@@ -83,7 +83,7 @@ extern "C" int pa_autotune_set_layout(uint32_t model, uint32_t L, uint64_t tiles
 
 extern "C" int pa_autotune_set(uint32_t model, uint32_t layout, uint32_t L, uint64_t tiles,
                                uint32_t split) {
-  if (model != PA_MODEL_PM && model != PA_MODEL_GAUSS16) return PA_EINVAL;
+  if (model != PA_MODEL_PM && model != PA_MODEL_GAUSS16 && model != PA_MODEL_GAUSS) return PA_EINVAL;
   if (layout != PA_LAYOUT_INT8 && layout != PA_LAYOUT_BITPACK64) return PA_EINVAL;
   if (L < 4 || L > (uint32_t)pa::kMaxL || (L & 1u) || tiles == 0) return PA_EINVAL;
   if (split != 4 && split != 8) return PA_EINVAL;

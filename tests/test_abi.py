@@ -43,7 +43,7 @@ def test_workspace_sizing_and_argument_checks():
     assert nb >= 2 * (cap // 64) * 1000 * 8
     assert nb < 200 * 2 ** 20
     for bad in (dict(L=5), dict(L=2), dict(L=18), dict(R=0), dict(layout=7), dict(flags=8),
-                dict(flags=0x80000000), dict(capacity=10), dict(model=2)):
+                dict(flags=0x80000000), dict(capacity=10), dict(model=3)):
         q = pam.pa_params(L=10, R=1000, capacity=0, layout=1, seed=1, flags=0, model=0)
         for k, v in bad.items():
             setattr(q, k, v)
@@ -90,7 +90,7 @@ def test_autotune_set_checks_its_arguments():
 
     lib = pam.lib()
     assert lib.pa_autotune_set(0, 2, 10, 7813, 8) == pam.PA_OK
-    for bad in ((2, 2, 10, 7813, 8), (0, 0, 10, 7813, 8), (0, 2, 5, 7813, 8), (0, 2, 18, 7813, 8),
+    for bad in ((3, 2, 10, 7813, 8), (0, 0, 10, 7813, 8), (0, 2, 5, 7813, 8), (0, 2, 18, 7813, 8),
                 (0, 2, 10, 0, 8), (0, 2, 10, 7813, 6)):
         assert lib.pa_autotune_set(*bad) == pam.PA_EINVAL, bad
     assert lib.pa_autotune_reset() == pam.PA_OK
@@ -132,12 +132,43 @@ def test_layout_choice_follows_the_layout_table():
         assert lib.pa_autotune_reset() == pam.PA_OK
         assert pam.pa_layout_choice(8, 100000) == "bitpack64"
         out = ctypes.c_uint32(0)
-        for bad in ((2, 8, 1000), (0, 7, 1000), (0, 2, 1000), (0, 18, 1000), (0, 8, 0)):
+        for bad in ((3, 8, 1000), (0, 7, 1000), (0, 2, 1000), (0, 18, 1000), (0, 8, 0)):
             assert lib.pa_layout_choice(*bad, ctypes.byref(out)) == pam.PA_EINVAL, bad
         assert lib.pa_layout_choice(0, 8, 1000, None) == pam.PA_EINVAL
-        for bad in ((2, 8, 16, 1), (0, 8, 16, 0), (0, 8, 16, 3), (0, 9, 16, 1), (0, 8, 0, 1)):
+        for bad in ((3, 8, 16, 1), (0, 8, 16, 0), (0, 8, 16, 3), (0, 9, 16, 1), (0, 8, 0, 1)):
             assert lib.pa_autotune_set_layout(*bad) == pam.PA_EINVAL, bad
         assert lib.pa_autotune_layout(None, None, None, 0, None, 1.0, 10, 3, None,
                                       None) == pam.PA_EINVAL
     finally:
         lib.pa_autotune_reset()
+
+
+def test_real_coupling_model_sizing_and_argument_checks():
+    """PA_MODEL_GAUSS: int64 energy words, the he and threshold tables of every
+    (site, pattern) and one reduction partial per slot block; the creation
+    call rejects bad couplings before any device work."""
+    import paper_1711_02146_amd as pam
+
+    L, R = 10, 100000
+    q = pam.pa_params(L=L, R=R, capacity=0, layout=2, seed=1, flags=0, model=0)
+    g = pam.pa_params(L=L, R=R, capacity=0, layout=2, seed=1, flags=0, model=pam.PA_MODEL_GAUSS)
+    cap = R + 16 * 316 + 256
+    cap = (cap + 255) // 256 * 256
+    extra = pam.pa_workspace_bytes(g) - pam.pa_workspace_bytes(q)
+    # (less the +-J histogram and resampling table of 3N + 1 levels)
+    assert extra >= 2 * cap * 4 + 2 * L ** 3 * 64 * 8 + (cap // 256) * 32 - 20 * 3001 - 8192
+    lib = pam.lib()
+    out = ctypes.c_void_p()
+    good = np.ldexp(np.rint(np.ldexp(np.linspace(-3, 3, 3 * L ** 3), 32)), -32)
+    for J in (np.where(np.arange(3000) == 7, np.nan, good), np.where(np.arange(3000) == 5, 8.0, good),
+              np.where(np.arange(3000) == 5, -np.inf, good)):
+        J = np.ascontiguousarray(J, np.float64)
+        assert lib.pa_init_instance_real(ctypes.byref(g), J.ctypes.data, 256, 1 << 30, None,
+                                         ctypes.byref(out)) == pam.PA_EINVAL
+    # the real-coupling model takes FP64 couplings only, and only them
+    J8 = np.ones(3 * L ** 3, np.int8)
+    assert lib.pa_init_instance(ctypes.byref(g), J8.ctypes.data, 256, 1 << 30, None,
+                                ctypes.byref(out)) == pam.PA_EINVAL
+    assert lib.pa_init_instance_real(ctypes.byref(q), good.ctypes.data, 256, 1 << 30, None,
+                                     ctypes.byref(out)) == pam.PA_EINVAL
+    assert lib.pa_export_energies(None, None) == pam.PA_ESTATE
