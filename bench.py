@@ -35,6 +35,11 @@ WORKLOAD = dict(name="L10_R500k_bitpack64_adaptive_eps0.1", L=10, R=500000, eps=
 GAUSS_WORKLOAD = dict(name="L10_R500k_bitpack64_gauss16_adaptive_eps0.1", L=10, R=500000,
                       eps=0.1, beta_max=5.0, n_sweeps=10, layout="bitpack64", model="gauss16")
 
+# The same anneal with the couplings as real numbers (unit normals on the grid
+# 2^-32): per-replica weights, exact fixed-point sums, the bisection on the device.
+REAL_WORKLOAD = dict(name="L10_R500k_bitpack64_gauss_real_adaptive_eps0.1", L=10, R=500000,
+                     eps=0.1, beta_max=5.0, n_sweeps=10, layout="bitpack64", model="gauss")
+
 # Peak figures of one MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz
 # retire 39.3e12 full-rate 32-bit VALU lane-instructions per second; HBM3E 8 TB/s.
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
@@ -65,6 +70,12 @@ OPS_PER_ATTEMPT = 10 + 2 + 102 / 64
 # the flip mask's half = 19 (the row's couplings are uniform over a wave's
 # lanes, so sum k and the coupling bytes cost no lane instructions).
 OPS_PER_ATTEMPT_GAUSS = 10 + 19
+# With real couplings, per replica: the pattern of the six "neighbour differs"
+# bits (6 XORs with the own word, 6 extracts, 5 shift-ors), 1 table address,
+# 1 load of the (site, pattern) threshold, 1 compare (64-bit) and 1 select of
+# the flip mask's half = 21; the threshold table (N x 64 x 8 bytes) is read
+# through the caches, one row of 512 bytes per site and wave.
+OPS_PER_ATTEMPT_REAL = 10 + 21
 # Algorithmic HBM bytes of one sweep launch: the bit-packed population read and
 # written once (N bits per replica each way) plus 20 B per replica (source index,
 # energy and family label read, energy and family label written).
@@ -102,6 +113,8 @@ def parse():
     ap.add_argument("--gauss-steps", type=int, default=300,
                     help="timed steps of the Gaussian-coupling anneal (0 skips it)")
     ap.add_argument("--no-int8", action="store_true", help="skip the int8-layout C1/C2 runs")
+    ap.add_argument("--real-steps", type=int, default=50,
+                    help="steps of the real-Gaussian-coupling anneal (0: skip)")
     ap.add_argument("--oracle-one-thread", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (used to "
@@ -559,12 +572,80 @@ def gauss_bench(pam, steps: int, warmup: int, autotune: bool):
                   "hbm_algorithmic_GBs": r["bytes_per_launch"] / (r["avg_ms"] * 1e-3) / 1e9},
         "sweep_fraction_of_wall": sum(r["sweep_ms"]) * 1e-3 / wall,
         "autotune": tune,
-        "layout_autotune": ltune,
         "anneals_completed": len(anneals),
         "steps_per_anneal": anneals,
         "beta_at_end": stats[-1][0] if stats else None,
         "link_overlap": link,
     }
+
+
+def gauss_real_bench(pam, steps: int, warmup: int, autotune: bool):
+    """The benchmark anneal with real Gaussian couplings (PA_MODEL_GAUSS)."""
+    import torch
+
+    import pa_inputs
+
+    w = REAL_WORKLOAD
+    J = pa_inputs.couplings_gauss(w["L"], pa_inputs.coupling_seed(3, 0))
+    seed0 = pa_inputs.population_seed(3, 0, 0)
+    tune = None
+    if autotune:
+        tp = pam.Population(w["L"], w["R"], J, seed0 + 999, layout=w["layout"], model=w["model"])
+        tune = tp.autotune(beta=0.3, n_sweeps=w["n_sweeps"], repeats=5)
+        tp.close()
+    run_steps(pam, J, w, warmup, seed0 + 1000)
+    sweeps, stats, anneals = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    attempts = run_steps(pam, J, w, steps, seed0, sweeps, stats, anneals)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r = sweep_roofline(w, sweeps, OPS_PER_ATTEMPT_REAL, 1 / 8)
+    return {
+        "workload": w["name"],
+        "couplings": "Gaussian N(0,1) as FP64 on the grid 2^-32 (int64 energy words)",
+        "value": attempts / wall, "unit": "attempts/s", "steps": steps, "warmup": warmup,
+        "ms_per_step": 1e3 * wall / steps,
+        "sweep": {"kernel": "k_sweep<bitpack64, L=10, real> (gather + 10 sweeps + energy)",
+                  "avg_launch_ms": r["avg_ms"], "launches": r["n_launch"],
+                  "attempts_per_launch": r["avg_att"],
+                  "sweep_attempts_per_s": r["avg_att"] / (r["avg_ms"] * 1e-3),
+                  "achieved": r["achieved_ops"] / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                  "unit": "Tops/s", "frac": r["achieved_ops"] / VALU_PEAK_OPS,
+                  "ops_per_attempt": OPS_PER_ATTEMPT_REAL, "traffic": None,
+                  "algorithmic_bytes_per_launch": r["bytes_per_launch"],
+                  "hbm_algorithmic_GBs": r["bytes_per_launch"] / (r["avg_ms"] * 1e-3) / 1e9},
+        "sweep_fraction_of_wall": sum(r["sweep_ms"]) * 1e-3 / wall,
+        "outside_sweep_us_per_step": 1e6 * (wall - sum(r["sweep_ms"]) * 1e-3) / steps,
+        "autotune": tune,
+        "anneals_completed": len(anneals),
+        "steps_per_anneal": anneals,
+        "beta_at_end": stats[-1][0] if stats else None,
+    }
+
+
+def gauss_real_cpu_baseline(w, R_sample=50000, n_steps=2):
+    """The oracle on the first n_steps temperature steps of the real-coupling
+    workload at a tenth of its population (same L, couplings and culling)."""
+    import oracle
+    import pa_inputs
+
+    oracle.build(force=False)
+    J = pa_inputs.couplings_gauss(w["L"], pa_inputs.coupling_seed(3, 0))
+    t0 = time.perf_counter()
+    p = oracle.GaussRealPopulation(w["L"], J, R_sample, pa_inputs.population_seed(3, 0, 0))
+    att = 0
+    for _ in range(n_steps):
+        b = p.choose_beta(w["eps"], w["beta_max"])
+        p.resample(b)
+        p.sweep(b, w["n_sweeps"])
+        p.observables()
+        att += w["n_sweeps"] * w["L"] ** 3 * p.R_tilde
+    t1 = time.perf_counter()
+    return {"value": att / (t1 - t0), "unit": "attempts/s", "cores": omp_threads(), "kind": "oracle",
+            "sample": f"the first {n_steps} temperature steps (init, then step choice + resample + "
+                      f"{w['n_sweeps']} sweeps each) of the real-coupling workload at R={R_sample}",
+            "seconds": round(t1 - t0, 2)}
 
 
 def link_overlap_bench(pam, K, w, repeats: int = 5):
@@ -837,6 +918,10 @@ def main():
     if args.gauss_steps > 0:
         print(f"# Gaussian couplings: {args.gauss_steps} steps", file=sys.stderr, flush=True)
         line["gauss16"] = gauss_bench(pam, args.gauss_steps, args.warmup, not args.no_autotune)
+    if args.real_steps > 0:
+        print(f"# real Gaussian couplings: {args.real_steps} steps", file=sys.stderr, flush=True)
+        line["gauss_real"] = gauss_real_bench(pam, args.real_steps, args.warmup,
+                                              not args.no_autotune)
     if not args.no_int8:
         print("# int8 layout: C1 and C2 whole runs", file=sys.stderr, flush=True)
         line["int8"] = {"C1": linear_run(pam, C1, 1, False), "C2": linear_run(pam, C2, 2, True)}
@@ -853,6 +938,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(w)
         if "gauss16" in line:
             line["gauss16"]["cpu_baseline"] = gauss_cpu_baseline(GAUSS_WORKLOAD)
+        if "gauss_real" in line:
+            line["gauss_real"]["cpu_baseline"] = gauss_real_cpu_baseline(REAL_WORKLOAD)
         if "int8" in line:
             line["int8"]["C1"]["cpu_baseline"] = int8_cpu_baseline(C1, 1, False, C1["n_temps"] - 1)
             line["int8"]["C2"]["cpu_baseline"] = int8_cpu_baseline(C2, 2, True, 2)

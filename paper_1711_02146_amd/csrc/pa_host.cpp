@@ -388,7 +388,7 @@ int fetch_hist(pa_instance* in, bool with_family) {
   PA_HIP(in, pa::launch_zero_acc(B, group_of(in, in->d_meta->perpop, 1), in->stream));
   if (P.model == pa::kModelReal) {
     // no levels: the lowest energy, the replicas at it and the energy sum
-    PA_HIP(in, pa::launch_real_stats(B, group_of(in, in->d_meta->slots, in->meta.slots[1]),
+    PA_HIP(in, pa::launch_real_stats(B, group_of(in, in->d_meta->rsum, in->meta.rsum[1]),
                                      in->stream));
     if (with_family)
       PA_HIP(in, pa::launch_family(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), false,
@@ -527,7 +527,7 @@ int choose_from_hist(pa_instance* in, double eps_target, double beta_max, double
     // mass, decided and advanced by the last workgroup of each
     const double rem = beta_max - in->beta;
     const pa::BatchDev B = one_set(in, plain_step(in->cur));
-    const pa::Group g = group_of(in, in->d_meta->slots, in->meta.slots[1]);
+    const pa::Group g = group_of(in, in->d_meta->rsum, in->meta.rsum[1]);
     PA_HIP(in, pa::launch_real_bisect_init(in->dev, rem, eps_target, in->stream));
     for (int e = 0; e < 66; ++e) PA_HIP(in, pa::launch_real_bisect_eval(B, g, in->stream));
     PA_HIP(in, hipMemcpyAsync(in->h_rs, in->dev.rs, sizeof(pa::RealScalars),
@@ -614,7 +614,8 @@ int queue_resample(pa_instance* in, double beta_next, Table* t, uint32_t step_fl
     ps.dbeta = dbeta;
     const pa::BatchDev B = one_set(in, ps);
     const pa::Group g = group_of(in, in->d_meta->slots, in->meta.slots[1]);
-    PA_HIP(in, pa::launch_real_sum(B, g, false, in->stream));
+    PA_HIP(in, pa::launch_real_sum(B, group_of(in, in->d_meta->rsum, in->meta.rsum[1]), false,
+                                   in->stream));
     PA_HIP(in, pa::launch_real_counts(B, g, in->stream));
     PA_HIP(in, pa::launch_scan(B, group_of(in, in->d_meta->perpop, 1), in->stream));
     PA_HIP(in, pa::launch_scatter(B, g, in->stream));
@@ -1054,6 +1055,7 @@ int init_instance(const pa_params* p, const int8_t* J_host, const std::vector<lo
   mt.etiles[0] = 0; mt.etiles[1] = l.capacity / 64;
   mt.pair_pops[0] = 0; mt.pair_pops[1] = 1;
   mt.pairs[0] = 0; mt.pairs[1] = 0;
+  mt.rsum[0] = 0; mt.rsum[1] = std::min(pa::blocks_slots(l.capacity), pa::kRealSumBlocks);
 
   auto fail = [&](int rc) {
     pa_free(in);

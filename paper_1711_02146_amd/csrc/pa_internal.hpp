@@ -51,6 +51,10 @@ constexpr uint32_t kModelGauss16 = 1;
 // energy is -he before and +he after the flip.
 constexpr uint32_t kModelReal = 2;
 constexpr uint32_t kRealPatterns = 64;  // patterns y per site
+// Workgroups of the kModelReal weight reductions (grid-stride over the
+// replicas): few enough that their arrivals and partials cost little, enough
+// to give every CU one.
+constexpr uint32_t kRealSumBlocks = 256;
 constexpr int kGaussKMax = 127;
 constexpr int kGaussDEMax = 2 * 6 * kGaussKMax;  // largest |dE16| of one flip
 
