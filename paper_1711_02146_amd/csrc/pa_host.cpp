@@ -617,8 +617,7 @@ int queue_resample(pa_instance* in, double beta_next, Table* t, uint32_t step_fl
     PA_HIP(in, pa::launch_real_sum(B, group_of(in, in->d_meta->rsum, in->meta.rsum[1]), false,
                                    in->stream));
     PA_HIP(in, pa::launch_real_counts(B, g, in->stream));
-    PA_HIP(in, pa::launch_scan(B, group_of(in, in->d_meta->perpop, 1), in->stream));
-    PA_HIP(in, pa::launch_scatter(B, g, in->stream));
+    PA_HIP(in, pa::launch_scan_scatter(B, g, in->stream));
     return PA_OK;
   }
   const Levels lv = levels_of(in);
@@ -632,10 +631,10 @@ int queue_resample(pa_instance* in, double beta_next, Table* t, uint32_t step_fl
   ps.step = in->step + 1;
   ps.flags = step_flags;
   const pa::BatchDev B = one_set(in, ps);
-  PA_HIP(in, pa::launch_counts(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
-  PA_HIP(in, pa::launch_scan(B, group_of(in, in->d_meta->perpop, 1), in->stream));
-  // k_scatter does nothing when the scan flagged an overflow
-  PA_HIP(in, pa::launch_scatter(B, group_of(in, in->d_meta->slots, in->meta.slots[1]), in->stream));
+  const pa::Group g = group_of(in, in->d_meta->slots, in->meta.slots[1]);
+  PA_HIP(in, pa::launch_counts(B, g, in->stream));
+  // the scan and the copy map; over capacity, the flag stops the sweep
+  PA_HIP(in, pa::launch_scan_scatter(B, g, in->stream));
   return PA_OK;
 }
 

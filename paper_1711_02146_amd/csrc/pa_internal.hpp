@@ -258,6 +258,8 @@ hipError_t launch_table(const BatchDev& B, const Group& per_pop, hipStream_t str
 hipError_t launch_counts(const BatchDev& B, const Group& g, hipStream_t stream);
 hipError_t launch_scan(const BatchDev& B, const Group& per_pop, hipStream_t stream);
 hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream);
+// k_scan and k_scatter of one population in one launch (g: its slot blocks)
+hipError_t launch_scan_scatter(const BatchDev& B, const Group& g, hipStream_t stream);
 // sweep launch over the populations of one (layout, L, model) group: one tile
 // per workgroup of `split` (4 or 8) waves; g's blocks are blocks_sweep(capacity)
 hipError_t launch_sweep(const BatchDev& B, const Group& g, uint32_t layout, uint32_t L,

@@ -1361,6 +1361,65 @@ __global__ __launch_bounds__(kBlockCounts) void k_scatter(BatchDev B, Group G) {
   }
 }
 
+// The scan and the copy map of one population in one launch (calls on single
+// instances): workgroup b starts its new slots at the sum of the block sums
+// before it, then maps them as k_scatter does.  The last workgroup, whose
+// range ends at the new size R~', records it with the capacity check and the
+// culled count, and (kStepHist) clears the histogram and the family sum, as
+// k_scan does.  A workgroup whose range would pass the capacity writes
+// nothing; the overflow flag then keeps the sweep from applying the step.
+__global__ __launch_bounds__(kBlockCounts) void k_scan_scatter(BatchDev B, Group G) {
+  __shared__ uint32_t scratch[kBlockCounts / kWave];
+  __shared__ uint32_t excl_s[kBlockCounts];
+  __shared__ uint32_t s_base;
+  const Member m = member_of(G);
+  const DevPop P = B.pops[m.pop];
+  if (P.sc->dead) return;
+  const PopStep sp = step_of(B, m.pop);
+  uint32_t before = 0;
+  for (uint32_t b = threadIdx.x; b < m.lb; b += kBlockCounts) before += P.block_sums[b];
+  before = block_sum<kBlockCounts, uint32_t>(before, scratch);
+  if (threadIdx.x == 0) s_base = before;
+  __syncthreads();
+  const uint32_t base = s_base;
+  const uint32_t R = P.sc->R_tilde;
+  const uint32_t i = m.lb * kBlockCounts + threadIdx.x;
+  const uint32_t n = i < R ? P.counts[i] : 0u;
+  uint32_t total;
+  const uint32_t excl = block_exclusive_scan<kBlockCounts>(n, &total, scratch);
+  const bool fits = (unsigned long long)base + total <= P.cap_limit;
+  if (fits && i < R) P.offsets[i] = base + excl;
+  excl_s[threadIdx.x] = excl;
+  __syncthreads();
+  if (fits) {
+    for (uint32_t j = threadIdx.x; j < total; j += kBlockCounts) {
+      uint32_t lo = 0, hi = kBlockCounts;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (excl_s[mid] <= j)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      P.src[base + j] = m.lb * kBlockCounts + lo;
+    }
+  }
+  if (m.lb + 1 != m.nb) return;
+  uint32_t cull = 0;
+  for (uint32_t b = threadIdx.x; b < m.nb; b += kBlockCounts) cull += P.block_culled[b];
+  cull = block_sum<kBlockCounts, uint32_t>(cull, scratch);
+  if (sp.flags & kStepHist) {
+    for (uint32_t j = threadIdx.x; j < P.n_levels; j += kBlockCounts) P.hist[j] = 0;
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t all = base + total;
+    P.sc->R_next = all;
+    P.sc->err = all > P.cap_limit ? 1u : 0u;
+    P.sc->n_culled = cull;
+    if (sp.flags & kStepHist) P.sc->sum_eta2 = 0;
+  }
+}
+
 // Gather (optional) + n_sweeps checkerboard Metropolis sweeps + energy for
 // one 64-replica tile per workgroup.  Reads buffer cur, writes buffer cur ^ 1.
 // SPLIT wavefronts share the tile's LDS image: each takes every SPLIT-th
@@ -1930,6 +1989,12 @@ hipError_t launch_counts(const BatchDev& B, const Group& g, hipStream_t stream) 
 hipError_t launch_scan(const BatchDev& B, const Group& g, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
   hipLaunchKernelGGL(k_scan, dim3(g.blocks), dim3(1024), 0, stream, B, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_scatter(const BatchDev& B, const Group& g, hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_scatter, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
   return hipGetLastError();
 }
 
