@@ -87,7 +87,18 @@ BYTES_PER_REPLICA_FIXED = 20
 # plain copy of known size reads, --copy-calibration), and the executed VALU
 # lane-instructions per attempt = SQ_INSTS_VALU x 64 / attempts per launch.
 # None: no counters for the current source yet.
-PROFILE = None
+PROFILE = {
+    "kernel_src_sha256": "d0d481f0d67583929f0529e046dd44187a7dc2880ee64d1cd69b6fc9bf8792ce",
+    # FETCH_SIZE KiB x 2 + WRITE_SIZE KiB x 1, per launch (profiles/*_hbm_counters.md)
+    "bytes_per_launch": (32850.9 * 2 + 64946.1) * 1024,
+    "gauss16_bytes_per_launch": (32622.2 * 2 + 64942.5) * 1024,
+    "real_bytes_per_launch": (36171.2 * 2 + 66898.5) * 1024,
+    "link_overlap_bytes_per_launch": (61559.6 * 2 + 10484.4) * 1024,
+    "int8_C2_bytes_per_launch": (25934.4 * 2 + 50797.2) * 1024,
+    "int8_overlap_bytes_per_call": (50025.6 * 2 + 342.9) * 1024,
+    # SQ_INSTS_VALU 1.0286e9 per launch x 64 lanes / 5.0e9 attempts
+    "valu_per_attempt": 1.0286e9 * 64 / 5.0e9,
+}
 
 
 def parse():
@@ -477,6 +488,7 @@ def linear_run(pam, c, pops_n, with_q):
     avg_ms = sum(sweep_ms) / len(sweep_ms)
     avg_att = sweep_att / len(sweep_ms)
     avg_R = avg_att / (c["n_sweeps"] * N)
+    profiled = PROFILE is not None and PROFILE["kernel_src_sha256"] == kernel_src_sha256()
     ops = OPS_PER_ATTEMPT * avg_att / (avg_ms * 1e-3)
     bytes_launch = 2 * avg_R * N + BYTES_PER_REPLICA_FIXED * avg_R
     out = {"workload": c["name"], "populations": pops_n, "steps": len(betas) - 1,
@@ -490,7 +502,10 @@ def linear_run(pam, c, pops_n, with_q):
                      "ops_per_attempt": OPS_PER_ATTEMPT,
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "hbm_algorithmic_GBs": bytes_launch / (avg_ms * 1e-3) / 1e9,
-                     "bytes_per_attempt": bytes_launch / avg_att},
+                     "bytes_per_attempt": bytes_launch / avg_att,
+                     # rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE per launch (C2's shape only)
+                     "traffic": (PROFILE["int8_C2_bytes_per_launch"]
+                                 if profiled and c["config"] == 2 else None)},
            "beta_F": [p.observables()["beta_F"] for p in pops], "rho_t": last["rho_t"]}
     if with_q:
         pairs = min(p.observables()["R_tilde"] for p in pops[:2])
@@ -498,6 +513,8 @@ def linear_run(pam, c, pops_n, with_q):
                           "avg_call_ms": sum(q_ms) / len(q_ms), "calls": len(q_ms),
                           "pairs": pairs, "algorithmic_bytes": 2 * pairs * N,
                           "hbm_GBs": 2 * pairs * N / (sum(q_ms) / len(q_ms) * 1e-3) / 1e9,
+                          "kernel_traffic": (PROFILE["int8_overlap_bytes_per_call"]
+                                             if profiled else None),
                           "q_bins_nonzero": int(np.count_nonzero(q))}
     for p in pops:
         p.close()
@@ -612,7 +629,9 @@ def gauss_real_bench(pam, steps: int, warmup: int, autotune: bool):
                   "sweep_attempts_per_s": r["avg_att"] / (r["avg_ms"] * 1e-3),
                   "achieved": r["achieved_ops"] / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                   "unit": "Tops/s", "frac": r["achieved_ops"] / VALU_PEAK_OPS,
-                  "ops_per_attempt": OPS_PER_ATTEMPT_REAL, "traffic": None,
+                  "ops_per_attempt": OPS_PER_ATTEMPT_REAL,
+                  "traffic": (PROFILE["real_bytes_per_launch"] if PROFILE is not None and
+                              PROFILE["kernel_src_sha256"] == kernel_src_sha256() else None),
                   "algorithmic_bytes_per_launch": r["bytes_per_launch"],
                   "hbm_algorithmic_GBs": r["bytes_per_launch"] / (r["avg_ms"] * 1e-3) / 1e9},
         "sweep_fraction_of_wall": sum(r["sweep_ms"]) * 1e-3 / wall,
@@ -712,11 +731,14 @@ def gauss_cpu_baseline(w, R_sample=100000, n_steps=3):
 
 
 def kernel_src_sha256():
+    """SHA-256 over the kernel sources (pa_kernels.hip and the file it includes)."""
     import hashlib
 
-    src = os.path.join(ROOT, "paper_1711_02146_amd", "csrc", "pa_kernels.hip")
-    with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("pa_kernels.hip", "pa_real_kernels.inc", "pa_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1711_02146_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def omp_threads() -> int:

@@ -127,7 +127,10 @@ bool make_layout(const pa_params* p, Layout* out) {
   const size_t per_site = real ? (size_t)l.N * pa::kRealPatterns * 8 : 0;
   l.off_rhe = take(per_site);
   l.off_rthr = take(per_site);
-  l.off_rpart = take(real ? (size_t)l.n_blocks * sizeof(pa::RealPartial) : 0);
+  // (one per slot block for the copy counts, three per reduction workgroup
+  // for the bisection's evaluations)
+  const size_t n_part = std::max<size_t>(l.n_blocks, 3 * (size_t)pa::kRealSumBlocks);
+  l.off_rpart = take(real ? n_part * sizeof(pa::RealPartial) : 0);
   l.total = o;
   *out = l;
   return true;
@@ -614,9 +617,10 @@ int queue_resample(pa_instance* in, double beta_next, Table* t, uint32_t step_fl
     ps.dbeta = dbeta;
     const pa::BatchDev B = one_set(in, ps);
     const pa::Group g = group_of(in, in->d_meta->slots, in->meta.slots[1]);
-    PA_HIP(in, pa::launch_real_sum(B, group_of(in, in->d_meta->rsum, in->meta.rsum[1]), false,
+    PA_HIP(in, pa::launch_real_sum(B, group_of(in, in->d_meta->rsum, in->meta.rsum[1]),
                                    in->stream));
-    PA_HIP(in, pa::launch_real_counts(B, g, in->stream));
+    PA_HIP(in, pa::launch_real_counts(B, group_of(in, in->d_meta->rsum, in->meta.rsum[1]),
+                                      in->stream));
     PA_HIP(in, pa::launch_scan_scatter(B, g, in->stream));
     return PA_OK;
   }

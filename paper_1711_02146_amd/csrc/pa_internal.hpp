@@ -296,17 +296,19 @@ hipError_t launch_advance(uint32_t* step_ctr, hipStream_t stream);
 hipError_t launch_real_thresholds(const DevPop& P, double beta, hipStream_t stream);
 // E_min, replicas at E_min and the sum of the energy words into P.rs
 hipError_t launch_real_stats(const BatchDev& B, const Group& slots, hipStream_t stream);
-// the sum S of the weights exp(-dbeta (E - E_min)) into P.rs->S: dbeta of the
-// step parameters (bisect = false) or the bisection's next candidate
-hipError_t launch_real_sum(const BatchDev& B, const Group& slots, bool bisect, hipStream_t stream);
+// the sum S of the weights exp(-dbeta (E - E_min)) at the step's dbeta into P.rs->S
+hipError_t launch_real_sum(const BatchDev& B, const Group& slots, hipStream_t stream);
 // the constant-culling bisection (Sec. III.C): set up for the remaining range
-// and target, then one evaluation (weight sum + culled mass + decision) per
-// launch_real_bisect_eval; 66 of them finish it (P.rs->result)
+// and target, then one evaluation (culled mass at the current candidate, the
+// weight sums of the two that can follow, the decision) per
+// launch_real_bisect_eval; 66 of them finish it (P.rs->result).  `slots`:
+// at most kRealSumBlocks workgroups (the partials hold three sums each)
 hipError_t launch_real_bisect_init(const DevPop& P, double rem, double target,
                                    hipStream_t stream);
 hipError_t launch_real_bisect_eval(const BatchDev& B, const Group& slots, hipStream_t stream);
 // copy counts of the step (after launch_real_sum at its dbeta): counts, block
 // sums and culled counts as k_counts, and the culled fraction into P.rs->eps
+// (`slots`: at most kRealSumBlocks workgroups, each over every nb-th slot block)
 hipError_t launch_real_counts(const BatchDev& B, const Group& slots, hipStream_t stream);
 
 // Blocks each population needs in each kind of launch.

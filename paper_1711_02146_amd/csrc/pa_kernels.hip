@@ -2195,10 +2195,9 @@ hipError_t launch_real_stats(const BatchDev& B, const Group& g, hipStream_t stre
   return hipGetLastError();
 }
 
-hipError_t launch_real_sum(const BatchDev& B, const Group& g, bool bisect, hipStream_t stream) {
+hipError_t launch_real_sum(const BatchDev& B, const Group& g, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
-  hipLaunchKernelGGL(k_rsum, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g,
-                     bisect ? 1u : 0u);
+  hipLaunchKernelGGL(k_rsum, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
   return hipGetLastError();
 }
 
@@ -2210,8 +2209,7 @@ hipError_t launch_real_bisect_init(const DevPop& P, double rem, double target,
 
 hipError_t launch_real_bisect_eval(const BatchDev& B, const Group& g, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
-  hipLaunchKernelGGL(k_rsum, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g, 1u);
-  hipLaunchKernelGGL(k_rcull, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
+  hipLaunchKernelGGL(k_reval, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
   return hipGetLastError();
 }
 
