@@ -627,16 +627,25 @@ int queue_resample(pa_instance* in, double beta_next, Table* t, uint32_t step_fl
   const Levels lv = levels_of(in);
   *t = resample_table(in->h_hist, lv.n, lv.unit, lv.E_lo, P.R, in->R_tilde, dbeta, in->h_table);
   if (t->jmin < 0) return PA_ESTATE;  // empty population
-  // only the occupied range is read by the copy counts
+  // only the occupied range is read by the copy counts: passed with the
+  // launch when it fits, else uploaded to the workspace's table first
   const size_t j0 = (size_t)t->jmin, nj = (size_t)(t->jmax - t->jmin + 1);
-  PA_HIP(in, hipMemcpyAsync(P.table + j0, in->h_table + j0, nj * sizeof(pa::TableEntry),
-                            hipMemcpyHostToDevice, in->stream));
   pa::PopStep ps = plain_step(in->cur);
   ps.step = in->step + 1;
   ps.flags = step_flags;
   const pa::BatchDev B = one_set(in, ps);
   const pa::Group g = group_of(in, in->d_meta->slots, in->meta.slots[1]);
-  PA_HIP(in, pa::launch_counts(B, g, in->stream));
+  if (nj <= pa::kInlineLevels) {
+    static thread_local pa::InlineTable it;
+    it.j0 = (uint32_t)j0;
+    it.n = (uint32_t)nj;
+    std::memcpy(it.e, in->h_table + j0, nj * sizeof(pa::TableEntry));
+    PA_HIP(in, pa::launch_counts_inline(B, g, it, in->stream));
+  } else {
+    PA_HIP(in, hipMemcpyAsync(P.table + j0, in->h_table + j0, nj * sizeof(pa::TableEntry),
+                              hipMemcpyHostToDevice, in->stream));
+    PA_HIP(in, pa::launch_counts(B, g, in->stream));
+  }
   // the scan and the copy map; over capacity, the flag stops the sweep
   PA_HIP(in, pa::launch_scan_scatter(B, g, in->stream));
   return PA_OK;

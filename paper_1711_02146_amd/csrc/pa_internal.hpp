@@ -140,6 +140,17 @@ struct TableEntry {
 };
 static_assert(sizeof(TableEntry) == 16, "TableEntry is 16 bytes");
 
+// The occupied range of a resampling table passed by value to the copy-count
+// kernel of a single population, when it fits: no separate upload (and no
+// dispatch between the upload and the kernel).  Entry e[j - j0] is level j.
+constexpr uint32_t kInlineLevels = 224;
+struct InlineTable {
+  uint32_t j0, n;
+  uint32_t pad[2];
+  TableEntry e[kInlineLevels];
+};
+static_assert(sizeof(InlineTable) == 16 + 16 * kInlineLevels, "InlineTable layout");
+
 // Device pointers of one population (all inside its workspace).
 struct DevPop {
   uint32_t L, N, R, capacity;   // capacity: slots per buffer, a multiple of kBlockCounts
@@ -256,6 +267,9 @@ hipError_t launch_hist(const BatchDev& B, const Group& g, uint32_t max_levels, b
                        hipStream_t stream);
 hipError_t launch_table(const BatchDev& B, const Group& per_pop, hipStream_t stream);
 hipError_t launch_counts(const BatchDev& B, const Group& g, hipStream_t stream);
+// the same with the table's occupied range passed by value (single populations)
+hipError_t launch_counts_inline(const BatchDev& B, const Group& g, const InlineTable& t,
+                                hipStream_t stream);
 hipError_t launch_scan(const BatchDev& B, const Group& per_pop, hipStream_t stream);
 hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream);
 // k_scan and k_scatter of one population in one launch (g: its slot blocks)

@@ -1253,8 +1253,22 @@ __device__ T block_sum(T v, T* scratch) {
 }
 
 // Nearest-integer copy counts (Sec. II): n_i = fl[U_i] + [u53 < T[U_i]] with
-// u53 = (w0 << 21) | (w1 >> 11) from Philox(seed; i, step, 0, RES).
-__global__ __launch_bounds__(kBlockCounts) void k_counts(BatchDev B, Group G) {
+// u53 = (w0 << 21) | (w1 >> 11) from Philox(seed; i, step, 0, RES).  The
+// table comes from the workspace, or (INLINE) from the kernel's argument,
+// which holds the occupied levels j0 .. j0 + n - 1.
+template <bool INLINE>
+__device__ __forceinline__ TableEntry table_entry(const DevPop& P, const InlineTable* t,
+                                                  uint32_t lev) {
+  if constexpr (INLINE) {
+    const uint32_t k = lev - t->j0;
+    return t->e[k < t->n ? k : t->n - 1];
+  } else {
+    return P.table[min(lev, P.n_levels - 1)];
+  }
+}
+
+template <bool INLINE>
+__device__ __forceinline__ void counts_body(BatchDev B, Group G, const InlineTable* t) {
   __shared__ uint32_t scratch[kBlockCounts / kWave];
   const Member m = member_of(G);
   const DevPop P = B.pops[m.pop];
@@ -1267,10 +1281,9 @@ __global__ __launch_bounds__(kBlockCounts) void k_counts(BatchDev B, Group G) {
   if (i < R) {
     // energy level of the replica: U (kModelPm) or E16 - E_lo (kModelGauss16)
     const uint32_t lev = P.model == kModelGauss16 ? U[i] - (uint32_t)P.sc->E_lo : U[i];
-    const uint32_t u = min(lev, P.n_levels - 1);
     const Words4 w = philox10(i, sp.step, 0u, kTagRes, (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
     const unsigned long long u53 = ((unsigned long long)w.w[0] << 21) | (w.w[1] >> 11);
-    const TableEntry te = P.table[u];
+    const TableEntry te = table_entry<INLINE>(P, t, lev);
     n = te.fl + (u53 < te.T ? 1u : 0u);
     P.counts[i] = n;
     culled = n == 0;
@@ -1281,6 +1294,15 @@ __global__ __launch_bounds__(kBlockCounts) void k_counts(BatchDev B, Group G) {
     P.block_sums[m.lb] = s;
     P.block_culled[m.lb] = c;
   }
+}
+
+__global__ __launch_bounds__(kBlockCounts) void k_counts(BatchDev B, Group G) {
+  counts_body<false>(B, G, nullptr);
+}
+
+__global__ __launch_bounds__(kBlockCounts) void k_counts_inline(BatchDev B, Group G,
+                                                                InlineTable t) {
+  counts_body<true>(B, G, &t);
 }
 
 // Exclusive scan of the per-block sums (one workgroup per population), the
@@ -1376,8 +1398,16 @@ __global__ __launch_bounds__(kBlockCounts) void k_scan_scatter(BatchDev B, Group
   const DevPop P = B.pops[m.pop];
   if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
+  // the block sums before this workgroup, four per 16-byte load (the array
+  // starts 256-byte aligned), the last lb mod 4 one by one
   uint32_t before = 0;
-  for (uint32_t b = threadIdx.x; b < m.lb; b += kBlockCounts) before += P.block_sums[b];
+  const uint32_t q = m.lb / 4;
+  const uint4* bs4 = reinterpret_cast<const uint4*>(P.block_sums);
+  for (uint32_t b = threadIdx.x; b < q; b += kBlockCounts) {
+    const uint4 v = bs4[b];
+    before += v.x + v.y + v.z + v.w;
+  }
+  for (uint32_t b = 4 * q + threadIdx.x; b < m.lb; b += kBlockCounts) before += P.block_sums[b];
   before = block_sum<kBlockCounts, uint32_t>(before, scratch);
   if (threadIdx.x == 0) s_base = before;
   __syncthreads();
@@ -1983,6 +2013,13 @@ hipError_t launch_table(const BatchDev& B, const Group& g, hipStream_t stream) {
 hipError_t launch_counts(const BatchDev& B, const Group& g, hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
   hipLaunchKernelGGL(k_counts, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_counts_inline(const BatchDev& B, const Group& g, const InlineTable& t,
+                                hipStream_t stream) {
+  if (!g.blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_counts_inline, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g, t);
   return hipGetLastError();
 }
 
