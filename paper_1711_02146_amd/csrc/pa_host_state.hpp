@@ -27,7 +27,7 @@ struct MetaU32 {
   uint32_t etiles[2];     // one-wave tiles (energy recompute)
   uint32_t pair_pops[2];  // {0, 1}: the instance and its overlap partner
   uint32_t pairs[2];      // overlap workgroups, set per call
-  uint32_t rsum[2];       // PA_MODEL_GAUSS weight reductions: min(capacity / 256, 256)
+  uint32_t rsum[2];       // PA_MODEL_GAUSS weight reductions: min(capacity / 256, kRealSumBlocks)
 };
 
 struct Layout {

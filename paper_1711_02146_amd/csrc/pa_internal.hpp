@@ -52,8 +52,9 @@ constexpr uint32_t kModelGauss16 = 1;
 constexpr uint32_t kModelReal = 2;
 constexpr uint32_t kRealPatterns = 64;  // patterns y per site
 // Workgroups of the kModelReal weight reductions (grid-stride over the
-// replicas): few enough that their arrivals and partials cost little, enough
-// to give every CU one.
+// replicas), one per CU: measured at L=10, R=5e5, an evaluation of the
+// bisection takes 17 us on 256 workgroups, 21 us on 128 and 29 us on 1024
+// (each workgroup's arrival costs a device-scope fence and atomic).
 constexpr uint32_t kRealSumBlocks = 256;
 constexpr int kGaussKMax = 127;
 constexpr int kGaussDEMax = 2 * 6 * kGaussKMax;  // largest |dE16| of one flip
