@@ -1743,11 +1743,17 @@ __global__ __launch_bounds__(256) void k_record(BatchDev B, Group G) {
 // Spin-overlap histogram (Sec. II.A): slot i of population a against slot i
 // of population b; d = differing sites, bin = (128 (N - d) + N) / (2N).
 // Member m of the group is pair k = G.pop[m] (populations pair_pops[2k], pair_pops[2k+1]).
+// One workgroup per 64-pair tile; its kOverlapWaves waves take every
+// kOverlapWaves-th site (more loads in flight than one wave per tile) and
+// their counts are added per pair through LDS.
+constexpr uint32_t kOverlapWaves = 4;
+
 template <int LAYOUT>
-__global__ __launch_bounds__(64) void k_overlap(BatchDev B, Group G,
+__global__ __launch_bounds__(64 * kOverlapWaves) void k_overlap(BatchDev B, Group G,
                                                 const uint32_t* __restrict__ pair_pops,
                                                 uint32_t post, uint32_t cur_a1, uint32_t cur_b1) {
   __shared__ uint32_t hb[65];
+  __shared__ uint32_t dpart[kOverlapWaves][64];
   const Member m = member_of(G);
   const uint32_t k = m.pop;  // pair index
   const uint32_t ia = __builtin_amdgcn_readfirstlane(pair_pops[2 * k]);
@@ -1763,10 +1769,10 @@ __global__ __launch_bounds__(64) void k_overlap(BatchDev B, Group G,
       B.qhist ? B.qhist + ((size_t)step_index(B) * B.n_pairs + k) * 65 : A.ovl_hist;
   const uint32_t tile = m.lb;
   const uint32_t lane = lane_id();
+  const uint32_t part = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const uint32_t n = min(A.sc->R_tilde, Bp.sc->R_tilde);
   if (tile * 64 >= n) return;
-  for (uint32_t b = lane; b < 65; b += 64) hb[b] = 0;
-  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < 65; b += 64 * kOverlapWaves) hb[b] = 0;
   const uint32_t i = tile * 64 + lane;
   const uint32_t N = A.N;
   uint32_t d = 0;
@@ -1775,15 +1781,25 @@ __global__ __launch_bounds__(64) void k_overlap(BatchDev B, Group G,
                                   (size_t)tile * N;
     const unsigned long long* b = static_cast<const unsigned long long*>(pick(Bp.spins, cur_b)) +
                                   (size_t)tile * N;
-    for (uint32_t cm = 0; cm < N; ++cm) d += (uint32_t)((a[cm] ^ b[cm]) >> lane) & 1u;
+#pragma unroll 8
+    for (uint32_t cm = part; cm < N; cm += kOverlapWaves)
+      d += (uint32_t)((a[cm] ^ b[cm]) >> lane) & 1u;
   } else {
     const int8_t* a = static_cast<const int8_t*>(pick(A.spins, cur_a)) + (size_t)tile * N * 64 + lane;
     const int8_t* b = static_cast<const int8_t*>(pick(Bp.spins, cur_b)) + (size_t)tile * N * 64 + lane;
-    for (uint32_t cm = 0; cm < N; ++cm) d += a[64 * (size_t)cm] != b[64 * (size_t)cm];
+#pragma unroll 8
+    for (uint32_t cm = part; cm < N; cm += kOverlapWaves) d += a[64 * (size_t)cm] != b[64 * (size_t)cm];
   }
-  if (i < n) atomicAdd(&hb[(128u * (N - d) + N) / (2u * N)], 1u);
+  dpart[part][lane] = d;
   __syncthreads();
-  for (uint32_t b = lane; b < 65; b += 64)
+  if (part == 0) {
+    d = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kOverlapWaves; ++w) d += dpart[w][lane];
+    if (i < n) atomicAdd(&hb[(128u * (N - d) + N) / (2u * N)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < 65; b += 64 * kOverlapWaves)
     if (hb[b]) atomicAdd(&out[b], (unsigned long long)hb[b]);
 }
 
@@ -2172,10 +2188,10 @@ hipError_t launch_overlap(const BatchDev& B, const Group& g, const uint32_t* pai
                           hipStream_t stream) {
   if (!g.blocks) return hipSuccess;
   if (layout == 2)
-    hipLaunchKernelGGL(k_overlap<2>, dim3(g.blocks), dim3(64), 0, stream, B, g, pair_pops,
+    hipLaunchKernelGGL(k_overlap<2>, dim3(g.blocks), dim3(64 * kOverlapWaves), 0, stream, B, g, pair_pops,
                        post ? 1u : 0u, cur_a, cur_b);
   else
-    hipLaunchKernelGGL(k_overlap<1>, dim3(g.blocks), dim3(64), 0, stream, B, g, pair_pops,
+    hipLaunchKernelGGL(k_overlap<1>, dim3(g.blocks), dim3(64 * kOverlapWaves), 0, stream, B, g, pair_pops,
                        post ? 1u : 0u, cur_a, cur_b);
   return hipGetLastError();
 }
