@@ -63,19 +63,18 @@ HBM_PEAK_GBS = 8000.0
 #   threshold's address, then 1 compare (64-bit) and 1 select of the flip
 #   mask's half = 2.
 OPS_PER_ATTEMPT = 10 + 2 + 102 / 64
-# With couplings k = 16 J (Gaussian, quantised), per replica: 6 bit extracts
-# of the neighbour spins and 6 multiply-adds for m = sum k b, 1 extract of the
-# own spin and 1 select for acc = m or sum k - m, 1 for dE16 = 2 sum k - 4 acc,
-# 1 clamp, 1 for the threshold-table address, 1 compare (64-bit), 1 select of
-# the flip mask's half = 19 (the row's couplings are uniform over a wave's
-# lanes, so sum k and the coupling bytes cost no lane instructions).
-OPS_PER_ATTEMPT_GAUSS = 10 + 19
-# With real couplings, per replica: the pattern of the six "neighbour differs"
-# bits (6 XORs with the own word, 6 extracts, 5 shift-ors), 1 table address,
-# 1 load of the (site, pattern) threshold, 1 compare (64-bit) and 1 select of
-# the flip mask's half = 21; the threshold table (N x 64 x 8 bytes) is read
-# through the caches, one row of 512 bytes per site and wave.
-OPS_PER_ATTEMPT_REAL = 10 + 21
+# Gaussian couplings, bit-sliced pattern pass: per site and 64 replicas, 12
+# XORs (neighbour ^ own, two 32-replica halves) and 120 to spread the six
+# "neighbour differs" planes into one byte per replica holding 4 y (per half,
+# 5 plane rotations, then 8 words x (1 AND + 5 masked merges) and 7 rotations)
+# = 132, i.e. 132/64 per attempt.  Per replica, quantised couplings (k = 16 J):
+# the byte is the offset of the site's table entry, whose value is the LDS
+# address of the dE16 threshold, then 1 compare (64-bit) and 1 select of the
+# flip mask's half = 2; real couplings: 1 shift (the 8-byte threshold of the
+# (site, pattern) table at 8 y), 1 compare (64-bit), 1 select = 3.  Each site
+# and wave also reads one table row through the caches (a 64-lane gather).
+OPS_PER_ATTEMPT_GAUSS = 10 + 2 + 132 / 64
+OPS_PER_ATTEMPT_REAL = 10 + 3 + 132 / 64
 # Algorithmic HBM bytes of one sweep launch: the bit-packed population read and
 # written once (N bits per replica each way) plus 20 B per replica (source index,
 # energy and family label read, energy and family label written).

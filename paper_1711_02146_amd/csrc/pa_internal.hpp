@@ -30,9 +30,9 @@ constexpr int kBlockCounts = 256;  // slots per block in the copy-count / scatte
 constexpr int kHistSlots = 4096;   // slots per block of the histogram kernel
 constexpr int kWindowLdsLevels = 16384;  // largest E16 window counted in LDS (64 KiB)
 constexpr int kMaxL = 16;
-// +-J sweep: per wave, the threshold byte addresses of one chunk of 64 sites
-// x 64 replicas, one byte each (phase 1 of the colour pass: one site per
-// lane).  With the 8 KB tile image at L = 10, eight such areas leave four
+// Sweep: per wave, one byte for each of 64 sites x 64 replicas (phase 1 of
+// the colour pass: one site per lane): the threshold byte address (+-J) or
+// the neighbour pattern (Gaussian couplings).  With the 8 KB tile image at L = 10, eight such areas leave four
 // workgroups of eight waves (eight waves per SIMD) in a CU's 160 KB.
 constexpr uint32_t kPlaneAreaBytes = 64 * 64;
 constexpr uint32_t kLinkCopies = 32;  // partial link-overlap histograms (see launch_link_overlap)
@@ -51,6 +51,10 @@ constexpr uint32_t kModelGauss16 = 1;
 // energy is -he before and +he after the flip.
 constexpr uint32_t kModelReal = 2;
 constexpr uint32_t kRealPatterns = 64;  // patterns y per site
+// Rows (sites) past the last of the per-(site, pattern) tables: the Gaussian
+// colour pass reads one group of four sites past a 64-site chunk ahead, whose
+// entries it never uses.
+constexpr uint32_t kPatternPadRows = 64;
 // Workgroups of the kModelReal weight reductions (grid-stride over the
 // replicas), one per CU: measured at L=10, R=5e5, an evaluation of the
 // bisection takes 17 us on 256 workgroups, 21 us on 128 and 29 us on 1024
@@ -75,7 +79,7 @@ static_assert(sizeof(SiteEntry) == 16, "SiteEntry must be 16 bytes");
 // threshold table, which sits at address 0 (the kernel checks both).
 constexpr uint32_t kTileLdsBase = 64;
 
-// The same site for phase 1 of the +-J colour pass (lane = site), laid out so
+// The same site for phase 1 of the colour passes (lane = site), laid out so
 // that nothing needs unpacking: the LDS addresses kTileLdsBase + 8 nb[k] of
 // the six neighbours' words, and the coupling bits.  32 bytes: two 16-byte
 // loads per lane.
@@ -172,7 +176,7 @@ struct DevPop {
   uint32_t* hist;               // n_levels
   struct TableEntry* table;     // n_levels: the resampling table by energy level
   const SiteEntry* sites;       // N entries, colour-major
-  const PlaneSite* psites;      // N entries, colour-major (phase 1 of the +-J pass)
+  const PlaneSite* psites;      // N entries, colour-major (phase 1 of the colour passes)
   const uint16_t* cm_of_site;   // N entries: lexicographic site -> colour-major index
   const unsigned long long* rowj;  // 2 L^2 row words: bit 6q + k set iff the bond from
                                    // site q of row (colour, y, z) to neighbour k is -1
@@ -186,6 +190,9 @@ struct DevPop {
                                 // coupling k of its site q to neighbour k (J = k / 16)
   const unsigned long long* gthr;  // kModelGauss16: thr[d] = floor(2^32 exp(-beta d / 16)),
                                    // d = 0..kGaussDEMax, for the coming sweep
+  const uint32_t* gaddr;            // kModelGauss16: 16 max(he16[cm][y], 0), N x 64, with he16
+                                   // the he of kModelReal in units 1/16: the byte offset of the
+                                   // move's threshold in the dE16 table (dE16 = 2 he16)
   const long long* rhe;            // kModelReal: he[cm][y], N x 64 (see kModelReal)
   unsigned long long* rthr;        // kModelReal: Metropolis threshold of (cm, y) for the
                                    // coming sweep, N x 64

@@ -227,7 +227,7 @@ struct MetPhilox {
   }
 };
 
-// One colour pass of the checkerboard Metropolis update on the LDS tile.
+// Row addressing of the LDS tile (the energy of a tile when no sweep runs).
 // For even L, the sites of colour c in row rho = y + L z are x = 2q + p,
 // q = 0..L/2-1, p = (c + y + z) & 1, with colour-major indices
 // c*N/2 + (L/2) rho + q.  Their neighbours of the other colour, in that
@@ -237,18 +237,12 @@ struct MetPhilox {
 // wrapped x neighbour shared by the last and first site, and the four y/z
 // rows); every site reads its words at compile-time offsets from them.
 //
-// Rows are walked four at a time: 4 (L/2) sites = L/2 whole Philox groups
-// (colour-major indices 4g .. 4g+3 share one call, word cm & 3 is site cm's),
-// so a block never shares a group with its neighbour.  Waves that share a
-// tile take every nparts-th block (same-colour sites are independent); the
-// pass ends with a workgroup barrier, so the next colour sees every flip.
-//
-// nu = number of unsatisfied bonds at the site (own bit ^ neighbour bit ^
-// [J = -1]); flipping changes the energy by dE = 12 - 4 nu, and the move is
-// accepted iff its draw is below thr_of_nu[nu] (floor(2^32 exp(-beta dE)) for
-// nu <= 2, 2^32 for nu >= 3).  With ACCUM, the pass also sums this colour's
-// post-move nu: in the colour-1 pass of the last sweep that is the energy U
-// (every bond joins one site of each colour).
+// Metropolis test (+-J): nu = number of unsatisfied bonds at the site (own
+// bit ^ neighbour bit ^ [J = -1]); flipping changes the energy by
+// dE = 12 - 4 nu, and the move is accepted iff its draw is below thr_of_nu[nu]
+// (floor(2^32 exp(-beta dE)) for nu <= 2, 2^32 for nu >= 3).  The colour
+// passes below sum the post-move energy in the colour-1 pass of the last
+// sweep (every bond joins one site of each colour).
 struct TileCtx {
   uint32_t* lds;
   const unsigned long long* thr_of_nu;
@@ -262,7 +256,7 @@ struct TileCtx {
   // kModelGauss16
   const int8_t* rowk;                  // row couplings (see DevPop)
   uint32_t rowk_stride;
-  const unsigned long long* gtab;      // LDS copy of the dE16 threshold table
+  const uint32_t* gaddr;               // 16 max(he16, 0) of (site, pattern), see DevPop
   // kModelReal
   const unsigned long long* rthr;      // thresholds of (site, pattern) for this sweep
   const long long* rhe;                // half energy changes he of (site, pattern)
@@ -362,37 +356,6 @@ __device__ __forceinline__ SiteLoad load_site_words(const RowAddr& a) {
   return w;
 }
 
-template <int L, int Q, bool ACCUM>
-__device__ __forceinline__ void site_update(const TileCtx& c, const RowAddr& a, const SiteLoad& w,
-                                            uint32_t draw, uint32_t& usum) {
-  uint32_t* const own_p = const_cast<uint32_t*>(a.own) + 2 * Q;
-  const uint32_t jlo = (uint32_t)a.j, jhi = (uint32_t)(a.j >> 32);
-  uint32_t b[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int bit = 6 * Q + k;  // coupling bit of (site Q, neighbour k) in the row word
-    const uint32_t jm = bit < 32 ? (uint32_t)((int32_t)(jlo << (31 - bit)) >> 31)
-                                 : (uint32_t)((int32_t)(jhi << (63 - bit)) >> 31);
-    b[k] = __builtin_amdgcn_ubfe(xor3_s(w.nb[k], w.own, jm), c.pos, 1);
-  }
-  // nu = sum of the six bits; the threshold table sits at LDS address 0, so
-  // its byte address 8 nu comes out of one v_add_lshl_u32
-  const uint32_t part = b[0] + b[1] + b[2] + b[3] + b[4];
-  uint32_t addr;
-  asm("v_add_lshl_u32 %0, %1, %2, 3" : "=v"(addr) : "v"(part), "v"(b[5]));
-  const unsigned long long thr = *reinterpret_cast<const unsigned long long*>(
-      reinterpret_cast<const char*>(c.thr_of_nu) + addr);
-  const bool acc = (unsigned long long)draw < thr;
-  if (ACCUM) {
-    const uint32_t n = addr >> 3;
-    usum += acc ? 6u - n : n;
-  }
-  const unsigned long long f = __ballot(acc);
-  const uint32_t fh = c.hoff ? (uint32_t)(f >> 32) : (uint32_t)f;
-  // one lane per half applies the flips of its 32 replicas
-  if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 // Coupling k (in quanta 1/16) of site Q of a row to its neighbour K: a
 // sign-extended byte of the row's words (uniform: scalar registers).
 template <int Q, int K>
@@ -402,51 +365,6 @@ __device__ __forceinline__ int32_t row_k(const RowAddr& a) {
   return (int32_t)(w << (24 - 8 * (b % 4))) >> 24;
 }
 
-// b * k + c for a 0/1 lane value b and a uniform coupling k (|k| < 2^23):
-// one v_mad_i32_i24 with k in a scalar register.
-__device__ __forceinline__ int32_t mad_i24(uint32_t b, int32_t k, int32_t c) {
-  int32_t r;
-  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(b), "s"(k), "v"(c));
-  return r;
-}
-
-// Metropolis update of one site for quantised Gaussian couplings.  With x_k =
-// [s_i != s_k] (own bit ^ neighbour bit), sum_k k_k s_i s_k = csum - 2 acc
-// where csum = sum_k k_k and acc = sum_k k_k x_k, so flipping s_i changes
-// E16 by dE = 2 csum - 4 acc.  acc is formed from the neighbour bits b_k
-// alone: with m = sum_k k_k b_k, acc = m if the own bit is 0 and csum - m if
-// it is 1 (x_k = b_k or 1 - b_k), which saves the six XORs with the own word.
-// The move is taken iff its draw is below gtab[max(dE, 0)] (gtab[0] = 2^32:
-// every move with dE <= 0 is taken).  With ACCUM the pass also sums the
-// site's post-move energy -sum_k k_k s_i s_k: in the colour-1 pass of the
-// last sweep that is E16.
-template <int L, int Q, bool ACCUM>
-__device__ __forceinline__ void site_update_g(const TileCtx& c, const RowAddr& a,
-                                              const SiteLoad& w, uint32_t draw, uint32_t& usum) {
-  uint32_t* const own_p = const_cast<uint32_t*>(a.own) + 2 * Q;
-  const int32_t k0 = row_k<Q, 0>(a), k1 = row_k<Q, 1>(a), k2 = row_k<Q, 2>(a);
-  const int32_t k3 = row_k<Q, 3>(a), k4 = row_k<Q, 4>(a), k5 = row_k<Q, 5>(a);
-  const int32_t csum = k0 + k1 + k2 + k3 + k4 + k5;
-  int32_t m = (int32_t)__builtin_amdgcn_ubfe(w.nb[0], c.pos, 1) * k0;
-  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[1], c.pos, 1), k1, m);
-  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[2], c.pos, 1), k2, m);
-  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[3], c.pos, 1), k3, m);
-  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[4], c.pos, 1), k4, m);
-  m = mad_i24(__builtin_amdgcn_ubfe(w.nb[5], c.pos, 1), k5, m);
-  const bool own1 = __builtin_amdgcn_ubfe(w.own, c.pos, 1) != 0u;
-  const int32_t acc = own1 ? csum - m : m;
-  const int32_t dE = 2 * csum - 4 * acc;
-  const unsigned long long thr = c.gtab[dE > 0 ? dE : 0];
-  const bool accept = (unsigned long long)draw < thr;
-  if (ACCUM) {
-    const int32_t e = 2 * acc - csum;  // the site's energy before the move
-    usum += (uint32_t)(accept ? -e : e);
-  }
-  const unsigned long long f = __ballot(accept);
-  const uint32_t fh = c.hoff ? (uint32_t)(f >> 32) : (uint32_t)f;
-  if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 // Pattern y of a site for this lane: bit k set iff neighbour k's spin differs
 // from the site's own (k in the order +x,-x,+y,-y,+z,-z).
 __device__ __forceinline__ uint32_t real_pattern(const TileCtx& c, const SiteLoad& w) {
@@ -454,78 +372,6 @@ __device__ __forceinline__ uint32_t real_pattern(const TileCtx& c, const SiteLoa
 #pragma unroll
   for (int k = 1; k < 6; ++k) y |= __builtin_amdgcn_ubfe(w.nb[k] ^ w.own, c.pos, 1) << k;
   return y;
-}
-
-// Metropolis update of one site for real couplings: the move is taken iff
-// the draw is below thr[cm][y] (the table of the sweep's beta, 2^32 for
-// dE <= 0); with ACCUM the pass also sums the site's post-move bond energy,
-// +he[cm][y] if the spin flipped and -he[cm][y] if not (in the colour-1 pass
-// of the last sweep that is the energy word E32).
-template <int L, int Q, bool ACCUM>
-__device__ __forceinline__ void site_update_r(const TileCtx& c, const RowAddr& a,
-                                              const SiteLoad& w, uint32_t draw, long long& esum) {
-  uint32_t* const own_p = const_cast<uint32_t*>(a.own) + 2 * Q;
-  const uint32_t idx = (a.cm0 + Q) * kRealPatterns + real_pattern(c, w);
-  const unsigned long long thr = c.rthr[idx];
-  const bool accept = (unsigned long long)draw < thr;
-  if (ACCUM) {
-    const long long he = c.rhe[idx];
-    esum += accept ? he : -he;
-  }
-  const unsigned long long f = __ballot(accept);
-  const uint32_t fh = c.hoff ? (uint32_t)(f >> 32) : (uint32_t)f;
-  if (c.pos == 0) __hip_atomic_fetch_xor(own_p, fh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Sites Q.. of row I of a 4-row block.  The words of site Q + 1 are read
-// before site Q is updated: they are other-colour words (not written in this
-// pass) and a different own word, so the early read sees the same values and
-// its LDS latency overlaps the current site's work.  A new Philox group
-// starts every fourth site of the block.
-template <int L, int M, int I, int Q, bool ACCUM>
-__device__ __forceinline__ void block_row(const TileCtx& c, const RowAddr& a, uint32_t g0,
-                                          Words4& d, typename AccOf<M>::type& usum,
-                                          const SiteLoad& w) {
-  constexpr int H = L / 2;
-  constexpr int S = I * H + Q;  // site index within the block
-  SiteLoad wn;
-  if constexpr (Q + 1 < H) wn = load_site_words<L, Q + 1>(a);
-  // a Philox call per group of four sites whether or not a draw can matter (a
-  // threshold of 0 or 2^32 decides without it): no branch in the unrolled rows
-  if constexpr (S % 4 == 0) d = c.ph.draw(c.t, g0 + (uint32_t)(S / 4));
-  if constexpr (M == (int)kModelGauss16)
-    site_update_g<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
-  else if constexpr (M == (int)kModelReal)
-    site_update_r<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
-  else
-    site_update<L, Q, ACCUM>(c, a, w, d.w[S % 4], usum);
-  if constexpr (Q + 1 < H) block_row<L, M, I, Q + 1, ACCUM>(c, a, g0, d, usum, wn);
-}
-
-template <int L, int M, bool ACCUM>
-__device__ typename AccOf<M>::type sweep_colour_blocks(const TileCtx& c,
-                                                       const unsigned long long* rowj,
-                                                       uint32_t colour, uint32_t part,
-                                                       uint32_t nparts) {
-  constexpr uint32_t H = L / 2, N = L * L * L, ROWS = L * L;
-  const uint32_t own0 = colour * (N / 2);
-  typename AccOf<M>::type usum = 0;
-  Words4 d;
-  d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0u;
-  for (uint32_t rb = 4 * part; rb < ROWS; rb += 4 * nparts) {
-    const uint32_t rbu = __builtin_amdgcn_readfirstlane(rb);
-    const uint32_t g0 = (own0 + H * rbu) >> 2;  // first Philox group of the block
-    const RowAddr a0 = row_addr<L, M>(c, rowj, colour, rbu);
-    block_row<L, M, 0, 0, ACCUM>(c, a0, g0, d, usum, load_site_words<L, 0>(a0));
-    const RowAddr a1 = row_addr<L, M>(c, rowj, colour, rbu + 1);
-    block_row<L, M, 1, 0, ACCUM>(c, a1, g0, d, usum, load_site_words<L, 0>(a1));
-    const RowAddr a2 = row_addr<L, M>(c, rowj, colour, rbu + 2);
-    block_row<L, M, 2, 0, ACCUM>(c, a2, g0, d, usum, load_site_words<L, 0>(a2));
-    const RowAddr a3 = row_addr<L, M>(c, rowj, colour, rbu + 3);
-    block_row<L, M, 3, 0, ACCUM>(c, a3, g0, d, usum, load_site_words<L, 0>(a3));
-  }
-  __syncthreads();
-  return usum;
 }
 
 // ---------------------------------------------------------------------------
@@ -820,6 +666,258 @@ __device__ uint32_t sweep_colour_planes(const TileCtx& c, const PlaneSite* __res
   return usum;
 }
 
+// ---------------------------------------------------------------------------
+// Gaussian colour pass (quantised and real couplings) in the same two phases.
+// The threshold of a move depends on the site and on the pattern y of its six
+// "neighbour differs" bits (bit k: s_i != s_k, k in the order +x,-x,+y,-y,
+// +z,-z).  Phase 1 (lane = site) forms the six words x_k = neighbour ^ own of
+// 32 replicas each and spreads them into one byte per replica holding 4 y;
+// phase 2 (lane = replica) reads its byte and looks up the site's threshold
+// for it: for real couplings thr[cm][y] of the sweep's beta (8 bytes, byte
+// offset 8 y), for quantised ones the entry a[cm][y] = 16 max(he16, 0) of a
+// fixed table (4 bytes, byte offset 4 y), the byte address of the dE16 =
+// 2 he16 threshold in the workgroup's LDS copy of the dE16 table.  The draws,
+// the thresholds and the test are those of the one-site-at-a-time form.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ constexpr uint32_t rotl_c(uint32_t m, int k) {
+  return k == 0 ? m : (m << k) | (m >> (32 - k));
+}
+
+// Word J (J = 0..7) of a half's 32 bytes: byte m holds 4 y of the replica at
+// bit J + 8m.  With plane k rotated left by k (once per half, xr[k]), the bit
+// that word J needs from plane k sits at J + k + 8m (mod 32): the six masked
+// merges never overlap (k < 8), and one rotation right by J - 2 moves it to
+// 8m + 2 + k.  The replica at bit b of a half finds its byte where the +-J
+// pass puts it (plane_byte).
+template <int J>
+__device__ __forceinline__ uint32_t pattern_word(const uint32_t (&xr)[6]) {
+  constexpr uint32_t m = 0x01010101u << J;
+  uint32_t t = xr[0] & m;
+#pragma unroll
+  for (int k = 1; k < 6; ++k) t = (xr[k] & rotl_c(m, k)) | t;
+  return J == 2 ? t : rotr32(t, (uint32_t)(J - 2) & 31u);
+}
+
+// Phase 1 of the Gaussian pass for a chunk of n <= 64 sites from colour-major
+// index cm0 (see plane_chunk: same site table, same entry layout).  Lanes past
+// n take site n - 1 again, so that every entry of the area holds a pattern of
+// a site of the chunk (phase 2 reads one group past the chunk's end ahead).
+__device__ __forceinline__ void pattern_chunk(const TileCtx& c, const PlaneSite* __restrict__ sites,
+                                              uint32_t cm0, uint32_t n, uint32_t lane,
+                                              char* planes) {
+  {
+    const uint32_t cm = cm0 + min(lane, n - 1u);
+    const uint4 e0 = reinterpret_cast<const uint4*>(sites)[2 * cm];
+    const uint2 e1 = reinterpret_cast<const uint2*>(sites)[4 * cm + 2];
+    const uint32_t nb8[6] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y};
+    const uint2* w = reinterpret_cast<const uint2*>(c.lds);
+    const char* lds0 = reinterpret_cast<const char*>(c.thr_of_nu);  // LDS address 0
+    const uint2 o = w[cm];
+    uint32_t xa[6], xb[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const uint2 v = *reinterpret_cast<const uint2*>(lds0 + nb8[k]);
+      xa[k] = k == 0 ? v.x ^ o.x : rotr32(v.x ^ o.x, 32u - (uint32_t)k);
+      xb[k] = k == 0 ? v.y ^ o.y : rotr32(v.y ^ o.y, 32u - (uint32_t)k);
+    }
+    uint4 q[4];
+    q[0] = make_uint4(pattern_word<0>(xa), pattern_word<1>(xa), pattern_word<2>(xa),
+                      pattern_word<3>(xa));
+    q[1] = make_uint4(pattern_word<4>(xa), pattern_word<5>(xa), pattern_word<6>(xa),
+                      pattern_word<7>(xa));
+    q[2] = make_uint4(pattern_word<0>(xb), pattern_word<1>(xb), pattern_word<2>(xb),
+                      pattern_word<3>(xb));
+    q[3] = make_uint4(pattern_word<4>(xb), pattern_word<5>(xb), pattern_word<6>(xb),
+                      pattern_word<7>(xb));
+    char* const entry = planes + 64 * lane;
+    const uint32_t rot = plane_rot(lane);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      *reinterpret_cast<uint4*>(entry + 16 * ((j + rot) & 3u)) = q[j];
+  }
+}
+
+// Global memory (vector loads with a uniform 64-bit base and a 32-bit lane
+// offset).
+typedef const __attribute__((address_space(1))) char GlobalChar;
+
+// The threshold of this lane's move at site cm from its byte b = 4 y, in two
+// stages so that a group's reads can be issued ahead: pattern_ref reads the
+// site's table entry (real couplings: the threshold; quantised: the LDS byte
+// offset of the dE16 threshold) and pattern_thr finishes it (quantised: the
+// read of the LDS dE16 table, at byte address GT).
+template <int M>
+struct PatternRef {
+  using type = uint32_t;
+};
+template <>
+struct PatternRef<(int)kModelReal> {
+  using type = unsigned long long;
+};
+
+// Bytes per site of the table pattern_ref reads, and its first row.
+template <int M>
+constexpr uint32_t pattern_row_bytes() {
+  return M == (int)kModelReal ? kRealPatterns * 8 : kRealPatterns * 4;
+}
+template <int M>
+__device__ __forceinline__ GlobalChar* pattern_table(const TileCtx& c) {
+  if constexpr (M == (int)kModelReal)
+    return (GlobalChar*)c.rthr;
+  else
+    return (GlobalChar*)c.gaddr;
+}
+
+// row: the site's row of the table (a uniform address), b: the lane's byte.
+template <int M>
+__device__ __forceinline__ typename PatternRef<M>::type pattern_ref(GlobalChar* row, uint32_t b) {
+  // (a plain 32-bit lane offset: left to itself, the compiler masks the byte
+  // again and forms a 64-bit address per lane)
+  asm("" : "+v"(b));
+  if constexpr (M == (int)kModelReal)
+    return *(const __attribute__((address_space(1))) unsigned long long*)(row + 2u * b);
+  else
+    return *(const __attribute__((address_space(1))) uint32_t*)(row + b);
+}
+
+template <int M, uint32_t GT>
+__device__ __forceinline__ unsigned long long pattern_thr(const TileCtx& c,
+                                                         typename PatternRef<M>::type r) {
+  if constexpr (M == (int)kModelReal) {
+    return r;
+  } else {
+    return *reinterpret_cast<const unsigned long long*>(
+        reinterpret_cast<const char*>(c.thr_of_nu) + GT + r);
+  }
+}
+
+// The site's bond energy he (see kModelReal) for this lane's pattern: the
+// site contributes -he before its move and +he after it.  Quantised
+// couplings keep only 16 max(he16, 0) per pattern; he16(y ^ 63) = -he16(y)
+// (every bit of the pattern inverted), so he16 = (a[y] - a[y ^ 63]) / 16.
+template <int M>
+__device__ __forceinline__ typename AccOf<M>::type pattern_he(const TileCtx& c, uint32_t cm,
+                                                             uint32_t b) {
+  if constexpr (M == (int)kModelReal) {
+    GlobalChar* row = (GlobalChar*)(c.rhe + (size_t)cm * kRealPatterns);
+    return *(const __attribute__((address_space(1))) long long*)(row + 2u * b);
+  } else {
+    GlobalChar* row = (GlobalChar*)(c.gaddr + (size_t)cm * kRealPatterns);
+    const int32_t a = *(const __attribute__((address_space(1))) int32_t*)(row + b);
+    const int32_t an = *(const __attribute__((address_space(1))) int32_t*)(row + (b ^ 252u));
+    return (uint32_t)((a - an) >> 4);
+  }
+}
+
+// The Metropolis test of this lane's replica at site E of a chunk, and the flip.
+template <int M, int E, bool ACCUM>
+__device__ __forceinline__ void pattern_site(const TileCtx& c, const char* ownb, uint32_t cm0,
+                                             uint32_t b, uint32_t draw, unsigned long long thr,
+                                             typename AccOf<M>::type& esum) {
+  const bool acc = (unsigned long long)draw < thr;
+  if (ACCUM) {
+    const typename AccOf<M>::type he = pattern_he<M>(c, cm0 + E, b);
+    esum += acc ? he : -he;
+  }
+  const uint32_t fh = (uint32_t)(__ballot(acc) >> c.hshift);
+  lds_xor_two_lanes<8 * E>(ownb, fh, c.writers);
+}
+
+// The bytes of group G of a chunk and their table entries (pattern_ref).
+// rows: the chunk's first row.  A group past the chunk's end (n) reads bytes
+// of the chunk's last site and the rows of the sites after it (the tables
+// have kPatternPadRows rows to spare); its entries are never used.
+template <int M, int G>
+__device__ __forceinline__ void group_refs(GlobalChar* rows, const PlaneReads& pr,
+                                           uint32_t (&b)[4],
+                                           typename PatternRef<M>::type (&r)[4]) {
+  constexpr uint32_t RB = pattern_row_bytes<M>();
+  b[0] = plane_read<4 * G>(pr);
+  b[1] = plane_read<4 * G + 1>(pr);
+  b[2] = plane_read<4 * G + 2>(pr);
+  b[3] = plane_read<4 * G + 3>(pr);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = pattern_ref<M>(rows + (4 * G + i) * RB, b[i]);
+}
+
+// Phase 2 of the Gaussian pass for the four sites of group G of a chunk and
+// the groups after it (n uniform: the chunk ends at the first group at or past
+// n).  The table entries of group G (b, r) were read one group earlier; this
+// group reads those of group G + 1 before its own Philox call and tests, so
+// that the latency of the dependent reads (byte, table entry, and for
+// quantised couplings the LDS threshold) overlaps a group's work.  The plane
+// area and the tables are not written in this phase.
+template <int M, uint32_t GT, int G, bool ACCUM>
+__device__ __forceinline__ void pattern_groups(const TileCtx& c, const char* ownb,
+                                               const PlaneReads& pr, GlobalChar* rows,
+                                               uint32_t cm0, uint32_t n, const uint32_t (&b)[4],
+                                               const typename PatternRef<M>::type (&r)[4],
+                                               typename AccOf<M>::type& esum) {
+  if ((uint32_t)(4 * G) >= n) return;
+  constexpr uint32_t RB = pattern_row_bytes<M>();
+  uint32_t bn[4];
+  typename PatternRef<M>::type rn[4];
+  if constexpr (G + 1 < 16) {
+    bn[0] = plane_read<4 * G + 4>(pr);
+    bn[1] = plane_read<4 * G + 5>(pr);
+    bn[2] = plane_read<4 * G + 6>(pr);
+    bn[3] = plane_read<4 * G + 7>(pr);
+  }
+  unsigned long long thr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) thr[i] = pattern_thr<M, GT>(c, r[i]);
+  if constexpr (G + 1 < 16) {
+    // the next group's first row as a base of its own in scalar registers:
+    // the four reads then take 12-bit immediate offsets from it (left to
+    // itself, the compiler runs out of offset range and forms 64-bit
+    // addresses per lane)
+    GlobalChar* rg = rows + (4 * G + 4) * RB;
+    asm("" : "+s"(rg));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rn[i] = pattern_ref<M>(rg + i * RB, bn[i]);
+  }
+  const Words4 d = c.ph.draw(c.t, (cm0 >> 2) + (uint32_t)G);
+  pattern_site<M, 4 * G, ACCUM>(c, ownb, cm0, b[0], d.w[0], thr[0], esum);
+  pattern_site<M, 4 * G + 1, ACCUM>(c, ownb, cm0, b[1], d.w[1], thr[1], esum);
+  pattern_site<M, 4 * G + 2, ACCUM>(c, ownb, cm0, b[2], d.w[2], thr[2], esum);
+  pattern_site<M, 4 * G + 3, ACCUM>(c, ownb, cm0, b[3], d.w[3], thr[3], esum);
+  if constexpr (G + 1 < 16)
+    pattern_groups<M, GT, G + 1, ACCUM>(c, ownb, pr, rows, cm0, n, bn, rn, esum);
+}
+
+// One Gaussian colour pass of this wave over its range of wave_sites() sites,
+// a 64-site chunk at a time (see sweep_colour_planes).
+template <int L, int SPLIT, int M, bool ACCUM>
+__device__ typename AccOf<M>::type sweep_colour_patterns(const TileCtx& c,
+                                                         const PlaneSite* __restrict__ sites,
+                                                         uint32_t colour, uint32_t part,
+                                                         char* planes, const PlaneReads& pr,
+                                                         uint32_t lane) {
+  constexpr uint32_t N = L * L * L, HALF = N / 2, W = wave_sites<L, SPLIT>();
+  const uint32_t own0 = colour * HALF;
+  const uint32_t first = part * W;
+  const uint32_t last = min(first + W, HALF);
+  typename AccOf<M>::type esum = 0;
+  const char* const own_h = reinterpret_cast<const char*>(c.lds) + c.hoff;
+  for (uint32_t s0 = first; s0 < last; s0 += 64) {
+    const uint32_t n = __builtin_amdgcn_readfirstlane(min(64u, last - s0));
+    const uint32_t cm0 = __builtin_amdgcn_readfirstlane(own0 + s0);
+    pattern_chunk(c, sites, cm0, n, lane, planes);
+    __builtin_amdgcn_wave_barrier();
+    const char* ownb = own_h + whole_s(8 * cm0);
+    GlobalChar* const rows = pattern_table<M>(c) + (size_t)cm0 * pattern_row_bytes<M>();
+    uint32_t b[4];
+    typename PatternRef<M>::type r[4];
+    group_refs<M, 0>(rows, pr, b, r);
+    pattern_groups<M, kTileLdsBase + 8 * N + kPlaneAreaBytes * SPLIT, 0, ACCUM>(c, ownb, pr, rows,
+                                                                             cm0, n, b, r, esum);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  return esum;
+}
+
 // One row's share of tile_energy_rows, sites Q.. of the row.
 template <int L, int M, int Q>
 __device__ __forceinline__ void tile_energy_row(const TileCtx& c, const RowAddr& a,
@@ -854,7 +952,8 @@ __device__ __forceinline__ void tile_energy_row(const TileCtx& c, const RowAddr&
 
 // Energy of the tile when no sweep ran: sum over colour-0 sites of nu (every
 // bond joins one site of each colour); for kModelGauss16 the sum over colour-0
-// sites of -sum_k k_k s_i s_k = 2 acc - csum (see site_update_g), i.e. E16.
+// sites of -sum_k k_k s_i s_k = 2 acc - csum with csum = sum_k k_k and acc =
+// sum_k k_k [s_i != s_k], i.e. E16; for kModelReal the sum of -he.
 template <int L, int M>
 __device__ typename AccOf<M>::type tile_energy_rows(const TileCtx& c,
                                                     const unsigned long long* rowj, uint32_t part,
@@ -1477,7 +1576,7 @@ __global__ __launch_bounds__(64 * SPLIT)
 __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_sweep(BatchDev B,
                                                                                 Group G) {
   constexpr uint32_t N = L * L * L;
-  __shared__ unsigned long long thr_of_nu[8];  // first LDS object: address 0 (see site_update)
+  __shared__ unsigned long long thr_of_nu[8];  // first LDS object: address 0 (see chunk_sites)
   extern __shared__ uint32_t lds_all[];
   const Member m = member_of(G);
   const DevPop P = B.pops[m.pop];
@@ -1499,10 +1598,11 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
       __builtin_amdgcn_readfirstlane(m.lb < active ? xcd_block(m.lb, active) : m.lb);
   // whole workgroups leave together (the passes below use workgroup barriers)
   if (tile * 64 >= Rs) return;
-  // site_update indexes the threshold table by byte address 8 nu: it must sit
-  // at LDS address 0, and phase 1 of the +-J pass reads the tile image at the
-  // absolute addresses of its site table, so the image must start at
-  // kTileLdsBase.  If the toolchain ever places them elsewhere, report a
+  // Phase 2 of the +-J pass indexes the threshold table by byte address 8 nu:
+  // it must sit at LDS address 0; phase 1 of the colour passes reads the tile
+  // image at the absolute addresses of its site table, so the image must start
+  // at kTileLdsBase; the Gaussian pass reads the dE16 table at the address
+  // that follows from both.  If the toolchain ever places them elsewhere, report a
   // configuration error instead of computing with wrong addresses.
   if ((uint32_t)(uintptr_t)thr_of_nu != 0u || (uint32_t)(uintptr_t)lds_all != kTileLdsBase) {
     if (threadIdx.x == 0) {
@@ -1518,8 +1618,9 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
                                                 : (1ull << 32);
   uint32_t* const lds = lds_all;
   // kModelGauss16: the dE16 threshold table, after the tile image and the
-  // per-replica reduction area (visible after the gather's barrier)
-  unsigned long long* const gtab = reinterpret_cast<unsigned long long*>(lds_all + 2 * N + 64 * SPLIT);
+  // waves' plane areas (visible after the gather's barrier)
+  unsigned long long* const gtab =
+      reinterpret_cast<unsigned long long*>(lds_all + 2 * N + kPlaneAreaBytes / 4 * SPLIT);
   if constexpr (M == (int)kModelGauss16) {
     for (uint32_t i = threadIdx.x; i <= (uint32_t)kGaussDEMax; i += 64 * SPLIT) gtab[i] = P.gthr[i];
   }
@@ -1545,7 +1646,7 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
                (sp.thr[2] != 0 && sp.thr[2] < (1ull << 32));
   c.rowk = P.rowk;
   c.rowk_stride = P.rowk_stride;
-  c.gtab = gtab;
+  c.gaddr = P.gaddr;
   c.rthr = P.rthr;
   c.rhe = P.rhe;
   const unsigned long long* rowj = P.rowj;
@@ -1553,27 +1654,27 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   if (sp.n_sweeps == 0) {
     U = tile_energy_rows<L, M>(c, rowj, part, SPLIT);
   } else {
+    // this wave's plane area (phase 1 of the colour passes), after the tile
+    // image, and the lane's byte address in it for each rotation
+    char* const planes = reinterpret_cast<char*>(lds_all + 2 * N) + kPlaneAreaBytes * part;
+    PlaneReads pr;
+    {
+      const uint32_t pb = plane_byte(lane);
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k)
+        pr.at[k] = reinterpret_cast<const uint8_t*>(planes) + 16u * (((pb >> 4) + k) & 3u) +
+                   (pb & 15u);
+    }
     if constexpr (M != (int)kModelPm) {
       for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
         c.t = sp.t0 + s;
-        sweep_colour_blocks<L, M, false>(c, rowj, 0u, part, SPLIT);
-        sweep_colour_blocks<L, M, false>(c, rowj, 1u, part, SPLIT);
+        sweep_colour_patterns<L, SPLIT, M, false>(c, P.psites, 0u, part, planes, pr, lane);
+        sweep_colour_patterns<L, SPLIT, M, false>(c, P.psites, 1u, part, planes, pr, lane);
       }
       c.t = sp.t0 + sp.n_sweeps - 1;
-      sweep_colour_blocks<L, M, false>(c, rowj, 0u, part, SPLIT);
-      U = sweep_colour_blocks<L, M, true>(c, rowj, 1u, part, SPLIT);
+      sweep_colour_patterns<L, SPLIT, M, false>(c, P.psites, 0u, part, planes, pr, lane);
+      U = sweep_colour_patterns<L, SPLIT, M, true>(c, P.psites, 1u, part, planes, pr, lane);
     } else {
-      // this wave's plane area (phase 1 of the +-J colour passes), after the
-      // tile image, and the lane's byte address in it for each rotation
-      char* const planes = reinterpret_cast<char*>(lds_all + 2 * N) + kPlaneAreaBytes * part;
-      PlaneReads pr;
-      {
-        const uint32_t pb = plane_byte(lane);
-#pragma unroll
-        for (uint32_t k = 0; k < 4; ++k)
-          pr.at[k] = reinterpret_cast<const uint8_t*>(planes) + 16u * (((pb >> 4) + k) & 3u) +
-                     (pb & 15u);
-      }
       // every move that raises the energy has a threshold below 2^32 (beta
       // not 0 in double precision): the passes take the 32-bit form, but for
       // the last colour-1 pass, which also sums the energy
@@ -2065,10 +2166,9 @@ void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t 
   // after the tile image: the reduction area and the Gaussian threshold table,
   // or the +-J plane areas (one per wave; the reduction area lies over them)
   const size_t after = model == kModelGauss16
-                           ? 4 * 64 * split + (size_t)(kGaussDEMax + 1) * 8
-                       : model == kModelReal
-                           ? (size_t)8 * 64 * split
-                           : std::max((size_t)kPlaneAreaBytes * split, (size_t)4 * 64 * split);
+                           ? (size_t)kPlaneAreaBytes * split + (size_t)(kGaussDEMax + 1) * 8
+                           : (size_t)kPlaneAreaBytes * split;
+  static_assert(kPlaneAreaBytes >= 8 * 64, "the reduction area lies over the plane areas");
   const size_t lds = (size_t)L * L * L * 8 + after;
   if (model == kModelReal) {
     if (split == 8)
