@@ -742,12 +742,11 @@ __device__ __forceinline__ void pattern_chunk(const TileCtx& c, const PlaneSite*
 // offset).
 typedef const __attribute__((address_space(1))) char GlobalChar;
 
-// The threshold of this lane's move at a site from its byte b = 4 y.  The
-// site's table row (real couplings: thresholds, 8 bytes per pattern;
-// quantised: the LDS byte offsets 16 max(he16, 0) of the dE16 thresholds, 4
-// bytes per pattern) is read from the wave's staging area in LDS: stage_ref
-// reads the entry, pattern_thr finishes it (quantised: the read of the dE16
-// table at LDS byte address GT).
+// The threshold of this lane's move at site cm from its byte b = 4 y, in two
+// stages so that a group's reads can be issued ahead: pattern_ref reads the
+// site's table entry (real couplings: the threshold; quantised: the LDS byte
+// offset of the dE16 threshold) and pattern_thr finishes it (quantised: the
+// read of the LDS dE16 table, at byte address GT).
 template <int M>
 struct PatternRef {
   using type = uint32_t;
@@ -757,15 +756,10 @@ struct PatternRef<(int)kModelReal> {
   using type = unsigned long long;
 };
 
-// Bytes per site of the table, its first row, and the bytes of the four rows
-// of a Philox group (one staging area).
+// Bytes per site of the table pattern_ref reads, and its first row.
 template <int M>
 constexpr uint32_t pattern_row_bytes() {
   return M == (int)kModelReal ? kRealPatterns * 8 : kRealPatterns * 4;
-}
-template <int M>
-constexpr uint32_t pattern_stage_bytes() {
-  return 4 * pattern_row_bytes<M>();
 }
 template <int M>
 __device__ __forceinline__ GlobalChar* pattern_table(const TileCtx& c) {
@@ -775,12 +769,16 @@ __device__ __forceinline__ GlobalChar* pattern_table(const TileCtx& c) {
     return (GlobalChar*)c.gaddr;
 }
 
+// row: the site's row of the table (a uniform address), b: the lane's byte.
 template <int M>
-__device__ __forceinline__ typename PatternRef<M>::type stage_ref(const char* row, uint32_t b) {
+__device__ __forceinline__ typename PatternRef<M>::type pattern_ref(GlobalChar* row, uint32_t b) {
+  // (a plain 32-bit lane offset: left to itself, the compiler masks the byte
+  // again and forms a 64-bit address per lane)
+  asm("" : "+v"(b));
   if constexpr (M == (int)kModelReal)
-    return *reinterpret_cast<const unsigned long long*>(row + 2u * b);
+    return *(const __attribute__((address_space(1))) unsigned long long*)(row + 2u * b);
   else
-    return *reinterpret_cast<const uint32_t*>(row + b);
+    return *(const __attribute__((address_space(1))) uint32_t*)(row + b);
 }
 
 template <int M, uint32_t GT>
@@ -795,19 +793,19 @@ __device__ __forceinline__ unsigned long long pattern_thr(const TileCtx& c,
 }
 
 // The site's bond energy he (see kModelReal) for this lane's pattern: the
-// site contributes -he before its move and +he after it.  Real couplings read
-// it from the he table; quantised couplings keep only 16 max(he16, 0) per
-// pattern, and he16(y ^ 63) = -he16(y) (every bit of the pattern inverted), so
-// he16 = (a[y] - a[y ^ 63]) / 16 from the staged row.
+// site contributes -he before its move and +he after it.  Quantised
+// couplings keep only 16 max(he16, 0) per pattern; he16(y ^ 63) = -he16(y)
+// (every bit of the pattern inverted), so he16 = (a[y] - a[y ^ 63]) / 16.
 template <int M>
 __device__ __forceinline__ typename AccOf<M>::type pattern_he(const TileCtx& c, uint32_t cm,
-                                                             const char* row, uint32_t b) {
+                                                             uint32_t b) {
   if constexpr (M == (int)kModelReal) {
-    GlobalChar* hrow = (GlobalChar*)(c.rhe + (size_t)cm * kRealPatterns);
-    return *(const __attribute__((address_space(1))) long long*)(hrow + 2u * b);
+    GlobalChar* row = (GlobalChar*)(c.rhe + (size_t)cm * kRealPatterns);
+    return *(const __attribute__((address_space(1))) long long*)(row + 2u * b);
   } else {
-    const int32_t a = *reinterpret_cast<const int32_t*>(row + b);
-    const int32_t an = *reinterpret_cast<const int32_t*>(row + (b ^ 252u));
+    GlobalChar* row = (GlobalChar*)(c.gaddr + (size_t)cm * kRealPatterns);
+    const int32_t a = *(const __attribute__((address_space(1))) int32_t*)(row + b);
+    const int32_t an = *(const __attribute__((address_space(1))) int32_t*)(row + (b ^ 252u));
     return (uint32_t)((a - an) >> 4);
   }
 }
@@ -815,116 +813,105 @@ __device__ __forceinline__ typename AccOf<M>::type pattern_he(const TileCtx& c, 
 // The Metropolis test of this lane's replica at site E of a chunk, and the flip.
 template <int M, int E, bool ACCUM>
 __device__ __forceinline__ void pattern_site(const TileCtx& c, const char* ownb, uint32_t cm0,
-                                             const char* row, uint32_t b, uint32_t draw,
-                                             unsigned long long thr,
+                                             uint32_t b, uint32_t draw, unsigned long long thr,
                                              typename AccOf<M>::type& esum) {
   const bool acc = (unsigned long long)draw < thr;
   if (ACCUM) {
-    const typename AccOf<M>::type he = pattern_he<M>(c, cm0 + E, row, b);
+    const typename AccOf<M>::type he = pattern_he<M>(c, cm0 + E, b);
     esum += acc ? he : -he;
   }
   const uint32_t fh = (uint32_t)(__ballot(acc) >> c.hshift);
   lds_xor_two_lanes<8 * E>(ownb, fh, c.writers);
 }
 
-// The four table rows of a group, one 16-byte piece (or two) per lane: a
-// contiguous read of 1 KB (2 KB) per wave instruction.  rg is the group's
-// first row (uniform), lane16 = 16 lane.
-typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
-template <int M>
-struct StageRegs {
-  U32x4 q[pattern_stage_bytes<M>() / 1024];
-};
-
-template <int M>
-__device__ __forceinline__ StageRegs<M> stage_load(GlobalChar* rg, uint32_t lane16) {
-  // the group's rows as a base of their own in scalar registers (left to
-  // itself, the compiler runs out of immediate offset range and forms 64-bit
-  // addresses per lane)
-  asm("" : "+s"(rg));
-  StageRegs<M> s;
-#pragma unroll
-  for (uint32_t k = 0; k < pattern_stage_bytes<M>() / 1024; ++k)
-    s.q[k] = *(const __attribute__((address_space(1))) U32x4*)(rg + 1024 * k + lane16);
-  return s;
-}
-
-template <int M>
-__device__ __forceinline__ void stage_store(char* stage_lane, const StageRegs<M>& s) {
-#pragma unroll
-  for (uint32_t k = 0; k < pattern_stage_bytes<M>() / 1024; ++k)
-    *reinterpret_cast<U32x4*>(stage_lane + 1024 * k) = s.q[k];
-}
-
-// Phase 2 of the Gaussian pass for the four sites of group G of a chunk and
-// the groups after it (n uniform: the chunk ends at the first group at or past
-// n).  The group's four table rows are in the wave's staging area; after the
-// group has read its entries, the rows of group G + 1, read from global memory
-// before its Philox call, replace them (a wave's LDS operations take effect in
-// order).  A group past the chunk's end reads the rows of the sites after it
-// (the tables have kPatternPadRows rows to spare) and never uses them.  The
-// plane area and the tables are not written in this phase.
-template <int M, uint32_t GT, int G, bool ACCUM>
-__device__ __forceinline__ void pattern_groups(const TileCtx& c, const char* ownb,
-                                               const PlaneReads& pr, GlobalChar* rows,
-                                               const char* stage, char* stage_lane,
-                                               uint32_t lane16, uint32_t cm0, uint32_t n,
-                                               typename AccOf<M>::type& esum) {
-  if ((uint32_t)(4 * G) >= n) return;
+// The bytes of group G of a chunk and their table entries (pattern_ref).
+// rows: the chunk's first row.  A group past the chunk's end (n) reads bytes
+// of the chunk's last site and the rows of the sites after it (the tables
+// have kPatternPadRows rows to spare); its entries are never used.
+template <int M, int G>
+__device__ __forceinline__ void group_refs(GlobalChar* rows, const PlaneReads& pr,
+                                           uint32_t (&b)[4],
+                                           typename PatternRef<M>::type (&r)[4]) {
   constexpr uint32_t RB = pattern_row_bytes<M>();
-  uint32_t b[4];
   b[0] = plane_read<4 * G>(pr);
   b[1] = plane_read<4 * G + 1>(pr);
   b[2] = plane_read<4 * G + 2>(pr);
   b[3] = plane_read<4 * G + 3>(pr);
-  typename PatternRef<M>::type r[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) r[i] = stage_ref<M>(stage + i * RB, b[i]);
-  StageRegs<M> next;
-  if constexpr (G + 1 < 16) next = stage_load<M>(rows + (4 * G + 4) * RB, lane16);
+  for (int i = 0; i < 4; ++i) r[i] = pattern_ref<M>(rows + (4 * G + i) * RB, b[i]);
+}
+
+// Phase 2 of the Gaussian pass for the four sites of group G of a chunk and
+// the groups after it (n uniform: the chunk ends at the first group at or past
+// n).  The table entries of group G (b, r) were read one group earlier; this
+// group reads those of group G + 1 before its own Philox call and tests, so
+// that the latency of the dependent reads (byte, table entry, and for
+// quantised couplings the LDS threshold) overlaps a group's work.  The plane
+// area and the tables are not written in this phase.
+template <int M, uint32_t GT, int G, bool ACCUM>
+__device__ __forceinline__ void pattern_groups(const TileCtx& c, const char* ownb,
+                                               const PlaneReads& pr, GlobalChar* rows,
+                                               uint32_t cm0, uint32_t n, const uint32_t (&b)[4],
+                                               const typename PatternRef<M>::type (&r)[4],
+                                               typename AccOf<M>::type& esum) {
+  if ((uint32_t)(4 * G) >= n) return;
+  constexpr uint32_t RB = pattern_row_bytes<M>();
+  uint32_t bn[4];
+  typename PatternRef<M>::type rn[4];
+  if constexpr (G + 1 < 16) {
+    bn[0] = plane_read<4 * G + 4>(pr);
+    bn[1] = plane_read<4 * G + 5>(pr);
+    bn[2] = plane_read<4 * G + 6>(pr);
+    bn[3] = plane_read<4 * G + 7>(pr);
+  }
   unsigned long long thr[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) thr[i] = pattern_thr<M, GT>(c, r[i]);
-  const Words4 d = c.ph.draw(c.t, (cm0 >> 2) + (uint32_t)G);
-  pattern_site<M, 4 * G, ACCUM>(c, ownb, cm0, stage, b[0], d.w[0], thr[0], esum);
-  pattern_site<M, 4 * G + 1, ACCUM>(c, ownb, cm0, stage + RB, b[1], d.w[1], thr[1], esum);
-  pattern_site<M, 4 * G + 2, ACCUM>(c, ownb, cm0, stage + 2 * RB, b[2], d.w[2], thr[2], esum);
-  pattern_site<M, 4 * G + 3, ACCUM>(c, ownb, cm0, stage + 3 * RB, b[3], d.w[3], thr[3], esum);
   if constexpr (G + 1 < 16) {
-    stage_store<M>(stage_lane, next);
-    pattern_groups<M, GT, G + 1, ACCUM>(c, ownb, pr, rows, stage, stage_lane, lane16, cm0, n,
-                                        esum);
+    // the next group's first row as a base of its own in scalar registers:
+    // the four reads then take 12-bit immediate offsets from it (left to
+    // itself, the compiler runs out of offset range and forms 64-bit
+    // addresses per lane)
+    GlobalChar* rg = rows + (4 * G + 4) * RB;
+    asm("" : "+s"(rg));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rn[i] = pattern_ref<M>(rg + i * RB, bn[i]);
   }
+  const Words4 d = c.ph.draw(c.t, (cm0 >> 2) + (uint32_t)G);
+  pattern_site<M, 4 * G, ACCUM>(c, ownb, cm0, b[0], d.w[0], thr[0], esum);
+  pattern_site<M, 4 * G + 1, ACCUM>(c, ownb, cm0, b[1], d.w[1], thr[1], esum);
+  pattern_site<M, 4 * G + 2, ACCUM>(c, ownb, cm0, b[2], d.w[2], thr[2], esum);
+  pattern_site<M, 4 * G + 3, ACCUM>(c, ownb, cm0, b[3], d.w[3], thr[3], esum);
+  if constexpr (G + 1 < 16)
+    pattern_groups<M, GT, G + 1, ACCUM>(c, ownb, pr, rows, cm0, n, bn, rn, esum);
 }
 
 // One Gaussian colour pass of this wave over its range of wave_sites() sites,
-// a 64-site chunk at a time (see sweep_colour_planes).  stage: the wave's
-// staging area (pattern_stage_bytes), GT: the LDS byte address of the dE16
-// table (quantised couplings).
-template <int L, int SPLIT, int M, bool ACCUM, uint32_t GT>
+// a 64-site chunk at a time (see sweep_colour_planes).
+template <int L, int SPLIT, int M, bool ACCUM>
 __device__ typename AccOf<M>::type sweep_colour_patterns(const TileCtx& c,
                                                          const PlaneSite* __restrict__ sites,
                                                          uint32_t colour, uint32_t part,
                                                          char* planes, const PlaneReads& pr,
-                                                         char* stage, uint32_t lane) {
+                                                         uint32_t lane) {
   constexpr uint32_t N = L * L * L, HALF = N / 2, W = wave_sites<L, SPLIT>();
   const uint32_t own0 = colour * HALF;
   const uint32_t first = part * W;
   const uint32_t last = min(first + W, HALF);
   typename AccOf<M>::type esum = 0;
   const char* const own_h = reinterpret_cast<const char*>(c.lds) + c.hoff;
-  const uint32_t lane16 = 16u * lane;
-  char* const stage_lane = stage + lane16;
   for (uint32_t s0 = first; s0 < last; s0 += 64) {
     const uint32_t n = __builtin_amdgcn_readfirstlane(min(64u, last - s0));
     const uint32_t cm0 = __builtin_amdgcn_readfirstlane(own0 + s0);
-    GlobalChar* const rows = pattern_table<M>(c) + (size_t)cm0 * pattern_row_bytes<M>();
-    const StageRegs<M> first_rows = stage_load<M>(rows, lane16);
     pattern_chunk(c, sites, cm0, n, lane, planes);
-    stage_store<M>(stage_lane, first_rows);
     __builtin_amdgcn_wave_barrier();
     const char* ownb = own_h + whole_s(8 * cm0);
-    pattern_groups<M, GT, 0, ACCUM>(c, ownb, pr, rows, stage, stage_lane, lane16, cm0, n, esum);
+    GlobalChar* const rows = pattern_table<M>(c) + (size_t)cm0 * pattern_row_bytes<M>();
+    uint32_t b[4];
+    typename PatternRef<M>::type r[4];
+    group_refs<M, 0>(rows, pr, b, r);
+    pattern_groups<M, kTileLdsBase + 8 * N + kPlaneAreaBytes * SPLIT, 0, ACCUM>(c, ownb, pr, rows,
+                                                                             cm0, n, b, r, esum);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
@@ -1630,11 +1617,10 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
                              : threadIdx.x == 2 ? sp.thr[0]
                                                 : (1ull << 32);
   uint32_t* const lds = lds_all;
-  // kModelGauss16: the dE16 threshold table, after the tile image, the
-  // waves' plane areas and their staging areas (visible after the gather's
-  // barrier)
-  unsigned long long* const gtab = reinterpret_cast<unsigned long long*>(
-      lds_all + 2 * N + (kPlaneAreaBytes + pattern_stage_bytes<kModelGauss16>()) / 4 * SPLIT);
+  // kModelGauss16: the dE16 threshold table, after the tile image and the
+  // waves' plane areas (visible after the gather's barrier)
+  unsigned long long* const gtab =
+      reinterpret_cast<unsigned long long*>(lds_all + 2 * N + kPlaneAreaBytes / 4 * SPLIT);
   if constexpr (M == (int)kModelGauss16) {
     for (uint32_t i = threadIdx.x; i <= (uint32_t)kGaussDEMax; i += 64 * SPLIT) gtab[i] = P.gthr[i];
   }
@@ -1680,23 +1666,14 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
                    (pb & 15u);
     }
     if constexpr (M != (int)kModelPm) {
-      // this wave's staging area for table rows, after the plane areas
-      constexpr uint32_t SB = pattern_stage_bytes<M>();
-      char* const stage =
-          reinterpret_cast<char*>(lds_all + 2 * N) + kPlaneAreaBytes * SPLIT + SB * part;
-      constexpr uint32_t GT = kTileLdsBase + 8 * N + (kPlaneAreaBytes + SB) * SPLIT;
       for (uint32_t s = 0; s + 1 < sp.n_sweeps; ++s) {
         c.t = sp.t0 + s;
-        sweep_colour_patterns<L, SPLIT, M, false, GT>(c, P.psites, 0u, part, planes, pr, stage,
-                                                      lane);
-        sweep_colour_patterns<L, SPLIT, M, false, GT>(c, P.psites, 1u, part, planes, pr, stage,
-                                                      lane);
+        sweep_colour_patterns<L, SPLIT, M, false>(c, P.psites, 0u, part, planes, pr, lane);
+        sweep_colour_patterns<L, SPLIT, M, false>(c, P.psites, 1u, part, planes, pr, lane);
       }
       c.t = sp.t0 + sp.n_sweeps - 1;
-      sweep_colour_patterns<L, SPLIT, M, false, GT>(c, P.psites, 0u, part, planes, pr, stage,
-                                                    lane);
-      U = sweep_colour_patterns<L, SPLIT, M, true, GT>(c, P.psites, 1u, part, planes, pr, stage,
-                                                       lane);
+      sweep_colour_patterns<L, SPLIT, M, false>(c, P.psites, 0u, part, planes, pr, lane);
+      U = sweep_colour_patterns<L, SPLIT, M, true>(c, P.psites, 1u, part, planes, pr, lane);
     } else {
       // every move that raises the energy has a threshold below 2^32 (beta
       // not 0 in double precision): the passes take the 32-bit form, but for
@@ -2184,15 +2161,13 @@ hipError_t launch_scatter(const BatchDev& B, const Group& g, hipStream_t stream)
 template <int LAYOUT, int L>
 void launch_sweep_l(const BatchDev& B, const Group& g, uint32_t split, uint32_t model,
                     hipStream_t stream) {
-  // after the tile image: the plane areas (one per wave; the reduction area
-  // of the epilogue lies over them), for Gaussian couplings the staging areas
-  // (one per wave), and for quantised couplings the dE16 threshold table
-  const size_t after =
-      model == kModelGauss16
-          ? (size_t)(kPlaneAreaBytes + pattern_stage_bytes<kModelGauss16>()) * split +
-                (size_t)(kGaussDEMax + 1) * 8
-      : model == kModelReal ? (size_t)(kPlaneAreaBytes + pattern_stage_bytes<kModelReal>()) * split
-                            : (size_t)kPlaneAreaBytes * split;
+  // after the tile image and the reduction area: the Gaussian threshold table,
+  // or the +-J plane areas (one per wave)
+  // after the tile image: the reduction area and the Gaussian threshold table,
+  // or the +-J plane areas (one per wave; the reduction area lies over them)
+  const size_t after = model == kModelGauss16
+                           ? (size_t)kPlaneAreaBytes * split + (size_t)(kGaussDEMax + 1) * 8
+                           : (size_t)kPlaneAreaBytes * split;
   static_assert(kPlaneAreaBytes >= 8 * 64, "the reduction area lies over the plane areas");
   const size_t lds = (size_t)L * L * L * 8 + after;
   if (model == kModelReal) {
