@@ -132,7 +132,7 @@ bool make_layout(const pa_params* p, Layout* out) {
   const size_t n_part = std::max<size_t>(l.n_blocks, 3 * (size_t)pa::kRealSumBlocks);
   l.off_rpart = take(real ? n_part * sizeof(pa::RealPartial) : 0);
   // PA_MODEL_GAUSS16: the threshold offsets of every (site, pattern)
-  l.off_gaddr = take(p->model == PA_MODEL_GAUSS16 ? rows * pa::kRealPatterns * 4 : 0);
+  l.off_gaddr = take(p->model == PA_MODEL_GAUSS16 ? rows * pa::kRealPatterns * 2 : 0);
   l.total = o;
   *out = l;
   return true;
@@ -1019,14 +1019,14 @@ int init_instance(const pa_params* p, const int8_t* J_host, const std::vector<lo
   build_sites(l.L, J_host, &in->sites, &in->cm_of_site, &in->rowj);
   // PA_MODEL_GAUSS16: per (site, pattern) the LDS byte offset 8 max(dE16, 0)
   // = 16 max(he16, 0) of the move's threshold in the sweep's dE16 table
-  std::vector<uint32_t> gaddr;
+  std::vector<uint16_t> gaddr;
   if (l.model == PA_MODEL_GAUSS16) {
     build_rowk(l.L, J_host, l.rowk_stride, &in->rowk);
     const std::vector<long long> k16(J_host, J_host + 3 * (size_t)l.N);
     const std::vector<long long> he16 = real_he_table(l.L, k16);
     gaddr.resize(he16.size());
     for (size_t i = 0; i < he16.size(); ++i)
-      gaddr[i] = 16u * (uint32_t)(he16[i] > 0 ? he16[i] : 0);
+      gaddr[i] = (uint16_t)(16 * (he16[i] > 0 ? he16[i] : 0));  // <= 16 x 6 x 127
   }
 
   DevPop& P = in->dev;
@@ -1066,7 +1066,7 @@ int init_instance(const pa_params* p, const int8_t* J_host, const std::vector<lo
   P.rowk = reinterpret_cast<const int8_t*>(w + l.off_rowk);
   P.gthr = reinterpret_cast<const unsigned long long*>(w + l.off_gthr);
   const bool real = l.model == PA_MODEL_GAUSS;
-  P.gaddr = gaddr.empty() ? nullptr : reinterpret_cast<const uint32_t*>(w + l.off_gaddr);
+  P.gaddr = gaddr.empty() ? nullptr : reinterpret_cast<const uint16_t*>(w + l.off_gaddr);
   P.rhe = real ? reinterpret_cast<const long long*>(w + l.off_rhe) : nullptr;
   P.rthr = real ? reinterpret_cast<unsigned long long*>(w + l.off_rthr) : nullptr;
   P.rs = reinterpret_cast<pa::RealScalars*>(w + l.off_rs);
@@ -1141,7 +1141,7 @@ int init_instance(const pa_params* p, const int8_t* J_host, const std::vector<lo
       hipMemcpyAsync(P.rs, &rs0, sizeof(rs0), hipMemcpyHostToDevice, in->stream) != hipSuccess ||
       (real && hipMemcpyAsync(w + l.off_rhe, rhe->data(), rhe->size() * 8, hipMemcpyHostToDevice,
                               in->stream) != hipSuccess) ||
-      (!gaddr.empty() && hipMemcpyAsync(w + l.off_gaddr, gaddr.data(), gaddr.size() * 4,
+      (!gaddr.empty() && hipMemcpyAsync(w + l.off_gaddr, gaddr.data(), gaddr.size() * 2,
                                         hipMemcpyHostToDevice, in->stream) != hipSuccess) ||
       hipMemcpyAsync(in->d_pops, &in->dev, sizeof(DevPop), hipMemcpyHostToDevice, in->stream) !=
           hipSuccess ||

@@ -190,7 +190,7 @@ struct DevPop {
                                 // coupling k of its site q to neighbour k (J = k / 16)
   const unsigned long long* gthr;  // kModelGauss16: thr[d] = floor(2^32 exp(-beta d / 16)),
                                    // d = 0..kGaussDEMax, for the coming sweep
-  const uint32_t* gaddr;            // kModelGauss16: 16 max(he16[cm][y], 0), N x 64, with he16
+  const uint16_t* gaddr;            // kModelGauss16: 16 max(he16[cm][y], 0), N x 64, with he16
                                    // the he of kModelReal in units 1/16: the byte offset of the
                                    // move's threshold in the dE16 table (dE16 = 2 he16)
   const long long* rhe;            // kModelReal: he[cm][y], N x 64 (see kModelReal)

@@ -256,7 +256,7 @@ struct TileCtx {
   // kModelGauss16
   const int8_t* rowk;                  // row couplings (see DevPop)
   uint32_t rowk_stride;
-  const uint32_t* gaddr;               // 16 max(he16, 0) of (site, pattern), see DevPop
+  const uint16_t* gaddr;               // 16 max(he16, 0) of (site, pattern), see DevPop
   // kModelReal
   const unsigned long long* rthr;      // thresholds of (site, pattern) for this sweep
   const long long* rhe;                // half energy changes he of (site, pattern)
@@ -671,12 +671,12 @@ __device__ uint32_t sweep_colour_planes(const TileCtx& c, const PlaneSite* __res
 // The threshold of a move depends on the site and on the pattern y of its six
 // "neighbour differs" bits (bit k: s_i != s_k, k in the order +x,-x,+y,-y,
 // +z,-z).  Phase 1 (lane = site) forms the six words x_k = neighbour ^ own of
-// 32 replicas each and spreads them into one byte per replica holding 4 y;
+// 32 replicas each and spreads them into one byte per replica holding y << B;
 // phase 2 (lane = replica) reads its byte and looks up the site's threshold
 // for it: for real couplings thr[cm][y] of the sweep's beta (8 bytes, byte
-// offset 8 y), for quantised ones the entry a[cm][y] = 16 max(he16, 0) of a
-// fixed table (4 bytes, byte offset 4 y), the byte address of the dE16 =
-// 2 he16 threshold in the workgroup's LDS copy of the dE16 table.  The draws,
+// offset 8 y, B = 2), for quantised ones the entry a[cm][y] = 16 max(he16, 0)
+// of a fixed table (2 bytes, byte offset 2 y, B = 1), the byte address of the
+// dE16 = 2 he16 threshold in the workgroup's LDS copy of the dE16 table.  The draws,
 // the thresholds and the test are those of the one-site-at-a-time form.
 // ---------------------------------------------------------------------------
 
@@ -684,25 +684,34 @@ __device__ __forceinline__ constexpr uint32_t rotl_c(uint32_t m, int k) {
   return k == 0 ? m : (m << k) | (m >> (32 - k));
 }
 
-// Word J (J = 0..7) of a half's 32 bytes: byte m holds 4 y of the replica at
-// bit J + 8m.  With plane k rotated left by k (once per half, xr[k]), the bit
-// that word J needs from plane k sits at J + k + 8m (mod 32): the six masked
-// merges never overlap (k < 8), and one rotation right by J - 2 moves it to
-// 8m + 2 + k.  The replica at bit b of a half finds its byte where the +-J
-// pass puts it (plane_byte).
-template <int J>
+// The pattern byte of a replica holds y << B: the byte offset of its entry
+// in the site's table row (quantised couplings: 2-byte entries, B = 1; real
+// couplings: 8-byte thresholds at twice the byte, B = 2).
+template <int M>
+constexpr int pattern_shift() {
+  return M == (int)kModelReal ? 2 : 1;
+}
+
+// Word J (J = 0..7) of a half's 32 bytes: byte m holds y << B of the replica
+// at bit J + 8m.  With plane k rotated left by k (once per half, xr[k]), the
+// bit that word J needs from plane k sits at J + k + 8m (mod 32): the six
+// masked merges never overlap (k < 8), and one rotation right by J - B moves
+// it to 8m + B + k.  The replica at bit b of a half finds its byte where the
+// +-J pass puts it (plane_byte).
+template <int J, int B>
 __device__ __forceinline__ uint32_t pattern_word(const uint32_t (&xr)[6]) {
   constexpr uint32_t m = 0x01010101u << J;
   uint32_t t = xr[0] & m;
 #pragma unroll
   for (int k = 1; k < 6; ++k) t = (xr[k] & rotl_c(m, k)) | t;
-  return J == 2 ? t : rotr32(t, (uint32_t)(J - 2) & 31u);
+  return J == B ? t : rotr32(t, (uint32_t)(J - B) & 31u);
 }
 
 // Phase 1 of the Gaussian pass for a chunk of n <= 64 sites from colour-major
 // index cm0 (see plane_chunk: same site table, same entry layout).  Lanes past
 // n take site n - 1 again, so that every entry of the area holds a pattern of
 // a site of the chunk (phase 2 reads one group past the chunk's end ahead).
+template <int M>
 __device__ __forceinline__ void pattern_chunk(const TileCtx& c, const PlaneSite* __restrict__ sites,
                                               uint32_t cm0, uint32_t n, uint32_t lane,
                                               char* planes) {
@@ -721,15 +730,16 @@ __device__ __forceinline__ void pattern_chunk(const TileCtx& c, const PlaneSite*
       xa[k] = k == 0 ? v.x ^ o.x : rotr32(v.x ^ o.x, 32u - (uint32_t)k);
       xb[k] = k == 0 ? v.y ^ o.y : rotr32(v.y ^ o.y, 32u - (uint32_t)k);
     }
+    constexpr int B = pattern_shift<M>();
     uint4 q[4];
-    q[0] = make_uint4(pattern_word<0>(xa), pattern_word<1>(xa), pattern_word<2>(xa),
-                      pattern_word<3>(xa));
-    q[1] = make_uint4(pattern_word<4>(xa), pattern_word<5>(xa), pattern_word<6>(xa),
-                      pattern_word<7>(xa));
-    q[2] = make_uint4(pattern_word<0>(xb), pattern_word<1>(xb), pattern_word<2>(xb),
-                      pattern_word<3>(xb));
-    q[3] = make_uint4(pattern_word<4>(xb), pattern_word<5>(xb), pattern_word<6>(xb),
-                      pattern_word<7>(xb));
+    q[0] = make_uint4(pattern_word<0, B>(xa), pattern_word<1, B>(xa), pattern_word<2, B>(xa),
+                      pattern_word<3, B>(xa));
+    q[1] = make_uint4(pattern_word<4, B>(xa), pattern_word<5, B>(xa), pattern_word<6, B>(xa),
+                      pattern_word<7, B>(xa));
+    q[2] = make_uint4(pattern_word<0, B>(xb), pattern_word<1, B>(xb), pattern_word<2, B>(xb),
+                      pattern_word<3, B>(xb));
+    q[3] = make_uint4(pattern_word<4, B>(xb), pattern_word<5, B>(xb), pattern_word<6, B>(xb),
+                      pattern_word<7, B>(xb));
     char* const entry = planes + 64 * lane;
     const uint32_t rot = plane_rot(lane);
 #pragma unroll
@@ -742,7 +752,7 @@ __device__ __forceinline__ void pattern_chunk(const TileCtx& c, const PlaneSite*
 // offset).
 typedef const __attribute__((address_space(1))) char GlobalChar;
 
-// The threshold of this lane's move at site cm from its byte b = 4 y, in two
+// The threshold of this lane's move at site cm from its byte b = y << B, in two
 // stages so that a group's reads can be issued ahead: pattern_ref reads the
 // site's table entry (real couplings: the threshold; quantised: the LDS byte
 // offset of the dE16 threshold) and pattern_thr finishes it (quantised: the
@@ -759,7 +769,7 @@ struct PatternRef<(int)kModelReal> {
 // Bytes per site of the table pattern_ref reads, and its first row.
 template <int M>
 constexpr uint32_t pattern_row_bytes() {
-  return M == (int)kModelReal ? kRealPatterns * 8 : kRealPatterns * 4;
+  return M == (int)kModelReal ? kRealPatterns * 8 : kRealPatterns * 2;
 }
 template <int M>
 __device__ __forceinline__ GlobalChar* pattern_table(const TileCtx& c) {
@@ -778,7 +788,7 @@ __device__ __forceinline__ typename PatternRef<M>::type pattern_ref(GlobalChar* 
   if constexpr (M == (int)kModelReal)
     return *(const __attribute__((address_space(1))) unsigned long long*)(row + 2u * b);
   else
-    return *(const __attribute__((address_space(1))) uint32_t*)(row + b);
+    return *(const __attribute__((address_space(1))) uint16_t*)(row + b);
 }
 
 template <int M, uint32_t GT>
@@ -804,8 +814,8 @@ __device__ __forceinline__ typename AccOf<M>::type pattern_he(const TileCtx& c, 
     return *(const __attribute__((address_space(1))) long long*)(row + 2u * b);
   } else {
     GlobalChar* row = (GlobalChar*)(c.gaddr + (size_t)cm * kRealPatterns);
-    const int32_t a = *(const __attribute__((address_space(1))) int32_t*)(row + b);
-    const int32_t an = *(const __attribute__((address_space(1))) int32_t*)(row + (b ^ 252u));
+    const int32_t a = *(const __attribute__((address_space(1))) uint16_t*)(row + b);
+    const int32_t an = *(const __attribute__((address_space(1))) uint16_t*)(row + (b ^ 126u));
     return (uint32_t)((a - an) >> 4);
   }
 }
@@ -903,7 +913,7 @@ __device__ typename AccOf<M>::type sweep_colour_patterns(const TileCtx& c,
   for (uint32_t s0 = first; s0 < last; s0 += 64) {
     const uint32_t n = __builtin_amdgcn_readfirstlane(min(64u, last - s0));
     const uint32_t cm0 = __builtin_amdgcn_readfirstlane(own0 + s0);
-    pattern_chunk(c, sites, cm0, n, lane, planes);
+    pattern_chunk<M>(c, sites, cm0, n, lane, planes);
     __builtin_amdgcn_wave_barrier();
     const char* ownb = own_h + whole_s(8 * cm0);
     GlobalChar* const rows = pattern_table<M>(c) + (size_t)cm0 * pattern_row_bytes<M>();
