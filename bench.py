@@ -117,6 +117,11 @@ def parse():
                     help="resident-request limit of the serving run (default 256)")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="request rate of the serving run (default 4 per second)")
+    ap.add_argument("--serve-load-seconds", type=float, default=15.0,
+                    help="arrival window of a second serving run at --serve-load-rate, which "
+                         "keeps several requests resident at once (0 skips it)")
+    ap.add_argument("--serve-load-rate", type=float, default=24.0,
+                    help="request rate of that run")
     ap.add_argument("--serve-lockstep", action="store_true",
                     help="step every resident request on every tick (no work-fair selection)")
     ap.add_argument("--workload", default="c3")
@@ -954,6 +959,14 @@ def main():
         print(f"# serving: Poisson arrivals for {args.serve_seconds:.0f} s", file=sys.stderr,
               flush=True)
         line["serving"] = serving_bench(args.serve_seconds, args.serve_max_active or None)
+    if args.serve_load_seconds > 0 and args.serve_seconds > 0:
+        # the same request mix at a rate where requests overlap (the configured
+        # rate keeps about one resident at a time on this device)
+        print(f"# serving under load: {args.serve_load_rate:g} requests/s for "
+              f"{args.serve_load_seconds:.0f} s", file=sys.stderr, flush=True)
+        line["serving_load"] = serving_bench(args.serve_load_seconds,
+                                             args.serve_max_active or None,
+                                             rate=args.serve_load_rate)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)
