@@ -341,13 +341,15 @@ inline uint32_t blocks_slots(uint32_t capacity) { return capacity / kBlockCounts
 // blocks find no replicas and leave).
 inline uint32_t blocks_sweep(uint32_t capacity) { return (capacity / 64 + 7) / 8 * 8; }
 // Waves per tile of a sweep launch over `tiles` tiles of linear size L, from
-// timings on MI355X: eight waves pay off on large lattices and on launches too
-// small to fill the chip with four; L = 4 has only four row blocks per colour.
+// timings on MI355X (both layouts, beta = 1, 10 sweeps; the same two-phase
+// colour pass for every coupling model): eight waves from L = 10 up, and on
+// smaller lattices while the launch is too small to fill the chip with four
+// (fewer than 256 (L - 2) tiles: 512 at L = 4, 1024 at L = 6, 1536 at L = 8);
+// four otherwise, where more resident tiles per CU pay (L = 4, 4096 tiles:
+// 0.13 against 0.19 ms).
 inline uint32_t sweep_split_default(uint32_t model, uint32_t L, uint64_t tiles) {
-  // +-J (bit-sliced colour pass): eight waves from L = 10 up (at L = 10 they
-  // take three blocks per plane group against two with four waves)
-  const uint32_t big = model == kModelPm ? 10u : 14u;
-  return (L >= big || (L >= 6 && tiles < 2048)) ? 8u : 4u;
+  (void)model;
+  return (L >= 10 || tiles < 256ull * (L - 2)) ? 8u : 4u;
 }
 // The split a launch uses: the autotuner's choice for (model, layout, L, size
 // class of `tiles`) when one was measured in this process, else the default (pa_tune.cpp).

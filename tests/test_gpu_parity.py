@@ -84,9 +84,10 @@ def test_sweep_parity(pam, layout, beta):
 @pytest.mark.parametrize("layout", ["int8", "bitpack64"])
 @pytest.mark.parametrize("L,R", [(4, 140000), (6, 140000), (4, 131071), (6, 5000)])
 def test_sweep_forms_parity(pam, layout, L, R):
-    """Both sweep forms: one tile per wave (populations of 2048 tiles and more)
-    and the shared-tile form (fewer tiles), each bit-exact against the oracle,
-    through two resampling steps (gather fused into the sweep) at beta 0.4, 0.8."""
+    """Both sweep forms under the built-in rule: four waves per tile (the large
+    launches at L = 4 and 6) and eight (the small one), each bit-exact against
+    the oracle, through two resampling steps (gather fused into the sweep) at
+    beta 0.4, 0.8."""
     say("sweep forms", layout, L, R)
     J, g, o = pair(pam, L, R, 4321 + R, layout, 9 + L)
     for b in (0.4, 0.8):
