@@ -70,8 +70,10 @@ OPS_PER_ATTEMPT = 10 + 2 + 102 / 64
 # = 132, i.e. 132/64 per attempt.  Per replica, quantised couplings (k = 16 J):
 # the byte is the offset of the site's table entry, whose value is the LDS
 # address of the dE16 threshold, then 1 compare (64-bit) and 1 select of the
-# flip mask's half = 2; real couplings: 1 shift (the 8-byte threshold of the
-# (site, pattern) table at 8 y), 1 compare (64-bit), 1 select = 3.  Each site
+# flip mask's half = 2; real couplings: the byte is the offset of the site's
+# 4-byte entry min(thr, 2^32 - 1), then 1 compare (32-bit), 1 select, and 1 for
+# the search of the draw 2^32 - 1 among each lane's four draws (3 max + 1
+# compare per four), where the exact 8-byte threshold decides = 3.  Each site
 # and wave also reads one table row through the caches (a 64-lane gather).
 OPS_PER_ATTEMPT_GAUSS = 10 + 2 + 132 / 64
 OPS_PER_ATTEMPT_REAL = 10 + 3 + 132 / 64

@@ -127,6 +127,7 @@ bool make_layout(const pa_params* p, Layout* out) {
   const size_t rows = (size_t)l.N + pa::kPatternPadRows;
   l.off_rhe = take(real ? rows * pa::kRealPatterns * 8 : 0);
   l.off_rthr = take(real ? rows * pa::kRealPatterns * 8 : 0);
+  l.off_rthr32 = take(real ? rows * pa::kRealPatterns * 4 : 0);
   // (one per slot block for the copy counts, three per reduction workgroup
   // for the bisection's evaluations)
   const size_t n_part = std::max<size_t>(l.n_blocks, 3 * (size_t)pa::kRealSumBlocks);
@@ -1069,6 +1070,7 @@ int init_instance(const pa_params* p, const int8_t* J_host, const std::vector<lo
   P.gaddr = gaddr.empty() ? nullptr : reinterpret_cast<const uint16_t*>(w + l.off_gaddr);
   P.rhe = real ? reinterpret_cast<const long long*>(w + l.off_rhe) : nullptr;
   P.rthr = real ? reinterpret_cast<unsigned long long*>(w + l.off_rthr) : nullptr;
+  P.rthr32 = real ? reinterpret_cast<uint32_t*>(w + l.off_rthr32) : nullptr;
   P.rs = reinterpret_cast<pa::RealScalars*>(w + l.off_rs);
   P.rpart = real ? reinterpret_cast<pa::RealPartial*>(w + l.off_rpart) : nullptr;
   in->d_pops = reinterpret_cast<DevPop*>(w + l.off_pops);

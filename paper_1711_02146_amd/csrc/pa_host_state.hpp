@@ -36,7 +36,7 @@ struct Layout {
   size_t hist_bytes;  // the histogram's share of its block (n_levels words, 64-byte multiple)
   size_t off_spins[2], off_U[2], off_fam[2], off_counts, off_offsets, off_src, off_bsum, off_boff,
       off_bcull, off_hist, off_table, off_sites, off_psites, off_cm, off_rowj, off_rowk, off_gthr, off_ovl,
-      off_lovl, off_lpart, off_sc, off_rs, off_pops, off_meta, off_rhe, off_rthr, off_rpart, off_gaddr;
+      off_lovl, off_lpart, off_sc, off_rs, off_pops, off_meta, off_rhe, off_rthr, off_rthr32, off_rpart, off_gaddr;
   size_t total;
 };
 

@@ -196,6 +196,8 @@ struct DevPop {
   const long long* rhe;            // kModelReal: he[cm][y], N x 64 (see kModelReal)
   unsigned long long* rthr;        // kModelReal: Metropolis threshold of (cm, y) for the
                                    // coming sweep, N x 64
+  uint32_t* rthr32;                // kModelReal: min(thr, 2^32 - 1) of the same (cm, y): the
+                                   // sweep's table (see pattern_thr)
   RealScalars* rs;                 // kModelReal: scalars of the weight reductions
   RealPartial* rpart;              // kModelReal: one per workgroup of kBlockCounts slots
 };

@@ -259,6 +259,7 @@ struct TileCtx {
   const uint16_t* gaddr;               // 16 max(he16, 0) of (site, pattern), see DevPop
   // kModelReal
   const unsigned long long* rthr;      // thresholds of (site, pattern) for this sweep
+  const uint32_t* rthr32;              // the same, min(thr, 2^32 - 1)
   const long long* rhe;                // half energy changes he of (site, pattern)
 };
 
@@ -673,8 +674,9 @@ __device__ uint32_t sweep_colour_planes(const TileCtx& c, const PlaneSite* __res
 // +z,-z).  Phase 1 (lane = site) forms the six words x_k = neighbour ^ own of
 // 32 replicas each and spreads them into one byte per replica holding y << B;
 // phase 2 (lane = replica) reads its byte and looks up the site's threshold
-// for it: for real couplings thr[cm][y] of the sweep's beta (8 bytes, byte
-// offset 8 y, B = 2), for quantised ones the entry a[cm][y] = 16 max(he16, 0)
+// for it: for real couplings min(thr[cm][y], 2^32 - 1) of the sweep's beta (4
+// bytes, byte offset 4 y, B = 2; see pattern_groups for the draw 2^32 - 1),
+// for quantised ones the entry a[cm][y] = 16 max(he16, 0)
 // of a fixed table (2 bytes, byte offset 2 y, B = 1), the byte address of the
 // dE16 = 2 he16 threshold in the workgroup's LDS copy of the dE16 table.  The draws,
 // the thresholds and the test are those of the one-site-at-a-time form.
@@ -686,7 +688,7 @@ __device__ __forceinline__ constexpr uint32_t rotl_c(uint32_t m, int k) {
 
 // The pattern byte of a replica holds y << B: the byte offset of its entry
 // in the site's table row (quantised couplings: 2-byte entries, B = 1; real
-// couplings: 8-byte thresholds at twice the byte, B = 2).
+// couplings: 4-byte thresholds, B = 2).
 template <int M>
 constexpr int pattern_shift() {
   return M == (int)kModelReal ? 2 : 1;
@@ -754,27 +756,23 @@ typedef const __attribute__((address_space(1))) char GlobalChar;
 
 // The threshold of this lane's move at site cm from its byte b = y << B, in two
 // stages so that a group's reads can be issued ahead: pattern_ref reads the
-// site's table entry (real couplings: the threshold; quantised: the LDS byte
-// offset of the dE16 threshold) and pattern_thr finishes it (quantised: the
-// read of the LDS dE16 table, at byte address GT).
+// site's table entry (real couplings: min(thr, 2^32 - 1); quantised: the LDS
+// byte offset of the dE16 threshold) and pattern_thr finishes it (quantised:
+// the read of the LDS dE16 table, at byte address GT).
 template <int M>
 struct PatternRef {
   using type = uint32_t;
-};
-template <>
-struct PatternRef<(int)kModelReal> {
-  using type = unsigned long long;
 };
 
 // Bytes per site of the table pattern_ref reads, and its first row.
 template <int M>
 constexpr uint32_t pattern_row_bytes() {
-  return M == (int)kModelReal ? kRealPatterns * 8 : kRealPatterns * 2;
+  return M == (int)kModelReal ? kRealPatterns * 4 : kRealPatterns * 2;
 }
 template <int M>
 __device__ __forceinline__ GlobalChar* pattern_table(const TileCtx& c) {
   if constexpr (M == (int)kModelReal)
-    return (GlobalChar*)c.rthr;
+    return (GlobalChar*)c.rthr32;
   else
     return (GlobalChar*)c.gaddr;
 }
@@ -786,7 +784,7 @@ __device__ __forceinline__ typename PatternRef<M>::type pattern_ref(GlobalChar* 
   // again and forms a 64-bit address per lane)
   asm("" : "+v"(b));
   if constexpr (M == (int)kModelReal)
-    return *(const __attribute__((address_space(1))) unsigned long long*)(row + 2u * b);
+    return *(const __attribute__((address_space(1))) uint32_t*)(row + b);
   else
     return *(const __attribute__((address_space(1))) uint16_t*)(row + b);
 }
@@ -820,17 +818,18 @@ __device__ __forceinline__ typename AccOf<M>::type pattern_he(const TileCtx& c, 
   }
 }
 
-// The Metropolis test of this lane's replica at site E of a chunk, and the flip.
+// The flips of site E of a chunk (taken: the wave's mask of accepted moves),
+// and with ACCUM this lane's share of the energy.
 template <int M, int E, bool ACCUM>
 __device__ __forceinline__ void pattern_site(const TileCtx& c, const char* ownb, uint32_t cm0,
-                                             uint32_t b, uint32_t draw, unsigned long long thr,
+                                             uint32_t b, unsigned long long taken,
                                              typename AccOf<M>::type& esum) {
-  const bool acc = (unsigned long long)draw < thr;
   if (ACCUM) {
+    const bool acc = ((taken >> lane_id()) & 1ull) != 0ull;
     const typename AccOf<M>::type he = pattern_he<M>(c, cm0 + E, b);
     esum += acc ? he : -he;
   }
-  const uint32_t fh = (uint32_t)(__ballot(acc) >> c.hshift);
+  const uint32_t fh = (uint32_t)(taken >> c.hshift);
   lds_xor_two_lanes<8 * E>(ownb, fh, c.writers);
 }
 
@@ -888,10 +887,36 @@ __device__ __forceinline__ void pattern_groups(const TileCtx& c, const char* own
     for (int i = 0; i < 4; ++i) rn[i] = pattern_ref<M>(rg + i * RB, bn[i]);
   }
   const Words4 d = c.ph.draw(c.t, (cm0 >> 2) + (uint32_t)G);
-  pattern_site<M, 4 * G, ACCUM>(c, ownb, cm0, b[0], d.w[0], thr[0], esum);
-  pattern_site<M, 4 * G + 1, ACCUM>(c, ownb, cm0, b[1], d.w[1], thr[1], esum);
-  pattern_site<M, 4 * G + 2, ACCUM>(c, ownb, cm0, b[2], d.w[2], thr[2], esum);
-  pattern_site<M, 4 * G + 3, ACCUM>(c, ownb, cm0, b[3], d.w[3], thr[3], esum);
+  // the wave's masks of accepted moves at the group's four sites
+  unsigned long long taken[4];
+  if constexpr (M == (int)kModelReal) {
+    // The 32-bit entry min(thr, 2^32 - 1) decides every draw as thr does but
+    // one: for the draw 2^32 - 1 the thresholds 2^32 (taken) and 2^32 - 1 (not
+    // taken) share the entry.  Lanes with that draw (a group of a wave has one
+    // in about 2^24) read the site's exact threshold.
+#pragma unroll
+    for (int i = 0; i < 4; ++i) taken[i] = __ballot(d.w[i] < r[i]);
+    const uint32_t mx = max(max(d.w[0], d.w[1]), max(d.w[2], d.w[3]));
+    if (__builtin_expect(__ballot(mx == 0xFFFFFFFFu) != 0ull, 0)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool top = d.w[i] == 0xFFFFFFFFu;
+        bool exact = false;
+        if (top)
+          exact = *(const __attribute__((address_space(1))) unsigned long long*)(
+                      (GlobalChar*)(c.rthr + (size_t)(cm0 + 4 * G + i) * kRealPatterns) +
+                      2u * b[i]) > 0xFFFFFFFFull;
+        taken[i] = (taken[i] & ~__ballot(top)) | __ballot(exact);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) taken[i] = __ballot((unsigned long long)d.w[i] < thr[i]);
+  }
+  pattern_site<M, 4 * G, ACCUM>(c, ownb, cm0, b[0], taken[0], esum);
+  pattern_site<M, 4 * G + 1, ACCUM>(c, ownb, cm0, b[1], taken[1], esum);
+  pattern_site<M, 4 * G + 2, ACCUM>(c, ownb, cm0, b[2], taken[2], esum);
+  pattern_site<M, 4 * G + 3, ACCUM>(c, ownb, cm0, b[3], taken[3], esum);
   if constexpr (G + 1 < 16)
     pattern_groups<M, GT, G + 1, ACCUM>(c, ownb, pr, rows, cm0, n, bn, rn, esum);
 }
@@ -1658,6 +1683,7 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves_per_eu<L, M>()))) void k_swee
   c.rowk_stride = P.rowk_stride;
   c.gaddr = P.gaddr;
   c.rthr = P.rthr;
+  c.rthr32 = P.rthr32;
   c.rhe = P.rhe;
   const unsigned long long* rowj = P.rowj;
   typename AccOf<M>::type U;

@@ -266,3 +266,21 @@ def test_capacity_overflow_at_the_same_step(pam):
         same_state(g, o, f"step {k}")
     assert failed
     g.close()
+
+
+def test_draw_of_all_ones_takes_the_exact_threshold(pam):
+    """The sweep decides with min(thr, 2^32 - 1) and reads the exact threshold
+    only for the draw 2^32 - 1, where 2^32 (taken) and 2^32 - 1 (not taken)
+    part.  At beta = 0 every threshold is 2^32, so the draw 2^32 - 1 that
+    replica 58 gets at site 0 in the first sweep under this seed (pinned
+    against rocRAND's Philox in test_philox_layout_pins.py) is taken like
+    every other move: one sweep flips every spin, as in the oracle."""
+    L, R, seed = 4, 64, 0x5EED0000000C56F4
+    say("top draw", L, R, hex(seed))
+    J, g, o = pair(pam, L, R, 0xC0DE0777, seed)
+    start = o.spins.copy()
+    g.sweep(0.0, 1)
+    o.sweep(0.0, 1)
+    same_state(g, o, "one sweep at beta = 0")
+    np.testing.assert_array_equal(o.spins, -start)
+    g.close()

@@ -58,6 +58,17 @@ def rocrand(tmp_path_factory, oracle_lib):
     return run
 
 
+# A population seed whose Metropolis stream holds the draw 2^32 - 1 in its
+# first sweep: replica 58, site group 0, word 0 (the site at colour-major
+# index 0).  The real-coupling GPU test of that draw relies on it.
+SEED_TOP_DRAW = 0x5EED0000000C56F4
+
+
+def test_top_draw_seed(rocrand):
+    w = rocrand([(58, 0, 0, TAG_MET)], SEED_TOP_DRAW)
+    assert int(w[0][0]) == 0xFFFFFFFF
+
+
 @pytest.mark.parametrize("L,seed", [(3, 1), (4, 0xC0DE0000), (10, 2 ** 63 + 5)])
 def test_couplings_counter_layout(rocrand, L, seed):
     nb = 3 * L ** 3
