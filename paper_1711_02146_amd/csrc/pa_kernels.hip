@@ -1121,23 +1121,43 @@ __global__ __launch_bounds__(256) void k_zero_acc(BatchDev B, Group G) {
   }
 }
 
+// The words of this thread's slots among a workgroup's kHistSlots (slot
+// i0 + threadIdx.x + 256 k for a 256-thread workgroup), loaded together: one
+// memory round trip rather than one per word.  Slots at or past i1 are not
+// read; their entries are left undefined and the caller skips them.
+constexpr uint32_t kHistPer = kHistSlots / 256;
+__device__ __forceinline__ void slot_words(const uint32_t* U, uint32_t i0, uint32_t i1,
+                                           uint32_t u[kHistPer]) {
+  const __attribute__((address_space(1))) uint32_t* const Ug =
+      (const __attribute__((address_space(1))) uint32_t*)U;
+#pragma unroll
+  for (uint32_t k = 0; k < kHistPer; ++k) {
+    const uint32_t i = i0 + threadIdx.x + 256u * k;
+    u[k] = i < i1 ? Ug[i] : 0u;
+  }
+}
+
 // Energy histogram h_j = #{i < R~ : U_i = j} (the sum of Eq. 2 regrouped by
 // integer level), privatised in LDS; each workgroup takes kHistSlots slots.
 __global__ __launch_bounds__(256) void k_hist(BatchDev B, Group G, uint32_t post) {
   extern __shared__ uint32_t h[];
   const Member m = member_of(G);
   const DevPop P = B.pops[m.pop];
-  if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
   const uint32_t* U = pick(P.U, post ? sp.cur ^ 1u : sp.cur);
+  // the population's flag and size and the thread's slot words read together
+  // (every slot below the capacity is allocated), then the flag checked
+  const uint32_t dead = P.sc->dead, R = P.sc->R_tilde;
+  const uint32_t i0 = m.lb * kHistSlots, i1 = min(R, i0 + kHistSlots);
+  uint32_t u[kHistPer];
+  slot_words(U, i0, min(P.capacity, i0 + kHistSlots), u);
+  asm volatile("" ::"v"(R));
+  if (dead) return;
   for (uint32_t i = threadIdx.x; i < P.n_levels; i += blockDim.x) h[i] = 0;
   __syncthreads();
-  const uint32_t R = P.sc->R_tilde;
-  const uint32_t i0 = m.lb * kHistSlots, i1 = min(R, i0 + kHistSlots);
-  for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const uint32_t u = U[i];
-    if (u < P.n_levels) atomicAdd(&h[u], 1u);
-  }
+#pragma unroll
+  for (uint32_t k = 0; k < kHistPer; ++k)
+    if (i0 + threadIdx.x + 256u * k < i1 && u[k] < P.n_levels) atomicAdd(&h[u[k]], 1u);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < P.n_levels; i += blockDim.x)
     if (h[i]) atomicAdd(&P.hist[i], h[i]);
@@ -1179,11 +1199,14 @@ __global__ __launch_bounds__(256) void k_minmax(BatchDev B, Group G, uint32_t po
   const uint32_t i0 = m.lb * kHistSlots, i1 = min(R, i0 + kHistSlots);
   if (i0 >= R) return;
   int32_t lo = 0x7FFFFFFF, hi = (int32_t)0x80000000;
-  for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const int32_t e = (int32_t)U[i];
-    lo = min(lo, e);
-    hi = max(hi, e);
-  }
+  uint32_t u[kHistPer];
+  slot_words(U, i0, i1, u);
+#pragma unroll
+  for (uint32_t k = 0; k < kHistPer; ++k)
+    if (i0 + threadIdx.x + 256u * k < i1) {
+      lo = min(lo, (int32_t)u[k]);
+      hi = max(hi, (int32_t)u[k]);
+    }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     lo = min(lo, __shfl_xor(lo, off, kWave));
@@ -1224,10 +1247,14 @@ __global__ __launch_bounds__(256) void k_hist_window(BatchDev B, Group G, uint32
   if (i0 >= R) return;
   if (use_lds) {
     for (uint32_t b = threadIdx.x; b < n_win; b += blockDim.x) hl[b] = 0;
+    uint32_t u[kHistPer];
+    slot_words(U, i0, i1, u);
     __syncthreads();
-    for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-      const int32_t lev = (int32_t)U[i] - lo;
-      if (lev >= 0 && (uint32_t)lev < n_win) atomicAdd(&hl[lev], 1u);
+#pragma unroll
+    for (uint32_t k = 0; k < kHistPer; ++k) {
+      const int32_t lev = (int32_t)u[k] - lo;
+      if (i0 + threadIdx.x + 256u * k < i1 && lev >= 0 && (uint32_t)lev < n_win)
+        atomicAdd(&hl[lev], 1u);
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < n_win; b += blockDim.x)
@@ -1406,15 +1433,20 @@ __device__ __forceinline__ void counts_body(BatchDev B, Group G, const InlineTab
   __shared__ uint32_t scratch[kBlockCounts / kWave];
   const Member m = member_of(G);
   const DevPop P = B.pops[m.pop];
-  if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
   const uint32_t* U = pick(P.U, sp.cur);
-  const uint32_t R = P.sc->R_tilde;
   const uint32_t i = m.lb * kBlockCounts + threadIdx.x;
+  // the population's flag and size and this slot's word read together (every
+  // slot below the capacity is allocated), then the flag checked; the asm
+  // keeps the compiler from moving the loads below the check
+  const uint32_t dead = P.sc->dead, R = P.sc->R_tilde, E_lo = (uint32_t)P.sc->E_lo;
+  const uint32_t word = i < P.capacity ? U[i] : 0u;
+  asm volatile("" ::"v"(R), "v"(E_lo), "v"(word));
+  if (dead) return;
   uint32_t n = 0, culled = 0;
   if (i < R) {
     // energy level of the replica: U (kModelPm) or E16 - E_lo (kModelGauss16)
-    const uint32_t lev = P.model == kModelGauss16 ? U[i] - (uint32_t)P.sc->E_lo : U[i];
+    const uint32_t lev = P.model == kModelGauss16 ? word - E_lo : word;
     const Words4 w = philox10(i, sp.step, 0u, kTagRes, (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
     const unsigned long long u53 = ((unsigned long long)w.w[0] << 21) | (w.w[1] >> 11);
     const TableEntry te = table_entry<INLINE>(P, t, lev);
@@ -1530,13 +1562,22 @@ __global__ __launch_bounds__(kBlockCounts) void k_scan_scatter(BatchDev B, Group
   __shared__ uint32_t s_base;
   const Member m = member_of(G);
   const DevPop P = B.pops[m.pop];
-  if (P.sc->dead) return;
   const PopStep sp = step_of(B, m.pop);
+  // the population's flag and size and this slot's count read together
+  // (every slot below the capacity is allocated), then the flag checked
+  const uint32_t i = m.lb * kBlockCounts + threadIdx.x;
+  const uint32_t dead = P.sc->dead, R = P.sc->R_tilde;
+  const uint32_t cnt = i < P.capacity ? P.counts[i] : 0u;
+  asm volatile("" ::"v"(R), "v"(cnt));
+  if (dead) return;
+  const uint32_t n = i < R ? cnt : 0u;
   // the block sums before this workgroup, four per 16-byte load (the array
-  // starts 256-byte aligned), the last lb mod 4 one by one
+  // starts 256-byte aligned), the last lb mod 4 one by one; the unrolled
+  // loop keeps several loads of a thread in flight
   uint32_t before = 0;
   const uint32_t q = m.lb / 4;
   const uint4* bs4 = reinterpret_cast<const uint4*>(P.block_sums);
+#pragma unroll 4
   for (uint32_t b = threadIdx.x; b < q; b += kBlockCounts) {
     const uint4 v = bs4[b];
     before += v.x + v.y + v.z + v.w;
@@ -1546,9 +1587,6 @@ __global__ __launch_bounds__(kBlockCounts) void k_scan_scatter(BatchDev B, Group
   if (threadIdx.x == 0) s_base = before;
   __syncthreads();
   const uint32_t base = s_base;
-  const uint32_t R = P.sc->R_tilde;
-  const uint32_t i = m.lb * kBlockCounts + threadIdx.x;
-  const uint32_t n = i < R ? P.counts[i] : 0u;
   uint32_t total;
   const uint32_t excl = block_exclusive_scan<kBlockCounts>(n, &total, scratch);
   const bool fits = (unsigned long long)base + total <= P.cap_limit;
@@ -1570,6 +1608,7 @@ __global__ __launch_bounds__(kBlockCounts) void k_scan_scatter(BatchDev B, Group
   }
   if (m.lb + 1 != m.nb) return;
   uint32_t cull = 0;
+#pragma unroll 8
   for (uint32_t b = threadIdx.x; b < m.nb; b += kBlockCounts) cull += P.block_culled[b];
   cull = block_sum<kBlockCounts, uint32_t>(cull, scratch);
   if (sp.flags & kStepHist) {
