@@ -18,9 +18,14 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <atomic>
+#include <condition_variable>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
+
+#include <unistd.h>
 
 #include "../../include/pa.h"
 #include "pa_host_state.hpp"
@@ -523,6 +528,113 @@ void philox_host(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0
   out[3] = c3;
 }
 
+// The culling fraction of Sec. III.C at a candidate step dbeta over the
+// occupied levels (exp argument, count) in level order: w_j, S and tau_j
+// formed exactly as resample_table() does, eps R = the sum over levels with
+// tau_j < 1 of h_j (1 - tau_j).  w is the caller's buffer of n entries.
+struct EpsLevels {
+  const double* arg;
+  const double* cnt;
+  size_t n;
+  uint32_t R;
+};
+
+double culled_fraction(const EpsLevels& lv, double dbeta, double* w) {
+  if (lv.n == 0) return 0.0;
+  double S = 0.0;
+  for (size_t i = 0; i < lv.n; ++i) {
+    w[i] = std::exp(-dbeta * lv.arg[i]);
+    S = S + lv.cnt[i] * w[i];
+  }
+  double acc = 0.0;
+  for (size_t i = 0; i < lv.n; ++i) {
+    const double tau = ((double)lv.R * w[i]) / S;
+    if (tau < 1.0) acc = acc + lv.cnt[i] * (1.0 - tau);
+  }
+  return acc / (double)lv.R;
+}
+
+// Host threads that evaluate culling fractions beside the calling thread, for
+// the speculative bisection below: kEvalHelpers workers (a round evaluates
+// the candidates of kEvalDepth halvings), started on first use
+// and kept for the life of the process (never destroyed, so that process exit
+// does not wait on them).  A round hands out one candidate per worker, the
+// caller evaluates its own, and waits until every worker has finished.
+// Workers spin for a short while after a round (the rounds of one search come
+// microseconds apart), then sleep until the next.  One search uses the pool
+// at a time; a search that finds it busy, or runs in a process forked after
+// the workers started, evaluates its candidates itself.
+constexpr int kEvalDepth = 3;                      // halvings per round
+constexpr int kEvalLanes = (1 << kEvalDepth) - 1;  // candidates per round
+constexpr int kEvalHelpers = kEvalLanes - 1;
+constexpr long kEvalSpin = 1l << 13;  // pause loops before a worker sleeps (tens of microseconds)
+
+class EvalPool {
+ public:
+  static EvalPool* get() {
+    static EvalPool* pool = new EvalPool();
+    return pool->pid_ == getpid() ? pool : nullptr;
+  }
+  std::mutex& busy() { return busy_; }
+  // out[k] = culled_fraction(lv, x[k]) for k < n (n <= kEvalLanes); the
+  // caller takes x[0] itself.  Call with busy() held.
+  void run(const EpsLevels& lv, const double* x, double* out, int n) {
+    lv_ = &lv;
+    x_ = x;
+    out_ = out;
+    n_ = n;
+    done_.store(0, std::memory_order_relaxed);
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      gen_.fetch_add(1, std::memory_order_release);
+    }
+    cv_.notify_all();
+    own_.resize(lv.n);
+    out[0] = culled_fraction(lv, x[0], own_.data());
+    while (done_.load(std::memory_order_acquire) != kEvalHelpers) __builtin_ia32_pause();
+  }
+
+ private:
+  EvalPool() : pid_(getpid()) {
+    for (int k = 0; k < kEvalHelpers; ++k) std::thread([this, k] { work(k + 1); }).detach();
+  }
+  void work(int lane) {
+    std::vector<double> w;
+    uint64_t seen = 0;
+    for (;;) {
+      uint64_t g = gen_.load(std::memory_order_acquire);
+      for (long spin = 0; g == seen; g = gen_.load(std::memory_order_acquire)) {
+        __builtin_ia32_pause();
+        if (++spin > kEvalSpin) {
+          std::unique_lock<std::mutex> lk(m_);
+          cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != seen; });
+          spin = 0;
+        }
+      }
+      seen = g;
+      if (lane < n_) {
+        w.resize(lv_->n);
+        out_[lane] = culled_fraction(*lv_, x_[lane], w.data());
+      }
+      done_.fetch_add(1, std::memory_order_acq_rel);
+    }
+  }
+  const pid_t pid_;
+  std::mutex busy_, m_;
+  std::condition_variable cv_;
+  std::atomic<uint64_t> gen_{0};
+  std::atomic<int> done_{0};
+  const EpsLevels* lv_ = nullptr;
+  const double* x_ = nullptr;
+  double* out_ = nullptr;
+  int n_ = 0;
+  std::vector<double> own_;
+};
+
+// Occupied levels from which the search uses the worker threads; below it
+// one evaluation costs less than handing it out.
+constexpr size_t kEvalPoolLevels = 512;
+
 // The constant-culling step of Sec. III.C on the histogram in in->h_hist:
 // the beta_next in (beta, beta_max] whose culling fraction is eps_target, by
 // 64 bisection halvings keeping the lower end (pa_choose_beta).
@@ -566,35 +678,71 @@ int choose_from_hist(pa_instance* in, double eps_target, double beta_max, double
     arg.push_back(lv.unit * (double)((int)j - jmin));
     cnt.push_back((double)h[j]);
   }
-  const size_t n_occ = arg.size();
-  auto eps_of = [&](double dbeta) {
-    if (n_occ == 0) return 0.0;
-    static thread_local std::vector<double> w;
-    w.resize(n_occ);
-    double S = 0.0;
-    for (size_t i = 0; i < n_occ; ++i) {
-      w[i] = std::exp(-dbeta * arg[i]);
-      S = S + cnt[i] * w[i];
-    }
-    double acc = 0.0;
-    for (size_t i = 0; i < n_occ; ++i) {
-      const double tau = ((double)R * w[i]) / S;
-      if (tau < 1.0) acc = acc + cnt[i] * (1.0 - tau);
-    }
-    return acc / (double)R;
-  };
-  if (eps_of(0.0) > eps_target) return PA_ESCHEDULE;
+  const EpsLevels lvs{arg.data(), cnt.data(), arg.size(), R};
+  static thread_local std::vector<double> w;
+  w.resize(lvs.n);
+  auto eps_of = [&](double dbeta) { return culled_fraction(lvs, dbeta, w.data()); };
   const double rem = beta_max - in->beta;
-  if (eps_of(rem) <= eps_target) {
+  // 64 halvings of [0, rem], keeping the lower end (eps(lo) <= target).
+  // With many occupied levels the worker threads evaluate kEvalDepth
+  // halvings' candidates at once: the candidate (lo + (hi - lo)/2) and those
+  // of the halvings after it on either outcome, each formed from the (lo, hi)
+  // the sequential search would hold there, so that lo takes the same bits.
+  EvalPool* pool = lvs.n >= kEvalPoolLevels ? EvalPool::get() : nullptr;
+  std::unique_lock<std::mutex> held;
+  if (pool) {
+    held = std::unique_lock<std::mutex>(pool->busy(), std::try_to_lock);
+    if (!held.owns_lock()) pool = nullptr;
+  }
+  double e0, erem;
+  if (pool) {
+    const double x[2] = {0.0, rem};
+    double out[2];
+    pool->run(lvs, x, out, 2);
+    e0 = out[0];
+    erem = out[1];
+  } else {
+    e0 = eps_of(0.0);
+    erem = e0 > eps_target ? 0.0 : eps_of(rem);
+  }
+  if (e0 > eps_target) return PA_ESCHEDULE;
+  if (erem <= eps_target) {
     *beta_next = beta_max;
     return PA_OK;
   }
-  // 64 halvings of [0, rem], keeping the lower end (eps(lo) <= target)
   double lo = 0.0, hi = rem;
-  for (int it = 0; it < 64; ++it) {
-    const double mid = lo + 0.5 * (hi - lo);
-    if (eps_of(mid) <= eps_target) lo = mid;
-    else hi = mid;
+  if (!pool) {
+    for (int it = 0; it < 64; ++it) {
+      const double mid = lo + 0.5 * (hi - lo);
+      if (eps_of(mid) <= eps_target) lo = mid;
+      else hi = mid;
+    }
+  } else {
+    // the subtree of (lo, hi): node k has children 2k + 1 (not taken: hi =
+    // its candidate) and 2k + 2 (taken: lo = its candidate)
+    for (int left = 64; left > 0;) {
+      const int depth = left < kEvalDepth ? left : kEvalDepth, n = (1 << depth) - 1;
+      double nlo[kEvalLanes], nhi[kEvalLanes], x[kEvalLanes], e[kEvalLanes];
+      nlo[0] = lo;
+      nhi[0] = hi;
+      for (int k = 0; k < n; ++k) {
+        x[k] = nlo[k] + 0.5 * (nhi[k] - nlo[k]);
+        if (2 * k + 2 < n) {
+          nlo[2 * k + 1] = nlo[k];
+          nhi[2 * k + 1] = x[k];
+          nlo[2 * k + 2] = x[k];
+          nhi[2 * k + 2] = nhi[k];
+        }
+      }
+      pool->run(lvs, x, e, n);
+      for (int d = 0, k = 0; d < depth; ++d) {
+        const bool ok = e[k] <= eps_target;
+        if (ok) lo = x[k];
+        else hi = x[k];
+        k = 2 * k + (ok ? 2 : 1);
+      }
+      left -= depth;
+    }
   }
   *beta_next = in->beta + lo;
   return PA_OK;
