@@ -114,6 +114,30 @@ def test_adaptive_prefix_l10_bitpack(pam):
     g.close()
 
 
+def test_adaptive_steps_many_levels_l8(pam):
+    """Twenty constant-culling steps at L = 8, R = 2e4, where about 1700 levels
+    are occupied at every step: the host's step choice evaluates three
+    halvings' candidates at once on worker threads there, and every chosen
+    beta, every step's observables and the final population must still equal
+    the oracle's sequential search."""
+    L, R = 8, 20000
+    K, g, o = pair(pam, L, R, 0x5EED0031, "bitpack64", 31)
+    for k in range(1, 21):
+        lo, _ = o.window()
+        occupied = int(np.count_nonzero(np.bincount(o.U[: o.R_tilde] - lo)))
+        assert occupied >= 512, (k, occupied)
+        bg = g.choose_beta(0.1, 5.0)
+        bo = o.choose_beta(0.1, 5.0)
+        assert bg == bo, (k, bg, bo)
+        g.resample(bg)
+        o.resample(bo)
+        g.sweep(bg, 10)
+        o.sweep(bo, 10)
+        compare_obs(g.observables(), o.observables(), k)
+    assert_state(g, o, "adaptive steps, many levels")
+    g.close()
+
+
 @pytest.mark.parametrize("L,R", [(4, 140000), (6, 5000)])
 def test_sweep_forms_parity(pam, L, R):
     K, g, o = pair(pam, L, R, 4321 + R, "bitpack64", 9 + L)
