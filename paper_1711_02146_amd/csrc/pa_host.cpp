@@ -644,10 +644,16 @@ int choose_from_hist(pa_instance* in, double eps_target, double beta_max, double
     // evaluations of the culling fraction, each a weight sum and a culled
     // mass, decided and advanced by the last workgroup of each
     const double rem = beta_max - in->beta;
-    const pa::BatchDev B = one_set(in, plain_step(in->cur));
-    const pa::Group g = group_of(in, in->d_meta->rsum, in->meta.rsum[1]);
+    pa::RevalArgs a{};
+    a.E = reinterpret_cast<const long long*>(in->dev.U[in->cur]);
+    a.sc = in->dev.sc;
+    a.rs = in->dev.rs;
+    a.rpart = in->dev.rpart;
+    a.R = in->dev.R;
+    a.capacity = in->dev.capacity;
     PA_HIP(in, pa::launch_real_bisect_init(in->dev, rem, eps_target, in->stream));
-    for (int e = 0; e < 66; ++e) PA_HIP(in, pa::launch_real_bisect_eval(B, g, in->stream));
+    for (int e = 0; e < 66; ++e)
+      PA_HIP(in, pa::launch_real_bisect_eval(a, in->meta.rsum[1], in->stream));
     PA_HIP(in, hipMemcpyAsync(in->h_rs, in->dev.rs, sizeof(pa::RealScalars),
                               hipMemcpyDeviceToHost, in->stream));
     PA_HIP(in, hipStreamSynchronize(in->stream));

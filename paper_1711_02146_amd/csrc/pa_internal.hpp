@@ -325,11 +325,21 @@ hipError_t launch_real_sum(const BatchDev& B, const Group& slots, hipStream_t st
 // the constant-culling bisection (Sec. III.C): set up for the remaining range
 // and target, then one evaluation (culled mass at the current candidate, the
 // weight sums of the two that can follow, the decision) per
-// launch_real_bisect_eval; 66 of them finish it (P.rs->result).  `slots`:
-// at most kRealSumBlocks workgroups (the partials hold three sums each)
+// launch_real_bisect_eval; 66 of them finish it (P.rs->result).  Each
+// evaluation runs on `blocks` workgroups (at most kRealSumBlocks: the
+// partials hold three sums each) over one population, whose buffers it takes
+// as arguments, so that its first loads need no descriptor read before them.
+struct RevalArgs {
+  const long long* E;     // energy words of the population's current buffer
+  const DevScalars* sc;   // R_tilde
+  RealScalars* rs;        // the search state
+  RealPartial* rpart;     // 3 x blocks partials
+  uint32_t R;             // target population size
+  uint32_t capacity;      // slots per buffer (every slot below it is allocated)
+};
 hipError_t launch_real_bisect_init(const DevPop& P, double rem, double target,
                                    hipStream_t stream);
-hipError_t launch_real_bisect_eval(const BatchDev& B, const Group& slots, hipStream_t stream);
+hipError_t launch_real_bisect_eval(const RevalArgs& a, uint32_t blocks, hipStream_t stream);
 // copy counts of the step (after launch_real_sum at its dbeta): counts, block
 // sums and culled counts as k_counts, and the culled fraction into P.rs->eps
 // (`slots`: at most kRealSumBlocks workgroups, each over every nb-th slot block)

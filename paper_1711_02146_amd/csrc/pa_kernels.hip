@@ -2435,9 +2435,9 @@ hipError_t launch_real_bisect_init(const DevPop& P, double rem, double target,
   return hipGetLastError();
 }
 
-hipError_t launch_real_bisect_eval(const BatchDev& B, const Group& g, hipStream_t stream) {
-  if (!g.blocks) return hipSuccess;
-  hipLaunchKernelGGL(k_reval, dim3(g.blocks), dim3(kBlockCounts), 0, stream, B, g);
+hipError_t launch_real_bisect_eval(const RevalArgs& a, uint32_t blocks, hipStream_t stream) {
+  if (!blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_reval, dim3(blocks), dim3(kBlockCounts), 0, stream, a);
   return hipGetLastError();
 }
 
