@@ -89,13 +89,13 @@ BYTES_PER_REPLICA_FIXED = 20
 # lane-instructions per attempt = SQ_INSTS_VALU x 64 / attempts per launch.
 # None: no counters for the current source yet.
 PROFILE = {
-    "kernel_src_sha256": "c576670f8a13b94d8fc5cb5818587f1247e646661281fba463394a986f88c6ac",
+    "kernel_src_sha256": "09a636d0398f288f2ffcc9e73ed17ebb9a9070905e5d048eb50c82aaedef6373",
     # FETCH_SIZE KiB x 2 + WRITE_SIZE KiB x 1, per launch (profiles/*_hbm_counters.md)
-    "bytes_per_launch": (32861.8 * 2 + 64946.1) * 1024,
-    "gauss16_bytes_per_launch": (33333.7 * 2 + 64942.5) * 1024,
-    "real_bytes_per_launch": (35154.0 * 2 + 66898.5) * 1024,
-    "link_overlap_bytes_per_launch": (61563.1 * 2 + 10484.4) * 1024,
-    "int8_C2_bytes_per_launch": (26058.3 * 2 + 50797.2) * 1024,
+    "bytes_per_launch": (32861.6 * 2 + 64946.1) * 1024,
+    "gauss16_bytes_per_launch": (33336.6 * 2 + 64942.5) * 1024,
+    "real_bytes_per_launch": (35163.6 * 2 + 66898.5) * 1024,
+    "link_overlap_bytes_per_launch": (61563.2 * 2 + 10484.4) * 1024,
+    "int8_C2_bytes_per_launch": (26059.5 * 2 + 50797.2) * 1024,
     "int8_overlap_bytes_per_call": (50034.2 * 2 + 342.9) * 1024,
     # SQ_INSTS_VALU 1.0286e9 per launch x 64 lanes / 5.0e9 attempts
     "valu_per_attempt": 1.0286e9 * 64 / 5.0e9,
