@@ -571,9 +571,11 @@ constexpr long kEvalSpin = 1l << 13;  // pause loops before a worker sleeps (ten
 
 class EvalPool {
  public:
+  // nullptr (the caller evaluates by itself) when the workers could not all be
+  // started, or in a process forked after they were
   static EvalPool* get() {
-    static EvalPool* pool = new EvalPool();
-    return pool->pid_ == getpid() ? pool : nullptr;
+    static EvalPool* pool = make();
+    return pool && pool->started_ == kEvalHelpers && pool->pid_ == getpid() ? pool : nullptr;
   }
   std::mutex& busy() { return busy_; }
   // out[k] = culled_fraction(lv, x[k]) for k < n (n <= kEvalLanes); the
@@ -595,8 +597,22 @@ class EvalPool {
   }
 
  private:
+  static EvalPool* make() noexcept {
+    try {
+      return new EvalPool();
+    } catch (...) {
+      return nullptr;
+    }
+  }
   EvalPool() : pid_(getpid()) {
-    for (int k = 0; k < kEvalHelpers; ++k) std::thread([this, k] { work(k + 1); }).detach();
+    for (int k = 0; k < kEvalHelpers; ++k) {
+      try {
+        std::thread([this, k] { work(k + 1); }).detach();
+      } catch (...) {
+        break;  // a pool without all its workers is never used
+      }
+      ++started_;
+    }
   }
   void work(int lane) {
     std::vector<double> w;
@@ -620,6 +636,7 @@ class EvalPool {
     }
   }
   const pid_t pid_;
+  int started_ = 0;
   std::mutex busy_, m_;
   std::condition_variable cv_;
   std::atomic<uint64_t> gen_{0};
